@@ -1,0 +1,372 @@
+"""CPU FP64 oracle of FilterReg's E-step and twist M-step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this package:
+only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark do.
+It shares no code with the GPU library (``paper_1811_10136_amd``) and neither
+package imports the other; the seeded input generators live in ``synth``.
+
+Layout
+* ``lattice.c``     -- permutohedral embedding, splat, slice and a brute-force
+  kernel sum (binary32 key path, binary64 values), loaded with ctypes.
+* this module       -- features, E-step driver, the M-step of Eq. (7)/(10)
+  through the twist Jacobian of Eq. (16), the Gauss-Newton step of Eq. (17)-(18),
+  the SE(3) exponential and the rigid EM loop, all in float64 NumPy.
+* ``articulated.py`` / ``nodegraph.py`` -- the kinematic models of Sec. 5.1/5.2.
+
+Every function names the passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, "lattice.c")]
+_lib = None
+
+C_FLAGS = ["-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (binary32 key path: no FMA contraction)."""
+    if force or not os.path.exists(_SO) or any(os.path.getmtime(s) > os.path.getmtime(_SO) for s in _SRC):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *C_FLAGS, *_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        ci = ctypes.c_int
+        lib.or_scale_factors.argtypes = [ci, P, P]
+        lib.or_embed_many.argtypes = [ci, i64, P, P, P, P, P]
+        lib.or_lattice_build.argtypes = [ci, ci, i64, P, P, P, P, P, P]
+        lib.or_lattice_build.restype = i64
+        lib.or_slice.argtypes = [ci, ci, i64, P, P, i64, P, P, P, P]
+        lib.or_bf_lattice_sum.argtypes = [ci, ci, i64, P, P, i64, P, P, P]
+        lib.or_transform_f32.argtypes = [i64, P, P, P, ci]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# Features and embedding (Sec. 3.3 "Features", Sec. 4.1 normalised features)
+# ---------------------------------------------------------------------------
+
+def feature_sigmas(feat: int, sigma, sigma_n: float):
+    """Per-dimension kernel widths: position axes, then normal axes for d = 6."""
+    s = [float(v) for v in sigma]
+    if feat == 6:
+        s += [float(sigma_n)] * 3
+    return np.asarray(s, dtype=np.float64)
+
+
+def scale_factors(sigmas) -> np.ndarray:
+    """k_i = sqrt(2/3)(d+1)/(sigma_i sqrt((i+1)(i+2))) in binary32: feature normalisation
+    (Sec. 4.1) folded into the lattice scale of the permutohedral method (Sec. 4.2)."""
+    sig = np.ascontiguousarray(sigmas, dtype=np.float64)
+    k = np.zeros(len(sig), dtype=np.float32)
+    _L().or_scale_factors(len(sig), _p(sig), _p(k))
+    return k
+
+
+def features(points: np.ndarray, normals: Optional[np.ndarray], feat: int) -> np.ndarray:
+    """Raw binary32 feature rows: [x, y, z] or [x, y, z, nx, ny, nz] (Eq. 8)."""
+    p = np.asarray(points, dtype=np.float32)
+    if feat == 3:
+        return np.ascontiguousarray(p)
+    return np.ascontiguousarray(np.concatenate([p, np.asarray(normals, dtype=np.float32)], axis=1))
+
+
+def embed(feat_rows: np.ndarray, k: np.ndarray):
+    """Permutohedral embedding of each row (Sec. 4.2): keys (n, d+1, d) int32,
+    barycentric weights (n, d+1) float64, elevated coordinates (n, d+1) float32."""
+    f = np.ascontiguousarray(feat_rows, dtype=np.float32)
+    n, d = f.shape
+    keys = np.zeros((n, d + 1, d), dtype=np.int32)
+    b = np.zeros((n, d + 1), dtype=np.float64)
+    e = np.zeros((n, d + 1), dtype=np.float32)
+    _L().or_embed_many(d, n, _p(f), _p(np.ascontiguousarray(k, dtype=np.float32)), _p(keys), _p(b), _p(e))
+    return keys, b, e
+
+
+def splat_values(points: np.ndarray, normals: Optional[np.ndarray], residual: str) -> np.ndarray:
+    """Per-observation values v_y of Eq. (11): [1, y] (Eq. 6) or [1, y, n_y] (Eq. 9)."""
+    y = np.asarray(points, dtype=np.float64)
+    cols = [np.ones((len(y), 1)), y]
+    if residual == "pt2pl":
+        cols.append(np.asarray(normals, dtype=np.float64))
+    return np.ascontiguousarray(np.concatenate(cols, axis=1))
+
+
+class Lattice:
+    """The observation's lattice: sorted keys, occupancy and per-vertex value sums."""
+
+    def __init__(self, keys, occ, vals, k, d):
+        self.keys, self.occ, self.vals, self.k, self.d = keys, occ, vals, k, d
+
+    @property
+    def n_vertices(self):
+        return len(self.occ)
+
+
+def lattice_build(feat_rows: np.ndarray, vals: np.ndarray, k: np.ndarray) -> Lattice:
+    """Splat every observation value onto the d+1 vertices of its simplex (Sec. 4.2, Eq. 14)."""
+    f = np.ascontiguousarray(feat_rows, dtype=np.float32)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    n, d = f.shape if f.ndim == 2 else (0, len(k))
+    nv = v.shape[1]
+    cap = max(1, n * (d + 1))
+    keys = np.zeros((cap, d), dtype=np.int32)
+    occ = np.zeros(cap, dtype=np.int32)
+    out = np.zeros((cap, nv), dtype=np.float64)
+    kk = np.ascontiguousarray(k, dtype=np.float32)
+    if n == 0:
+        return Lattice(keys[:0], occ[:0], out[:0], kk, d)
+    nvtx = _L().or_lattice_build(d, nv, n, _p(f), _p(v), _p(kk), _p(keys), _p(occ), _p(out))
+    if nvtx < 0:
+        raise MemoryError("oracle lattice build: out of memory")
+    return Lattice(keys[:nvtx].copy(), occ[:nvtx].copy(), out[:nvtx].copy(), kk, d)
+
+
+def lattice_slice(lat: Lattice, feat_rows: np.ndarray, return_touched: bool = False):
+    """Interpolate the lattice at query features with their barycentric weights (Sec. 4.2)."""
+    f = np.ascontiguousarray(feat_rows, dtype=np.float32)
+    m = len(f)
+    nv = lat.vals.shape[1]
+    out = np.zeros((m, nv), dtype=np.float64)
+    touched = np.zeros(max(1, lat.n_vertices), dtype=np.uint8)
+    if m and lat.n_vertices:
+        _L().or_slice(lat.d, nv, lat.n_vertices, _p(lat.keys), _p(lat.vals), m, _p(f), _p(lat.k),
+                      _p(out), _p(touched))
+    if return_touched:
+        return out, int(touched[: lat.n_vertices].sum())
+    return out
+
+
+def brute_force_lattice_sum(fy, vals, fx, k):
+    """Sum_y K(x, y) v_y with K from pairs of shared simplex vertices; no lattice built."""
+    fy = np.ascontiguousarray(fy, dtype=np.float32)
+    fx = np.ascontiguousarray(fx, dtype=np.float32)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    n, d = fy.shape
+    m = len(fx)
+    out = np.zeros((m, v.shape[1]), dtype=np.float64)
+    _L().or_bf_lattice_sum(d, v.shape[1], n, _p(fy), _p(v), m, _p(fx),
+                           _p(np.ascontiguousarray(k, dtype=np.float32)), _p(out))
+    return out
+
+
+def transform_f32(mat12: np.ndarray, pts: np.ndarray, translate: bool = True) -> np.ndarray:
+    """Pinned binary32 rigid transform ((R0 x + R1 y) + R2 z) + t (Eq. 15 with T in binary32)."""
+    p = np.ascontiguousarray(pts, dtype=np.float32)
+    out = np.zeros_like(p)
+    m = np.ascontiguousarray(mat12, dtype=np.float32).reshape(12)
+    if len(p):
+        _L().or_transform_f32(len(p), _p(m), _p(p), _p(out), 1 if translate else 0)
+    return out
+
+
+def pose_to_mat12(T: np.ndarray) -> np.ndarray:
+    """Row-major [R | t] of a float64 pose, each entry rounded once to binary32."""
+    return np.ascontiguousarray(np.asarray(T, dtype=np.float64)[:3, :4].astype(np.float32).reshape(12))
+
+
+# ---------------------------------------------------------------------------
+# E-step (Eq. 6, 8, 9) through the lattice
+# ---------------------------------------------------------------------------
+
+def estep(lat: Lattice, x32: np.ndarray, n32: Optional[np.ndarray], feat: int, residual: str):
+    """M0 (M,), M1 (M,3) and, for point-to-plane, the un-normalised normal sum (M,3)."""
+    g = lattice_slice(lat, features(x32, n32, feat))
+    m0 = g[:, 0].copy()
+    m1 = g[:, 1:4].copy()
+    ns = g[:, 4:7].copy() if residual == "pt2pl" else None
+    return m0, m1, ns
+
+
+def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
+    """c of Eq. (7), c = w/(1-w) N/M, converted from PDF units to the un-normalised
+    kernel sums of Eq. (11) by the dropped factor (2 pi)^(3/2) sigma_x sigma_y sigma_z."""
+    if n_model == 0 or w <= 0.0:
+        return 0.0
+    s = np.asarray(sigma, dtype=np.float64)
+    return float(w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** 1.5 * s[0] * s[1] * s[2])
+
+
+# ---------------------------------------------------------------------------
+# M-step: twist Jacobian (Eq. 16) and Gauss-Newton normal equations (Eq. 17-18)
+# ---------------------------------------------------------------------------
+
+def skew(v: np.ndarray) -> np.ndarray:
+    """[v]_x with [v]_x b = v x b; works on (..., 3)."""
+    v = np.asarray(v, dtype=np.float64)
+    z = np.zeros(v.shape[:-1])
+    return np.stack([
+        np.stack([z, -v[..., 2], v[..., 1]], -1),
+        np.stack([v[..., 2], z, -v[..., 0]], -1),
+        np.stack([-v[..., 1], v[..., 0], z], -1)], -2)
+
+
+def point_jacobian(x: np.ndarray) -> np.ndarray:
+    """d x_new / d zeta at zeta = 0 for x_new = (I + [w]_x) x + t (Eq. 16): [-[x]_x, I] (M, 3, 6).
+
+    The update matrix of Eq. (16) adds w x x, and w x x = -[x]_x w, so the
+    rotational block is -[x]_x; the printed [skew(x), I] has the opposite
+    sign, and finite differences side with the update matrix."""
+    x = np.asarray(x, dtype=np.float64)
+    J = np.zeros(x.shape[:-1] + (3, 6))
+    J[..., :, :3] = -skew(x)
+    J[..., :, 3:] = np.eye(3)
+    return J
+
+
+def residuals_and_jacobians(x, m0, m1, nsum, c, sigma, residual, normalize_n=False):
+    """Per-point weight, residual and twist Jacobian of Eq. (7) / Eq. (10).
+
+    Points with M0 = 0 have no target and get weight 0.  Returns
+    (w (M,), r (M, k), J (M, k, 6), support mask) with k = 3 (pt2pt) or 1 (pt2pl).
+    Residuals are divided by sigma (the Sigma^-1 weighting of Eq. 7).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    m0 = np.asarray(m0, dtype=np.float64)
+    sup = m0 > 0
+    safe = np.where(sup, m0, 1.0)
+    w = np.where(sup, m0 / (m0 + c), 0.0)
+    tgt = np.asarray(m1, dtype=np.float64) / safe[:, None]
+    Jx = point_jacobian(x)
+    if residual == "pt2pt":
+        r = (x - tgt) / sigma
+        J = Jx / sigma
+    else:
+        n = np.asarray(nsum, dtype=np.float64) / safe[:, None]
+        if normalize_n:
+            nn = np.linalg.norm(n, axis=1, keepdims=True)
+            n = np.where(nn > 0, n / np.where(nn > 0, nn, 1.0), 0.0)
+        r = (np.einsum("ij,ij->i", n, x - tgt) / sigma)[:, None]
+        J = np.einsum("ij,ijk->ik", n, Jx)[:, None, :] / sigma
+    r = np.where(sup[:, None], r, 0.0)
+    J = np.where(sup[:, None, None], J, 0.0)
+    return w, r, J, sup
+
+
+def normal_equations(x, m0, m1, nsum, c, sigma, residual, normalize_n=False):
+    """A = sum w J^T J, b = sum w J^T r (Eq. 17-18 with the rigid dzeta/dtheta = I of Sec. 5),
+    plus stats [sum w, sum w r^2, n_support, sum M0]."""
+    w, r, J, sup = residuals_and_jacobians(x, m0, m1, nsum, c, sigma, residual, normalize_n)
+    A = np.einsum("i,ikp,ikq->pq", w, J, J)
+    b = np.einsum("i,ikp,ik->p", w, J, r)
+    stats = np.array([w.sum(), np.einsum("i,ik,ik->", w, r, r), float(sup.sum()),
+                      float(np.asarray(m0, dtype=np.float64).sum())])
+    return A, b, stats
+
+
+def per_point_jtj(x, m0, m1, nsum, c, sigma, residual, normalize_n=False):
+    """Per-point w J^T J (M, 6, 6) and w J^T r (M, 6): the summands of Alg. 1, lines 1-4."""
+    w, r, J, _ = residuals_and_jacobians(x, m0, m1, nsum, c, sigma, residual, normalize_n)
+    return np.einsum("i,ikp,ikq->ipq", w, J, J), np.einsum("i,ikp,ik->ip", w, J, r)
+
+
+def se3_exp(zeta: np.ndarray) -> np.ndarray:
+    """Exponential of the twist zeta = (w, v) (Eq. 16 ordering alpha, beta, gamma, a, b, c).
+
+    R = I + A [w]_x + B [w]_x^2, p = (I + B [w]_x + C [w]_x^2) v with
+    A = sin t / t, B = (1 - cos t)/t^2, C = (t - sin t)/t^3, t = |w|; below
+    t = 1e-4 the leading two terms of each series are used."""
+    z = np.asarray(zeta, dtype=np.float64)
+    w, v = z[:3], z[3:]
+    th = float(np.linalg.norm(w))
+    K = skew(w)
+    K2 = K @ K
+    if th < 1e-4:
+        t2 = th * th
+        A = 1.0 - t2 / 6.0
+        B = 0.5 - t2 / 24.0
+        C = 1.0 / 6.0 - t2 / 120.0
+    else:
+        A = math.sin(th) / th
+        B = (1.0 - math.cos(th)) / (th * th)
+        C = (th - math.sin(th)) / (th ** 3)
+    T = np.eye(4)
+    T[:3, :3] = np.eye(3) + A * K + B * K2
+    T[:3, 3] = (np.eye(3) + B * K + C * K2) @ v
+    return T
+
+
+class Degenerate(RuntimeError):
+    """The normal equations are not positive definite (no support or rank-deficient)."""
+
+
+def gn_step(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Delta = -A^-1 b (Eq. 17) by Cholesky; raises Degenerate when A is not SPD."""
+    try:
+        L = np.linalg.cholesky(A)
+    except np.linalg.LinAlgError as e:
+        raise Degenerate(str(e)) from e
+    y = np.linalg.solve(L, -b)
+    return np.linalg.solve(L.T, y)
+
+
+# ---------------------------------------------------------------------------
+# Rigid EM loop (Sec. 3.1 with the rigid kinematics of Sec. 5)
+# ---------------------------------------------------------------------------
+
+def build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n):
+    k = scale_factors(feature_sigmas(feat, sigma, sigma_n))
+    lat = lattice_build(features(obs, obs_n, feat), splat_values(obs, obs_n, residual), k)
+    return lat
+
+
+def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n=0.5, c=None, w=0.1,
+                   iters=20, T0=None, lattice: Optional[Lattice] = None, normalize_n=False,
+                   history: Optional[list] = None):
+    """Rigid FilterReg: build the observation lattice once, then `iters` EM iterations of
+    E-step (slice at the pinned binary32 transform of the model) and one Gauss-Newton step
+    T <- Exp(-A^-1 b) T.  Returns the float64 pose."""
+    T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
+    if c is None:
+        c = outlier_constant(w, len(obs), len(model), sigma)
+    sig_m = float(np.mean(sigma))
+    lat = lattice if lattice is not None else build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n)
+    model = np.asarray(model, dtype=np.float32)
+    for _ in range(iters):
+        mat = pose_to_mat12(T)
+        x32 = transform_f32(mat, model)
+        n32 = transform_f32(mat, model_n, translate=False) if feat == 6 else None
+        m0, m1, ns = estep(lat, x32, n32, feat, residual)
+        R32 = mat.reshape(3, 4).astype(np.float64)
+        x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
+        A, b, stats = normal_equations(x64, m0, m1, ns, c, sig_m, residual, normalize_n)
+        dz = gn_step(A, b)
+        T = se3_exp(dz) @ T
+        if history is not None:
+            history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
+    return T
+
+
+def alignment_error(T, T_gt, x_ref) -> float:
+    """Eq. (22): mean over reference points of |(T - T_gt) x|_2."""
+    x = np.asarray(x_ref, dtype=np.float64)
+    D = np.asarray(T) - np.asarray(T_gt)
+    return float(np.mean(np.linalg.norm(x @ D[:3, :3].T + D[:3, 3], axis=1)))
+
+
+def rotation_angle(R: np.ndarray) -> float:
+    c = (np.trace(R) - 1.0) / 2.0
+    return float(math.acos(max(-1.0, min(1.0, c))))

@@ -1,0 +1,362 @@
+"""Seeded synthetic workloads for registration pairs.
+
+This module only makes inputs: point clouds, normals, ground-truth motions and
+request streams.  It holds none of the registration arithmetic (no lattice, no
+E-step, no M-step, no solver).  Both the CPU oracle tests and the GPU tests
+draw their inputs from here, so the two sides always see identical float32
+arrays.
+
+The paper measures on datasets that are not available here (Stanford bunny,
+Stanford Lounge, robot RGBD, a DynamicFusion sequence; Sec. 6).  The
+generators below stand in for them with clouds of the same structure:
+
+* ``ellipsoid_pair``  -- rigid point-to-point, 2k points on an ellipsoid plus
+  10% uniform outliers (stands in for the bunny robustness test, Sec. 6.1).
+* ``depth_pair``      -- rigid point-to-plane, a 640x480 pinhole depth render of
+  3 planes + 5 spheres (stands in for RGBD frame-to-frame tracking, Sec. 6.2).
+* ``articulated_pair``-- 20 capsule links, 32 revolute DOF (Sec. 5.1 / 6.4).
+* ``nodegraph_pair``  -- a displaced-sphere blob skinned to 512 nodes
+  (Sec. 5.2 / 6.5).
+* ``request_stream``  -- Poisson arrivals of depth pairs with log-uniform sizes.
+
+All arrays are row-major ``(n, 3)`` float32 unless stated; poses are 4x4
+float64.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+__all__ = [
+    "Pair",
+    "ellipsoid_pair",
+    "depth_pair",
+    "random_cloud_pair",
+    "separated_pair",
+    "random_motion",
+    "request_stream",
+]
+
+
+@dataclasses.dataclass
+class Pair:
+    """One registration problem: move ``model`` onto ``obs``.
+
+    ``model``/``model_n``: reference positions / normals of the model X (M, 3).
+    ``obs``/``obs_n``:     observation Y positions / normals (N, 3).
+    ``T_gt``:              4x4 motion with ``T_gt @ model ~= obs``.
+    ``sigma``:             per-axis kernel width of the position feature.
+    ``sigma_n``:           kernel width of the normal feature (d = 6 lifting).
+    ``feat``:              3 (position) or 6 (position + normal).
+    ``residual``:          "pt2pt" or "pt2pl".
+    ``iters``:             fixed EM iteration count of the workload.
+    ``w``:                 outlier ratio used for the outlier constant c.
+    """
+
+    model: np.ndarray
+    obs: np.ndarray
+    T_gt: np.ndarray
+    sigma: tuple
+    feat: int
+    residual: str
+    iters: int
+    model_n: Optional[np.ndarray] = None
+    obs_n: Optional[np.ndarray] = None
+    sigma_n: float = 0.5
+    w: float = 0.1
+    name: str = ""
+    extra: dict = dataclasses.field(default_factory=dict)
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def random_motion(rng, max_angle_rad, max_trans, exact_angle=None):
+    """Rotation with a uniform axis on S^2 and an angle U[0, max]; translation U[-t, t]^3."""
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    ang = rng.uniform(0.0, max_angle_rad) if exact_angle is None else exact_angle
+    T = np.eye(4)
+    T[:3, :3] = Rotation.from_rotvec(axis * ang).as_matrix()
+    T[:3, 3] = rng.uniform(-max_trans, max_trans, size=3)
+    return T
+
+
+def _apply(T, p):
+    return p @ T[:3, :3].T + T[:3, 3]
+
+
+# ---------------------------------------------------------------------------
+# Rigid point-to-point: ellipsoid + outliers
+# ---------------------------------------------------------------------------
+
+def _ellipsoid_surface(rng, axes, m):
+    """Uniform-by-area samples on an ellipsoid (rejection from the unit sphere).
+
+    The map u -> diag(axes) u scales the sphere's area element by
+    sqrt((bc ux)^2 + (ac uy)^2 + (ab uz)^2); accept with that factor / its max.
+    """
+    a, b, c = axes
+    gmax = max(b * c, a * c, a * b)
+    out = []
+    have = 0
+    while have < m:
+        u = rng.normal(size=(2 * m, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        g = np.sqrt((b * c * u[:, 0]) ** 2 + (a * c * u[:, 1]) ** 2 + (a * b * u[:, 2]) ** 2)
+        keep = u[rng.uniform(size=len(u)) < g / gmax]
+        out.append(keep)
+        have += len(keep)
+    u = np.concatenate(out)[:m]
+    p = u * np.asarray(axes)
+    n = p / np.asarray(axes) ** 2
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return p, n
+
+
+def ellipsoid_pair(seed: int, m: int = 2000, outlier_frac: float = 0.1, noise: float = 0.005,
+                   max_angle_deg: float = 30.0, max_trans: float = 0.1, sigma: float = 0.02,
+                   iters: int = 30) -> Pair:
+    """Rigid point-to-point workload: ``m`` points on a random ellipsoid.
+
+    Semi-axes U[0.5, 1]; observation = model under a random motion (axis
+    uniform, angle U[0, 30 deg], translation U[-0.1, 0.1]^3) with Gaussian noise
+    ``noise`` plus ``outlier_frac * m`` uniform outliers in the observation's
+    bounding box.  Filter sigma 0.02, 30 EM iterations.
+    """
+    rng = np.random.default_rng(seed)
+    axes = rng.uniform(0.5, 1.0, size=3)
+    x, xn = _ellipsoid_surface(rng, axes, m)
+    T = random_motion(rng, math.radians(max_angle_deg), max_trans)
+    y = _apply(T, x) + rng.normal(scale=noise, size=x.shape)
+    yn = xn @ T[:3, :3].T
+    n_out = int(round(outlier_frac * m))
+    lo, hi = y.min(0), y.max(0)
+    yo = rng.uniform(lo, hi, size=(n_out, 3))
+    on = rng.normal(size=(n_out, 3))
+    on /= np.linalg.norm(on, axis=1, keepdims=True)
+    return Pair(model=_f32(x), obs=_f32(np.concatenate([y, yo])), T_gt=T,
+                sigma=(sigma, sigma, sigma), feat=3, residual="pt2pt", iters=iters,
+                model_n=_f32(xn), obs_n=_f32(np.concatenate([yn, on])), w=outlier_frac,
+                name=f"ellipsoid-{m}-seed{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Rigid point-to-plane: pinhole depth render of planes + spheres
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class _Scene:
+    planes: list      # (normal (3,), offset o with n.p = o, lo (3,), hi (3,))
+    spheres: list     # (center (3,), radius)
+
+
+def _make_scene(rng) -> _Scene:
+    """Room corner (floor, back wall, left wall) and 5 spheres at 1-4 m depth."""
+    planes = [
+        (np.array([0.0, -1.0, 0.0]), -1.0, np.array([-2.6, 0.99, 0.3]), np.array([2.6, 1.01, 4.6])),   # floor y = 1
+        (np.array([0.0, 0.0, -1.0]), -4.6, np.array([-2.6, -1.6, 4.59]), np.array([2.45, 1.01, 4.61])), # back wall z = 4.6
+        (np.array([1.0, 0.0, 0.0]), -2.6, np.array([-2.61, -1.6, 0.3]), np.array([-2.59, 1.01, 4.6])), # left wall x = -2.6
+    ]
+    spheres = []
+    for _ in range(5):
+        z = rng.uniform(1.0, 4.0)
+        r = rng.uniform(0.1, 0.3)
+        x = rng.uniform(-0.45, 0.45) * z
+        y = rng.uniform(-0.3, 0.3) * z
+        spheres.append((np.array([x, min(y, 1.0 - r)]).tolist() + [z], r))
+    spheres = [(np.asarray(c, dtype=np.float64), r) for c, r in spheres]
+    return _Scene(planes, spheres)
+
+
+def _render(scene: _Scene, width: int, height: int, f: float, cx: float, cy: float, T_scene=None):
+    """Ray-cast the scene (optionally moved by ``T_scene``) from a camera at the origin.
+
+    Returns per-hit camera-frame points (z = depth), unit normals facing the
+    camera, and the ray directions (z = 1) of the hit pixels.
+    """
+    u, v = np.meshgrid(np.arange(width, dtype=np.float64), np.arange(height, dtype=np.float64))
+    d = np.stack([(u - cx) / f, (v - cy) / f, np.ones_like(u)], axis=-1).reshape(-1, 3)
+    if T_scene is None:
+        R = np.eye(3)
+        t = np.zeros(3)
+    else:
+        R, t = T_scene[:3, :3], T_scene[:3, 3]
+    # Moving the scene by T equals moving the camera by T^-1: cast rays o' + s d' in scene frame.
+    o = -R.T @ t
+    ds = d @ R                      # rows: R^T d
+    best = np.full(len(d), np.inf)
+    nrm = np.zeros((len(d), 3))
+    for n, off, lo, hi in scene.planes:
+        den = ds @ n
+        with np.errstate(divide="ignore", invalid="ignore"):
+            s = (off - o @ n) / den
+        p = o + s[:, None] * ds
+        ok = (s > 1e-6) & np.all((p >= lo) & (p <= hi), axis=1) & (s < best)
+        best = np.where(ok, s, best)
+        nrm[ok] = n
+    for c, r in scene.spheres:
+        oc = o - c
+        a = np.einsum("ij,ij->i", ds, ds)
+        b = 2.0 * ds @ oc
+        cc = oc @ oc - r * r
+        disc = b * b - 4 * a * cc
+        hit = disc > 0
+        sq = np.sqrt(np.where(hit, disc, 0.0))
+        s = (-b - sq) / (2 * a)
+        ok = hit & (s > 1e-6) & (s < best)
+        p = o + s[:, None] * ds
+        nn = (p - c) / r
+        best = np.where(ok, s, best)
+        nrm[ok] = nn[ok]
+    hit = np.isfinite(best) & (best < 6.0)
+    s = best[hit]
+    n_cam = nrm[hit] @ R.T
+    dd = d[hit]
+    # Orient normals toward the camera.
+    flip = np.einsum("ij,ij->i", n_cam, dd) > 0
+    n_cam[flip] *= -1.0
+    return s, dd, n_cam
+
+
+def depth_pair(seed: int, width: int = 640, height: int = 480, f: float = 525.0,
+               max_angle_deg: float = 10.0, max_trans: float = 0.05, depth_noise: float = 0.002,
+               dropout: float = 0.05, sigma: float = 0.03, sigma_n: float = 0.5, feat: int = 6,
+               iters: int = 20, target_points: Optional[int] = None) -> Pair:
+    """Rigid point-to-plane workload: a pinhole depth render of 3 planes + 5 spheres.
+
+    Model = noise-free render of the scene (camera frame, analytic normals).
+    Observation = render of the scene after a random rigid motion (<= 10 deg,
+    <= 0.05 m per axis), depth noise ``depth_noise`` along each ray and
+    ``dropout`` of the pixels removed.  ``target_points`` rescales focal length
+    and resolution by sqrt(target / 250k) and subsamples the model to exactly
+    ``target_points`` (request streams of uneven size).
+    """
+    rng = np.random.default_rng(seed)
+    scene = _make_scene(rng)
+    T = random_motion(rng, math.radians(max_angle_deg), max_trans)
+    if target_points is not None:
+        scale = math.sqrt(max(target_points, 16) / 250_000.0) * 1.02
+        width = max(8, int(round(width * scale)))
+        height = max(6, int(round(height * scale)))
+        f = f * scale
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    s, d, n = _render(scene, width, height, f, cx, cy)
+    x = s[:, None] * d
+    so, do, no = _render(scene, width, height, f, cx, cy, T_scene=T)
+    so = so + rng.normal(scale=depth_noise, size=so.shape)
+    keep = rng.uniform(size=len(so)) >= dropout
+    y = (so[:, None] * do)[keep]
+    yn = no[keep]
+    if target_points is not None:
+        if len(x) > target_points:
+            idx = np.sort(rng.choice(len(x), size=target_points, replace=False))
+            x, n = x[idx], n[idx]
+        ny = int(round(target_points * len(y) / max(1, len(s))))
+        if 0 < ny < len(y):
+            idy = np.sort(rng.choice(len(y), size=ny, replace=False))
+            y, yn = y[idy], yn[idy]
+    return Pair(model=_f32(x), obs=_f32(y), T_gt=T, sigma=(sigma, sigma, sigma), feat=feat,
+                residual="pt2pl", iters=iters, model_n=_f32(n), obs_n=_f32(yn), sigma_n=sigma_n,
+                w=0.1, name=f"depth-{len(x)}-seed{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Generic small clouds for parity tests
+# ---------------------------------------------------------------------------
+
+def random_cloud_pair(seed: int, m: int, n: int, extent: float = 0.3, sigma: float = 0.02,
+                      feat: int = 3, residual: str = "pt2pt", surface: bool = True,
+                      max_angle_deg: float = 5.0, max_trans: float = 0.01) -> Pair:
+    """Small pair on a wavy surface patch (or a uniform blob) with unit normals.
+
+    Used for parity and edge-case tests: sizes are free, values are bounded by
+    ``extent``, and the motion is small so most model points have support.
+    """
+    rng = np.random.default_rng(seed)
+
+    def sample(k):
+        if surface:
+            uv = rng.uniform(-extent, extent, size=(k, 2))
+            h = 0.15 * extent * np.sin(3.0 * uv[:, 0] / extent) * np.cos(2.0 * uv[:, 1] / extent)
+            p = np.column_stack([uv, h])
+            gx = 0.15 * 3.0 * np.cos(3.0 * uv[:, 0] / extent) * np.cos(2.0 * uv[:, 1] / extent)
+            gy = -0.15 * 2.0 * np.sin(3.0 * uv[:, 0] / extent) * np.sin(2.0 * uv[:, 1] / extent)
+            nn = np.column_stack([-gx, -gy, np.ones(k)])
+        else:
+            p = rng.uniform(-extent, extent, size=(k, 3))
+            nn = rng.normal(size=(k, 3))
+        nn /= np.linalg.norm(nn, axis=1, keepdims=True)
+        return p, nn
+
+    x, xn = sample(m)
+    T = random_motion(rng, math.radians(max_angle_deg), max_trans)
+    yb, ybn = sample(n)
+    y = _apply(T, yb)
+    yn = ybn @ T[:3, :3].T
+    return Pair(model=_f32(x), obs=_f32(y), T_gt=T, sigma=(sigma, sigma, sigma), feat=feat,
+                residual=residual, iters=10, model_n=_f32(xn), obs_n=_f32(yn), w=0.1,
+                name=f"cloud-{m}x{n}-seed{seed}")
+
+
+def separated_pair(seed: int, m: int = 400, sigma: float = 0.02, spacing: float = 4.0, feat: int = 3,
+                   residual: str = "pt2pt", start_disp: float = 0.4) -> Pair:
+    """Noise-free pair whose points are at least ``spacing - 0.4`` sigma apart.
+
+    Points are a random subset of a grid of pitch ``spacing * sigma`` jittered by
+    +-0.2 sigma; normals are random unit vectors; observation = ``T_gt`` applied
+    exactly (no noise, no outliers).  ``extra["T0"]`` is a start pose that
+    displaces every model point by at most ``start_disp * sigma`` from its
+    ground-truth position.
+    """
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(m ** (1.0 / 3.0))) + 2
+    g = np.stack(np.meshgrid(*[np.arange(side)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+    g = g[rng.choice(len(g), size=m, replace=False)]
+    x = (g - side / 2.0) * spacing * sigma + rng.uniform(-0.2, 0.2, size=(m, 3)) * sigma
+    xn = rng.normal(size=(m, 3))
+    xn /= np.linalg.norm(xn, axis=1, keepdims=True)
+    T = random_motion(rng, math.radians(20.0), 0.05)
+    y = _apply(T, x)
+    yn = xn @ T[:3, :3].T
+    # start pose: T_gt composed with a small motion about the cloud centre
+    radius = float(np.linalg.norm(x - x.mean(0), axis=1).max())
+    budget = start_disp * sigma
+    ang = 0.5 * budget / max(radius, 1e-9)
+    P = random_motion(rng, 0.0, 0.0, exact_angle=ang)
+    dirv = rng.normal(size=3)
+    P[:3, 3] = 0.5 * budget * dirv / np.linalg.norm(dirv)
+    c = x.mean(0)
+    P[:3, 3] += c - P[:3, :3] @ c
+    T0 = T @ P
+    return Pair(model=_f32(x), obs=_f32(y), T_gt=T, sigma=(sigma, sigma, sigma), feat=feat,
+                residual=residual, iters=15, model_n=_f32(xn), obs_n=_f32(yn), w=0.0,
+                name=f"separated-{m}-seed{seed}", extra={"T0": T0})
+
+
+# ---------------------------------------------------------------------------
+# Request stream (served batch)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    size: int
+    seed: int
+
+
+def request_stream(seed: int, n_requests: int = 4096, lo: int = 1000, hi: int = 300_000,
+                   rate_per_s: float = 100.0):
+    """Poisson arrivals (exponential gaps, ``rate_per_s``) of log-uniform sizes in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_requests)).astype(np.int64)
+    gaps = rng.exponential(1.0 / rate_per_s, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    seeds = rng.integers(0, 2**31 - 1, size=n_requests)
+    return [Request(i, float(t[i]), int(sizes[i]), int(seeds[i])) for i in range(n_requests)]
