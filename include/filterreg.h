@@ -1,0 +1,243 @@
+/*
+ * filterreg.h -- C ABI of the MI355X FilterReg hot path.
+ *
+ * FilterReg (Gao & Tedrake, CVPR 2019) registers a model point set X, moved by
+ * a motion parameter theta, onto a fixed observation Y (Sec. 3.1).  Its E-step
+ * is a Gaussian transform evaluated with a permutohedral lattice built once
+ * from Y (Sec. 3.2, Sec. 4); its M-step is a Gauss-Newton step in the twist
+ * parameterisation (Sec. 5).  This library runs both on one gfx950 GPU.
+ *
+ * Conventions shared by every call
+ *  - Every array argument named "device" is GPU memory owned by the caller and
+ *    must stay valid until the work queued on `stream` has finished.  Arrays
+ *    named "host" are read (or written) before the call returns.
+ *  - Point clouds are structure-of-arrays binary32.  A cloud may hold several
+ *    independent sets (registration pairs) back to back; `offsets` (host,
+ *    n_sets + 1 entries, offsets[0] == 0, non-decreasing) delimits them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that take a stream only enqueue work and return; device-side faults
+ *    they detect (key range overflow) are latched in the handle and returned by
+ *    the next synchronising call (fr_lattice_stats, fr_lattice_export,
+ *    fr_register, fr_sync_status).
+ *  - Every call returns fr_status; FR_OK is 0.  fr_last_error() gives a
+ *    thread-local message for the last failure.  No C++ exception crosses the
+ *    ABI.  Argument errors are reported before anything is enqueued.
+ *  - Opaque handles (fr_ctx, fr_lattice) are owned by the library and freed
+ *    only by their destroy call; destroying a handle twice returns FR_EINVAL.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef FILTERREG_H
+#define FILTERREG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fr_status;
+enum {
+    FR_OK = 0,
+    FR_EINVAL = 1,       /* bad argument (NULL, size, sigma <= 0, unsupported d, mismatched sets) */
+    FR_ENOMEM = 2,       /* device allocation failed */
+    FR_EBUDGET = 3,      /* the context's HBM budget would be exceeded */
+    FR_ERANGE = 4,       /* a lattice coordinate left the packed key range [-2^20, 2^20) */
+    FR_EDEGENERATE = 5,  /* normal equations not positive definite, or no model point has support */
+    FR_EDEVICE = 6       /* a HIP runtime call failed */
+};
+
+enum { FR_FEAT_POS = 3, FR_FEAT_POS_NORMAL = 6 };         /* feature dimension d */
+enum { FR_VAL_PT2PT = 4, FR_VAL_PT2PL = 7 };              /* value channels V of the lattice */
+enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
+enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
+enum { FR_PT2PT = 0, FR_PT2PL = 1 };
+enum { FR_KIN_RIGID = 0 };
+enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4 };
+
+typedef struct fr_ctx fr_ctx;
+typedef struct fr_lattice fr_lattice;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t fr_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *fr_last_error(void);
+
+/*
+ * Create a context on HIP device `device`.  Every device allocation the
+ * library makes through this context is charged to `hbm_budget_bytes`
+ * (0 = no limit); a call that would exceed it fails with FR_EBUDGET.
+ */
+fr_status fr_ctx_create(int32_t device, size_t hbm_budget_bytes, fr_ctx **out);
+fr_status fr_ctx_destroy(fr_ctx *ctx);
+/* Bytes currently charged to the context's budget. */
+fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes_in_use);
+
+/* A point cloud of n_sets sets (see the conventions above). */
+typedef struct {
+    const float *x, *y, *z;        /* device, offsets[n_sets] entries each */
+    const float *nx, *ny, *nz;     /* device, same length, or all NULL */
+    const int64_t *offsets;        /* host, n_sets + 1 */
+    int32_t n_sets;
+} fr_cloud;
+
+/*
+ * Lattice parameters.  Features are normalised to identity covariance
+ * (Sec. 4.1): position / sigma[axis], and for feat == 6 also the normal /
+ * sigma_n (the feature extension of Sec. 3.3, Eq. 8).  Values splatted per
+ * observation point are [1, y] (Eq. 6) or [1, y, n_y] (Eq. 9).
+ */
+typedef struct {
+    int32_t feat;          /* FR_FEAT_POS or FR_FEAT_POS_NORMAL */
+    int32_t values;        /* FR_VAL_PT2PT or FR_VAL_PT2PL */
+    double sigma[3];       /* > 0 */
+    double sigma_n;        /* > 0 when feat == 6 */
+    int32_t splat;         /* FR_SPLAT_SORTED: bitwise deterministic; FR_SPLAT_ATOMIC: float atomics */
+    int32_t reserved;      /* must be 0 */
+} fr_lattice_params;
+
+/*
+ * Build the lattice of every set of `obs` (Sec. 3.2: built once per
+ * observation when the variance is fixed; Sec. 4.2: splat of the
+ * permutohedral filter, no blur).  Each observation point adds b_k * value to
+ * the d+1 vertices of its enclosing simplex; occupancy counts incidences.
+ * Normals are required when feat == 6 or values == FR_VAL_PT2PL.
+ * Synchronises once with the stream (vertex counts size the tables).
+ * A set with no points gets an empty lattice.  On success *out owns all
+ * device memory of the lattice (charged to ctx).
+ */
+fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, void *stream,
+                           fr_lattice **out);
+fr_status fr_lattice_destroy(fr_lattice *lat);
+
+/* Vertex count, hash capacity (slots) and device bytes of set `set`; synchronises. */
+fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertices, int64_t *capacity,
+                           int64_t *device_bytes);
+
+/*
+ * Copy set `set` of the lattice to host arrays, vertices in lexicographic key
+ * order: keys_h n_v x d int32 (the first d of the d+1 lattice coordinates),
+ * occ_h n_v int32, vals_h n_v x V binary32.  Synchronises.
+ */
+fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h, int32_t *occ_h, float *vals_h);
+
+/*
+ * Motion applied to model reference points before the E-step (Eq. 15,
+ * x_i = T_i x_ref_i).  mats is device memory, one row-major [R | t] of 12
+ * binary32 per segment.  FR_XF_RIGID: one matrix per set.  FR_XF_SEGMENTED:
+ * seg_offsets (host, n_seg + 1) partitions the cloud's points into segments
+ * that each lie inside one set (e.g. the rigid bodies of Sec. 5.1).
+ * FR_XF_NONE: points are used as given.  The transform is evaluated in
+ * binary32 as ((R0 x + R1 y) + R2 z) + t with no fused multiply-add; normals
+ * are rotated the same way without t.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t n_seg;
+    const float *mats;
+    const int64_t *seg_offsets;
+} fr_xform;
+
+/*
+ * E-step through the lattice (Eq. 6, Eq. 9 via Eq. 11): for every model point
+ * of every set, slice the set's lattice at the transformed point's feature:
+ *   m0[i]           = sum_k b_k value_0[v_k]                  (device, M)
+ *   m1[c * M + i]   = sum_k b_k value_(1+c)[v_k], c = 0..2    (device, 3M)
+ *   nsum[c * M + i] = sum_k b_k value_(4+c)[v_k]              (device, 3M; NULL unless V = 7)
+ * where M = offsets[n_sets] of `model_ref`; vertices absent from the lattice
+ * contribute nothing, so points without support get m0 = 0.  `model_ref`
+ * must have the lattice's n_sets, and normals when the lattice has feat 6.
+ */
+fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
+                   float *nsum, void *stream);
+
+/*
+ * Diagnostic: number of distinct lattice vertices the E-step of set `set`
+ * reads (found by at least one lookup).  Synchronises.
+ */
+fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, int32_t set,
+                           int64_t *n_touched);
+
+/*
+ * M-step terms (Eq. 7 point-to-point, Eq. 10 point-to-plane) linearised in
+ * the twist of each point's transform (Eq. 16, with d x / d omega = -[x]_x) and
+ * reduced per segment into the Gauss-Newton normal equations (Eq. 17-18):
+ *   w_i = m0_i / (m0_i + c), target = m1_i / m0_i, n_i = nsum_i / m0_i,
+ *   pt2pt: r = (x_i - target) / sigma,        J = [-[x_i]_x, I] / sigma
+ *   pt2pl: r = n_i . (x_i - target) / sigma,  J = [x_i x n_i, n_i] / sigma
+ *   jtj[s] = sum w J^T J (21 doubles: upper triangle, row-major),
+ *   jtr[s] = sum w J^T r (6 doubles), stats[s] = [sum w, sum w r^2, n_support, sum m0]
+ * over the points of segment s (device outputs).  Points with m0 = 0 are
+ * skipped.  x_i is the model point moved by `xf` (segments of `xf` are the
+ * reduction segments; FR_XF_NONE/RIGID reduce per set).  Per-point terms are
+ * accumulated in binary32 per tile, tiles are summed in binary64 in a fixed
+ * order (bitwise reproducible).  c_per_set (host, n_sets) overrides c.
+ */
+typedef struct {
+    int32_t residual;      /* FR_PT2PT or FR_PT2PL */
+    int32_t normalize_n;   /* 1: use n_i / |n_i| */
+    double c;              /* outlier constant of Eq. 7 in un-normalised kernel units, >= 0 */
+    double sigma;          /* residual scale (Sigma^-1/2 of Eq. 7), > 0 */
+    const double *c_per_set;
+} fr_mstep_params;
+
+fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const float *m0, const float *m1,
+                          const float *nsum, const fr_mstep_params *params, double *jtj, double *jtr,
+                          double *stats, void *stream);
+
+/*
+ * Rigid Gauss-Newton update on the device in binary64 (Eq. 17 and the
+ * left-multiplied update of Eq. 16): for each of n sets,
+ *   dzeta = -A^-1 b (Cholesky), T <- Exp(dzeta) T,
+ * poses (device, n x 16 row-major float64) are updated in place, mats
+ * (device, n x 12) receive the binary32 [R | t], twist_norm (device, n x 2)
+ * receives |omega| and |v| of dzeta, status (device, n int32) receives FR_OK
+ * or FR_EDEGENERATE (pose left unchanged) per set.  Sets with active[i] == 0
+ * are skipped (active may be NULL).
+ */
+fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
+                         double *twist_norm, int32_t *status, const int32_t *active, void *stream);
+
+/* Registration parameters (Sec. 3.1 EM loop; termination on a small twist, Sec. 6.1). */
+typedef struct {
+    fr_lattice_params lattice;
+    int32_t residual;      /* FR_PT2PT or FR_PT2PL */
+    int32_t max_iters;     /* EM iterations (exact count with FR_FIXED_ITERS) */
+    double w;              /* outlier ratio of Eq. 4 in [0, 1); c derived per set as
+                              w/(1-w) N/M (2 pi)^(3/2) sigma_x sigma_y sigma_z */
+    double c_override;     /* >= 0: use this c for every set instead; < 0: derive from w */
+    double twist_tol;      /* stop a set when |omega| and |v| of its step are below this */
+    int32_t flags;         /* FR_FIXED_ITERS | FR_PROFILE_EVENTS | FR_FUSED */
+    int32_t kinematics;    /* FR_KIN_RIGID */
+} fr_register_params;
+
+typedef struct {
+    int32_t iterations;        /* EM iterations run */
+    int32_t n_degenerate;      /* sets that stopped on a degenerate system */
+    double build_ms;           /* lattice build (host clock) */
+    double em_ms;              /* EM loop incl. final copy (host clock) */
+    double estep_ms;           /* sum of E-step kernel times (FR_PROFILE_EVENTS) */
+    double mstep_ms;           /* sum of reduce + solve times (FR_PROFILE_EVENTS) */
+    int64_t estep_launches;
+} fr_report;
+
+/*
+ * Rigid registration of every set of `model_ref` onto the same set of `obs`
+ * (Sec. 3.1 with the rigid kinematics of Sec. 5): build the lattices once,
+ * then per EM iteration E-step, reduce and FP64 solve/update, all on the
+ * device.  theta_inout_h (host, n_sets x 16 float64, row-major 4x4) holds the
+ * start poses and receives the results; status_h (host, n_sets int32, may be
+ * NULL) receives each set's status.  Synchronous.  Returns FR_EDEGENERATE if
+ * any set degenerated (its pose is left at the last good value).
+ */
+fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_register_params *params,
+                      double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
+
+/* Return (and clear) a device fault latched in `lat` by earlier async calls; synchronises. */
+fr_status fr_sync_status(const fr_lattice *lat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FILTERREG_H */

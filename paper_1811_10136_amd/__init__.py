@@ -1,0 +1,369 @@
+"""Python binding of the MI355X FilterReg library (``libfilterreg.so``).
+
+Argument marshalling only: every step of the registration runs in the HIP
+kernels behind the C ABI declared in ``include/filterreg.h``.  PyTorch provides
+device memory (tensors) and streams (``torch.cuda.current_stream()``).  The
+functions ``fr_*`` mirror the C entry points one to one; ``Cloud``, ``Lattice``
+and ``register`` are conveniences built on them.
+
+Importing the package loads the shared library and fails loudly if it has not
+been built (``python -m paper_1811_10136_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfilterreg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1811_10136_amd.build` (hipcc, gfx950)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# --- constants (include/filterreg.h) ----------------------------------------
+FR_OK, FR_EINVAL, FR_ENOMEM, FR_EBUDGET, FR_ERANGE, FR_EDEGENERATE, FR_EDEVICE = range(7)
+FR_FEAT_POS, FR_FEAT_POS_NORMAL = 3, 6
+FR_VAL_PT2PT, FR_VAL_PT2PL = 4, 7
+FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
+FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
+FR_PT2PT, FR_PT2PL = 0, 1
+FR_KIN_RIGID = 0
+FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED = 1, 2, 4
+
+STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
+                5: "FR_EDEGENERATE", 6: "FR_EDEVICE"}
+
+
+class FRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# --- C structures ------------------------------------------------------------
+_P = ctypes.c_void_p
+
+
+class fr_cloud(ctypes.Structure):
+    _fields_ = [("x", _P), ("y", _P), ("z", _P), ("nx", _P), ("ny", _P), ("nz", _P),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)), ("n_sets", ctypes.c_int32)]
+
+
+class fr_lattice_params(ctypes.Structure):
+    _fields_ = [("feat", ctypes.c_int32), ("values", ctypes.c_int32), ("sigma", ctypes.c_double * 3),
+                ("sigma_n", ctypes.c_double), ("splat", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fr_xform(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_seg", ctypes.c_int32), ("mats", _P),
+                ("seg_offsets", ctypes.POINTER(ctypes.c_int64))]
+
+
+class fr_mstep_params(ctypes.Structure):
+    _fields_ = [("residual", ctypes.c_int32), ("normalize_n", ctypes.c_int32), ("c", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("c_per_set", ctypes.POINTER(ctypes.c_double))]
+
+
+class fr_register_params(ctypes.Structure):
+    _fields_ = [("lattice", fr_lattice_params), ("residual", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("w", ctypes.c_double), ("c_override", ctypes.c_double), ("twist_tol", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("kinematics", ctypes.c_int32)]
+
+
+class fr_report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("n_degenerate", ctypes.c_int32), ("build_ms", ctypes.c_double),
+                ("em_ms", ctypes.c_double), ("estep_ms", ctypes.c_double), ("mstep_ms", ctypes.c_double),
+                ("estep_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _sig(name, restype, argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+_i32 = ctypes.c_int32
+_st = ctypes.c_int32
+_sig("fr_version", _i32, [])
+_sig("fr_last_error", ctypes.c_char_p, [])
+_sig("fr_ctx_create", _st, [_i32, ctypes.c_size_t, ctypes.POINTER(_P)])
+_sig("fr_ctx_destroy", _st, [_P])
+_sig("fr_ctx_usage", _st, [_P, ctypes.POINTER(ctypes.c_size_t)])
+_sig("fr_lattice_build", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_lattice_params), _P,
+                               ctypes.POINTER(_P)])
+_sig("fr_lattice_destroy", _st, [_P])
+_sig("fr_lattice_stats", _st, [_P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int64)])
+_sig("fr_lattice_export", _st, [_P, _i32, _P, _P, _P])
+_sig("fr_estep", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P, _P])
+_sig("fr_estep_touched", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _i32,
+                               ctypes.POINTER(ctypes.c_int64)])
+_sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
+                              ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
+_sig("fr_solve_rigid", _st, [_i32, _P, _P, _P, _P, _P, _P, _P, _P])
+_sig("fr_register", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
+                          ctypes.POINTER(fr_register_params), _P, _P, ctypes.POINTER(fr_report), _P])
+_sig("fr_sync_status", _st, [_P])
+
+ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
+                 "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
+                 "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status"]
+
+
+def _check(status: int):
+    if status != FR_OK:
+        raise FRError(status, _lib.fr_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# --- wrapper objects -----------------------------------------------------------
+class Cloud:
+    """Structure-of-arrays binary32 device cloud of one or more sets (see fr_cloud)."""
+
+    def __init__(self, x, y, z, nx=None, ny=None, nz=None, offsets: Sequence[int] = None):
+        self.x, self.y, self.z, self.nx, self.ny, self.nz = x, y, z, nx, ny, nz
+        n = int(x.numel())
+        self.offsets = np.ascontiguousarray(offsets if offsets is not None else [0, n], dtype=np.int64)
+        self._c = fr_cloud(_ptr(x), _ptr(y), _ptr(z), _ptr(nx), _ptr(ny), _ptr(nz),
+                           self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(self.offsets) - 1)
+
+    @property
+    def n_sets(self):
+        return len(self.offsets) - 1
+
+    @property
+    def n(self):
+        return int(self.offsets[-1])
+
+    @classmethod
+    def from_numpy(cls, sets: Sequence, normals: Optional[Sequence] = None, device="cuda"):
+        """Upload a list of (n_i, 3) float32 arrays (and matching normals) as one multi-set cloud."""
+        torch = _torch()
+        pts = np.concatenate([np.asarray(s, np.float32).reshape(-1, 3) for s in sets]) if len(sets) else \
+            np.zeros((0, 3), np.float32)
+        off = np.concatenate([[0], np.cumsum([len(s) for s in sets])]).astype(np.int64)
+        t = torch.from_numpy(np.ascontiguousarray(pts.T)).to(device)
+        cols = [t[0].contiguous(), t[1].contiguous(), t[2].contiguous()]
+        ncols = [None, None, None]
+        if normals is not None:
+            nrm = np.concatenate([np.asarray(s, np.float32).reshape(-1, 3) for s in normals])
+            tn = torch.from_numpy(np.ascontiguousarray(nrm.T)).to(device)
+            ncols = [tn[0].contiguous(), tn[1].contiguous(), tn[2].contiguous()]
+        return cls(*cols, *ncols, offsets=off)
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+class XForm:
+    """fr_xform holding references to its device matrices and host offsets for as long as it lives."""
+
+    def __init__(self, kind: int = 0, mats=None, seg_offsets: Optional[Sequence[int]] = None, n_seg: int = 0):
+        self.kind = kind
+        self.mats = mats
+        self.off = None
+        if seg_offsets is not None:
+            self.off = np.ascontiguousarray(seg_offsets, dtype=np.int64)
+            n_seg = len(self.off) - 1
+        self._c = fr_xform(kind, n_seg, _ptr(mats),
+                           self.off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if self.off is not None else None)
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def lattice_params(feat: int, values: int, sigma, sigma_n: float = 0.5, splat: int = FR_SPLAT_SORTED):
+    s = [float(v) for v in (sigma if hasattr(sigma, "__len__") else (sigma, sigma, sigma))]
+    return fr_lattice_params(feat, values, (ctypes.c_double * 3)(*s), float(sigma_n), splat, 0)
+
+
+# --- one-to-one ABI wrappers ---------------------------------------------------
+def fr_version() -> int:
+    return _lib.fr_version()
+
+
+def fr_ctx_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = _P()
+    _check(_lib.fr_ctx_create(device, hbm_budget_bytes, ctypes.byref(h)))
+    return h
+
+
+def fr_ctx_destroy(ctx):
+    _check(_lib.fr_ctx_destroy(ctx))
+
+
+def fr_ctx_usage(ctx) -> int:
+    v = ctypes.c_size_t()
+    _check(_lib.fr_ctx_usage(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def fr_lattice_build(ctx, obs: Cloud, params: fr_lattice_params, stream=None):
+    h = _P()
+    _check(_lib.fr_lattice_build(ctx, obs.c(), ctypes.byref(params), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def fr_lattice_destroy(lat):
+    _check(_lib.fr_lattice_destroy(lat))
+
+
+def fr_lattice_stats(lat, set_index: int = 0):
+    nv, cap, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.fr_lattice_stats(lat, set_index, ctypes.byref(nv), ctypes.byref(cap), ctypes.byref(nb)))
+    return nv.value, cap.value, nb.value
+
+
+def fr_lattice_export(lat, set_index: int, d: int, V: int):
+    nv, _, _ = fr_lattice_stats(lat, set_index)
+    keys = np.zeros((nv, d), np.int32)
+    occ = np.zeros(nv, np.int32)
+    vals = np.zeros((nv, V), np.float32)
+    _check(_lib.fr_lattice_export(lat, set_index, keys.ctypes.data, occ.ctypes.data, vals.ctypes.data))
+    return keys, occ, vals
+
+
+def fr_estep(lat, model: Cloud, xf: XForm, m0, m1, nsum=None, stream=None):
+    _check(_lib.fr_estep(lat, model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), _stream(stream)))
+
+
+def fr_estep_touched(lat, model: Cloud, xf: XForm, set_index: int = 0) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.fr_estep_touched(lat, model.c(), xf.c(), set_index, ctypes.byref(n)))
+    return n.value
+
+
+def fr_mstep_reduce(model: Cloud, xf: XForm, m0, m1, nsum, residual: int, c: float, sigma: float, jtj, jtr,
+                    stats, normalize_n: int = 0, c_per_set: Optional[Sequence[float]] = None, stream=None):
+    cps = None
+    keep = None
+    if c_per_set is not None:
+        keep = np.ascontiguousarray(c_per_set, dtype=np.float64)
+        cps = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    prm = fr_mstep_params(residual, normalize_n, float(c), float(sigma), cps)
+    _check(_lib.fr_mstep_reduce(model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), ctypes.byref(prm),
+                                _ptr(jtj), _ptr(jtr), _ptr(stats), _stream(stream)))
+    del keep
+
+
+def fr_solve_rigid(n: int, jtj, jtr, poses, mats, twist_norm, status, active=None, stream=None):
+    _check(_lib.fr_solve_rigid(n, _ptr(jtj), _ptr(jtr), _ptr(poses), _ptr(mats), _ptr(twist_norm), _ptr(status),
+                               _ptr(active), _stream(stream)))
+
+
+def fr_register(ctx, model: Cloud, obs: Cloud, params: fr_register_params, theta: np.ndarray, stream=None):
+    """theta: (n_sets, 4, 4) float64, updated in place.  Returns (status per set, report)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    status = np.zeros(model.n_sets, np.int32)
+    rep = fr_report()
+    st = _lib.fr_register(ctx, model.c(), obs.c(), ctypes.byref(params), th.ctypes.data, status.ctypes.data,
+                          ctypes.byref(rep), _stream(stream))
+    theta[...] = th
+    if st not in (FR_OK, FR_EDEGENERATE):
+        _check(st)
+    return status, rep
+
+
+def fr_sync_status(lat):
+    _check(_lib.fr_sync_status(lat))
+
+
+# --- conveniences ----------------------------------------------------------------
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.h = fr_ctx_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.h is not None:
+            fr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Lattice:
+    def __init__(self, ctx: Context, obs: Cloud, params: fr_lattice_params, stream=None):
+        self.ctx = ctx
+        self.params = params
+        self.n_sets = obs.n_sets
+        self.h = fr_lattice_build(ctx.h, obs, params, stream)
+
+    @property
+    def d(self):
+        return self.params.feat
+
+    @property
+    def V(self):
+        return self.params.values
+
+    def stats(self, set_index=0):
+        return fr_lattice_stats(self.h, set_index)
+
+    def export(self, set_index=0):
+        return fr_lattice_export(self.h, set_index, self.d, self.V)
+
+    def close(self):
+        if self.h is not None:
+            fr_lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
+    """c of Eq. (7) in un-normalised kernel units: w/(1-w) N/M (2 pi)^(3/2) sigma_x sigma_y sigma_z."""
+    if n_model == 0 or w <= 0:
+        return 0.0
+    s = list(sigma) if hasattr(sigma, "__len__") else [sigma] * 3
+    return w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** 1.5 * s[0] * s[1] * s[2]
+
+
+def register_params(feat: int, residual: str, sigma, sigma_n=0.5, iters=20, w=0.1, c=None, tol=1e-6,
+                    fixed=True, profile=False, splat=FR_SPLAT_SORTED, fused=False) -> fr_register_params:
+    res = FR_PT2PL if residual == "pt2pl" else FR_PT2PT
+    vals = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
+    flags = (FR_FIXED_ITERS if fixed else 0) | (FR_PROFILE_EVENTS if profile else 0) | (FR_FUSED if fused else 0)
+    return fr_register_params(lattice_params(feat, vals, sigma, sigma_n, splat), res, iters, float(w),
+                              -1.0 if c is None else float(c), float(tol), flags, FR_KIN_RIGID)
+
+
+def register(ctx: Context, model: Cloud, obs: Cloud, params: fr_register_params, T0=None, stream=None):
+    """Rigid registration of every set; returns (poses (n_sets, 4, 4), status, report)."""
+    S = model.n_sets
+    theta = np.repeat(np.eye(4)[None], S, 0) if T0 is None else np.array(T0, dtype=np.float64).reshape(S, 4, 4)
+    status, rep = fr_register(ctx.h, model, obs, params, theta, stream)
+    return theta, status, rep

@@ -1,0 +1,736 @@
+// The C ABI: argument checking, contexts and budgets, lattice handles, per-call
+// tile maps, and the rigid EM driver (Sec. 3.1: E-step, M-step, repeat).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "fr_internal.h"
+
+namespace fr {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (ctx->budget != 0 && ctx->in_use + bytes > ctx->budget) {
+        set_error("HBM budget exceeded: %zu in use + %zu requested > %zu", ctx->in_use, bytes, ctx->budget);
+        return FR_EBUDGET;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return FR_ENOMEM;
+    }
+    ctx->in_use += bytes;
+    return FR_OK;
+}
+
+void dev_free(fr_ctx *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    // Kernels queued on any stream may still read the buffer (error paths
+    // return early); wait for the device before releasing it.
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+    if (bytes == 0) bytes = 16;
+    ctx->in_use -= std::min(ctx->in_use, bytes);
+}
+
+fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what)
+{
+    if (c == nullptr || c->offsets == nullptr || c->n_sets < 1) {
+        set_error("%s: cloud is NULL, has no offsets, or n_sets < 1", what);
+        return FR_EINVAL;
+    }
+    if (c->offsets[0] != 0) {
+        set_error("%s: offsets[0] must be 0", what);
+        return FR_EINVAL;
+    }
+    for (int32_t s = 0; s < c->n_sets; ++s)
+        if (c->offsets[s + 1] < c->offsets[s]) {
+            set_error("%s: offsets must be non-decreasing (set %d)", what, s);
+            return FR_EINVAL;
+        }
+    const int64_t n = c->offsets[c->n_sets];
+    if (n > 0 && (c->x == nullptr || c->y == nullptr || c->z == nullptr)) {
+        set_error("%s: x/y/z must be non-NULL", what);
+        return FR_EINVAL;
+    }
+    if (need_normals && n > 0 && (c->nx == nullptr || c->ny == nullptr || c->nz == nullptr)) {
+        set_error("%s: normals are required (feat 6 or point-to-plane)", what);
+        return FR_EINVAL;
+    }
+    if (n >= (int64_t)1 << 31) {
+        set_error("%s: %lld points exceed 2^31", what, (long long)n);
+        return FR_EINVAL;
+    }
+    return FR_OK;
+}
+
+fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host,
+                    hipStream_t st, Plan &plan)
+{
+    plan.tile = tile;
+    plan.n_sets = cloud->n_sets;
+    const bool seg = xf != nullptr && xf->kind == FR_XF_SEGMENTED;
+    if (seg) {
+        plan.n_seg = xf->n_seg;
+        plan.seg_off.assign(xf->seg_offsets, xf->seg_offsets + xf->n_seg + 1);
+        plan.seg_set.assign(xf->n_seg, 0);
+        int32_t set = 0;
+        for (int32_t s = 0; s < xf->n_seg; ++s) {
+            const int64_t a = plan.seg_off[s], b = plan.seg_off[s + 1];
+            while (set < cloud->n_sets && cloud->offsets[set + 1] <= a && !(a == b && cloud->offsets[set + 1] == a))
+                ++set;
+            if (set >= cloud->n_sets || a < cloud->offsets[set] || b > cloud->offsets[set + 1]) {
+                set_error("fr_xform: segment %d [%lld, %lld) does not lie inside one set", s, (long long)a,
+                          (long long)b);
+                return FR_EINVAL;
+            }
+            plan.seg_set[s] = set;
+        }
+    } else {
+        plan.n_seg = cloud->n_sets;
+        plan.seg_off.assign(cloud->offsets, cloud->offsets + cloud->n_sets + 1);
+        plan.seg_set.resize(cloud->n_sets);
+        for (int32_t s = 0; s < cloud->n_sets; ++s) plan.seg_set[s] = s;
+    }
+    plan.seg_tile.assign(plan.n_seg + 1, 0);
+    for (int32_t s = 0; s < plan.n_seg; ++s)
+        plan.seg_tile[s + 1] = plan.seg_tile[s] + (int32_t)((plan.seg_off[s + 1] - plan.seg_off[s] + tile - 1) / tile);
+    plan.n_tiles = plan.seg_tile[plan.n_seg];
+    // XCD-contiguous tile order pays off once the launch is several waves of the chip deep
+    int32_t chunk = 0, grid = plan.n_tiles;
+    if (plan.n_tiles >= 8 * 64) {
+        chunk = (plan.n_tiles + 7) / 8;
+        grid = chunk * 8;
+    }
+    plan.grid = grid;
+    std::vector<float> cseg(plan.n_seg, 0.0f);
+    if (c_seg_host)
+        for (int32_t s = 0; s < plan.n_seg; ++s) cseg[s] = (float)c_seg_host[plan.seg_set[s]];
+    const size_t b_off = sizeof(int64_t) * (plan.n_seg + 1);
+    const size_t b_tile = sizeof(int32_t) * (plan.n_seg + 1);
+    const size_t b_set = sizeof(int32_t) * plan.n_seg;
+    const size_t b_c = sizeof(float) * plan.n_seg;
+    std::vector<char> host(b_off + b_tile + b_set + b_c);
+    std::memcpy(host.data(), plan.seg_off.data(), b_off);
+    std::memcpy(host.data() + b_off, plan.seg_tile.data(), b_tile);
+    std::memcpy(host.data() + b_off + b_tile, plan.seg_set.data(), b_set);
+    std::memcpy(host.data() + b_off + b_tile + b_set, cseg.data(), b_c);
+    FR_TRY(plan.meta.alloc(ctx, host.size()));
+    FR_HIP(hipMemcpyAsync(plan.meta.p, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    FR_HIP(hipStreamSynchronize(st));
+    const char *p = plan.meta.as<char>();
+    plan.tm.seg_off = reinterpret_cast<const int64_t *>(p);
+    plan.tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
+    plan.tm.seg_set = reinterpret_cast<const int32_t *>(p + b_off + b_tile);
+    plan.seg_c = reinterpret_cast<const float *>(p + b_off + b_tile + b_set);
+    plan.tm.n_seg = plan.n_seg;
+    plan.tm.n_tiles = plan.n_tiles;
+    plan.tm.tile = tile;
+    plan.tm.xcd_chunk = chunk;
+    return FR_OK;
+}
+
+static bool ctx_ok(const fr_ctx *c) { return c != nullptr && c->magic == kCtxMagic; }
+static bool lat_ok(const fr_lattice *l) { return l != nullptr && l->magic == kLatMagic; }
+
+static fr_status check_lattice_params(const fr_lattice_params *p)
+{
+    if (p == nullptr) {
+        set_error("lattice params are NULL");
+        return FR_EINVAL;
+    }
+    if (p->feat != 3 && p->feat != 6) {
+        set_error("feat must be 3 or 6 (got %d)", p->feat);
+        return FR_EINVAL;
+    }
+    if (p->values != 4 && p->values != 7) {
+        set_error("values must be 4 (pt2pt) or 7 (pt2pl) (got %d)", p->values);
+        return FR_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!(p->sigma[i] > 0.0) || !std::isfinite(p->sigma[i])) {
+            set_error("sigma[%d] must be finite and > 0", i);
+            return FR_EINVAL;
+        }
+    if (p->feat == 6 && (!(p->sigma_n > 0.0) || !std::isfinite(p->sigma_n))) {
+        set_error("sigma_n must be finite and > 0 for feat 6");
+        return FR_EINVAL;
+    }
+    if (p->splat != FR_SPLAT_SORTED && p->splat != FR_SPLAT_ATOMIC) {
+        set_error("splat must be FR_SPLAT_SORTED or FR_SPLAT_ATOMIC");
+        return FR_EINVAL;
+    }
+    if (p->reserved != 0) {
+        set_error("reserved must be 0");
+        return FR_EINVAL;
+    }
+    return FR_OK;
+}
+
+static void free_lattice(fr_lattice *lat)
+{
+    if (lat->table) dev_free(lat->ctx, lat->table, lat->table_bytes);
+    if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable));
+    if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes);
+    if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t));
+    lat->table = nullptr;
+    lat->sets_d = nullptr;
+    lat->vkey = nullptr;
+    lat->err_d = nullptr;
+}
+
+// Lattice scale per feature dimension: sqrt(2/3) (d+1) / (sigma_i sqrt((i+1)(i+2))),
+// rounded once to binary32 (the feature normalisation of Sec. 4.1 folded into
+// the permutohedral lattice scale).
+static void scale_factors(const fr_lattice_params *p, float *k)
+{
+    const int d = p->feat;
+    for (int i = 0; i < 8; ++i) k[i] = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        const double sig = (i < 3) ? p->sigma[i] : p->sigma_n;
+        k[i] = (float)(std::sqrt(2.0 / 3.0) * (double)(d + 1) / (sig * std::sqrt((double)((i + 1) * (i + 2)))));
+    }
+}
+
+static fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
+                                    hipStream_t st, fr_lattice **out)
+{
+    fr_lattice *lat = new (std::nothrow) fr_lattice();
+    if (!lat) {
+        set_error("out of host memory");
+        return FR_ENOMEM;
+    }
+    lat->ctx = ctx;
+    lat->d = params->feat;
+    lat->V = params->values;
+    lat->KW = (params->feat + 2) / 3;
+    lat->n_sets = obs->n_sets;
+    lat->splat = params->splat;
+    lat->n_points_total = cloud_points(obs);
+    scale_factors(params, lat->k);
+    fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
+    if (s == FR_OK) s = build_lattice(ctx, obs, params, st, lat);
+    if (s != FR_OK) {
+        free_lattice(lat);
+        lat->magic = kDeadMagic;
+        delete lat;
+        return s;
+    }
+    *out = lat;
+    return FR_OK;
+}
+
+static fr_status check_xform(const fr_xform *xf, const fr_cloud *cloud, const char *what)
+{
+    if (xf == nullptr) return FR_OK;
+    if (xf->kind == FR_XF_NONE) return FR_OK;
+    if (xf->kind != FR_XF_RIGID && xf->kind != FR_XF_SEGMENTED) {
+        set_error("%s: unknown xform kind %d", what, xf->kind);
+        return FR_EINVAL;
+    }
+    if (xf->mats == nullptr) {
+        set_error("%s: xform mats is NULL", what);
+        return FR_EINVAL;
+    }
+    if (xf->kind == FR_XF_RIGID && xf->n_seg != 0 && xf->n_seg != cloud->n_sets) {
+        set_error("%s: rigid xform needs one matrix per set", what);
+        return FR_EINVAL;
+    }
+    if (xf->kind == FR_XF_SEGMENTED) {
+        if (xf->seg_offsets == nullptr || xf->n_seg < 1) {
+            set_error("%s: segmented xform needs seg_offsets and n_seg >= 1", what);
+            return FR_EINVAL;
+        }
+        if (xf->seg_offsets[0] != 0 || xf->seg_offsets[xf->n_seg] != cloud_points(cloud)) {
+            set_error("%s: seg_offsets must partition [0, M)", what);
+            return FR_EINVAL;
+        }
+        for (int32_t s = 0; s < xf->n_seg; ++s)
+            if (xf->seg_offsets[s + 1] < xf->seg_offsets[s]) {
+                set_error("%s: seg_offsets must be non-decreasing", what);
+                return FR_EINVAL;
+            }
+    }
+    return FR_OK;
+}
+
+}  // namespace fr
+
+using namespace fr;
+
+// ===========================================================================
+// extern "C"
+// ===========================================================================
+extern "C" {
+
+int32_t fr_version(void) { return 100; }
+
+const char *fr_last_error(void) { return g_err; }
+
+fr_status fr_ctx_create(int32_t device, size_t hbm_budget_bytes, fr_ctx **out)
+{
+    clear_error();
+    if (out == nullptr) {
+        set_error("fr_ctx_create: out is NULL");
+        return FR_EINVAL;
+    }
+    *out = nullptr;
+    int n = 0;
+    FR_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) {
+        set_error("fr_ctx_create: device %d not in [0, %d)", device, n);
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(device));
+    fr_ctx *c = new (std::nothrow) fr_ctx();
+    if (!c) {
+        set_error("out of host memory");
+        return FR_ENOMEM;
+    }
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cu_count = cus;
+    *out = c;
+    return FR_OK;
+}
+
+fr_status fr_ctx_destroy(fr_ctx *ctx)
+{
+    clear_error();
+    if (!ctx_ok(ctx)) {
+        set_error("fr_ctx_destroy: invalid or destroyed context");
+        return FR_EINVAL;
+    }
+    ctx->magic = kDeadMagic;
+    delete ctx;
+    return FR_OK;
+}
+
+fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || bytes == nullptr) {
+        set_error("fr_ctx_usage: invalid argument");
+        return FR_EINVAL;
+    }
+    *bytes = ctx->in_use;
+    return FR_OK;
+}
+
+fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, void *stream,
+                           fr_lattice **out)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || out == nullptr) {
+        set_error("fr_lattice_build: invalid context or out pointer");
+        return FR_EINVAL;
+    }
+    *out = nullptr;
+    FR_TRY(check_lattice_params(params));
+    FR_TRY(check_cloud(obs, params->feat == 6 || params->values == 7, "fr_lattice_build"));
+    FR_HIP(hipSetDevice(ctx->device));
+    return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out);
+}
+
+fr_status fr_lattice_destroy(fr_lattice *lat)
+{
+    clear_error();
+    if (!lat_ok(lat)) {
+        set_error("fr_lattice_destroy: invalid or destroyed lattice");
+        return FR_EINVAL;
+    }
+    (void)hipSetDevice(lat->ctx->device);
+    (void)hipDeviceSynchronize();
+    free_lattice(lat);
+    lat->magic = kDeadMagic;
+    delete lat;
+    return FR_OK;
+}
+
+fr_status fr_sync_status(const fr_lattice *lat)
+{
+    clear_error();
+    if (!lat_ok(lat)) {
+        set_error("fr_sync_status: invalid lattice");
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    FR_HIP(hipDeviceSynchronize());
+    int32_t e = 0;
+    FR_HIP(hipMemcpy(&e, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (e != 0) {
+        FR_HIP(hipMemset(lat->err_d, 0, sizeof(int32_t)));
+        set_error("a lattice coordinate left [-2^20, 2^20) in an earlier call");
+        return FR_ERANGE;
+    }
+    return FR_OK;
+}
+
+fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertices, int64_t *capacity,
+                           int64_t *device_bytes)
+{
+    clear_error();
+    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets) {
+        set_error("fr_lattice_stats: invalid lattice or set");
+        return FR_EINVAL;
+    }
+    FR_TRY(fr_sync_status(lat));
+    const SetTable &st = lat->sets_h[set];
+    const int KW = lat->KW;
+    const int NQ = (2 * KW + lat->V + 3) / 4;
+    if (n_vertices) *n_vertices = st.n_vertices;
+    if (capacity) *capacity = (int64_t)st.mask + 1;
+    if (device_bytes)
+        *device_bytes = ((int64_t)st.mask + 1) * 16 * NQ +
+                        (int64_t)st.n_vertices * (KW * 8 + 4 + 4 * lat->V);
+    return FR_OK;
+}
+
+fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h, int32_t *occ_h, float *vals_h)
+{
+    clear_error();
+    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets) {
+        set_error("fr_lattice_export: invalid lattice or set");
+        return FR_EINVAL;
+    }
+    FR_TRY(fr_sync_status(lat));
+    const int64_t v0 = lat->vbase[set], nv = lat->vbase[set + 1] - v0, NV = lat->n_vertices_total;
+    if (nv == 0) return FR_OK;
+    if (!keys_h || !occ_h || !vals_h) {
+        set_error("fr_lattice_export: NULL output");
+        return FR_EINVAL;
+    }
+    const int KW = lat->KW, V = lat->V, d = lat->d;
+    std::vector<uint64_t> key((size_t)KW * nv);
+    std::vector<uint32_t> occ(nv);
+    std::vector<float> val((size_t)V * nv);
+    for (int w = 0; w < KW; ++w)
+        FR_HIP(hipMemcpy(key.data() + (size_t)w * nv, lat->vkey + (size_t)w * NV + v0, nv * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost));
+    FR_HIP(hipMemcpy(occ.data(), lat->vocc + v0, nv * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    for (int c = 0; c < V; ++c)
+        FR_HIP(hipMemcpy(val.data() + (size_t)c * nv, lat->vval + (size_t)c * NV + v0, nv * sizeof(float),
+                         hipMemcpyDeviceToHost));
+    // packed keys order lexicographically by coordinates (coordinate 0 in the top bits of word 0)
+    std::vector<int64_t> order(nv);
+    for (int64_t i = 0; i < nv; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        for (int w = 0; w < KW; ++w) {
+            const uint64_t ka = key[(size_t)w * nv + a], kb = key[(size_t)w * nv + b];
+            if (ka != kb) return ka < kb;
+        }
+        return false;
+    });
+    for (int64_t o = 0; o < nv; ++o) {
+        const int64_t i = order[o];
+        uint64_t words[4] = {0, 0, 0, 0};
+        for (int w = 0; w < KW; ++w) words[w] = key[(size_t)w * nv + i];
+        for (int j = 0; j < d; ++j) keys_h[o * d + j] = unpack_coord(words, j);
+        occ_h[o] = (int32_t)occ[i];
+        for (int c = 0; c < V; ++c) vals_h[o * V + c] = val[(size_t)c * nv + i];
+    }
+    return FR_OK;
+}
+
+fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
+                   float *nsum, void *stream)
+{
+    clear_error();
+    if (!lat_ok(lat)) {
+        set_error("fr_estep: invalid lattice");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, lat->d == 6, "fr_estep"));
+    if (model_ref->n_sets != lat->n_sets) {
+        set_error("fr_estep: model has %d sets, lattice has %d", model_ref->n_sets, lat->n_sets);
+        return FR_EINVAL;
+    }
+    FR_TRY(check_xform(xf, model_ref, "fr_estep"));
+    const int64_t M = cloud_points(model_ref);
+    if (M > 0 && (m0 == nullptr || m1 == nullptr)) {
+        set_error("fr_estep: m0/m1 must be non-NULL");
+        return FR_EINVAL;
+    }
+    if (M == 0) return FR_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    Plan plan;
+    FR_TRY(make_plan(lat->ctx, model_ref, xf, 256, nullptr, st, plan));
+    const int kind = xf ? xf->kind : FR_XF_NONE;
+    FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1,
+                        lat->V == 7 ? nsum : nullptr, nullptr, st));
+    // plan.meta is released after the launch completes
+    FR_HIP(hipStreamSynchronize(st));
+    return FR_OK;
+}
+
+fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, int32_t set,
+                           int64_t *n_touched)
+{
+    clear_error();
+    if (!lat_ok(lat) || n_touched == nullptr || set < 0 || set >= lat->n_sets) {
+        set_error("fr_estep_touched: invalid argument");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, lat->d == 6, "fr_estep_touched"));
+    if (model_ref->n_sets != lat->n_sets) {
+        set_error("fr_estep_touched: set count mismatch");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_xform(xf, model_ref, "fr_estep_touched"));
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = nullptr;
+    const SetTable &t = lat->sets_h[set];
+    const size_t total_slots = lat->table_bytes / (16 * ((2 * lat->KW + lat->V + 3) / 4));
+    DevBuf flags;
+    FR_TRY(flags.alloc(lat->ctx, total_slots * sizeof(uint32_t)));
+    FR_HIP(hipMemset(flags.p, 0, total_slots * sizeof(uint32_t)));
+    Plan plan;
+    FR_TRY(make_plan(lat->ctx, model_ref, xf, 256, nullptr, st, plan));
+    const int kind = xf ? xf->kind : FR_XF_NONE;
+    FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, nullptr, nullptr,
+                        nullptr, flags.as<uint32_t>(), st));
+    FR_HIP(hipDeviceSynchronize());
+    std::vector<uint32_t> h((size_t)t.mask + 1);
+    FR_HIP(hipMemcpy(h.data(), flags.as<uint32_t>() + t.slot_base, h.size() * sizeof(uint32_t),
+                     hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (uint32_t v : h) n += v != 0u;
+    *n_touched = n;
+    return FR_OK;
+}
+
+fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const float *m0, const float *m1,
+                          const float *nsum, const fr_mstep_params *params, double *jtj, double *jtr, double *stats,
+                          void *stream)
+{
+    clear_error();
+    FR_TRY(check_cloud(model_ref, false, "fr_mstep_reduce"));
+    FR_TRY(check_xform(xf, model_ref, "fr_mstep_reduce"));
+    if (params == nullptr || (params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
+        !(params->sigma > 0.0) || !(params->c >= 0.0)) {
+        set_error("fr_mstep_reduce: residual must be PT2PT/PT2PL, sigma > 0, c >= 0");
+        return FR_EINVAL;
+    }
+    if (jtj == nullptr || jtr == nullptr || stats == nullptr) {
+        set_error("fr_mstep_reduce: outputs must be non-NULL");
+        return FR_EINVAL;
+    }
+    const int64_t M = cloud_points(model_ref);
+    if (M > 0 && (m0 == nullptr || m1 == nullptr || (params->residual == FR_PT2PL && nsum == nullptr))) {
+        set_error("fr_mstep_reduce: m0/m1 (and nsum for point-to-plane) must be non-NULL");
+        return FR_EINVAL;
+    }
+    int dev = 0;
+    FR_HIP(hipGetDevice(&dev));
+    fr_ctx tmp_ctx;
+    tmp_ctx.device = dev;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<double> cset(model_ref->n_sets, params->c);
+    if (params->c_per_set)
+        for (int32_t s = 0; s < model_ref->n_sets; ++s) cset[s] = params->c_per_set[s];
+    Plan plan;
+    FR_TRY(make_plan(&tmp_ctx, model_ref, xf, 1024, cset.data(), st, plan));
+    DevBuf part;
+    FR_TRY(part.alloc(&tmp_ctx, reduce_partials_floats(plan) * sizeof(float)));
+    const int kind = xf ? xf->kind : FR_XF_NONE;
+    FR_TRY(launch_reduce(model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1, nsum,
+                         params->residual, params->normalize_n, params->sigma, jtj, jtr, stats, part.as<float>(),
+                         st));
+    FR_HIP(hipStreamSynchronize(st));
+    return FR_OK;
+}
+
+fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
+                         double *twist_norm, int32_t *status, const int32_t *active, void *stream)
+{
+    clear_error();
+    if (n < 0 || (n > 0 && (!jtj || !jtr || !poses || !mats || !twist_norm || !status))) {
+        set_error("fr_solve_rigid: invalid argument");
+        return FR_EINVAL;
+    }
+    return launch_solve_rigid(n, jtj, jtr, poses, mats, twist_norm, status, active,
+                              static_cast<hipStream_t>(stream));
+}
+
+fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_register_params *params,
+                      double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream)
+{
+    clear_error();
+    using clk = std::chrono::steady_clock;
+    if (!ctx_ok(ctx) || params == nullptr || theta_inout_h == nullptr) {
+        set_error("fr_register: invalid context, params or theta");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_lattice_params(&params->lattice));
+    if (params->residual != FR_PT2PT && params->residual != FR_PT2PL) {
+        set_error("fr_register: residual must be FR_PT2PT or FR_PT2PL");
+        return FR_EINVAL;
+    }
+    if (params->residual == FR_PT2PL && params->lattice.values != FR_VAL_PT2PL) {
+        set_error("fr_register: point-to-plane needs a lattice with values = FR_VAL_PT2PL");
+        return FR_EINVAL;
+    }
+    if (params->max_iters < 0 || params->kinematics != FR_KIN_RIGID || !(params->w >= 0.0 && params->w < 1.0)) {
+        set_error("fr_register: max_iters >= 0, rigid kinematics and 0 <= w < 1 are required");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register(model)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register(obs)"));
+    if (model_ref->n_sets != obs->n_sets) {
+        set_error("fr_register: model has %d sets, observation %d", model_ref->n_sets, obs->n_sets);
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t S = model_ref->n_sets;
+    const int64_t M = cloud_points(model_ref);
+    fr_report rep{};
+
+    auto t0 = clk::now();
+    fr_lattice *lat = nullptr;
+    FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat));
+    struct LatGuard {
+        fr_lattice *l;
+        ~LatGuard()
+        {
+            if (l) fr_lattice_destroy(l);
+        }
+    } guard{lat};
+    auto t1 = clk::now();
+    rep.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+    // per-set outlier constant (Eq. 7 in un-normalised kernel units)
+    std::vector<double> cset(S, 0.0);
+    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
+    for (int32_t s = 0; s < S; ++s) {
+        const double Ms = (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]);
+        const double Ns = (double)(obs->offsets[s + 1] - obs->offsets[s]);
+        if (params->c_override >= 0.0) cset[s] = params->c_override;
+        else if (Ms > 0 && params->w > 0.0)
+            cset[s] = params->w / (1.0 - params->w) * (Ns / Ms) * std::pow(2.0 * M_PI, 1.5) * s3;
+    }
+    const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
+
+    Plan pe, pr;
+    FR_TRY(make_plan(ctx, model_ref, nullptr, 256, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
+    const bool pl = params->residual == FR_PT2PL;
+    const size_t nM = (size_t)std::max<int64_t>(M, 1);
+    DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive;
+    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+    if (pl || params->lattice.values == 7) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
+    FR_TRY(part.alloc(ctx, reduce_partials_floats(pr) * sizeof(float)));
+    FR_TRY(wjtj.alloc(ctx, S * 21 * sizeof(double)));
+    FR_TRY(wjtr.alloc(ctx, S * 6 * sizeof(double)));
+    FR_TRY(wstat.alloc(ctx, S * 4 * sizeof(double)));
+    FR_TRY(wpose.alloc(ctx, S * 16 * sizeof(double)));
+    FR_TRY(wmats.alloc(ctx, S * 12 * sizeof(float)));
+    FR_TRY(wtn.alloc(ctx, S * 2 * sizeof(double)));
+    FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
+    FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
+    std::vector<float> mats_h((size_t)S * 12);
+    for (int32_t s = 0; s < S; ++s)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 4; ++j) mats_h[(size_t)s * 12 + 4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
+    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK);
+    FR_HIP(hipMemcpyAsync(wpose.p, theta_inout_h, S * 16 * sizeof(double), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wmats.p, mats_h.data(), S * 12 * sizeof(float), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wstatus.p, status_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipStreamSynchronize(st));
+
+    const bool prof = (params->flags & FR_PROFILE_EVENTS) != 0;
+    const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
+    const int max_it = params->max_iters;
+    std::vector<hipEvent_t> ev;
+    if (prof) {
+        ev.resize(3 * (size_t)max_it + 1);
+        for (auto &e : ev) FR_HIP(hipEventCreate(&e));
+    }
+    auto t2 = clk::now();
+    int it = 0;
+    for (; it < max_it; ++it) {
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                            lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                             pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
+                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
+                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
+        if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_it)) {
+            std::vector<double> tn((size_t)S * 2);
+            FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipStreamSynchronize(st));
+            int n_active = 0;
+            for (int32_t s = 0; s < S; ++s) {
+                if (status_v[s] != FR_OK || (tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
+                    active_h[s] = 0;
+                n_active += active_h[s];
+            }
+            FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            if (n_active == 0) {
+                ++it;
+                break;
+            }
+        }
+    }
+    FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    auto t3 = clk::now();
+    rep.iterations = it;
+    rep.em_ms = std::chrono::duration<double, std::milli>(t3 - t2).count();
+    if (prof) {
+        for (int i = 0; i < it; ++i) {
+            float a = 0.0f, b = 0.0f;
+            FR_HIP(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
+            FR_HIP(hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]));
+            rep.estep_ms += a;
+            rep.mstep_ms += b;
+        }
+        rep.estep_launches = it;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    int32_t n_deg = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        if (status_v[s] != FR_OK) ++n_deg;
+        if (status_h) status_h[s] = status_v[s];
+    }
+    rep.n_degenerate = n_deg;
+    if (report_h) *report_h = rep;
+    FR_TRY(fr_sync_status(lat));
+    if (n_deg > 0) {
+        set_error("fr_register: %d set(s) had a degenerate normal-equation system", n_deg);
+        return FR_EDEGENERATE;
+    }
+    return FR_OK;
+}
+
+}  // extern "C"

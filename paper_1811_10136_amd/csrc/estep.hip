@@ -1,0 +1,194 @@
+// E-step slice (Eq. 6, Eq. 9 through the general Gaussian transform Eq. 11):
+// one thread per model point moves the point (Eq. 15), embeds its feature in
+// the lattice, probes the D = d + 1 vertices of its simplex in the set's table
+// and accumulates b_k * [1, y, n_y] into M0, M1 and the normal sum.
+//
+// Memory behaviour: model points and outputs are streamed once (structure of
+// arrays, coalesced, non-temporal so they do not evict the table from L2);
+// the table of the set being sliced is read through L2, and the logical tile
+// order keeps one set's tiles on one XCD.
+#include "fr_internal.h"
+
+namespace fr {
+
+struct EstepArgs {
+    const float *x, *y, *z, *nx, *ny, *nz;
+    const float *mats;            // per segment [R | t], or NULL for no transform
+    const uint4 *table;
+    const SetTable *sets;
+    TileMap tm;
+    float k[8];
+    float *m0, *m1, *ns;          // outputs (m1/ns channel-major, stride M)
+    int64_t M;
+    uint32_t *touched;            // optional: per-slot "was found" flags
+    int32_t *err;
+};
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
+template <int d, int V, bool XF>
+__global__ void __launch_bounds__(256) k_estep(EstepArgs a)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_off[s + 1]) return;
+    const SetTable st = a.sets[a.tm.seg_set[s]];
+
+    float px = ld_stream(a.x + i), py = ld_stream(a.y + i), pz = ld_stream(a.z + i);
+    float p[d];
+    if constexpr (XF) {
+        float m[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+        xform_point(m, px, py, pz, p[0], p[1], p[2]);
+        if constexpr (d == 6) {
+            xform_normal(m, ld_stream(a.nx + i), ld_stream(a.ny + i), ld_stream(a.nz + i), p[3], p[4], p[5]);
+        }
+    } else {
+        p[0] = px;
+        p[1] = py;
+        p[2] = pz;
+        if constexpr (d == 6) {
+            p[3] = ld_stream(a.nx + i);
+            p[4] = ld_stream(a.ny + i);
+            p[5] = ld_stream(a.nz + i);
+        }
+    }
+    float kk[d];
+#pragma unroll
+    for (int j = 0; j < d; ++j) kk[j] = a.k[j];
+
+    uint64_t keys[D][KW];
+    float b[D];
+    if (!embed<d>(p, kk, keys, b)) atomicOr(a.err, 1);
+
+    float acc[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[c] = 0.0f;
+#pragma unroll
+    for (int v = 0; v < D; ++v) probe_accumulate<KW, V>(a.table, st, keys[v], b[v], acc);
+
+    st_stream(a.m0 + i, acc[0]);
+    st_stream(a.m1 + i, acc[1]);
+    st_stream(a.m1 + a.M + i, acc[2]);
+    st_stream(a.m1 + 2 * a.M + i, acc[3]);
+    if constexpr (V == 7) {
+        if (a.ns != nullptr) {
+            st_stream(a.ns + i, acc[4]);
+            st_stream(a.ns + a.M + i, acc[5]);
+            st_stream(a.ns + 2 * a.M + i, acc[6]);
+        }
+    }
+}
+
+// Diagnostic twin of k_estep: marks every table slot a lookup finds.
+template <int d, int V, bool XF>
+__global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    using L = SlotLayout<KW, V>;
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_off[s + 1]) return;
+    const SetTable st = a.sets[a.tm.seg_set[s]];
+    float p[d];
+    if constexpr (XF) {
+        float m[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+        xform_point(m, a.x[i], a.y[i], a.z[i], p[0], p[1], p[2]);
+        if constexpr (d == 6) xform_normal(m, a.nx[i], a.ny[i], a.nz[i], p[3], p[4], p[5]);
+    } else {
+        p[0] = a.x[i];
+        p[1] = a.y[i];
+        p[2] = a.z[i];
+        if constexpr (d == 6) {
+            p[3] = a.nx[i];
+            p[4] = a.ny[i];
+            p[5] = a.nz[i];
+        }
+    }
+    float kk[d];
+#pragma unroll
+    for (int j = 0; j < d; ++j) kk[j] = a.k[j];
+    uint64_t keys[D][KW];
+    float b[D];
+    embed<d>(p, kk, keys, b);
+    const uint4 *base = a.table + st.slot_base * L::kNQ;
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        uint32_t h = hash_key<KW>(keys[v]) & st.mask;
+        for (uint32_t n = 0; n <= st.mask; ++n) {
+            const uint4 q = base[(size_t)h * L::kNQ];
+            const uint64_t w0 = (uint64_t)q.x | ((uint64_t)q.y << 32);
+            if (w0 == kKeyEmpty) break;
+            bool eq = (w0 == keys[v][0]);
+            if constexpr (KW >= 2) eq = eq && (((uint64_t)q.z | ((uint64_t)q.w << 32)) == keys[v][1]);
+            if (eq) {
+                a.touched[st.slot_base + h] = 1u;
+                break;
+            }
+            h = (h + 1) & st.mask;
+        }
+    }
+}
+
+template <int d, int V>
+static void launch_dv(const EstepArgs &a, bool xf, bool touch, int grid, hipStream_t st)
+{
+    if (touch) {
+        if (xf) k_estep_touch<d, V, true><<<grid, 256, 0, st>>>(a);
+        else k_estep_touch<d, V, false><<<grid, 256, 0, st>>>(a);
+    } else {
+        if (xf) k_estep<d, V, true><<<grid, 256, 0, st>>>(a);
+        else k_estep<d, V, false><<<grid, 256, 0, st>>>(a);
+    }
+}
+
+fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
+{
+    if (plan.grid == 0) return FR_OK;
+    EstepArgs a{};
+    a.x = model->x;
+    a.y = model->y;
+    a.z = model->z;
+    a.nx = model->nx;
+    a.ny = model->ny;
+    a.nz = model->nz;
+    a.mats = mats;
+    a.table = static_cast<const uint4 *>(lat->table);
+    a.sets = lat->sets_d;
+    a.tm = plan.tm;
+    for (int j = 0; j < 8; ++j) a.k[j] = lat->k[j];
+    a.m0 = m0;
+    a.m1 = m1;
+    a.ns = nsum;
+    a.M = cloud_points(model);
+    a.touched = touched;
+    a.err = lat->err_d;
+    const bool xf = xf_kind != FR_XF_NONE;
+    const bool touch = touched != nullptr;
+    if (lat->d == 3 && lat->V == 4) launch_dv<3, 4>(a, xf, touch, plan.grid, st);
+    else if (lat->d == 3 && lat->V == 7) launch_dv<3, 7>(a, xf, touch, plan.grid, st);
+    else if (lat->d == 6 && lat->V == 4) launch_dv<6, 4>(a, xf, touch, plan.grid, st);
+    else if (lat->d == 6 && lat->V == 7) launch_dv<6, 7>(a, xf, touch, plan.grid, st);
+    else {
+        set_error("fr_estep: unsupported lattice d=%d V=%d", lat->d, lat->V);
+        return FR_EINVAL;
+    }
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+}  // namespace fr

@@ -1,0 +1,156 @@
+// Host-side internals shared by the translation units of the library:
+// context and lattice objects, error reporting, budgeted device allocation,
+// per-call tile maps and the kernel launchers of each .hip file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/filterreg.h"
+#include "fr_device.h"
+
+namespace fr {
+
+constexpr uint32_t kCtxMagic = 0xF17E0C7Cu;
+constexpr uint32_t kLatMagic = 0xF17E1A77u;
+constexpr uint32_t kDeadMagic = 0xDEADDEADu;
+
+// --- errors ---------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Status {
+    fr_status code = FR_OK;
+    bool ok() const { return code == FR_OK; }
+};
+
+#define FR_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            ::fr::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                            __LINE__);                                                        \
+            return FR_EDEVICE;                                                                \
+        }                                                                                     \
+    } while (0)
+
+#define FR_TRY(expr)                    \
+    do {                                \
+        fr_status _s = (expr);          \
+        if (_s != FR_OK) return _s;     \
+    } while (0)
+
+}  // namespace fr
+
+// --- handles (global namespace: they complete the ABI's opaque types) ------
+struct fr_ctx {
+    uint32_t magic = fr::kCtxMagic;
+    int32_t device = 0;
+    size_t budget = 0;       // 0 = unlimited
+    size_t in_use = 0;
+    int cu_count = 256;
+};
+
+struct fr_lattice {
+    uint32_t magic = fr::kLatMagic;
+    fr_ctx *ctx = nullptr;
+    int32_t d = 3, V = 4, KW = 1;
+    int32_t n_sets = 0;
+    int32_t splat = FR_SPLAT_SORTED;
+    float k[8] = {0};
+    int64_t n_points_total = 0;
+    // table
+    void *table = nullptr;            // all sets' slots
+    size_t table_bytes = 0;
+    fr::SetTable *sets_d = nullptr;   // device copy of sets_h
+    std::vector<fr::SetTable> sets_h;
+    // vertex arrays (for export), vertices of set s are [vbase[s], vbase[s+1])
+    uint64_t *vkey = nullptr;         // KW words per vertex, word-major: vkey[w * nv + v]
+    uint32_t *vocc = nullptr;
+    float *vval = nullptr;            // V per vertex, channel-major: vval[c * nv + v]
+    int64_t n_vertices_total = 0;
+    std::vector<int64_t> vbase;
+    size_t vert_bytes = 0;
+    int32_t *err_d = nullptr;         // latched device fault bits
+    size_t charged = 0;
+};
+
+namespace fr {
+
+// --- budgeted allocation ---------------------------------------------------
+fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes);
+void dev_free(fr_ctx *ctx, void *p, size_t bytes);
+
+// RAII temporary device buffer charged to the context.
+struct DevBuf {
+    fr_ctx *ctx = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    fr_status alloc(fr_ctx *c, size_t b)
+    {
+        reset();
+        ctx = c;
+        bytes = b < 16 ? 16 : b;
+        fr_status s = dev_alloc(ctx, &p, bytes);
+        if (s != FR_OK) { p = nullptr; bytes = 0; }
+        return s;
+    }
+    void reset()
+    {
+        if (p) dev_free(ctx, p, bytes);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// --- per-call tile maps ----------------------------------------------------
+// Device copy of the segment table of a cloud (segments are the sets, or the
+// segments of an fr_xform), split into tiles of `tile` points.
+struct Plan {
+    int32_t n_seg = 0, n_sets = 0, tile = 256, n_tiles = 0, grid = 0;
+    std::vector<int64_t> seg_off;   // host copies
+    std::vector<int32_t> seg_tile, seg_set;
+    DevBuf meta;                    // device: seg_off | seg_tile | seg_set | seg_c | mats of NONE
+    TileMap tm{};
+    const float *seg_c = nullptr;   // device, per segment outlier constant (reduce only)
+};
+
+// Build a plan for `model_ref` segmented per `xf` (NULL = per set).
+fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host,
+                    hipStream_t stream, Plan &plan);
+
+inline int64_t cloud_points(const fr_cloud *c) { return c->offsets[c->n_sets]; }
+fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what);
+
+// --- launchers ---------------------------------------------------------------
+// lattice_build.hip
+fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t stream,
+                        fr_lattice *lat);
+
+// estep.hip
+fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t stream);
+
+// mstep.hip
+fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
+                        const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
+                        double *jtr, double *stats, float *partials, hipStream_t stream);
+size_t reduce_partials_floats(const Plan &plan);
+
+// solve.hip
+fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
+                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t stream);
+
+// scan / sort helpers (lattice_build.hip)
+fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, bool flags, hipStream_t stream);
+
+}  // namespace fr

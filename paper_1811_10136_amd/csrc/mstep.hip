@@ -1,0 +1,189 @@
+// M-step reduction (Eq. 7 / Eq. 10 linearised in the twist, Eq. 16, summed
+// into the Gauss-Newton normal equations of Eq. 17-18).
+//
+// k_reduce: one block per tile of 1024 model points of one segment.  Each
+// thread accumulates w J^T J (21 upper entries), w J^T r (6) and 4 statistics
+// in binary32 registers over its points; the block reduces the 31 values with
+// wavefront butterflies and an LDS exchange between its 4 waves and writes one
+// partial row per tile.  k_reduce_final: one block per segment sums its
+// tiles' partial rows in tile order in binary64 (fixed order -> bitwise
+// reproducible) and applies the 1/sigma^2 of the residual scaling.
+#include "fr_internal.h"
+
+namespace fr {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedPerThread = 4;
+constexpr int kRedTile = kRedThreads * kRedPerThread;
+constexpr int kRedVals = 31;      // 21 JtJ + 6 Jtr + 4 stats
+constexpr int kRedStride = 32;
+
+struct ReduceArgs {
+    const float *x, *y, *z;
+    const float *mats;
+    TileMap tm;
+    const float *m0, *m1, *ns;
+    int64_t M;
+    const float *seg_c;
+    float *partials;
+    int normalize_n;
+};
+
+__host__ __device__ constexpr int ut_index(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
+
+template <int NR>
+__device__ __forceinline__ void accumulate_rows(float (&acc)[kRedVals], const float (&J)[NR][6], const float (&r)[NR],
+                                                float w)
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        float wj[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) wj[a] = w * J[q][a];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+#pragma unroll
+            for (int b = a; b < 6; ++b) acc[ut_index(a, b)] = fmaf(wj[a], J[q][b], acc[ut_index(a, b)]);
+            acc[21 + a] = fmaf(wj[a], r[q], acc[21 + a]);
+        }
+    }
+}
+
+template <int RES, bool XF>
+__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
+{
+    __shared__ float part[kRedThreads / 64][kRedStride];
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    const int64_t start = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
+    const int64_t stop = min(start + (int64_t)a.tm.tile, a.tm.seg_off[s + 1]);
+    const float c = a.seg_c[s];
+    float m[12];
+    if constexpr (XF) {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+    }
+    float acc[kRedVals];
+#pragma unroll
+    for (int j = 0; j < kRedVals; ++j) acc[j] = 0.0f;
+
+    for (int64_t i = start + threadIdx.x; i < stop; i += kRedThreads) {
+        float x = __builtin_nontemporal_load(a.x + i);
+        float y = __builtin_nontemporal_load(a.y + i);
+        float z = __builtin_nontemporal_load(a.z + i);
+        if constexpr (XF) {
+            float ox, oy, oz;
+            xform_point(m, x, y, z, ox, oy, oz);
+            x = ox;
+            y = oy;
+            z = oz;
+        }
+        const float m0 = __builtin_nontemporal_load(a.m0 + i);
+        if (!(m0 > 0.0f)) continue;
+        const float w = m0 / (m0 + c);
+        const float inv = 1.0f / m0;
+        const float tx = __builtin_nontemporal_load(a.m1 + i) * inv;
+        const float ty = __builtin_nontemporal_load(a.m1 + a.M + i) * inv;
+        const float tz = __builtin_nontemporal_load(a.m1 + 2 * a.M + i) * inv;
+        const float dx = x - tx, dy = y - ty, dz = z - tz;
+        float r2;
+        if constexpr (RES == FR_PT2PT) {
+            // rows of J = [-[x]_x, I]
+            const float J[3][6] = {{0.0f, z, -y, 1.0f, 0.0f, 0.0f},
+                                   {-z, 0.0f, x, 0.0f, 1.0f, 0.0f},
+                                   {y, -x, 0.0f, 0.0f, 0.0f, 1.0f}};
+            const float r[3] = {dx, dy, dz};
+            accumulate_rows<3>(acc, J, r, w);
+            r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        } else {
+            float nx = __builtin_nontemporal_load(a.ns + i) * inv;
+            float ny = __builtin_nontemporal_load(a.ns + a.M + i) * inv;
+            float nz = __builtin_nontemporal_load(a.ns + 2 * a.M + i) * inv;
+            if (a.normalize_n) {
+                const float nn = sqrtf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+                const float in = nn > 0.0f ? 1.0f / nn : 0.0f;
+                nx *= in;
+                ny *= in;
+                nz *= in;
+            }
+            const float rr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+            // J = [x cross n, n]
+            const float J[1][6] = {{y * nz - z * ny, z * nx - x * nz, x * ny - y * nx, nx, ny, nz}};
+            const float r[1] = {rr};
+            accumulate_rows<1>(acc, J, r, w);
+            r2 = rr * rr;
+        }
+        acc[27] += w;
+        acc[28] = fmaf(w, r2, acc[28]);
+        acc[29] += 1.0f;
+        acc[30] += m0;
+    }
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < kRedVals; ++j) {
+        float v = acc[j];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) part[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedVals) {
+        float v = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kRedThreads / 64; ++w) v += part[w][threadIdx.x];
+        a.partials[(size_t)t * kRedStride + threadIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_reduce_final(TileMap tm, const float *partials, double inv_s2, double *jtj,
+                                                     double *jtr, double *stats)
+{
+    const int32_t s = blockIdx.x;
+    const int j = threadIdx.x;
+    if (j >= kRedVals) return;
+    double acc = 0.0;
+    for (int32_t t = tm.seg_tile[s]; t < tm.seg_tile[s + 1]; ++t) acc += (double)partials[(size_t)t * kRedStride + j];
+    if (j < 21) jtj[(size_t)s * 21 + j] = acc * inv_s2;
+    else if (j < 27) jtr[(size_t)s * 6 + (j - 21)] = acc * inv_s2;
+    else stats[(size_t)s * 4 + (j - 27)] = (j == 28) ? acc * inv_s2 : acc;
+}
+
+size_t reduce_partials_floats(const Plan &plan) { return (size_t)(plan.n_tiles + 1) * kRedStride; }
+
+fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
+                        const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
+                        double *jtr, double *stats, float *partials, hipStream_t st)
+{
+    if (plan.n_seg == 0) return FR_OK;
+    ReduceArgs a{};
+    a.x = model->x;
+    a.y = model->y;
+    a.z = model->z;
+    a.mats = mats;
+    a.tm = plan.tm;
+    a.m0 = m0;
+    a.m1 = m1;
+    a.ns = nsum;
+    a.M = cloud_points(model);
+    a.seg_c = plan.seg_c;
+    a.partials = partials;
+    a.normalize_n = normalize_n;
+    const bool xf = xf_kind != FR_XF_NONE;
+    if (plan.grid > 0) {
+        if (residual == FR_PT2PT) {
+            if (xf) k_reduce<FR_PT2PT, true><<<plan.grid, kRedThreads, 0, st>>>(a);
+            else k_reduce<FR_PT2PT, false><<<plan.grid, kRedThreads, 0, st>>>(a);
+        } else {
+            if (xf) k_reduce<FR_PT2PL, true><<<plan.grid, kRedThreads, 0, st>>>(a);
+            else k_reduce<FR_PT2PL, false><<<plan.grid, kRedThreads, 0, st>>>(a);
+        }
+        FR_HIP(hipGetLastError());
+    }
+    k_reduce_final<<<plan.n_seg, 64, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+}  // namespace fr

@@ -1,0 +1,142 @@
+// Rigid Gauss-Newton update in binary64 on the device (Eq. 17 and the
+// left-multiplied twist update of Eq. 16): one thread per set solves
+// A dzeta = -b by Cholesky, maps dzeta through the SE(3) exponential and
+// composes it on the left of the set's pose; it also refreshes the binary32
+// [R | t] the next E-step reads.
+#include "fr_internal.h"
+
+namespace fr {
+
+// Exp of the twist (w, v): R = I + A [w]x + B [w]x^2, p = (I + B [w]x + C [w]x^2) v,
+// A = sin t / t, B = (1 - cos t) / t^2, C = (t - sin t) / t^3, t = |w|; two-term
+// series below t = 1e-4.
+__device__ inline void se3_exp(const double (&z)[6], double (&E)[3][4])
+{
+    const double wx = z[0], wy = z[1], wz = z[2];
+    const double th2 = wx * wx + wy * wy + wz * wz;
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-4) {
+        A = 1.0 - th2 / 6.0;
+        B = 0.5 - th2 / 24.0;
+        C = 1.0 / 6.0 - th2 / 120.0;
+    } else {
+        const double sn = sin(th), cs = cos(th);
+        A = sn / th;
+        B = (1.0 - cs) / th2;
+        C = (th - sn) / (th2 * th);
+    }
+    const double K[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
+    double K2[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) K2[i][j] = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double p = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double I = (i == j) ? 1.0 : 0.0;
+            E[i][j] = I + A * K[i][j] + B * K2[i][j];
+            p += (I + B * K[i][j] + C * K2[i][j]) * z[3 + j];
+        }
+        E[i][3] = p;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses,
+                                                    float *mats, double *twist_norm, int32_t *status,
+                                                    const int32_t *active)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (active != nullptr && active[s] == 0) return;
+    double A[6][6], b[6];
+    {
+        int idx = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i; j < 6; ++j) {
+                const double v = jtj[(size_t)s * 21 + idx++];
+                A[i][j] = v;
+                A[j][i] = v;
+            }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) b[i] = jtr[(size_t)s * 6 + i];
+    }
+    // Cholesky A = L L^T (in the lower triangle of A)
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double sum = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sum -= A[j][k] * A[j][k];
+        ok = ok && (sum > 0.0);
+        const double ljj = sqrt(ok ? sum : 1.0);
+        A[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double v = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+            A[i][j] = v / ljj;
+        }
+    }
+    if (!ok) {
+        status[s] = FR_EDEGENERATE;
+        twist_norm[2 * s] = 0.0;
+        twist_norm[2 * s + 1] = 0.0;
+        return;
+    }
+    double y[6], z[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double v = -b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= A[i][k] * y[k];
+        y[i] = v / A[i][i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) v -= A[k][i] * z[k];
+        z[i] = v / A[i][i];
+    }
+    double E[3][4];
+    se3_exp(z, E);
+    double T[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) T[i][j] = poses[(size_t)s * 16 + 4 * i + j];
+    double N[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            N[i][j] = E[i][0] * T[0][j] + E[i][1] * T[1][j] + E[i][2] * T[2][j] + (j == 3 ? E[i][3] : 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            poses[(size_t)s * 16 + 4 * i + j] = N[i][j];
+            mats[(size_t)s * 12 + 4 * i + j] = (float)N[i][j];
+        }
+    twist_norm[2 * s] = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    twist_norm[2 * s + 1] = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    status[s] = FR_OK;
+}
+
+fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
+                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t st)
+{
+    if (n <= 0) return FR_OK;
+    k_solve_rigid<<<(n + 63) / 64, 64, 0, st>>>(n, jtj, jtr, poses, mats, twist_norm, status, active);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+}  // namespace fr

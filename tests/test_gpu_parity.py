@@ -1,0 +1,372 @@
+"""GPU parity: every call of the C ABI against the CPU oracle on the same seeded inputs.
+
+Sizes span several tiles with ragged tails; tolerances are derived in _helpers.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _helpers import (abs_scales, assert_estep_close, assert_lattice_equal, oracle_lattice, pose_close, soa,
+                      upload, upper)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1811_10136_amd as fr
+    return fr
+
+
+@pytest.fixture(scope="module")
+def ctx(fr):
+    c = fr.Context(0)
+    yield c
+    c.close()
+
+
+RES = {4: "pt2pt", 7: "pt2pl"}
+CASES = [(3, 4), (3, 7), (6, 4), (6, 7)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("splat", [0, 1], ids=["sorted", "atomic"])
+@pytest.mark.parametrize("feat,V", CASES)
+def test_lattice_build_parity(fr, ctx, feat, V, splat):
+    p = synth.random_cloud_pair(21 + feat + V, 1000, 3001, feat=feat, residual=RES[V])
+    _say(f"[lattice] feat={feat} V={V} splat={splat} N={len(p.obs)}")
+    obs = upload([p.obs], [p.obs_n])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(feat, V, p.sigma, p.sigma_n, splat))
+    keys, occ, vals = lat.export(0)
+    ref = oracle_lattice(p.obs, p.obs_n, feat, RES[V], p.sigma, p.sigma_n)
+    assert_lattice_equal(keys, occ, vals, ref, L=float(np.abs(p.obs).max()))
+    nv, cap, _ = lat.stats(0)
+    assert nv == ref.n_vertices and cap >= 2 * nv and cap & (cap - 1) == 0
+    lat.close()
+
+
+def test_lattice_full_depth_frame(fr, ctx):
+    p = synth.depth_pair(0)
+    _say(f"[lattice-full] depth frame N={len(p.obs)} d=6 V=7")
+    obs = upload([p.obs], [p.obs_n])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 0))
+    keys, occ, vals = lat.export(0)
+    ref = oracle_lattice(p.obs, p.obs_n, 6, "pt2pl", p.sigma, p.sigma_n)
+    assert_lattice_equal(keys, occ, vals, ref, L=float(np.abs(p.obs).max()))
+    assert occ.sum() == 7 * len(p.obs)
+    lat.close()
+
+
+def _estep_case(fr, ctx, p, feat, V, T):
+    res = RES[V]
+    obs = upload([p.obs], [p.obs_n])
+    model = upload([p.model], [p.model_n])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(feat, V, p.sigma, p.sigma_n, 0))
+    M = len(p.model)
+    mat = oracle.pose_to_mat12(T)
+    mats = torch.from_numpy(mat.copy()).cuda()
+    xf = fr.XForm(fr.FR_XF_RIGID, mats, n_seg=1)
+    m0 = torch.empty(M, device="cuda")
+    m1 = torch.empty(3 * M, device="cuda")
+    ns = torch.empty(3 * M, device="cuda") if V == 7 else None
+    fr.fr_estep(lat.h, model, xf, m0, m1, ns)
+    torch.cuda.synchronize()
+    ref_lat = oracle_lattice(p.obs, p.obs_n, feat, res, p.sigma, p.sigma_n)
+    x32 = oracle.transform_f32(mat, p.model)
+    n32 = oracle.transform_f32(mat, p.model_n, translate=False)
+    g, touched = oracle.lattice_slice(ref_lat, oracle.features(x32, n32, feat), return_touched=True)
+    vmax = float(ref_lat.vals[:, 0].max())
+    assert_estep_close(soa(m0), soa(m1).reshape(3, M).T, soa(ns).reshape(3, M).T if ns is not None else None,
+                       g[:, 0], g[:, 1:4], g[:, 4:7] if V == 7 else None, vmax, float(np.abs(p.obs).max()))
+    return lat, model, xf, touched, g
+
+
+@pytest.mark.parametrize("feat,V", CASES)
+def test_estep_parity(fr, ctx, feat, V):
+    p = synth.random_cloud_pair(31 + feat + V, 2777, 2500, feat=feat, residual=RES[V])
+    _say(f"[estep] feat={feat} V={V} M={len(p.model)}")
+    T = synth.random_motion(np.random.default_rng(feat * V), math.radians(2.0), 0.005)
+    lat, model, xf, touched, g = _estep_case(fr, ctx, p, feat, V, T)
+    assert (g[:, 0] > 0).mean() > 0.5
+    assert fr.fr_estep_touched(lat.h, model, xf, 0) == touched
+    lat.close()
+
+
+def test_estep_identity_xform_and_segments(fr, ctx):
+    """FR_XF_NONE equals FR_XF_RIGID with the identity; a segmented transform equals per-segment rigid."""
+    p = synth.random_cloud_pair(77, 1500, 1500, feat=3, residual="pt2pt")
+    obs = upload([p.obs])
+    model = upload([p.model])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(3, 4, p.sigma))
+    M = len(p.model)
+    outs = []
+    eye = torch.tensor(np.eye(4)[:3].reshape(12), dtype=torch.float32, device="cuda")
+    for kind, mats in ((fr.FR_XF_NONE, None), (fr.FR_XF_RIGID, eye)):
+        xf = fr.XForm(kind, mats, n_seg=1 if mats is not None else 0)
+        m0 = torch.empty(M, device="cuda")
+        m1 = torch.empty(3 * M, device="cuda")
+        fr.fr_estep(lat.h, model, xf, m0, m1)
+        outs.append((soa(m0), soa(m1)))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    # three segments with different motions
+    rng = np.random.default_rng(5)
+    Ts = [synth.random_motion(rng, 0.03, 0.004) for _ in range(3)]
+    off = [0, 400, 401, M]
+    mats = torch.from_numpy(np.concatenate([oracle.pose_to_mat12(T) for T in Ts])).cuda()
+    xf = fr.XForm(fr.FR_XF_SEGMENTED, mats, seg_offsets=off)
+    m0 = torch.empty(M, device="cuda")
+    m1 = torch.empty(3 * M, device="cuda")
+    fr.fr_estep(lat.h, model, xf, m0, m1)
+    ref_lat = oracle_lattice(p.obs, None, 3, "pt2pt", p.sigma, p.sigma_n)
+    x32 = np.concatenate([oracle.transform_f32(oracle.pose_to_mat12(Ts[s]), p.model[off[s]:off[s + 1]])
+                          for s in range(3)])
+    g = oracle.lattice_slice(ref_lat, oracle.features(x32, None, 3))
+    assert_estep_close(soa(m0), soa(m1).reshape(3, M).T, None, g[:, 0], g[:, 1:4], None,
+                       float(ref_lat.vals[:, 0].max()), float(np.abs(p.obs).max()))
+    lat.close()
+
+
+def test_estep_full_size_depth_frame_sampled(fr, ctx):
+    """Config-2 scale (about 260k points, d = 6, V = 7) in the launch configuration of the benchmark;
+    the oracle checks a sample of 4000 points one by one."""
+    p = synth.depth_pair(2)
+    _say(f"[estep-full] M={len(p.model)} N={len(p.obs)}")
+    obs = upload([p.obs], [p.obs_n])
+    model = upload([p.model], [p.model_n])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 0))
+    M = len(p.model)
+    T = p.T_gt @ oracle.se3_exp(np.array([0.003, -0.002, 0.001, 0.004, 0.002, -0.003]))
+    mat = oracle.pose_to_mat12(T)
+    xf = fr.XForm(fr.FR_XF_RIGID, torch.from_numpy(mat.copy()).cuda(), n_seg=1)
+    m0 = torch.empty(M, device="cuda")
+    m1 = torch.empty(3 * M, device="cuda")
+    ns = torch.empty(3 * M, device="cuda")
+    fr.fr_estep(lat.h, model, xf, m0, m1, ns)
+    idx = np.sort(np.random.default_rng(0).choice(M, 4000, replace=False))
+    ref_lat = oracle_lattice(p.obs, p.obs_n, 6, "pt2pl", p.sigma, p.sigma_n)
+    x32 = oracle.transform_f32(mat, p.model[idx])
+    n32 = oracle.transform_f32(mat, p.model_n[idx], translate=False)
+    g = oracle.lattice_slice(ref_lat, oracle.features(x32, n32, 6))
+    assert (g[:, 0] > 0).mean() > 0.5
+    assert_estep_close(soa(m0)[idx], soa(m1).reshape(3, M).T[idx], soa(ns).reshape(3, M).T[idx], g[:, 0],
+                       g[:, 1:4], g[:, 4:7], float(ref_lat.vals[:, 0].max()), float(np.abs(p.obs).max()))
+    # property at any size: M0 >= 0 everywhere and M1/M0 within the lattice's bounding box
+    a0 = soa(m0)
+    assert a0.min() >= 0.0
+    lat.close()
+
+
+@pytest.mark.parametrize("residual", ["pt2pt", "pt2pl"])
+def test_mstep_reduce_parity(fr, ctx, residual):
+    rng = np.random.default_rng(3)
+    M = 5000 + 333
+    x_ref = rng.normal(scale=0.5, size=(M, 3)).astype(np.float32)
+    m0 = rng.uniform(0.0, 3.0, size=M).astype(np.float32)
+    m0[rng.uniform(size=M) < 0.2] = 0.0
+    m1 = ((x_ref + rng.normal(scale=0.01, size=(M, 3))) * m0[:, None]).astype(np.float32)
+    ns = (rng.normal(size=(M, 3)) * m0[:, None]).astype(np.float32)
+    T = synth.random_motion(rng, 0.2, 0.1)
+    mat = oracle.pose_to_mat12(T)
+    model = upload([x_ref])
+    xf = fr.XForm(fr.FR_XF_RIGID, torch.from_numpy(mat.copy()).cuda(), n_seg=1)
+    tm0 = torch.from_numpy(m0).cuda()
+    tm1 = torch.from_numpy(np.ascontiguousarray(m1.T).reshape(-1)).cuda()
+    tns = torch.from_numpy(np.ascontiguousarray(ns.T).reshape(-1)).cuda()
+    jtj = torch.zeros(21, dtype=torch.float64, device="cuda")
+    jtr = torch.zeros(6, dtype=torch.float64, device="cuda")
+    st = torch.zeros(4, dtype=torch.float64, device="cuda")
+    c, sigma = 0.37, 0.02
+    res = fr.FR_PT2PL if residual == "pt2pl" else fr.FR_PT2PT
+    fr.fr_mstep_reduce(model, xf, tm0, tm1, tns, res, c, sigma, jtj, jtr, st)
+    R = mat.reshape(3, 4).astype(np.float64)
+    x64 = x_ref.astype(np.float64) @ R[:, :3].T + R[:, 3]
+    A, b, stats = oracle.normal_equations(x64, m0, m1, ns, c, sigma, residual)
+    sA, sb = abs_scales(x64, m0, m1, ns, c, sigma, residual)
+    assert (np.abs(soa(jtj) - upper(A)) <= 1e-5 * upper(sA) + 1e-12).all()
+    assert (np.abs(soa(jtr) - b) <= 1e-5 * sb + 1e-12).all()
+    np.testing.assert_allclose(soa(st), stats, rtol=1e-5)
+
+
+def test_mstep_reduce_segments_and_bitwise_repeat(fr, ctx):
+    rng = np.random.default_rng(9)
+    M = 4099
+    x_ref = rng.normal(size=(M, 3)).astype(np.float32)
+    m0 = rng.uniform(0.1, 2.0, size=M).astype(np.float32)
+    m1 = (x_ref * m0[:, None]).astype(np.float32) + 0.01
+    off = [0, 1000, 1000, 3100, M]
+    Ts = [synth.random_motion(rng, 0.1, 0.05) for _ in range(4)]
+    mats = torch.from_numpy(np.concatenate([oracle.pose_to_mat12(T) for T in Ts])).cuda()
+    model = upload([x_ref])
+    xf = fr.XForm(fr.FR_XF_SEGMENTED, mats, seg_offsets=off)
+    tm0 = torch.from_numpy(m0).cuda()
+    tm1 = torch.from_numpy(np.ascontiguousarray(m1.T).reshape(-1)).cuda()
+    outs = []
+    for _ in range(2):
+        jtj = torch.zeros(4 * 21, dtype=torch.float64, device="cuda")
+        jtr = torch.zeros(4 * 6, dtype=torch.float64, device="cuda")
+        st = torch.zeros(4 * 4, dtype=torch.float64, device="cuda")
+        fr.fr_mstep_reduce(model, xf, tm0, tm1, None, fr.FR_PT2PT, 0.5, 0.03, jtj, jtr, st)
+        outs.append((soa(jtj), soa(jtr), soa(st)))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    for s in range(4):
+        sl = slice(off[s], off[s + 1])
+        R = oracle.pose_to_mat12(Ts[s]).reshape(3, 4).astype(np.float64)
+        x64 = x_ref[sl].astype(np.float64) @ R[:, :3].T + R[:, 3]
+        A, b, stats = oracle.normal_equations(x64, m0[sl], m1[sl], None, 0.5, 0.03, "pt2pt")
+        sA, sb = abs_scales(x64, m0[sl], m1[sl], None, 0.5, 0.03, "pt2pt")
+        assert (np.abs(outs[0][0][21 * s:21 * s + 21] - upper(A)) <= 1e-5 * upper(sA) + 1e-12).all()
+        assert (np.abs(outs[0][1][6 * s:6 * s + 6] - b) <= 1e-5 * sb + 1e-12).all()
+        np.testing.assert_allclose(outs[0][2][4 * s:4 * s + 4], stats, rtol=1e-5, atol=1e-12)
+
+
+def test_solve_rigid_parity(fr, ctx):
+    rng = np.random.default_rng(4)
+    n = 7
+    As, bs, Ts = [], [], []
+    for i in range(n):
+        G = rng.normal(size=(6, 6))
+        As.append(G @ G.T + 0.1 * np.eye(6))
+        bs.append(rng.normal(size=6) * 10 ** rng.uniform(-6, -1))
+        Ts.append(synth.random_motion(rng, 1.0, 1.0))
+    As[3] = np.zeros((6, 6))   # degenerate
+    jtj = torch.tensor(np.concatenate([upper(A) for A in As]), dtype=torch.float64, device="cuda")
+    jtr = torch.tensor(np.concatenate(bs), dtype=torch.float64, device="cuda")
+    poses = torch.tensor(np.stack(Ts).reshape(-1), dtype=torch.float64, device="cuda")
+    mats = torch.zeros(n * 12, dtype=torch.float32, device="cuda")
+    tn = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    fr.fr_solve_rigid(n, jtj, jtr, poses, mats, tn, status)
+    P = soa(poses).reshape(n, 4, 4)
+    S = soa(status)
+    for i in range(n):
+        if i == 3:
+            assert S[i] == fr.FR_EDEGENERATE
+            np.testing.assert_array_equal(P[i], Ts[i])
+            continue
+        assert S[i] == 0
+        dz = oracle.gn_step(As[i], bs[i])
+        ref = oracle.se3_exp(dz) @ Ts[i]
+        np.testing.assert_allclose(P[i], ref, atol=1e-12)
+        np.testing.assert_array_equal(soa(mats).reshape(n, 12)[i], oracle.pose_to_mat12(ref))
+        np.testing.assert_allclose(soa(tn).reshape(n, 2)[i], [np.linalg.norm(dz[:3]), np.linalg.norm(dz[3:])],
+                                   rtol=1e-12)
+
+
+def test_register_parity_ellipsoid(fr, ctx):
+    p = synth.ellipsoid_pair(1)
+    _say(f"[register] ellipsoid M={len(p.model)} N={len(p.obs)} pt2pt d=3, 30 iterations")
+    T0 = p.T_gt @ oracle.se3_exp(np.array([0.01, -0.01, 0.005, 0.004, 0.0, -0.003]))
+    ref = oracle.register_rigid(p.model, None, p.obs, None, feat=3, residual="pt2pt", sigma=p.sigma, w=p.w,
+                                iters=p.iters, T0=T0)
+    prm = fr.register_params(3, "pt2pt", p.sigma, iters=p.iters, w=p.w)
+    T, status, rep = fr.register(ctx, upload([p.model]), upload([p.obs]), prm, T0=T0[None])
+    ang, dt, ok = pose_close(T[0], ref)
+    assert status[0] == 0 and ok, (ang, dt)
+    assert rep.iterations == p.iters
+
+
+@pytest.mark.parametrize("feat,residual", [(3, "pt2pt"), (6, "pt2pl"), (3, "pt2pl")])
+def test_register_exact_recovery(fr, ctx, feat, residual):
+    p = synth.separated_pair(8, 700, feat=feat, residual=residual)
+    prm = fr.register_params(feat, residual, p.sigma, p.sigma_n, iters=12, c=0.0)
+    T, status, _ = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm,
+                               T0=p.extra["T0"][None])
+    assert status[0] == 0
+    assert np.abs(T[0] - p.T_gt).max() < 1e-5
+    assert oracle.alignment_error(T[0], p.T_gt, p.model) < 1e-5
+
+
+def test_register_parity_depth_batch_and_alone_bitwise(fr, ctx):
+    """Three depth pairs of different sizes registered alone and as one batch: identical poses,
+    all within tolerance of the oracle."""
+    pairs = [synth.depth_pair(s, width=w, height=h, f=f) for s, (w, h, f) in
+             enumerate([(160, 120, 131.25), (96, 72, 78.75), (200, 150, 164.06)])]
+    T0s = [q.T_gt @ oracle.se3_exp(np.array([0.004, -0.003, 0.002, 0.004, 0.003, -0.002])) for q in pairs]
+    prm = fr.register_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, iters=15, w=0.1)
+    _say("[register] depth batch of 3 " + str([len(q.model) for q in pairs]))
+    Tb, sb, _ = fr.register(ctx, upload([q.model for q in pairs], [q.model_n for q in pairs]),
+                            upload([q.obs for q in pairs], [q.obs_n for q in pairs]), prm, T0=np.stack(T0s))
+    assert (sb == 0).all()
+    for i, q in enumerate(pairs):
+        Ta, sa, _ = fr.register(ctx, upload([q.model], [q.model_n]), upload([q.obs], [q.obs_n]), prm,
+                                T0=T0s[i][None])
+        np.testing.assert_array_equal(Ta[0], Tb[i])
+        ref = oracle.register_rigid(q.model, q.model_n, q.obs, q.obs_n, feat=6, residual="pt2pl", sigma=q.sigma,
+                                    sigma_n=q.sigma_n, w=0.1, iters=15, T0=T0s[i])
+        ang, dt, ok = pose_close(Tb[i], ref)
+        assert ok, (i, ang, dt)
+
+
+def test_sorted_build_is_bitwise_deterministic(fr, ctx):
+    p = synth.depth_pair(5, width=320, height=240, f=262.5)
+    obs = upload([p.obs], [p.obs_n])
+    a = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 0)).export(0)
+    b = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 0)).export(0)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    c = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 1)).export(0)
+    np.testing.assert_array_equal(a[0], c[0])
+    np.testing.assert_array_equal(a[1], c[1])
+    np.testing.assert_allclose(a[2], c[2], rtol=1e-5, atol=1e-5)
+
+
+def test_edge_cases(fr, ctx):
+    p = synth.random_cloud_pair(2, 300, 301)
+    # a batch with an empty observation set, an empty model set and a single point
+    obs = upload([p.obs, np.zeros((0, 3), np.float32), p.obs[:1], p.obs[:50]])
+    model = upload([p.model, p.model[:10], np.zeros((0, 3), np.float32), p.model[:50]])
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(3, 4, p.sigma))
+    assert lat.stats(1)[0] == 0 and lat.stats(2)[0] == 4
+    M = model.n
+    m0 = torch.full((M,), -1.0, device="cuda")
+    m1 = torch.full((3 * M,), -1.0, device="cuda")
+    xf = fr.XForm(fr.FR_XF_NONE)
+    fr.fr_estep(lat.h, model, xf, m0, m1)
+    a0 = soa(m0)
+    assert (a0[300:310] == 0).all()          # empty lattice -> no support, zeros written
+    for s, (o, y) in enumerate([(p.obs, p.model), (None, None), (p.obs[:1], None), (p.obs[:50], p.model[:50])]):
+        if y is None:
+            continue
+        ref = oracle_lattice(o, None, 3, "pt2pt", p.sigma, 0.5)
+        g = oracle.lattice_slice(ref, oracle.features(y, None, 3))
+        lo = int(model.offsets[s])
+        np.testing.assert_allclose(a0[lo:lo + len(y)], g[:, 0], rtol=1e-5, atol=1e-6)
+    lat.close()
+    # registration of a pair with no observation is degenerate, the others still succeed
+    prm = fr.register_params(3, "pt2pt", p.sigma, iters=3, w=0.0)
+    T, status, _ = fr.register(ctx, upload([p.model, p.model]), upload([p.obs, np.zeros((0, 3), np.float32)]), prm)
+    assert status[0] == 0 and status[1] == fr.FR_EDEGENERATE
+    # key range overflow is reported, not silently wrapped
+    far = (p.obs * 0 + 1.0e5).astype(np.float32)
+    with pytest.raises(fr.FRError) as e:
+        fr.Lattice(ctx, upload([far]), fr.lattice_params(3, 4, (0.01, 0.01, 0.01)))
+    assert e.value.status == fr.FR_ERANGE
+    # argument errors
+    with pytest.raises(fr.FRError) as e:
+        fr.Lattice(ctx, upload([p.obs]), fr.lattice_params(3, 4, (0.0, 0.01, 0.01)))
+    assert e.value.status == fr.FR_EINVAL
+    with pytest.raises(fr.FRError) as e:
+        fr.Lattice(ctx, upload([p.obs]), fr.lattice_params(6, 7, p.sigma))   # feat 6 without normals
+    assert e.value.status == fr.FR_EINVAL
+
+
+def test_budget_is_enforced(fr):
+    p = synth.random_cloud_pair(2, 300, 3000)
+    small = fr.Context(0, hbm_budget_bytes=64 * 1024)
+    with pytest.raises(fr.FRError) as e:
+        fr.Lattice(small, upload([p.obs]), fr.lattice_params(3, 4, p.sigma))
+    assert e.value.status == fr.FR_EBUDGET
+    assert fr.fr_ctx_usage(small.h) == 0
+    small.close()
