@@ -52,7 +52,7 @@ enum { FR_VAL_PT2PT = 4, FR_VAL_PT2PL = 7 };              /* value channels V of
 enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
 enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
 enum { FR_PT2PT = 0, FR_PT2PL = 1 };
-enum { FR_KIN_RIGID = 0 };
+enum { FR_KIN_RIGID = 0, FR_KIN_ARTICULATED = 1 };
 enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4 };
 
 typedef struct fr_ctx fr_ctx;
@@ -233,6 +233,52 @@ typedef struct {
  */
 fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_register_params *params,
                       double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
+
+/*
+ * Kinematic tree of an articulated model (Sec. 5.1).  Body b (0 <= b < n_bodies)
+ * hangs from parent[b] < b (-1 = world) at the joint origin origin[3b..3b+2]
+ * given in the parent's frame, and owns the revolute DOFs
+ * [dof_offset[b], dof_offset[b+1]).  Its frame is
+ *   T_b = T_parent . Trans(origin_b) . Rot(axis_k0, theta_k0) . Rot(axis_k1, theta_k1) ...
+ * with each unit axis[3k..3k+2] given in the frame left by the preceding
+ * rotations.  All arrays are host memory; at most 128 bodies and 64 DOFs.
+ */
+typedef struct {
+    int32_t n_bodies;
+    const int32_t *parent;
+    const int32_t *dof_offset;
+    const double *origin;
+    const double *axis;
+} fr_kinematic_tree;
+
+/*
+ * Articulated Gauss-Newton step on the device in binary64 (Eq. 19-20, Alg. 1
+ * lines 5-9): given per-body sums jtj (device, n_bodies x 21, upper triangle
+ * row-major) and jtr (device, n_bodies x 6) from fr_mstep_reduce segmented by
+ * body at the current angles, builds the spatial velocity Jacobian of every
+ * body by forward kinematics (DOF k moves the bodies below its joint with the
+ * twist (w_k, q_k x w_k) of its world axis w_k through the joint point q_k),
+ * assembles A = sum_b J_b^T jtj_b J_b and b = sum_b J_b^T jtr_b, solves
+ * A dtheta = -b by Cholesky, updates theta (device, n_dof) in place and writes
+ * the binary32 [R | t] of every body at the new angles to mats (device,
+ * n_bodies x 12).  status (device int32, may be NULL) receives FR_OK or
+ * FR_EDEGENERATE (theta unchanged).  jtj/jtr may be NULL for forward
+ * kinematics only (theta unchanged, mats written).
+ */
+fr_status fr_articulated_step(fr_ctx *ctx, const fr_kinematic_tree *tree, const double *jtj, const double *jtr,
+                              double *theta, float *mats, int32_t *status, void *stream);
+
+/*
+ * Articulated registration (Sec. 3.1 with the kinematics of Sec. 5.1) of one
+ * model (one set, points grouped by body: body_offsets host, n_bodies + 1)
+ * onto one observation set.  theta_inout_h (host, n_dof) holds the start
+ * angles and receives the result.  Synchronous; FR_EDEGENERATE if the
+ * normal equations degenerate (theta left at the last good value).
+ */
+fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const int64_t *body_offsets,
+                                  const fr_cloud *obs, const fr_kinematic_tree *tree,
+                                  const fr_register_params *params, double *theta_inout_h, fr_report *report_h,
+                                  void *stream);
 
 /* Return (and clear) a device fault latched in `lat` by earlier async calls; synchronises. */
 fr_status fr_sync_status(const fr_lattice *lat);

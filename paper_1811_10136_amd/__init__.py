@@ -33,7 +33,7 @@ FR_VAL_PT2PT, FR_VAL_PT2PL = 4, 7
 FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
 FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
-FR_KIN_RIGID = 0
+FR_KIN_RIGID, FR_KIN_ARTICULATED = 0, 1
 FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED = 1, 2, 4
 
 STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
@@ -76,6 +76,12 @@ class fr_register_params(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("kinematics", ctypes.c_int32)]
 
 
+class fr_kinematic_tree(ctypes.Structure):
+    _fields_ = [("n_bodies", ctypes.c_int32), ("parent", ctypes.POINTER(ctypes.c_int32)),
+                ("dof_offset", ctypes.POINTER(ctypes.c_int32)), ("origin", ctypes.POINTER(ctypes.c_double)),
+                ("axis", ctypes.POINTER(ctypes.c_double))]
+
+
 class fr_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("n_degenerate", ctypes.c_int32), ("build_ms", ctypes.c_double),
                 ("em_ms", ctypes.c_double), ("estep_ms", ctypes.c_double), ("mstep_ms", ctypes.c_double),
@@ -114,10 +120,15 @@ _sig("fr_solve_rigid", _st, [_i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("fr_register", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
                           ctypes.POINTER(fr_register_params), _P, _P, ctypes.POINTER(fr_report), _P])
 _sig("fr_sync_status", _st, [_P])
+_sig("fr_articulated_step", _st, [_P, ctypes.POINTER(fr_kinematic_tree), _P, _P, _P, _P, _P, _P])
+_sig("fr_register_articulated", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_kinematic_tree),
+                                      ctypes.POINTER(fr_register_params), _P, ctypes.POINTER(fr_report), _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
-                 "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status"]
+                 "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status",
+                 "fr_articulated_step", "fr_register_articulated"]
 
 
 def _check(status: int):
@@ -367,3 +378,50 @@ def register(ctx: Context, model: Cloud, obs: Cloud, params: fr_register_params,
     theta = np.repeat(np.eye(4)[None], S, 0) if T0 is None else np.array(T0, dtype=np.float64).reshape(S, 4, 4)
     status, rep = fr_register(ctx.h, model, obs, params, theta, stream)
     return theta, status, rep
+
+
+# --- articulated models ------------------------------------------------------------
+class KinematicTree:
+    """fr_kinematic_tree over host arrays kept alive by this object (Sec. 5.1)."""
+
+    def __init__(self, parent, dof_offset, origin, axis):
+        self.parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.dof_offset = np.ascontiguousarray(dof_offset, dtype=np.int32)
+        self.origin = np.ascontiguousarray(origin, dtype=np.float64).reshape(-1)
+        self.axis = np.ascontiguousarray(axis, dtype=np.float64).reshape(-1)
+        self._c = fr_kinematic_tree(len(self.parent),
+                                    self.parent.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    self.dof_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    self.origin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    self.axis.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    @property
+    def n_bodies(self):
+        return len(self.parent)
+
+    @property
+    def n_dof(self):
+        return int(self.dof_offset[-1])
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def fr_articulated_step(ctx, tree: KinematicTree, jtj, jtr, theta, mats, status=None, stream=None):
+    _check(_lib.fr_articulated_step(ctx, tree.c(), _ptr(jtj), _ptr(jtr), _ptr(theta), _ptr(mats), _ptr(status),
+                                    _stream(stream)))
+
+
+def fr_register_articulated(ctx, model: Cloud, body_offsets, obs: Cloud, tree: KinematicTree,
+                            params: fr_register_params, theta: np.ndarray, stream=None):
+    """theta: (n_dof,) float64 start angles, updated in place.  Returns (status, report)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    bo = np.ascontiguousarray(body_offsets, dtype=np.int64)
+    rep = fr_report()
+    st = _lib.fr_register_articulated(ctx, model.c(), bo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), obs.c(),
+                                      tree.c(), ctypes.byref(params), th.ctypes.data, ctypes.byref(rep),
+                                      _stream(stream))
+    theta[...] = th
+    if st not in (FR_OK, FR_EDEGENERATE):
+        _check(st)
+    return st, rep

@@ -188,11 +188,13 @@ static fr_status check_lattice_params(const fr_lattice_params *p)
 
 static void free_lattice(fr_lattice *lat)
 {
-    if (lat->table) dev_free(lat->ctx, lat->table, lat->table_bytes);
+    if (lat->tkey) dev_free(lat->ctx, lat->tkey, lat->tkey_bytes);
+    if (lat->tval) dev_free(lat->ctx, lat->tval, lat->tval_bytes);
     if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable));
     if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes);
     if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t));
-    lat->table = nullptr;
+    lat->tkey = nullptr;
+    lat->tval = nullptr;
     lat->sets_d = nullptr;
     lat->vkey = nullptr;
     lat->err_d = nullptr;
@@ -398,11 +400,11 @@ fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertic
     FR_TRY(fr_sync_status(lat));
     const SetTable &st = lat->sets_h[set];
     const int KW = lat->KW;
-    const int NQ = (2 * KW + lat->V + 3) / 4;
+    const int VP = lat->V <= 4 ? 4 : 8;
     if (n_vertices) *n_vertices = st.n_vertices;
-    if (capacity) *capacity = (int64_t)st.mask + 1;
+    if (capacity) *capacity = (int64_t)st.cap;
     if (device_bytes)
-        *device_bytes = ((int64_t)st.mask + 1) * 16 * NQ +
+        *device_bytes = (int64_t)st.cap * (KW * 8 + VP * 4) +
                         (int64_t)st.n_vertices * (KW * 8 + 4 + 4 * lat->V);
     return FR_OK;
 }
@@ -502,7 +504,7 @@ fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, con
     FR_HIP(hipSetDevice(lat->ctx->device));
     hipStream_t st = nullptr;
     const SetTable &t = lat->sets_h[set];
-    const size_t total_slots = lat->table_bytes / (16 * ((2 * lat->KW + lat->V + 3) / 4));
+    const size_t total_slots = (size_t)lat->n_slots;
     DevBuf flags;
     FR_TRY(flags.alloc(lat->ctx, total_slots * sizeof(uint32_t)));
     FR_HIP(hipMemset(flags.p, 0, total_slots * sizeof(uint32_t)));
@@ -512,7 +514,7 @@ fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, con
     FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, nullptr, nullptr,
                         nullptr, flags.as<uint32_t>(), st));
     FR_HIP(hipDeviceSynchronize());
-    std::vector<uint32_t> h((size_t)t.mask + 1);
+    std::vector<uint32_t> h((size_t)t.cap);
     FR_HIP(hipMemcpy(h.data(), flags.as<uint32_t>() + t.slot_base, h.size() * sizeof(uint32_t),
                      hipMemcpyDeviceToHost));
     int64_t n = 0;
@@ -728,6 +730,147 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     FR_TRY(fr_sync_status(lat));
     if (n_deg > 0) {
         set_error("fr_register: %d set(s) had a degenerate normal-equation system", n_deg);
+        return FR_EDEGENERATE;
+    }
+    return FR_OK;
+}
+
+
+fr_status fr_articulated_step(fr_ctx *ctx, const fr_kinematic_tree *tree, const double *jtj, const double *jtr,
+                              double *theta, float *mats, int32_t *status, void *stream)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || tree == nullptr || theta == nullptr || mats == nullptr || ((jtj == nullptr) != (jtr == nullptr))) {
+        set_error("fr_articulated_step: invalid argument");
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ArtTreeHost t;
+    FR_TRY(upload_tree(ctx, tree, st, t));
+    FR_TRY(launch_articulated_step(t, jtj ? 1 : 0, jtj, jtr, theta, mats, nullptr, status, st));
+    FR_HIP(hipStreamSynchronize(st));
+    return FR_OK;
+}
+
+fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const int64_t *body_offsets,
+                                  const fr_cloud *obs, const fr_kinematic_tree *tree,
+                                  const fr_register_params *params, double *theta_inout_h, fr_report *report_h,
+                                  void *stream)
+{
+    clear_error();
+    using clk = std::chrono::steady_clock;
+    if (!ctx_ok(ctx) || params == nullptr || theta_inout_h == nullptr || tree == nullptr || body_offsets == nullptr) {
+        set_error("fr_register_articulated: invalid context, params, tree, body offsets or theta");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_lattice_params(&params->lattice));
+    if ((params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
+        (params->residual == FR_PT2PL && params->lattice.values != FR_VAL_PT2PL) || params->max_iters < 0 ||
+        !(params->w >= 0.0 && params->w < 1.0)) {
+        set_error("fr_register_articulated: bad residual/values, max_iters or w");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register_articulated(model)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register_articulated(obs)"));
+    if (model_ref->n_sets != 1 || obs->n_sets != 1) {
+        set_error("fr_register_articulated: one model set and one observation set");
+        return FR_EINVAL;
+    }
+    const int32_t B = tree->n_bodies;
+    const int64_t M = cloud_points(model_ref);
+    fr_xform xf{FR_XF_SEGMENTED, B, nullptr, body_offsets};
+    if (B < 1 || body_offsets[0] != 0 || body_offsets[B] != M) {
+        set_error("fr_register_articulated: body_offsets must partition [0, M)");
+        return FR_EINVAL;
+    }
+    for (int32_t b = 0; b < B; ++b)
+        if (body_offsets[b + 1] < body_offsets[b]) {
+            set_error("fr_register_articulated: body_offsets must be non-decreasing");
+            return FR_EINVAL;
+        }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ArtTreeHost t;
+    FR_TRY(upload_tree(ctx, tree, st, t));
+    const int32_t n = t.n_dof;
+    fr_report rep{};
+
+    auto t0 = clk::now();
+    fr_lattice *lat = nullptr;
+    FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat));
+    struct LatGuard {
+        fr_lattice *l;
+        ~LatGuard()
+        {
+            if (l) fr_lattice_destroy(l);
+        }
+    } guard{lat};
+    auto t1 = clk::now();
+    rep.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
+    double c = 0.0;
+    if (params->c_override >= 0.0) c = params->c_override;
+    else if (M > 0 && params->w > 0.0)
+        c = params->w / (1.0 - params->w) * ((double)cloud_points(obs) / (double)M) * std::pow(2.0 * M_PI, 1.5) * s3;
+    const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
+
+    Plan pe, pr;
+    FR_TRY(make_plan(ctx, model_ref, &xf, 256, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, model_ref, &xf, 1024, &c, st, pr));
+    const bool pl = params->residual == FR_PT2PL;
+    const size_t nM = (size_t)std::max<int64_t>(M, 1);
+    DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wth, wmats, wnorm, wstatus;
+    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+    if (lat->V == 7) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
+    FR_TRY(part.alloc(ctx, reduce_partials_floats(pr) * sizeof(float)));
+    FR_TRY(wjtj.alloc(ctx, B * 21 * sizeof(double)));
+    FR_TRY(wjtr.alloc(ctx, B * 6 * sizeof(double)));
+    FR_TRY(wstat.alloc(ctx, B * 4 * sizeof(double)));
+    FR_TRY(wth.alloc(ctx, n * sizeof(double)));
+    FR_TRY(wmats.alloc(ctx, B * 12 * sizeof(float)));
+    FR_TRY(wnorm.alloc(ctx, sizeof(double)));
+    FR_TRY(wstatus.alloc(ctx, sizeof(int32_t)));
+    int32_t status_h = FR_OK;
+    FR_HIP(hipMemcpyAsync(wth.p, theta_inout_h, n * sizeof(double), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wstatus.p, &status_h, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_TRY(launch_articulated_step(t, 0, nullptr, nullptr, wth.as<double>(), wmats.as<float>(), nullptr, nullptr, st));
+    FR_HIP(hipStreamSynchronize(st));
+
+    const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
+    auto t2 = clk::now();
+    int it = 0;
+    for (; it < params->max_iters; ++it) {
+        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_SEGMENTED, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                            lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+        FR_TRY(launch_reduce(model_ref, pr, FR_XF_SEGMENTED, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                             pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
+                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+        FR_TRY(launch_articulated_step(t, 1, wjtj.as<double>(), wjtr.as<double>(), wth.as<double>(),
+                                       wmats.as<float>(), wnorm.as<double>(), wstatus.as<int32_t>(), st));
+        if (!fixed || it + 1 == params->max_iters) {
+            double nrm = 0.0;
+            FR_HIP(hipMemcpyAsync(&nrm, wnorm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipMemcpyAsync(&status_h, wstatus.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipStreamSynchronize(st));
+            if (status_h != FR_OK || (!fixed && nrm < params->twist_tol)) {
+                ++it;
+                break;
+            }
+        }
+    }
+    FR_HIP(hipMemcpyAsync(theta_inout_h, wth.p, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(&status_h, wstatus.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    rep.iterations = it;
+    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t2).count();
+    rep.n_degenerate = status_h != FR_OK ? 1 : 0;
+    if (report_h) *report_h = rep;
+    FR_TRY(fr_sync_status(lat));
+    if (status_h != FR_OK) {
+        set_error("fr_register_articulated: degenerate normal equations");
         return FR_EDEGENERATE;
     }
     return FR_OK;

@@ -1,0 +1,273 @@
+// Articulated Gauss-Newton step in binary64 on the device (Sec. 5.1, Eq. 19-20,
+// Alg. 1 lines 5-9): one block per kinematic tree.
+//
+// Inputs are the per-body sums S_b = sum J^T J (6x6) and g_b = sum J^T r of the
+// points on body b, reduced by the segmented M-step kernel (Alg. 1 lines 1-4).
+// The block runs forward kinematics at the current joint angles to get, for
+// every revolute DOF k, its world axis w_k and a point q_k on it; DOF k moves
+// every body below its joint with the twist u_k = (w_k, q_k x w_k) (the twist
+// convention of Eq. 16), so the spatial velocity Jacobian of body b has column
+// u_k for the DOFs of b and its ancestors.  Then
+//   A[k][l] = sum_{b moved by k and l} u_k^T S_b u_l,   rhs[k] = sum_{b moved by k} u_k . g_b,
+// a Cholesky solve gives dtheta = -A^-1 rhs, theta += dtheta, and a second
+// forward kinematics pass writes the binary32 [R | t] of every body for the
+// next E-step.
+//
+// Tree layout (device, built by the host): parent[B], dof_off[B + 1],
+// origin[3B] (joint origin in the parent frame), axis[3 n_dof] (unit axis in
+// the frame left by the preceding rotations), moved_by[B] (bit k set if DOF k
+// moves body b).  n_dof <= 64.
+#include "fr_internal.h"
+
+namespace fr {
+
+constexpr int kArtThreads = 256;
+constexpr int kArtMaxDof = 64;
+constexpr int kArtMaxBodies = 128;
+
+struct ArtTree {
+    int32_t n_bodies, n_dof;
+    const int32_t *parent;
+    const int32_t *dof_off;
+    const double *origin;
+    const double *axis;
+    const uint64_t *moved_by;
+};
+
+// R = exp(angle [a]_x) for a unit axis a (two-term series below |angle| = 1e-4).
+__device__ inline void axis_rotation(const double *a, double angle, double (&R)[3][3])
+{
+    double s, c1;
+    const double t2 = angle * angle;
+    if (fabs(angle) < 1e-4) {
+        s = angle * (1.0 - t2 / 6.0);
+        c1 = t2 * (0.5 - t2 / 24.0);
+    } else {
+        s = sin(angle);
+        c1 = 1.0 - cos(angle);
+    }
+    const double K[3][3] = {{0.0, -a[2], a[1]}, {a[2], 0.0, -a[0]}, {-a[1], a[0], 0.0}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double K2 = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+            R[i][j] = (i == j ? 1.0 : 0.0) + s * K[i][j] + c1 * K2;
+        }
+}
+
+// Forward kinematics by one thread: body frames (R in bodyR[9b], t in bodyT[3b])
+// and per-DOF world axis w (3k) and point q (3k).
+__device__ void forward_kinematics(const ArtTree &t, const double *theta, double *bodyR, double *bodyT, double *w,
+                                   double *q)
+{
+    for (int b = 0; b < t.n_bodies; ++b) {
+        double R[3][3], p[3];
+        const int pa = t.parent[b];
+        if (pa < 0) {
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
+                p[i] = 0.0;
+            }
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) R[i][j] = bodyR[9 * pa + 3 * i + j];
+                p[i] = bodyT[3 * pa + i];
+            }
+        }
+        // joint origin: F = P . Trans(o)
+        double o[3];
+        for (int i = 0; i < 3; ++i)
+            o[i] = R[i][0] * t.origin[3 * b] + R[i][1] * t.origin[3 * b + 1] + R[i][2] * t.origin[3 * b + 2] + p[i];
+        for (int k = t.dof_off[b]; k < t.dof_off[b + 1]; ++k) {
+            const double *a = t.axis + 3 * k;
+            for (int i = 0; i < 3; ++i) {
+                w[3 * k + i] = R[i][0] * a[0] + R[i][1] * a[1] + R[i][2] * a[2];
+                q[3 * k + i] = o[i];
+            }
+            double Q[3][3], N[3][3];
+            axis_rotation(a, theta[k], Q);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) N[i][j] = R[i][0] * Q[0][j] + R[i][1] * Q[1][j] + R[i][2] * Q[2][j];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) R[i][j] = N[i][j];
+        }
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) bodyR[9 * b + 3 * i + j] = R[i][j];
+            bodyT[3 * b + i] = o[i];
+        }
+    }
+}
+
+// mode 0: forward kinematics only (writes mats); mode 1: Gauss-Newton step + forward kinematics.
+__global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, int mode, const double *jtj,
+                                                                  const double *jtr, double *theta, float *mats,
+                                                                  double *step_norm, int32_t *status)
+{
+    __shared__ double s_th[kArtMaxDof], s_w[3 * kArtMaxDof], s_q[3 * kArtMaxDof], s_u[6 * kArtMaxDof];
+    __shared__ double s_A[kArtMaxDof * kArtMaxDof], s_rhs[kArtMaxDof], s_x[kArtMaxDof];
+    __shared__ double s_R[9 * kArtMaxBodies], s_T[3 * kArtMaxBodies];
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const int n = tree.n_dof;
+    for (int k = tid; k < n; k += kArtThreads) s_th[k] = theta[k];
+    if (tid == 0) s_ok = 1;
+    __syncthreads();
+    if (mode == 1) {
+        if (tid == 0) forward_kinematics(tree, s_th, s_R, s_T, s_w, s_q);
+        __syncthreads();
+        for (int k = tid; k < n; k += kArtThreads) {
+            const double *w = s_w + 3 * k, *q = s_q + 3 * k;
+            s_u[6 * k + 0] = w[0];
+            s_u[6 * k + 1] = w[1];
+            s_u[6 * k + 2] = w[2];
+            s_u[6 * k + 3] = q[1] * w[2] - q[2] * w[1];
+            s_u[6 * k + 4] = q[2] * w[0] - q[0] * w[2];
+            s_u[6 * k + 5] = q[0] * w[1] - q[1] * w[0];
+        }
+        __syncthreads();
+        // A[k][l] = sum over bodies moved by k and l of u_k^T S_b u_l (upper triangle, then mirrored)
+        for (int e = tid; e < n * n; e += kArtThreads) {
+            const int k = e / n, l = e % n;
+            if (l < k) continue;
+            double acc = 0.0;
+            for (int b = 0; b < tree.n_bodies; ++b) {
+                const uint64_t mb = tree.moved_by[b];
+                if (!((mb >> k) & 1ull) || !((mb >> l) & 1ull)) continue;
+                const double *S = jtj + 21 * b;
+                double Su[6];
+                int idx = 0;
+                double Sf[6][6];
+                for (int i = 0; i < 6; ++i)
+                    for (int j = i; j < 6; ++j) {
+                        Sf[i][j] = S[idx];
+                        Sf[j][i] = S[idx];
+                        ++idx;
+                    }
+                for (int i = 0; i < 6; ++i) {
+                    double v = 0.0;
+                    for (int j = 0; j < 6; ++j) v += Sf[i][j] * s_u[6 * l + j];
+                    Su[i] = v;
+                }
+                for (int i = 0; i < 6; ++i) acc += s_u[6 * k + i] * Su[i];
+            }
+            s_A[k * n + l] = acc;
+            s_A[l * n + k] = acc;
+        }
+        for (int k = tid; k < n; k += kArtThreads) {
+            double acc = 0.0;
+            for (int b = 0; b < tree.n_bodies; ++b) {
+                if (!((tree.moved_by[b] >> k) & 1ull)) continue;
+                for (int i = 0; i < 6; ++i) acc += s_u[6 * k + i] * jtr[6 * b + i];
+            }
+            s_rhs[k] = acc;
+        }
+        __syncthreads();
+        // Cholesky A = L L^T in place (lower triangle), column by column
+        for (int j = 0; j < n; ++j) {
+            if (tid == 0) {
+                double v = s_A[j * n + j];
+                for (int k = 0; k < j; ++k) v -= s_A[j * n + k] * s_A[j * n + k];
+                if (!(v > 0.0)) {
+                    s_ok = 0;
+                    v = 1.0;
+                }
+                s_A[j * n + j] = sqrt(v);
+            }
+            __syncthreads();
+            for (int i = j + 1 + tid; i < n; i += kArtThreads) {
+                double v = s_A[i * n + j];
+                for (int k = 0; k < j; ++k) v -= s_A[i * n + k] * s_A[j * n + k];
+                s_A[i * n + j] = v / s_A[j * n + j];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (s_ok) {
+                for (int i = 0; i < n; ++i) {
+                    double v = -s_rhs[i];
+                    for (int k = 0; k < i; ++k) v -= s_A[i * n + k] * s_x[k];
+                    s_x[i] = v / s_A[i * n + i];
+                }
+                double nrm = 0.0;
+                for (int i = n - 1; i >= 0; --i) {
+                    double v = s_x[i];
+                    for (int k = i + 1; k < n; ++k) v -= s_A[k * n + i] * s_x[k];
+                    s_x[i] = v / s_A[i * n + i];
+                    nrm += s_x[i] * s_x[i];
+                }
+                for (int i = 0; i < n; ++i) s_th[i] += s_x[i];
+                if (step_norm) *step_norm = sqrt(nrm);
+                if (status) *status = FR_OK;
+            } else {
+                if (step_norm) *step_norm = 0.0;
+                if (status) *status = FR_EDEGENERATE;
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < n; k += kArtThreads) theta[k] = s_th[k];
+    }
+    if (tid == 0) forward_kinematics(tree, s_th, s_R, s_T, s_w, s_q);
+    __syncthreads();
+    for (int b = tid; b < tree.n_bodies; b += kArtThreads) {
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) mats[12 * b + 4 * i + j] = (float)s_R[9 * b + 3 * i + j];
+            mats[12 * b + 4 * i + 3] = (float)s_T[3 * b + i];
+        }
+    }
+}
+
+fr_status launch_articulated_step(const ArtTreeHost &h, int mode, const double *jtj, const double *jtr, double *theta,
+                                  float *mats, double *step_norm, int32_t *status, hipStream_t st)
+{
+    ArtTree t{h.n_bodies, h.n_dof, h.parent, h.dof_off, h.origin, h.axis, h.moved_by};
+    k_articulated_step<<<1, kArtThreads, 0, st>>>(t, mode, jtj, jtr, theta, mats, step_norm, status);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status upload_tree(fr_ctx *ctx, const fr_kinematic_tree *tree, hipStream_t st, ArtTreeHost &out)
+{
+    const int32_t B = tree->n_bodies;
+    if (B < 1 || B > kArtMaxBodies || !tree->parent || !tree->dof_offset || !tree->origin || !tree->axis) {
+        set_error("kinematic tree: 1..%d bodies with parent, dof_offset, origin and axis arrays required",
+                  kArtMaxBodies);
+        return FR_EINVAL;
+    }
+    const int32_t n = tree->dof_offset[B];
+    if (tree->dof_offset[0] != 0 || n < 1 || n > kArtMaxDof) {
+        set_error("kinematic tree: dof_offset[0] must be 0 and 1 <= n_dof <= %d", kArtMaxDof);
+        return FR_EINVAL;
+    }
+    std::vector<uint64_t> moved(B, 0);
+    for (int32_t b = 0; b < B; ++b) {
+        if (tree->parent[b] >= b || tree->parent[b] < -1 || tree->dof_offset[b + 1] < tree->dof_offset[b]) {
+            set_error("kinematic tree: parent[b] must be in [-1, b) and dof_offset non-decreasing (body %d)", b);
+            return FR_EINVAL;
+        }
+        uint64_t m = tree->parent[b] >= 0 ? moved[tree->parent[b]] : 0ull;
+        for (int32_t k = tree->dof_offset[b]; k < tree->dof_offset[b + 1]; ++k) m |= 1ull << k;
+        moved[b] = m;
+    }
+    out.n_bodies = B;
+    out.n_dof = n;
+    const size_t bp = sizeof(int32_t) * B, bd = sizeof(int32_t) * (B + 1), bo = sizeof(double) * 3 * B,
+                 ba = sizeof(double) * 3 * n, bm = sizeof(uint64_t) * B;
+    // 8-byte aligned sub-buffers: doubles and masks first
+    FR_TRY(out.buf.alloc(ctx, bo + ba + bm + bp + bd));
+    char *p = out.buf.as<char>();
+    FR_HIP(hipMemcpyAsync(p, tree->origin, bo, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo, tree->axis, ba, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo + ba, moved.data(), bm, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo + ba + bm, tree->parent, bp, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo + ba + bm + bp, tree->dof_offset, bd, hipMemcpyHostToDevice, st));
+    FR_HIP(hipStreamSynchronize(st));
+    out.origin = reinterpret_cast<const double *>(p);
+    out.axis = reinterpret_cast<const double *>(p + bo);
+    out.moved_by = reinterpret_cast<const uint64_t *>(p + bo + ba);
+    out.parent = reinterpret_cast<const int32_t *>(p + bo + ba + bm);
+    out.dof_off = reinterpret_cast<const int32_t *>(p + bo + ba + bm + bp);
+    return FR_OK;
+}
+
+}  // namespace fr

@@ -1,7 +1,9 @@
 // E-step slice (Eq. 6, Eq. 9 through the general Gaussian transform Eq. 11):
 // one thread per model point moves the point (Eq. 15), embeds its feature in
-// the lattice, probes the D = d + 1 vertices of its simplex in the set's table
-// and accumulates b_k * [1, y, n_y] into M0, M1 and the normal sum.
+// the lattice, looks the D = d + 1 vertices of its simplex up in the set's
+// cuckoo table (all 2D candidate key slots are read at once, then the value
+// slots of the vertices found) and accumulates b_k * [1, y, n_y] into M0, M1
+// and the normal sum.
 //
 // Memory behaviour: model points and outputs are streamed once (structure of
 // arrays, coalesced, non-temporal so they do not evict the table from L2);
@@ -14,7 +16,8 @@ namespace fr {
 struct EstepArgs {
     const float *x, *y, *z, *nx, *ny, *nz;
     const float *mats;            // per segment [R | t], or NULL for no transform
-    const uint4 *table;
+    const uint64_t *tkey;
+    const float *tval;
     const SetTable *sets;
     TileMap tm;
     float k[8];
@@ -72,8 +75,8 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     float acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0f;
-#pragma unroll
-    for (int v = 0; v < D; ++v) probe_accumulate<KW, V>(a.table, st, keys[v], b[v], acc);
+    slice_simplex<KW, V, D>(a.tkey + st.slot_base * KW, a.tval + st.slot_base * ValPad<V>::value, st, keys, b,
+                            acc);
 
     st_stream(a.m0 + i, acc[0]);
     st_stream(a.m1 + i, acc[1]);
@@ -94,7 +97,6 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    using L = SlotLayout<KW, V>;
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
@@ -124,22 +126,10 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     uint64_t keys[D][KW];
     float b[D];
     embed<d>(p, kk, keys, b);
-    const uint4 *base = a.table + st.slot_base * L::kNQ;
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        uint32_t h = hash_key<KW>(keys[v]) & st.mask;
-        for (uint32_t n = 0; n <= st.mask; ++n) {
-            const uint4 q = base[(size_t)h * L::kNQ];
-            const uint64_t w0 = (uint64_t)q.x | ((uint64_t)q.y << 32);
-            if (w0 == kKeyEmpty) break;
-            bool eq = (w0 == keys[v][0]);
-            if constexpr (KW >= 2) eq = eq && (((uint64_t)q.z | ((uint64_t)q.w << 32)) == keys[v][1]);
-            if (eq) {
-                a.touched[st.slot_base + h] = 1u;
-                break;
-            }
-            h = (h + 1) & st.mask;
-        }
+        const int64_t slot = find_slot<KW>(a.tkey + st.slot_base * KW, st, keys[v]);
+        if (slot >= 0) a.touched[st.slot_base + slot] = 1u;
     }
 }
 
@@ -167,7 +157,8 @@ fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan 
     a.ny = model->ny;
     a.nz = model->nz;
     a.mats = mats;
-    a.table = static_cast<const uint4 *>(lat->table);
+    a.tkey = lat->tkey;
+    a.tval = lat->tval;
     a.sets = lat->sets_d;
     a.tm = plan.tm;
     for (int j = 0; j < 8; ++j) a.k[j] = lat->k[j];

@@ -20,19 +20,21 @@ constexpr uint32_t kOwnerEmpty = 0xFFFFFFFFu;
 
 template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; };   // 3 coordinates per u64
 
-// Slot of the lattice table: packed key words, then V binary32 values,
-// padded to whole 16-byte quads so one slot is read with NQ dwordx4 loads.
-template <int KW, int V> struct SlotLayout {
-    static constexpr int kWords = 2 * KW + V;
-    static constexpr int kNQ = (kWords + 3) / 4;
-    static constexpr int kBytes = 16 * kNQ;
-};
+// The lattice table of one set is a two-choice cuckoo hash: every vertex key
+// sits in one of two slots p1(key), p2(key), so a lookup reads exactly two
+// key slots and, on a match, one value slot -- no probe chains.  Keys and
+// values are separate arrays: keys[slot] holds KW packed words (word 0 ==
+// kKeyEmpty marks a free slot), vals[slot] holds V binary32 values padded to
+// VP = 4 or 8 (one or two 16-byte loads).
+template <int V> struct ValPad { static constexpr int value = V <= 4 ? 4 : 8; };
 
 // Per-set view of the lattice table.
 struct SetTable {
     uint64_t slot_base;   // first slot of the set in the shared table
-    uint32_t mask;        // capacity - 1 (capacity is a power of two)
+    uint32_t cap;         // slots of the set (>= 16)
     uint32_t n_vertices;
+    uint32_t seed;        // hash seed (changed when a cuckoo insertion has to be redone)
+    uint32_t mask;        // cap - 1 for the power-of-two tables of the build
 };
 
 // Tiles of points grouped by segment; a segment lies inside one set.
@@ -78,27 +80,83 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
     return h;
 }
 
+// Multiply-add hash of the packed key words with a final avalanche.
 template <int KW>
-__device__ __forceinline__ uint32_t hash_key(const uint64_t (&w)[KW])
+__device__ __forceinline__ uint32_t hash_key(const uint64_t (&w)[KW], uint32_t seed)
 {
-    uint32_t h = 0x9E3779B9u;
+    uint32_t h = seed;
 #pragma unroll
     for (int i = 0; i < KW; ++i) {
-        h = (h ^ (uint32_t)w[i]) * 0x01000193u;
-        h = (h ^ (uint32_t)(w[i] >> 32)) * 0x27D4EB2Fu;
+        h = (h + (uint32_t)w[i]) * 0x9E3779B1u;
+        h = (h + (uint32_t)(w[i] >> 32)) * 0x85EBCA77u;
     }
-    return fmix32(h);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return h;
+}
+
+// The two candidate slots of a key in a table of `cap` slots: two hashes
+// mapped to [0, cap) by a multiply-high range reduction (no power-of-two
+// capacity needed); the second moves on by one if it coincides with the first.
+__device__ __forceinline__ void cuckoo_slots(uint32_t h, uint32_t cap, uint32_t &p1, uint32_t &p2)
+{
+    p1 = __umulhi(h, cap);
+    const uint32_t h2 = (h ^ (h >> 16)) * 0x7FEB352Du;
+    p2 = __umulhi(h2, cap);
+    p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
+}
+
+// Loads from a uniform table base with a 32-bit byte offset (slot < 2^27), so
+// the compiler can use the scalar-base + vector-offset addressing form.
+template <typename T>
+__device__ __forceinline__ T load_at(const void *__restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <int KW>
+__device__ __forceinline__ void load_key(const uint64_t *__restrict__ keys, uint32_t slot, uint64_t (&k)[KW])
+{
+    if constexpr (KW == 2) {
+        const uint4 q = load_at<uint4>(keys, slot << 4);
+        k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+        k[1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+    } else {
+        static_assert(KW == 1, "keys of 1 or 2 words");
+        const uint2 q = load_at<uint2>(keys, slot << 3);
+        k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+    }
+}
+
+template <int KW>
+__device__ __forceinline__ bool key_equal(const uint64_t (&a)[KW], const uint64_t (&b)[KW])
+{
+    bool eq = true;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) eq = eq && (a[w] == b[w]);
+    return eq;
 }
 
 // The permutohedral embedding of one point (the lattice method the paper uses
 // for its filter, Sec. 4.2; features normalised by sigma, Sec. 4.1):
 //   cf_i = p_i k_i; e_j = (cf_j + ... + cf_(d-1)) - j cf_(j-1), e_0 = sum cf;
-//   g_j = nearest multiple of D = d+1 (ties to the lower); ranks of e - g with
-//   ties broken by index; the sum of g / D shifts the ranks, and a rank that
-//   wraps moves g_j by -/+ D; weights are differences of the rank-sorted
-//   (e - g) / D; vertex k has coordinates g_j + k - D [rank_j > d - k].
+//   g_j = nearest multiple of D = d+1 to e_j (ties to the lower one);
+//   rank_j = #{i: delta_i > delta_j} + #{i < j: delta_i == delta_j}, delta = e - g;
+//   s = sum(g) / D.
+// The enclosing simplex is usually written after a correction that adds s to
+// every rank and moves the coordinates whose rank wraps by -/+D.  That
+// correction only relabels the simplex: its vertex k is vertex (k + s) mod D of
+// the uncorrected simplex moved by -s in every coordinate, with the same
+// weight.  So, with no correction step, vertex m (m = 0..d) is
+//   v_m[j] = g_j - s + m - D [rank_j > d - m],
+// with weight b_0 = 1 + (u_(d) - u_(0)), b_m = u_(d-m) - u_(d-m+1), where u_(r)
+// is the r-th largest delta / D.  Vertex order is immaterial to splat and
+// slice, which sum over all d + 1 vertices.
 // All key-path arithmetic is binary32 in this exact order (no contraction).
-// Outputs: packed keys of the D vertices and their weights; returns false if a
+// Keys: 21-bit biased coordinates packed 3 per u64 (coordinate 0 in the top
+// field of word 0); vertex m's key is vertex m-1's plus +1 in every field and
+// -D in the field of the coordinate of rank d - m + 1.  Returns false if a
 // coordinate leaves the packed range.
 template <int d>
 __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
@@ -120,23 +178,25 @@ __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
     }
     e[0] = S;
 
+    // nearest multiple of D: floor(v) D or the next one (up = floor(v) D + D
+    // equals ceil(v) D unless v is integral, where e is within rounding of the
+    // lower one and the lower one wins either way)
     int32_t g[D];
+    float delta[D];
     int32_t sum_g = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         const float v = e[j] * invD;
-        const float up = ceilf(v) * fD;
         const float dn = floorf(v) * fD;
+        const float up = dn + fD;
         const float du = up - e[j];
         const float dd = e[j] - dn;
-        g[j] = (du < dd) ? (int32_t)up : (int32_t)dn;
+        const float gf = (du < dd) ? up : dn;
+        g[j] = (int32_t)gf;
+        delta[j] = e[j] - gf;
         sum_g += g[j];
     }
     const int32_t s = sum_g / D;
-
-    float delta[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) delta[j] = e[j] - (float)g[j];
 
     int32_t rank[D];
 #pragma unroll
@@ -145,41 +205,58 @@ __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = i + 1; j < D; ++j) {
-            // rank_j counts larger deltas and equal deltas of lower index
-            if (delta[i] < delta[j]) rank[i]++; else rank[j]++;
+            // the larger delta ranks first; on a tie the lower index ranks first
+            const int32_t c = delta[i] < delta[j] ? 1 : 0;
+            rank[i] += c;
+            rank[j] += 1 - c;
         }
 
+    // deltas in descending order (odd-even transposition network)
+    float us[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        rank[j] += s;
-        if (rank[j] < 0) { rank[j] += D; g[j] += D; }
-        else if (rank[j] > d) { rank[j] -= D; g[j] -= D; }
-    }
-
-    // u by rank, gathered with selects (no dynamic register indexing)
-    float ur[D];
+    for (int j = 0; j < D; ++j) us[j] = delta[j];
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        float acc = 0.0f;
+    for (int r = 0; r < D; ++r)
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc = (rank[j] == r) ? (e[j] - (float)g[j]) * invD : acc;
-        ur[r] = acc;
-    }
-    b[0] = (1.0f + ur[d]) - ur[0];
+        for (int i = r & 1; i + 1 < D; i += 2) {
+            const float hi = fmaxf(us[i], us[i + 1]);
+            const float lo = fminf(us[i], us[i + 1]);
+            us[i] = hi;
+            us[i + 1] = lo;
+        }
+    b[0] = 1.0f + (us[d] - us[0]) * invD;
 #pragma unroll
-    for (int kk = 1; kk <= d; ++kk) b[kk] = ur[d - kk] - ur[d - kk + 1];
+    for (int m = 1; m <= d; ++m) b[m] = (us[d - m] - us[d - m + 1]) * invD;
 
     bool ok = true;
+    uint64_t P[KW];
 #pragma unroll
-    for (int kk = 0; kk < D; ++kk) {
+    for (int w = 0; w < KW; ++w) P[w] = 0;
 #pragma unroll
-        for (int w = 0; w < KW; ++w) keys[kk][w] = 0;
+    for (int j = 0; j < d; ++j) {
+        const int32_t c = g[j] - s;
+        ok = ok && (c >= -kKeyBias + D) && (c < kKeyBias - D);
+        P[j / 3] |= (uint64_t)((uint32_t)(c + kKeyBias) & ((1u << kKeyBits) - 1u)) << (kKeyBits * (2 - (j % 3)));
+    }
 #pragma unroll
-        for (int j = 0; j < d; ++j) {
-            const int32_t c = g[j] + kk - ((rank[j] > d - kk) ? D : 0);
-            ok = ok && (c >= -kKeyBias) && (c < kKeyBias);
-            const uint64_t field = (uint64_t)((uint32_t)(c + kKeyBias) & ((1u << kKeyBits) - 1u));
-            keys[kk][j / 3] |= field << (kKeyBits * (2 - (j % 3)));
+    for (int w = 0; w < KW; ++w) keys[0][w] = P[w];
+#pragma unroll
+    for (int m = 1; m <= d; ++m) {
+        const int32_t t = d - m + 1;
+#pragma unroll
+        for (int w = 0; w < KW; ++w) {
+            uint64_t ones = 0, down = 0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const int j = 3 * w + f;
+                if (j < d) {
+                    const uint64_t unit = 1ull << (kKeyBits * (2 - f));
+                    ones += unit;
+                    down = (rank[j] == t) ? (uint64_t)D * unit : down;
+                }
+            }
+            P[w] += ones - down;
+            keys[m][w] = P[w];
         }
     }
     return ok;
@@ -208,40 +285,57 @@ __device__ __forceinline__ void xform_normal(const float *m, float x, float y, f
     oz = (m[8] * x + m[9] * y) + m[10] * z;
 }
 
-// Look a packed key up in one set's table; on a hit add b * values to acc.
-// The table always has an empty slot (load factor <= 1/2), so probing ends at
-// the key or at an empty slot; the probe count is bounded by the capacity.
-template <int KW, int V>
-__device__ __forceinline__ bool probe_accumulate(const uint4 *__restrict__ table, const SetTable &st,
-                                                 const uint64_t (&key)[KW], float bw, float (&acc)[V])
+// Slice one point: read the two candidate key slots of all D vertices at
+// once, then one value slot per vertex, and accumulate b * value.  A vertex
+// absent from the lattice gets weight 0 (its value read falls on a valid slot),
+// so there are no divergent branches.  kb/vb are the set's table bases
+// (uniform per block), slots are 32-bit offsets.
+template <int KW, int V, int D>
+__device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, const float *__restrict__ vb,
+                                              const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
+                                              float (&acc)[V])
 {
-    using L = SlotLayout<KW, V>;
-    uint32_t h = hash_key<KW>(key) & st.mask;
-    const uint4 *base = table + st.slot_base * L::kNQ;
-    for (uint32_t n = 0; n <= st.mask; ++n) {
-        uint4 q[L::kNQ];
+    constexpr int VP = ValPad<V>::value;
+    uint32_t p1[D], p2[D];
+    uint64_t ka[D][KW], kc[D][KW];
 #pragma unroll
-        for (int i = 0; i < L::kNQ; ++i) q[i] = base[(size_t)h * L::kNQ + i];
-        const uint64_t w0 = (uint64_t)q[0].x | ((uint64_t)q[0].y << 32);
-        if (w0 == kKeyEmpty) return false;
-        bool eq = (w0 == key[0]);
-        if constexpr (KW >= 2) eq = eq && (((uint64_t)q[0].z | ((uint64_t)q[0].w << 32)) == key[1]);
-        if (eq) {
-            uint32_t words[4 * L::kNQ];
-#pragma unroll
-            for (int i = 0; i < L::kNQ; ++i) {
-                words[4 * i + 0] = q[i].x;
-                words[4 * i + 1] = q[i].y;
-                words[4 * i + 2] = q[i].z;
-                words[4 * i + 3] = q[i].w;
-            }
-#pragma unroll
-            for (int c = 0; c < V; ++c) acc[c] = fmaf(bw, __uint_as_float(words[2 * KW + c]), acc[c]);
-            return true;
-        }
-        h = (h + 1) & st.mask;
+    for (int v = 0; v < D; ++v) {
+        cuckoo_slots(hash_key<KW>(keys[v], st.seed), st.cap, p1[v], p2[v]);
+        load_key<KW>(kb, p1[v], ka[v]);
+        load_key<KW>(kb, p2[v], kc[v]);
     }
-    return false;
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        const bool in1 = key_equal<KW>(ka[v], keys[v]);
+        const bool in2 = key_equal<KW>(kc[v], keys[v]);
+        const uint32_t slot = in1 ? p1[v] : p2[v];
+        const float w = (in1 || in2) ? b[v] : 0.0f;
+        const uint32_t off = slot * (uint32_t)(VP * sizeof(float));
+        float val[VP];
+        const float4 q0 = load_at<float4>(vb, off);
+        val[0] = q0.x; val[1] = q0.y; val[2] = q0.z; val[3] = q0.w;
+        if constexpr (VP == 8) {
+            const float4 q1 = load_at<float4>(vb, off + 16u);
+            val[4] = q1.x; val[5] = q1.y; val[6] = q1.z; val[7] = q1.w;
+        }
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
+    }
+}
+
+// Slot of a key in a set's table (relative to the set's base), or -1.
+template <int KW>
+__device__ __forceinline__ int64_t find_slot(const uint64_t *__restrict__ kb, const SetTable &st,
+                                             const uint64_t (&key)[KW])
+{
+    uint32_t p1, p2;
+    cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+    uint64_t k1[KW], k2[KW];
+    load_key<KW>(kb, p1, k1);
+    load_key<KW>(kb, p2, k2);
+    if (key_equal<KW>(k1, key)) return (int64_t)p1;
+    if (key_equal<KW>(k2, key)) return (int64_t)p2;
+    return -1;
 }
 
 }  // namespace fr

@@ -63,9 +63,11 @@ struct fr_lattice {
     int32_t splat = FR_SPLAT_SORTED;
     float k[8] = {0};
     int64_t n_points_total = 0;
-    // table
-    void *table = nullptr;            // all sets' slots
-    size_t table_bytes = 0;
+    // cuckoo tables of all sets: keys (KW words per slot) and padded values
+    uint64_t *tkey = nullptr;
+    float *tval = nullptr;
+    size_t tkey_bytes = 0, tval_bytes = 0;
+    uint64_t n_slots = 0;
     fr::SetTable *sets_d = nullptr;   // device copy of sets_h
     std::vector<fr::SetTable> sets_h;
     // vertex arrays (for export), vertices of set s are [vbase[s], vbase[s+1])
@@ -76,7 +78,6 @@ struct fr_lattice {
     std::vector<int64_t> vbase;
     size_t vert_bytes = 0;
     int32_t *err_d = nullptr;         // latched device fault bits
-    size_t charged = 0;
 };
 
 namespace fr {
@@ -150,7 +151,19 @@ size_t reduce_partials_floats(const Plan &plan);
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
                              double *twist_norm, int32_t *status, const int32_t *active, hipStream_t stream);
 
+// articulated.hip
+struct ArtTreeHost {
+    int32_t n_bodies = 0, n_dof = 0;
+    const int32_t *parent = nullptr, *dof_off = nullptr;
+    const double *origin = nullptr, *axis = nullptr;
+    const uint64_t *moved_by = nullptr;
+    DevBuf buf;
+};
+fr_status upload_tree(fr_ctx *ctx, const fr_kinematic_tree *tree, hipStream_t stream, ArtTreeHost &out);
+fr_status launch_articulated_step(const ArtTreeHost &tree, int mode, const double *jtj, const double *jtr,
+                                  double *theta, float *mats, double *step_norm, int32_t *status, hipStream_t stream);
+
 // scan / sort helpers (lattice_build.hip)
-fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, bool flags, hipStream_t stream);
+fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t stream);
 
 }  // namespace fr

@@ -6,17 +6,22 @@
 //   2. insert     one thread per record: insert the key into a provisional
 //                 open-addressing table of the record's set (32-bit owner CAS,
 //                 keys compared through the owner record, so keys of any
-//                 width work); count incidences per slot.
-//   3. compact    exclusive scan of occupied slots -> vertex ids; per-vertex
-//                 key and occupancy.
+//                 width work).
+//   3. vertices   the record that owns each slot defines a vertex; an
+//                 exclusive scan over records numbers the vertices in owner
+//                 order (so vertex ids follow point order) and gives each
+//                 set's contiguous vertex range.
 //   4. values     sorted mode: stable LSD radix sort of the records by vertex
 //                 id (records start in point order, so each vertex's records
-//                 stay in point order), then one thread per vertex sums
-//                 b * [1, y, n_y] in that order in binary64 -> bitwise
-//                 deterministic.  Atomic mode: binary32 hardware atomics.
-//   5. final      per set, a table of capacity pow2 >= 2 n_v whose slots hold
-//                 the packed key and the binary32 values inline, so that a
-//                 lookup in the E-step is one 32/48-byte read.
+//                 stay in point order); segment lengths give the occupancy
+//                 and one thread per vertex sums b * [1, y, n_y] in that
+//                 order in binary64 -> bitwise deterministic.  Atomic mode:
+//                 binary32 hardware atomics and an occupancy counter.
+//   5. final      per set, a two-choice cuckoo table (load factor <= 0.4):
+//                 every key sits in one of its two candidate slots, so an
+//                 E-step lookup is two key reads and one value read.
+#include <algorithm>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -39,7 +44,8 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
     return v;
 }
 
-template <bool FLAGS>
+// MODE 0: scan the values; 1: scan (x != 0); 2: scan (x != 0xFFFFFFFF).
+template <int MODE>
 __global__ void __launch_bounds__(kScanThreads) k_scan_tile(const uint32_t *in, uint32_t *out, uint32_t *bsum, size_t n)
 {
     __shared__ uint32_t wsum[kScanThreads / 64];
@@ -49,8 +55,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tile(const uint32_t *in, 
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const size_t idx = base + i;
-        uint32_t x = idx < n ? in[idx] : 0u;
-        if (FLAGS) x = x != 0u;
+        uint32_t x = idx < n ? in[idx] : (MODE == 2 ? kOwnerEmpty : 0u);
+        if (MODE == 1) x = x != 0u;
+        if (MODE == 2) x = x != kOwnerEmpty;
         v[i] = tot;
         tot += x;
     }
@@ -77,22 +84,24 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t *out, const 
     }
 }
 
-fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, bool flags, hipStream_t st)
+fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t st)
 {
     if (n == 0) return FR_OK;
     const size_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 1) {
-        if (flags) k_scan_tile<true><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
-        else k_scan_tile<false><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
+        if (mode == 1) k_scan_tile<1><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
+        else if (mode == 2) k_scan_tile<2><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
+        else k_scan_tile<0><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
         FR_HIP(hipGetLastError());
         return FR_OK;
     }
     DevBuf bs;
     FR_TRY(bs.alloc(ctx, nb * sizeof(uint32_t)));
-    if (flags) k_scan_tile<true><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
-    else k_scan_tile<false><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
+    if (mode == 1) k_scan_tile<1><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
+    else if (mode == 2) k_scan_tile<2><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
+    else k_scan_tile<0><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
     FR_HIP(hipGetLastError());
-    FR_TRY(scan_exclusive_u32(ctx, bs.as<uint32_t>(), bs.as<uint32_t>(), nb, false, st));
+    FR_TRY(scan_exclusive_u32(ctx, bs.as<uint32_t>(), bs.as<uint32_t>(), nb, 0, st));
     k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, bs.as<uint32_t>(), n);
     FR_HIP(hipGetLastError());
     // bs is freed by the destructor: DevBuf frees after a stream sync (see dev_free).
@@ -199,7 +208,7 @@ static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, u
     for (int shift = 0; shift < bits; shift += 8, ++passes) {
         k_rs_hist<<<nb, kRsThreads, 0, st>>>(ka, n, shift, hist.as<uint32_t>(), nb);
         FR_HIP(hipGetLastError());
-        FR_TRY(scan_exclusive_u32(ctx, hist.as<uint32_t>(), hist.as<uint32_t>(), (size_t)256 * nb, false, st));
+        FR_TRY(scan_exclusive_u32(ctx, hist.as<uint32_t>(), hist.as<uint32_t>(), (size_t)256 * nb, 0, st));
         k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ka, va, kb, vb, n, shift, hist.as<uint32_t>(), nb);
         FR_HIP(hipGetLastError());
         std::swap(ka, kb);
@@ -220,46 +229,67 @@ struct Pts {
     const float *x, *y, *z, *nx, *ny, *nz;
 };
 
+// One thread per observation point: the D (key, weight) records of its
+// simplex.  Records are r = point * D + m; the block stages its 256 * D
+// records in LDS so the global writes are contiguous.
 template <int d>
 __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, float4 k0, float4 k1, uint64_t *rec_key,
                                                   float *rec_b, size_t R, int32_t *err)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
+    __shared__ uint64_t s_key[KW][256 * D];
+    __shared__ float s_b[256 * D];
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
-    const int64_t i = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
-    if (i >= tm.seg_off[s + 1]) return;
-    float p[d];
-    float kk[d];
-    const float kall[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+    const int64_t first = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile;
+    const int64_t i = first + threadIdx.x;
+    const int64_t n_here = min((int64_t)tm.tile, tm.seg_off[s + 1] - first);
+    if (i < tm.seg_off[s + 1]) {
+        float p[d];
+        float kk[d];
+        const float kall[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
 #pragma unroll
-    for (int j = 0; j < d; ++j) kk[j] = kall[j];
-    p[0] = pts.x[i];
-    p[1] = pts.y[i];
-    p[2] = pts.z[i];
-    if constexpr (d == 6) {
-        p[3] = pts.nx[i];
-        p[4] = pts.ny[i];
-        p[5] = pts.nz[i];
+        for (int j = 0; j < d; ++j) kk[j] = kall[j];
+        p[0] = pts.x[i];
+        p[1] = pts.y[i];
+        p[2] = pts.z[i];
+        if constexpr (d == 6) {
+            p[3] = pts.nx[i];
+            p[4] = pts.ny[i];
+            p[5] = pts.nz[i];
+        }
+        uint64_t keys[D][KW];
+        float b[D];
+        if (!embed<d>(p, kk, keys, b)) atomicOr(err, 1);
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+#pragma unroll
+            for (int w = 0; w < KW; ++w) s_key[w][threadIdx.x * D + v] = keys[v][w];
+            s_b[threadIdx.x * D + v] = b[v];
+        }
     }
-    uint64_t keys[D][KW];
-    float b[D];
-    if (!embed<d>(p, kk, keys, b)) atomicOr(err, 1);
+    __syncthreads();
+    const size_t r0 = (size_t)first * D;
+    const int nrec = (int)n_here * D;
+    for (int q = threadIdx.x; q < nrec; q += 256) {
 #pragma unroll
-    for (int v = 0; v < D; ++v) {
-        const size_t r = (size_t)i * D + v;
-#pragma unroll
-        for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r] = keys[v][w];
-        rec_b[r] = b[v];
+        for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r0 + q] = s_key[w][q];
+        rec_b[r0 + q] = s_b[q];
     }
 }
 
-// One thread per record: find or claim the record's key in the provisional table.
+// One thread per record: find or claim the record's key in the provisional
+// linear-probing table of its set.  A slot that already has an owner is
+// compared with a plain read first; only free slots are claimed with a CAS.
+// Probing stops after kMaxProbe slots and raises `fail` (the host then
+// retries with a larger table).
+constexpr uint32_t kMaxProbe = 128;
+
 template <int KW>
 __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTable *tables, const uint64_t *rec_key,
-                                                       size_t R, uint32_t *own, uint32_t *occ, uint32_t *rec_slot)
+                                                       size_t R, uint32_t *own, uint32_t *rec_slot, int32_t *fail)
 {
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
@@ -270,63 +300,91 @@ __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTab
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = rec_key[(size_t)w * R + r];
     const SetTable st = tables[s];
-    uint32_t h = hash_key<KW>(key) & st.mask;
-    for (uint32_t n = 0; n <= st.mask; ++n) {
+    uint32_t h = hash_key<KW>(key, 0u) & st.mask;
+    const uint32_t limit = min(st.mask + 1u, kMaxProbe);
+    for (uint32_t n = 0; n < limit; ++n) {
         const size_t slot = st.slot_base + h;
-        const uint32_t old = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
-        bool mine = (old == kOwnerEmpty);
+        uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
+        bool mine = (o == kOwnerEmpty);
         if (!mine) {
             mine = true;
 #pragma unroll
-            for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + old] == key[w]);
+            for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
         }
         if (mine) {
             rec_slot[r] = (uint32_t)slot;
-            atomicAdd(&occ[slot], 1u);
             return;
         }
         h = (h + 1) & st.mask;
     }
+    atomicOr(fail, 1);
 }
 
-// Per-set vertex counts from the scanned occupancy flags (one thread per set).
-__global__ void k_set_counts(const SetTable *tables, int32_t n_sets, const uint32_t *vid, const uint32_t *occ,
-                             size_t n_slots, uint32_t *counts)
+// flag[r] = 1 if record r owns its slot (the first record of its vertex to claim it).
+__global__ void __launch_bounds__(256) k_owner_flags(size_t R, const uint32_t *rec_slot, const uint32_t *own,
+                                                    uint32_t *flag)
 {
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_sets) return;
-    const size_t b0 = tables[s].slot_base;
-    const size_t b1 = b0 + (size_t)tables[s].mask + 1;
-    const uint32_t total_end = (b1 < n_slots) ? vid[b1] : (vid[n_slots - 1] + (occ[n_slots - 1] != 0u ? 1u : 0u));
-    counts[s] = total_end - vid[b0];
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    flag[r] = own[rec_slot[r]] == (uint32_t)r ? 1u : 0u;
 }
 
+// Vertex ids in owner-record order (the exclusive scan of the flags): owners
+// write their vertex's key and the slot -> vertex map.
 template <int KW>
-__global__ void __launch_bounds__(256) k_compact_slots(size_t n_slots, const uint32_t *occ, const uint32_t *own,
-                                                      const uint32_t *vid, const uint64_t *rec_key, size_t R,
-                                                      uint64_t *vkey, uint32_t *vocc, size_t NV)
+__global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *own,
+                                                   const uint32_t *ovid, const uint64_t *rec_key, uint64_t *vkey,
+                                                   size_t NV, uint32_t *slot_vid)
 {
-    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_slots) return;
-    const uint32_t c = occ[j];
-    if (c == 0u) return;
-    const uint32_t v = vid[j];
-    const uint32_t r = own[j];
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint32_t slot = rec_slot[r];
+    if (own[slot] != (uint32_t)r) return;
+    const uint32_t v = ovid[r];
 #pragma unroll
     for (int w = 0; w < KW; ++w) vkey[(size_t)w * NV + v] = rec_key[(size_t)w * R + r];
-    vocc[v] = c;
+    slot_vid[slot] = v;
 }
 
-__global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t *rec_slot, const uint32_t *vid,
+// Vertex count of each set: owners of its records form one contiguous id range.
+__global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32_t *ovid, size_t R, uint32_t nv_total,
+                            uint32_t *vbase)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_sets) return;
+    const int64_t r = rec_off[s];
+    vbase[s] = (r < (int64_t)R) ? ovid[r] : nv_total;
+}
+
+__global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t *rec_slot, const uint32_t *slot_vid,
                                                       uint32_t *rvid, uint32_t *rid)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    rvid[r] = vid[rec_slot[r]];
+    rvid[r] = slot_vid[rec_slot[r]];
     rid[r] = (uint32_t)r;
 }
 
-// Sorted mode: ordered binary64 sums per vertex.
+// Sorted mode: segment starts and lengths of the vertex-sorted records.
+__global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t *rvid_sorted, uint32_t *voff)
+{
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= R) return;
+    const uint32_t v = rvid_sorted[q];
+    if (q == 0 || rvid_sorted[q - 1] != v) voff[v] = (uint32_t)q;
+}
+
+__global__ void __launch_bounds__(256) k_segment_lengths(size_t NV, size_t R, const uint32_t *voff, uint32_t *vocc)
+{
+    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= NV) return;
+    vocc[v] = (uint32_t)((v + 1 < NV ? voff[v + 1] : (uint32_t)R) - voff[v]);
+}
+
+// Sorted mode: ordered binary64 sums per vertex.  Vertex ids follow the
+// owner records, so neighbouring threads gather from neighbouring points;
+// record ids are fetched four at a time so the dependent gathers overlap.
 template <int D, int V>
 __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint32_t *voff, const uint32_t *vocc,
                                                           const uint32_t *rid_sorted, const float *rec_b, Pts pts,
@@ -338,34 +396,50 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0;
     const uint32_t q0 = voff[v], q1 = q0 + vocc[v];
-    for (uint32_t q = q0; q < q1; ++q) {
-        const uint32_t r = rid_sorted[q];
-        const uint32_t i = r / D;
-        const double bw = (double)rec_b[r];
-        acc[0] += bw;
-        acc[1] += bw * (double)pts.x[i];
-        acc[2] += bw * (double)pts.y[i];
-        acc[3] += bw * (double)pts.z[i];
-        if constexpr (V == 7) {
-            acc[4] += bw * (double)pts.nx[i];
-            acc[5] += bw * (double)pts.ny[i];
-            acc[6] += bw * (double)pts.nz[i];
+    for (uint32_t q = q0; q < q1; q += 4) {
+        uint32_t r[4];
+        float bw[4], val[4][V - 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = (q + u < q1) ? rid_sorted[q + u] : rid_sorted[q0];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = r[u] / D;
+            bw[u] = (q + u < q1) ? rec_b[r[u]] : 0.0f;
+            val[u][0] = pts.x[i];
+            val[u][1] = pts.y[i];
+            val[u][2] = pts.z[i];
+            if constexpr (V == 7) {
+                val[u][3] = pts.nx[i];
+                val[u][4] = pts.ny[i];
+                val[u][5] = pts.nz[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q + u >= q1) break;
+            const double w = (double)bw[u];
+            acc[0] += w;
+#pragma unroll
+            for (int c = 1; c < V; ++c) acc[c] += w * (double)val[u][c - 1];
         }
     }
 #pragma unroll
     for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = (float)acc[c];
 }
 
-// Atomic mode: one thread per record, binary32 hardware atomics.
+// Atomic mode: one thread per record, binary32 hardware atomics; occupancy by
+// integer atomics.
 template <int D, int V>
-__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t R, const uint32_t *rec_slot, const uint32_t *vid,
-                                                          const float *rec_b, Pts pts, float *vval, size_t NV)
+__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t R, const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                          const float *rec_b, Pts pts, float *vval, uint32_t *vocc,
+                                                          size_t NV)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    const uint32_t v = vid[rec_slot[r]];
+    const uint32_t v = slot_vid[rec_slot[r]];
     const size_t i = r / D;
     const float bw = rec_b[r];
+    atomicAdd(&vocc[v], 1u);
     unsafeAtomicAdd(&vval[v], bw);
     unsafeAtomicAdd(&vval[NV + v], bw * pts.x[i]);
     unsafeAtomicAdd(&vval[2 * NV + v], bw * pts.y[i]);
@@ -377,44 +451,68 @@ __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t R, const uint3
     }
 }
 
-// One thread per vertex: claim a slot of the set's final table and write the
-// packed key and values inline.  Keys are unique, so a claimed slot is never
-// compared.
-template <int KW, int V>
-__global__ void __launch_bounds__(256) k_final_insert(TileMap tm, const SetTable *tables, const uint64_t *vkey,
-                                                     const float *vval, size_t NV, uint32_t *own, uint4 *table)
+// Two-choice cuckoo insertion of the vertices of each set (one thread per
+// vertex).  A thread always holds exactly one vertex: it swaps it into one of
+// the vertex's two slots and carries on with whatever it evicted, toward that
+// vertex's other slot, until it lands in a free slot.  Every vertex therefore
+// ends in exactly one slot; a thread that gives up after kMaxKicks raises
+// `fail` and the host rebuilds the table with another seed.
+constexpr int kMaxKicks = 512;
+
+template <int KW>
+__global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTable *tables, const uint64_t *vkey,
+                                                      size_t NV, uint32_t *own, int32_t *fail)
 {
-    using L = SlotLayout<KW, V>;
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
     const int64_t v = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
     if (v >= tm.seg_off[s + 1]) return;
+    const SetTable st = tables[s];
+    uint32_t cur = (uint32_t)v;
     uint64_t key[KW];
 #pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
-    const SetTable st = tables[s];
-    uint32_t h = hash_key<KW>(key) & st.mask;
-    for (uint32_t n = 0; n <= st.mask; ++n) {
-        const size_t slot = st.slot_base + h;
-        if (atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)v) == kOwnerEmpty) {
-            uint32_t words[4 * L::kNQ];
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
+    uint32_t p1, p2;
+    cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+    uint32_t pos = p1;
+    for (int it = 0; it < kMaxKicks; ++it) {
+        const uint32_t old = atomicExch(&own[st.slot_base + pos], cur);
+        if (old == kOwnerEmpty) return;
+        cur = old;
 #pragma unroll
-            for (int i = 0; i < 4 * L::kNQ; ++i) words[i] = 0u;
-#pragma unroll
-            for (int w = 0; w < KW; ++w) {
-                words[2 * w] = (uint32_t)key[w];
-                words[2 * w + 1] = (uint32_t)(key[w] >> 32);
-            }
-#pragma unroll
-            for (int c = 0; c < V; ++c) words[2 * KW + c] = __float_as_uint(vval[(size_t)c * NV + v]);
-#pragma unroll
-            for (int i = 0; i < L::kNQ; ++i)
-                table[slot * L::kNQ + i] = make_uint4(words[4 * i], words[4 * i + 1], words[4 * i + 2], words[4 * i + 3]);
-            return;
-        }
-        h = (h + 1) & st.mask;
+        for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
+        cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+        pos = (pos == p1) ? p2 : p1;
     }
+    atomicOr(fail, 1);
+}
+
+// One thread per slot: write the key words and padded values of its vertex,
+// or the empty marker.
+template <int KW, int V>
+__global__ void __launch_bounds__(256) k_cuckoo_fill(size_t n_slots, const uint32_t *own, const uint64_t *vkey,
+                                                    const float *vval, size_t NV, uint64_t *tkey, float *tval)
+{
+    constexpr int VP = ValPad<V>::value;
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_slots) return;
+    const uint32_t o = own[j];
+    float val[VP];
+#pragma unroll
+    for (int c = 0; c < VP; ++c) val[c] = 0.0f;
+    if (o == kOwnerEmpty) {
+#pragma unroll
+        for (int w = 0; w < KW; ++w) tkey[KW * j + w] = kKeyEmpty;
+    } else {
+#pragma unroll
+        for (int w = 0; w < KW; ++w) tkey[KW * j + w] = vkey[(size_t)w * NV + o];
+#pragma unroll
+        for (int c = 0; c < V; ++c) val[c] = vval[(size_t)c * NV + o];
+    }
+    float4 *dst = reinterpret_cast<float4 *>(tval + VP * j);
+    dst[0] = make_float4(val[0], val[1], val[2], val[3]);
+    if constexpr (VP == 8) dst[1] = make_float4(val[4], val[5], val[6], val[7]);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,40 +559,23 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
+    constexpr int VP = ValPad<V>::value;
     const int32_t S = obs->n_sets;
     const int64_t N = cloud_points(obs);
     const size_t R = (size_t)N * D;
+    const bool sorted = lat->splat == FR_SPLAT_SORTED;
     if (R >= 0xFFFFFFF0ull) {
         set_error("fr_lattice_build: %lld records exceed the 32-bit record index", (long long)R);
         return FR_EINVAL;
     }
     Pts pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
 
-    // provisional tables: capacity pow2 >= 2 * records of the set
-    std::vector<SetTable> t1(S);
-    uint64_t n1 = 0;
-    for (int32_t s = 0; s < S; ++s) {
-        const uint64_t rs = (uint64_t)(obs->offsets[s + 1] - obs->offsets[s]) * D;
-        const uint32_t cap = next_pow2(2 * rs);
-        t1[s] = SetTable{n1, cap - 1, 0};
-        n1 += cap;
-    }
-    if (n1 >= 0xFFFFFFF0ull) {
-        set_error("fr_lattice_build: provisional table too large");
-        return FR_EINVAL;
-    }
-
-    DevBuf rec_key, rec_b, rec_slot, own1, occ1, vid, t1_d, ptmap, rtmap;
+    DevBuf rec_key, rec_b, rec_slot, own1, t1_d, ptmap, rtmap, fail;
     FR_TRY(rec_key.alloc(ctx, R * KW * sizeof(uint64_t)));
     FR_TRY(rec_b.alloc(ctx, R * sizeof(float)));
     FR_TRY(rec_slot.alloc(ctx, R * sizeof(uint32_t)));
-    FR_TRY(own1.alloc(ctx, n1 * sizeof(uint32_t)));
-    FR_TRY(occ1.alloc(ctx, n1 * sizeof(uint32_t)));
-    FR_TRY(vid.alloc(ctx, n1 * sizeof(uint32_t)));
+    FR_TRY(fail.alloc(ctx, sizeof(int32_t)));
     FR_TRY(t1_d.alloc(ctx, S * sizeof(SetTable)));
-    FR_HIP(hipMemcpyAsync(t1_d.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
-    FR_HIP(hipMemsetAsync(occ1.p, 0, n1 * sizeof(uint32_t), st));
     FR_HIP(hipMemsetAsync(lat->err_d, 0, sizeof(int32_t), st));
 
     // 1. embed
@@ -508,26 +589,66 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                                     lat->err_d);
         FR_HIP(hipGetLastError());
     }
-    // 2. insert
+    // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
     std::vector<int64_t> roff(S + 1);
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm));
-    if (rtm.n_tiles > 0) {
-        k_insert_records<KW><<<rtm.n_tiles, 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
-                                                          own1.as<uint32_t>(), occ1.as<uint32_t>(),
-                                                          rec_slot.as<uint32_t>());
+    uint64_t n1 = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        std::vector<SetTable> t1(S);
+        n1 = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            const uint64_t rs = (uint64_t)(roff[s + 1] - roff[s]);
+            const uint32_t cap = next_pow2(attempt == 0 ? rs / 2 : 2 * rs);
+            t1[s] = SetTable{n1, cap, 0, 0, cap - 1};
+            n1 += cap;
+        }
+        if (n1 >= 0xFFFFFFF0ull) {
+            set_error("fr_lattice_build: provisional table too large");
+            return FR_EINVAL;
+        }
+        FR_TRY(own1.alloc(ctx, n1 * sizeof(uint32_t)));
+        FR_HIP(hipMemcpyAsync(t1_d.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
+        FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
+        FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
+        if (rtm.n_tiles > 0) {
+            k_insert_records<KW><<<rtm.n_tiles, 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
+                                                              own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
+                                                              fail.as<int32_t>());
+            FR_HIP(hipGetLastError());
+        }
+        int32_t failed = 0;
+        FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipStreamSynchronize(st));
+        if (!failed) break;
+        if (attempt == 1) {
+            set_error("fr_lattice_build: provisional table overflow");
+            return FR_EDEVICE;
+        }
+    }
+
+    // 3. vertex ids in owner-record order, per-set ranges, keys
+    DevBuf ovid, slot_vid, vb_d;
+    FR_TRY(ovid.alloc(ctx, R * sizeof(uint32_t)));
+    FR_TRY(slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
+    FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
+    if (R > 0) {
+        k_owner_flags<<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), own1.as<uint32_t>(),
+                                                           ovid.as<uint32_t>());
         FR_HIP(hipGetLastError());
     }
-    // 3. compact
-    FR_TRY(scan_exclusive_u32(ctx, occ1.as<uint32_t>(), vid.as<uint32_t>(), n1, true, st));
-    DevBuf counts_d;
-    FR_TRY(counts_d.alloc(ctx, S * sizeof(uint32_t)));
-    k_set_counts<<<blocks_for(S, 64), 64, 0, st>>>(t1_d.as<SetTable>(), S, vid.as<uint32_t>(), occ1.as<uint32_t>(),
-                                                    n1, counts_d.as<uint32_t>());
+    uint32_t last_flag = 0, last_scan = 0;
+    if (R > 0) FR_HIP(hipMemcpyAsync(&last_flag, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToHost, st));
+    FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), R, 0, st));
+    if (R > 0) FR_HIP(hipMemcpyAsync(&last_scan, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    const uint32_t nv_total = last_scan + last_flag;
+    k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), R, nv_total,
+                                                      vb_d.as<uint32_t>());
     FR_HIP(hipGetLastError());
-    std::vector<uint32_t> counts(S);
+    std::vector<uint32_t> vb_h(S + 1);
     int32_t err_h = 0;
-    FR_HIP(hipMemcpyAsync(counts.data(), counts_d.p, S * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(vb_h.data(), vb_d.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipMemcpyAsync(&err_h, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipStreamSynchronize(st));
     if (err_h != 0) {
@@ -535,8 +656,12 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         return FR_ERANGE;
     }
     lat->vbase.assign(S + 1, 0);
-    for (int32_t s = 0; s < S; ++s) lat->vbase[s + 1] = lat->vbase[s] + counts[s];
-    const size_t NV = (size_t)lat->vbase[S];
+    std::vector<uint32_t> counts(S);
+    for (int32_t s = 0; s < S; ++s) {
+        lat->vbase[s + 1] = vb_h[s + 1];
+        counts[s] = vb_h[s + 1] - vb_h[s];
+    }
+    const size_t NV = nv_total;
     lat->n_vertices_total = (int64_t)NV;
 
     // vertex arrays (kept for export)
@@ -544,75 +669,100 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     {
         void *p = nullptr;
         FR_TRY(dev_alloc(ctx, &p, lat->vert_bytes));
-        lat->charged += lat->vert_bytes;
         char *c = static_cast<char *>(p);
         lat->vkey = reinterpret_cast<uint64_t *>(c);
         lat->vval = reinterpret_cast<float *>(c + NV * KW * sizeof(uint64_t));
         lat->vocc = reinterpret_cast<uint32_t *>(c + NV * (KW * sizeof(uint64_t) + V * sizeof(float)));
     }
     if (NV > 0) {
-        k_compact_slots<KW><<<blocks_for(n1, 256), 256, 0, st>>>(n1, occ1.as<uint32_t>(), own1.as<uint32_t>(),
-                                                                 vid.as<uint32_t>(), rec_key.as<uint64_t>(), R,
-                                                                 lat->vkey, lat->vocc, NV);
+        k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), own1.as<uint32_t>(),
+                                                             ovid.as<uint32_t>(), rec_key.as<uint64_t>(), lat->vkey,
+                                                             NV, slot_vid.as<uint32_t>());
         FR_HIP(hipGetLastError());
     }
 
     // 4. values
     if (NV > 0) {
-        if (lat->splat == FR_SPLAT_SORTED) {
+        if (sorted) {
             DevBuf rvid, rid, tk, tv, voff;
             FR_TRY(rvid.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(rid.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(tk.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(tv.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(voff.alloc(ctx, NV * sizeof(uint32_t)));
-            k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), vid.as<uint32_t>(),
+            k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(),
                                                                  rvid.as<uint32_t>(), rid.as<uint32_t>());
             FR_HIP(hipGetLastError());
             int bits = 0;
             while (bits < 32 && (NV - 1) >> bits) ++bits;
             FR_TRY(radix_sort_pairs(ctx, rvid.as<uint32_t>(), rid.as<uint32_t>(), tk.as<uint32_t>(),
                                     tv.as<uint32_t>(), R, bits, st));
-            FR_TRY(scan_exclusive_u32(ctx, lat->vocc, voff.as<uint32_t>(), NV, false, st));
+            k_segment_heads<<<blocks_for(R, 256), 256, 0, st>>>(R, rvid.as<uint32_t>(), voff.as<uint32_t>());
+            FR_HIP(hipGetLastError());
+            k_segment_lengths<<<blocks_for(NV, 256), 256, 0, st>>>(NV, R, voff.as<uint32_t>(), lat->vocc);
+            FR_HIP(hipGetLastError());
             k_vertex_sum_sorted<D, V><<<blocks_for(NV, 256), 256, 0, st>>>(
                 NV, voff.as<uint32_t>(), lat->vocc, rid.as<uint32_t>(), rec_b.as<float>(), pts, lat->vval);
             FR_HIP(hipGetLastError());
             FR_HIP(hipStreamSynchronize(st));
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
+            FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
             k_vertex_sum_atomic<D, V><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(),
-                                                                           vid.as<uint32_t>(), rec_b.as<float>(), pts,
-                                                                           lat->vval, NV);
+                                                                           slot_vid.as<uint32_t>(), rec_b.as<float>(),
+                                                                           pts, lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
         }
     }
+    // the provisional table and records are no longer needed
+    rec_key.reset();
+    rec_b.reset();
+    rec_slot.reset();
+    own1.reset();
+    ovid.reset();
+    slot_vid.reset();
 
-    // 5. final tables
-    using L = SlotLayout<KW, V>;
+    // 5. final two-choice cuckoo tables, load factor 0.4
     lat->sets_h.resize(S);
     uint64_t n2 = 0;
     for (int32_t s = 0; s < S; ++s) {
-        const uint32_t cap = next_pow2(2 * (uint64_t)counts[s]);
-        lat->sets_h[s] = SetTable{n2, cap - 1, counts[s]};
+        const uint32_t cap = (uint32_t)std::max<uint64_t>(16, (5 * (uint64_t)counts[s] + 1) / 2);
+        lat->sets_h[s] = SetTable{n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0};
         n2 += cap;
     }
-    lat->table_bytes = n2 * L::kBytes;
-    FR_TRY(dev_alloc(ctx, &lat->table, lat->table_bytes));
-    lat->charged += lat->table_bytes;
+    lat->n_slots = n2;
+    lat->tkey_bytes = n2 * KW * sizeof(uint64_t);
+    lat->tval_bytes = n2 * VP * sizeof(float);
+    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tkey), lat->tkey_bytes));
+    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tval), lat->tval_bytes));
     FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->sets_d), S * sizeof(SetTable)));
-    lat->charged += S * sizeof(SetTable);
-    FR_HIP(hipMemcpyAsync(lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemsetAsync(lat->table, 0xFF, lat->table_bytes, st));
-    if (NV > 0) {
-        DevBuf own2, vtmap;
-        FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
+    DevBuf own2, vtmap;
+    FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
+    TileMap vtm{};
+    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm));
+    for (int attempt = 0;; ++attempt) {
+        FR_HIP(hipMemcpyAsync(lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
         FR_HIP(hipMemsetAsync(own2.p, 0xFF, n2 * sizeof(uint32_t), st));
-        TileMap vtm{};
-        FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm));
-        k_final_insert<KW, V><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey, lat->vval, NV,
-                                                           own2.as<uint32_t>(), static_cast<uint4 *>(lat->table));
-        FR_HIP(hipGetLastError());
+        FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
+        if (vtm.n_tiles > 0) {
+            k_cuckoo_insert<KW><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey, NV, own2.as<uint32_t>(),
+                                                             fail.as<int32_t>());
+            FR_HIP(hipGetLastError());
+        }
+        int32_t failed = 0;
+        FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
+        if (!failed) break;
+        if (attempt >= 16) {
+            set_error("fr_lattice_build: cuckoo insertion did not converge after %d seeds", attempt + 1);
+            return FR_EDEVICE;
+        }
+        for (int32_t s = 0; s < S; ++s) lat->sets_h[s].seed = lat->sets_h[s].seed * 0x9E3779B1u + 0x7F4A7C15u;
+    }
+    if (n2 > 0) {
+        k_cuckoo_fill<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, own2.as<uint32_t>(), lat->vkey, lat->vval, NV,
+                                                                 lat->tkey, lat->tval);
+        FR_HIP(hipGetLastError());
     }
     FR_HIP(hipStreamSynchronize(st));
     return FR_OK;

@@ -137,17 +137,33 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
     }
 }
 
-__global__ void __launch_bounds__(64) k_reduce_final(TileMap tm, const float *partials, double inv_s2, double *jtj,
-                                                     double *jtr, double *stats)
+// One block per segment: 8 lanes per value each sum every 8th tile in binary64,
+// then the 8 lane sums are added in lane order (fixed order, reproducible).
+constexpr int kFinalLanes = 8;
+
+__global__ void __launch_bounds__(256) k_reduce_final(TileMap tm, const float *partials, double inv_s2, double *jtj,
+                                                      double *jtr, double *stats)
 {
+    __shared__ double lane_sum[kRedVals][kFinalLanes];
     const int32_t s = blockIdx.x;
-    const int j = threadIdx.x;
-    if (j >= kRedVals) return;
-    double acc = 0.0;
-    for (int32_t t = tm.seg_tile[s]; t < tm.seg_tile[s + 1]; ++t) acc += (double)partials[(size_t)t * kRedStride + j];
-    if (j < 21) jtj[(size_t)s * 21 + j] = acc * inv_s2;
-    else if (j < 27) jtr[(size_t)s * 6 + (j - 21)] = acc * inv_s2;
-    else stats[(size_t)s * 4 + (j - 27)] = (j == 28) ? acc * inv_s2 : acc;
+    const int j = threadIdx.x / kFinalLanes;
+    const int l = threadIdx.x % kFinalLanes;
+    if (j < kRedVals) {
+        double acc = 0.0;
+        for (int32_t t = tm.seg_tile[s] + l; t < tm.seg_tile[s + 1]; t += kFinalLanes)
+            acc += (double)partials[(size_t)t * kRedStride + j];
+        lane_sum[j][l] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedVals) {
+        const int jj = threadIdx.x;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kFinalLanes; ++q) acc += lane_sum[jj][q];
+        if (jj < 21) jtj[(size_t)s * 21 + jj] = acc * inv_s2;
+        else if (jj < 27) jtr[(size_t)s * 6 + (jj - 21)] = acc * inv_s2;
+        else stats[(size_t)s * 4 + (jj - 27)] = (jj == 28) ? acc * inv_s2 : acc;
+    }
 }
 
 size_t reduce_partials_floats(const Plan &plan) { return (size_t)(plan.n_tiles + 1) * kRedStride; }
@@ -181,7 +197,7 @@ fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, co
         }
         FR_HIP(hipGetLastError());
     }
-    k_reduce_final<<<plan.n_seg, 64, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
+    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -37,6 +37,9 @@ __all__ = [
     "depth_pair",
     "random_cloud_pair",
     "separated_pair",
+    "articulated_pair",
+    "nodegraph_pair",
+    "KinTree",
     "random_motion",
     "request_stream",
 ]
@@ -337,6 +340,209 @@ def separated_pair(seed: int, m: int = 400, sigma: float = 0.02, spacing: float 
     return Pair(model=_f32(x), obs=_f32(y), T_gt=T, sigma=(sigma, sigma, sigma), feat=feat,
                 residual=residual, iters=15, model_n=_f32(xn), obs_n=_f32(yn), w=0.0,
                 name=f"separated-{m}-seed{seed}", extra={"T0": T0})
+
+
+# ---------------------------------------------------------------------------
+# Articulated: a tree of capsule links with revolute joints
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class KinTree:
+    """Kinematic tree: parent[b] < b (-1 = world); body b owns DOFs [dof_offset[b], dof_offset[b+1]);
+    joint origin origin[b] in the parent frame; axis[k] in the frame left by the preceding rotations."""
+    parent: np.ndarray
+    dof_offset: np.ndarray
+    origin: np.ndarray
+    axis: np.ndarray
+
+
+def _pose_bodies(tree: KinTree, theta):
+    """Body frames for joint angles theta (independent posing code for generating observations)."""
+    B = len(tree.parent)
+    Rs, ts = [None] * B, [None] * B
+    for b in range(B):
+        if tree.parent[b] < 0:
+            Rp, tp = np.eye(3), np.zeros(3)
+        else:
+            Rp, tp = Rs[tree.parent[b]], ts[tree.parent[b]]
+        t = Rp @ tree.origin[b] + tp
+        R = Rp
+        for k in range(tree.dof_offset[b], tree.dof_offset[b + 1]):
+            R = R @ Rotation.from_rotvec(tree.axis[k] * theta[k]).as_matrix()
+        Rs[b], ts[b] = R, t
+    return Rs, ts
+
+
+def _capsule_points(rng, length, radius, n):
+    """Uniform-by-area samples on a capsule along +x from the origin, with outward normals."""
+    a_cyl = 2 * math.pi * radius * length
+    a_cap = 4 * math.pi * radius ** 2
+    n_cyl = rng.binomial(n, a_cyl / (a_cyl + a_cap))
+    u = rng.uniform(0, length, n_cyl)
+    phi = rng.uniform(0, 2 * math.pi, n_cyl)
+    nc = np.column_stack([np.zeros(n_cyl), np.cos(phi), np.sin(phi)])
+    pc = np.column_stack([u, np.zeros(n_cyl), np.zeros(n_cyl)]) + radius * nc
+    m = n - n_cyl
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    centre = np.where(d[:, :1] >= 0, length, 0.0) * np.array([[1.0, 0.0, 0.0]])
+    ps = centre + radius * d
+    return np.concatenate([pc, ps]), np.concatenate([nc, d])
+
+
+def articulated_pair(seed: int, n_bodies: int = 20, n_dof: int = 32, m: int = 60_000, noise: float = 0.003,
+                     occlusion: float = 0.15, sigma: float = 0.01, sigma_n: float = 0.5, iters: int = 15,
+                     max_angle: float = 0.5, start_perturb: float = 0.1) -> Pair:
+    """Articulated workload: capsule links (length U[0.05, 0.15], radius U[0.015, 0.03]) in a random
+    tree, 1-3 revolute DOFs per joint summing to ``n_dof``, joint angles U[-0.5, 0.5];
+    observation = posed model + Gaussian noise, minus the ``occlusion`` fraction of points with
+    the largest projection on a random direction.  ``extra`` holds the tree, the per-body
+    point offsets, theta_gt and the start theta0 = theta_gt + U[-0.1, 0.1]."""
+    rng = np.random.default_rng(seed)
+    parent = np.array([-1] + [int(rng.integers(0, b)) for b in range(1, n_bodies)])
+    dofs = np.ones(n_bodies, dtype=np.int64)
+    while dofs.sum() < n_dof:
+        b = int(rng.integers(0, n_bodies))
+        if dofs[b] < 3:
+            dofs[b] += 1
+    dof_offset = np.concatenate([[0], np.cumsum(dofs)])
+    lengths = rng.uniform(0.05, 0.15, n_bodies)
+    radii = rng.uniform(0.015, 0.03, n_bodies)
+    origin = np.zeros((n_bodies, 3))
+    for b in range(1, n_bodies):
+        origin[b] = [lengths[parent[b]], 0.0, 0.0]
+    axis = rng.normal(size=(n_dof, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    tree = KinTree(parent, dof_offset, origin, axis)
+    area = 2 * math.pi * radii * lengths + 4 * math.pi * radii ** 2
+    counts = rng.multinomial(m, area / area.sum())
+    pts, nrm = [], []
+    for b in range(n_bodies):
+        p, n = _capsule_points(rng, lengths[b], radii[b], int(counts[b]))
+        pts.append(p)
+        nrm.append(n)
+    body_offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    x_ref = np.concatenate(pts)
+    n_ref = np.concatenate(nrm)
+    theta_gt = rng.uniform(-max_angle, max_angle, n_dof)
+    Rs, ts = _pose_bodies(tree, theta_gt)
+    y = np.zeros_like(x_ref)
+    yn = np.zeros_like(n_ref)
+    for b in range(n_bodies):
+        sl = slice(body_offsets[b], body_offsets[b + 1])
+        y[sl] = x_ref[sl] @ Rs[b].T + ts[b]
+        yn[sl] = n_ref[sl] @ Rs[b].T
+    y = y + rng.normal(scale=noise, size=y.shape)
+    direction = rng.normal(size=3)
+    proj = y @ direction
+    keep = proj <= np.quantile(proj, 1.0 - occlusion) if occlusion > 0 else np.ones(len(y), bool)
+    theta0 = theta_gt + rng.uniform(-start_perturb, start_perturb, n_dof)
+    return Pair(model=_f32(x_ref), obs=_f32(y[keep]), T_gt=np.eye(4), sigma=(sigma, sigma, sigma), feat=6,
+                residual="pt2pl", iters=iters, model_n=_f32(n_ref), obs_n=_f32(yn[keep]), sigma_n=sigma_n, w=0.1,
+                name=f"articulated-{m}-seed{seed}",
+                extra={"tree": tree, "body_offsets": body_offsets, "theta_gt": theta_gt, "theta0": theta0})
+
+
+# ---------------------------------------------------------------------------
+# Node graph: a displaced-sphere blob skinned to farthest-point-sampled nodes
+# ---------------------------------------------------------------------------
+
+def _farthest_points(rng, pts, k):
+    idx = np.zeros(k, dtype=np.int64)
+    idx[0] = int(rng.integers(0, len(pts)))
+    d = np.linalg.norm(pts - pts[idx[0]], axis=1)
+    for i in range(1, k):
+        idx[i] = int(np.argmax(d))
+        d = np.minimum(d, np.linalg.norm(pts - pts[idx[i]], axis=1))
+    return idx
+
+
+def _dq_blend(node_R, node_t, skin_idx, skin_w):
+    """Dual-quaternion blended rotation matrices and translations (generator's own implementation)."""
+    q = Rotation.from_matrix(node_R).as_quat()             # (K, 4) x, y, z, w
+    qr = np.concatenate([q[:, 3:], q[:, :3]], 1)            # w, x, y, z
+    tq = np.concatenate([np.zeros((len(node_t), 1)), node_t], 1)
+
+    def mul(a, b):
+        return np.stack([a[..., 0] * b[..., 0] - np.sum(a[..., 1:] * b[..., 1:], -1),
+                         *(a[..., :1] * b[..., 1:] + b[..., :1] * a[..., 1:] + np.cross(a[..., 1:], b[..., 1:])).T], -1) \
+            if a.ndim == 1 else np.concatenate(
+                [(a[..., 0] * b[..., 0] - np.sum(a[..., 1:] * b[..., 1:], -1))[..., None],
+                 a[..., :1] * b[..., 1:] + b[..., :1] * a[..., 1:] + np.cross(a[..., 1:], b[..., 1:])], -1)
+
+    qd = 0.5 * mul(tq, qr)
+    ref = qr[skin_idx[:, 0]]
+    sgn = np.where(np.einsum("ij,ikj->ik", ref, qr[skin_idx]) >= 0, 1.0, -1.0)
+    ww = skin_w * sgn
+    br = np.einsum("ik,ikj->ij", ww, qr[skin_idx])
+    bd = np.einsum("ik,ikj->ij", ww, qd[skin_idx])
+    nrm = np.linalg.norm(br, axis=1, keepdims=True)
+    br, bd = br / nrm, bd / nrm
+    R = Rotation.from_quat(np.concatenate([br[:, 1:], br[:, :1]], 1)).as_matrix()
+    conj = br * np.array([1.0, -1.0, -1.0, -1.0])
+    t = 2.0 * mul(bd, conj)[:, 1:]
+    return R, t
+
+
+def nodegraph_pair(seed: int, m: int = 100_000, n_nodes: int = 512, noise: float = 0.003, sigma: float = 0.02,
+                   max_angle_deg: float = 5.0, max_trans: float = 0.02, iters: int = 20, n_edges: int = 8,
+                   rigid: bool = False) -> Pair:
+    """Node-graph workload: ``m`` points on a sphere displaced by low-frequency noise, ``n_nodes``
+    nodes by farthest-point sampling, each point skinned to its 4 nearest nodes with weights
+    exp(-d^2 / (2 r^2)) (r = mean nearest-node spacing), ground-truth node motions from a smooth
+    random twist field (<= 5 deg, <= 0.02), observation = blended model + noise.
+    ``extra``: nodes, skin_idx, skin_w, edges (8-NN, directed), node_R/node_t ground truth."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    freqs = rng.normal(size=(6, 3)) * 1.5
+    phases = rng.uniform(0, 2 * math.pi, 6)
+    amps = rng.uniform(0.03, 0.08, 6)
+    radius = 1.0 + np.sum(amps[None] * np.sin(u @ freqs.T + phases[None]), 1)
+    x = u * radius[:, None]
+    # normals from the radial function by finite differences on the sphere
+    eps = 1e-4
+    def surf(v):
+        v = v / np.linalg.norm(v, axis=1, keepdims=True)
+        return v * (1.0 + np.sum(amps[None] * np.sin(v @ freqs.T + phases[None]), 1))[:, None]
+    a = np.cross(u, np.where(np.abs(u[:, :1]) < 0.9, [[1.0, 0, 0]], [[0, 1.0, 0]]))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    bvec = np.cross(u, a)
+    n = np.cross(surf(u + eps * a) - surf(u - eps * a), surf(u + eps * bvec) - surf(u - eps * bvec))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    n *= np.sign(np.sum(n * u, 1, keepdims=True))
+    nodes = x[_farthest_points(rng, x, n_nodes)]
+    tree = cKDTree(nodes)
+    dn, _ = tree.query(nodes, k=2)
+    r = float(np.mean(dn[:, 1]))
+    d4, i4 = tree.query(x, k=4)
+    w4 = np.exp(-d4 ** 2 / (2 * r * r))
+    w4 /= w4.sum(1, keepdims=True)
+    _, ie = tree.query(nodes, k=n_edges + 1)
+    edges = np.array([(j, k) for j in range(n_nodes) for k in ie[j, 1:]], dtype=np.int64)
+    if rigid:
+        T = random_motion(rng, math.radians(max_angle_deg), max_trans)
+        node_R = np.repeat(T[:3, :3][None], n_nodes, 0)
+        node_t = np.repeat(T[:3, 3][None], n_nodes, 0)
+    else:
+        fw = rng.normal(size=(3, 3)) * 1.2
+        fv = rng.normal(size=(3, 3)) * 1.2
+        pw = rng.uniform(0, 2 * math.pi, 3)
+        pv = rng.uniform(0, 2 * math.pi, 3)
+        wfield = np.sin(nodes @ fw.T + pw)
+        vfield = np.sin(nodes @ fv.T + pv)
+        wfield *= math.radians(max_angle_deg) / np.max(np.linalg.norm(wfield, axis=1))
+        vfield *= max_trans / np.max(np.abs(vfield))
+        node_R = Rotation.from_rotvec(wfield).as_matrix()
+        node_t = vfield
+    R, t = _dq_blend(node_R, node_t, i4, w4)
+    y = np.einsum("ijk,ik->ij", R, x) + t + rng.normal(scale=noise, size=x.shape)
+    yn = np.einsum("ijk,ik->ij", R, n)
+    return Pair(model=_f32(x), obs=_f32(y), T_gt=np.eye(4), sigma=(sigma, sigma, sigma), feat=3, residual="pt2pt",
+                iters=iters, model_n=_f32(n), obs_n=_f32(yn), w=0.1, name=f"nodegraph-{m}-seed{seed}",
+                extra={"nodes": nodes, "skin_idx": i4.astype(np.int32), "skin_w": w4, "edges": edges,
+                       "node_R": node_R, "node_t": node_t, "spacing": r})
 
 
 # ---------------------------------------------------------------------------
