@@ -52,7 +52,7 @@ enum { FR_VAL_PT2PT = 4, FR_VAL_PT2PL = 7 };              /* value channels V of
 enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
 enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
 enum { FR_PT2PT = 0, FR_PT2PL = 1 };
-enum { FR_KIN_RIGID = 0, FR_KIN_ARTICULATED = 1 };
+enum { FR_KIN_RIGID = 0, FR_KIN_ARTICULATED = 1, FR_KIN_NODEGRAPH = 2 };
 enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4 };
 
 typedef struct fr_ctx fr_ctx;
@@ -220,6 +220,8 @@ typedef struct {
     double estep_ms;           /* sum of E-step kernel times (FR_PROFILE_EVENTS) */
     double mstep_ms;           /* sum of reduce + solve times (FR_PROFILE_EVENTS) */
     int64_t estep_launches;
+    int32_t solver_iters;      /* node graph: conjugate-gradient iterations of the last solve */
+    double solver_residual;    /* node graph: relative residual of the last solve */
 } fr_report;
 
 /*
@@ -279,6 +281,38 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
                                   const fr_cloud *obs, const fr_kinematic_tree *tree,
                                   const fr_register_params *params, double *theta_inout_h, fr_report *report_h,
                                   void *stream);
+
+/*
+ * Node graph of a deformable model (Sec. 5.2, Eq. 21): nodes {p_k, T_k}; model
+ * point i moves by the normalised dual-quaternion blend of the transforms of
+ * its 4 skinning nodes skin_idx[4i..4i+3] with weights skin_w[4i..4i+3] (sum 1).
+ * The point twist is the blend of the node twists, so the node normal
+ * equations collect w_ki w_li J_i^T J_i per node pair; lambda weights the
+ * regulariser sum over directed edges (j, k) of |(T_j p_k - T_k p_k) / sigma|^2.
+ * All arrays are host memory.
+ */
+typedef struct {
+    int32_t n_nodes;
+    const double *nodes;        /* 3 x n_nodes reference node positions */
+    const int32_t *skin_idx;    /* 4 x M */
+    const float *skin_w;        /* 4 x M */
+    int32_t n_edges;
+    const int32_t *edges;       /* 2 x n_edges */
+    double lambda;              /* >= 0 */
+} fr_node_graph;
+
+/*
+ * Node-graph registration of one model set onto one observation set: per EM
+ * iteration the model is warped on the device (binary64 blend, binary32
+ * output), sliced, reduced into the block-sparse node system, which is solved
+ * by block-Jacobi preconditioned conjugate gradients in binary64 (relative
+ * residual 1e-10, at most 2000 iterations), and every node is updated by
+ * T_k <- Exp(dzeta_k) T_k.  node_T_inout_h (host, n_nodes x 16 row-major)
+ * holds the start transforms and receives the result.  Synchronous.
+ */
+fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_node_graph *graph,
+                                const fr_register_params *params, double *node_T_inout_h, fr_report *report_h,
+                                void *stream);
 
 /* Return (and clear) a device fault latched in `lat` by earlier async calls; synchronises. */
 fr_status fr_sync_status(const fr_lattice *lat);

@@ -33,7 +33,7 @@ FR_VAL_PT2PT, FR_VAL_PT2PL = 4, 7
 FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
 FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
-FR_KIN_RIGID, FR_KIN_ARTICULATED = 0, 1
+FR_KIN_RIGID, FR_KIN_ARTICULATED, FR_KIN_NODEGRAPH = 0, 1, 2
 FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED = 1, 2, 4
 
 STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
@@ -82,10 +82,17 @@ class fr_kinematic_tree(ctypes.Structure):
                 ("axis", ctypes.POINTER(ctypes.c_double))]
 
 
+class fr_node_graph(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("nodes", ctypes.POINTER(ctypes.c_double)),
+                ("skin_idx", ctypes.POINTER(ctypes.c_int32)), ("skin_w", ctypes.POINTER(ctypes.c_float)),
+                ("n_edges", ctypes.c_int32), ("edges", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.c_double)]
+
+
 class fr_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("n_degenerate", ctypes.c_int32), ("build_ms", ctypes.c_double),
                 ("em_ms", ctypes.c_double), ("estep_ms", ctypes.c_double), ("mstep_ms", ctypes.c_double),
-                ("estep_launches", ctypes.c_int64)]
+                ("estep_launches", ctypes.c_int64), ("solver_iters", ctypes.c_int32),
+                ("solver_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,6 +128,9 @@ _sig("fr_register", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud)
                           ctypes.POINTER(fr_register_params), _P, _P, ctypes.POINTER(fr_report), _P])
 _sig("fr_sync_status", _st, [_P])
 _sig("fr_articulated_step", _st, [_P, ctypes.POINTER(fr_kinematic_tree), _P, _P, _P, _P, _P, _P])
+_sig("fr_register_nodegraph", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
+                                    ctypes.POINTER(fr_node_graph), ctypes.POINTER(fr_register_params), _P,
+                                    ctypes.POINTER(fr_report), _P])
 _sig("fr_register_articulated", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_kinematic_tree),
                                       ctypes.POINTER(fr_register_params), _P, ctypes.POINTER(fr_report), _P])
@@ -128,7 +138,7 @@ _sig("fr_register_articulated", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINT
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
                  "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status",
-                 "fr_articulated_step", "fr_register_articulated"]
+                 "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph"]
 
 
 def _check(status: int):
@@ -422,6 +432,42 @@ def fr_register_articulated(ctx, model: Cloud, body_offsets, obs: Cloud, tree: K
                                       tree.c(), ctypes.byref(params), th.ctypes.data, ctypes.byref(rep),
                                       _stream(stream))
     theta[...] = th
+    if st not in (FR_OK, FR_EDEGENERATE):
+        _check(st)
+    return st, rep
+
+
+# --- node-graph models -------------------------------------------------------------
+class NodeGraph:
+    """fr_node_graph over host arrays kept alive by this object (Sec. 5.2)."""
+
+    def __init__(self, nodes, skin_idx, skin_w, edges, lam=1.0):
+        self.nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1)
+        self.skin_idx = np.ascontiguousarray(skin_idx, dtype=np.int32).reshape(-1)
+        self.skin_w = np.ascontiguousarray(skin_w, dtype=np.float32).reshape(-1)
+        self.edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1)
+        self.lam = float(lam)
+        self._c = fr_node_graph(len(self.nodes) // 3, self.nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                self.skin_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                self.skin_w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(self.edges) // 2,
+                                self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.lam)
+
+    @property
+    def n_nodes(self):
+        return len(self.nodes) // 3
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def fr_register_nodegraph(ctx, model: Cloud, obs: Cloud, graph: NodeGraph, params: fr_register_params,
+                          node_T: np.ndarray, stream=None):
+    """node_T: (n_nodes, 4, 4) float64 start transforms, updated in place.  Returns (status, report)."""
+    T = np.ascontiguousarray(node_T, dtype=np.float64)
+    rep = fr_report()
+    st = _lib.fr_register_nodegraph(ctx, model.c(), obs.c(), graph.c(), ctypes.byref(params), T.ctypes.data,
+                                    ctypes.byref(rep), _stream(stream))
+    node_T[...] = T
     if st not in (FR_OK, FR_EDEGENERATE):
         _check(st)
     return st, rep

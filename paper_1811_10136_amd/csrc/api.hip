@@ -876,4 +876,124 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
     return FR_OK;
 }
 
+
+fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_node_graph *graph,
+                                const fr_register_params *params, double *node_T_inout_h, fr_report *report_h,
+                                void *stream)
+{
+    clear_error();
+    using clk = std::chrono::steady_clock;
+    if (!ctx_ok(ctx) || params == nullptr || node_T_inout_h == nullptr || graph == nullptr) {
+        set_error("fr_register_nodegraph: invalid context, params, graph or node transforms");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_lattice_params(&params->lattice));
+    if ((params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
+        (params->residual == FR_PT2PL && params->lattice.values != FR_VAL_PT2PL) || params->max_iters < 0 ||
+        !(params->w >= 0.0 && params->w < 1.0)) {
+        set_error("fr_register_nodegraph: bad residual/values, max_iters or w");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register_nodegraph(model)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register_nodegraph(obs)"));
+    if (model_ref->n_sets != 1 || obs->n_sets != 1) {
+        set_error("fr_register_nodegraph: one model set and one observation set");
+        return FR_EINVAL;
+    }
+    const int64_t M = cloud_points(model_ref);
+    const int32_t K = graph->n_nodes;
+    if (K < 1 || graph->nodes == nullptr || (M > 0 && (graph->skin_idx == nullptr || graph->skin_w == nullptr)) ||
+        graph->n_edges < 0 || (graph->n_edges > 0 && graph->edges == nullptr) || !(graph->lambda >= 0.0)) {
+        set_error("fr_register_nodegraph: graph needs nodes, skinning arrays, edges and lambda >= 0");
+        return FR_EINVAL;
+    }
+    for (int64_t i = 0; i < 4 * M; ++i)
+        if (graph->skin_idx[i] < 0 || graph->skin_idx[i] >= K) {
+            set_error("fr_register_nodegraph: skin index %d out of [0, %d)", graph->skin_idx[i], K);
+            return FR_EINVAL;
+        }
+    for (int32_t q = 0; q < 2 * graph->n_edges; ++q)
+        if (graph->edges[q] < 0 || graph->edges[q] >= K) {
+            set_error("fr_register_nodegraph: edge node out of range");
+            return FR_EINVAL;
+        }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    fr_report rep{};
+    auto t0 = clk::now();
+    fr_lattice *lat = nullptr;
+    FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat));
+    struct LatGuard {
+        fr_lattice *l;
+        ~LatGuard()
+        {
+            if (l) fr_lattice_destroy(l);
+        }
+    } guard{lat};
+    rep.build_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+
+    NodeGraphDev d;
+    FR_TRY(ng_setup(ctx, graph, M, st, d));
+    std::vector<double> T12((size_t)12 * K);
+    for (int32_t k = 0; k < K; ++k)
+        for (int j = 0; j < 12; ++j) T12[(size_t)12 * k + j] = node_T_inout_h[(size_t)16 * k + j];
+    FR_HIP(hipMemcpyAsync(d.T, T12.data(), T12.size() * sizeof(double), hipMemcpyHostToDevice, st));
+
+    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
+    double c = 0.0;
+    if (params->c_override >= 0.0) c = params->c_override;
+    else if (M > 0 && params->w > 0.0)
+        c = params->w / (1.0 - params->w) * ((double)cloud_points(obs) / (double)M) * std::pow(2.0 * M_PI, 1.5) * s3;
+    const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
+    const bool normals = params->lattice.feat == 6;
+    const size_t nM = (size_t)std::max<int64_t>(M, 1);
+    DevBuf wpts, wm0, wm1, wns;
+    FR_TRY(wpts.alloc(ctx, (normals ? 6 : 3) * nM * sizeof(float)));
+    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+    if (lat->V == 7) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
+    float *wp = wpts.as<float>();
+    float *const outs[6] = {wp, wp + nM, wp + 2 * nM, normals ? wp + 3 * nM : nullptr, normals ? wp + 4 * nM : nullptr,
+                            normals ? wp + 5 * nM : nullptr};
+    int64_t offs[2] = {0, M};
+    fr_cloud warped{outs[0], outs[1], outs[2], outs[3], outs[4], outs[5], offs, 1};
+    Plan pe;
+    FR_TRY(make_plan(ctx, &warped, nullptr, 256, nullptr, st, pe));
+    auto t2 = clk::now();
+    int it = 0;
+    double info[2] = {0.0, 0.0};
+    int32_t bad = 0;
+    for (; it < params->max_iters; ++it) {
+        FR_TRY(ng_warp(d, model_ref, outs, st));
+        FR_TRY(launch_estep(lat, &warped, pe, FR_XF_NONE, nullptr, wm0.as<float>(), wm1.as<float>(),
+                            lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+        FR_TRY(ng_step(d, outs[0], outs[1], outs[2], wm0.as<float>(), wm1.as<float>(),
+                       lat->V == 7 ? wns.as<float>() : nullptr, params->residual, c, sig_m, graph->lambda, 1e-10, 2000,
+                       st));
+        FR_HIP(hipMemcpyAsync(info, d.info, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(&bad, d.bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipStreamSynchronize(st));
+        if (bad) {
+            ++it;
+            break;
+        }
+    }
+    FR_HIP(hipMemcpyAsync(T12.data(), d.T, T12.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    for (int32_t k = 0; k < K; ++k)
+        for (int j = 0; j < 12; ++j) node_T_inout_h[(size_t)16 * k + j] = T12[(size_t)12 * k + j];
+    rep.iterations = it;
+    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t2).count();
+    rep.solver_iters = (int32_t)info[0];
+    rep.solver_residual = info[1];
+    rep.n_degenerate = bad ? 1 : 0;
+    if (report_h) *report_h = rep;
+    FR_TRY(fr_sync_status(lat));
+    if (bad) {
+        set_error("fr_register_nodegraph: a node's diagonal block is singular");
+        return FR_EDEGENERATE;
+    }
+    return FR_OK;
+}
+
 }  // extern "C"

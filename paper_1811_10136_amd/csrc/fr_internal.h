@@ -163,6 +163,31 @@ fr_status upload_tree(fr_ctx *ctx, const fr_kinematic_tree *tree, hipStream_t st
 fr_status launch_articulated_step(const ArtTreeHost &tree, int mode, const double *jtj, const double *jtr,
                                   double *theta, float *mats, double *step_norm, int32_t *status, hipStream_t stream);
 
+// nodegraph.hip
+struct NodeGraphDev {
+    int32_t K = 0, E = 0, n_blocks = 0;
+    int64_t M = 0;
+    DevBuf meta, work;
+    const double *nodes = nullptr;
+    const int32_t *edges = nullptr;
+    const int4 *skin_idx = nullptr;
+    const float4 *skin_w = nullptr;
+    const int32_t *blk_off = nullptr, *blk_pts = nullptr, *rhs_off = nullptr, *rhs_pts = nullptr;
+    const float *blk_w = nullptr, *rhs_w = nullptr;
+    const int32_t *reg_off = nullptr, *reg_ref = nullptr, *nreg_off = nullptr, *nreg_ref = nullptr;
+    const int32_t *row_off = nullptr, *row_blk = nullptr, *row_col = nullptr, *diag_blk = nullptr;
+    double *T = nullptr, *dq = nullptr, *data21 = nullptr, *bdata = nullptr, *edge_terms = nullptr, *A = nullptr,
+           *minv = nullptr, *rhs = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+           *info = nullptr;
+    float *terms = nullptr;
+    int32_t *bad = nullptr;
+};
+fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t stream, NodeGraphDev &d);
+fr_status ng_warp(const NodeGraphDev &d, const fr_cloud *ref, float *const out[6], hipStream_t stream);
+fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
+                  const float *ns, int residual, double c, double sigma, double lambda, double tol, int32_t max_it,
+                  hipStream_t stream);
+
 // scan / sort helpers (lattice_build.hip)
 fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t stream);
 
