@@ -261,7 +261,8 @@ typedef struct {
  * body by forward kinematics (DOF k moves the bodies below its joint with the
  * twist (w_k, q_k x w_k) of its world axis w_k through the joint point q_k),
  * assembles A = sum_b J_b^T jtj_b J_b and b = sum_b J_b^T jtr_b, solves
- * A dtheta = -b by Cholesky, updates theta (device, n_dof) in place and writes
+ * A dtheta = -b by Cholesky (a DOF whose row of A is zero -- it moves no
+ * supported point -- is held at its value), updates theta (device, n_dof) in place and writes
  * the binary32 [R | t] of every body at the new angles to mats (device,
  * n_bodies x 12).  status (device int32, may be NULL) receives FR_OK or
  * FR_EDEGENERATE (theta unchanged).  jtj/jtr may be NULL for forward

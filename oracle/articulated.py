@@ -131,6 +131,20 @@ def normal_equations_direct(tree, theta, x, body_offsets, m0, m1, ns, c, sigma, 
     return A, bvec
 
 
+def hold_unsupported(A, b):
+    """A DOF that moves no supported point has an all-zero row and column in A (Alg. 1 sums
+    only supported points).  Reading: such a DOF is held, dtheta_k = 0, and the other DOFs are
+    solved as if it were absent (its row/column replaced by the identity, b_k = 0)."""
+    held = np.diag(A) == 0.0
+    if not held.any():
+        return A, b
+    A = A.copy()
+    A[held, :] = 0.0
+    A[:, held] = 0.0
+    A[held, held] = 1.0
+    return A, np.where(held, 0.0, b)
+
+
 def register_articulated(tree: Tree, x_ref, n_ref, body_offsets, obs, obs_n, *, feat, residual, sigma,
                          sigma_n=0.5, c=None, w=0.1, iters=15, theta0=None, history=None):
     """Articulated FilterReg: lattice built once, then per EM iteration slice at the pinned
@@ -156,7 +170,7 @@ def register_articulated(tree: Tree, x_ref, n_ref, body_offsets, obs, obs_n, *, 
             x64[sl] = x_ref[sl].astype(np.float64) @ R[:, :3].T + R[:, 3]
         m0, m1, ns = estep(lat, x32, n32, feat, residual)
         A, b = normal_equations_alg1(tree, theta, x64, body_offsets, m0, m1, ns, c, sig_m, residual)
-        dth = gn_step(A, b)
+        dth = gn_step(*hold_unsupported(A, b))
         theta = theta + dth
         if history is not None:
             history.append(dict(A=A, b=b, dtheta=dth, theta=theta.copy()))

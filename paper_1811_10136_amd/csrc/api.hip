@@ -139,6 +139,7 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
     FR_HIP(hipStreamSynchronize(st));
     const char *p = plan.meta.as<char>();
     plan.tm.seg_off = reinterpret_cast<const int64_t *>(p);
+    plan.tm.seg_end = plan.tm.seg_off + 1;
     plan.tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
     plan.tm.seg_set = reinterpret_cast<const int32_t *>(p + b_off + b_tile);
     plan.seg_c = reinterpret_cast<const float *>(p + b_off + b_tile + b_set);

@@ -163,6 +163,15 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
             s_rhs[k] = acc;
         }
         __syncthreads();
+        // a DOF that moves no supported point has an all-zero row and column: hold it (identity
+        // row, zero right-hand side) and solve the others
+        for (int k = tid; k < n; k += kArtThreads) {
+            if (s_A[k * n + k] == 0.0) {
+                s_A[k * n + k] = 1.0;
+                s_rhs[k] = 0.0;
+            }
+        }
+        __syncthreads();
         // Cholesky A = L L^T in place (lower triangle), column by column
         for (int j = 0; j < n; ++j) {
             if (tid == 0) {

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
-    if (i >= a.tm.seg_off[s + 1]) return;
+    if (i >= a.tm.seg_end[s]) return;
     const SetTable st = a.sets[a.tm.seg_set[s]];
 
     float px = ld_stream(a.x + i), py = ld_stream(a.y + i), pz = ld_stream(a.z + i);
@@ -75,8 +75,7 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     float acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0f;
-    slice_simplex<KW, V, D>(a.tkey + st.slot_base * KW, a.tval + st.slot_base * ValPad<V>::value, st, keys, b,
-                            acc);
+    slice_simplex<KW, V, D>(st.keys, st.vals, st, keys, b, acc);
 
     st_stream(a.m0 + i, acc[0]);
     st_stream(a.m1 + i, acc[1]);
@@ -101,7 +100,7 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
-    if (i >= a.tm.seg_off[s + 1]) return;
+    if (i >= a.tm.seg_end[s]) return;
     const SetTable st = a.sets[a.tm.seg_set[s]];
     float p[d];
     if constexpr (XF) {
@@ -128,7 +127,7 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     embed<d>(p, kk, keys, b);
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        const int64_t slot = find_slot<KW>(a.tkey + st.slot_base * KW, st, keys[v]);
+        const int64_t slot = find_slot<KW>(st.keys, st, keys[v]);
         if (slot >= 0) a.touched[st.slot_base + slot] = 1u;
     }
 }

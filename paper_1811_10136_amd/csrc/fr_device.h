@@ -28,9 +28,12 @@ template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; }; 
 // VP = 4 or 8 (one or two 16-byte loads).
 template <int V> struct ValPad { static constexpr int value = V <= 4 ? 4 : 8; };
 
-// Per-set view of the lattice table.
+// Per-set view of the lattice table.  keys/vals point at the set's first
+// slot, so one launch can slice sets of lattices that were built separately.
 struct SetTable {
-    uint64_t slot_base;   // first slot of the set in the shared table
+    const uint64_t *keys; // KW words per slot
+    const float *vals;    // VP binary32 per slot
+    uint64_t slot_base;   // first slot of the set in its lattice's table
     uint32_t cap;         // slots of the set (>= 16)
     uint32_t n_vertices;
     uint32_t seed;        // hash seed (changed when a cuckoo insertion has to be redone)
@@ -39,7 +42,8 @@ struct SetTable {
 
 // Tiles of points grouped by segment; a segment lies inside one set.
 struct TileMap {
-    const int64_t *seg_off;    // n_seg + 1 point offsets
+    const int64_t *seg_off;    // n_seg first points
+    const int64_t *seg_end;    // n_seg end points (seg_off + 1 for a partition)
     const int32_t *seg_tile;   // n_seg + 1 tile prefix
     const int32_t *seg_set;    // n_seg
     int32_t n_seg;

@@ -245,8 +245,8 @@ __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, float4 k
     const int32_t s = tile_segment(tm, t);
     const int64_t first = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile;
     const int64_t i = first + threadIdx.x;
-    const int64_t n_here = min((int64_t)tm.tile, tm.seg_off[s + 1] - first);
-    if (i < tm.seg_off[s + 1]) {
+    const int64_t n_here = min((int64_t)tm.tile, tm.seg_end[s] - first);
+    if (i < tm.seg_end[s]) {
         float p[d];
         float kk[d];
         const float kall[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTab
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
     const int64_t r = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
-    if (r >= tm.seg_off[s + 1]) return;
+    if (r >= tm.seg_end[s]) return;
     uint64_t key[KW];
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = rec_key[(size_t)w * R + r];
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
     const int64_t v = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
-    if (v >= tm.seg_off[s + 1]) return;
+    if (v >= tm.seg_end[s]) return;
     const SetTable st = tables[s];
     uint32_t cur = (uint32_t)v;
     uint64_t key[KW];
@@ -544,6 +544,7 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     FR_HIP(hipMemcpyAsync(p + b_off, tiles.data(), b_tile, hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(p + b_off + b_tile, sets.data(), b_set, hipMemcpyHostToDevice, st));
     tm.seg_off = reinterpret_cast<const int64_t *>(p);
+    tm.seg_end = tm.seg_off + 1;
     tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
     tm.seg_set = reinterpret_cast<const int32_t *>(p + b_off + b_tile);
     tm.n_seg = n;
@@ -600,7 +601,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         for (int32_t s = 0; s < S; ++s) {
             const uint64_t rs = (uint64_t)(roff[s + 1] - roff[s]);
             const uint32_t cap = next_pow2(attempt == 0 ? rs / 2 : 2 * rs);
-            t1[s] = SetTable{n1, cap, 0, 0, cap - 1};
+            t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1};
             n1 += cap;
         }
         if (n1 >= 0xFFFFFFF0ull) {
@@ -727,7 +728,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     uint64_t n2 = 0;
     for (int32_t s = 0; s < S; ++s) {
         const uint32_t cap = (uint32_t)std::max<uint64_t>(16, (5 * (uint64_t)counts[s] + 1) / 2);
-        lat->sets_h[s] = SetTable{n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0};
+        lat->sets_h[s] = SetTable{nullptr, nullptr, n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0};
         n2 += cap;
     }
     lat->n_slots = n2;
@@ -736,6 +737,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tkey), lat->tkey_bytes));
     FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tval), lat->tval_bytes));
     FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->sets_d), S * sizeof(SetTable)));
+    for (int32_t s = 0; s < S; ++s) {
+        lat->sets_h[s].keys = lat->tkey + lat->sets_h[s].slot_base * KW;
+        lat->sets_h[s].vals = lat->tval + lat->sets_h[s].slot_base * VP;
+    }
     DevBuf own2, vtmap;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
     TileMap vtm{};

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     const int64_t start = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
-    const int64_t stop = min(start + (int64_t)a.tm.tile, a.tm.seg_off[s + 1]);
+    const int64_t stop = min(start + (int64_t)a.tm.tile, a.tm.seg_end[s]);
     const float c = a.seg_c[s];
     float m[12];
     if constexpr (XF) {

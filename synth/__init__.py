@@ -392,27 +392,45 @@ def _capsule_points(rng, length, radius, n):
 
 def articulated_pair(seed: int, n_bodies: int = 20, n_dof: int = 32, m: int = 60_000, noise: float = 0.003,
                      occlusion: float = 0.15, sigma: float = 0.01, sigma_n: float = 0.5, iters: int = 15,
-                     max_angle: float = 0.5, start_perturb: float = 0.1) -> Pair:
-    """Articulated workload: capsule links (length U[0.05, 0.15], radius U[0.015, 0.03]) in a random
-    tree, 1-3 revolute DOFs per joint summing to ``n_dof``, joint angles U[-0.5, 0.5];
-    observation = posed model + Gaussian noise, minus the ``occlusion`` fraction of points with
-    the largest projection on a random direction.  ``extra`` holds the tree, the per-body
-    point offsets, theta_gt and the start theta0 = theta_gt + U[-0.1, 0.1]."""
+                     max_angle: float = 0.5, start_perturb: float = 0.03) -> Pair:
+    """Articulated workload: capsule links (length U[0.05, 0.15], radius U[0.015, 0.03], axis along
+    the body's x) in a random tree, 1-3 revolute DOFs per joint summing to ``n_dof``, joint angles
+    U[-0.5, 0.5]; observation = posed model + Gaussian noise, minus the ``occlusion`` fraction of
+    points with the largest projection on a random direction.  ``extra`` holds the tree, the
+    per-body point offsets, theta_gt and the start theta0 = theta_gt + U[-start_perturb, start_perturb].
+
+    A capsule is symmetric about its own axis, so a spin about that axis is seen only through the
+    bodies hanging from it.  Joint axes are chosen so that every DOF moves some surface: one or two
+    DOFs turn about orthogonal axes across the link (in its y-z plane); a third DOF, the spin about
+    the link axis, is given only to bodies with children, and children hang off-axis from the end
+    of their parent."""
     rng = np.random.default_rng(seed)
     parent = np.array([-1] + [int(rng.integers(0, b)) for b in range(1, n_bodies)])
+    has_child = np.zeros(n_bodies, bool)
+    has_child[parent[parent >= 0]] = True
     dofs = np.ones(n_bodies, dtype=np.int64)
+    if n_dof > int(np.where(has_child, 3, 2).sum()):
+        raise ValueError("too many DOFs for this tree")
     while dofs.sum() < n_dof:
         b = int(rng.integers(0, n_bodies))
-        if dofs[b] < 3:
+        if dofs[b] < (3 if has_child[b] else 2):
             dofs[b] += 1
     dof_offset = np.concatenate([[0], np.cumsum(dofs)])
     lengths = rng.uniform(0.05, 0.15, n_bodies)
     radii = rng.uniform(0.015, 0.03, n_bodies)
     origin = np.zeros((n_bodies, 3))
     for b in range(1, n_bodies):
-        origin[b] = [lengths[parent[b]], 0.0, 0.0]
-    axis = rng.normal(size=(n_dof, 3))
-    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+        phi = rng.uniform(0, 2 * math.pi)
+        r = 0.7 * radii[parent[b]]
+        origin[b] = [lengths[parent[b]], r * math.cos(phi), r * math.sin(phi)]
+    axis = np.zeros((n_dof, 3))
+    for b in range(n_bodies):
+        k0, nb = dof_offset[b], dofs[b]
+        phi = rng.uniform(0, 2 * math.pi)
+        across = [np.array([0.0, math.cos(phi), math.sin(phi)]), np.array([0.0, -math.sin(phi), math.cos(phi)])]
+        seq = across[:nb] if nb <= 2 else [np.array([1.0, 0.0, 0.0])] + across
+        for j, a in enumerate(seq):
+            axis[k0 + j] = a
     tree = KinTree(parent, dof_offset, origin, axis)
     area = 2 * math.pi * radii * lengths + 4 * math.pi * radii ** 2
     counts = rng.multinomial(m, area / area.sum())

@@ -109,3 +109,25 @@ def test_articulated_exact_recovery():
                                   sigma=p.sigma, sigma_n=p.sigma_n, c=0.0, iters=10, theta0=p.extra["theta0"])
     assert np.abs(th - p.extra["theta_gt"]).max() < 1e-6
     assert np.abs(p.extra["theta0"] - p.extra["theta_gt"]).max() > 1e-4
+
+
+def test_dofs_of_a_body_without_points_are_held():
+    """The last body is a leaf; with none of its points in the model its DOFs move nothing.  They
+    stay at their start values and the other DOFs follow exactly the registration of the tree
+    without that body."""
+    p, tree = separated_articulated(4)
+    bo = p.extra["body_offsets"]
+    B = tree.n_bodies
+    assert not np.any(tree.parent == B - 1)
+    nd = int(tree.dof_offset[B - 1])
+    keep = slice(0, int(bo[B - 1]))
+    bo_full = np.concatenate([bo[:B], [bo[B - 1]]])           # last body: 0 points
+    th0 = p.extra["theta0"]
+    kw = dict(feat=6, residual="pt2pl", sigma=p.sigma, sigma_n=p.sigma_n, c=0.0, iters=5)
+    th_full = art.register_articulated(tree, p.model[keep], p.model_n[keep], bo_full, p.obs, p.obs_n,
+                                       theta0=th0, **kw)
+    sub = art.Tree(tree.parent[:B - 1], tree.dof_offset[:B], tree.origin[:B - 1], tree.axis[:nd])
+    th_sub = art.register_articulated(sub, p.model[keep], p.model_n[keep], bo[:B], p.obs, p.obs_n,
+                                      theta0=th0[:nd], **kw)
+    np.testing.assert_array_equal(th_full[nd:], th0[nd:])
+    np.testing.assert_allclose(th_full[:nd], th_sub, rtol=0, atol=1e-12)
