@@ -70,17 +70,32 @@ def traffic_from_profile(pairs_points):
     return prof.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(pair, iters):
-    """The CPU oracle on one pair of the batch: lattice build + `iters` EM iterations."""
+def cpu_baseline(pairs, iters):
+    """The CPU oracle on the first pairs of the batch: lattice build + `iters` EM iterations each."""
     import oracle
     T0 = np.eye(4)
     t0 = time.perf_counter()
-    oracle.register_rigid(pair.model, pair.model_n, pair.obs, pair.obs_n, feat=6, residual="pt2pl",
-                          sigma=pair.sigma, sigma_n=pair.sigma_n, w=pair.w, iters=iters, T0=T0)
+    for pair in pairs:
+        oracle.register_rigid(pair.model, pair.model_n, pair.obs, pair.obs_n, feat=6, residual="pt2pl",
+                              sigma=pair.sigma, sigma_n=pair.sigma_n, w=pair.w, iters=iters, T0=T0)
     dt = time.perf_counter() - t0
-    return {"value": len(pair.model) * iters / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of the batch's pairs ({len(pair.model)} model / {len(pair.obs)} obs points): "
-                      f"lattice build + {iters} EM iterations, single-threaded C + NumPy float64, {dt:.1f} s"}
+    pts = sum(len(p.model) for p in pairs)
+    return {"value": pts * iters / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {len(pairs)} pairs of the batch ({pts} model / {sum(len(p.obs) for p in pairs)} obs "
+                      f"points): lattice build + {iters} EM iterations each, single-threaded C + NumPy float64, "
+                      f"{dt:.1f} s"}
+
+
+def copy_reference(nbytes=256 << 20, reps=3):
+    """Plain device-to-device copies of a known size, so a counter run over this process can scale
+    its HBM byte counters (the copy moves exactly nbytes in and nbytes out per launch)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy reference: {reps} copies of {nbytes} bytes")
 
 
 def main():
@@ -92,6 +107,8 @@ def main():
     ap.add_argument("--iters", type=int, default=ITERS)
     ap.add_argument("--splat", choices=["sorted", "atomic"], default="sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=3, help="pairs the CPU oracle baseline runs")
+    ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
 
@@ -192,8 +209,10 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on one pair ...")
-        out["cpu_baseline"] = cpu_baseline(pairs[0], args.iters)
+        log(f"timing the CPU oracle on {args.cpu_pairs} pairs ...")
+        out["cpu_baseline"] = cpu_baseline(pairs[:args.cpu_pairs], args.iters)
+    if args.copy_ref:
+        copy_reference()
     print(json.dumps(out), flush=True)
 
 

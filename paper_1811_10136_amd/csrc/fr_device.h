@@ -111,24 +111,32 @@ __device__ __forceinline__ void cuckoo_slots(uint32_t h, uint32_t cap, uint32_t 
     p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
 }
 
-// Loads from a uniform table base with a 32-bit byte offset (slot < 2^27), so
-// the compiler can use the scalar-base + vector-offset addressing form.
+// Loads from a uniform table base with a 32-bit byte offset (slot < 2^27).
+// The base is cast to the global address space: table pointers arrive through
+// memory (the per-set table), where the compiler cannot infer it, and a
+// generic pointer would turn every lookup into a flat load with 64-bit address
+// arithmetic instead of the scalar-base + vector-offset global form.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const char global_cchar;
+
 template <typename T>
 __device__ __forceinline__ T load_at(const void *__restrict__ base, uint32_t byte_off)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    typedef __attribute__((address_space(1))) const T global_T;
+    return *(global_T *)((global_cchar *)base + byte_off);
 }
 
 template <int KW>
 __device__ __forceinline__ void load_key(const uint64_t *__restrict__ keys, uint32_t slot, uint64_t (&k)[KW])
 {
     if constexpr (KW == 2) {
-        const uint4 q = load_at<uint4>(keys, slot << 4);
+        const u32x4 q = load_at<u32x4>(keys, slot << 4);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
         k[1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
     } else {
         static_assert(KW == 1, "keys of 1 or 2 words");
-        const uint2 q = load_at<uint2>(keys, slot << 3);
+        const u32x2 q = load_at<u32x2>(keys, slot << 3);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
     }
 }
@@ -290,10 +298,10 @@ __device__ __forceinline__ void xform_normal(const float *m, float x, float y, f
 }
 
 // Slice one point: read the two candidate key slots of all D vertices at
-// once, then one value slot per vertex, and accumulate b * value.  A vertex
-// absent from the lattice gets weight 0 (its value read falls on a valid slot),
-// so there are no divergent branches.  kb/vb are the set's table bases
-// (uniform per block), slots are 32-bit offsets.
+// once, then the value slot of each vertex found, and accumulate b * value.
+// A vertex absent from the lattice contributes nothing; its lane skips the
+// value load (a predicated load, the only divergence).  kb/vb are the set's
+// table bases (uniform per block), slots are 32-bit offsets.
 template <int KW, int V, int D>
 __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, const float *__restrict__ vb,
                                               const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
@@ -315,13 +323,16 @@ __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, c
         const uint32_t slot = in1 ? p1[v] : p2[v];
         const float w = (in1 || in2) ? b[v] : 0.0f;
         const uint32_t off = slot * (uint32_t)(VP * sizeof(float));
-        float val[VP];
-        const float4 q0 = load_at<float4>(vb, off);
-        val[0] = q0.x; val[1] = q0.y; val[2] = q0.z; val[3] = q0.w;
-        if constexpr (VP == 8) {
-            const float4 q1 = load_at<float4>(vb, off + 16u);
-            val[4] = q1.x; val[5] = q1.y; val[6] = q1.z; val[7] = q1.w;
+        // only lanes whose vertex exists fetch its values: an absent vertex
+        // would otherwise pull a random table line through the caches
+        u32x4 q0 = {0u, 0u, 0u, 0u}, q1 = q0;
+        if (in1 || in2) {
+            q0 = load_at<u32x4>(vb, off);
+            if constexpr (VP == 8) q1 = load_at<u32x4>(vb, off + 16u);
         }
+        const float val[8] = {__uint_as_float(q0.x), __uint_as_float(q0.y), __uint_as_float(q0.z),
+                              __uint_as_float(q0.w), __uint_as_float(q1.x), __uint_as_float(q1.y),
+                              __uint_as_float(q1.z), __uint_as_float(q1.w)};
 #pragma unroll
         for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
     }
