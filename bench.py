@@ -10,10 +10,20 @@ spheres (about 260k points with normals); observation = the scene after a
 random motion (<= 10 deg, <= 0.05 m), 2 mm depth noise, 5% dropout; d = 6
 features (position / 0.03 m, normal / 0.5), point-to-plane, sorted splat.
 
+Then the served stream: 4096 rigid point-to-plane requests of log-uniform
+size (1k-300k model points, drawn from depth renders like the above) arrive
+as a Poisson stream and are registered (20 EM iterations each) either one at
+a time by fr_register (the plain loop) or by the continuous-batching server
+(fr_engine_*: every resident request advances one EM iteration per batched
+step).  The arrival rate sweeps multiples of the plain loop's measured
+capacity; the headline is the largest rate whose served p99 latency stays
+under 100 ms.
+
 Prints one JSON line: metric/value (E-step model points per second over the
-whole step), registrations/s and step latency percentiles, the roofline of the
-E-step kernel (algorithmic bytes / mean kernel time from HIP events recorded
-on the launch stream during the timed steps) and the CPU oracle baseline.
+whole batched step), registrations/s and p50/p99 latency of the served stream,
+the roofline of the E-step kernel (algorithmic bytes / mean kernel time from
+HIP events recorded on the launch stream during the timed steps), the plain
+loop beside the server, and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -98,6 +108,141 @@ def copy_reference(nbytes=256 << 20, reps=3):
     log(f"copy reference: {reps} copies of {nbytes} bytes")
 
 
+# ------------------------------------------------------------------------------
+# served stream
+SERVE_FRAMES = 64
+SERVE_FRAME_POINTS = 300_000
+
+
+def _make_frame(seed):
+    return synth.depth_pair(seed, target_points=SERVE_FRAME_POINTS)
+
+
+def make_request_stream(n, seed, workers):
+    """Requests of log-uniform size in [1k, 300k] model points.  Request i is a sorted random
+    subsample (m_i model points, m_i * N/M observation points, image order kept) of one of
+    SERVE_FRAMES depth-frame pairs rendered at 300k points; the subsampling runs on the device
+    with a seeded generator.  Returns the model and observation clouds (one set per request,
+    resident in HBM) and the per-request point counts."""
+    import math
+    import torch
+    import paper_1811_10136_amd as fr
+    t = time.time()
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        frames = list(ex.map(_make_frame, range(10_000, 10_000 + SERVE_FRAMES)))
+    log(f"rendered {len(frames)} frames for the request stream in {time.time() - t:.1f} s")
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(1000), math.log(300_000), n)).astype(np.int64)
+    fid = rng.integers(0, SERVE_FRAMES, n)
+    fm = [torch.from_numpy(np.ascontiguousarray(np.concatenate([f.model, f.model_n], 1).T)).cuda() for f in frames]
+    fo = [torch.from_numpy(np.ascontiguousarray(np.concatenate([f.obs, f.obs_n], 1).T)).cuda() for f in frames]
+    m = np.array([min(int(sizes[i]), fm[fid[i]].shape[1]) for i in range(n)], dtype=np.int64)
+    k = np.array([min(max(1, int(round(m[i] * fo[fid[i]].shape[1] / fm[fid[i]].shape[1]))), fo[fid[i]].shape[1])
+                  for i in range(n)], dtype=np.int64)
+    mo = np.concatenate([[0], np.cumsum(m)])
+    oo = np.concatenate([[0], np.cumsum(k)])
+    M = torch.empty((6, int(mo[-1])), dtype=torch.float32, device="cuda")
+    O = torch.empty((6, int(oo[-1])), dtype=torch.float32, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    for i in range(n):
+        a, b = fm[fid[i]], fo[fid[i]]
+        im = torch.randperm(a.shape[1], generator=g, device="cuda")[:m[i]].sort().values
+        io = torch.randperm(b.shape[1], generator=g, device="cuda")[:k[i]].sort().values
+        M[:, mo[i]:mo[i + 1]] = a[:, im]
+        O[:, oo[i]:oo[i + 1]] = b[:, io]
+    torch.cuda.synchronize()
+    del fm, fo
+    model = fr.Cloud(*[M[j] for j in range(6)], offsets=mo)
+    obs = fr.Cloud(*[O[j] for j in range(6)], offsets=oo)
+    return model, obs, m, k, (M, O)
+
+
+def run_plain(fr, ctx, model, obs, arrivals, prm):
+    """One request at a time through fr_register, in arrival order."""
+    from paper_1811_10136_amd.serve import Result
+    out = []
+    t0 = time.perf_counter()
+    for i, a in enumerate(arrivals):
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+            now = time.perf_counter() - t0
+        T, st, _ = fr.register(ctx, model.sets(i, i + 1), obs.sets(i, i + 1), prm)
+        out.append(Result(i, float(a), now, time.perf_counter() - t0, T[0], int(st[0])))
+    return out
+
+
+def run_served(fr, ctx, model, obs, m, k, arrivals, iters, eprm, budget, max_admit):
+    from paper_1811_10136_amd.serve import EngineBackend, Request, Server
+    be = EngineBackend(ctx, eprm, lambda reqs: (model.sets(reqs[0].rid, reqs[-1].rid + 1),
+                                                obs.sets(reqs[0].rid, reqs[-1].rid + 1)))
+    srv = Server(be, iters=iters, budget_bytes=budget, bytes_per_obs_point=400.0, max_admit=max_admit,
+                 max_inflight=3)
+    res = srv.run([Request(i, float(arrivals[i]), int(m[i]), int(k[i])) for i in range(len(arrivals))])
+    be.close()
+    return res, srv
+
+
+def serve_bench(fr, ctx, args):
+    from paper_1811_10136_amd.serve import poisson_arrivals, summarize
+    t = time.time()
+    model, obs, m, k, keep = make_request_stream(args.serve_requests, 5, args.workers)
+    n = len(m)
+    log(f"request stream: {n} requests, {int(m.sum())} model / {int(k.sum())} obs points, staged in "
+        f"{time.time() - t:.1f} s")
+    p0 = synth.depth_pair(0, target_points=1000)
+    prm = fr.register_params(6, "pt2pl", p0.sigma, p0.sigma_n, iters=args.iters, w=0.1, fixed=True)
+    eprm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=args.serve_slots,
+                            arena_points=args.serve_arena, w=0.1)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    # warm both paths
+    run_plain(fr, ctx, model, obs, np.zeros(8), prm)
+    run_served(fr, ctx, model, obs, m[:16], k[:16], np.zeros(16), args.iters, eprm, budget, args.serve_admit)
+    # plain-loop capacity: the first requests back to back
+    nc = min(n, args.serve_capacity_requests)
+    t0 = time.perf_counter()
+    run_plain(fr, ctx, model, obs, np.zeros(nc), prm)
+    cap = nc / (time.perf_counter() - t0)
+    log(f"plain loop capacity {cap:.1f} registrations/s ({nc} requests back to back)")
+    served, plain = [], []
+    for x in args.serve_lambdas:
+        rate = x * cap
+        arr = poisson_arrivals(n, rate, 11)
+        t0 = time.perf_counter()
+        res, srv = run_served(fr, ctx, model, obs, m, k, arr, args.iters, eprm, budget, args.serve_admit)
+        s = summarize(res)
+        s.update({"lambda_x": x, "lambda_per_s": rate, "ticks": srv.ticks, "max_resident": srv.max_resident,
+                  "wall_s": time.perf_counter() - t0})
+        served.append(s)
+        log(f"served  lambda={x}x ({rate:.0f}/s): {s['registrations_per_s']:.1f} reg/s, p50 "
+            f"{s['latency_ms']['p50']:.1f} ms, p99 {s['latency_ms']['p99']:.1f} ms, resident <= {srv.max_resident}")
+    for x in args.plain_lambdas:
+        rate = x * cap
+        arr = poisson_arrivals(n, rate, 11)
+        s = summarize(run_plain(fr, ctx, model, obs, arr, prm))
+        s.update({"lambda_x": x, "lambda_per_s": rate})
+        plain.append(s)
+        log(f"plain   lambda={x}x ({rate:.0f}/s): {s['registrations_per_s']:.1f} reg/s, p50 "
+            f"{s['latency_ms']['p50']:.1f} ms, p99 {s['latency_ms']['p99']:.1f} ms")
+    ok = [s for s in served if s["latency_ms"]["p99"] < 100.0]
+    head = max(ok, key=lambda s: s["lambda_x"]) if ok else None
+    del keep
+    return {
+        "workload": f"{n} rigid point-to-plane requests, model points log-uniform in [1k, 300k] (sorted random "
+                    f"subsamples of {SERVE_FRAMES} depth renders at 300k points), d=6, {args.iters} EM iterations "
+                    f"each, Poisson arrivals",
+        "requests": n, "model_points": int(m.sum()), "obs_points": int(k.sum()),
+        "plain_capacity_per_s": cap, "served": served, "plain": plain,
+        "engine": {"max_slots": args.serve_slots, "arena_points": args.serve_arena,
+                   "lattice_budget_gib": args.serve_budget_gib, "max_admit": args.serve_admit},
+        "headline": None if head is None else {
+            "lambda_x": head["lambda_x"], "registrations_per_s": head["registrations_per_s"],
+            "p50_ms": head["latency_ms"]["p50"], "p99_ms": head["latency_ms"]["p99"],
+            "rule": "largest swept arrival rate whose served p99 latency is under 100 ms"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +255,15 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=3, help="pairs the CPU oracle baseline runs")
     ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=1024)
+    ap.add_argument("--serve-arena", type=int, default=64 << 20)
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--serve-admit", type=int, default=32)
+    ap.add_argument("--serve-capacity-requests", type=int, default=256)
+    ap.add_argument("--serve-lambdas", type=float, nargs="*", default=[1.0, 2.0, 4.0, 8.0])
+    ap.add_argument("--plain-lambdas", type=float, nargs="*", default=[1.0])
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -195,6 +349,8 @@ def main():
         "registrations_per_s": len(pairs) * args.steps / total_s,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "latency of one batched step (all pairs of the batch complete together)"},
+        "batch": {"registrations_per_s": len(pairs) * args.steps / total_s,
+                  "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99))},
         "build_ms_mean": float(np.mean(build_ms)),
         "roofline": {
             "kernel": "k_estep<6,7,rigid>",
@@ -208,6 +364,13 @@ def main():
             "mean_launch_ms": est_avg_s * 1e3,
         },
     }
+    if not args.no_serve:
+        out["serving"] = serve_bench(fr, ctx, args)
+        h = out["serving"]["headline"]
+        if h is not None:
+            out["registrations_per_s"] = h["registrations_per_s"]
+            out["latency_ms"] = {"p50": h["p50_ms"], "p99": h["p99_ms"],
+                                 "note": f"served request stream at {h['lambda_x']}x the plain loop's capacity"}
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on {args.cpu_pairs} pairs ...")
         out["cpu_baseline"] = cpu_baseline(pairs[:args.cpu_pairs], args.iters)

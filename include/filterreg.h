@@ -315,6 +315,71 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
                                 const fr_register_params *params, double *node_T_inout_h, fr_report *report_h,
                                 void *stream);
 
+/*
+ * Serving engine: continuous batching of rigid registrations (the EM loop of
+ * Sec. 3.1 with the rigid twist M-step of Sec. 5, one request = one
+ * observation/model pair).  An engine keeps up to max_slots registrations
+ * resident at once -- each slot holds its model points in the engine's point
+ * arena, the lattice of its observation (built once, Sec. 3.2), its binary64
+ * pose and binary32 transform -- and fr_engine_step runs one EM iteration of
+ * any subset of the occupied slots with one E-step, one reduction and one
+ * solve launch.  Requests of different sizes therefore share every launch,
+ * and a slot joins or leaves between two steps.
+ *
+ * Streams: every step, read and release is enqueued on the engine's `stream`
+ * (given at creation).  Lattice builds run on a stream of the engine's own,
+ * so a build overlaps the steps already queued; a step that includes a newly
+ * admitted slot waits for that slot's build on the device, not on the host.
+ * Results are bitwise those of fr_register on the same pair alone (sorted
+ * splat; same iteration count).  One host thread at a time per engine.
+ */
+typedef struct fr_engine fr_engine;
+
+typedef struct {
+    fr_lattice_params lattice;  /* shared by every request */
+    int32_t residual;           /* FR_PT2PT or FR_PT2PL */
+    int32_t max_slots;          /* 1 .. 4096 registrations resident at once */
+    int64_t arena_points;       /* model points resident at once (>= 1) */
+    double w;                   /* outlier ratio of Eq. 4; c per request as in fr_register_params */
+    double c_override;          /* >= 0: this c for every request; < 0: derive from w */
+} fr_engine_params;
+
+/* Create an engine; allocates the point arena (52 bytes per point for d = 6
+ * point-to-plane) and the per-slot state from ctx's budget. */
+fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *stream, fr_engine **out);
+/* Wait for all queued work and free everything the engine holds. */
+fr_status fr_engine_destroy(fr_engine *eng);
+
+/*
+ * Admit n requests: request j is set j of model_ref (device, normals when
+ * feat == 6) and set j of obs; it occupies slot slots_h[j] (must be free) and
+ * arena points [arena_begin_h[j], arena_begin_h[j] + M_j) (inside the arena,
+ * disjoint from every occupied slot's range and from each other), and starts
+ * at pose T0_h[16 j .. 16 j + 15] (host, row-major 4x4).  The n lattices are
+ * built in one build on the engine's build stream (the host waits for that
+ * build only); the model points are copied into the arena, on the device,
+ * once the steps queued so far have finished.  obs may be reused when the
+ * call returns; model_ref must stay valid until the engine stream has
+ * completed a later fr_engine_step or fr_engine_read (both wait for every
+ * earlier admission on the device).
+ */
+fr_status fr_engine_admit(fr_engine *eng, int32_t n, const int32_t *slots_h, const fr_cloud *model_ref,
+                          const fr_cloud *obs, const int64_t *arena_begin_h, const double *T0_h);
+
+/* One EM iteration (E-step, reduction, binary64 solve and pose update) of the
+ * n occupied slots listed in slots_h (host), enqueued on the engine stream. */
+fr_status fr_engine_step(fr_engine *eng, int32_t n, const int32_t *slots_h);
+
+/* Enqueue a copy of every slot's pose (max_slots x 16 float64, row-major) and
+ * status (max_slots int32: FR_OK or FR_EDEGENERATE of its last solve) into
+ * host memory; pinned host memory makes it asynchronous.  Returns FR_ERANGE
+ * (and clears it) if an E-step saw a lattice coordinate out of range. */
+fr_status fr_engine_read(fr_engine *eng, double *poses_h, int32_t *status_h);
+
+/* Free n slots.  Their arena ranges may be admitted again at once; a lattice
+ * is freed (ordered after the queued steps) when its last slot is released. */
+fr_status fr_engine_release(fr_engine *eng, int32_t n, const int32_t *slots_h);
+
 /* Return (and clear) a device fault latched in `lat` by earlier async calls; synchronises. */
 fr_status fr_sync_status(const fr_lattice *lat);
 

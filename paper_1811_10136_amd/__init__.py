@@ -88,6 +88,11 @@ class fr_node_graph(ctypes.Structure):
                 ("n_edges", ctypes.c_int32), ("edges", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.c_double)]
 
 
+class fr_engine_params(ctypes.Structure):
+    _fields_ = [("lattice", fr_lattice_params), ("residual", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("arena_points", ctypes.c_int64), ("w", ctypes.c_double), ("c_override", ctypes.c_double)]
+
+
 class fr_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("n_degenerate", ctypes.c_int32), ("build_ms", ctypes.c_double),
                 ("em_ms", ctypes.c_double), ("estep_ms", ctypes.c_double), ("mstep_ms", ctypes.c_double),
@@ -134,11 +139,19 @@ _sig("fr_register_nodegraph", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER
 _sig("fr_register_articulated", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_kinematic_tree),
                                       ctypes.POINTER(fr_register_params), _P, ctypes.POINTER(fr_report), _P])
+_sig("fr_engine_create", _st, [_P, ctypes.POINTER(fr_engine_params), _P, ctypes.POINTER(_P)])
+_sig("fr_engine_destroy", _st, [_P])
+_sig("fr_engine_admit", _st, [_P, _i32, _P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), _P, _P])
+_sig("fr_engine_step", _st, [_P, _i32, _P])
+_sig("fr_engine_read", _st, [_P, _P, _P])
+_sig("fr_engine_release", _st, [_P, _i32, _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
                  "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status",
-                 "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph"]
+                 "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph",
+                 "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
+                 "fr_engine_release"]
 
 
 def _check(status: int):
@@ -197,6 +210,13 @@ class Cloud:
             tn = torch.from_numpy(np.ascontiguousarray(nrm.T)).to(device)
             ncols = [tn[0].contiguous(), tn[1].contiguous(), tn[2].contiguous()]
         return cls(*cols, *ncols, offsets=off)
+
+    def sets(self, a: int, b: int) -> "Cloud":
+        """View of sets [a, b) as a cloud of its own (no copy)."""
+        o = self.offsets
+        lo, hi = int(o[a]), int(o[b])
+        cols = [None if t is None else t[lo:hi] for t in (self.x, self.y, self.z, self.nx, self.ny, self.nz)]
+        return Cloud(*cols, offsets=o[a:b + 1] - lo)
 
     def c(self):
         return ctypes.byref(self._c)
@@ -471,3 +491,85 @@ def fr_register_nodegraph(ctx, model: Cloud, obs: Cloud, graph: NodeGraph, param
     if st not in (FR_OK, FR_EDEGENERATE):
         _check(st)
     return st, rep
+
+
+# --- serving engine ------------------------------------------------------------
+def _i32_array(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.int32).reshape(-1))
+
+
+def fr_engine_create(ctx, params: fr_engine_params, stream=None):
+    h = _P()
+    _check(_lib.fr_engine_create(ctx, ctypes.byref(params), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def fr_engine_destroy(eng):
+    _check(_lib.fr_engine_destroy(eng))
+
+
+def fr_engine_admit(eng, slots, model: Cloud, obs: Cloud, arena_begin, T0):
+    sl = _i32_array(slots)
+    ab = np.ascontiguousarray(np.asarray(arena_begin, dtype=np.int64).reshape(-1))
+    T = np.ascontiguousarray(np.asarray(T0, dtype=np.float64).reshape(-1))
+    assert len(ab) == len(sl) and len(T) == 16 * len(sl)
+    _check(_lib.fr_engine_admit(eng, len(sl), sl.ctypes.data, model.c(), obs.c(), ab.ctypes.data, T.ctypes.data))
+
+
+def fr_engine_step(eng, slots):
+    sl = _i32_array(slots)
+    _check(_lib.fr_engine_step(eng, len(sl), sl.ctypes.data))
+
+
+def fr_engine_read(eng, poses_h, status_h):
+    """Enqueue the copy of all slot poses / statuses into host buffers (pinned torch tensors or numpy arrays)."""
+    pp = poses_h.data_ptr() if hasattr(poses_h, "data_ptr") else poses_h.ctypes.data
+    sp = status_h.data_ptr() if hasattr(status_h, "data_ptr") else status_h.ctypes.data
+    _check(_lib.fr_engine_read(eng, pp, sp))
+
+
+def fr_engine_release(eng, slots):
+    sl = _i32_array(slots)
+    _check(_lib.fr_engine_release(eng, len(sl), sl.ctypes.data))
+
+
+def engine_params(feat: int, residual: str, sigma, sigma_n=0.5, max_slots=256, arena_points=1 << 24, w=0.1,
+                  c=None, splat: int = FR_SPLAT_SORTED) -> fr_engine_params:
+    values = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
+    return fr_engine_params(lattice_params(feat, values, sigma, sigma_n, splat),
+                            FR_PT2PL if residual == "pt2pl" else FR_PT2PT, int(max_slots), int(arena_points),
+                            float(w), -1.0 if c is None else float(c))
+
+
+class Engine:
+    """Owner of an fr_engine handle on one stream (see fr_engine_create)."""
+
+    def __init__(self, ctx: "Context", params: fr_engine_params, stream=None):
+        torch = _torch()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.params = params
+        self.max_slots = int(params.max_slots)
+        self.h = fr_engine_create(ctx.h, params, self.stream)
+
+    def admit(self, slots, model: Cloud, obs: Cloud, arena_begin, T0):
+        fr_engine_admit(self.h, slots, model, obs, arena_begin, T0)
+
+    def step(self, slots):
+        fr_engine_step(self.h, slots)
+
+    def read(self, poses_h, status_h):
+        fr_engine_read(self.h, poses_h, status_h)
+
+    def release(self, slots):
+        fr_engine_release(self.h, slots)
+
+    def close(self):
+        if self.h:
+            fr_engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -22,34 +22,129 @@ void set_error(const char *fmt, ...)
 
 void clear_error() { g_err[0] = '\0'; }
 
+static thread_local hipStream_t tls_stream = nullptr;
+
+hipStream_t current_stream() { return tls_stream; }
+StreamScope::StreamScope(hipStream_t st) : prev(tls_stream) { tls_stream = st; }
+StreamScope::~StreamScope() { tls_stream = prev; }
+
+// Sizes are rounded so that freed blocks fit later requests of similar size:
+// powers of two up to 1 MiB, multiples of 2 MiB above.
+static size_t round_alloc(size_t b)
+{
+    if (b == 0) b = 16;
+    if (b <= ((size_t)1 << 20)) {
+        size_t r = 512;
+        while (r < b) r <<= 1;
+        return r;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (b + g - 1) / g * g;
+}
+
+static void recycle_event(fr_ctx *ctx, hipEvent_t ev)
+{
+    if (ev) ctx->spare_events.push_back(ev);
+}
+
+// Free cached blocks back to HIP: those whose last use has finished, or with
+// wait == true all of them (waiting for their streams first).
+static void trim_cache(fr_ctx *ctx, bool wait)
+{
+    std::vector<fr_ctx::Block> keep;
+    for (const fr_ctx::Block &b : ctx->cache) {
+        bool idle = b.done == nullptr || hipEventQuery(b.done) == hipSuccess;
+        if (!idle && wait) idle = hipEventSynchronize(b.done) == hipSuccess;
+        if (!idle) {
+            keep.push_back(b);
+            continue;
+        }
+        (void)hipFree(b.p);
+        ctx->cached -= b.bytes;
+        recycle_event(ctx, b.done);
+    }
+    (void)hipGetLastError();
+    ctx->cache.swap(keep);
+}
+
 fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes)
 {
     *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    if (ctx->budget != 0 && ctx->in_use + bytes > ctx->budget) {
-        set_error("HBM budget exceeded: %zu in use + %zu requested > %zu", ctx->in_use, bytes, ctx->budget);
+    const size_t rb = round_alloc(bytes);
+    const hipStream_t st = current_stream();
+    // best fit among cached blocks of this size class that this stream may use now
+    int best = -1;
+    const size_t slack = rb <= ((size_t)1 << 20) ? 0 : rb / 4;
+    for (int i = 0; i < (int)ctx->cache.size(); ++i) {
+        const fr_ctx::Block &b = ctx->cache[i];
+        if (b.bytes < rb || b.bytes > rb + slack) continue;
+        if (best >= 0 && b.bytes >= ctx->cache[best].bytes) continue;
+        if (b.done != nullptr && b.stream != st && hipEventQuery(b.done) != hipSuccess) continue;
+        best = i;
+    }
+    (void)hipGetLastError();
+    if (best >= 0) {
+        const fr_ctx::Block b = ctx->cache[best];
+        ctx->cache.erase(ctx->cache.begin() + best);
+        ctx->cached -= b.bytes;
+        ctx->in_use += b.bytes;
+        recycle_event(ctx, b.done);
+        *p = b.p;
+        return FR_OK;
+    }
+    if (ctx->budget != 0 && ctx->in_use + ctx->cached + rb > ctx->budget) trim_cache(ctx, false);
+    if (ctx->budget != 0 && ctx->in_use + ctx->cached + rb > ctx->budget) trim_cache(ctx, true);
+    if (ctx->budget != 0 && ctx->in_use + rb > ctx->budget) {
+        set_error("HBM budget exceeded: %zu in use + %zu requested > %zu", ctx->in_use, rb, ctx->budget);
         return FR_EBUDGET;
     }
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = hipMalloc(p, rb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim_cache(ctx, true);
+        e = hipMalloc(p, rb);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
-        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        set_error("hipMalloc(%zu) failed: %s", rb, hipGetErrorString(e));
         return FR_ENOMEM;
     }
-    ctx->in_use += bytes;
+    ctx->in_use += rb;
     return FR_OK;
 }
 
-void dev_free(fr_ctx *ctx, void *p, size_t bytes)
+void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle)
 {
     if (!p) return;
-    // Kernels queued on any stream may still read the buffer (error paths
-    // return early); wait for the device before releasing it.
+    const size_t rb = round_alloc(bytes);
+    hipEvent_t ev = nullptr;
+    if (!idle) {
+        if (!ctx->spare_events.empty()) {
+            ev = ctx->spare_events.back();
+            ctx->spare_events.pop_back();
+        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+        }
+        if (ev == nullptr || hipEventRecord(ev, st) != hipSuccess) {
+            // no event: fall back to waiting for the device
+            (void)hipGetLastError();
+            (void)hipDeviceSynchronize();
+            recycle_event(ctx, ev);
+            ev = nullptr;
+        }
+    }
+    ctx->cache.push_back(fr_ctx::Block{p, rb, st, ev});
+    ctx->in_use -= std::min(ctx->in_use, rb);
+    ctx->cached += rb;
+}
+
+void dev_release_cache(fr_ctx *ctx)
+{
     (void)hipDeviceSynchronize();
-    (void)hipFree(p);
-    if (bytes == 0) bytes = 16;
-    ctx->in_use -= std::min(ctx->in_use, bytes);
+    trim_cache(ctx, true);
+    for (hipEvent_t ev : ctx->spare_events) (void)hipEventDestroy(ev);
+    ctx->spare_events.clear();
 }
 
 fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what)
@@ -150,10 +245,21 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
     return FR_OK;
 }
 
-static bool ctx_ok(const fr_ctx *c) { return c != nullptr && c->magic == kCtxMagic; }
+bool ctx_ok(const fr_ctx *c) { return c != nullptr && c->magic == kCtxMagic; }
 static bool lat_ok(const fr_lattice *l) { return l != nullptr && l->magic == kLatMagic; }
 
-static fr_status check_lattice_params(const fr_lattice_params *p)
+// Outlier constant c of Eq. 7 in un-normalised kernel units: the uniform term
+// w/(1-w) (1/M) over the Gaussian normaliser (2 pi)^(-3/2) / (sigma_x sigma_y
+// sigma_z) of the N observation components.
+double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns)
+{
+    if (c_override >= 0.0) return c_override;
+    if (!(Ms > 0) || !(w > 0.0)) return 0.0;
+    const double s3 = lp.sigma[0] * lp.sigma[1] * lp.sigma[2];
+    return w / (1.0 - w) * (Ns / Ms) * std::pow(2.0 * M_PI, 1.5) * s3;
+}
+
+fr_status check_lattice_params(const fr_lattice_params *p)
 {
     if (p == nullptr) {
         set_error("lattice params are NULL");
@@ -187,13 +293,13 @@ static fr_status check_lattice_params(const fr_lattice_params *p)
     return FR_OK;
 }
 
-static void free_lattice(fr_lattice *lat)
+void free_lattice(fr_lattice *lat, hipStream_t st, bool idle)
 {
-    if (lat->tkey) dev_free(lat->ctx, lat->tkey, lat->tkey_bytes);
-    if (lat->tval) dev_free(lat->ctx, lat->tval, lat->tval_bytes);
-    if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable));
-    if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes);
-    if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t));
+    if (lat->tkey) dev_free(lat->ctx, lat->tkey, lat->tkey_bytes, st, idle);
+    if (lat->tval) dev_free(lat->ctx, lat->tval, lat->tval_bytes, st, idle);
+    if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable), st, idle);
+    if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes, st, idle);
+    if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t), st, idle);
     lat->tkey = nullptr;
     lat->tval = nullptr;
     lat->sets_d = nullptr;
@@ -204,7 +310,7 @@ static void free_lattice(fr_lattice *lat)
 // Lattice scale per feature dimension: sqrt(2/3) (d+1) / (sigma_i sqrt((i+1)(i+2))),
 // rounded once to binary32 (the feature normalisation of Sec. 4.1 folded into
 // the permutohedral lattice scale).
-static void scale_factors(const fr_lattice_params *p, float *k)
+void scale_factors(const fr_lattice_params *p, float *k)
 {
     const int d = p->feat;
     for (int i = 0; i < 8; ++i) k[i] = 0.0f;
@@ -214,7 +320,7 @@ static void scale_factors(const fr_lattice_params *p, float *k)
     }
 }
 
-static fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
+fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
                                     hipStream_t st, fr_lattice **out)
 {
     fr_lattice *lat = new (std::nothrow) fr_lattice();
@@ -233,7 +339,7 @@ static fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_l
     fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
     if (s == FR_OK) s = build_lattice(ctx, obs, params, st, lat);
     if (s != FR_OK) {
-        free_lattice(lat);
+        free_lattice(lat, st, false);
         lat->magic = kDeadMagic;
         delete lat;
         return s;
@@ -325,6 +431,8 @@ fr_status fr_ctx_destroy(fr_ctx *ctx)
         set_error("fr_ctx_destroy: invalid or destroyed context");
         return FR_EINVAL;
     }
+    (void)hipSetDevice(ctx->device);
+    dev_release_cache(ctx);
     ctx->magic = kDeadMagic;
     delete ctx;
     return FR_OK;
@@ -353,6 +461,7 @@ fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_pa
     FR_TRY(check_lattice_params(params));
     FR_TRY(check_cloud(obs, params->feat == 6 || params->values == 7, "fr_lattice_build"));
     FR_HIP(hipSetDevice(ctx->device));
+    StreamScope scope(static_cast<hipStream_t>(stream));
     return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out);
 }
 
@@ -364,8 +473,9 @@ fr_status fr_lattice_destroy(fr_lattice *lat)
         return FR_EINVAL;
     }
     (void)hipSetDevice(lat->ctx->device);
+    // kernels queued on any stream may still read the lattice
     (void)hipDeviceSynchronize();
-    free_lattice(lat);
+    free_lattice(lat, nullptr, true);
     lat->magic = kDeadMagic;
     delete lat;
     return FR_OK;
@@ -477,6 +587,7 @@ fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xf
     }
     if (M == 0) return FR_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     FR_HIP(hipSetDevice(lat->ctx->device));
     Plan plan;
     FR_TRY(make_plan(lat->ctx, model_ref, xf, 256, nullptr, st, plan));
@@ -550,6 +661,7 @@ fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const f
     fr_ctx tmp_ctx;
     tmp_ctx.device = dev;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     std::vector<double> cset(model_ref->n_sets, params->c);
     if (params->c_per_set)
         for (int32_t s = 0; s < model_ref->n_sets; ++s) cset[s] = params->c_per_set[s];
@@ -607,6 +719,7 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     }
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     const int32_t S = model_ref->n_sets;
     const int64_t M = cloud_points(model_ref);
     fr_report rep{};
@@ -626,14 +739,10 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
 
     // per-set outlier constant (Eq. 7 in un-normalised kernel units)
     std::vector<double> cset(S, 0.0);
-    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
-    for (int32_t s = 0; s < S; ++s) {
-        const double Ms = (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]);
-        const double Ns = (double)(obs->offsets[s + 1] - obs->offsets[s]);
-        if (params->c_override >= 0.0) cset[s] = params->c_override;
-        else if (Ms > 0 && params->w > 0.0)
-            cset[s] = params->w / (1.0 - params->w) * (Ns / Ms) * std::pow(2.0 * M_PI, 1.5) * s3;
-    }
+    for (int32_t s = 0; s < S; ++s)
+        cset[s] = outlier_constant(params->lattice, params->w, params->c_override,
+                                   (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]),
+                                   (double)(obs->offsets[s + 1] - obs->offsets[s]));
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
 
     Plan pe, pr;
@@ -747,6 +856,7 @@ fr_status fr_articulated_step(fr_ctx *ctx, const fr_kinematic_tree *tree, const 
     }
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     ArtTreeHost t;
     FR_TRY(upload_tree(ctx, tree, st, t));
     FR_TRY(launch_articulated_step(t, jtj ? 1 : 0, jtj, jtr, theta, mats, nullptr, status, st));
@@ -792,6 +902,7 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
         }
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     ArtTreeHost t;
     FR_TRY(upload_tree(ctx, tree, st, t));
     const int32_t n = t.n_dof;
@@ -810,11 +921,8 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
     auto t1 = clk::now();
     rep.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 
-    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
-    double c = 0.0;
-    if (params->c_override >= 0.0) c = params->c_override;
-    else if (M > 0 && params->w > 0.0)
-        c = params->w / (1.0 - params->w) * ((double)cloud_points(obs) / (double)M) * std::pow(2.0 * M_PI, 1.5) * s3;
+    const double c = outlier_constant(params->lattice, params->w, params->c_override, (double)M,
+                                      (double)cloud_points(obs));
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
 
     Plan pe, pr;
@@ -920,6 +1028,7 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
         }
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
     fr_report rep{};
     auto t0 = clk::now();
     fr_lattice *lat = nullptr;
@@ -940,11 +1049,8 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
         for (int j = 0; j < 12; ++j) T12[(size_t)12 * k + j] = node_T_inout_h[(size_t)16 * k + j];
     FR_HIP(hipMemcpyAsync(d.T, T12.data(), T12.size() * sizeof(double), hipMemcpyHostToDevice, st));
 
-    const double s3 = params->lattice.sigma[0] * params->lattice.sigma[1] * params->lattice.sigma[2];
-    double c = 0.0;
-    if (params->c_override >= 0.0) c = params->c_override;
-    else if (M > 0 && params->w > 0.0)
-        c = params->w / (1.0 - params->w) * ((double)cloud_points(obs) / (double)M) * std::pow(2.0 * M_PI, 1.5) * s3;
+    const double c = outlier_constant(params->lattice, params->w, params->c_override, (double)M,
+                                      (double)cloud_points(obs));
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
     const bool normals = params->lattice.feat == 6;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);

@@ -16,15 +16,14 @@ namespace fr {
 struct EstepArgs {
     const float *x, *y, *z, *nx, *ny, *nz;
     const float *mats;            // per segment [R | t], or NULL for no transform
-    const uint64_t *tkey;
-    const float *tval;
     const SetTable *sets;
     TileMap tm;
     float k[8];
     float *m0, *m1, *ns;          // outputs (m1/ns channel-major, stride M)
     int64_t M;
     uint32_t *touched;            // optional: per-slot "was found" flags
-    int32_t *err;
+    int32_t *err;                 // range-error flag: one word, or one per segment
+    int32_t err_stride;           // 0: one word; 1: err[segment]
 };
 
 template <typename T>
@@ -70,7 +69,7 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
 
     uint64_t keys[D][KW];
     float b[D];
-    if (!embed<d>(p, kk, keys, b)) atomicOr(a.err, 1);
+    if (!embed<d>(p, kk, keys, b)) atomicOr(a.err + a.err_stride * s, 1);
 
     float acc[V];
 #pragma unroll
@@ -144,8 +143,9 @@ static void launch_dv(const EstepArgs &a, bool xf, bool touch, int grid, hipStre
     }
 }
 
-fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
-                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
+fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+                            const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
+                            float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
 {
     if (plan.grid == 0) return FR_OK;
     EstepArgs a{};
@@ -156,29 +156,35 @@ fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan 
     a.ny = model->ny;
     a.nz = model->nz;
     a.mats = mats;
-    a.tkey = lat->tkey;
-    a.tval = lat->tval;
-    a.sets = lat->sets_d;
+    a.sets = sets;
     a.tm = plan.tm;
-    for (int j = 0; j < 8; ++j) a.k[j] = lat->k[j];
+    for (int j = 0; j < 8; ++j) a.k[j] = k[j];
     a.m0 = m0;
     a.m1 = m1;
     a.ns = nsum;
-    a.M = cloud_points(model);
+    a.M = M;
     a.touched = touched;
-    a.err = lat->err_d;
+    a.err = err;
+    a.err_stride = err_stride;
     const bool xf = xf_kind != FR_XF_NONE;
     const bool touch = touched != nullptr;
-    if (lat->d == 3 && lat->V == 4) launch_dv<3, 4>(a, xf, touch, plan.grid, st);
-    else if (lat->d == 3 && lat->V == 7) launch_dv<3, 7>(a, xf, touch, plan.grid, st);
-    else if (lat->d == 6 && lat->V == 4) launch_dv<6, 4>(a, xf, touch, plan.grid, st);
-    else if (lat->d == 6 && lat->V == 7) launch_dv<6, 7>(a, xf, touch, plan.grid, st);
+    if (d == 3 && V == 4) launch_dv<3, 4>(a, xf, touch, plan.grid, st);
+    else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, plan.grid, st);
+    else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, plan.grid, st);
+    else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, plan.grid, st);
     else {
-        set_error("fr_estep: unsupported lattice d=%d V=%d", lat->d, lat->V);
+        set_error("fr_estep: unsupported lattice d=%d V=%d", d, V);
         return FR_EINVAL;
     }
     FR_HIP(hipGetLastError());
     return FR_OK;
+}
+
+fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
+{
+    return launch_estep_sets(lat->d, lat->V, lat->k, lat->sets_d, lat->err_d, 0, model, cloud_points(model), plan,
+                             xf_kind, mats, m0, m1, nsum, touched, st);
 }
 
 }  // namespace fr

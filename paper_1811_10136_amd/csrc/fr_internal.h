@@ -50,9 +50,22 @@ struct Status {
 struct fr_ctx {
     uint32_t magic = fr::kCtxMagic;
     int32_t device = 0;
-    size_t budget = 0;       // 0 = unlimited
-    size_t in_use = 0;
+    size_t budget = 0;       // 0 = unlimited; covers live and cached blocks
+    size_t in_use = 0;       // bytes of live allocations
+    size_t cached = 0;       // bytes of freed blocks kept for reuse
     int cu_count = 256;
+    // A freed block is reused at once by allocations on the stream that last
+    // used it (stream order makes that safe), elsewhere once `done` -- an event
+    // recorded on that stream at the free -- has completed.  done == nullptr
+    // marks a block freed with the device idle.
+    struct Block {
+        void *p;
+        size_t bytes;
+        hipStream_t stream;
+        hipEvent_t done;
+    };
+    std::vector<Block> cache;
+    std::vector<hipEvent_t> spare_events;
 };
 
 struct fr_lattice {
@@ -83,14 +96,35 @@ struct fr_lattice {
 namespace fr {
 
 // --- budgeted allocation ---------------------------------------------------
+// Stream of the API call running on this thread (set by StreamScope at each
+// entry point); allocations remember it so that their release is stream-ordered.
+hipStream_t current_stream();
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t st);
+    ~StreamScope();
+};
+
+// Budgeted allocation through the context's block cache.  dev_free keeps the
+// block for reuse: ordered after the work queued so far on `st`, or, with
+// idle == true, after work the caller has already waited for.
 fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes);
-void dev_free(fr_ctx *ctx, void *p, size_t bytes);
+void free_lattice(fr_lattice *lat, hipStream_t st, bool idle);
+bool ctx_ok(const fr_ctx *c);
+fr_status check_lattice_params(const fr_lattice_params *p);
+fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
+                             fr_lattice **out);
+void scale_factors(const fr_lattice_params *p, float *k);
+double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns);
+void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle = false);
+void dev_release_cache(fr_ctx *ctx);
 
 // RAII temporary device buffer charged to the context.
 struct DevBuf {
     fr_ctx *ctx = nullptr;
     void *p = nullptr;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -100,13 +134,14 @@ struct DevBuf {
         reset();
         ctx = c;
         bytes = b < 16 ? 16 : b;
+        stream = current_stream();
         fr_status s = dev_alloc(ctx, &p, bytes);
         if (s != FR_OK) { p = nullptr; bytes = 0; }
         return s;
     }
     void reset()
     {
-        if (p) dev_free(ctx, p, bytes);
+        if (p) dev_free(ctx, p, bytes, stream);
         p = nullptr;
         bytes = 0;
     }
@@ -138,6 +173,9 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
                         fr_lattice *lat);
 
 // estep.hip
+fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+                            const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
+                            float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st);
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
                        float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t stream);
 

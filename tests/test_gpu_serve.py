@@ -1,0 +1,166 @@
+"""The serving engine on the GPU: continuous batching gives every request the result it gets alone."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _helpers import upload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SIZES = [3000, 41000, 1200, 17000, 64000, 5000, 9000, 26000]
+ITERS = 6
+
+
+@pytest.fixture(scope="module")
+def fr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1811_10136_amd as fr
+    return fr
+
+
+@pytest.fixture(scope="module")
+def ctx(fr):
+    c = fr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    return [synth.depth_pair(100 + i, target_points=m) for i, m in enumerate(SIZES)]
+
+
+def _alone(fr, ctx, p, iters=ITERS):
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=iters, w=p.w, fixed=True)
+    T, st, _ = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm, T0=np.eye(4)[None])
+    return T[0], int(st[0])
+
+
+def _engine(fr, ctx, p0, slots=4, arena=150_000):
+    prm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=slots, arena_points=arena, w=p0.w)
+    return fr.Engine(ctx, prm)
+
+
+def _read(eng, S):
+    poses = torch.empty((S, 16), dtype=torch.float64, pin_memory=True)
+    status = torch.empty(S, dtype=torch.int32, pin_memory=True)
+    eng.read(poses, status)
+    torch.cuda.synchronize()
+    return poses.numpy().reshape(S, 4, 4).copy(), status.numpy().copy()
+
+
+def test_engine_mix_is_bitwise_the_pair_alone(fr, ctx, pairs):
+    """Requests join and leave at different ticks, reuse slots and arena ranges, and share every
+    launch with different neighbours; each ends bitwise where fr_register leaves it alone."""
+    alone = [_alone(fr, ctx, p) for p in pairs]
+    eng = _engine(fr, ctx, pairs[0])
+    S = eng.max_slots
+    # schedule: (tick, requests admitted at that tick into (slot, arena begin))
+    admissions = {0: [(0, 0, 0), (1, 1, 10_000)], 2: [(2, 2, 65_000), (3, 3, 70_000)],
+                  ITERS: [(4, 0, 0)], ITERS + 1: [(5, 1, 90_000)], ITERS + 3: [(6, 2, 100_000), (7, 3, 110_000)]}
+    resident, results = {}, {}
+    keep = []      # the model clouds stay alive until a later step has consumed them
+    tick = 0
+    while len(results) < len(pairs):
+        for rid, slot, begin in admissions.get(tick, []):
+            p = pairs[rid]
+            keep.append(upload([p.model], [p.model_n]))
+            eng.admit([slot], keep[-1], upload([p.obs], [p.obs_n]), [begin], np.eye(4)[None])
+            resident[slot] = [rid, 0]
+        if resident:
+            eng.step(sorted(resident))
+            fin = []
+            for slot in list(resident):
+                resident[slot][1] += 1
+                if resident[slot][1] == ITERS:
+                    fin.append(slot)
+            if fin:
+                poses, status = _read(eng, S)
+                for slot in fin:
+                    results[resident[slot][0]] = (poses[slot], int(status[slot]))
+                    del resident[slot]
+                eng.release(fin)
+        tick += 1
+        assert tick < 100
+    eng.close()
+    for rid in range(len(pairs)):
+        T_mix, st_mix = results[rid]
+        T_alone, st_alone = alone[rid]
+        assert st_mix == st_alone == 0, rid
+        np.testing.assert_array_equal(T_mix, T_alone, err_msg=f"request {rid}")
+
+
+def test_engine_result_matches_the_oracle(fr, ctx, pairs):
+    p = pairs[5]
+    eng = _engine(fr, ctx, p)
+    model = upload([p.model], [p.model_n])
+    eng.admit([2], model, upload([p.obs], [p.obs_n]), [500], np.eye(4)[None])
+    for _ in range(ITERS):
+        eng.step([2])
+    poses, status = _read(eng, eng.max_slots)
+    eng.close()
+    ref = oracle.register_rigid(p.model, p.model_n, p.obs, p.obs_n, feat=6, residual="pt2pl", sigma=p.sigma,
+                                sigma_n=p.sigma_n, w=p.w, iters=ITERS, T0=np.eye(4))
+    assert status[2] == 0
+    assert np.abs(poses[2] - ref).max() < 1e-4
+
+
+def test_engine_rejects_bad_slot_and_arena_use(fr, ctx, pairs):
+    p = pairs[0]
+    eng = _engine(fr, ctx, p, slots=2, arena=10_000)
+    m, o = upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n])
+    eng.admit([0], m, o, [0], np.eye(4)[None])
+    with pytest.raises(fr.FRError) as e:
+        eng.admit([0], m, o, [5000], np.eye(4)[None])          # slot occupied
+    assert e.value.status == fr.FR_EINVAL
+    with pytest.raises(fr.FRError):
+        eng.admit([1], m, o, [len(p.model) - 1], np.eye(4)[None])   # overlaps slot 0's range
+    with pytest.raises(fr.FRError):
+        eng.admit([1], m, o, [10_000 - len(p.model) + 1], np.eye(4)[None])   # past the arena
+    with pytest.raises(fr.FRError):
+        eng.step([1])                                             # not occupied
+    with pytest.raises(fr.FRError):
+        eng.step([0, 0])                                          # repeated
+    eng.step([0])
+    eng.release([0])
+    with pytest.raises(fr.FRError):
+        eng.release([0])
+    eng.admit([1], m, o, [len(p.model) - 1], np.eye(4)[None])    # range free again
+    eng.step([1])
+    _, status = _read(eng, 2)
+    assert status[1] == 0
+    eng.close()
+
+
+def test_server_on_the_gpu_matches_alone_runs(fr, ctx, pairs):
+    """A small Poisson stream through the server: every result equals the pair alone, bitwise."""
+    from paper_1811_10136_amd.serve import EngineBackend, Request, Server, poisson_arrivals, summarize
+    reqs_p = [pairs[i % len(pairs)] for i in range(16)]
+    model = fr.Cloud.from_numpy([p.model for p in reqs_p], [p.model_n for p in reqs_p])
+    obs = fr.Cloud.from_numpy([p.obs for p in reqs_p], [p.obs_n for p in reqs_p])
+
+    def clouds(reqs):
+        a, b = reqs[0].rid, reqs[-1].rid + 1
+        assert [r.rid for r in reqs] == list(range(a, b))
+        return model.sets(a, b), obs.sets(a, b)
+
+    prm = fr.engine_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, max_slots=5, arena_points=160_000,
+                           w=pairs[0].w)
+    be = EngineBackend(ctx, prm, clouds)
+    t = poisson_arrivals(len(reqs_p), 400.0, 7)
+    reqs = [Request(i, float(t[i]), len(p.model), len(p.obs)) for i, p in enumerate(reqs_p)]
+    res = Server(be, iters=ITERS, budget_bytes=1 << 31, max_admit=3).run(reqs)
+    be.close()
+    alone = {}
+    for r in res:
+        k = r.rid % len(pairs)
+        if k not in alone:
+            alone[k] = _alone(fr, ctx, pairs[k])
+        assert r.status == 0
+        np.testing.assert_array_equal(r.pose, alone[k][0], err_msg=f"request {r.rid}")
+        assert r.completed > r.admitted >= r.arrival
+    s = summarize(res)
+    print(f"[serve] {s}", flush=True)
