@@ -208,7 +208,8 @@ typedef struct {
                               w/(1-w) N/M (2 pi)^(3/2) sigma_x sigma_y sigma_z */
     double c_override;     /* >= 0: use this c for every set instead; < 0: derive from w */
     double twist_tol;      /* stop a set when |omega| and |v| of its step are below this */
-    int32_t flags;         /* FR_FIXED_ITERS | FR_PROFILE_EVENTS | FR_FUSED */
+    int32_t flags;         /* FR_FIXED_ITERS | FR_PROFILE_EVENTS | FR_FUSED (slice and reduction in one
+                              kernel: same terms, binary32 partial sums taken in another order) */
     int32_t kinematics;    /* FR_KIN_RIGID */
 } fr_register_params;
 
@@ -331,7 +332,7 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
  * so a build overlaps the steps already queued; a step that includes a newly
  * admitted slot waits for that slot's build on the device, not on the host.
  * Results are bitwise those of fr_register on the same pair alone (sorted
- * splat; same iteration count).  One host thread at a time per engine.
+ * splat; same iteration count and FR_FUSED setting).  One host thread at a time per engine.
  */
 typedef struct fr_engine fr_engine;
 
@@ -342,6 +343,8 @@ typedef struct {
     int64_t arena_points;       /* model points resident at once (>= 1) */
     double w;                   /* outlier ratio of Eq. 4; c per request as in fr_register_params */
     double c_override;          /* >= 0: this c for every request; < 0: derive from w */
+    int32_t flags;              /* FR_FUSED: as fr_register with FR_FUSED */
+    int32_t reserved;           /* must be 0 */
 } fr_engine_params;
 
 /* Create an engine; allocates the point arena (52 bytes per point for d = 6

@@ -90,7 +90,8 @@ class fr_node_graph(ctypes.Structure):
 
 class fr_engine_params(ctypes.Structure):
     _fields_ = [("lattice", fr_lattice_params), ("residual", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("arena_points", ctypes.c_int64), ("w", ctypes.c_double), ("c_override", ctypes.c_double)]
+                ("arena_points", ctypes.c_int64), ("w", ctypes.c_double), ("c_override", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fr_report(ctypes.Structure):
@@ -534,11 +535,11 @@ def fr_engine_release(eng, slots):
 
 
 def engine_params(feat: int, residual: str, sigma, sigma_n=0.5, max_slots=256, arena_points=1 << 24, w=0.1,
-                  c=None, splat: int = FR_SPLAT_SORTED) -> fr_engine_params:
+                  c=None, splat: int = FR_SPLAT_SORTED, fused=False) -> fr_engine_params:
     values = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
     return fr_engine_params(lattice_params(feat, values, sigma, sigma_n, splat),
                             FR_PT2PL if residual == "pt2pl" else FR_PT2PT, int(max_slots), int(arena_points),
-                            float(w), -1.0 if c is None else float(c))
+                            float(w), -1.0 if c is None else float(c), FR_FUSED if fused else 0, 0)
 
 
 class Engine:

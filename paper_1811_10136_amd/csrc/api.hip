@@ -590,7 +590,7 @@ fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xf
     StreamScope scope(st);
     FR_HIP(hipSetDevice(lat->ctx->device));
     Plan plan;
-    FR_TRY(make_plan(lat->ctx, model_ref, xf, 256, nullptr, st, plan));
+    FR_TRY(make_plan(lat->ctx, model_ref, xf, kEstepTile, nullptr, st, plan));
     const int kind = xf ? xf->kind : FR_XF_NONE;
     FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1,
                         lat->V == 7 ? nsum : nullptr, nullptr, st));
@@ -621,7 +621,7 @@ fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, con
     FR_TRY(flags.alloc(lat->ctx, total_slots * sizeof(uint32_t)));
     FR_HIP(hipMemset(flags.p, 0, total_slots * sizeof(uint32_t)));
     Plan plan;
-    FR_TRY(make_plan(lat->ctx, model_ref, xf, 256, nullptr, st, plan));
+    FR_TRY(make_plan(lat->ctx, model_ref, xf, kEstepTile, nullptr, st, plan));
     const int kind = xf ? xf->kind : FR_XF_NONE;
     FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, nullptr, nullptr,
                         nullptr, flags.as<uint32_t>(), st));
@@ -745,16 +745,19 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                                    (double)(obs->offsets[s + 1] - obs->offsets[s]));
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
 
+    const bool fused = (params->flags & FR_FUSED) != 0;
     Plan pe, pr;
-    FR_TRY(make_plan(ctx, model_ref, nullptr, 256, nullptr, st, pe));
-    FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
+    FR_TRY(make_plan(ctx, model_ref, nullptr, kEstepTile, cset.data(), st, pe));
+    if (!fused) FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
     const bool pl = params->residual == FR_PT2PL;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);
     DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive;
-    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
-    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
-    if (pl || params->lattice.values == 7) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
-    FR_TRY(part.alloc(ctx, reduce_partials_floats(pr) * sizeof(float)));
+    if (!fused) {
+        FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+        FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+        if (pl || params->lattice.values == 7) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
+    }
+    FR_TRY(part.alloc(ctx, reduce_partials_floats(fused ? pe : pr) * sizeof(float)));
     FR_TRY(wjtj.alloc(ctx, S * 21 * sizeof(double)));
     FR_TRY(wjtr.alloc(ctx, S * 6 * sizeof(double)));
     FR_TRY(wstat.alloc(ctx, S * 4 * sizeof(double)));
@@ -786,12 +789,20 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     int it = 0;
     for (; it < max_it; ++it) {
         if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
-        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
-                            lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
-        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
-                             pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
-                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+        if (fused) {
+            FR_TRY(launch_estep_fused(lat->d, lat->V, lat->k, lat->sets_d, lat->err_d, 0, model_ref, pe,
+                                      wmats.as<float>(), params->residual, 0, part.as<float>(), st));
+            if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+            FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
+                                       wstat.as<double>(), st));
+        } else {
+            FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
+                                wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+            if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+            FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                                 pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
+                                 wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+        }
         FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
                                   wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
         if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
@@ -926,7 +937,7 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
 
     Plan pe, pr;
-    FR_TRY(make_plan(ctx, model_ref, &xf, 256, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, model_ref, &xf, kEstepTile, nullptr, st, pe));
     FR_TRY(make_plan(ctx, model_ref, &xf, 1024, &c, st, pr));
     const bool pl = params->residual == FR_PT2PL;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);
@@ -1065,7 +1076,7 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
     int64_t offs[2] = {0, M};
     fr_cloud warped{outs[0], outs[1], outs[2], outs[3], outs[4], outs[5], offs, 1};
     Plan pe;
-    FR_TRY(make_plan(ctx, &warped, nullptr, 256, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, &warped, nullptr, kEstepTile, nullptr, st, pe));
     auto t2 = clk::now();
     int it = 0;
     double info[2] = {0.0, 0.0};

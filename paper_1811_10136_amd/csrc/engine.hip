@@ -66,6 +66,7 @@ struct fr_engine {
     fr_ctx *ctx = nullptr;
     fr_engine_params prm{};
     int d = 3, V = 4;
+    bool fused = false;
     float k[8] = {};
     double sig_m = 1.0;
     int32_t S = 0;
@@ -104,8 +105,8 @@ struct fr_engine {
 
 static bool eng_ok(const fr_engine *e) { return e != nullptr && e->magic == kEngMagic; }
 
-// Plan image layout (S segments): seg_off i64[S] | seg_end i64[S] | tiles of
-// 256 i32[S+1] | tiles of 1024 i32[S+1] | seg_set i32[S] | active i32[S] | c f32[S]
+// Plan image layout (S segments): seg_off i64[S] | seg_end i64[S] | E-step
+// tiles i32[S+1] | tiles of 1024 i32[S+1] | seg_set i32[S] | active i32[S] | c f32[S]
 static size_t plan_image_bytes(int32_t S) { return ((size_t)36 * S + 8 + 255) / 256 * 256; }
 
 static void engine_free(fr_engine *e)
@@ -161,6 +162,10 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
         set_error("fr_engine_create: 0 <= w < 1 required");
         return FR_EINVAL;
     }
+    if ((p.flags & ~FR_FUSED) != 0 || p.reserved != 0) {
+        set_error("fr_engine_create: flags may only hold FR_FUSED and reserved must be 0");
+        return FR_EINVAL;
+    }
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     StreamScope scope(st);
@@ -188,7 +193,8 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     };
     const bool normals = e->d == 6;
     const int n_in = normals ? 6 : 3;
-    const size_t arena_floats = (size_t)P * (n_in + 4 + (e->V == 7 ? 3 : 0));
+    e->fused = (p.flags & FR_FUSED) != 0;
+    const size_t arena_floats = (size_t)P * (n_in + (e->fused ? 0 : 4 + (e->V == 7 ? 3 : 0)));
     fr_status s = e->arena.alloc(ctx, arena_floats * sizeof(float));
     if (s != FR_OK) return fail(s);
     float *a = e->arena.as<float>();
@@ -200,9 +206,11 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
         e->ny = a + 4 * P;
         e->nz = a + 5 * P;
     }
-    e->m0 = a + n_in * P;
-    e->m1 = e->m0 + P;
-    if (e->V == 7) e->ns = e->m1 + 3 * P;
+    if (!e->fused) {
+        e->m0 = a + n_in * P;
+        e->m1 = e->m0 + P;
+        if (e->V == 7) e->ns = e->m1 + 3 * P;
+    }
     // per-slot state
     const size_t b_pose = S * 16 * sizeof(double), b_jtj = S * 21 * sizeof(double), b_jtr = S * 6 * sizeof(double);
     const size_t b_stat = S * 4 * sizeof(double), b_tw = S * 2 * sizeof(double), b_mats = S * 12 * sizeof(float);
@@ -233,8 +241,8 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     e->plan_bytes = plan_image_bytes(e->S);
     s = e->plan_d.alloc(ctx, e->plan_bytes);
     if (s != FR_OK) return fail(s);
-    // reduction partials: at most one tile of 1024 per slot beyond P / 1024
-    s = e->partials.alloc(ctx, ((size_t)(P / 1024 + S + 2)) * 32 * sizeof(float));
+    // reduction partials: at most one tile per slot beyond P / tile
+    s = e->partials.alloc(ctx, ((size_t)(P / std::min(1024, kEstepTile) + S + 2)) * 32 * sizeof(float));
     if (s != FR_OK) return fail(s);
     s = e->admit_d.alloc(ctx, S * sizeof(AdmitRec));
     if (s != FR_OK) return fail(s);
@@ -449,7 +457,7 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         off[s] = sl.begin;
         end[s] = on ? sl.begin + sl.m : sl.begin;
         const int64_t m = on ? sl.m : 0;
-        te[s + 1] = te[s] + (int32_t)((m + 255) / 256);
+        te[s + 1] = te[s] + (int32_t)((m + kEstepTile - 1) / kEstepTile);
         tr[s + 1] = tr[s] + (int32_t)((m + 1023) / 1024);
         set[s] = s;
         act[s] = on ? 1 : 0;
@@ -489,14 +497,20 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         p.seg_c = d_c;
     };
     Plan pe, pr;
-    make(d_te, te[S], 256, pe);
+    make(d_te, te[S], kEstepTile, pe);
     make(d_tr, tr[S], 1024, pr);
     fr_cloud arena{e->x, e->y, e->z, e->nx, e->ny, e->nz, e->offsets_h, 1};
-    FR_TRY(launch_estep_sets(e->d, e->V, e->k, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats, e->m0,
-                             e->m1, e->V == 7 ? e->ns : nullptr, nullptr, e->st));
-    FR_TRY(launch_reduce(&arena, pr, FR_XF_RIGID, e->mats, e->m0, e->m1,
-                         e->prm.residual == FR_PT2PL ? e->ns : nullptr, e->prm.residual, 0, e->sig_m, e->jtj, e->jtr,
-                         e->stats, e->partials.as<float>(), e->st));
+    if (e->fused) {
+        FR_TRY(launch_estep_fused(e->d, e->V, e->k, e->tables, e->err, 1, &arena, pe, e->mats, e->prm.residual, 0,
+                                  e->partials.as<float>(), e->st));
+        FR_TRY(launch_reduce_final(pe, e->partials.as<float>(), e->sig_m, e->jtj, e->jtr, e->stats, e->st));
+    } else {
+        FR_TRY(launch_estep_sets(e->d, e->V, e->k, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats,
+                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, e->st));
+        FR_TRY(launch_reduce(&arena, pr, FR_XF_RIGID, e->mats, e->m0, e->m1,
+                             e->prm.residual == FR_PT2PL ? e->ns : nullptr, e->prm.residual, 0, e->sig_m, e->jtj,
+                             e->jtr, e->stats, e->partials.as<float>(), e->st));
+    }
     FR_TRY(launch_solve_rigid(S, e->jtj, e->jtr, e->poses, e->mats, e->twist, e->status, d_act, e->st));
     return FR_OK;
 }

@@ -18,6 +18,11 @@ constexpr int32_t kKeyBias = 1 << 20;              // coordinates live in [-2^20
 constexpr uint64_t kKeyEmpty = ~0ull;              // never a packed key: bit 63 of a key is 0
 constexpr uint32_t kOwnerEmpty = 0xFFFFFFFFu;
 
+// E-step tiling: each of the 256 threads of a block slices kEstepPP
+// consecutive model points.
+constexpr int kEstepPP = 4;
+constexpr int kEstepTile = 256 * kEstepPP;
+
 template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; };   // 3 coordinates per u64
 
 // The lattice table of one set is a two-choice cuckoo hash: every vertex key

@@ -184,6 +184,13 @@ fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, co
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
                         double *jtr, double *stats, float *partials, hipStream_t stream);
 size_t reduce_partials_floats(const Plan &plan);
+fr_status launch_reduce_final(const Plan &plan, const float *partials, double sigma, double *jtj, double *jtr,
+                              double *stats, hipStream_t st);
+// Fused slice + reduction (E-step and M-step terms of every point in one
+// pass): one partial row per E-step tile, then launch_reduce_final on `plan`.
+fr_status launch_estep_fused(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+                             const fr_cloud *model, const Plan &plan, const float *mats, int residual,
+                             int normalize_n, float *partials, hipStream_t st);
 
 // solve.hip
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,

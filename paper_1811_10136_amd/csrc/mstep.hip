@@ -9,15 +9,13 @@
 // tiles' partial rows in tile order in binary64 (fixed order -> bitwise
 // reproducible) and applies the 1/sigma^2 of the residual scaling.
 #include "fr_internal.h"
+#include "fr_mstep.h"
 
 namespace fr {
 
 constexpr int kRedThreads = 256;
 constexpr int kRedPerThread = 4;
 constexpr int kRedTile = kRedThreads * kRedPerThread;
-constexpr int kRedVals = 31;      // 21 JtJ + 6 Jtr + 4 stats
-constexpr int kRedStride = 32;
-
 struct ReduceArgs {
     const float *x, *y, *z;
     const float *mats;
@@ -28,26 +26,6 @@ struct ReduceArgs {
     float *partials;
     int normalize_n;
 };
-
-__host__ __device__ constexpr int ut_index(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
-
-template <int NR>
-__device__ __forceinline__ void accumulate_rows(float (&acc)[kRedVals], const float (&J)[NR][6], const float (&r)[NR],
-                                                float w)
-{
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        float wj[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) wj[a] = w * J[q][a];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-#pragma unroll
-            for (int b = a; b < 6; ++b) acc[ut_index(a, b)] = fmaf(wj[a], J[q][b], acc[ut_index(a, b)]);
-            acc[21 + a] = fmaf(wj[a], r[q], acc[21 + a]);
-        }
-    }
-}
 
 template <int RES, bool XF>
 __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
@@ -81,60 +59,17 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
         }
         const float m0 = __builtin_nontemporal_load(a.m0 + i);
         if (!(m0 > 0.0f)) continue;
-        const float w = m0 / (m0 + c);
-        const float inv = 1.0f / m0;
-        const float tx = __builtin_nontemporal_load(a.m1 + i) * inv;
-        const float ty = __builtin_nontemporal_load(a.m1 + a.M + i) * inv;
-        const float tz = __builtin_nontemporal_load(a.m1 + 2 * a.M + i) * inv;
-        const float dx = x - tx, dy = y - ty, dz = z - tz;
-        float r2;
-        if constexpr (RES == FR_PT2PT) {
-            // rows of J = [-[x]_x, I]
-            const float J[3][6] = {{0.0f, z, -y, 1.0f, 0.0f, 0.0f},
-                                   {-z, 0.0f, x, 0.0f, 1.0f, 0.0f},
-                                   {y, -x, 0.0f, 0.0f, 0.0f, 1.0f}};
-            const float r[3] = {dx, dy, dz};
-            accumulate_rows<3>(acc, J, r, w);
-            r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        } else {
-            float nx = __builtin_nontemporal_load(a.ns + i) * inv;
-            float ny = __builtin_nontemporal_load(a.ns + a.M + i) * inv;
-            float nz = __builtin_nontemporal_load(a.ns + 2 * a.M + i) * inv;
-            if (a.normalize_n) {
-                const float nn = sqrtf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
-                const float in = nn > 0.0f ? 1.0f / nn : 0.0f;
-                nx *= in;
-                ny *= in;
-                nz *= in;
-            }
-            const float rr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
-            // J = [x cross n, n]
-            const float J[1][6] = {{y * nz - z * ny, z * nx - x * nz, x * ny - y * nx, nx, ny, nz}};
-            const float r[1] = {rr};
-            accumulate_rows<1>(acc, J, r, w);
-            r2 = rr * rr;
+        float nsx = 0.0f, nsy = 0.0f, nsz = 0.0f;
+        if constexpr (RES == FR_PT2PL) {
+            nsx = __builtin_nontemporal_load(a.ns + i);
+            nsy = __builtin_nontemporal_load(a.ns + a.M + i);
+            nsz = __builtin_nontemporal_load(a.ns + 2 * a.M + i);
         }
-        acc[27] += w;
-        acc[28] = fmaf(w, r2, acc[28]);
-        acc[29] += 1.0f;
-        acc[30] += m0;
+        mstep_point<RES>(acc, x, y, z, m0, __builtin_nontemporal_load(a.m1 + i),
+                         __builtin_nontemporal_load(a.m1 + a.M + i), __builtin_nontemporal_load(a.m1 + 2 * a.M + i),
+                         nsx, nsy, nsz, c, a.normalize_n);
     }
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int j = 0; j < kRedVals; ++j) {
-        float v = acc[j];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) part[wave][j] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kRedVals) {
-        float v = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kRedThreads / 64; ++w) v += part[w][threadIdx.x];
-        a.partials[(size_t)t * kRedStride + threadIdx.x] = v;
-    }
+    block_partials(acc, part, a.partials + (size_t)t * kRedStride);
 }
 
 // One block per segment: 8 lanes per value each sum every 8th tile in binary64,
@@ -167,6 +102,15 @@ __global__ void __launch_bounds__(256) k_reduce_final(TileMap tm, const float *p
 }
 
 size_t reduce_partials_floats(const Plan &plan) { return (size_t)(plan.n_tiles + 1) * kRedStride; }
+
+fr_status launch_reduce_final(const Plan &plan, const float *partials, double sigma, double *jtj, double *jtr,
+                              double *stats, hipStream_t st)
+{
+    if (plan.n_seg == 0) return FR_OK;
+    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
 
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,

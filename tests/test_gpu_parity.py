@@ -288,14 +288,15 @@ def test_register_exact_recovery(fr, ctx, feat, residual):
     assert oracle.alignment_error(T[0], p.T_gt, p.model) < 1e-5
 
 
-def test_register_parity_depth_batch_and_alone_bitwise(fr, ctx):
+@pytest.mark.parametrize("fused", [False, True])
+def test_register_parity_depth_batch_and_alone_bitwise(fr, ctx, fused):
     """Three depth pairs of different sizes registered alone and as one batch: identical poses,
-    all within tolerance of the oracle."""
+    all within tolerance of the oracle (also with the slice and the reduction fused)."""
     pairs = [synth.depth_pair(s, width=w, height=h, f=f) for s, (w, h, f) in
              enumerate([(160, 120, 131.25), (96, 72, 78.75), (200, 150, 164.06)])]
     T0s = [q.T_gt @ oracle.se3_exp(np.array([0.004, -0.003, 0.002, 0.004, 0.003, -0.002])) for q in pairs]
-    prm = fr.register_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, iters=15, w=0.1)
-    _say("[register] depth batch of 3 " + str([len(q.model) for q in pairs]))
+    prm = fr.register_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, iters=15, w=0.1, fused=fused)
+    _say(f"[register] depth batch of 3 {[len(q.model) for q in pairs]} fused={fused}")
     Tb, sb, _ = fr.register(ctx, upload([q.model for q in pairs], [q.model_n for q in pairs]),
                             upload([q.obs for q in pairs], [q.obs_n for q in pairs]), prm, T0=np.stack(T0s))
     assert (sb == 0).all()
@@ -370,3 +371,21 @@ def test_budget_is_enforced(fr):
     assert e.value.status == fr.FR_EBUDGET
     assert fr.fr_ctx_usage(small.h) == 0
     small.close()
+
+
+@pytest.mark.parametrize("feat,residual", [(3, "pt2pt"), (3, "pt2pl"), (6, "pt2pt")])
+def test_register_fused_matches_oracle_other_variants(fr, ctx, feat, residual):
+    """The fused slice + reduction for the other feature/residual combinations, from a start near
+    the ground truth, against the oracle."""
+    q = synth.depth_pair(9, width=160, height=120, f=131.25)
+    T0 = q.T_gt @ oracle.se3_exp(np.array([0.003, 0.002, -0.003, -0.003, 0.002, 0.003]))
+    prm = fr.register_params(feat, residual, q.sigma, q.sigma_n, iters=10, w=0.1, fused=True)
+    nrm = feat == 6 or residual == "pt2pl"
+    T, st, _ = fr.register(ctx, upload([q.model], [q.model_n] if feat == 6 else None),
+                           upload([q.obs], [q.obs_n] if nrm else None), prm, T0=T0[None])
+    ref = oracle.register_rigid(q.model, q.model_n if feat == 6 else None, q.obs, q.obs_n if nrm else None,
+                                feat=feat, residual=residual, sigma=q.sigma, sigma_n=q.sigma_n, w=0.1, iters=10,
+                                T0=T0)
+    assert int(st[0]) == 0
+    ang, dt, ok = pose_close(T[0], ref)
+    assert ok, (ang, dt)

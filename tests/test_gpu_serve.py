@@ -33,14 +33,15 @@ def pairs():
     return [synth.depth_pair(100 + i, target_points=m) for i, m in enumerate(SIZES)]
 
 
-def _alone(fr, ctx, p, iters=ITERS):
-    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=iters, w=p.w, fixed=True)
+def _alone(fr, ctx, p, iters=ITERS, fused=False):
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=iters, w=p.w, fixed=True, fused=fused)
     T, st, _ = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm, T0=np.eye(4)[None])
     return T[0], int(st[0])
 
 
-def _engine(fr, ctx, p0, slots=4, arena=150_000):
-    prm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=slots, arena_points=arena, w=p0.w)
+def _engine(fr, ctx, p0, slots=4, arena=150_000, fused=False):
+    prm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=slots, arena_points=arena, w=p0.w,
+                           fused=fused)
     return fr.Engine(ctx, prm)
 
 
@@ -52,11 +53,13 @@ def _read(eng, S):
     return poses.numpy().reshape(S, 4, 4).copy(), status.numpy().copy()
 
 
-def test_engine_mix_is_bitwise_the_pair_alone(fr, ctx, pairs):
+@pytest.mark.parametrize("fused", [False, True])
+def test_engine_mix_is_bitwise_the_pair_alone(fr, ctx, pairs, fused):
     """Requests join and leave at different ticks, reuse slots and arena ranges, and share every
     launch with different neighbours; each ends bitwise where fr_register leaves it alone."""
-    alone = [_alone(fr, ctx, p) for p in pairs]
-    eng = _engine(fr, ctx, pairs[0])
+    print(f"[serve] mix fused={fused}", flush=True)
+    alone = [_alone(fr, ctx, p, fused=fused) for p in pairs]
+    eng = _engine(fr, ctx, pairs[0], fused=fused)
     S = eng.max_slots
     # schedule: (tick, requests admitted at that tick into (slot, arena begin))
     admissions = {0: [(0, 0, 0), (1, 1, 10_000)], 2: [(2, 2, 65_000), (3, 3, 70_000)],
