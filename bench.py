@@ -44,6 +44,7 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 EST_BYTES_PER_POINT = 24 + 28          # model position + normal in, M0 + M1 + N out (binary32)
+FUSED_BYTES_PER_POINT = 24             # fused slice + reduction: only the model point and normal move
 VERTEX_BYTES = 16 + 4 * 7              # packed 6-coordinate key + 7 binary32 values
 ITERS = 20
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "estep_depth64_counters.json")
@@ -64,18 +65,19 @@ def make_pairs(n, workers):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("estep.hip", "fr_device.h"):
+    for f in ("estep.hip", "fr_device.h", "fr_mstep.h"):
         h.update(open(os.path.join(ROOT, "paper_1811_10136_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(pairs_points):
+def traffic_from_profile(pairs_points, kernel):
     """HBM bytes per E-step launch from committed rocprofv3 counter runs, if they match this kernel."""
     try:
         prof = json.load(open(PROFILE_SUMMARY))
     except (OSError, ValueError):
         return None
-    if prof.get("kernel_source_hash") != kernel_source_hash() or prof.get("model_points") != pairs_points:
+    if (prof.get("kernel_source_hash") != kernel_source_hash() or prof.get("model_points") != pairs_points
+            or prof.get("kernel") != kernel):
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -243,6 +245,83 @@ def serve_bench(fr, ctx, args):
     }
 
 
+# ------------------------------------------------------------------------------
+# the other workloads: single-pair times (latency and throughput context, not roofline)
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts)), out
+
+
+def other_workloads(fr, ctx, reps=5):
+    out = {}
+    # ellipsoid pair: 2000 points + 10% outliers, point-to-point, d = 3, 30 iterations
+    p = synth.ellipsoid_pair(0)
+    prm = fr.register_params(3, "pt2pt", p.sigma, iters=30, w=p.w, profile=True)
+    m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+    ms, (T, st, rep) = _timed(lambda: fr.register(ctx, m, o, prm), reps)
+    out["ellipsoid_pt2pt"] = {"model_points": len(p.model), "obs_points": len(p.obs), "iters": 30,
+                              "registration_ms": ms, "build_ms": rep.build_ms,
+                              "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches)}
+    # one depth-frame pair: the single-pair latency of the batched workload
+    p = synth.depth_pair(0)
+    m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+    for fused in (False, True):
+        prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, profile=True, fused=fused)
+        ms, (T, st, rep) = _timed(lambda: fr.register(ctx, m, o, prm), reps)
+        out["depth_pt2pl" + ("_fused" if fused else "")] = {
+            "model_points": len(p.model), "obs_points": len(p.obs), "iters": 20, "registration_ms": ms,
+            "build_ms": rep.build_ms, "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches),
+            "mstep_ms_per_iter": rep.mstep_ms / max(1, rep.iterations)}
+    # articulated: 60k points, 20 capsule links, 32 DOF, 15 iterations
+    p = synth.articulated_pair(1)
+    t = p.extra["tree"]
+    kt = fr.KinematicTree(t.parent, t.dof_offset, t.origin, t.axis)
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=p.iters, w=p.w, profile=True)
+    m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+
+    def art():
+        th = p.extra["theta0"].copy()
+        return fr.fr_register_articulated(ctx.h, m, p.extra["body_offsets"], o, kt, prm, th)
+    ms, (st, rep) = _timed(art, reps)
+    out["articulated_pt2pl"] = {"model_points": len(p.model), "obs_points": len(p.obs), "bodies": 20, "dof": 32,
+                                "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
+                                "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches)}
+    # node graph: 100k points, 512 nodes, 20 iterations
+    p = synth.nodegraph_pair(0)
+    e = p.extra
+    g = fr.NodeGraph(e["nodes"], e["skin_idx"], e["skin_w"], e["edges"], 1.0)
+    prm = fr.register_params(3, "pt2pt", p.sigma, iters=p.iters, w=p.w, profile=True)
+    m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+
+    def ngr():
+        T = np.repeat(np.eye(4)[None], len(e["nodes"]), 0)
+        return fr.fr_register_nodegraph(ctx.h, m, o, g, prm, T)
+    ms, (st, rep) = _timed(ngr, 3)
+    out["nodegraph_pt2pt"] = {"model_points": len(p.model), "obs_points": len(p.obs), "nodes": len(e["nodes"]),
+                              "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
+                              "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches),
+                              "pcg_iters_last": rep.solver_iters}
+    return out
+
+
+def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):
+    """Lattice build of the 64 observation frames, sorted and atomic splat (observation points per second)."""
+    res = {}
+    for name, splat in (("sorted", fr.FR_SPLAT_SORTED), ("atomic", fr.FR_SPLAT_ATOMIC)):
+        prm = fr.lattice_params(6, 7, sigma, sigma_n, splat)
+        ms, _ = _timed(lambda: fr.Lattice(ctx, obs, prm).close(), reps)
+        res[name] = {"ms": ms, "obs_points_per_s": obs.n / ms * 1e3}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +330,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--iters", type=int, default=ITERS)
     ap.add_argument("--splat", choices=["sorted", "atomic"], default="sorted")
+    ap.add_argument("--fused", type=int, default=0, help="1: slice and reduction in one kernel (FR_FUSED)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=3, help="pairs the CPU oracle baseline runs")
     ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
@@ -288,7 +368,7 @@ def main():
     sigma, sigma_n = pairs[0].sigma, pairs[0].sigma_n
     splat = fr.FR_SPLAT_SORTED if args.splat == "sorted" else fr.FR_SPLAT_ATOMIC
     prm = fr.register_params(6, "pt2pl", sigma, sigma_n, iters=args.iters, w=0.1, fixed=True, profile=True,
-                             splat=splat)
+                             splat=splat, fused=bool(args.fused))
     T0 = np.repeat(np.eye(4)[None], len(pairs), 0)
     torch.cuda.synchronize()
 
@@ -320,10 +400,12 @@ def main():
     lat.close()
 
     points_per_launch = sum(M)
-    alg_bytes = points_per_launch * EST_BYTES_PER_POINT + touched * VERTEX_BYTES
+    per_point = FUSED_BYTES_PER_POINT if args.fused else EST_BYTES_PER_POINT
+    alg_bytes = points_per_launch * per_point + touched * VERTEX_BYTES
     est_avg_s = est_ms / max(1, est_n) / 1e3
     achieved = alg_bytes / est_avg_s / 1e9
-    traffic = traffic_from_profile(points_per_launch)
+    kernel = "k_estep_fused<6,7,rigid,pt2pl>" if args.fused else "k_estep<6,7,rigid>"
+    traffic = traffic_from_profile(points_per_launch, kernel)
 
     value = points_per_launch * args.iters * args.steps / total_s
     out = {
@@ -353,7 +435,8 @@ def main():
                   "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99))},
         "build_ms_mean": float(np.mean(build_ms)),
         "roofline": {
-            "kernel": "k_estep<6,7,rigid>",
+            "kernel": kernel,
+            "bytes_per_point": per_point, "bytes_per_touched_vertex": VERTEX_BYTES,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -364,6 +447,9 @@ def main():
             "mean_launch_ms": est_avg_s * 1e3,
         },
     }
+    log("other workloads and build rates ...")
+    out["other_workloads"] = other_workloads(fr, ctx)
+    out["build"] = build_rates(fr, ctx, obs, sigma, sigma_n)
     if not args.no_serve:
         out["serving"] = serve_bench(fr, ctx, args)
         h = out["serving"]["headline"]

@@ -36,199 +36,101 @@ __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontempora
 template <typename T>
 __device__ __forceinline__ void st_stream(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
-// Each thread slices kEstepPP consecutive points of its segment.  Model
-// points arrive in scan order, so neighbouring points mostly share simplex
-// vertices (three in four for depth frames): a vertex whose key equals one of
-// the previous point's takes that point's table slot and lookup result, and
-// only the remaining vertices are hashed into the table.  The block first
-// stages its tile of points through LDS so that the HBM reads stay coalesced.
-// The arithmetic of every point -- its embedding, its weights and the order
-// of its sum over vertices -- is the same as for a point sliced on its own.
-template <int d>
-struct Stage {
-    static constexpr int NIN = d == 6 ? 6 : 3;
-    static constexpr int ROW = 256 * (kEstepPP + 1);   // padded: point j of the tile sits at j + j / PP
-    float v[NIN][ROW];
-};
-
-// Slice the tile of segment s starting at point `first` (n_here points);
-// emit(i, x, y, z, acc) receives every point's index, moved position and
-// slice sums.
-template <int d, int V, bool XF, class Emit>
-__device__ __forceinline__ void slice_tile(const EstepArgs &a, int32_t s, int64_t first, int32_t n_here,
-                                           Stage<d> &sg, Emit &&emit)
+// Slice model point i of segment s: its moved position (x[0..2]) and the
+// slice sums acc = sum_k b_k [1, y, n_y] over the vertices found.
+template <int d, int V, bool XF>
+__device__ __forceinline__ void slice_point(const EstepArgs &a, int32_t s, int64_t i, const SetTable &st,
+                                            float (&x)[3], float (&acc)[V])
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    constexpr int PP = kEstepPP;
-    constexpr int NIN = Stage<d>::NIN;
-    auto &stage = sg.v;
-    const SetTable st = a.sets[a.tm.seg_set[s]];
-
-    const float *src[6] = {a.x, a.y, a.z, a.nx, a.ny, a.nz};
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int32_t j = q * 256 + (int32_t)threadIdx.x;
-        if (j < n_here) {
-#pragma unroll
-            for (int c = 0; c < NIN; ++c) stage[c][j + j / PP] = ld_stream(src[c] + first + j);
-        }
-    }
-    __syncthreads();
-
-    float m[12];
+    float px = ld_stream(a.x + i), py = ld_stream(a.y + i), pz = ld_stream(a.z + i);
+    float p[d];
     if constexpr (XF) {
+        float m[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+        xform_point(m, px, py, pz, p[0], p[1], p[2]);
+        if constexpr (d == 6) {
+            xform_normal(m, ld_stream(a.nx + i), ld_stream(a.ny + i), ld_stream(a.nz + i), p[3], p[4], p[5]);
+        }
+    } else {
+        p[0] = px;
+        p[1] = py;
+        p[2] = pz;
+        if constexpr (d == 6) {
+            p[3] = ld_stream(a.nx + i);
+            p[4] = ld_stream(a.ny + i);
+            p[5] = ld_stream(a.nz + i);
+        }
     }
     float kk[d];
 #pragma unroll
     for (int j = 0; j < d; ++j) kk[j] = a.k[j];
 
-    uint64_t pk[D][KW];          // previous point's vertex keys (kKeyEmpty: none)
-    uint32_t pslot[D];           // and their value-slot byte offsets
-    uint32_t pfound = 0;         // bit v: previous vertex v is in the table
-#pragma unroll
-    for (int v = 0; v < D; ++v) {
-#pragma unroll
-        for (int w = 0; w < KW; ++w) pk[v][w] = kKeyEmpty;
-        pslot[v] = 0;
-    }
-    constexpr uint32_t VB = (uint32_t)(ValPad<V>::value * sizeof(float));
-    const int32_t base = (int32_t)threadIdx.x * PP;
-    for (int q = 0; q < PP; ++q) {
-        const int32_t j = base + q;
-        if (j >= n_here) break;
-        const int32_t sj = j + j / PP;
-        float p[d];
-        if constexpr (XF) {
-            xform_point(m, stage[0][sj], stage[1][sj], stage[2][sj], p[0], p[1], p[2]);
-            if constexpr (d == 6) xform_normal(m, stage[3][sj], stage[4][sj], stage[5][sj], p[3], p[4], p[5]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < d; ++c) p[c] = stage[c][sj];
-        }
-        uint64_t keys[D][KW];
-        float b[D];
-        if (!embed<d>(p, kk, keys, b)) atomicOr(a.err + a.err_stride * s, 1);
+    uint64_t keys[D][KW];
+    float b[D];
+    if (!embed<d>(p, kk, keys, b)) atomicOr(a.err + a.err_stride * s, 1);
 
-        // vertices shared with the previous point
-        uint32_t slot[D];
-        uint32_t found = 0, known = 0;
 #pragma unroll
-        for (int v = 0; v < D; ++v) {
-            slot[v] = 0;
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const bool eq = key_equal<KW>(keys[v], pk[u]);
-                slot[v] = eq ? pslot[u] : slot[v];
-                found |= eq ? ((pfound >> u) & 1u) << v : 0u;
-                known |= eq ? 1u << v : 0u;
-            }
-        }
-        // the others through the table: both candidate key slots, read only by
-        // lanes that need them
-        uint32_t p1[D], p2[D];
-        uint64_t ka[D][KW], kc[D][KW];
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-            cuckoo_slots(hash_key<KW>(keys[v], st.seed), st.cap, p1[v], p2[v]);
-#pragma unroll
-            for (int w = 0; w < KW; ++w) {
-                ka[v][w] = kKeyEmpty;
-                kc[v][w] = kKeyEmpty;
-            }
-            if (!((known >> v) & 1u)) {
-                load_key<KW>(st.keys, p1[v], ka[v]);
-                load_key<KW>(st.keys, p2[v], kc[v]);
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-            if (!((known >> v) & 1u)) {
-                const bool in1 = key_equal<KW>(ka[v], keys[v]);
-                const bool in2 = key_equal<KW>(kc[v], keys[v]);
-                slot[v] = (in1 ? p1[v] : p2[v]) * VB;
-                found |= (in1 || in2) ? 1u << v : 0u;
-            }
-        }
-        float acc[V];
-#pragma unroll
-        for (int c = 0; c < V; ++c) acc[c] = 0.0f;
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-            const bool f = (found >> v) & 1u;
-            const float w = f ? b[v] : 0.0f;
-            u32x4 q0 = {0u, 0u, 0u, 0u}, q1 = q0;
-            if (f) {
-                q0 = load_at<u32x4>(st.vals, slot[v]);
-                if constexpr (V > 4) q1 = load_at<u32x4>(st.vals, slot[v] + 16u);
-            }
-            const float val[8] = {__uint_as_float(q0.x), __uint_as_float(q0.y), __uint_as_float(q0.z),
-                                  __uint_as_float(q0.w), __uint_as_float(q1.x), __uint_as_float(q1.y),
-                                  __uint_as_float(q1.z), __uint_as_float(q1.w)};
-#pragma unroll
-            for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
-        }
-        emit(first + j, p[0], p[1], p[2], acc);
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) pk[v][w] = keys[v][w];
-            pslot[v] = slot[v];
-        }
-        pfound = found;
-    }
+    for (int c = 0; c < V; ++c) acc[c] = 0.0f;
+    slice_simplex<KW, V, D>(st.keys, st.vals, st, keys, b, acc);
+    x[0] = p[0];
+    x[1] = p[1];
+    x[2] = p[2];
 }
 
 template <int d, int V, bool XF>
 __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
 {
-    __shared__ Stage<d> sg;
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
-    const int64_t first = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
-    const int32_t n_here = (int32_t)min((int64_t)a.tm.tile, a.tm.seg_end[s] - first);
-    slice_tile<d, V, XF>(a, s, first, n_here, sg, [&](int64_t i, float, float, float, const float (&acc)[V]) {
-        a.m0[i] = acc[0];
-        a.m1[i] = acc[1];
-        a.m1[a.M + i] = acc[2];
-        a.m1[2 * a.M + i] = acc[3];
-        if constexpr (V == 7) {
-            if (a.ns != nullptr) {
-                a.ns[i] = acc[4];
-                a.ns[a.M + i] = acc[5];
-                a.ns[2 * a.M + i] = acc[6];
-            }
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_end[s]) return;
+    const SetTable st = a.sets[a.tm.seg_set[s]];
+    float x[3], acc[V];
+    slice_point<d, V, XF>(a, s, i, st, x, acc);
+    st_stream(a.m0 + i, acc[0]);
+    st_stream(a.m1 + i, acc[1]);
+    st_stream(a.m1 + a.M + i, acc[2]);
+    st_stream(a.m1 + 2 * a.M + i, acc[3]);
+    if constexpr (V == 7) {
+        if (a.ns != nullptr) {
+            st_stream(a.ns + i, acc[4]);
+            st_stream(a.ns + a.M + i, acc[5]);
+            st_stream(a.ns + 2 * a.M + i, acc[6]);
         }
-    });
+    }
 }
 
 // Fused slice + reduction: every point's M-step terms (Eq. 7 / Eq. 10 in the
-// twist of Eq. 16) are accumulated right after its slice, and the block writes
-// one partial row of the normal equations per tile; M0, M1 and N never leave
-// the chip.
+// twist of Eq. 16) are formed right after its slice and the block writes one
+// partial row of the normal equations per tile; M0, M1 and N never leave the
+// chip.
 template <int d, int V, bool XF, int RES>
 __global__ void __launch_bounds__(256) k_estep_fused(EstepArgs a)
 {
-    __shared__ Stage<d> sg;
     __shared__ float part[4][kRedStride];
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
-    const int64_t first = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
-    const int32_t n_here = (int32_t)min((int64_t)a.tm.tile, a.tm.seg_end[s] - first);
-    const float c = a.seg_c[s];
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
     float red[kRedVals];
 #pragma unroll
     for (int j = 0; j < kRedVals; ++j) red[j] = 0.0f;
-    slice_tile<d, V, XF>(a, s, first, n_here, sg, [&](int64_t, float x, float y, float z, const float (&acc)[V]) {
+    if (i < a.tm.seg_end[s]) {
+        const SetTable st = a.sets[a.tm.seg_set[s]];
+        float x[3], acc[V];
+        slice_point<d, V, XF>(a, s, i, st, x, acc);
+        const float c = a.seg_c[s];
         if constexpr (RES == FR_PT2PL)
-            mstep_point<RES>(red, x, y, z, acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], c, a.normalize_n);
+            mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], c,
+                             a.normalize_n);
         else
-            mstep_point<RES>(red, x, y, z, acc[0], acc[1], acc[2], acc[3], 0.0f, 0.0f, 0.0f, c, a.normalize_n);
-    });
+            mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], 0.0f, 0.0f, 0.0f, c,
+                             a.normalize_n);
+    }
     block_partials(red, part, a.partials + (size_t)t * kRedStride);
 }
 
@@ -241,39 +143,36 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_end[s]) return;
     const SetTable st = a.sets[a.tm.seg_set[s]];
-    const int64_t first = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
-    for (int q = 0; q < kEstepPP; ++q) {
-        const int64_t i = first + q * 256 + threadIdx.x;
-        if (i >= a.tm.seg_end[s]) break;
-        float p[d];
-        if constexpr (XF) {
-            float m[12];
+    float p[d];
+    if constexpr (XF) {
+        float m[12];
 #pragma unroll
-            for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
-            xform_point(m, a.x[i], a.y[i], a.z[i], p[0], p[1], p[2]);
-            if constexpr (d == 6) xform_normal(m, a.nx[i], a.ny[i], a.nz[i], p[3], p[4], p[5]);
-        } else {
-            p[0] = a.x[i];
-            p[1] = a.y[i];
-            p[2] = a.z[i];
-            if constexpr (d == 6) {
-                p[3] = a.nx[i];
-                p[4] = a.ny[i];
-                p[5] = a.nz[i];
-            }
+        for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+        xform_point(m, a.x[i], a.y[i], a.z[i], p[0], p[1], p[2]);
+        if constexpr (d == 6) xform_normal(m, a.nx[i], a.ny[i], a.nz[i], p[3], p[4], p[5]);
+    } else {
+        p[0] = a.x[i];
+        p[1] = a.y[i];
+        p[2] = a.z[i];
+        if constexpr (d == 6) {
+            p[3] = a.nx[i];
+            p[4] = a.ny[i];
+            p[5] = a.nz[i];
         }
-        float kk[d];
+    }
+    float kk[d];
 #pragma unroll
-        for (int j = 0; j < d; ++j) kk[j] = a.k[j];
-        uint64_t keys[D][KW];
-        float b[D];
-        embed<d>(p, kk, keys, b);
+    for (int j = 0; j < d; ++j) kk[j] = a.k[j];
+    uint64_t keys[D][KW];
+    float b[D];
+    embed<d>(p, kk, keys, b);
 #pragma unroll
-        for (int v = 0; v < D; ++v) {
-            const int64_t slot = find_slot<KW>(st.keys, st, keys[v]);
-            if (slot >= 0) a.touched[st.slot_base + slot] = 1u;
-        }
+    for (int v = 0; v < D; ++v) {
+        const int64_t slot = find_slot<KW>(st.keys, st, keys[v]);
+        if (slot >= 0) a.touched[st.slot_base + slot] = 1u;
     }
 }
 

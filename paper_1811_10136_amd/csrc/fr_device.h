@@ -18,10 +18,8 @@ constexpr int32_t kKeyBias = 1 << 20;              // coordinates live in [-2^20
 constexpr uint64_t kKeyEmpty = ~0ull;              // never a packed key: bit 63 of a key is 0
 constexpr uint32_t kOwnerEmpty = 0xFFFFFFFFu;
 
-// E-step tiling: each of the 256 threads of a block slices kEstepPP
-// consecutive model points.
-constexpr int kEstepPP = 4;
-constexpr int kEstepTile = 256 * kEstepPP;
+// E-step tiling: one model point per thread, 256 threads per block.
+constexpr int kEstepTile = 256;
 
 template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; };   // 3 coordinates per u64
 

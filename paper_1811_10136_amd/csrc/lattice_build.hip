@@ -280,93 +280,45 @@ __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, float4 k
     }
 }
 
-// Find or claim a key in the provisional linear-probing table of its set.  A
-// slot that already has an owner is compared with a plain read first; only
-// free slots are claimed with a CAS.  Probing stops after kMaxProbe slots and
-// returns kOwnerEmpty (the host then retries with a larger table).
+// One thread per record: find or claim the record's key in the provisional
+// linear-probing table of its set.  A slot that already has an owner is
+// compared with a plain read first; only free slots are claimed with a CAS.
+// Probing stops after kMaxProbe slots and raises `fail` (the host then
+// retries with a larger table).
 constexpr uint32_t kMaxProbe = 128;
 
 template <int KW>
-__device__ __forceinline__ uint32_t insert_key(const SetTable &st, const uint64_t (&key)[KW], uint32_t r,
-                                               const uint64_t *rec_key, size_t R, uint32_t *own)
-{
-    uint32_t h = hash_key<KW>(key, 0u) & st.mask;
-    const uint32_t limit = min(st.mask + 1u, kMaxProbe);
-    for (uint32_t n = 0; n < limit; ++n) {
-        const size_t slot = st.slot_base + h;
-        uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, r);
-        bool mine = (o == kOwnerEmpty);
-        if (!mine) {
-            mine = true;
-#pragma unroll
-            for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
-        }
-        if (mine) return (uint32_t)slot;
-        h = (h + 1) & st.mask;
-    }
-    return kOwnerEmpty;
-}
-
-// Each thread inserts the D records of kInsertPP consecutive observation
-// points.  Points arrive in scan order and neighbours share most simplex
-// vertices, so a record whose key equals one of the previous point's takes
-// that record's slot without touching the table (the slot is already owned by
-// an earlier record of the same key).
-constexpr int kInsertPP = 4;
-
-template <int KW, int D>
 __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTable *tables, const uint64_t *rec_key,
                                                        size_t R, uint32_t *own, uint32_t *rec_slot, int32_t *fail)
 {
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
-    const int64_t p0 = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + (int64_t)threadIdx.x * kInsertPP;
-    const int64_t pend = tm.seg_end[s];
+    const int64_t r = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
+    if (r >= tm.seg_end[s]) return;
+    uint64_t key[KW];
+#pragma unroll
+    for (int w = 0; w < KW; ++w) key[w] = rec_key[(size_t)w * R + r];
     const SetTable st = tables[s];
-    uint64_t pk[D][KW];
-    uint32_t ps[D];
+    uint32_t h = hash_key<KW>(key, 0u) & st.mask;
+    const uint32_t limit = min(st.mask + 1u, kMaxProbe);
+    for (uint32_t n = 0; n < limit; ++n) {
+        const size_t slot = st.slot_base + h;
+        uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
+        bool mine = (o == kOwnerEmpty);
+        if (!mine) {
+            mine = true;
 #pragma unroll
-    for (int v = 0; v < D; ++v) {
-#pragma unroll
-        for (int w = 0; w < KW; ++w) pk[v][w] = kKeyEmpty;
-        ps[v] = 0;
+            for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
+        }
+        if (mine) {
+            rec_slot[r] = (uint32_t)slot;
+            return;
+        }
+        h = (h + 1) & st.mask;
     }
-    for (int q = 0; q < kInsertPP; ++q) {
-        const int64_t p = p0 + q;
-        if (p >= pend) break;
-        uint64_t key[D][KW];
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) key[v][w] = rec_key[(size_t)w * R + (size_t)p * D + v];
-        }
-        uint32_t slot[D];
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-            bool known = false;
-            uint32_t sl = 0;
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const bool eq = key_equal<KW>(key[v], pk[u]);
-                sl = eq ? ps[u] : sl;
-                known = known || eq;
-            }
-            if (!known) {
-                sl = insert_key<KW>(st, key[v], (uint32_t)((size_t)p * D + v), rec_key, R, own);
-                if (sl == kOwnerEmpty) atomicOr(fail, 1);
-            }
-            rec_slot[(size_t)p * D + v] = sl;
-            slot[v] = sl;
-        }
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) pk[v][w] = key[v][w];
-            ps[v] = slot[v];
-        }
-    }
+    atomicOr(fail, 1);
 }
 
 // flag[r] = 1 if record r owns its slot (the first record of its vertex to claim it).
@@ -642,9 +594,6 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     std::vector<int64_t> roff(S + 1);
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm));
-    DevBuf itmap;
-    TileMap itm{};
-    FR_TRY(make_offset_map(ctx, poff, 256 * kInsertPP, st, itmap, itm));
     uint64_t n1 = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<SetTable> t1(S);
@@ -663,10 +612,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         FR_HIP(hipMemcpyAsync(t1_d.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
         FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
-        if (itm.n_tiles > 0) {
-            k_insert_records<KW, D><<<itm.n_tiles, 256, 0, st>>>(itm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(),
-                                                                 R, own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
-                                                                 fail.as<int32_t>());
+        if (rtm.n_tiles > 0) {
+            k_insert_records<KW><<<rtm.n_tiles, 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
+                                                              own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
+                                                              fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
         int32_t failed = 0;
