@@ -292,8 +292,7 @@ def other_workloads(fr, ctx, reps=5):
         return fr.fr_register_articulated(ctx.h, m, p.extra["body_offsets"], o, kt, prm, th)
     ms, (st, rep) = _timed(art, reps)
     out["articulated_pt2pl"] = {"model_points": len(p.model), "obs_points": len(p.obs), "bodies": 20, "dof": 32,
-                                "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
-                                "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches)}
+                                "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms}
     # node graph: 100k points, 512 nodes, 20 iterations
     p = synth.nodegraph_pair(0)
     e = p.extra
@@ -307,7 +306,6 @@ def other_workloads(fr, ctx, reps=5):
     ms, (st, rep) = _timed(ngr, 3)
     out["nodegraph_pt2pt"] = {"model_points": len(p.model), "obs_points": len(p.obs), "nodes": len(e["nodes"]),
                               "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
-                              "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches),
                               "pcg_iters_last": rep.solver_iters}
     return out
 
@@ -336,6 +334,7 @@ def main():
     ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    ap.add_argument("--no-other", action="store_true", help="skip the single-pair workloads and build rates")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-slots", type=int, default=1024)
     ap.add_argument("--serve-arena", type=int, default=64 << 20)
@@ -447,9 +446,10 @@ def main():
             "mean_launch_ms": est_avg_s * 1e3,
         },
     }
-    log("other workloads and build rates ...")
-    out["other_workloads"] = other_workloads(fr, ctx)
-    out["build"] = build_rates(fr, ctx, obs, sigma, sigma_n)
+    if not args.no_other:
+        log("other workloads and build rates ...")
+        out["other_workloads"] = other_workloads(fr, ctx)
+        out["build"] = build_rates(fr, ctx, obs, sigma, sigma_n)
     if not args.no_serve:
         out["serving"] = serve_bench(fr, ctx, args)
         h = out["serving"]["headline"]
