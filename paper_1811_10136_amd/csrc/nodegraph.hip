@@ -24,12 +24,16 @@
 #include <cmath>
 #include <cstring>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "fr_internal.h"
 
 namespace fr {
 
 constexpr int kNgThreads = 256;
 constexpr int kPcgThreads = 1024;
+constexpr int kCoopThreads = 128;      // threads per workgroup of the grid-wide PCG
+constexpr int kCoopMaxBlocks = 32;
 
 // --- dual quaternions (w, x, y, z) --------------------------------------------
 __device__ inline void qmul4(const double *a, const double *b, double *o)
@@ -417,6 +421,154 @@ __global__ void __launch_bounds__(kPcgThreads) k_ng_pcg(int32_t K, const int32_t
     }
 }
 
+// The same block-Jacobi PCG spread over G workgroups of one cooperative
+// launch: workgroup g owns a contiguous range of nodes (their rows of A, x, r,
+// z, p, q); the two dot products of an iteration are summed per workgroup in a
+// fixed order, exchanged through `part` and added in workgroup order after a
+// grid-wide barrier, so every workgroup takes the same decisions and the
+// result is reproducible.  Three barriers per iteration.
+struct PcgArgs {
+    int32_t K;
+    const int32_t *row_off, *row_blk, *row_col;
+    const double *A, *minv, *rhs;
+    double *x, *r, *z, *p, *q;
+    double *part;           // 2 x 3 x gridDim.x partial sums
+    double tol;
+    int32_t max_it;
+    double *info;
+};
+
+__device__ double coop_block_sum(double v, double *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kCoopThreads / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+__global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
+{
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    __shared__ double red[kCoopThreads / 64];
+    __shared__ double lanes[kCoopThreads];
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const int kb = (a.K + G - 1) / G;
+    const int k0 = min(a.K, g * kb), k1 = min(a.K, k0 + kb);
+    const int u0 = 6 * k0, u1 = 6 * k1, R = u1 - u0;
+    const int L = R > 0 ? max(1, min(8, kCoopThreads / R)) : 1;   // lanes per SpMV row
+    // grid-wide sums of n (1 or 2) values per workgroup through partial arrays
+    // slot, slot + 1 (of 6: a slot is written again only two iterations later,
+    // after every workgroup has passed further barriers)
+    auto grid_sum = [&](int n, double v0, double v1, int slot, double &s0, double &s1) {
+        const double b0 = coop_block_sum(v0, red);
+        const double b1 = n > 1 ? coop_block_sum(v1, red) : 0.0;
+        if (tid == 0) {
+            a.part[slot * G + g] = b0;
+            if (n > 1) a.part[(slot + 1) * G + g] = b1;
+        }
+        __threadfence();
+        grid.sync();
+        s0 = 0.0;
+        s1 = 0.0;
+        for (int b = 0; b < G; ++b) {
+            s0 += a.part[slot * G + b];
+            if (n > 1) s1 += a.part[(slot + 1) * G + b];
+        }
+    };
+    auto precond = [&]() {
+        for (int u = u0 + tid; u < u1; u += kCoopThreads) {
+            const int k = u / 6, c = u % 6;
+            const double *Mi = a.minv + 36 * k;
+            double v = 0.0;
+            for (int b = 0; b < 6; ++b) v += Mi[6 * c + b] * a.r[6 * k + b];
+            a.z[u] = v;
+        }
+    };
+    double bb = 0.0;
+    for (int u = u0 + tid; u < u1; u += kCoopThreads) {
+        a.x[u] = 0.0;
+        a.r[u] = -a.rhs[u];
+        bb += a.rhs[u] * a.rhs[u];
+    }
+    __syncthreads();   // the preconditioner reads the r of a node's six rows, written by other threads
+    precond();
+    double rz_loc = 0.0;
+    for (int u = u0 + tid; u < u1; u += kCoopThreads) {
+        a.p[u] = a.z[u];
+        rz_loc += a.r[u] * a.z[u];
+    }
+    double bnorm2, rz;
+    grid_sum(2, bb, rz_loc, 0, bnorm2, rz);
+    const double bnorm = sqrt(bnorm2);
+    int it = 0;
+    double rel = bnorm > 0.0 ? 1.0 : 0.0;
+    while (it < a.max_it && bnorm > 0.0) {
+        const int par = (it & 1) ? 3 : 0;   // partial slots of this iteration
+        grid.sync();   // p of every workgroup is complete
+        // q = A p for the owned rows, L lanes per row summing every L-th entry
+        double pq_loc = 0.0;
+        for (int r0 = 0; r0 < R; r0 += kCoopThreads / L) {
+            const int row = r0 + tid / L, lane = tid % L;
+            double acc = 0.0;
+            const bool on = tid / L < kCoopThreads / L && row < R;
+            if (on) {
+                const int u = u0 + row, k = u / 6, c = u % 6;
+                for (int e = a.row_off[k] + lane; e < a.row_off[k + 1]; e += L) {
+                    const int ref = a.row_blk[e];
+                    const double *B = a.A + (size_t)36 * (ref >> 1);
+                    const double *pl = a.p + 6 * a.row_col[e];
+                    if (!(ref & 1))
+                        for (int b = 0; b < 6; ++b) acc += B[6 * c + b] * pl[b];
+                    else
+                        for (int b = 0; b < 6; ++b) acc += B[6 * b + c] * pl[b];
+                }
+            }
+            lanes[tid] = acc;
+            __syncthreads();
+            if (on && lane == 0) {
+                double y = 0.0;
+                for (int l = 0; l < L; ++l) y += lanes[tid + l];
+                const int u = u0 + row;
+                a.q[u] = y;
+                pq_loc += a.p[u] * y;
+            }
+            __syncthreads();
+        }
+        double pq, unused;
+        grid_sum(1, pq_loc, 0.0, par, pq, unused);
+        if (!(pq > 0.0)) break;
+        const double alpha = rz / pq;
+        double rr_loc = 0.0;
+        for (int u = u0 + tid; u < u1; u += kCoopThreads) {
+            a.x[u] += alpha * a.p[u];
+            a.r[u] -= alpha * a.q[u];
+            rr_loc += a.r[u] * a.r[u];
+        }
+        __syncthreads();
+        precond();
+        double rzn_loc = 0.0;
+        for (int u = u0 + tid; u < u1; u += kCoopThreads) rzn_loc += a.r[u] * a.z[u];
+        double rr, rz_new;
+        grid_sum(2, rr_loc, rzn_loc, par + 1, rr, rz_new);
+        ++it;
+        rel = sqrt(rr) / bnorm;
+        if (rel <= a.tol) break;
+        const double beta = rz_new / rz;
+        rz = rz_new;
+        for (int u = u0 + tid; u < u1; u += kCoopThreads) a.p[u] = a.z[u] + beta * a.p[u];
+    }
+    if (g == 0 && tid == 0) {
+        a.info[0] = it;
+        a.info[1] = rel;
+    }
+}
+
 // Inverse of each diagonal 6x6 block by Gauss-Jordan with partial pivoting
 // (blocks are SPD); flags a non-positive pivot.
 __global__ void k_ng_block_inverse(int32_t K, const double *A, const int32_t *diag_blk, double *minv, int32_t *bad)
@@ -524,7 +676,19 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
                 ent.push_back({(int64_t)k * K + l, (int32_t)i, w[a] * w[c]});
             }
     }
-    std::stable_sort(ent.begin(), ent.end(), [](const Ent &x, const Ent &y) { return x.key < y.key; });
+    // group the entries by block key, keeping point order inside a block: a
+    // counting sort over the K x K keys when that table is small, else a
+    // stable sort
+    if ((int64_t)K * K <= ((int64_t)1 << 24)) {
+        std::vector<int32_t> cnt((size_t)K * K + 1, 0);
+        for (const Ent &e : ent) ++cnt[(size_t)e.key + 1];
+        for (size_t q = 1; q < cnt.size(); ++q) cnt[q] += cnt[q - 1];
+        std::vector<Ent> sorted(ent.size());
+        for (const Ent &e : ent) sorted[(size_t)cnt[(size_t)e.key]++] = e;
+        ent.swap(sorted);
+    } else {
+        std::stable_sort(ent.begin(), ent.end(), [](const Ent &x, const Ent &y) { return x.key < y.key; });
+    }
     std::vector<int64_t> keys;
     std::vector<int32_t> data_off;   // per block offsets into ent
     for (size_t e = 0; e < ent.size(); ++e)
@@ -572,20 +736,24 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     std::vector<int32_t> roff(K + 1, 0), rpts;
     std::vector<float> rw;
     {
-        std::vector<std::vector<std::pair<int32_t, float>>> per(K);
+        // counting sort of (point, weight) by node, point order kept
         for (int64_t i = 0; i < M; ++i)
             for (int a = 0; a < 4; ++a) {
                 const int32_t k = g->skin_idx[4 * i + a];
-                if (k >= 0 && k < K) per[k].push_back({(int32_t)i, g->skin_w[4 * i + a]});
+                if (k >= 0 && k < K) ++roff[k + 1];
             }
-        for (int32_t k = 0; k < K; ++k) {
-            roff[k] = (int32_t)rpts.size();
-            for (auto &pw : per[k]) {
-                rpts.push_back(pw.first);
-                rw.push_back(pw.second);
+        for (int32_t k = 0; k < K; ++k) roff[k + 1] += roff[k];
+        rpts.resize(roff[K]);
+        rw.resize(roff[K]);
+        std::vector<int32_t> fill(roff.begin(), roff.end() - 1);
+        for (int64_t i = 0; i < M; ++i)
+            for (int a = 0; a < 4; ++a) {
+                const int32_t k = g->skin_idx[4 * i + a];
+                if (k >= 0 && k < K) {
+                    rpts[fill[k]] = (int32_t)i;
+                    rw[fill[k]++] = g->skin_w[4 * i + a];
+                }
             }
-        }
-        roff[K] = (int32_t)rpts.size();
     }
     // regulariser references per block and per node (edge order)
     std::vector<std::vector<int32_t>> breg(NB), nreg(K);
@@ -679,7 +847,7 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     const size_t n = 6 * (size_t)K;
     FR_TRY(d.work.alloc(ctx, sizeof(double) * (12 * (size_t)K + 8 * (size_t)K + 21 * (size_t)NB + 6 * (size_t)K +
                                                120 * (size_t)std::max(E, 1) + 36 * (size_t)NB + 36 * (size_t)K +
-                                               6 * n + 2 + 8) +
+                                               6 * n + 2 + 8 + 6 * (size_t)kCoopMaxBlocks) +
                                 sizeof(float) * 27 * (size_t)std::max<int64_t>(M, 1) + sizeof(int32_t) * 4));
     double *w = d.work.as<double>();
     d.T = w;
@@ -710,6 +878,8 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     w += n;
     d.info = w;
     w += 8;
+    d.part = w;
+    w += 6 * (size_t)kCoopMaxBlocks;
     d.terms = reinterpret_cast<float *>(w);
     d.bad = reinterpret_cast<int32_t *>(d.terms + 27 * (size_t)std::max<int64_t>(M, 1));
     return FR_OK;
@@ -758,9 +928,30 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
     FR_HIP(hipMemsetAsync(d.bad, 0, sizeof(int32_t), st));
     k_ng_block_inverse<<<(d.K + 63) / 64, 64, 0, st>>>(d.K, d.A, d.diag_blk, d.minv, d.bad);
     FR_HIP(hipGetLastError());
-    k_ng_pcg<<<1, kPcgThreads, 0, st>>>(d.K, d.row_off, d.row_blk, d.row_col, d.A, d.minv, d.rhs, d.x, d.r, d.z, d.p,
-                                        d.q, tol, max_it, d.info);
-    FR_HIP(hipGetLastError());
+    // grid-wide PCG when the device can hold the workgroups of one cooperative
+    // launch at once, else the single-workgroup kernel
+    int per_cu = 0, dev = 0, cus = 0, coop = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_ng_pcg_coop),
+                                                        kCoopThreads, 0);
+    (void)hipGetLastError();
+    const int G = std::min({kCoopMaxBlocks, std::max(1, d.K / 4), per_cu * cus});
+    bool done = false;
+    if (coop && G >= 8) {
+        PcgArgs pa{d.K, d.row_off, d.row_blk, d.row_col, d.A, d.minv, d.rhs, d.x, d.r, d.z, d.p, d.q, d.part,
+                   tol, max_it, d.info};
+        void *args[] = {&pa};
+        done = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_ng_pcg_coop), dim3(G), dim3(kCoopThreads),
+                                          args, 0, st) == hipSuccess;
+        if (!done) (void)hipGetLastError();
+    }
+    if (!done) {
+        k_ng_pcg<<<1, kPcgThreads, 0, st>>>(d.K, d.row_off, d.row_blk, d.row_col, d.A, d.minv, d.rhs, d.x, d.r, d.z,
+                                            d.p, d.q, tol, max_it, d.info);
+        FR_HIP(hipGetLastError());
+    }
     k_ng_update<<<(d.K + 63) / 64, 64, 0, st>>>(d.K, d.x, d.T);
     FR_HIP(hipGetLastError());
     return FR_OK;
