@@ -374,9 +374,10 @@ fr_status fr_engine_admit(fr_engine *eng, int32_t n, const int32_t *slots_h, con
 fr_status fr_engine_step(fr_engine *eng, int32_t n, const int32_t *slots_h);
 
 /* Enqueue a copy of every slot's pose (max_slots x 16 float64, row-major) and
- * status (max_slots int32: FR_OK or FR_EDEGENERATE of its last solve) into
- * host memory; pinned host memory makes it asynchronous.  Returns FR_ERANGE
- * (and clears it) if an E-step saw a lattice coordinate out of range. */
+ * status (max_slots int32: FR_OK or FR_EDEGENERATE of its last solve, or
+ * FR_ERANGE if one of its E-steps saw a lattice coordinate out of range; the
+ * flag is cleared when the slot is admitted again) into host memory; pinned
+ * host memory makes it asynchronous. */
 fr_status fr_engine_read(fr_engine *eng, double *poses_h, int32_t *status_h);
 
 /* Free n slots.  Their arena ranges may be admitted again at once; a lattice

@@ -13,9 +13,7 @@
 
 namespace fr {
 
-constexpr int kRedThreads = 256;
-constexpr int kRedPerThread = 4;
-constexpr int kRedTile = kRedThreads * kRedPerThread;
+constexpr int kRedThreads = 256;   // a tile of 1024 points: 4 per thread
 struct ReduceArgs {
     const float *x, *y, *z;
     const float *mats;

@@ -17,7 +17,9 @@
 //   k_ng_blocks      per block: ordered binary64 sums over its point list
 //   k_ng_edges       per edge: regulariser blocks and right-hand sides
 //   k_ng_assemble    per block / node: data + regulariser in fixed order
-//   k_ng_pcg         one workgroup: block-Jacobi PCG to a relative residual
+//   k_ng_pcg_coop    block-Jacobi PCG to a relative residual over the
+//                    workgroups of one cooperative launch (k_ng_pcg: the same
+//                    in one workgroup, where cooperative launch is unavailable)
 //   k_ng_update      per node: Exp(dzeta_k) T_k and the binary32 copy
 // All sums run in a fixed order, so results are bitwise reproducible.
 #include <algorithm>
