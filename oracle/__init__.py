@@ -106,12 +106,15 @@ def embed(feat_rows: np.ndarray, k: np.ndarray):
     return keys, b, e
 
 
-def splat_values(points: np.ndarray, normals: Optional[np.ndarray], residual: str) -> np.ndarray:
-    """Per-observation values v_y of Eq. (11): [1, y] (Eq. 6) or [1, y, n_y] (Eq. 9)."""
+def splat_values(points: np.ndarray, normals: Optional[np.ndarray], residual: str, m2: bool = False) -> np.ndarray:
+    """Per-observation values v_y of Eq. (11): [1, y] (Eq. 6) or [1, y, n_y] (Eq. 9); with m2 a last
+    column |y|^2, the second moment the optimised variance of Sec. 3.3 needs."""
     y = np.asarray(points, dtype=np.float64)
     cols = [np.ones((len(y), 1)), y]
     if residual == "pt2pl":
         cols.append(np.asarray(normals, dtype=np.float64))
+    if m2:
+        cols.append(np.sum(y * y, axis=1, keepdims=True))
     return np.ascontiguousarray(np.concatenate(cols, axis=1))
 
 
@@ -192,12 +195,15 @@ def pose_to_mat12(T: np.ndarray) -> np.ndarray:
 # E-step (Eq. 6, 8, 9) through the lattice
 # ---------------------------------------------------------------------------
 
-def estep(lat: Lattice, x32: np.ndarray, n32: Optional[np.ndarray], feat: int, residual: str):
-    """M0 (M,), M1 (M,3) and, for point-to-plane, the un-normalised normal sum (M,3)."""
+def estep(lat: Lattice, x32: np.ndarray, n32: Optional[np.ndarray], feat: int, residual: str, m2: bool = False):
+    """M0 (M,), M1 (M,3) and, for point-to-plane, the un-normalised normal sum (M,3); with m2 (a lattice
+    built from splat_values(..., m2=True)) also M2 = sum_k K |y_k|^2 (M,) as a fourth result."""
     g = lattice_slice(lat, features(x32, n32, feat))
     m0 = g[:, 0].copy()
     m1 = g[:, 1:4].copy()
     ns = g[:, 4:7].copy() if residual == "pt2pl" else None
+    if m2:
+        return m0, m1, ns, g[:, -1].copy()
     return m0, m1, ns
 
 
@@ -278,7 +284,7 @@ def normal_equations(x, m0, m1, nsum, c, sigma, residual, normalize_n=False):
 
 
 def per_point_jtj(x, m0, m1, nsum, c, sigma, residual, normalize_n=False):
-    """Per-point w J^T J (M, 6, 6) and w J^T r (M, 6): the summands of Alg. 1, lines 1-4."""
+    """Per-point w J^T J (M, 6, 6) and w J^T r (M, 6): the per-point summands of Alg. 1."""
     w, r, J, _ = residuals_and_jacobians(x, m0, m1, nsum, c, sigma, residual, normalize_n)
     return np.einsum("i,ikp,ikq->ipq", w, J, J), np.einsum("i,ikp,ik->ip", w, J, r)
 
@@ -358,6 +364,67 @@ def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
     return T
+
+
+def variance_terms(x, m0, m1, m2, c):
+    """The two sums of the optimised isotropic variance (Sec. 3.3, sigma as a decision variable, in the
+    closed form of the Coherent Point Drift M-step): with the posterior P_ik = K_ik / (M0_i + c) of
+    Eq. (4)-(5),
+        sum_ik P_ik |x_i - y_k|^2 = sum_i (M0_i |x_i|^2 - 2 x_i . M1_i + M2_i) / (M0_i + c),
+        sum_ik P_ik               = sum_i M0_i / (M0_i + c),
+    and sigma^2 = first / (3 * second).  Points with M0 = 0 contribute nothing."""
+    x = np.asarray(x, dtype=np.float64)
+    m0 = np.asarray(m0, dtype=np.float64)
+    sup = m0 > 0
+    den = np.where(sup, m0 + c, 1.0)
+    num = m0 * np.sum(x * x, axis=1) - 2.0 * np.sum(x * np.asarray(m1, dtype=np.float64), axis=1) + \
+        np.asarray(m2, dtype=np.float64)
+    return float(np.sum(np.where(sup, num / den, 0.0))), float(np.sum(np.where(sup, m0 / den, 0.0)))
+
+
+# Per-axis variance of the lattice's kernel K(x, y) = sum_v b_v(x) b_v(y) (splat and slice, no blur)
+# in units of the lattice scale s squared.  Derivation: the piecewise-linear hat of one lattice vertex
+# has, in the lattice's own coordinates (the (d+1)-scaled A*_d lattice), a second moment of trace
+# d (d+1)^2 / 12 spread evenly over the d directions; averaged over positions the kernel is the hat's
+# autocorrelation over the volume per vertex, whose second moment is twice the hat's, (d+1)^2 / 6 per
+# direction; the embedding maps a position offset of length r to (d+1) sqrt(2/3) r / s.  Hence
+# (d+1)^2 / 6 * s^2 * 3 / (2 (d+1)^2) = s^2 / 4 for every d.
+LATTICE_KERNEL_AXIS_VAR = 0.25
+
+
+def register_rigid_sigma(model, model_n, obs, obs_n, *, feat, residual, sigma0, sigma_min, sigma_n=0.5, w=0.1,
+                         iters=20, T0=None, history: Optional[list] = None):
+    """Rigid FilterReg with sigma updated every EM iteration (Sec. 3.3 optimised variance; Tab. 1
+    "updated sigma").  sigma is the lattice scale s, as everywhere in this module; the lattice filters
+    with a kernel of per-axis variance s^2 / 4 (LATTICE_KERNEL_AXIS_VAR), so the Gaussian of Eq. (5) it
+    stands for has variance s^2 / 4.  Each iteration builds the lattice at the current s (the index
+    depends on it, Sec. 3.1), takes the E-step at the pose and one Gauss-Newton step; the closed form
+    then gives that Gaussian's variance from the same E-step and pose, variance_terms first / (3 second),
+    and s^2 <- it / LATTICE_KERNEL_AXIS_VAR, floored at sigma_min.  c of Eq. (7) follows s as in the
+    fixed-sigma loop.  Returns (pose, s)."""
+    T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
+    sig = float(sigma0)
+    model = np.asarray(model, dtype=np.float32)
+    for _ in range(iters):
+        sv = [sig, sig, sig]
+        lat = lattice_build(features(obs, obs_n, feat), splat_values(obs, obs_n, residual, m2=True),
+                            scale_factors(feature_sigmas(feat, sv, sigma_n)))
+        c = outlier_constant(w, len(obs), len(model), sv)
+        mat = pose_to_mat12(T)
+        x32 = transform_f32(mat, model)
+        n32 = transform_f32(mat, model_n, translate=False) if feat == 6 else None
+        m0, m1, ns, m2 = estep(lat, x32, n32, feat, residual, m2=True)
+        R32 = mat.reshape(3, 4).astype(np.float64)
+        x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
+        A, b, stats = normal_equations(x64, m0, m1, ns, c, sig, residual)
+        dz = gn_step(A, b)
+        T = se3_exp(dz) @ T
+        vs, ws = variance_terms(x64, m0, m1, m2, c)
+        if ws > 0:
+            sig = max(sigma_min, math.sqrt(max(vs / (3.0 * ws), 0.0) / LATTICE_KERNEL_AXIS_VAR))
+        if history is not None:
+            history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy(), sigma=sig, var=vs, sum_w=ws))
+    return T, sig
 
 
 def alignment_error(T, T_gt, x_ref) -> float:

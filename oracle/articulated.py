@@ -13,7 +13,7 @@ Twists use the convention of Eq. 16 (x_new = x + w x x + v).  A unit change of
 DOF k rotates every descendant of its joint about the world axis w_k through
 the world point q_k, i.e. the twist (w_k, q_k x w_k); these columns form the
 spatial velocity Jacobian of each body (dzeta_b / dtheta).  Alg. 1 sums the
-per-point J^T J of each body (lines 1-4) and then A = sum_b J_sp,b^T (J^TJ)_b J_sp,b.
+per-point J^T J of each body and then A = sum_b J_sp,b^T (J^TJ)_b J_sp,b.
 """
 from __future__ import annotations
 
@@ -96,7 +96,7 @@ def pose_points(tree: Tree, theta, x_ref, body_offsets):
 
 
 def normal_equations_alg1(tree, theta, x, body_offsets, m0, m1, ns, c, sigma, residual):
-    """Alg. 1: per-body sums of J^T J and J^T r (lines 1-4), then A = sum_b J_sp^T (J^TJ)_b J_sp."""
+    """Alg. 1: per-body sums of J^T J and J^T r, then A = sum_b J_sp^T (J^TJ)_b J_sp."""
     from . import per_point_jtj
     JtJ, Jtr = per_point_jtj(x, m0, m1, ns, c, sigma, residual)
     Jsp = spatial_jacobians(tree, theta)
