@@ -48,7 +48,8 @@ enum {
 };
 
 enum { FR_FEAT_POS = 3, FR_FEAT_POS_NORMAL = 6 };         /* feature dimension d */
-enum { FR_VAL_PT2PT = 4, FR_VAL_PT2PL = 7 };              /* value channels V of the lattice */
+/* value channels V of the lattice: [1, y], [1, y, n_y]; the _M2 layouts add |y|^2 (variance update) */
+enum { FR_VAL_PT2PT = 4, FR_VAL_PT2PT_M2 = 5, FR_VAL_PT2PL = 7, FR_VAL_PT2PL_M2 = 8 };
 enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
 enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
 enum { FR_PT2PT = 0, FR_PT2PL = 1 };
@@ -90,7 +91,7 @@ typedef struct {
  */
 typedef struct {
     int32_t feat;          /* FR_FEAT_POS or FR_FEAT_POS_NORMAL */
-    int32_t values;        /* FR_VAL_PT2PT or FR_VAL_PT2PL */
+    int32_t values;        /* FR_VAL_PT2PT, FR_VAL_PT2PL or their _M2 layouts */
     double sigma[3];       /* > 0 */
     double sigma_n;        /* > 0 when feat == 6 */
     int32_t splat;         /* FR_SPLAT_SORTED: bitwise deterministic; FR_SPLAT_ATOMIC: float atomics */
@@ -102,7 +103,7 @@ typedef struct {
  * observation when the variance is fixed; Sec. 4.2: splat of the
  * permutohedral filter, no blur).  Each observation point adds b_k * value to
  * the d+1 vertices of its enclosing simplex; occupancy counts incidences.
- * Normals are required when feat == 6 or values == FR_VAL_PT2PL.
+ * Normals are required when feat == 6 or values is FR_VAL_PT2PL(_M2).
  * Synchronises once with the stream (vertex counts size the tables).
  * A set with no points gets an empty lattice.  On success *out owns all
  * device memory of the lattice (charged to ctx).
@@ -151,6 +152,21 @@ typedef struct {
  */
 fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
                    float *nsum, void *stream);
+
+/*
+ * fr_estep on a lattice built with a |y|^2 channel (values FR_VAL_PT2PT_M2 or
+ * FR_VAL_PT2PL_M2): also m2 (device, M float32), the second moment about the
+ * target t_i = M1_i / M0_i,
+ *   m2_i = sum_k K(x_i, y_k) |y_k - t_i|^2  (= M2_i - |M1_i|^2 / M0_i, 0 without support),
+ * which the variance update of Sec. 3.3 (optimised variance, the closed form
+ * of the Coherent Point Drift M-step) needs next to M0 and M1.  Each vertex
+ * keeps the scatter of its observations about its own mean, so the result
+ * is not a difference of |y|^2-sized binary32 numbers.  nsum is written for
+ * FR_VAL_PT2PL_M2.  fr_lattice_export returns that per-vertex scatter as the
+ * last channel.  FR_EINVAL on a lattice without the channel.
+ */
+fr_status fr_estep_m2(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
+                      float *nsum, float *m2, void *stream);
 
 /*
  * Diagnostic: number of distinct lattice vertices the E-step of set `set`
@@ -238,6 +254,31 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                       double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
 
 /*
+ * Rigid registration with an optimised isotropic variance per set (Sec. 3.3,
+ * Sigma_xyz = sigma^2 I as a decision variable; Tab. 1 "updated sigma").  The
+ * closed form is that of the Coherent Point Drift M-step: with the posterior
+ * P_ik = K(x_i, y_k) / (M0_i + c) of Eq. 4-5,
+ *   var = sum_ik P_ik |x_i - y_k|^2 / (3 sum_ik P_ik)
+ *       = sum_i w_i (|x_i - t_i|^2 + m2_i / M0_i) / (3 sum_i w_i)
+ * (t_i and m2_i as in fr_estep_m2), evaluated at the pose the E-step used.  sigma here is the lattice scale s,
+ * as in fr_lattice_params; the splat/slice kernel of scale s has per-axis
+ * variance s^2 / 4, so the Gaussian it stands for has variance s^2 / 4 and the
+ * update is s^2 <- 4 var, floored at sigma_min.  The lattice depends on s, so
+ * every iteration rebuilds it from `obs` with each set's s (the normal
+ * features keep lattice.sigma_n), and c of Eq. 7 follows s as in fr_register.
+ * params->lattice.values must be FR_VAL_PT2PT_M2 for FR_PT2PT and
+ * FR_VAL_PT2PL_M2 for FR_PT2PL; lattice.sigma is not used (it must still be
+ * valid); FR_FUSED is rejected.  sigma_inout_h (host, n_sets float64, > 0)
+ * holds the start scales and receives the scale each set would use next.
+ * theta_inout_h, status_h, report_h and the return value as fr_register
+ * (report_h->build_ms sums the rebuilds, em_ms excludes them).  Synchronises
+ * every iteration.
+ */
+fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs,
+                            const fr_register_params *params, double sigma_min, double *theta_inout_h,
+                            double *sigma_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
+
+/*
  * Kinematic tree of an articulated model (Sec. 5.1).  Body b (0 <= b < n_bodies)
  * hangs from parent[b] < b (-1 = world) at the joint origin origin[3b..3b+2]
  * given in the parent's frame, and owns the revolute DOFs
@@ -255,8 +296,8 @@ typedef struct {
 } fr_kinematic_tree;
 
 /*
- * Articulated Gauss-Newton step on the device in binary64 (Eq. 19-20, Alg. 1
- * lines 5-9): given per-body sums jtj (device, n_bodies x 21, upper triangle
+ * Articulated Gauss-Newton step on the device in binary64 (Eq. 19-20, the
+ * assembly and solve of Alg. 1): given per-body sums jtj (device, n_bodies x 21, upper triangle
  * row-major) and jtr (device, n_bodies x 6) from fr_mstep_reduce segmented by
  * body at the current angles, builds the spatial velocity Jacobian of every
  * body by forward kinematics (DOF k moves the bodies below its joint with the

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # --- constants (include/filterreg.h) ----------------------------------------
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EBUDGET, FR_ERANGE, FR_EDEGENERATE, FR_EDEVICE = range(7)
 FR_FEAT_POS, FR_FEAT_POS_NORMAL = 3, 6
-FR_VAL_PT2PT, FR_VAL_PT2PL = 4, 7
+FR_VAL_PT2PT, FR_VAL_PT2PT_M2, FR_VAL_PT2PL, FR_VAL_PT2PL_M2 = 4, 5, 7, 8
 FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
 FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
@@ -125,6 +125,7 @@ _sig("fr_lattice_stats", _st, [_P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.
                                ctypes.POINTER(ctypes.c_int64)])
 _sig("fr_lattice_export", _st, [_P, _i32, _P, _P, _P])
 _sig("fr_estep", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P, _P])
+_sig("fr_estep_m2", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P, _P, _P])
 _sig("fr_estep_touched", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _i32,
                                ctypes.POINTER(ctypes.c_int64)])
 _sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
@@ -132,6 +133,9 @@ _sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform)
 _sig("fr_solve_rigid", _st, [_i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("fr_register", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
                           ctypes.POINTER(fr_register_params), _P, _P, ctypes.POINTER(fr_report), _P])
+_sig("fr_register_sigma", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
+                                ctypes.POINTER(fr_register_params), ctypes.c_double, _P, _P, _P,
+                                ctypes.POINTER(fr_report), _P])
 _sig("fr_sync_status", _st, [_P])
 _sig("fr_articulated_step", _st, [_P, ctypes.POINTER(fr_kinematic_tree), _P, _P, _P, _P, _P, _P])
 _sig("fr_register_nodegraph", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
@@ -149,7 +153,8 @@ _sig("fr_engine_release", _st, [_P, _i32, _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
-                 "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register", "fr_sync_status",
+                 "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
+                 "fr_register_sigma", "fr_sync_status",
                  "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph",
                  "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
                  "fr_engine_release"]
@@ -295,6 +300,10 @@ def fr_estep(lat, model: Cloud, xf: XForm, m0, m1, nsum=None, stream=None):
     _check(_lib.fr_estep(lat, model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), _stream(stream)))
 
 
+def fr_estep_m2(lat, model: Cloud, xf: XForm, m0, m1, nsum, m2, stream=None):
+    _check(_lib.fr_estep_m2(lat, model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), _ptr(m2), _stream(stream)))
+
+
 def fr_estep_touched(lat, model: Cloud, xf: XForm, set_index: int = 0) -> int:
     n = ctypes.c_int64()
     _check(_lib.fr_estep_touched(lat, model.c(), xf.c(), set_index, ctypes.byref(n)))
@@ -327,6 +336,22 @@ def fr_register(ctx, model: Cloud, obs: Cloud, params: fr_register_params, theta
     st = _lib.fr_register(ctx, model.c(), obs.c(), ctypes.byref(params), th.ctypes.data, status.ctypes.data,
                           ctypes.byref(rep), _stream(stream))
     theta[...] = th
+    if st not in (FR_OK, FR_EDEGENERATE):
+        _check(st)
+    return status, rep
+
+
+def fr_register_sigma(ctx, model: Cloud, obs: Cloud, params: fr_register_params, sigma_min: float,
+                      theta: np.ndarray, sigma: np.ndarray, stream=None):
+    """theta: (n_sets, 4, 4) and sigma: (n_sets,) float64, updated in place.  Returns (status, report)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    status = np.zeros(model.n_sets, np.int32)
+    rep = fr_report()
+    st = _lib.fr_register_sigma(ctx, model.c(), obs.c(), ctypes.byref(params), float(sigma_min), th.ctypes.data,
+                                sg.ctypes.data, status.ctypes.data, ctypes.byref(rep), _stream(stream))
+    theta[...] = th
+    sigma[...] = sg
     if st not in (FR_OK, FR_EDEGENERATE):
         _check(st)
     return status, rep
@@ -395,10 +420,13 @@ def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
 
 
 def register_params(feat: int, residual: str, sigma, sigma_n=0.5, iters=20, w=0.1, c=None, tol=1e-6,
-                    fixed=True, profile=False, splat=FR_SPLAT_SORTED, fused=False) -> fr_register_params:
+                    fixed=True, profile=False, splat=FR_SPLAT_SORTED, fused=False,
+                    m2=False) -> fr_register_params:
     res = FR_PT2PL if residual == "pt2pl" else FR_PT2PT
     vals = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
     flags = (FR_FIXED_ITERS if fixed else 0) | (FR_PROFILE_EVENTS if profile else 0) | (FR_FUSED if fused else 0)
+    if m2:
+        vals = FR_VAL_PT2PL_M2 if residual == "pt2pl" else FR_VAL_PT2PT_M2
     return fr_register_params(lattice_params(feat, vals, sigma, sigma_n, splat), res, iters, float(w),
                               -1.0 if c is None else float(c), float(tol), flags, FR_KIN_RIGID)
 
@@ -409,6 +437,17 @@ def register(ctx: Context, model: Cloud, obs: Cloud, params: fr_register_params,
     theta = np.repeat(np.eye(4)[None], S, 0) if T0 is None else np.array(T0, dtype=np.float64).reshape(S, 4, 4)
     status, rep = fr_register(ctx.h, model, obs, params, theta, stream)
     return theta, status, rep
+
+
+def register_sigma(ctx: Context, model: Cloud, obs: Cloud, params: fr_register_params, sigma0, sigma_min: float,
+                   T0=None, stream=None):
+    """Rigid registration with the variance updated every iteration (params from register_params(..., m2=True));
+    returns (poses (n_sets, 4, 4), sigmas (n_sets,), status, report)."""
+    S = model.n_sets
+    theta = np.repeat(np.eye(4)[None], S, 0) if T0 is None else np.array(T0, dtype=np.float64).reshape(S, 4, 4)
+    sig = np.broadcast_to(np.asarray(sigma0, dtype=np.float64), (S,)).copy()
+    status, rep = fr_register_sigma(ctx.h, model, obs, params, sigma_min, theta, sig, stream)
+    return theta, sig, status, rep
 
 
 # --- articulated models ------------------------------------------------------------

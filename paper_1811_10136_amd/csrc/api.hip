@@ -269,8 +269,8 @@ fr_status check_lattice_params(const fr_lattice_params *p)
         set_error("feat must be 3 or 6 (got %d)", p->feat);
         return FR_EINVAL;
     }
-    if (p->values != 4 && p->values != 7) {
-        set_error("values must be 4 (pt2pt) or 7 (pt2pl) (got %d)", p->values);
+    if (p->values != 4 && p->values != 5 && p->values != 7 && p->values != 8) {
+        set_error("values must be FR_VAL_PT2PT, FR_VAL_PT2PT_M2, FR_VAL_PT2PL or FR_VAL_PT2PL_M2");
         return FR_EINVAL;
     }
     for (int i = 0; i < 3; ++i)
@@ -320,8 +320,8 @@ void scale_factors(const fr_lattice_params *p, float *k)
     }
 }
 
-fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
-                                    hipStream_t st, fr_lattice **out)
+fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
+                             fr_lattice **out, const double *sigma_set)
 {
     fr_lattice *lat = new (std::nothrow) fr_lattice();
     if (!lat) {
@@ -336,6 +336,16 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
     lat->splat = params->splat;
     lat->n_points_total = cloud_points(obs);
     scale_factors(params, lat->k);
+    lat->kset.resize((size_t)8 * obs->n_sets);
+    for (int32_t q = 0; q < obs->n_sets; ++q) {
+        if (sigma_set) {
+            fr_lattice_params ps = *params;
+            ps.sigma[0] = ps.sigma[1] = ps.sigma[2] = sigma_set[q];
+            scale_factors(&ps, lat->kset.data() + 8 * (size_t)q);
+        } else {
+            std::memcpy(lat->kset.data() + 8 * (size_t)q, lat->k, sizeof(lat->k));
+        }
+    }
     fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
     if (s == FR_OK) s = build_lattice(ctx, obs, params, st, lat);
     if (s != FR_OK) {
@@ -459,7 +469,7 @@ fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_pa
     }
     *out = nullptr;
     FR_TRY(check_lattice_params(params));
-    FR_TRY(check_cloud(obs, params->feat == 6 || params->values == 7, "fr_lattice_build"));
+    FR_TRY(check_cloud(obs, params->feat == 6 || params->values >= 7, "fr_lattice_build"));
     FR_HIP(hipSetDevice(ctx->device));
     StreamScope scope(static_cast<hipStream_t>(stream));
     return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out);
@@ -566,23 +576,23 @@ fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h,
     return FR_OK;
 }
 
-fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
-                   float *nsum, void *stream)
+static fr_status estep_impl(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0,
+                            float *m1, float *nsum, float *m2, void *stream, const char *what)
 {
     clear_error();
     if (!lat_ok(lat)) {
-        set_error("fr_estep: invalid lattice");
+        set_error("%s: invalid lattice", what);
         return FR_EINVAL;
     }
-    FR_TRY(check_cloud(model_ref, lat->d == 6, "fr_estep"));
+    FR_TRY(check_cloud(model_ref, lat->d == 6, what));
     if (model_ref->n_sets != lat->n_sets) {
-        set_error("fr_estep: model has %d sets, lattice has %d", model_ref->n_sets, lat->n_sets);
+        set_error("%s: model has %d sets, lattice has %d", what, model_ref->n_sets, lat->n_sets);
         return FR_EINVAL;
     }
-    FR_TRY(check_xform(xf, model_ref, "fr_estep"));
+    FR_TRY(check_xform(xf, model_ref, what));
     const int64_t M = cloud_points(model_ref);
     if (M > 0 && (m0 == nullptr || m1 == nullptr)) {
-        set_error("fr_estep: m0/m1 must be non-NULL");
+        set_error("%s: m0/m1 must be non-NULL", what);
         return FR_EINVAL;
     }
     if (M == 0) return FR_OK;
@@ -592,11 +602,29 @@ fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xf
     Plan plan;
     FR_TRY(make_plan(lat->ctx, model_ref, xf, kEstepTile, nullptr, st, plan));
     const int kind = xf ? xf->kind : FR_XF_NONE;
-    FR_TRY(launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1,
-                        lat->V == 7 ? nsum : nullptr, nullptr, st));
-    // plan.meta is released after the launch completes
-    FR_HIP(hipStreamSynchronize(st));
-    return FR_OK;
+    // the plan's device table goes back to the block cache ordered after the launch
+    return launch_estep(lat, model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1,
+                        lat->V >= 7 ? nsum : nullptr, nullptr, st, (lat->V == 5 || lat->V == 8) ? m2 : nullptr);
+}
+
+fr_status fr_estep(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
+                   float *nsum, void *stream)
+{
+    return estep_impl(lat, model_ref, xf, m0, m1, nsum, nullptr, stream, "fr_estep");
+}
+
+fr_status fr_estep_m2(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, float *m0, float *m1,
+                      float *nsum, float *m2, void *stream)
+{
+    if (lat_ok(lat) && (lat->V == 5 || lat->V == 8) && m2 == nullptr && cloud_points(model_ref) > 0) {
+        set_error("fr_estep_m2: m2 must be non-NULL");
+        return FR_EINVAL;
+    }
+    if (lat_ok(lat) && lat->V != 5 && lat->V != 8) {
+        set_error("fr_estep_m2: the lattice has no |y|^2 channel (values FR_VAL_PT2PT_M2 or FR_VAL_PT2PL_M2)");
+        return FR_EINVAL;
+    }
+    return estep_impl(lat, model_ref, xf, m0, m1, nsum, m2, stream, "fr_estep_m2");
 }
 
 fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, const fr_xform *xf, int32_t set,
@@ -707,12 +735,17 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         set_error("fr_register: point-to-plane needs a lattice with values = FR_VAL_PT2PL");
         return FR_EINVAL;
     }
+    if (params->lattice.values != FR_VAL_PT2PT && params->lattice.values != FR_VAL_PT2PL) {
+        set_error("fr_register: values must be FR_VAL_PT2PT or FR_VAL_PT2PL (the |y|^2 layouts serve "
+                  "fr_register_sigma)");
+        return FR_EINVAL;
+    }
     if (params->max_iters < 0 || params->kinematics != FR_KIN_RIGID || !(params->w >= 0.0 && params->w < 1.0)) {
         set_error("fr_register: max_iters >= 0, rigid kinematics and 0 <= w < 1 are required");
         return FR_EINVAL;
     }
     FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register(model)"));
-    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register(obs)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values >= 7, "fr_register(obs)"));
     if (model_ref->n_sets != obs->n_sets) {
         set_error("fr_register: model has %d sets, observation %d", model_ref->n_sets, obs->n_sets);
         return FR_EINVAL;
@@ -790,7 +823,7 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     for (; it < max_it; ++it) {
         if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
         if (fused) {
-            FR_TRY(launch_estep_fused(lat->d, lat->V, lat->k, lat->sets_d, lat->err_d, 0, model_ref, pe,
+            FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
                                       wmats.as<float>(), params->residual, 0, part.as<float>(), st));
             if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
             FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
@@ -857,6 +890,195 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
 }
 
 
+// The splat/slice kernel K(x, y) = sum_v b_v(x) b_v(y) of a lattice of scale s
+// has per-axis variance s^2 / 4: a vertex's linear hat has second moment
+// d (d+1)^2 / 12 (trace, isotropic) in lattice units, the position-averaged
+// kernel is the hat's autocorrelation (twice that moment), and a position
+// offset r is r (d+1) sqrt(2/3) / s lattice units.
+constexpr double kKernelAxisVar = 0.25;
+
+// Rigid EM with the isotropic variance as a decision variable.  The lattice
+// depends on sigma, so each iteration rebuilds it from the observation with
+// every set's current scale s; one E-step pass gives the Gauss-Newton terms and
+// the posterior-weighted squared distance V = sum_i w_i (|x_i - t_i|^2 +
+// m2_i / m0_i) (m2 taken about the target t_i).  V / (3 sum_i w_i) is the
+// variance of the Gaussian the kernel stands for, so
+// s^2 <- V / (3 sum_i w_i) / kKernelAxisVar after the pose step.
+fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs,
+                            const fr_register_params *params, double sigma_min, double *theta_inout_h,
+                            double *sigma_inout_h, int32_t *status_h, fr_report *report_h, void *stream)
+{
+    clear_error();
+    using clk = std::chrono::steady_clock;
+    if (!ctx_ok(ctx) || params == nullptr || theta_inout_h == nullptr || sigma_inout_h == nullptr) {
+        set_error("fr_register_sigma: invalid context, params, theta or sigma");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_lattice_params(&params->lattice));
+    const int32_t want = params->residual == FR_PT2PL ? FR_VAL_PT2PL_M2 : FR_VAL_PT2PT_M2;
+    if ((params->residual != FR_PT2PT && params->residual != FR_PT2PL) || params->lattice.values != want) {
+        set_error("fr_register_sigma: residual FR_PT2PT needs values FR_VAL_PT2PT_M2, FR_PT2PL needs "
+                  "FR_VAL_PT2PL_M2");
+        return FR_EINVAL;
+    }
+    if (params->max_iters < 0 || params->kinematics != FR_KIN_RIGID || !(params->w >= 0.0 && params->w < 1.0) ||
+        (params->flags & FR_FUSED) != 0 || !(sigma_min > 0.0)) {
+        set_error("fr_register_sigma: max_iters >= 0, rigid kinematics, 0 <= w < 1, sigma_min > 0 and no "
+                  "FR_FUSED are required");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register_sigma(model)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values >= 7, "fr_register_sigma(obs)"));
+    if (model_ref->n_sets != obs->n_sets) {
+        set_error("fr_register_sigma: model has %d sets, observation %d", model_ref->n_sets, obs->n_sets);
+        return FR_EINVAL;
+    }
+    const int32_t S = model_ref->n_sets;
+    for (int32_t s = 0; s < S; ++s)
+        if (!(sigma_inout_h[s] > 0.0) || !std::isfinite(sigma_inout_h[s])) {
+            set_error("fr_register_sigma: sigma of set %d must be finite and > 0", s);
+            return FR_EINVAL;
+        }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    const int64_t M = cloud_points(model_ref);
+    fr_report rep{};
+    std::vector<double> sig(sigma_inout_h, sigma_inout_h + S);
+
+    Plan pe, pr;
+    FR_TRY(make_plan(ctx, model_ref, nullptr, kEstepTile, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, nullptr, st, pr));
+    const bool pl = params->residual == FR_PT2PL;
+    const size_t nM = (size_t)std::max<int64_t>(M, 1);
+    DevBuf wm0, wm1, wns, wm2, part, wjtj, wjtr, wstat, wvar, wpose, wmats, wtn, wstatus, wactive;
+    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+    FR_TRY(wm2.alloc(ctx, nM * sizeof(float)));
+    if (pl) FR_TRY(wns.alloc(ctx, 3 * nM * sizeof(float)));
+    FR_TRY(part.alloc(ctx, reduce_partials_floats(pr) * sizeof(float)));
+    FR_TRY(wjtj.alloc(ctx, S * 21 * sizeof(double)));
+    FR_TRY(wjtr.alloc(ctx, S * 6 * sizeof(double)));
+    FR_TRY(wstat.alloc(ctx, S * 4 * sizeof(double)));
+    FR_TRY(wvar.alloc(ctx, S * sizeof(double)));
+    FR_TRY(wpose.alloc(ctx, S * 16 * sizeof(double)));
+    FR_TRY(wmats.alloc(ctx, S * 12 * sizeof(float)));
+    FR_TRY(wtn.alloc(ctx, S * 2 * sizeof(double)));
+    FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
+    FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
+    std::vector<float> mats_h((size_t)S * 12);
+    for (int32_t s = 0; s < S; ++s)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 4; ++j) mats_h[(size_t)s * 12 + 4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
+    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK);
+    FR_HIP(hipMemcpyAsync(wpose.p, theta_inout_h, S * 16 * sizeof(double), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wmats.p, mats_h.data(), S * 12 * sizeof(float), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wstatus.p, status_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+
+    const bool prof = (params->flags & FR_PROFILE_EVENTS) != 0;
+    const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
+    const int max_it = params->max_iters;
+    std::vector<hipEvent_t> ev;
+    if (prof) {
+        ev.resize(3 * (size_t)max_it + 1);
+        for (auto &e : ev) FR_HIP(hipEventCreate(&e));
+    }
+    std::vector<float> cseg(S);
+    std::vector<double> stats_h((size_t)S * 4), var_h(S), tn((size_t)S * 2);
+    auto t_em = clk::now();
+    int it = 0;
+    for (; it < max_it; ++it) {
+        auto tb = clk::now();
+        fr_lattice *lat = nullptr;
+        FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, sig.data()));
+        struct LatGuard {
+            fr_lattice *l;
+            ~LatGuard()
+            {
+                if (l) fr_lattice_destroy(l);
+            }
+        } guard{lat};
+        rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+        // outlier constant of each set at its current sigma
+        for (int32_t s = 0; s < S; ++s) {
+            fr_lattice_params ls = params->lattice;
+            ls.sigma[0] = ls.sigma[1] = ls.sigma[2] = sig[s];
+            cseg[s] = (float)outlier_constant(ls, params->w, params->c_override,
+                                              (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]),
+                                              (double)(obs->offsets[s + 1] - obs->offsets[s]));
+        }
+        FR_HIP(hipMemcpyAsync(const_cast<float *>(pr.seg_c), cseg.data(), S * sizeof(float), hipMemcpyHostToDevice,
+                              st));
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                            pl ? wns.as<float>() : nullptr, nullptr, st, wm2.as<float>()));
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+        // the Gauss-Newton step does not depend on the residual scale: reduce at sigma = 1
+        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+                             pl ? wns.as<float>() : nullptr, params->residual, 0, 1.0, wjtj.as<double>(),
+                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st, wm2.as<float>(),
+                             wvar.as<double>()));
+        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
+                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
+        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
+        FR_HIP(hipMemcpyAsync(stats_h.data(), wstat.p, S * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(var_h.data(), wvar.p, S * sizeof(double), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipStreamSynchronize(st));
+        FR_TRY(fr_sync_status(lat));
+        int n_active = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            if (!active_h[s]) continue;
+            // sets that stopped keep the sigma of their last pose
+            if (status_v[s] == FR_OK && stats_h[4 * s] > 0.0) {
+                const double var = var_h[s] / (3.0 * stats_h[4 * s]);
+                sig[s] = std::max(sigma_min, std::sqrt(std::max(var, 0.0) / kKernelAxisVar));
+            }
+            if (status_v[s] != FR_OK ||
+                (!fixed && tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
+                active_h[s] = 0;
+            n_active += active_h[s];
+        }
+        FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (n_active == 0) {
+            ++it;
+            break;
+        }
+    }
+    FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    rep.iterations = it;
+    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t_em).count() - rep.build_ms;
+    if (prof) {
+        for (int i = 0; i < it; ++i) {
+            float a = 0.0f, b = 0.0f;
+            FR_HIP(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
+            FR_HIP(hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]));
+            rep.estep_ms += a;
+            rep.mstep_ms += b;
+        }
+        rep.estep_launches = it;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    int32_t n_deg = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        if (status_v[s] != FR_OK) ++n_deg;
+        if (status_h) status_h[s] = status_v[s];
+        sigma_inout_h[s] = sig[s];
+    }
+    rep.n_degenerate = n_deg;
+    if (report_h) *report_h = rep;
+    if (n_deg > 0) {
+        set_error("fr_register_sigma: %d set(s) had a degenerate normal-equation system", n_deg);
+        return FR_EDEGENERATE;
+    }
+    return FR_OK;
+}
+
+
 fr_status fr_articulated_step(fr_ctx *ctx, const fr_kinematic_tree *tree, const double *jtj, const double *jtr,
                               double *theta, float *mats, int32_t *status, void *stream)
 {
@@ -889,12 +1111,13 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
     FR_TRY(check_lattice_params(&params->lattice));
     if ((params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
         (params->residual == FR_PT2PL && params->lattice.values != FR_VAL_PT2PL) || params->max_iters < 0 ||
+        (params->lattice.values != FR_VAL_PT2PT && params->lattice.values != FR_VAL_PT2PL) ||
         !(params->w >= 0.0 && params->w < 1.0)) {
         set_error("fr_register_articulated: bad residual/values, max_iters or w");
         return FR_EINVAL;
     }
     FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register_articulated(model)"));
-    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register_articulated(obs)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values >= 7, "fr_register_articulated(obs)"));
     if (model_ref->n_sets != 1 || obs->n_sets != 1) {
         set_error("fr_register_articulated: one model set and one observation set");
         return FR_EINVAL;
@@ -1010,12 +1233,13 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
     FR_TRY(check_lattice_params(&params->lattice));
     if ((params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
         (params->residual == FR_PT2PL && params->lattice.values != FR_VAL_PT2PL) || params->max_iters < 0 ||
+        (params->lattice.values != FR_VAL_PT2PT && params->lattice.values != FR_VAL_PT2PL) ||
         !(params->w >= 0.0 && params->w < 1.0)) {
         set_error("fr_register_nodegraph: bad residual/values, max_iters or w");
         return FR_EINVAL;
     }
     FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register_nodegraph(model)"));
-    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values == 7, "fr_register_nodegraph(obs)"));
+    FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values >= 7, "fr_register_nodegraph(obs)"));
     if (model_ref->n_sets != 1 || obs->n_sets != 1) {
         set_error("fr_register_nodegraph: one model set and one observation set");
         return FR_EINVAL;

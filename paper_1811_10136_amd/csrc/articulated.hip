@@ -1,8 +1,9 @@
 // Articulated Gauss-Newton step in binary64 on the device (Sec. 5.1, Eq. 19-20,
-// Alg. 1 lines 5-9): one block per kinematic tree.
+// Alg. 1, assembly and solve): one block per kinematic tree.
 //
 // Inputs are the per-body sums S_b = sum J^T J (6x6) and g_b = sum J^T r of the
-// points on body b, reduced by the segmented M-step kernel (Alg. 1 lines 1-4).
+// points on body b, reduced by the segmented M-step kernel (the per-body
+// accumulation of Alg. 1).
 // The block runs forward kinematics at the current joint angles to get, for
 // every revolute DOF k, its world axis w_k and a point q_k on it; DOF k moves
 // every body below its joint with the twist u_k = (w_k, q_k x w_k) (the twist

@@ -67,7 +67,6 @@ struct fr_engine {
     fr_engine_params prm{};
     int d = 3, V = 4;
     bool fused = false;
-    float k[8] = {};
     double sig_m = 1.0;
     int32_t S = 0;
     int64_t P = 0;
@@ -154,6 +153,10 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
         set_error("fr_engine_create: point-to-plane needs values = FR_VAL_PT2PL");
         return FR_EINVAL;
     }
+    if (p.lattice.values != FR_VAL_PT2PT && p.lattice.values != FR_VAL_PT2PL) {
+        set_error("fr_engine_create: values must be FR_VAL_PT2PT or FR_VAL_PT2PL");
+        return FR_EINVAL;
+    }
     if (p.max_slots < 1 || p.max_slots > kEngMaxSlots || p.arena_points < 1 || p.arena_points >= ((int64_t)1 << 31)) {
         set_error("fr_engine_create: 1 <= max_slots <= %d and 1 <= arena_points < 2^31 required", kEngMaxSlots);
         return FR_EINVAL;
@@ -183,7 +186,6 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     e->st = st;
     e->offsets_h[1] = e->P;
     e->sig_m = (p.lattice.sigma[0] + p.lattice.sigma[1] + p.lattice.sigma[2]) / 3.0;
-    scale_factors(&p.lattice, e->k);   // identical to those of the builds
     const int64_t P = e->P, S = e->S;
     auto fail = [&](fr_status s) {
         engine_free(e);
@@ -315,7 +317,7 @@ fr_status fr_engine_admit(fr_engine *e, int32_t n, const int32_t *slots_h, const
     FR_TRY(check_slots(e, n, slots_h, false, "fr_engine_admit"));
     const fr_lattice_params &lp = e->prm.lattice;
     FR_TRY(check_cloud(model_ref, e->d == 6, "fr_engine_admit(model)"));
-    FR_TRY(check_cloud(obs, e->d == 6 || e->V == 7, "fr_engine_admit(obs)"));
+    FR_TRY(check_cloud(obs, e->d == 6 || e->V >= 7, "fr_engine_admit(obs)"));
     if (model_ref->n_sets != n || obs->n_sets != n) {
         set_error("fr_engine_admit: model and observation must hold n = %d sets", n);
         return FR_EINVAL;
@@ -501,12 +503,12 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
     make(d_tr, tr[S], 1024, pr);
     fr_cloud arena{e->x, e->y, e->z, e->nx, e->ny, e->nz, e->offsets_h, 1};
     if (e->fused) {
-        FR_TRY(launch_estep_fused(e->d, e->V, e->k, e->tables, e->err, 1, &arena, pe, e->mats, e->prm.residual, 0,
+        FR_TRY(launch_estep_fused(e->d, e->V, e->tables, e->err, 1, &arena, pe, e->mats, e->prm.residual, 0,
                                   e->partials.as<float>(), e->st));
         FR_TRY(launch_reduce_final(pe, e->partials.as<float>(), e->sig_m, e->jtj, e->jtr, e->stats, e->st));
     } else {
-        FR_TRY(launch_estep_sets(e->d, e->V, e->k, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats,
-                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, e->st));
+        FR_TRY(launch_estep_sets(e->d, e->V, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats,
+                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, nullptr, e->st));
         FR_TRY(launch_reduce(&arena, pr, FR_XF_RIGID, e->mats, e->m0, e->m1,
                              e->prm.residual == FR_PT2PL ? e->ns : nullptr, e->prm.residual, 0, e->sig_m, e->jtj,
                              e->jtr, e->stats, e->partials.as<float>(), e->st));

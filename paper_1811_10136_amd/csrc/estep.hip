@@ -19,8 +19,8 @@ struct EstepArgs {
     const float *mats;            // per segment [R | t], or NULL for no transform
     const SetTable *sets;
     TileMap tm;
-    float k[8];
     float *m0, *m1, *ns;          // outputs (m1/ns channel-major, stride M)
+    float *m2;                    // output sum b |y|^2 (value layouts with that channel), or NULL
     int64_t M;
     uint32_t *touched;            // optional: per-slot "was found" flags
     int32_t *err;                 // range-error flag: one word, or one per segment
@@ -66,7 +66,7 @@ __device__ __forceinline__ void slice_point(const EstepArgs &a, int32_t s, int64
     }
     float kk[d];
 #pragma unroll
-    for (int j = 0; j < d; ++j) kk[j] = a.k[j];
+    for (int j = 0; j < d; ++j) kk[j] = st.k[j];
 
     uint64_t keys[D][KW];
     float b[D];
@@ -95,12 +95,15 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     st_stream(a.m1 + i, acc[1]);
     st_stream(a.m1 + a.M + i, acc[2]);
     st_stream(a.m1 + 2 * a.M + i, acc[3]);
-    if constexpr (V == 7) {
+    if constexpr (ValLayout<V>::normals) {
         if (a.ns != nullptr) {
             st_stream(a.ns + i, acc[4]);
             st_stream(a.ns + a.M + i, acc[5]);
             st_stream(a.ns + 2 * a.M + i, acc[6]);
         }
+    }
+    if constexpr (ValLayout<V>::m2) {
+        if (a.m2 != nullptr) st_stream(a.m2 + i, acc[V - 1]);
     }
 }
 
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     }
     float kk[d];
 #pragma unroll
-    for (int j = 0; j < d; ++j) kk[j] = a.k[j];
+    for (int j = 0; j < d; ++j) kk[j] = st.k[j];
     uint64_t keys[D][KW];
     float b[D];
     embed<d>(p, kk, keys, b);
@@ -188,9 +191,9 @@ static void launch_dv(const EstepArgs &a, bool xf, bool touch, int grid, hipStre
     }
 }
 
-fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                             const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
-                            float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
+                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st)
 {
     if (plan.grid == 0) return FR_OK;
     EstepArgs a{};
@@ -203,10 +206,10 @@ fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, 
     a.mats = mats;
     a.sets = sets;
     a.tm = plan.tm;
-    for (int j = 0; j < 8; ++j) a.k[j] = k[j];
     a.m0 = m0;
     a.m1 = m1;
     a.ns = nsum;
+    a.m2 = m2;
     a.M = M;
     a.touched = touched;
     a.err = err;
@@ -217,6 +220,10 @@ fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, 
     else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, plan.grid, st);
     else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, plan.grid, st);
     else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, plan.grid, st);
+    else if (d == 3 && V == 5) launch_dv<3, 5>(a, xf, touch, plan.grid, st);
+    else if (d == 3 && V == 8) launch_dv<3, 8>(a, xf, touch, plan.grid, st);
+    else if (d == 6 && V == 5) launch_dv<6, 5>(a, xf, touch, plan.grid, st);
+    else if (d == 6 && V == 8) launch_dv<6, 8>(a, xf, touch, plan.grid, st);
     else {
         set_error("fr_estep: unsupported lattice d=%d V=%d", d, V);
         return FR_EINVAL;
@@ -237,13 +244,13 @@ static void launch_fused_dv(const EstepArgs &a, int residual, int grid, hipStrea
     k_estep_fused<d, V, true, FR_PT2PT><<<grid, 256, 0, st>>>(a);
 }
 
-fr_status launch_estep_fused(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                              const fr_cloud *model, const Plan &plan, const float *mats, int residual,
                              int normalize_n, float *partials, hipStream_t st)
 {
     if (plan.grid == 0) return FR_OK;
-    if (residual == FR_PT2PL && V != 7) {
-        set_error("fused E-step: point-to-plane needs V = 7");
+    if ((residual == FR_PT2PL && V != 7) || (V != 4 && V != 7)) {
+        set_error("fused E-step: V = 4 or 7 (7 for point-to-plane)");
         return FR_EINVAL;
     }
     EstepArgs a{};
@@ -256,7 +263,6 @@ fr_status launch_estep_fused(int d, int V, const float *k, const SetTable *sets,
     a.mats = mats;
     a.sets = sets;
     a.tm = plan.tm;
-    for (int j = 0; j < 8; ++j) a.k[j] = k[j];
     a.M = cloud_points(model);
     a.err = err;
     a.err_stride = err_stride;
@@ -276,10 +282,10 @@ fr_status launch_estep_fused(int d, int V, const float *k, const SetTable *sets,
 }
 
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
-                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st)
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2)
 {
-    return launch_estep_sets(lat->d, lat->V, lat->k, lat->sets_d, lat->err_d, 0, model, cloud_points(model), plan,
-                             xf_kind, mats, m0, m1, nsum, touched, st);
+    return launch_estep_sets(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model, cloud_points(model), plan,
+                             xf_kind, mats, m0, m1, nsum, m2, touched, st);
 }
 
 }  // namespace fr

@@ -31,6 +31,16 @@ template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; }; 
 // VP = 4 or 8 (one or two 16-byte loads).
 template <int V> struct ValPad { static constexpr int value = V <= 4 ? 4 : 8; };
 
+// Value channels splatted per observation point: [1, y] (V = 4), [1, y, |y|^2]
+// (V = 5), [1, y, n_y] (V = 7), [1, y, n_y, |y|^2] (V = 8).  |y|^2 feeds the
+// variance update; it is always the last channel, and a vertex stores it as
+// the scatter about its own mean, S_v = sum b |y - mu_v|^2 with mu_v = M1_v / W_v,
+// so that no |y|^2-sized numbers are subtracted after rounding to binary32.
+template <int V> struct ValLayout {
+    static constexpr bool normals = V >= 7;
+    static constexpr bool m2 = V == 5 || V == 8;
+};
+
 // Per-set view of the lattice table.  keys/vals point at the set's first
 // slot, so one launch can slice sets of lattices that were built separately.
 struct SetTable {
@@ -41,6 +51,7 @@ struct SetTable {
     uint32_t n_vertices;
     uint32_t seed;        // hash seed (changed when a cuckoo insertion has to be redone)
     uint32_t mask;        // cap - 1 for the power-of-two tables of the build
+    float k[8];           // lattice scale of the set's features (binary32, see embed)
 };
 
 // Tiles of points grouped by segment; a segment lies inside one set.
@@ -304,7 +315,9 @@ __device__ __forceinline__ void xform_normal(const float *m, float x, float y, f
 // once, then the value slot of each vertex found, and accumulate b * value.
 // A vertex absent from the lattice contributes nothing; its lane skips the
 // value load (a predicated load, the only divergence).  kb/vb are the set's
-// table bases (uniform per block), slots are 32-bit offsets.
+// table bases (uniform per block), slots are 32-bit offsets.  For the |y|^2
+// layouts the last channel comes out as the second moment about the target,
+// sum_k K |y_k - t|^2 with t = M1 / M0 (0 without support).
 template <int KW, int V, int D>
 __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, const float *__restrict__ vb,
                                               const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
@@ -313,6 +326,7 @@ __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, c
     constexpr int VP = ValPad<V>::value;
     uint32_t p1[D], p2[D];
     uint64_t ka[D][KW], kc[D][KW];
+    float vw[D], vW[D], vm[D][3];   // |y|^2 layouts: weights, masses and first moments per vertex
 #pragma unroll
     for (int v = 0; v < D; ++v) {
         cuckoo_slots(hash_key<KW>(keys[v], st.seed), st.cap, p1[v], p2[v]);
@@ -338,6 +352,27 @@ __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, c
                               __uint_as_float(q1.z), __uint_as_float(q1.w)};
 #pragma unroll
         for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
+        if constexpr (ValLayout<V>::m2) {
+            vw[v] = w;
+            vW[v] = val[0];
+            vm[v][0] = val[1];
+            vm[v][1] = val[2];
+            vm[v][2] = val[3];
+        }
+    }
+    if constexpr (ValLayout<V>::m2) {
+        // second moment about the target t = M1 / M0:
+        //   sum_k K |y_k - t|^2 = sum_v b_v (S_v + W_v |mu_v - t|^2)
+        if (acc[0] > 0.0f) {
+            const float inv = 1.0f / acc[0];
+            const float tx = acc[1] * inv, ty = acc[2] * inv, tz = acc[3] * inv;
+#pragma unroll
+            for (int v = 0; v < D; ++v) {
+                const float iw = vW[v] > 0.0f ? 1.0f / vW[v] : 0.0f;
+                const float dx = vm[v][0] * iw - tx, dy = vm[v][1] * iw - ty, dz = vm[v][2] * iw - tz;
+                acc[V - 1] = fmaf(vw[v] * vW[v], fmaf(dx, dx, fmaf(dy, dy, dz * dz)), acc[V - 1]);
+            }
+        }
     }
 }
 

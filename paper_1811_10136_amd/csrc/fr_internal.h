@@ -74,7 +74,8 @@ struct fr_lattice {
     int32_t d = 3, V = 4, KW = 1;
     int32_t n_sets = 0;
     int32_t splat = FR_SPLAT_SORTED;
-    float k[8] = {0};
+    float k[8] = {0};               // scale factors of the lattice parameters
+    std::vector<float> kset;        // n_sets x 8: scale factors of each set (per-set sigma)
     int64_t n_points_total = 0;
     // cuckoo tables of all sets: keys (KW words per slot) and padded values
     uint64_t *tkey = nullptr;
@@ -112,8 +113,10 @@ fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes);
 void free_lattice(fr_lattice *lat, hipStream_t st, bool idle);
 bool ctx_ok(const fr_ctx *c);
 fr_status check_lattice_params(const fr_lattice_params *p);
+// sigma_set (host, n_sets, may be NULL): an isotropic position sigma per set
+// in place of params->sigma (the normal sigma stays params->sigma_n).
 fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
-                             fr_lattice **out);
+                             fr_lattice **out, const double *sigma_set = nullptr);
 void scale_factors(const fr_lattice_params *p, float *k);
 double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns);
 void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle = false);
@@ -173,22 +176,23 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
                         fr_lattice *lat);
 
 // estep.hip
-fr_status launch_estep_sets(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                             const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
-                            float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st);
+                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st);
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
-                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t stream);
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2 = nullptr);
 
 // mstep.hip
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
-                        double *jtr, double *stats, float *partials, hipStream_t stream);
+                        double *jtr, double *stats, float *partials, hipStream_t st, const float *m2 = nullptr,
+                        double *var_stat = nullptr);
 size_t reduce_partials_floats(const Plan &plan);
 fr_status launch_reduce_final(const Plan &plan, const float *partials, double sigma, double *jtj, double *jtr,
-                              double *stats, hipStream_t st);
+                              double *stats, hipStream_t st, double *var_stat = nullptr);
 // Fused slice + reduction (E-step and M-step terms of every point in one
 // pass): one partial row per E-step tile, then launch_reduce_final on `plan`.
-fr_status launch_estep_fused(int d, int V, const float *k, const SetTable *sets, int32_t *err, int32_t err_stride,
+fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                              const fr_cloud *model, const Plan &plan, const float *mats, int residual,
                              int normalize_n, float *partials, hipStream_t st);
 

@@ -8,7 +8,7 @@
 
 namespace fr {
 
-constexpr int kRedVals = 31;      // 21 JtJ (upper, row-major) + 6 Jtr + 4 statistics
+constexpr int kRedVals = 32;      // 21 JtJ (upper, row-major) + 6 Jtr + 4 statistics + variance term
 constexpr int kRedStride = 32;    // floats per partial row
 
 __host__ __device__ constexpr int ut_index(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
@@ -32,15 +32,17 @@ __device__ __forceinline__ void accumulate_rows(float (&acc)[kRedVals], const fl
 }
 
 // One model point at (moved) position x with slice results m0, m1 = sum b y,
-// ns = sum b n_y: weight w = m0 / (m0 + c), target m1 / m0, normal ns / m0;
-//   pt2pt: r = x - target, J = [-[x]_x, I]
-//   pt2pl: r = n . (x - target), J = [x cross n, n]
-// adds w J^T J, w J^T r, w, w r^2, 1, m0 to acc.  Points without support
-// (m0 = 0) add nothing.
-template <int RES>
+// ns = sum b n_y (and c2 = sum b |y - t|^2): weight w = m0 / (m0 + c), target
+// t = m1 / m0, normal ns / m0;
+//   pt2pt: r = x - t, J = [-[x]_x, I]
+//   pt2pl: r = n . (x - t), J = [x cross n, n]
+// adds w J^T J, w J^T r, w, w r^2, 1, m0 to acc, and with M2 the variance
+// term w (|x - t|^2 + c2 / m0), the posterior-weighted squared distance of the
+// point to the observations.  Points without support (m0 = 0) add nothing.
+template <int RES, bool M2 = false>
 __device__ __forceinline__ void mstep_point(float (&acc)[kRedVals], float x, float y, float z, float m0, float m1x,
                                             float m1y, float m1z, float nsx, float nsy, float nsz, float c,
-                                            int normalize_n)
+                                            int normalize_n, float m2 = 0.0f)
 {
     if (!(m0 > 0.0f)) return;
     const float w = m0 / (m0 + c);
@@ -74,6 +76,10 @@ __device__ __forceinline__ void mstep_point(float (&acc)[kRedVals], float x, flo
     acc[28] = fmaf(w, r2, acc[28]);
     acc[29] += 1.0f;
     acc[30] += m0;
+    if constexpr (M2) {
+        const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        acc[31] = fmaf(w, fmaf(m2, inv, dd), acc[31]);
+    }
 }
 
 // Sum acc over the 256 threads of the block (wavefront butterflies, then the 4

@@ -22,6 +22,8 @@
 //                 E-step lookup is two key reads and one value read.
 #include <algorithm>
 
+#include <cstring>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -233,7 +235,7 @@ struct Pts {
 // simplex.  Records are r = point * D + m; the block stages its 256 * D
 // records in LDS so the global writes are contiguous.
 template <int d>
-__global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, float4 k0, float4 k1, uint64_t *rec_key,
+__global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, const float *kset, uint64_t *rec_key,
                                                   float *rec_b, size_t R, int32_t *err)
 {
     constexpr int D = d + 1;
@@ -249,9 +251,8 @@ __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, float4 k
     if (i < tm.seg_end[s]) {
         float p[d];
         float kk[d];
-        const float kall[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
 #pragma unroll
-        for (int j = 0; j < d; ++j) kk[j] = kall[j];
+        for (int j = 0; j < d; ++j) kk[j] = kset[8 * s + j];
         p[0] = pts.x[i];
         p[1] = pts.y[i];
         p[2] = pts.z[i];
@@ -408,7 +409,7 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
             val[u][0] = pts.x[i];
             val[u][1] = pts.y[i];
             val[u][2] = pts.z[i];
-            if constexpr (V == 7) {
+            if constexpr (ValLayout<V>::normals) {
                 val[u][3] = pts.nx[i];
                 val[u][4] = pts.ny[i];
                 val[u][5] = pts.nz[i];
@@ -419,9 +420,20 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
             if (q + u >= q1) break;
             const double w = (double)bw[u];
             acc[0] += w;
+            constexpr int NL = ValLayout<V>::m2 ? V - 2 : V - 1;   // linear channels after the 1
 #pragma unroll
-            for (int c = 1; c < V; ++c) acc[c] += w * (double)val[u][c - 1];
+            for (int c = 0; c < NL; ++c) acc[1 + c] += w * (double)val[u][c];
+            if constexpr (ValLayout<V>::m2) {
+                const double y0 = val[u][0], y1 = val[u][1], y2 = val[u][2];
+                acc[V - 1] += w * (y0 * y0 + y1 * y1 + y2 * y2);
+            }
         }
+    }
+    if constexpr (ValLayout<V>::m2) {
+        // keep the scatter about the vertex mean, sum b |y - mu|^2 = sum b |y|^2 - |M1|^2 / W:
+        // the slice then never subtracts |y|^2-sized numbers stored in binary32
+        const double q = acc[0] > 0.0 ? (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0] : 0.0;
+        acc[V - 1] = fmax(acc[V - 1] - q, 0.0);
     }
 #pragma unroll
     for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = (float)acc[c];
@@ -444,11 +456,32 @@ __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t R, const uint3
     unsafeAtomicAdd(&vval[NV + v], bw * pts.x[i]);
     unsafeAtomicAdd(&vval[2 * NV + v], bw * pts.y[i]);
     unsafeAtomicAdd(&vval[3 * NV + v], bw * pts.z[i]);
-    if constexpr (V == 7) {
+    if constexpr (ValLayout<V>::normals) {
         unsafeAtomicAdd(&vval[4 * NV + v], bw * pts.nx[i]);
         unsafeAtomicAdd(&vval[5 * NV + v], bw * pts.ny[i]);
         unsafeAtomicAdd(&vval[6 * NV + v], bw * pts.nz[i]);
     }
+}
+
+// Atomic mode, |y|^2 layouts: second pass once the means are complete, adding
+// b |y - mu_v|^2 about the vertex mean mu_v = M1_v / W_v (the scatter that the
+// sorted mode keeps; about a mean rounded to binary32 it is larger by
+// W |mu - mu'|^2, far below the binary32 resolution of the sum).
+template <int D, int V>
+__global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t R, const uint32_t *rec_slot,
+                                                              const uint32_t *slot_vid, const float *rec_b, Pts pts,
+                                                              float *vval, size_t NV)
+{
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint32_t v = slot_vid[rec_slot[r]];
+    const size_t i = r / D;
+    const float W = vval[v];
+    const float inv = W > 0.0f ? 1.0f / W : 0.0f;
+    const float dx = pts.x[i] - vval[NV + v] * inv;
+    const float dy = pts.y[i] - vval[2 * NV + v] * inv;
+    const float dz = pts.z[i] - vval[3 * NV + v] * inv;
+    unsafeAtomicAdd(&vval[(size_t)(V - 1) * NV + v], rec_b[r] * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
 // Two-choice cuckoo insertion of the vertices of each set (one thread per
@@ -583,11 +616,12 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     std::vector<int64_t> poff(obs->offsets, obs->offsets + S + 1);
     TileMap ptm{}, rtm{};
     FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm));
-    const float4 k0 = make_float4(lat->k[0], lat->k[1], lat->k[2], lat->k[3]);
-    const float4 k1 = make_float4(lat->k[4], lat->k[5], lat->k[6], lat->k[7]);
+    DevBuf kset_d;
+    FR_TRY(kset_d.alloc(ctx, lat->kset.size() * sizeof(float)));
+    FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
     if (ptm.n_tiles > 0) {
-        k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, k0, k1, rec_key.as<uint64_t>(), rec_b.as<float>(), R,
-                                                    lat->err_d);
+        k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), rec_key.as<uint64_t>(),
+                                                    rec_b.as<float>(), R, lat->err_d);
         FR_HIP(hipGetLastError());
     }
     // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
@@ -601,7 +635,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         for (int32_t s = 0; s < S; ++s) {
             const uint64_t rs = (uint64_t)(roff[s + 1] - roff[s]);
             const uint32_t cap = next_pow2(attempt == 0 ? rs / 2 : 2 * rs);
-            t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1};
+            t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1, {}};
             n1 += cap;
         }
         if (n1 >= 0xFFFFFFF0ull) {
@@ -713,6 +747,11 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                                                            slot_vid.as<uint32_t>(), rec_b.as<float>(),
                                                                            pts, lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
+            if constexpr (ValLayout<V>::m2) {
+                k_vertex_scatter_atomic<D, V><<<blocks_for(R, 256), 256, 0, st>>>(
+                    R, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_b.as<float>(), pts, lat->vval, NV);
+                FR_HIP(hipGetLastError());
+            }
         }
     }
     // the provisional table and records are no longer needed
@@ -728,7 +767,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     uint64_t n2 = 0;
     for (int32_t s = 0; s < S; ++s) {
         const uint32_t cap = (uint32_t)std::max<uint64_t>(16, (5 * (uint64_t)counts[s] + 1) / 2);
-        lat->sets_h[s] = SetTable{nullptr, nullptr, n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0};
+        lat->sets_h[s] = SetTable{nullptr, nullptr, n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0, {}};
+        std::memcpy(lat->sets_h[s].k, lat->kset.data() + 8 * (size_t)s, sizeof(lat->sets_h[s].k));
         n2 += cap;
     }
     lat->n_slots = n2;
@@ -780,6 +820,10 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
     if (prm->feat == 3 && prm->values == 7) return build_impl<3, 7>(ctx, obs, st, lat);
     if (prm->feat == 6 && prm->values == 4) return build_impl<6, 4>(ctx, obs, st, lat);
     if (prm->feat == 6 && prm->values == 7) return build_impl<6, 7>(ctx, obs, st, lat);
+    if (prm->feat == 3 && prm->values == 5) return build_impl<3, 5>(ctx, obs, st, lat);
+    if (prm->feat == 3 && prm->values == 8) return build_impl<3, 8>(ctx, obs, st, lat);
+    if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat);
+    if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat);
     set_error("fr_lattice_build: unsupported feat=%d values=%d", prm->feat, prm->values);
     return FR_EINVAL;
 }

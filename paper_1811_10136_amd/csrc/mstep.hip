@@ -18,14 +18,14 @@ struct ReduceArgs {
     const float *x, *y, *z;
     const float *mats;
     TileMap tm;
-    const float *m0, *m1, *ns;
+    const float *m0, *m1, *ns, *m2;
     int64_t M;
     const float *seg_c;
     float *partials;
     int normalize_n;
 };
 
-template <int RES, bool XF>
+template <int RES, bool XF, bool M2>
 __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
 {
     __shared__ float part[kRedThreads / 64][kRedStride];
@@ -63,9 +63,10 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
             nsy = __builtin_nontemporal_load(a.ns + a.M + i);
             nsz = __builtin_nontemporal_load(a.ns + 2 * a.M + i);
         }
-        mstep_point<RES>(acc, x, y, z, m0, __builtin_nontemporal_load(a.m1 + i),
-                         __builtin_nontemporal_load(a.m1 + a.M + i), __builtin_nontemporal_load(a.m1 + 2 * a.M + i),
-                         nsx, nsy, nsz, c, a.normalize_n);
+        mstep_point<RES, M2>(acc, x, y, z, m0, __builtin_nontemporal_load(a.m1 + i),
+                             __builtin_nontemporal_load(a.m1 + a.M + i),
+                             __builtin_nontemporal_load(a.m1 + 2 * a.M + i), nsx, nsy, nsz, c, a.normalize_n,
+                             M2 ? __builtin_nontemporal_load(a.m2 + i) : 0.0f);
     }
     block_partials(acc, part, a.partials + (size_t)t * kRedStride);
 }
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
 constexpr int kFinalLanes = 8;
 
 __global__ void __launch_bounds__(256) k_reduce_final(TileMap tm, const float *partials, double inv_s2, double *jtj,
-                                                      double *jtr, double *stats)
+                                                      double *jtr, double *stats, double *var_stat)
 {
     __shared__ double lane_sum[kRedVals][kFinalLanes];
     const int32_t s = blockIdx.x;
@@ -95,24 +96,33 @@ __global__ void __launch_bounds__(256) k_reduce_final(TileMap tm, const float *p
         for (int q = 0; q < kFinalLanes; ++q) acc += lane_sum[jj][q];
         if (jj < 21) jtj[(size_t)s * 21 + jj] = acc * inv_s2;
         else if (jj < 27) jtr[(size_t)s * 6 + (jj - 21)] = acc * inv_s2;
-        else stats[(size_t)s * 4 + (jj - 27)] = (jj == 28) ? acc * inv_s2 : acc;
+        else if (jj < 31) stats[(size_t)s * 4 + (jj - 27)] = (jj == 28) ? acc * inv_s2 : acc;
+        else if (var_stat != nullptr) var_stat[s] = acc;
     }
 }
 
 size_t reduce_partials_floats(const Plan &plan) { return (size_t)(plan.n_tiles + 1) * kRedStride; }
 
 fr_status launch_reduce_final(const Plan &plan, const float *partials, double sigma, double *jtj, double *jtr,
-                              double *stats, hipStream_t st)
+                              double *stats, hipStream_t st, double *var_stat)
 {
     if (plan.n_seg == 0) return FR_OK;
-    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
+    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats, var_stat);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
+template <int RES, bool M2>
+static void launch_reduce_rm(const ReduceArgs &a, bool xf, int grid, hipStream_t st)
+{
+    if (xf) k_reduce<RES, true, M2><<<grid, kRedThreads, 0, st>>>(a);
+    else k_reduce<RES, false, M2><<<grid, kRedThreads, 0, st>>>(a);
+}
+
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
-                        double *jtr, double *stats, float *partials, hipStream_t st)
+                        double *jtr, double *stats, float *partials, hipStream_t st, const float *m2,
+                        double *var_stat)
 {
     if (plan.n_seg == 0) return FR_OK;
     ReduceArgs a{};
@@ -124,6 +134,7 @@ fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, co
     a.m0 = m0;
     a.m1 = m1;
     a.ns = nsum;
+    a.m2 = m2;
     a.M = cloud_points(model);
     a.seg_c = plan.seg_c;
     a.partials = partials;
@@ -131,17 +142,15 @@ fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, co
     const bool xf = xf_kind != FR_XF_NONE;
     if (plan.grid > 0) {
         if (residual == FR_PT2PT) {
-            if (xf) k_reduce<FR_PT2PT, true><<<plan.grid, kRedThreads, 0, st>>>(a);
-            else k_reduce<FR_PT2PT, false><<<plan.grid, kRedThreads, 0, st>>>(a);
+            if (m2) launch_reduce_rm<FR_PT2PT, true>(a, xf, plan.grid, st);
+            else launch_reduce_rm<FR_PT2PT, false>(a, xf, plan.grid, st);
         } else {
-            if (xf) k_reduce<FR_PT2PL, true><<<plan.grid, kRedThreads, 0, st>>>(a);
-            else k_reduce<FR_PT2PL, false><<<plan.grid, kRedThreads, 0, st>>>(a);
+            if (m2) launch_reduce_rm<FR_PT2PL, true>(a, xf, plan.grid, st);
+            else launch_reduce_rm<FR_PT2PL, false>(a, xf, plan.grid, st);
         }
         FR_HIP(hipGetLastError());
     }
-    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
+    return launch_reduce_final(plan, partials, sigma, jtj, jtr, stats, st, var_stat);
 }
 
 }  // namespace fr
