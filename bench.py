@@ -307,7 +307,44 @@ def other_workloads(fr, ctx, reps=5):
     out["nodegraph_pt2pt"] = {"model_points": len(p.model), "obs_points": len(p.obs), "nodes": len(e["nodes"]),
                               "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
                               "pcg_iters_last": rep.solver_iters}
+    out["updated_sigma"] = updated_sigma_workloads(fr, ctx)
     return out
+
+
+def updated_sigma_workloads(fr, ctx, n_pairs=8, max_iters=60, tol=1e-4):
+    """Fixed against updated sigma (Sec. 3.3, the two rows of Tab. 1): ellipsoid pairs (2000 points,
+    10% outliers, noise 0.01) under motions up to 10 deg / 5 cm from the identity, run until the
+    twist drops below `tol`; and one 640x480 depth frame, 20 iterations of the updated-sigma loop."""
+    rows = {"fixed": [], "updated": []}
+    for seed in range(n_pairs):
+        p = synth.ellipsoid_pair(100 + seed, max_angle_deg=10.0, max_trans=0.05, noise=0.01)
+        m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+        prm = fr.register_params(3, "pt2pt", p.sigma, iters=max_iters, w=p.w, tol=tol, fixed=False)
+        ms, (T, st, rep) = _timed(lambda: fr.register(ctx, m, o, prm), 3)
+        rows["fixed"].append((rep.iterations, ms, alignment_error(T[0], p.T_gt, p.model)))
+        prm = fr.register_params(3, "pt2pt", p.sigma, iters=max_iters, w=p.w, tol=tol, fixed=False, m2=True)
+        ms, (T, s, st, rep) = _timed(lambda: fr.register_sigma(ctx, m, o, prm, p.sigma[0], 1e-3), 3)
+        rows["updated"].append((rep.iterations, ms, alignment_error(T[0], p.T_gt, p.model)))
+    res = {"pairs": n_pairs, "start": "identity; motions up to 10 deg, 5 cm", "noise": 0.01, "sigma0": 0.02,
+           "stop": f"twist below {tol} or {max_iters} iterations"}
+    for k, v in rows.items():
+        a = np.array(v)
+        res[k] = {"mean_iterations": float(a[:, 0].mean()), "mean_ms": float(a[:, 1].mean()),
+                  "mean_error_m": float(a[:, 2].mean()), "converged_below_5mm": int((a[:, 2] < 5e-3).sum())}
+    p = synth.depth_pair(0)
+    m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, profile=True, m2=True)
+    ms, (T, s, st, rep) = _timed(lambda: fr.register_sigma(ctx, m, o, prm, p.sigma[0], 2e-3), 3)
+    res["depth_pt2pl_20_iters"] = {"model_points": len(p.model), "obs_points": len(p.obs), "registration_ms": ms,
+                                   "rebuild_ms_per_iter": rep.build_ms / 20, "estep_ms_per_launch":
+                                   rep.estep_ms / max(1, rep.estep_launches), "final_sigma": float(s[0])}
+    return res
+
+
+def alignment_error(T, T_gt, x):
+    """Mean |(T - T_gt) x| over the model points (Eq. 22)."""
+    D = np.asarray(T) - np.asarray(T_gt)
+    return float(np.mean(np.linalg.norm(np.asarray(x, np.float64) @ D[:3, :3].T + D[:3, 3], axis=1)))
 
 
 def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):

@@ -21,6 +21,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfilterreg.so")
 
+# torch ships its own HIP runtime under the same soname as the system one; load
+# it first so that this library binds to it and the process has one runtime
+# (loaded the other way round, torch finds no device)
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python -m paper_1811_10136_amd.build` (hipcc, gfx950)")

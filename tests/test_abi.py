@@ -1,4 +1,5 @@
 """The C-ABI library loads and exports every entry point its header declares (no GPU calls)."""
+import ast
 import ctypes
 import os
 import re
@@ -18,7 +19,12 @@ def declared_functions():
 
 def _lib():
     if not os.path.exists(LIB):
-        from paper_1811_10136_amd import build as hipbuild
+        # the build script by path: the package itself refuses to import without the library
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_fr_build", os.path.join(ROOT, "paper_1811_10136_amd",
+                                                                                "build.py"))
+        hipbuild = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(hipbuild)
         hipbuild.build()
     return ctypes.CDLL(LIB)
 
@@ -38,6 +44,20 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_every_declared_symbol():
     import paper_1811_10136_amd as fr
     assert sorted(fr.ABI_FUNCTIONS) == declared_functions()
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Importing the binding first still leaves one HIP runtime in the process (torch's): two
+    runtimes under one soname leave torch without a device."""
+    import subprocess
+    import sys
+    code = ("import paper_1811_10136_amd, torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    paths = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
+    import torch
+    assert os.path.dirname(paths[0]) == os.path.join(os.path.dirname(torch.__file__), "lib"), paths
 
 
 def test_version_and_error_string_without_gpu():
