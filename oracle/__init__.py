@@ -57,6 +57,8 @@ def _L():
         lib.or_slice.argtypes = [ci, ci, i64, P, P, i64, P, P, P, P]
         lib.or_bf_lattice_sum.argtypes = [ci, ci, i64, P, P, i64, P, P, P]
         lib.or_transform_f32.argtypes = [i64, P, P, P, ci]
+        lib.or_blur.argtypes = [ci, ci, i64, P, P, ctypes.c_double]
+        lib.or_blur.restype = ci
         _lib = lib
     return _lib
 
@@ -161,6 +163,41 @@ def lattice_slice(lat: Lattice, feat_rows: np.ndarray, return_touched: bool = Fa
     if return_touched:
         return out, int(touched[: lat.n_vertices].sum())
     return out
+
+
+def blur_output_scale(d: int) -> float:
+    """Output scale 1 / (1 + 2^-d) of the published permutohedral filter (the cited Adams et al. method)."""
+    return 1.0 / (1.0 + 2.0 ** (-d))
+
+
+def lattice_blur(lat: Lattice) -> Lattice:
+    """The uncustomised filter's blur: d+1 passes of [1/4, 1/2, 1/4] along the lattice directions,
+    then the output scale; a new Lattice with the blurred values (keys and occupancy shared)."""
+    vals = np.ascontiguousarray(lat.vals, dtype=np.float64).copy()
+    if lat.n_vertices:
+        if _L().or_blur(lat.d, vals.shape[1], lat.n_vertices, _p(np.ascontiguousarray(lat.keys)), _p(vals),
+                        blur_output_scale(lat.d)) != 0:
+            raise MemoryError("oracle blur: out of memory")
+    return Lattice(lat.keys, lat.occ, vals, lat.k, lat.d)
+
+
+def joint_lattice(fy: np.ndarray, vals: np.ndarray, fx: np.ndarray, k: np.ndarray) -> Lattice:
+    """Splat of the augmented input of the uncustomised filter: the observation's features with its
+    values and the query features with zero values, so that the query simplices exist in the lattice."""
+    fy = np.asarray(fy, dtype=np.float32)
+    fx = np.asarray(fx, dtype=np.float32)
+    v = np.asarray(vals, dtype=np.float64)
+    rows = np.concatenate([fy.reshape(-1, len(k)), fx.reshape(-1, len(k))])
+    allv = np.concatenate([v, np.zeros((len(fx), v.shape[1]))])
+    return lattice_build(rows, allv, k)
+
+
+def estep_blurred(obs, obs_n, x32, n32, feat: int, residual: str, k: np.ndarray):
+    """E-step through the uncustomised filter: splat of [Y, X] with values [v_y, 0], blur, slice at X.
+    Returns M0, M1 and (point-to-plane) the normal sum, like estep()."""
+    lat = joint_lattice(features(obs, obs_n, feat), splat_values(obs, obs_n, residual), features(x32, n32, feat), k)
+    g = lattice_slice(lattice_blur(lat), features(x32, n32, feat))
+    return g[:, 0].copy(), g[:, 1:4].copy(), (g[:, 4:7].copy() if residual == "pt2pl" else None)
 
 
 def brute_force_lattice_sum(fy, vals, fx, k):
@@ -425,6 +462,32 @@ def register_rigid_sigma(model, model_n, obs, obs_n, *, feat, residual, sigma0, 
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy(), sigma=sig, var=vs, sum_w=ws))
     return T, sig
+
+
+def register_rigid_blurred(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n=0.5, c=None, w=0.1,
+                           iters=20, T0=None, history: Optional[list] = None):
+    """Rigid EM with the uncustomised filter: every iteration splats the observation together with the
+    moved model, blurs and slices (the index depends on X, so it is rebuilt each iteration), then one
+    Gauss-Newton step as in register_rigid.  Returns the float64 pose."""
+    T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
+    if c is None:
+        c = outlier_constant(w, len(obs), len(model), sigma)
+    sig_m = float(np.mean(sigma))
+    k = scale_factors(feature_sigmas(feat, sigma, sigma_n))
+    model = np.asarray(model, dtype=np.float32)
+    for _ in range(iters):
+        mat = pose_to_mat12(T)
+        x32 = transform_f32(mat, model)
+        n32 = transform_f32(mat, model_n, translate=False) if feat == 6 else None
+        m0, m1, ns = estep_blurred(obs, obs_n, x32, n32, feat, residual, k)
+        R32 = mat.reshape(3, 4).astype(np.float64)
+        x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
+        A, b, stats = normal_equations(x64, m0, m1, ns, c, sig_m, residual)
+        dz = gn_step(A, b)
+        T = se3_exp(dz) @ T
+        if history is not None:
+            history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
+    return T
 
 
 def alignment_error(T, T_gt, x_ref) -> float:

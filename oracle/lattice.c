@@ -239,6 +239,56 @@ void or_slice(int d, int nv, int64_t n_v, const int32_t *keys, const double *lat
     }
 }
 
+/* ----------------------------------------------------------------------- */
+/* Blur: the uncustomised permutohedral filter (the cited Adams et al.      */
+/* method, referred to by Sec. 4.2 and rebuilt per iteration in Sec. 3.1).  */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * The d+1 lattice directions of the (d+1)-scaled A*_d lattice are the vectors
+ * with every coordinate +1 except coordinate j, which is -d (they sum to zero
+ * and connect a vertex to its nearest neighbours of the same remainder class).
+ * A pass along direction j replaces each vertex value by
+ *   1/2 v(x) + 1/4 v(x + e_j) + 1/4 v(x - e_j),
+ * reading the previous pass's values; vertices absent from the lattice read as
+ * 0 and are not created.  Passes run for j = 0..d in order; the values are
+ * finally multiplied by `scale`.  `vals` (n_v x nv) is updated in place; keys
+ * must be in lexicographic order (as or_lattice_build leaves them).  Returns
+ * 0, or -1 when out of memory.
+ */
+int or_blur(int d, int nv, int64_t n_v, const int32_t *keys, double *vals, double scale)
+{
+    if (n_v <= 0) return 0;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n_v * nv));
+    if (!tmp) return -1;
+    int32_t up[OR_MAXD], dn[OR_MAXD];
+    for (int j = 0; j <= d; j++) {
+        for (int64_t v = 0; v < n_v; v++) {
+            const int32_t *key = keys + v * d;
+            for (int i = 0; i < d; i++) {
+                up[i] = key[i] + 1;
+                dn[i] = key[i] - 1;
+            }
+            if (j < d) {
+                up[j] = key[j] - d;
+                dn[j] = key[j] + d;
+            }
+            const int64_t a = find_key(keys, n_v, d, up);
+            const int64_t b = find_key(keys, n_v, d, dn);
+            for (int c = 0; c < nv; c++) {
+                double s = 0.5 * vals[v * nv + c];
+                if (a >= 0) s += 0.25 * vals[a * nv + c];
+                if (b >= 0) s += 0.25 * vals[b * nv + c];
+                tmp[v * nv + c] = s;
+            }
+        }
+        memcpy(vals, tmp, sizeof(double) * (size_t)(n_v * nv));
+    }
+    for (int64_t q = 0; q < n_v * nv; q++) vals[q] *= scale;
+    free(tmp);
+    return 0;
+}
+
 /*
  * Brute force of the same kernel, with no lattice at all:
  *   out[i] = sum_j K(q_i, y_j) vals_j,
