@@ -308,7 +308,39 @@ def other_workloads(fr, ctx, reps=5):
                               "iters": p.iters, "registration_ms": ms, "build_ms": rep.build_ms,
                               "pcg_iters_last": rep.solver_iters}
     out["updated_sigma"] = updated_sigma_workloads(fr, ctx)
+    out["uncustomised_filter"] = uncustomised_filter_workloads(fr, ctx)
     return out
+
+
+def uncustomised_filter_workloads(fr, ctx, n_pairs=8, max_iters=60, tol=1e-4):
+    """The customised filter (lattice of Y built once, no blur) against the uncustomised one (joint
+    lattice of Y and the moved X, blurred, rebuilt every iteration): the ellipsoid sweep of
+    updated_sigma_workloads and one 640x480 depth frame, 20 iterations from near the ground truth."""
+    rows = {"customised": [], "uncustomised": []}
+    for seed in range(n_pairs):
+        p = synth.ellipsoid_pair(100 + seed, max_angle_deg=10.0, max_trans=0.05, noise=0.01)
+        m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+        for name, blurred in (("customised", False), ("uncustomised", True)):
+            prm = fr.register_params(3, "pt2pt", p.sigma, iters=max_iters, w=p.w, tol=tol, fixed=False,
+                                     blurred=blurred)
+            ms, (T, st, rep) = _timed(lambda: fr.register(ctx, m, o, prm), 3)
+            rows[name].append((rep.iterations, ms, alignment_error(T[0], p.T_gt, p.model)))
+    res = {"pairs": n_pairs, "start": "identity; motions up to 10 deg, 5 cm", "noise": 0.01, "sigma": 0.02,
+           "stop": f"twist below {tol} or {max_iters} iterations"}
+    for k, v in rows.items():
+        a = np.array(v)
+        res[k] = {"mean_iterations": float(a[:, 0].mean()), "mean_ms": float(a[:, 1].mean()),
+                  "mean_error_m": float(a[:, 2].mean()), "converged_below_5mm": int((a[:, 2] < 5e-3).sum())}
+    p = synth.depth_pair(0)
+    m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+    for name, blurred in (("customised", False), ("uncustomised", True)):
+        prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, profile=True, blurred=blurred)
+        ms, (T, st, rep) = _timed(lambda: fr.register(ctx, m, o, prm), 3)
+        res["depth_pt2pl_20_iters_" + name] = {
+            "model_points": len(p.model), "obs_points": len(p.obs), "registration_ms": ms,
+            "build_ms_total": rep.build_ms, "estep_ms_per_launch": rep.estep_ms / max(1, rep.estep_launches),
+            "error_m": alignment_error(T[0], p.T_gt, p.model)}
+    return res
 
 
 def updated_sigma_workloads(fr, ctx, n_pairs=8, max_iters=60, tol=1e-4):

@@ -54,7 +54,7 @@ enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
 enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
 enum { FR_PT2PT = 0, FR_PT2PL = 1 };
 enum { FR_KIN_RIGID = 0, FR_KIN_ARTICULATED = 1, FR_KIN_NODEGRAPH = 2 };
-enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4 };
+enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4, FR_BLURRED = 8 };
 
 typedef struct fr_ctx fr_ctx;
 typedef struct fr_lattice fr_lattice;
@@ -141,6 +141,32 @@ typedef struct {
 } fr_xform;
 
 /*
+ * The uncustomised permutohedral filter (the cited Adams et al. method that
+ * Sec. 4.2 customises; Sec. 3.1: with it the index depends on X and is rebuilt
+ * every EM iteration).  fr_lattice_build_joint splats, per set, the
+ * observation points with their values [1, y(, n_y)] together with the model
+ * points moved by `xf` (FR_XF_NONE, or FR_XF_RIGID with one binary32 [R | t]
+ * per set in device memory) with no value, so that every simplex the E-step
+ * will read at those model points exists; occupancy counts the incidences of
+ * both.  values must be FR_VAL_PT2PT or FR_VAL_PT2PL.  Synchronises like
+ * fr_lattice_build.
+ */
+fr_status fr_lattice_build_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model_ref, const fr_xform *xf,
+                                 const fr_lattice_params *params, void *stream, fr_lattice **out);
+
+/*
+ * Blur of the uncustomised filter, in place: for each lattice direction j =
+ * 0..d in turn (every coordinate +1, coordinate j -d), every vertex takes 1/2
+ * its value plus 1/4 of each of its two neighbours along j from the previous
+ * pass (absent neighbours read as 0, none are created); the result is scaled
+ * by 1 / (1 + 2^-d) (the published filter's output scale).  A slice of the
+ * blurred lattice (fr_estep) is the filter's output.  Table and exported
+ * vertex values are replaced; keys and occupancy are kept.  FR_EINVAL for the
+ * |y|^2 layouts.
+ */
+fr_status fr_lattice_blur(fr_lattice *lat, void *stream);
+
+/*
  * E-step through the lattice (Eq. 6, Eq. 9 via Eq. 11): for every model point
  * of every set, slice the set's lattice at the transformed point's feature:
  *   m0[i]           = sum_k b_k value_0[v_k]                  (device, M)
@@ -225,7 +251,10 @@ typedef struct {
     double c_override;     /* >= 0: use this c for every set instead; < 0: derive from w */
     double twist_tol;      /* stop a set when |omega| and |v| of its step are below this */
     int32_t flags;         /* FR_FIXED_ITERS | FR_PROFILE_EVENTS | FR_FUSED (slice and reduction in one
-                              kernel: same terms, binary32 partial sums taken in another order) */
+                              kernel: same terms, binary32 partial sums taken in another order) |
+                              FR_BLURRED (the uncustomised filter: every iteration builds the joint
+                              lattice of the observation and the moved model and blurs it, as
+                              fr_lattice_build_joint + fr_lattice_blur; not with FR_FUSED) */
     int32_t kinematics;    /* FR_KIN_RIGID */
 } fr_register_params;
 

@@ -39,7 +39,7 @@ FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
 FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
 FR_KIN_RIGID, FR_KIN_ARTICULATED, FR_KIN_NODEGRAPH = 0, 1, 2
-FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED = 1, 2, 4
+FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED, FR_BLURRED = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
                 5: "FR_EDEGENERATE", 6: "FR_EDEVICE"}
@@ -125,6 +125,9 @@ _sig("fr_ctx_destroy", _st, [_P])
 _sig("fr_ctx_usage", _st, [_P, ctypes.POINTER(ctypes.c_size_t)])
 _sig("fr_lattice_build", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_lattice_params), _P,
                                ctypes.POINTER(_P)])
+_sig("fr_lattice_build_joint", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform),
+                                     ctypes.POINTER(fr_lattice_params), _P, ctypes.POINTER(_P)])
+_sig("fr_lattice_blur", _st, [_P, _P])
 _sig("fr_lattice_destroy", _st, [_P])
 _sig("fr_lattice_stats", _st, [_P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int64)])
@@ -157,8 +160,8 @@ _sig("fr_engine_read", _st, [_P, _P, _P])
 _sig("fr_engine_release", _st, [_P, _i32, _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
-                 "fr_lattice_build", "fr_lattice_destroy", "fr_lattice_stats", "fr_lattice_export", "fr_estep",
-                 "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
+                 "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
+                 "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
                  "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph",
                  "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
@@ -282,6 +285,17 @@ def fr_lattice_build(ctx, obs: Cloud, params: fr_lattice_params, stream=None):
     return h
 
 
+def fr_lattice_build_joint(ctx, obs: Cloud, model: Cloud, xf: "XForm", params: fr_lattice_params, stream=None):
+    h = _P()
+    _check(_lib.fr_lattice_build_joint(ctx, obs.c(), model.c(), xf.c(), ctypes.byref(params), _stream(stream),
+                                       ctypes.byref(h)))
+    return h
+
+
+def fr_lattice_blur(lat, stream=None):
+    _check(_lib.fr_lattice_blur(lat, _stream(stream)))
+
+
 def fr_lattice_destroy(lat):
     _check(_lib.fr_lattice_destroy(lat))
 
@@ -384,11 +398,20 @@ class Context:
 
 
 class Lattice:
-    def __init__(self, ctx: Context, obs: Cloud, params: fr_lattice_params, stream=None):
+    def __init__(self, ctx: Context, obs: Cloud, params: fr_lattice_params, stream=None, model: "Cloud" = None,
+                 xf: "XForm" = None):
+        """The observation's lattice; with `model`, the joint lattice of the uncustomised filter (the model
+        moved by `xf` splatted with no value)."""
         self.ctx = ctx
         self.params = params
         self.n_sets = obs.n_sets
-        self.h = fr_lattice_build(ctx.h, obs, params, stream)
+        if model is None:
+            self.h = fr_lattice_build(ctx.h, obs, params, stream)
+        else:
+            self.h = fr_lattice_build_joint(ctx.h, obs, model, xf if xf is not None else XForm(), params, stream)
+
+    def blur(self, stream=None):
+        fr_lattice_blur(self.h, stream)
 
     @property
     def d(self):
@@ -426,10 +449,11 @@ def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
 
 def register_params(feat: int, residual: str, sigma, sigma_n=0.5, iters=20, w=0.1, c=None, tol=1e-6,
                     fixed=True, profile=False, splat=FR_SPLAT_SORTED, fused=False,
-                    m2=False) -> fr_register_params:
+                    m2=False, blurred=False) -> fr_register_params:
     res = FR_PT2PL if residual == "pt2pl" else FR_PT2PT
     vals = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
-    flags = (FR_FIXED_ITERS if fixed else 0) | (FR_PROFILE_EVENTS if profile else 0) | (FR_FUSED if fused else 0)
+    flags = (FR_FIXED_ITERS if fixed else 0) | (FR_PROFILE_EVENTS if profile else 0) | (FR_FUSED if fused else 0) | \
+        (FR_BLURRED if blurred else 0)
     if m2:
         vals = FR_VAL_PT2PL_M2 if residual == "pt2pl" else FR_VAL_PT2PT_M2
     return fr_register_params(lattice_params(feat, vals, sigma, sigma_n, splat), res, iters, float(w),

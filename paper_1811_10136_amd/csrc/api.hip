@@ -321,7 +321,8 @@ void scale_factors(const fr_lattice_params *p, float *k)
 }
 
 fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
-                             fr_lattice **out, const double *sigma_set)
+                             fr_lattice **out, const double *sigma_set, const fr_cloud *joint_model,
+                             const float *joint_mats)
 {
     fr_lattice *lat = new (std::nothrow) fr_lattice();
     if (!lat) {
@@ -334,7 +335,7 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
     lat->KW = (params->feat + 2) / 3;
     lat->n_sets = obs->n_sets;
     lat->splat = params->splat;
-    lat->n_points_total = cloud_points(obs);
+    lat->n_points_total = cloud_points(obs) + (joint_model ? cloud_points(joint_model) : 0);
     scale_factors(params, lat->k);
     lat->kset.resize((size_t)8 * obs->n_sets);
     for (int32_t q = 0; q < obs->n_sets; ++q) {
@@ -347,7 +348,9 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
         }
     }
     fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
-    if (s == FR_OK) s = build_lattice(ctx, obs, params, st, lat);
+    if (s == FR_OK)
+        s = joint_model ? build_joint_lattice(ctx, obs, joint_model, joint_mats, params, st, lat)
+                        : build_lattice(ctx, obs, params, st, lat);
     if (s != FR_OK) {
         free_lattice(lat, st, false);
         lat->magic = kDeadMagic;
@@ -473,6 +476,49 @@ fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_pa
     FR_HIP(hipSetDevice(ctx->device));
     StreamScope scope(static_cast<hipStream_t>(stream));
     return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out);
+}
+
+fr_status fr_lattice_build_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model_ref, const fr_xform *xf,
+                                 const fr_lattice_params *params, void *stream, fr_lattice **out)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || out == nullptr) {
+        set_error("fr_lattice_build_joint: invalid context or out pointer");
+        return FR_EINVAL;
+    }
+    *out = nullptr;
+    FR_TRY(check_lattice_params(params));
+    if (params->values != FR_VAL_PT2PT && params->values != FR_VAL_PT2PL) {
+        set_error("fr_lattice_build_joint: values must be FR_VAL_PT2PT or FR_VAL_PT2PL");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(obs, params->feat == 6 || params->values >= 7, "fr_lattice_build_joint(obs)"));
+    FR_TRY(check_cloud(model_ref, params->feat == 6, "fr_lattice_build_joint(model)"));
+    if (model_ref->n_sets != obs->n_sets) {
+        set_error("fr_lattice_build_joint: model has %d sets, observation %d", model_ref->n_sets, obs->n_sets);
+        return FR_EINVAL;
+    }
+    if (xf != nullptr && xf->kind != FR_XF_NONE &&
+        (xf->kind != FR_XF_RIGID || xf->mats == nullptr || (xf->n_seg != 0 && xf->n_seg != obs->n_sets))) {
+        set_error("fr_lattice_build_joint: xform must be FR_XF_NONE or FR_XF_RIGID with one matrix per set");
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(ctx->device));
+    StreamScope scope(static_cast<hipStream_t>(stream));
+    const float *mats = (xf != nullptr && xf->kind == FR_XF_RIGID) ? xf->mats : nullptr;
+    return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out, nullptr, model_ref, mats);
+}
+
+fr_status fr_lattice_blur(fr_lattice *lat, void *stream)
+{
+    clear_error();
+    if (!lat_ok(lat)) {
+        set_error("fr_lattice_blur: invalid lattice");
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    StreamScope scope(static_cast<hipStream_t>(stream));
+    return blur_lattice(lat, static_cast<hipStream_t>(stream));
 }
 
 fr_status fr_lattice_destroy(fr_lattice *lat)
@@ -717,6 +763,14 @@ fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double
                               static_cast<hipStream_t>(stream));
 }
 
+// Stream-ordered release of a lattice the caller's loop no longer reads.
+static void release_lattice(fr_lattice *lat, hipStream_t st)
+{
+    free_lattice(lat, st, false);
+    lat->magic = kDeadMagic;
+    delete lat;
+}
+
 fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_register_params *params,
                       double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream)
 {
@@ -744,6 +798,11 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         set_error("fr_register: max_iters >= 0, rigid kinematics and 0 <= w < 1 are required");
         return FR_EINVAL;
     }
+    const bool blurred = (params->flags & FR_BLURRED) != 0;
+    if (blurred && (params->flags & FR_FUSED) != 0) {
+        set_error("fr_register: FR_BLURRED and FR_FUSED cannot be combined");
+        return FR_EINVAL;
+    }
     FR_TRY(check_cloud(model_ref, params->lattice.feat == 6, "fr_register(model)"));
     FR_TRY(check_cloud(obs, params->lattice.feat == 6 || params->lattice.values >= 7, "fr_register(obs)"));
     if (model_ref->n_sets != obs->n_sets) {
@@ -759,7 +818,8 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
 
     auto t0 = clk::now();
     fr_lattice *lat = nullptr;
-    FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat));
+    // the uncustomised filter's lattice depends on the pose: built in the loop
+    if (!blurred) FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat));
     struct LatGuard {
         fr_lattice *l;
         ~LatGuard()
@@ -821,6 +881,17 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     auto t2 = clk::now();
     int it = 0;
     for (; it < max_it; ++it) {
+        if (blurred) {
+            auto tb = clk::now();
+            if (lat != nullptr) {
+                release_lattice(lat, st);
+                lat = guard.l = nullptr;
+            }
+            FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, nullptr, model_ref, wmats.as<float>()));
+            guard.l = lat;
+            FR_TRY(blur_lattice(lat, st));
+            rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+        }
         if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
         if (fused) {
             FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
@@ -880,8 +951,9 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         if (status_h) status_h[s] = status_v[s];
     }
     rep.n_degenerate = n_deg;
+    if (blurred) rep.em_ms -= rep.build_ms - std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (report_h) *report_h = rep;
-    FR_TRY(fr_sync_status(lat));
+    if (lat != nullptr) FR_TRY(fr_sync_status(lat));
     if (n_deg > 0) {
         set_error("fr_register: %d set(s) had a degenerate normal-equation system", n_deg);
         return FR_EDEGENERATE;

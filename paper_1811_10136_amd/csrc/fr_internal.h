@@ -115,8 +115,12 @@ bool ctx_ok(const fr_ctx *c);
 fr_status check_lattice_params(const fr_lattice_params *p);
 // sigma_set (host, n_sets, may be NULL): an isotropic position sigma per set
 // in place of params->sigma (the normal sigma stays params->sigma_n).
+// joint_model (may be NULL): build the uncustomised filter's joint lattice of
+// the observation and the model moved by joint_mats (device, n_sets x 12, or
+// NULL for the identity); the model points carry no value.
 fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
-                             fr_lattice **out, const double *sigma_set = nullptr);
+                             fr_lattice **out, const double *sigma_set = nullptr,
+                             const fr_cloud *joint_model = nullptr, const float *joint_mats = nullptr);
 void scale_factors(const fr_lattice_params *p, float *k);
 double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns);
 void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle = false);
@@ -172,8 +176,15 @@ fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what);
 
 // --- launchers ---------------------------------------------------------------
 // lattice_build.hip
-fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t stream,
-                        fr_lattice *lat);
+fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
+                        fr_lattice *lat, const int64_t *valued_end = nullptr);
+// Joint splat of each set's observation (valued) and its model moved by mats
+// (device, n_sets x 12 [R | t], or NULL), for the uncustomised filter.
+fr_status build_joint_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model, const float *mats,
+                              const fr_lattice_params *prm, hipStream_t st, fr_lattice *lat);
+// d+1 passes of [1/4, 1/2, 1/4] along the lattice directions, then the output
+// scale 1 / (1 + 2^-d); table and vertex values are replaced.
+fr_status blur_lattice(fr_lattice *lat, hipStream_t st);
 
 // estep.hip
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,

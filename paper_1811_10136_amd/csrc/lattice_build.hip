@@ -236,7 +236,7 @@ struct Pts {
 // records in LDS so the global writes are contiguous.
 template <int d>
 __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, const float *kset, uint64_t *rec_key,
-                                                  float *rec_b, size_t R, int32_t *err)
+                                                  float *rec_b, size_t R, int32_t *err, const int64_t *valued_end)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -264,6 +264,10 @@ __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, const fl
         uint64_t keys[D][KW];
         float b[D];
         if (!embed<d>(p, kk, keys, b)) atomicOr(err, 1);
+        // points past valued_end[s] create their vertices but carry no value
+        const float keep = (valued_end == nullptr || i < valued_end[s]) ? 1.0f : 0.0f;
+#pragma unroll
+        for (int v = 0; v < D; ++v) b[v] *= keep;
 #pragma unroll
         for (int v = 0; v < D; ++v) {
 #pragma unroll
@@ -589,7 +593,8 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
 }
 
 template <int d, int V>
-static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat)
+static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat,
+                            const int64_t *valued_end)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -621,7 +626,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
     if (ptm.n_tiles > 0) {
         k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), rec_key.as<uint64_t>(),
-                                                    rec_b.as<float>(), R, lat->err_d);
+                                                    rec_b.as<float>(), R, lat->err_d, valued_end);
         FR_HIP(hipGetLastError());
     }
     // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
@@ -814,17 +819,242 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
 }
 
 fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
-                        fr_lattice *lat)
+                        fr_lattice *lat, const int64_t *valued_end)
 {
-    if (prm->feat == 3 && prm->values == 4) return build_impl<3, 4>(ctx, obs, st, lat);
-    if (prm->feat == 3 && prm->values == 7) return build_impl<3, 7>(ctx, obs, st, lat);
-    if (prm->feat == 6 && prm->values == 4) return build_impl<6, 4>(ctx, obs, st, lat);
-    if (prm->feat == 6 && prm->values == 7) return build_impl<6, 7>(ctx, obs, st, lat);
-    if (prm->feat == 3 && prm->values == 5) return build_impl<3, 5>(ctx, obs, st, lat);
-    if (prm->feat == 3 && prm->values == 8) return build_impl<3, 8>(ctx, obs, st, lat);
-    if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat);
-    if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat);
+    const int64_t *ve = valued_end;
+    if (prm->feat == 3 && prm->values == 4) return build_impl<3, 4>(ctx, obs, st, lat, ve);
+    if (prm->feat == 3 && prm->values == 7) return build_impl<3, 7>(ctx, obs, st, lat, ve);
+    if (prm->feat == 6 && prm->values == 4) return build_impl<6, 4>(ctx, obs, st, lat, ve);
+    if (prm->feat == 6 && prm->values == 7) return build_impl<6, 7>(ctx, obs, st, lat, ve);
+    if (prm->feat == 3 && prm->values == 5) return build_impl<3, 5>(ctx, obs, st, lat, ve);
+    if (prm->feat == 3 && prm->values == 8) return build_impl<3, 8>(ctx, obs, st, lat, ve);
+    if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat, ve);
+    if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat, ve);
     set_error("fr_lattice_build: unsupported feat=%d values=%d", prm->feat, prm->values);
+    return FR_EINVAL;
+}
+
+// ---------------------------------------------------------------------------
+// Uncustomised filter: joint splat of [Y, X] and the blur of the cited
+// permutohedral method
+// ---------------------------------------------------------------------------
+
+// One thread per point of the joint cloud: set s holds its observation points
+// first (copied) and then its model points moved by the set's [R | t] (the
+// E-step's own pinned transform, so the slice finds the same simplices).
+struct JointArgs {
+    TileMap tm;                       // segments = sets of the joint cloud
+    const int64_t *obs_off, *model_off;
+    Pts obs, model;
+    const float *mats;                // n_sets x 12, or NULL (identity)
+    float *x, *y, *z, *nx, *ny, *nz;  // joint cloud (normals may be NULL)
+};
+
+__global__ void __launch_bounds__(256) k_joint_points(JointArgs a)
+{
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_end[s]) return;
+    const int64_t local = i - a.tm.seg_off[s];
+    const int64_t n_obs = a.obs_off[s + 1] - a.obs_off[s];
+    float px, py, pz, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+    if (local < n_obs) {
+        const int64_t j = a.obs_off[s] + local;
+        px = a.obs.x[j];
+        py = a.obs.y[j];
+        pz = a.obs.z[j];
+        if (a.obs.nx != nullptr) {
+            qx = a.obs.nx[j];
+            qy = a.obs.ny[j];
+            qz = a.obs.nz[j];
+        }
+    } else {
+        const int64_t j = a.model_off[s] + local - n_obs;
+        px = a.model.x[j];
+        py = a.model.y[j];
+        pz = a.model.z[j];
+        if (a.model.nx != nullptr) {
+            qx = a.model.nx[j];
+            qy = a.model.ny[j];
+            qz = a.model.nz[j];
+        }
+        if (a.mats != nullptr) {
+            const float *m = a.mats + 12 * (size_t)s;
+            xform_point(m, px, py, pz, px, py, pz);
+            xform_normal(m, qx, qy, qz, qx, qy, qz);
+        }
+    }
+    a.x[i] = px;
+    a.y[i] = py;
+    a.z[i] = pz;
+    if (a.nx != nullptr) {
+        a.nx[i] = qx;
+        a.ny[i] = qy;
+        a.nz[i] = qz;
+    }
+}
+
+fr_status build_joint_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model, const float *mats,
+                              const fr_lattice_params *prm, hipStream_t st, fr_lattice *lat)
+{
+    const int32_t S = obs->n_sets;
+    std::vector<int64_t> off(S + 1, 0), vend(S);
+    for (int32_t s = 0; s < S; ++s) {
+        const int64_t no = obs->offsets[s + 1] - obs->offsets[s], nm = model->offsets[s + 1] - model->offsets[s];
+        off[s + 1] = off[s] + no + nm;
+        vend[s] = off[s] + no;
+    }
+    const int64_t T = off[S];
+    const bool normals = obs->nx != nullptr;
+    DevBuf pts, offs, tmap;
+    FR_TRY(pts.alloc(ctx, std::max<int64_t>(T, 1) * (normals ? 6 : 3) * sizeof(float)));
+    FR_TRY(offs.alloc(ctx, (3 * (size_t)S + 2) * sizeof(int64_t)));
+    int64_t *od = offs.as<int64_t>();
+    FR_HIP(hipMemcpyAsync(od, obs->offsets, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(od + S + 1, model->offsets, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(od + 2 * S + 2, vend.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    TileMap tm{};
+    FR_TRY(make_offset_map(ctx, off, 256, st, tmap, tm));   // synchronises: the host vectors are free after
+    float *base = pts.as<float>();
+    const size_t n = (size_t)std::max<int64_t>(T, 1);
+    JointArgs a{tm, od, od + S + 1, Pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz},
+                Pts{model->x, model->y, model->z, model->nx, model->ny, model->nz}, mats, base, base + n,
+                base + 2 * n, normals ? base + 3 * n : nullptr, normals ? base + 4 * n : nullptr,
+                normals ? base + 5 * n : nullptr};
+    if (tm.n_tiles > 0) {
+        k_joint_points<<<tm.n_tiles, 256, 0, st>>>(a);
+        FR_HIP(hipGetLastError());
+    }
+    fr_cloud joint{a.x, a.y, a.z, a.nx, a.ny, a.nz, off.data(), S};
+    return build_lattice(ctx, &joint, prm, st, lat, od + 2 * S + 2);
+}
+
+// Neighbour of a packed key along lattice direction j (0 <= j <= d): every
+// coordinate +sgn, coordinate j (stored only for j < d) -sgn d.  False when a
+// coordinate would leave the packed range (such a vertex cannot exist).
+template <int d>
+__device__ __forceinline__ bool neighbour_key(const uint64_t (&key)[KeyWords<d>::value], int j, int sgn,
+                                              uint64_t (&out)[KeyWords<d>::value])
+{
+    constexpr int KW = KeyWords<d>::value;
+    bool ok = true;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) out[w] = 0;
+#pragma unroll
+    for (int i = 0; i < d; ++i) {
+        const int32_t c = unpack_coord(key, i) + (i == j ? -sgn * d : sgn);
+        ok = ok && c >= -kKeyBias && c < kKeyBias;
+        out[i / 3] |= (uint64_t)((uint32_t)(c + kKeyBias) & ((1u << kKeyBits) - 1u)) << (kKeyBits * (2 - (i % 3)));
+    }
+    return ok;
+}
+
+// One blur pass along direction `dir`: every slot of every set (one thread per
+// slot) takes 1/2 its own values plus 1/4 of each neighbour's, read from `tin`;
+// absent neighbours read as zero; empty slots stay zero.  `scale` multiplies
+// the result (the filter's output scale on the last pass, 1 before).
+template <int d, int V>
+__global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *sets, int dir, const float *tin,
+                                                  float *tout, float scale)
+{
+    constexpr int KW = KeyWords<d>::value;
+    constexpr int VP = ValPad<V>::value;
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;
+    const int32_t s = tile_segment(tm, t);
+    const int64_t q = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
+    if (q >= tm.seg_end[s]) return;
+    const SetTable st = sets[tm.seg_set[s]];
+    uint64_t key[KW];
+    load_key<KW>(st.keys, (uint32_t)(q - (int64_t)st.slot_base), key);
+    float acc[VP];
+#pragma unroll
+    for (int c = 0; c < VP; ++c) acc[c] = 0.0f;
+    if (key[0] != kKeyEmpty) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] = 0.5f * tin[(size_t)VP * q + c];
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            uint64_t nk[KW];
+            if (!neighbour_key<d>(key, dir, sgn, nk)) continue;
+            const int64_t r = find_slot<KW>(st.keys, st, nk);
+            if (r < 0) continue;
+            const float *src = tin + (size_t)VP * (st.slot_base + (uint64_t)r);
+#pragma unroll
+            for (int c = 0; c < V; ++c) acc[c] = fmaf(0.25f, src[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] *= scale;
+    }
+    float4 *dst = reinterpret_cast<float4 *>(tout + (size_t)VP * q);
+    dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if constexpr (VP == 8) dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+}
+
+// Copy the table values back to the vertex arrays (export reads those).
+template <int d, int V>
+__global__ void __launch_bounds__(256) k_table_to_vertices(TileMap tm, const SetTable *sets, const uint64_t *vkey,
+                                                          size_t NV, const float *tval, float *vval)
+{
+    constexpr int KW = KeyWords<d>::value;
+    constexpr int VP = ValPad<V>::value;
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;
+    const int32_t s = tile_segment(tm, t);
+    const int64_t v = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
+    if (v >= tm.seg_end[s]) return;
+    const SetTable st = sets[tm.seg_set[s]];
+    uint64_t key[KW];
+#pragma unroll
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
+    const int64_t r = find_slot<KW>(st.keys, st, key);
+    if (r < 0) return;   // cannot happen: every vertex sits in its set's table
+    const float *src = tval + (size_t)VP * (st.slot_base + (uint64_t)r);
+#pragma unroll
+    for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = src[c];
+}
+
+template <int d, int V>
+static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
+{
+    constexpr int VP = ValPad<V>::value;
+    fr_ctx *ctx = lat->ctx;
+    const int32_t S = lat->n_sets;
+    std::vector<int64_t> soff(S + 1, 0);
+    for (int32_t s = 0; s < S; ++s) soff[s + 1] = soff[s] + lat->sets_h[s].cap;
+    DevBuf tmp, smap, vmap;
+    TileMap stm{}, vtm{};
+    FR_TRY(make_offset_map(ctx, soff, 256, st, smap, stm));
+    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vmap, vtm));
+    const size_t n = (size_t)lat->n_slots;
+    if (n == 0) return FR_OK;
+    FR_TRY(tmp.alloc(ctx, n * VP * sizeof(float)));
+    float *bufs[2] = {lat->tval, tmp.as<float>()};
+    const float scale = (float)(1.0 / (1.0 + std::ldexp(1.0, -d)));
+    for (int j = 0; j <= d; ++j) {
+        k_blur_pass<d, V><<<stm.n_tiles, 256, 0, st>>>(stm, lat->sets_d, j, bufs[j & 1], bufs[(j + 1) & 1],
+                                                       j == d ? scale : 1.0f);
+        FR_HIP(hipGetLastError());
+    }
+    if (((d + 1) & 1) != 0)   // an odd number of passes ends in the scratch table
+        FR_HIP(hipMemcpyAsync(lat->tval, tmp.p, n * VP * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (vtm.n_tiles > 0) {
+        k_table_to_vertices<d, V><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey,
+                                                               (size_t)lat->n_vertices_total, lat->tval, lat->vval);
+        FR_HIP(hipGetLastError());
+    }
+    return FR_OK;
+}
+
+fr_status blur_lattice(fr_lattice *lat, hipStream_t st)
+{
+    if (lat->d == 3 && lat->V == 4) return blur_impl<3, 4>(lat, st);
+    if (lat->d == 3 && lat->V == 7) return blur_impl<3, 7>(lat, st);
+    if (lat->d == 6 && lat->V == 4) return blur_impl<6, 4>(lat, st);
+    if (lat->d == 6 && lat->V == 7) return blur_impl<6, 7>(lat, st);
+    set_error("fr_lattice_blur: values must be FR_VAL_PT2PT or FR_VAL_PT2PL");
     return FR_EINVAL;
 }
 
