@@ -490,6 +490,47 @@ def register_rigid_blurred(model, model_n, obs, obs_n, *, feat, residual, sigma,
     return T
 
 
+def feature_outlier_constant(w: float, n_obs: int, n_model: int, sigma_f: float, dim: int) -> float:
+    """c of Eq. (7) for a kernel over `dim` feature dimensions of width sigma_f (Eq. 8): the uniform
+    term over the dropped Gaussian normaliser (2 pi)^(dim/2) sigma_f^dim."""
+    if n_model == 0 or w <= 0.0:
+        return 0.0
+    return float(w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** (dim / 2.0) * sigma_f ** dim)
+
+
+def feature_lattice(obs, obs_feat, sigma_f: float) -> Lattice:
+    """The observation's lattice over descriptor space (Eq. 8), values [1, y]."""
+    f = np.ascontiguousarray(obs_feat, dtype=np.float32)
+    k = scale_factors(np.full(f.shape[1], float(sigma_f)))
+    return lattice_build(f, splat_values(obs, None, "pt2pt"), k)
+
+
+def register_rigid_features(model, model_feat, obs, obs_feat, *, sigma_f, w=0.2, c=None, iters=20, T0=None,
+                            history: Optional[list] = None):
+    """Rigid registration by descriptors (Sec. 3.3 "Features", Eq. 8 with the features alone): the
+    kernel does not involve the pose, so one E-step gives fixed targets M1/M0 and weights, and the
+    EM iterations are Gauss-Newton steps of Eq. (17) toward them (point-to-point, unit residual
+    scale).  Returns the float64 pose."""
+    T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
+    dim = np.asarray(model_feat).shape[1]
+    if c is None:
+        c = feature_outlier_constant(w, len(obs), len(model), sigma_f, dim)
+    lat = feature_lattice(obs, obs_feat, sigma_f)
+    g = lattice_slice(lat, np.ascontiguousarray(model_feat, dtype=np.float32))
+    m0, m1 = g[:, 0].copy(), g[:, 1:4].copy()
+    model = np.asarray(model, dtype=np.float32)
+    for _ in range(iters):
+        mat = pose_to_mat12(T)
+        R32 = mat.reshape(3, 4).astype(np.float64)
+        x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
+        A, b, stats = normal_equations(x64, m0, m1, None, c, 1.0, "pt2pt")
+        dz = gn_step(A, b)
+        T = se3_exp(dz) @ T
+        if history is not None:
+            history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy(), m0=m0, m1=m1))
+    return T
+
+
 def alignment_error(T, T_gt, x_ref) -> float:
     """Eq. (22): mean over reference points of |(T - T_gt) x|_2."""
     x = np.asarray(x_ref, dtype=np.float64)

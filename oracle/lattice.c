@@ -41,7 +41,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAXD 16
+#define OR_MAXD 32
 
 /* k_i = sqrt(2/3) (d+1) / (sigma_i sqrt((i+1)(i+2))), rounded once to binary32. */
 void or_scale_factors(int d, const double *sigma, float *k)

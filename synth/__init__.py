@@ -17,6 +17,10 @@ generators below stand in for them with clouds of the same structure:
 * ``articulated_pair``-- 20 capsule links, 32 revolute DOF (Sec. 5.1 / 6.4).
 * ``nodegraph_pair``  -- a displaced-sphere blob skinned to 512 nodes
   (Sec. 5.2 / 6.5).
+* ``feature_pair``    -- an object cloud with smooth unit-norm descriptors of
+  dimension 8-32, seen from an arbitrary pose with occlusion, noise and
+  background clutter (stands in for the learned-feature global registration
+  of Sec. 6.3, Tab. 2).
 * ``request_stream``  -- Poisson arrivals of depth pairs with log-uniform sizes.
 
 All arrays are row-major ``(n, 3)`` float32 unless stated; poses are 4x4
@@ -39,6 +43,7 @@ __all__ = [
     "separated_pair",
     "articulated_pair",
     "nodegraph_pair",
+    "feature_pair",
     "KinTree",
     "random_motion",
     "request_stream",
@@ -340,6 +345,56 @@ def separated_pair(seed: int, m: int = 400, sigma: float = 0.02, spacing: float 
     return Pair(model=_f32(x), obs=_f32(y), T_gt=T, sigma=(sigma, sigma, sigma), feat=feat,
                 residual=residual, iters=15, model_n=_f32(xn), obs_n=_f32(yn), w=0.0,
                 name=f"separated-{m}-seed{seed}", extra={"T0": T0})
+
+
+# ---------------------------------------------------------------------------
+# Feature registration: motion-invariant descriptors
+# ---------------------------------------------------------------------------
+
+def feature_pair(seed: int, m: int = 12000, dim: int = 16, sigma_f: float = 0.05, omega: float = 10.0,
+                 noise: float = 0.002, feat_noise: float = 0.005, keep: float = 0.7, clutter: float = 0.3,
+                 max_angle_deg: float = 180.0, max_trans: float = 0.3) -> Pair:
+    """Global registration by descriptors (Eq. 8 with features only; Tab. 2 stand-in).
+
+    Model: ``m`` points on an ellipsoid with semi-axes U[0.05, 0.15] m.  Each point carries the
+    unit-norm descriptor f(p) = normalise(cos(W p + c)) of its model-frame position (W ~ N(0,
+    omega^2) of shape (dim, 3), c ~ U[0, 2 pi)), so nearby points have nearby descriptors and the
+    descriptor does not depend on the pose.  Observation: the ``keep`` fraction of model points
+    facing a random view direction, moved by a random motion (rotation angle U[0, max_angle_deg],
+    uniform axis; translation U[-max_trans, max_trans]^3), with position noise ``noise`` and
+    descriptor noise ``feat_noise`` (renormalised), plus ``clutter`` * (kept points) background
+    points uniform in the box around the object carrying random unit descriptors.
+    ``extra``: model_feat (M, dim), obs_feat (N, dim) float32, dim, sigma_f.
+    """
+    rng = np.random.default_rng(seed)
+    axes = rng.uniform(0.05, 0.15, size=3)
+    x, xn = _ellipsoid_surface(rng, axes, m)
+    W = rng.normal(scale=omega, size=(dim, 3))
+    c = rng.uniform(0.0, 2.0 * math.pi, size=dim)
+
+    def desc(p):
+        f = np.cos(p @ W.T + c)
+        return f / np.linalg.norm(f, axis=1, keepdims=True)
+
+    fx = desc(x)
+    view = rng.normal(size=3)
+    view /= np.linalg.norm(view)
+    order = np.argsort(-(xn @ view))
+    vis = np.sort(order[: int(round(keep * m))])
+    T = random_motion(rng, math.radians(max_angle_deg), max_trans)
+    y = _apply(T, x[vis]) + rng.normal(scale=noise, size=(len(vis), 3))
+    fy = fx[vis] + rng.normal(scale=feat_noise, size=(len(vis), dim))
+    fy /= np.linalg.norm(fy, axis=1, keepdims=True)
+    n_bg = int(round(clutter * len(vis)))
+    lo, hi = y.min(0) - 0.1, y.max(0) + 0.1
+    yb = rng.uniform(lo, hi, size=(n_bg, 3))
+    fb = rng.normal(size=(n_bg, dim))
+    fb /= np.linalg.norm(fb, axis=1, keepdims=True)
+    return Pair(model=_f32(x), obs=_f32(np.concatenate([y, yb])), T_gt=T, sigma=(0.01, 0.01, 0.01), feat=dim,
+                residual="pt2pt", iters=20, model_n=_f32(xn), w=clutter / (1.0 + clutter),
+                name=f"feature-{dim}-{m}-seed{seed}",
+                extra={"model_feat": _f32(fx), "obs_feat": _f32(np.concatenate([fy, fb])), "dim": dim,
+                       "sigma_f": sigma_f})
 
 
 # ---------------------------------------------------------------------------
