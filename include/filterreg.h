@@ -155,6 +155,24 @@ fr_status fr_lattice_build_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_clou
                                  const fr_lattice_params *params, void *stream, fr_lattice **out);
 
 /*
+ * Descriptor lattices (Sec. 3.3 "Features", Eq. 8): the kernel is
+ * N(f_x; f_y, sigma_f^2 I) over dim-dimensional descriptors (dim = 8, 16 or
+ * 32) instead of positions.  fr_lattice_build_features splats, per set, the
+ * values [1, y] of the observation points (positions from `obs`) at their
+ * descriptors obs_feat (device, N x dim row-major binary32, rows 16-byte
+ * aligned), with scale factors sqrt(2/3)(dim+1) / (sigma_f sqrt((i+1)(i+2)))
+ * (no blur, as fr_lattice_build).  fr_estep_features slices it at the model
+ * descriptors model_feat (device, M x dim) -> m0 (device, M) and m1 (device,
+ * 3M channel-major); only the set offsets of `model_ref` are used, since the
+ * descriptors do not depend on the pose.  Build synchronises like
+ * fr_lattice_build; FR_EINVAL for other dimensions.
+ */
+fr_status fr_lattice_build_features(fr_ctx *ctx, const fr_cloud *obs, const float *obs_feat, int32_t dim,
+                                    double sigma_f, int32_t splat, void *stream, fr_lattice **out);
+fr_status fr_estep_features(const fr_lattice *lat, const fr_cloud *model_ref, const float *model_feat, float *m0,
+                            float *m1, void *stream);
+
+/*
  * Blur of the uncustomised filter, in place: for each lattice direction j =
  * 0..d in turn (every coordinate +1, coordinate j -d), every vertex takes 1/2
  * its value plus 1/4 of each of its two neighbours along j from the previous
@@ -306,6 +324,22 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
 fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs,
                             const fr_register_params *params, double sigma_min, double *theta_inout_h,
                             double *sigma_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
+
+/*
+ * Rigid registration by descriptors alone (Sec. 3.3 "Features" with Eq. 8;
+ * the global registration of Sec. 6.3): the kernel does not involve the pose,
+ * so one E-step (fr_estep_features) fixes the targets M1/M0 and the weights
+ * M0/(M0 + c), c = w/(1-w) N/M (2 pi)^(dim/2) sigma_f^dim (c_override if
+ * >= 0), and each EM iteration is one point-to-point Gauss-Newton step toward
+ * them (Eq. 17; residual scale 1).  params: residual FR_PT2PT, lattice.splat
+ * selects the splat (the other lattice fields are not used), max_iters, w,
+ * c_override, twist_tol, FR_FIXED_ITERS and
+ * FR_PROFILE_EVENTS as fr_register; FR_FUSED and FR_BLURRED are rejected.
+ * theta_inout_h, status_h, report_h and the return value as fr_register.
+ */
+fr_status fr_register_features(fr_ctx *ctx, const fr_cloud *model_ref, const float *model_feat, const fr_cloud *obs,
+                               const float *obs_feat, int32_t dim, double sigma_f, const fr_register_params *params,
+                               double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream);
 
 /*
  * Kinematic tree of an articulated model (Sec. 5.1).  Body b (0 <= b < n_bodies)

@@ -128,6 +128,12 @@ _sig("fr_lattice_build", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_l
 _sig("fr_lattice_build_joint", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform),
                                      ctypes.POINTER(fr_lattice_params), _P, ctypes.POINTER(_P)])
 _sig("fr_lattice_blur", _st, [_P, _P])
+_sig("fr_lattice_build_features", _st, [_P, ctypes.POINTER(fr_cloud), _P, _i32, ctypes.c_double, _i32, _P,
+                                        ctypes.POINTER(_P)])
+_sig("fr_estep_features", _st, [_P, ctypes.POINTER(fr_cloud), _P, _P, _P, _P])
+_sig("fr_register_features", _st, [_P, ctypes.POINTER(fr_cloud), _P, ctypes.POINTER(fr_cloud), _P, _i32,
+                                   ctypes.c_double, ctypes.POINTER(fr_register_params), _P, _P,
+                                   ctypes.POINTER(fr_report), _P])
 _sig("fr_lattice_destroy", _st, [_P])
 _sig("fr_lattice_stats", _st, [_P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int64)])
@@ -161,6 +167,7 @@ _sig("fr_engine_release", _st, [_P, _i32, _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
+                 "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
                  "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
                  "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph",
@@ -296,6 +303,32 @@ def fr_lattice_blur(lat, stream=None):
     _check(_lib.fr_lattice_blur(lat, _stream(stream)))
 
 
+def fr_lattice_build_features(ctx, obs: Cloud, obs_feat, dim: int, sigma_f: float, splat: int = 0, stream=None):
+    h = _P()
+    _check(_lib.fr_lattice_build_features(ctx, obs.c(), _ptr(obs_feat), dim, float(sigma_f), splat, _stream(stream),
+                                          ctypes.byref(h)))
+    return h
+
+
+def fr_estep_features(lat, model: Cloud, model_feat, m0, m1, stream=None):
+    _check(_lib.fr_estep_features(lat, model.c(), _ptr(model_feat), _ptr(m0), _ptr(m1), _stream(stream)))
+
+
+def fr_register_features(ctx, model: Cloud, model_feat, obs: Cloud, obs_feat, dim: int, sigma_f: float,
+                         params: fr_register_params, theta: np.ndarray, stream=None):
+    """theta: (n_sets, 4, 4) float64, updated in place.  Returns (status per set, report)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    status = np.zeros(model.n_sets, np.int32)
+    rep = fr_report()
+    st = _lib.fr_register_features(ctx, model.c(), _ptr(model_feat), obs.c(), _ptr(obs_feat), dim, float(sigma_f),
+                                   ctypes.byref(params), th.ctypes.data, status.ctypes.data, ctypes.byref(rep),
+                                   _stream(stream))
+    theta[...] = th
+    if st not in (FR_OK, FR_EDEGENERATE):
+        _check(st)
+    return status, rep
+
+
 def fr_lattice_destroy(lat):
     _check(_lib.fr_lattice_destroy(lat))
 
@@ -388,6 +421,35 @@ class Context:
     def close(self):
         if self.h is not None:
             fr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FeatureLattice:
+    """Descriptor lattice (Eq. 8) of an observation cloud; obs_feat is a (N, dim) float32 device tensor."""
+
+    def __init__(self, ctx: Context, obs: Cloud, obs_feat, sigma_f: float, splat: int = FR_SPLAT_SORTED,
+                 stream=None):
+        self.ctx = ctx
+        self.d = int(obs_feat.shape[1])
+        self.V = FR_VAL_PT2PT
+        self.n_sets = obs.n_sets
+        self.h = fr_lattice_build_features(ctx.h, obs, obs_feat, self.d, sigma_f, splat, stream)
+
+    def stats(self, set_index=0):
+        return fr_lattice_stats(self.h, set_index)
+
+    def export(self, set_index=0):
+        return fr_lattice_export(self.h, set_index, self.d, self.V)
+
+    def close(self):
+        if self.h is not None:
+            fr_lattice_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -300,6 +300,8 @@ void free_lattice(fr_lattice *lat, hipStream_t st, bool idle)
     if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable), st, idle);
     if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes, st, idle);
     if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t), st, idle);
+    if (lat->kfeat_d) dev_free(lat->ctx, lat->kfeat_d, lat->kfeat.size() * sizeof(float), st, idle);
+    lat->kfeat_d = nullptr;
     lat->tkey = nullptr;
     lat->tval = nullptr;
     lat->sets_d = nullptr;
@@ -358,6 +360,73 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
         return s;
     }
     *out = lat;
+    return FR_OK;
+}
+
+// Descriptor lattice of Eq. 8: d = dim, values [1, y], one isotropic width
+// sigma_f for every descriptor dimension (the scale factors of scale_factors()
+// with sigma_i = sigma_f).
+static fr_status feature_lattice_impl(fr_ctx *ctx, const fr_cloud *obs, const float *obs_feat, int32_t dim,
+                                      double sigma_f, int32_t splat, hipStream_t st, fr_lattice **out)
+{
+    fr_lattice *lat = new (std::nothrow) fr_lattice();
+    if (!lat) {
+        set_error("out of host memory");
+        return FR_ENOMEM;
+    }
+    lat->ctx = ctx;
+    lat->d = dim;
+    lat->V = FR_VAL_PT2PT;
+    lat->KW = (dim + 2) / 3;
+    lat->n_sets = obs->n_sets;
+    lat->splat = splat;
+    lat->n_points_total = cloud_points(obs);
+    lat->kfeat.resize(dim);
+    for (int i = 0; i < dim; ++i)
+        lat->kfeat[i] = (float)(std::sqrt(2.0 / 3.0) * (double)(dim + 1) /
+                                (sigma_f * std::sqrt((double)((i + 1) * (i + 2)))));
+    for (int i = 0; i < 8; ++i) lat->k[i] = lat->kfeat[i];
+    lat->kset.resize((size_t)8 * obs->n_sets);
+    for (int32_t q = 0; q < obs->n_sets; ++q) std::memcpy(lat->kset.data() + 8 * (size_t)q, lat->k, sizeof(lat->k));
+    fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
+    if (s == FR_OK) s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->kfeat_d), dim * sizeof(float));
+    if (s == FR_OK) {
+        const hipError_t e = hipMemcpyAsync(lat->kfeat_d, lat->kfeat.data(), dim * sizeof(float),
+                                            hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+            s = FR_EDEVICE;
+        }
+    }
+    if (s == FR_OK) s = build_feature_lattice(ctx, obs, obs_feat, st, lat);
+    if (s != FR_OK) {
+        free_lattice(lat, st, false);
+        lat->magic = kDeadMagic;
+        delete lat;
+        return s;
+    }
+    *out = lat;
+    return FR_OK;
+}
+
+// c of Eq. 7 for a kernel over dim descriptor dimensions of width sigma_f.
+static double feature_outlier_constant(double w, double c_override, double Ms, double Ns, double sigma_f, int dim)
+{
+    if (c_override >= 0.0) return c_override;
+    if (!(Ms > 0) || !(w > 0.0)) return 0.0;
+    return w / (1.0 - w) * (Ns / Ms) * std::pow(2.0 * M_PI, 0.5 * dim) * std::pow(sigma_f, (double)dim);
+}
+
+static fr_status check_features(const float *feat, int32_t dim, const char *what)
+{
+    if (feat == nullptr || !feature_dim_supported(dim)) {
+        set_error("%s: descriptors must be non-NULL with dimension 8, 16 or 32 (got %d)", what, dim);
+        return FR_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(feat) & 15u) != 0) {
+        set_error("%s: descriptor rows must be 16-byte aligned", what);
+        return FR_EINVAL;
+    }
     return FR_OK;
 }
 
@@ -509,6 +578,54 @@ fr_status fr_lattice_build_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_clou
     return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out, nullptr, model_ref, mats);
 }
 
+fr_status fr_lattice_build_features(fr_ctx *ctx, const fr_cloud *obs, const float *obs_feat, int32_t dim,
+                                    double sigma_f, int32_t splat, void *stream, fr_lattice **out)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || out == nullptr) {
+        set_error("fr_lattice_build_features: invalid context or out pointer");
+        return FR_EINVAL;
+    }
+    *out = nullptr;
+    FR_TRY(check_features(obs_feat, dim, "fr_lattice_build_features"));
+    if (!(sigma_f > 0.0) || !std::isfinite(sigma_f) || (splat != FR_SPLAT_SORTED && splat != FR_SPLAT_ATOMIC)) {
+        set_error("fr_lattice_build_features: sigma_f must be finite and > 0, splat sorted or atomic");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(obs, false, "fr_lattice_build_features"));
+    FR_HIP(hipSetDevice(ctx->device));
+    StreamScope scope(static_cast<hipStream_t>(stream));
+    return feature_lattice_impl(ctx, obs, obs_feat, dim, sigma_f, splat, static_cast<hipStream_t>(stream), out);
+}
+
+fr_status fr_estep_features(const fr_lattice *lat, const fr_cloud *model_ref, const float *model_feat, float *m0,
+                            float *m1, void *stream)
+{
+    clear_error();
+    if (!lat_ok(lat) || lat->kfeat_d == nullptr) {
+        set_error("fr_estep_features: invalid lattice (build it with fr_lattice_build_features)");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_features(model_feat, lat->d, "fr_estep_features"));
+    FR_TRY(check_cloud(model_ref, false, "fr_estep_features"));
+    if (model_ref->n_sets != lat->n_sets) {
+        set_error("fr_estep_features: model has %d sets, lattice has %d", model_ref->n_sets, lat->n_sets);
+        return FR_EINVAL;
+    }
+    const int64_t M = cloud_points(model_ref);
+    if (M > 0 && (m0 == nullptr || m1 == nullptr)) {
+        set_error("fr_estep_features: m0/m1 must be non-NULL");
+        return FR_EINVAL;
+    }
+    if (M == 0) return FR_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    Plan plan;
+    FR_TRY(make_plan(lat->ctx, model_ref, nullptr, kEstepTile, nullptr, st, plan));
+    return launch_estep_features(lat, model_ref, plan, model_feat, m0, m1, st);
+}
+
 fr_status fr_lattice_blur(fr_lattice *lat, void *stream)
 {
     clear_error();
@@ -613,7 +730,7 @@ fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h,
     });
     for (int64_t o = 0; o < nv; ++o) {
         const int64_t i = order[o];
-        uint64_t words[4] = {0, 0, 0, 0};
+        uint64_t words[12] = {0};
         for (int w = 0; w < KW; ++w) words[w] = key[(size_t)w * nv + i];
         for (int j = 0; j < d; ++j) keys_h[o * d + j] = unpack_coord(words, j);
         occ_h[o] = (int32_t)occ[i];
@@ -1150,6 +1267,150 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
     return FR_OK;
 }
 
+
+fr_status fr_register_features(fr_ctx *ctx, const fr_cloud *model_ref, const float *model_feat, const fr_cloud *obs,
+                               const float *obs_feat, int32_t dim, double sigma_f, const fr_register_params *params,
+                               double *theta_inout_h, int32_t *status_h, fr_report *report_h, void *stream)
+{
+    clear_error();
+    using clk = std::chrono::steady_clock;
+    if (!ctx_ok(ctx) || params == nullptr || theta_inout_h == nullptr) {
+        set_error("fr_register_features: invalid context, params or theta");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_features(model_feat, dim, "fr_register_features(model)"));
+    FR_TRY(check_features(obs_feat, dim, "fr_register_features(obs)"));
+    if (params->residual != FR_PT2PT || params->max_iters < 0 || params->kinematics != FR_KIN_RIGID ||
+        !(params->w >= 0.0 && params->w < 1.0) || (params->flags & (FR_FUSED | FR_BLURRED)) != 0 ||
+        !(sigma_f > 0.0) || !std::isfinite(sigma_f) ||
+        (params->lattice.splat != FR_SPLAT_SORTED && params->lattice.splat != FR_SPLAT_ATOMIC)) {
+        set_error("fr_register_features: point-to-point residual, rigid kinematics, max_iters >= 0, 0 <= w < 1, "
+                  "sigma_f > 0, no FR_FUSED / FR_BLURRED are required");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(model_ref, false, "fr_register_features(model)"));
+    FR_TRY(check_cloud(obs, false, "fr_register_features(obs)"));
+    if (model_ref->n_sets != obs->n_sets) {
+        set_error("fr_register_features: model has %d sets, observation %d", model_ref->n_sets, obs->n_sets);
+        return FR_EINVAL;
+    }
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    const int32_t S = model_ref->n_sets;
+    const int64_t M = cloud_points(model_ref);
+    fr_report rep{};
+    auto t0 = clk::now();
+    fr_lattice *lat = nullptr;
+    FR_TRY(feature_lattice_impl(ctx, obs, obs_feat, dim, sigma_f, params->lattice.splat, st, &lat));
+    struct LatGuard {
+        fr_lattice *l;
+        ~LatGuard()
+        {
+            if (l) fr_lattice_destroy(l);
+        }
+    } guard{lat};
+    rep.build_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    std::vector<double> cset(S);
+    for (int32_t s = 0; s < S; ++s)
+        cset[s] = feature_outlier_constant(params->w, params->c_override,
+                                           (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]),
+                                           (double)(obs->offsets[s + 1] - obs->offsets[s]), sigma_f, dim);
+    Plan pe, pr;
+    FR_TRY(make_plan(ctx, model_ref, nullptr, kEstepTile, nullptr, st, pe));
+    FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
+    const size_t nM = (size_t)std::max<int64_t>(M, 1);
+    DevBuf wm0, wm1, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive;
+    FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
+    FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
+    FR_TRY(part.alloc(ctx, reduce_partials_floats(pr) * sizeof(float)));
+    FR_TRY(wjtj.alloc(ctx, S * 21 * sizeof(double)));
+    FR_TRY(wjtr.alloc(ctx, S * 6 * sizeof(double)));
+    FR_TRY(wstat.alloc(ctx, S * 4 * sizeof(double)));
+    FR_TRY(wpose.alloc(ctx, S * 16 * sizeof(double)));
+    FR_TRY(wmats.alloc(ctx, S * 12 * sizeof(float)));
+    FR_TRY(wtn.alloc(ctx, S * 2 * sizeof(double)));
+    FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
+    FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
+    std::vector<float> mats_h((size_t)S * 12);
+    for (int32_t s = 0; s < S; ++s)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 4; ++j) mats_h[(size_t)s * 12 + 4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
+    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK);
+    FR_HIP(hipMemcpyAsync(wpose.p, theta_inout_h, S * 16 * sizeof(double), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wmats.p, mats_h.data(), S * 12 * sizeof(float), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(wstatus.p, status_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    auto t2 = clk::now();
+    // the kernel involves the descriptors only: one E-step fixes targets and weights
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    const bool prof = (params->flags & FR_PROFILE_EVENTS) != 0;
+    if (prof) {
+        FR_HIP(hipEventCreate(&ev.a));
+        FR_HIP(hipEventCreate(&ev.b));
+        FR_HIP(hipEventRecord(ev.a, st));
+    }
+    FR_TRY(launch_estep_features(lat, model_ref, pe, model_feat, wm0.as<float>(), wm1.as<float>(), st));
+    if (prof) FR_HIP(hipEventRecord(ev.b, st));
+    const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
+    const int max_it = params->max_iters;
+    int it = 0;
+    for (; it < max_it; ++it) {
+        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(), nullptr,
+                             FR_PT2PT, 0, 1.0, wjtj.as<double>(), wjtr.as<double>(), wstat.as<double>(),
+                             part.as<float>(), st));
+        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
+                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
+        if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_it)) {
+            std::vector<double> tn((size_t)S * 2);
+            FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            FR_HIP(hipStreamSynchronize(st));
+            int n_active = 0;
+            for (int32_t s = 0; s < S; ++s) {
+                if (status_v[s] != FR_OK || (tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
+                    active_h[s] = 0;
+                n_active += active_h[s];
+            }
+            FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            if (n_active == 0) {
+                ++it;
+                break;
+            }
+        }
+    }
+    FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipStreamSynchronize(st));
+    rep.iterations = it;
+    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t2).count();
+    if (prof) {
+        float a = 0.0f;
+        FR_HIP(hipEventElapsedTime(&a, ev.a, ev.b));
+        rep.estep_ms = a;
+        rep.estep_launches = 1;
+    }
+    int32_t n_deg = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        if (status_v[s] != FR_OK) ++n_deg;
+        if (status_h) status_h[s] = status_v[s];
+    }
+    rep.n_degenerate = n_deg;
+    if (report_h) *report_h = rep;
+    FR_TRY(fr_sync_status(lat));
+    if (n_deg > 0) {
+        set_error("fr_register_features: %d set(s) had a degenerate normal-equation system", n_deg);
+        return FR_EDEGENERATE;
+    }
+    return FR_OK;
+}
 
 fr_status fr_articulated_step(fr_ctx *ctx, const fr_kinematic_tree *tree, const double *jtj, const double *jtr,
                               double *theta, float *mats, int32_t *status, void *stream)

@@ -281,6 +281,80 @@ fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, i
     return FR_OK;
 }
 
+// Descriptor E-step (Eq. 8 with the features alone): one model point per
+// thread reads its descriptor row, walks the d+1 vertices of its simplex one at
+// a time (key, two candidate slots, value slot) and sums b * [1, y].
+struct FeatArgs {
+    const float *feat;        // M x d row-major
+    const float *kf;          // d scale factors
+    const SetTable *sets;
+    TileMap tm;
+    float *m0, *m1;
+    int64_t M;
+    int32_t *err;
+};
+
+template <int d>
+__global__ void __launch_bounds__(256) k_estep_feat(FeatArgs a)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    if (i >= a.tm.seg_end[s]) return;
+    const SetTable st = a.sets[a.tm.seg_set[s]];
+    float p[d], kk[d];
+    const float4 *row = reinterpret_cast<const float4 *>(a.feat + (size_t)i * d);
+#pragma unroll
+    for (int q = 0; q < d / 4; ++q) {
+        const float4 v = row[q];
+        p[4 * q] = v.x;
+        p[4 * q + 1] = v.y;
+        p[4 * q + 2] = v.z;
+        p[4 * q + 3] = v.w;
+    }
+#pragma unroll
+    for (int j = 0; j < d; ++j) kk[j] = a.kf[j];
+    HdEmbed<d> h;
+    embed_hd_init<d>(p, kk, h);
+    if (!h.ok) atomicOr(a.err, 1);
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int m = 0; m < D; ++m) {   // one vertex at a time: keeps the key walk in registers
+        const float b = embed_hd_next<d>(h, m);
+        const int64_t r = find_slot<KW>(st.keys, st, h.P);
+        if (r >= 0) {
+            const u32x4 q = load_at<u32x4>(st.vals, (uint32_t)r * 16u);
+            acc[0] = fmaf(b, __uint_as_float(q.x), acc[0]);
+            acc[1] = fmaf(b, __uint_as_float(q.y), acc[1]);
+            acc[2] = fmaf(b, __uint_as_float(q.z), acc[2]);
+            acc[3] = fmaf(b, __uint_as_float(q.w), acc[3]);
+        }
+    }
+    a.m0[i] = acc[0];
+    a.m1[i] = acc[1];
+    a.m1[a.M + i] = acc[2];
+    a.m1[2 * a.M + i] = acc[3];
+}
+
+fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, const float *feat,
+                                float *m0, float *m1, hipStream_t st)
+{
+    if (plan.grid == 0) return FR_OK;
+    FeatArgs a{feat, lat->kfeat_d, lat->sets_d, plan.tm, m0, m1, cloud_points(model), lat->err_d};
+    if (lat->d == 8) k_estep_feat<8><<<plan.grid, 256, 0, st>>>(a);
+    else if (lat->d == 16) k_estep_feat<16><<<plan.grid, 256, 0, st>>>(a);
+    else if (lat->d == 32) k_estep_feat<32><<<plan.grid, 256, 0, st>>>(a);
+    else {
+        set_error("descriptor E-step: dimension %d not supported", lat->d);
+        return FR_EINVAL;
+    }
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
                        float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2)
 {

@@ -98,19 +98,34 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
     return h;
 }
 
-// Multiply-add hash of the packed key words with a final avalanche.
+// Hash of the packed key words: the block mix and finaliser of MurmurHash3
+// (x86, 32-bit) over the 2 KW 32-bit halves.  Its rotations and xors make the
+// result depend on the seed non-linearly, so keys that collide under one seed
+// do not collide under the next (a multiply-add chain is affine in the words:
+// its collisions would not depend on the seed, and a rebuild with a new seed
+// could never separate three colliding keys).
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
 template <int KW>
 __device__ __forceinline__ uint32_t hash_key(const uint64_t (&w)[KW], uint32_t seed)
 {
     uint32_t h = seed;
 #pragma unroll
-    for (int i = 0; i < KW; ++i) {
-        h = (h + (uint32_t)w[i]) * 0x9E3779B1u;
-        h = (h + (uint32_t)(w[i] >> 32)) * 0x85EBCA77u;
+    for (int i = 0; i < 2 * KW; ++i) {
+        uint32_t k = (i & 1) ? (uint32_t)(w[i / 2] >> 32) : (uint32_t)w[i / 2];
+        k *= 0xCC9E2D51u;
+        k = rotl32(k, 15);
+        k *= 0x1B873593u;
+        h ^= k;
+        h = rotl32(h, 13);
+        h = h * 5u + 0xE6546B64u;
     }
-    h ^= h >> 15;
-    h *= 0x2C1B3C6Du;
-    h ^= h >> 12;
+    h ^= (uint32_t)(8 * KW);
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
     return h;
 }
 
@@ -123,6 +138,25 @@ __device__ __forceinline__ void cuckoo_slots(uint32_t h, uint32_t cap, uint32_t 
     const uint32_t h2 = (h ^ (h >> 16)) * 0x7FEB352Du;
     p2 = __umulhi(h2, cap);
     p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
+}
+
+// Both candidate slots of a key.  Positions (KW <= 2) take them from one
+// 32-bit hash.  Descriptor lattices hold millions of vertices per set, where
+// several keys share a 32-bit hash and, with it, both slots (three such keys
+// cannot be placed); their second slot comes from a second hash with another
+// seed, so a shared first hash no longer implies a shared pair.
+template <int KW>
+__device__ __forceinline__ void key_slots(const uint64_t (&key)[KW], uint32_t seed, uint32_t cap, uint32_t &p1,
+                                          uint32_t &p2)
+{
+    const uint32_t h = hash_key<KW>(key, seed);
+    if constexpr (KW <= 2) {
+        cuckoo_slots(h, cap, p1, p2);
+    } else {
+        p1 = __umulhi(h, cap);
+        p2 = __umulhi(hash_key<KW>(key, seed * 0x2545F491u + 0x9E3779B9u), cap);
+        p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
+    }
 }
 
 // Loads from a uniform table base with a 32-bit byte offset (slot < 2^27).
@@ -148,10 +182,17 @@ __device__ __forceinline__ void load_key(const uint64_t *__restrict__ keys, uint
         const u32x4 q = load_at<u32x4>(keys, slot << 4);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
         k[1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
-    } else {
-        static_assert(KW == 1, "keys of 1 or 2 words");
+    } else if constexpr (KW == 1) {
         const u32x2 q = load_at<u32x2>(keys, slot << 3);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+    } else {
+        // descriptor lattices: KW words of 8 bytes per slot
+        const uint32_t base = slot * (uint32_t)(8 * KW);
+#pragma unroll
+        for (int w = 0; w < KW; ++w) {
+            const u32x2 q = load_at<u32x2>(keys, base + 8u * w);
+            k[w] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+        }
     }
 }
 
@@ -288,6 +329,115 @@ __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
     return ok;
 }
 
+// The same embedding for descriptor spaces of dozens of dimensions, where the
+// d+1 keys do not fit in registers at once: embed_hd_init does the elevation,
+// rounding and ranking (the arithmetic of embed<d>, in the same binary32
+// order) and packs vertex 0's key; embed_hd_next then gives the weight of
+// vertex m and moves the key to it (vertices in order m = 0, 1, ..., d).  The
+// deltas of a given rank are found by scanning the d+1 coordinates, so that
+// nothing is indexed by a runtime value.
+template <int d> struct HdEmbed {
+    float delta[d + 1];
+    int32_t rank[d + 1];
+    float u_first, u_last;               // largest and smallest delta
+    uint64_t P[KeyWords<d>::value];      // key of the current vertex
+    bool ok;
+};
+
+template <int d>
+__device__ __forceinline__ void embed_hd_init(const float *p, const float *k, HdEmbed<d> &h)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    constexpr float invD = (float)(1.0 / (double)D);
+    constexpr float fD = (float)D;
+    float e[D];
+    float S = 0.0f;
+#pragma unroll
+    for (int j = d; j >= 1; --j) {
+        const float cf = p[j - 1] * k[j - 1];
+        const float jc = (float)j * cf;
+        e[j] = S - jc;
+        S = S + cf;
+    }
+    e[0] = S;
+    int32_t g[D];
+    int32_t sum_g = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const float v = e[j] * invD;
+        const float dn = floorf(v) * fD;
+        const float up = dn + fD;
+        const float du = up - e[j];
+        const float dd = e[j] - dn;
+        const float gf = (du < dd) ? up : dn;
+        g[j] = (int32_t)gf;
+        h.delta[j] = e[j] - gf;
+        sum_g += g[j];
+    }
+    const int32_t s = sum_g / D;
+#pragma unroll
+    for (int j = 0; j < D; ++j) h.rank[j] = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i + 1; j < D; ++j) {
+            const int32_t c = h.delta[i] < h.delta[j] ? 1 : 0;
+            h.rank[i] += c;
+            h.rank[j] += 1 - c;
+        }
+    h.u_first = 0.0f;
+    h.u_last = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        h.u_first = h.rank[j] == 0 ? h.delta[j] : h.u_first;
+        h.u_last = h.rank[j] == d ? h.delta[j] : h.u_last;
+    }
+    h.ok = true;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) h.P[w] = 0;
+#pragma unroll
+    for (int j = 0; j < d; ++j) {
+        const int32_t c = g[j] - s;
+        h.ok = h.ok && (c >= -kKeyBias + D) && (c < kKeyBias - D);
+        h.P[j / 3] |= (uint64_t)((uint32_t)(c + kKeyBias) & ((1u << kKeyBits) - 1u)) << (kKeyBits * (2 - (j % 3)));
+    }
+}
+
+// Weight of vertex m; for m >= 1 first steps the key from vertex m-1 to m
+// (+1 in every coordinate, -D in the coordinate of rank d - m + 1).
+template <int d>
+__device__ __forceinline__ float embed_hd_next(HdEmbed<d> &h, int m)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    constexpr float invD = (float)(1.0 / (double)D);
+    if (m == 0) return 1.0f + (h.u_last - h.u_first) * invD;
+    const int32_t t = d - m + 1;
+    float ua = 0.0f, ub = 0.0f;
+    uint64_t down[KW];
+#pragma unroll
+    for (int w = 0; w < KW; ++w) down[w] = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        ua = h.rank[j] == t - 1 ? h.delta[j] : ua;
+        ub = h.rank[j] == t ? h.delta[j] : ub;
+        if (j < d) {
+            const uint64_t unit = 1ull << (kKeyBits * (2 - (j % 3)));
+            down[j / 3] = h.rank[j] == t ? (uint64_t)D * unit : down[j / 3];
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < KW; ++w) {
+        uint64_t ones = 0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            if (3 * w + f < d) ones += 1ull << (kKeyBits * (2 - f));
+        h.P[w] += ones - down[w];
+    }
+    return (ua - ub) * invD;
+}
+
 // Unpack coordinate j of a packed key (for export).
 __host__ __device__ inline int32_t unpack_coord(const uint64_t *words, int j)
 {
@@ -329,7 +479,7 @@ __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, c
     float vw[D], vW[D], vm[D][3];   // |y|^2 layouts: weights, masses and first moments per vertex
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        cuckoo_slots(hash_key<KW>(keys[v], st.seed), st.cap, p1[v], p2[v]);
+        key_slots<KW>(keys[v], st.seed, st.cap, p1[v], p2[v]);
         load_key<KW>(kb, p1[v], ka[v]);
         load_key<KW>(kb, p2[v], kc[v]);
     }
@@ -382,7 +532,7 @@ __device__ __forceinline__ int64_t find_slot(const uint64_t *__restrict__ kb, co
                                              const uint64_t (&key)[KW])
 {
     uint32_t p1, p2;
-    cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+    key_slots<KW>(key, st.seed, st.cap, p1, p2);
     uint64_t k1[KW], k2[KW];
     load_key<KW>(kb, p1, k1);
     load_key<KW>(kb, p2, k2);

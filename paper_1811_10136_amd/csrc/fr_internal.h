@@ -92,6 +92,9 @@ struct fr_lattice {
     std::vector<int64_t> vbase;
     size_t vert_bytes = 0;
     int32_t *err_d = nullptr;         // latched device fault bits
+    // descriptor lattices (d = feature dimension): the d binary32 scale factors
+    float *kfeat_d = nullptr;
+    std::vector<float> kfeat;
 };
 
 namespace fr {
@@ -185,6 +188,12 @@ fr_status build_joint_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *
 // d+1 passes of [1/4, 1/2, 1/4] along the lattice directions, then the output
 // scale 1 / (1 + 2^-d); table and vertex values are replaced.
 fr_status blur_lattice(fr_lattice *lat, hipStream_t st);
+// Descriptor lattice (Eq. 8): keys from feat (device, N x dim row-major
+// binary32) scaled by lat->kfeat_d, values [1, y] from the points of obs.
+// dim is 8, 16 or 32.
+fr_status build_feature_lattice(fr_ctx *ctx, const fr_cloud *obs, const float *feat, hipStream_t st,
+                                fr_lattice *lat);
+bool feature_dim_supported(int dim);
 
 // estep.hip
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
@@ -192,6 +201,9 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
                             float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st);
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
                        float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2 = nullptr);
+// Descriptor E-step (Eq. 8): slice lat at feat (device, M x lat->d) -> m0, m1.
+fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, const float *feat,
+                                float *m0, float *m1, hipStream_t st);
 
 // mstep.hip
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,

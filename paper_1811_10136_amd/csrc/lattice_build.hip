@@ -285,6 +285,45 @@ __global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, const fl
     }
 }
 
+// Descriptor lattices: one thread per observation point writes its D records
+// straight to memory (D * KW words are too many to stage in LDS), producing the
+// vertices one at a time.
+template <int d>
+__global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const float *kf, TileMap tm,
+                                                   uint64_t *rec_key, float *rec_b, size_t R, int32_t *err)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;
+    const int32_t s = tile_segment(tm, t);
+    const int64_t i = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
+    if (i >= tm.seg_end[s]) return;
+    float p[d], kk[d];
+    const float4 *row = reinterpret_cast<const float4 *>(feat + (size_t)i * d);
+#pragma unroll
+    for (int q = 0; q < d / 4; ++q) {
+        const float4 v = row[q];
+        p[4 * q] = v.x;
+        p[4 * q + 1] = v.y;
+        p[4 * q + 2] = v.z;
+        p[4 * q + 3] = v.w;
+    }
+#pragma unroll
+    for (int j = 0; j < d; ++j) kk[j] = kf[j];
+    HdEmbed<d> h;
+    embed_hd_init<d>(p, kk, h);
+    if (!h.ok) atomicOr(err, 1);
+    const size_t r0 = (size_t)i * D;
+#pragma unroll 1
+    for (int m = 0; m < D; ++m) {   // one vertex at a time: keeps the key walk in registers
+        const float b = embed_hd_next<d>(h, m);
+#pragma unroll
+        for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r0 + m] = h.P[w];
+        rec_b[r0 + m] = b;
+    }
+}
+
 // One thread per record: find or claim the record's key in the provisional
 // linear-probing table of its set.  A slot that already has an owner is
 // compared with a plain read first; only free slots are claimed with a CAS.
@@ -511,7 +550,7 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
     uint32_t p1, p2;
-    cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+    key_slots<KW>(key, st.seed, st.cap, p1, p2);
     uint32_t pos = p1;
     for (int it = 0; it < kMaxKicks; ++it) {
         const uint32_t old = atomicExch(&own[st.slot_base + pos], cur);
@@ -519,7 +558,7 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
         cur = old;
 #pragma unroll
         for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
-        cuckoo_slots(hash_key<KW>(key, st.seed), st.cap, p1, p2);
+        key_slots<KW>(key, st.seed, st.cap, p1, p2);
         pos = (pos == p1) ? p2 : p1;
     }
     atomicOr(fail, 1);
@@ -594,7 +633,7 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
 
 template <int d, int V>
 static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat,
-                            const int64_t *valued_end)
+                            const int64_t *valued_end, const float *feat = nullptr)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -625,8 +664,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     FR_TRY(kset_d.alloc(ctx, lat->kset.size() * sizeof(float)));
     FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
     if (ptm.n_tiles > 0) {
-        k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), rec_key.as<uint64_t>(),
-                                                    rec_b.as<float>(), R, lat->err_d, valued_end);
+        if constexpr (d > 6) {
+            k_embed_feat<d><<<ptm.n_tiles, 256, 0, st>>>(feat, lat->kfeat_d, ptm, rec_key.as<uint64_t>(),
+                                                         rec_b.as<float>(), R, lat->err_d);
+        } else {
+            k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), rec_key.as<uint64_t>(),
+                                                        rec_b.as<float>(), R, lat->err_d, valued_end);
+        }
         FR_HIP(hipGetLastError());
     }
     // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
@@ -831,6 +875,18 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
     if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat, ve);
     if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat, ve);
     set_error("fr_lattice_build: unsupported feat=%d values=%d", prm->feat, prm->values);
+    return FR_EINVAL;
+}
+
+bool feature_dim_supported(int dim) { return dim == 8 || dim == 16 || dim == 32; }
+
+fr_status build_feature_lattice(fr_ctx *ctx, const fr_cloud *obs, const float *feat, hipStream_t st,
+                                fr_lattice *lat)
+{
+    if (lat->d == 8) return build_impl<8, 4>(ctx, obs, st, lat, nullptr, feat);
+    if (lat->d == 16) return build_impl<16, 4>(ctx, obs, st, lat, nullptr, feat);
+    if (lat->d == 32) return build_impl<32, 4>(ctx, obs, st, lat, nullptr, feat);
+    set_error("descriptor dimension %d not supported (8, 16 or 32)", lat->d);
     return FR_EINVAL;
 }
 
