@@ -51,7 +51,9 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    # export the C ABI only (fr_*); the C++ internals stay local to the library
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+           "-Wl,--version-script=" + os.path.join(CSRC, "exports.map"), "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -604,8 +604,12 @@ static uint32_t next_pow2(uint64_t x)
 static inline unsigned blocks_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 // Tile map over explicit offsets (device copy kept in `buf`).
+// Blocks to launch for a tile map: with XCD chunks, 8 whole chunks (the blocks
+// past the last tile return at once).
+static unsigned grid_of(const TileMap &tm) { return (unsigned)(tm.xcd_chunk > 0 ? tm.xcd_chunk * 8 : tm.n_tiles); }
+
 static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, int32_t tile, hipStream_t st,
-                                 DevBuf &buf, TileMap &tm)
+                                 DevBuf &buf, TileMap &tm, bool xcd = false)
 {
     const int32_t n = (int32_t)off.size() - 1;
     std::vector<int32_t> tiles(n + 1, 0), sets(n);
@@ -626,7 +630,8 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     tm.n_seg = n;
     tm.n_tiles = tiles[n];
     tm.tile = tile;
-    tm.xcd_chunk = 0;
+    // XCD-contiguous tiles: a set's tiles run on one XCD, so the set's tables stay in that XCD's L2
+    tm.xcd_chunk = (xcd && tm.n_tiles >= 8 * 64) ? (tm.n_tiles + 7) / 8 : 0;
     FR_HIP(hipStreamSynchronize(st));   // host vectors go out of scope
     return FR_OK;
 }
@@ -676,7 +681,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
     std::vector<int64_t> roff(S + 1);
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
-    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm));
+    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
     uint64_t n1 = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<SetTable> t1(S);
@@ -696,7 +701,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (rtm.n_tiles > 0) {
-            k_insert_records<KW><<<rtm.n_tiles, 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
+            k_insert_records<KW><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
                                                               own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
                                                               fail.as<int32_t>());
             FR_HIP(hipGetLastError());
@@ -833,13 +838,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     DevBuf own2, vtmap;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
     TileMap vtm{};
-    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm));
+    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true));
     for (int attempt = 0;; ++attempt) {
         FR_HIP(hipMemcpyAsync(lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
         FR_HIP(hipMemsetAsync(own2.p, 0xFF, n2 * sizeof(uint32_t), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (vtm.n_tiles > 0) {
-            k_cuckoo_insert<KW><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey, NV, own2.as<uint32_t>(),
+            k_cuckoo_insert<KW><<<grid_of(vtm), 256, 0, st>>>(vtm, lat->sets_d, lat->vkey, NV, own2.as<uint32_t>(),
                                                              fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }

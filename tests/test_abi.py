@@ -41,6 +41,17 @@ def test_library_exports_every_declared_symbol():
     assert not missing, f"not exported: {missing}"
 
 
+def test_library_exports_nothing_but_the_declared_symbols():
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"})
+    assert exported == declared_functions()
+
+
 def test_binding_covers_every_declared_symbol():
     import paper_1811_10136_amd as fr
     assert sorted(fr.ABI_FUNCTIONS) == declared_functions()
