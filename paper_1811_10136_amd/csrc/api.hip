@@ -515,6 +515,8 @@ fr_status fr_ctx_destroy(fr_ctx *ctx)
     }
     (void)hipSetDevice(ctx->device);
     dev_release_cache(ctx);
+    if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+    ctx->graph_stream = nullptr;
     ctx->magic = kDeadMagic;
     delete ctx;
     return FR_OK;
@@ -880,6 +882,25 @@ fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double
                               static_cast<hipStream_t>(stream));
 }
 
+// The context's capture stream (created on first use, default priority,
+// non-blocking); graphs are captured and replayed on it.
+static fr_status graph_stream(fr_ctx *ctx, hipStream_t &gs)
+{
+    if (ctx->graph_stream == nullptr) FR_HIP(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+    gs = ctx->graph_stream;
+    return FR_OK;
+}
+
+struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~GraphGuard()
+    {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
 // Stream-ordered release of a lattice the caller's loop no longer reads.
 static void release_lattice(fr_lattice *lat, hipStream_t st)
 {
@@ -995,53 +1016,113 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         ev.resize(3 * (size_t)max_it + 1);
         for (auto &e : ev) FR_HIP(hipEventCreate(&e));
     }
-    auto t2 = clk::now();
-    int it = 0;
-    for (; it < max_it; ++it) {
-        if (blurred) {
-            auto tb = clk::now();
-            if (lat != nullptr) {
-                release_lattice(lat, st);
-                lat = guard.l = nullptr;
-            }
-            FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, nullptr, model_ref, wmats.as<float>()));
-            guard.l = lat;
-            FR_TRY(blur_lattice(lat, st));
-            rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
-        }
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+    // one EM iteration on stream q (without the profiling events)
+    auto enqueue_iter = [&](hipStream_t q) -> fr_status {
         if (fused) {
-            FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
-                                      wmats.as<float>(), params->residual, 0, part.as<float>(), st));
-            if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+            FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe, wmats.as<float>(),
+                                      params->residual, 0, part.as<float>(), q));
             FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
-                                       wstat.as<double>(), st));
+                                       wstat.as<double>(), q));
         } else {
             FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
-                                wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
-            if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+                                wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, q));
             FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
                                  pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
-                                 wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+                                 wjtr.as<double>(), wstat.as<double>(), part.as<float>(), q));
         }
-        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
-                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
-        if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_it)) {
-            std::vector<double> tn((size_t)S * 2);
-            FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-            FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            FR_HIP(hipStreamSynchronize(st));
-            int n_active = 0;
-            for (int32_t s = 0; s < S; ++s) {
-                if (status_v[s] != FR_OK || (tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
-                    active_h[s] = 0;
-                n_active += active_h[s];
+        return launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
+                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), q);
+    };
+    // sets whose step fell below the twist tolerance (or degenerated) stop; returns the sets still active
+    auto check_active = [&](hipStream_t q, int &n_active) -> fr_status {
+        std::vector<double> tn((size_t)S * 2);
+        FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, q));
+        FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, q));
+        FR_HIP(hipStreamSynchronize(q));
+        n_active = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            if (status_v[s] != FR_OK || (tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
+                active_h[s] = 0;
+            n_active += active_h[s];
+        }
+        FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, q));
+        return FR_OK;
+    };
+    auto t2 = clk::now();
+    int it = 0;
+    if (!prof && !blurred && max_it > 0) {
+        // The iterations of a block are captured once into a HIP graph and replayed: one launch per block
+        // instead of three or four per iteration.  Capture needs a stream of its own (the caller's may be
+        // the null stream); the caller's stream is idle here, and the block is waited for below.
+        hipStream_t gs = nullptr;
+        FR_TRY(graph_stream(ctx, gs));
+        const int blk = fixed ? max_it : 4;
+        GraphGuard gg;
+        FR_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        fr_status cs = FR_OK;
+        for (int k = 0; k < blk && cs == FR_OK; ++k) cs = enqueue_iter(gs);
+        const hipError_t ce = hipStreamEndCapture(gs, &gg.g);
+        FR_TRY(cs);
+        if (ce != hipSuccess) {
+            set_error("fr_register: graph capture failed: %s", hipGetErrorString(ce));
+            return FR_EDEVICE;
+        }
+        FR_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+        while (it < max_it) {
+            const int n = std::min(blk, max_it - it);
+            if (n == blk) {
+                FR_HIP(hipGraphLaunch(gg.e, gs));
+            } else {
+                for (int k = 0; k < n; ++k) FR_TRY(enqueue_iter(gs));
             }
-            FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
-            if (n_active == 0) {
-                ++it;
-                break;
+            it += n;
+            if (!fixed) {
+                int n_active = 0;
+                FR_TRY(check_active(gs, n_active));
+                if (n_active == 0) break;
+            }
+        }
+        FR_HIP(hipStreamSynchronize(gs));
+    } else {
+        for (; it < max_it; ++it) {
+            if (blurred) {
+                auto tb = clk::now();
+                if (lat != nullptr) {
+                    release_lattice(lat, st);
+                    lat = guard.l = nullptr;
+                }
+                FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, nullptr, model_ref,
+                                          wmats.as<float>()));
+                guard.l = lat;
+                FR_TRY(blur_lattice(lat, st));
+                rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+            }
+            if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+            if (fused) {
+                FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
+                                          wmats.as<float>(), params->residual, 0, part.as<float>(), st));
+                if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+                FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
+                                           wstat.as<double>(), st));
+            } else {
+                FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
+                                    wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+                if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+                FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
+                                     wm1.as<float>(), pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m,
+                                     wjtj.as<double>(), wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+            }
+            FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(),
+                                      wmats.as<float>(), wtn.as<double>(), wstatus.as<int32_t>(),
+                                      wactive.as<int32_t>(), st));
+            if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
+            if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_it)) {
+                int n_active = 0;
+                FR_TRY(check_active(st, n_active));
+                if (n_active == 0) {
+                    ++it;
+                    break;
+                }
             }
         }
     }

@@ -66,6 +66,7 @@ struct fr_ctx {
     };
     std::vector<Block> cache;
     std::vector<hipEvent_t> spare_events;
+    hipStream_t graph_stream = nullptr;   // capture/replay stream of fr_register's graphs
 };
 
 struct fr_lattice {

@@ -389,3 +389,29 @@ def test_register_fused_matches_oracle_other_variants(fr, ctx, feat, residual):
     assert int(st[0]) == 0
     ang, dt, ok = pose_close(T[0], ref)
     assert ok, (ang, dt)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("fixed", [True, False])
+def test_graph_replay_equals_the_eager_loop(fr, ctx, fixed, fused):
+    """fr_register replays its iterations from a captured HIP graph unless FR_PROFILE_EVENTS asks for
+    per-kernel events (then every kernel is launched eagerly).  Several calls, each replaying its graph
+    (several times in the early-stopping mode, with the host's checks between replays), give the eager
+    loop's poses, statuses and iteration counts bitwise."""
+    pairs = [synth.depth_pair(40 + i, width=w, height=h, f=f)
+             for i, (w, h, f) in enumerate([(160, 120, 131.25), (96, 72, 78.75), (200, 150, 164.0)])]
+    q = pairs[0]
+    _say(f"[graph] fixed={fixed} fused={fused} sizes={[len(p.model) for p in pairs]}")
+    model = upload([p.model for p in pairs], [p.model_n for p in pairs])
+    obs = upload([p.obs for p in pairs], [p.obs_n for p in pairs])
+    T0 = np.stack([p.T_gt @ oracle.se3_exp(np.array([0.01, -0.01, 0.005, 0.01, 0.005, -0.01])) for p in pairs])
+    kw = dict(iters=14, w=q.w, fixed=fixed, fused=fused, tol=1e-5)
+    eager = fr.register(ctx, model, obs, fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, profile=True, **kw),
+                        T0=T0)
+    for _ in range(3):
+        T, st, rep = fr.register(ctx, model, obs, fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, **kw), T0=T0)
+        np.testing.assert_array_equal(T, eager[0])
+        np.testing.assert_array_equal(st, eager[1])
+        assert rep.iterations == eager[2].iterations
+    if not fixed:
+        assert eager[2].iterations < 14     # stopped early: the graph was replayed several times
