@@ -110,6 +110,25 @@ def copy_reference(nbytes=256 << 20, reps=3):
     log(f"copy reference: {reps} copies of {nbytes} bytes")
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: the best of `reps` device-to-device copies of `nbytes` (read + write
+    bytes over the copy's time, HIP events on the copy's stream)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2.0 * nbytes / best / 1e9
+
+
 # ------------------------------------------------------------------------------
 # served stream
 SERVE_FRAMES = 64
@@ -424,6 +443,50 @@ def alignment_error(T, T_gt, x):
     return float(np.mean(np.linalg.norm(np.asarray(x, np.float64) @ D[:3, :3].T + D[:3, 3], axis=1)))
 
 
+def profile_workload(name):
+    """One of the single-pair workloads alone, three times (the subject of a kernel trace)."""
+    import torch
+    import paper_1811_10136_amd as fr
+    ctx = fr.Context(0)
+    if name == "nodegraph":
+        p = synth.nodegraph_pair(0)
+        e = p.extra
+        g = fr.NodeGraph(e["nodes"], e["skin_idx"], e["skin_w"], e["edges"], 1.0)
+        prm = fr.register_params(3, "pt2pt", p.sigma, iters=p.iters, w=p.w)
+        m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+        run = lambda: fr.fr_register_nodegraph(ctx.h, m, o, g, prm, np.repeat(np.eye(4)[None], len(e["nodes"]), 0))
+    elif name == "articulated":
+        p = synth.articulated_pair(1)
+        t = p.extra["tree"]
+        kt = fr.KinematicTree(t.parent, t.dof_offset, t.origin, t.axis)
+        prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=p.iters, w=p.w)
+        m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+        run = lambda: fr.fr_register_articulated(ctx.h, m, p.extra["body_offsets"], o, kt, prm,
+                                                 p.extra["theta0"].copy())
+    elif name == "descriptors":
+        p = synth.feature_pair(7, m=200_000, dim=16)
+        e = p.extra
+        m, o = fr.Cloud.from_numpy([p.model]), fr.Cloud.from_numpy([p.obs])
+        mf, of = torch.from_numpy(e["model_feat"]).cuda(), torch.from_numpy(e["obs_feat"]).cuda()
+        prm = fr.register_params(3, "pt2pt", 0.01, iters=20, w=p.w)
+        run = lambda: fr.fr_register_features(ctx.h, m, mf, o, of, 16, e["sigma_f"], prm,
+                                              np.repeat(np.eye(4)[None], 1, 0))
+    else:
+        p = synth.depth_pair(0)
+        m, o = fr.Cloud.from_numpy([p.model], [p.model_n]), fr.Cloud.from_numpy([p.obs], [p.obs_n])
+        if name == "uncustomised":
+            prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, blurred=True)
+            run = lambda: fr.register(ctx, m, o, prm)
+        else:
+            prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, m2=True)
+            run = lambda: fr.register_sigma(ctx, m, o, prm, p.sigma[0], 2e-3)
+    for i in range(3):
+        run()
+        torch.cuda.synchronize()
+        log(f"{name}: run {i + 1} of 3 done")
+    ctx.close()
+
+
 def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):
     """Lattice build of the 64 observation frames, sorted and atomic splat (observation points per second)."""
     res = {}
@@ -457,7 +520,13 @@ def main():
     ap.add_argument("--serve-capacity-requests", type=int, default=256)
     ap.add_argument("--serve-lambdas", type=float, nargs="*", default=[1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--plain-lambdas", type=float, nargs="*", default=[1.0])
+    ap.add_argument("--profile-workload", choices=["nodegraph", "articulated", "descriptors", "uncustomised",
+                                                    "updated-sigma"],
+                    help="run one single-pair workload a few times and exit (for kernel traces)")
     args = ap.parse_args()
+    if args.profile_workload:
+        profile_workload(args.profile_workload)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
@@ -519,6 +588,7 @@ def main():
     achieved = alg_bytes / est_avg_s / 1e9
     kernel = "k_estep_fused<6,7,rigid,pt2pl>" if args.fused else "k_estep<6,7,rigid>"
     traffic = traffic_from_profile(points_per_launch, kernel)
+    copy_gbs = copy_bandwidth()
 
     value = points_per_launch * args.iters * args.steps / total_s
     out = {
@@ -558,6 +628,8 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
             "mean_launch_ms": est_avg_s * 1e3,
+            "measured_copy_gbs": copy_gbs,
+            "frac_of_measured_copy": achieved / copy_gbs,
         },
     }
     if not args.no_other:
