@@ -54,7 +54,7 @@ enum { FR_SPLAT_SORTED = 0, FR_SPLAT_ATOMIC = 1 };
 enum { FR_XF_NONE = 0, FR_XF_RIGID = 1, FR_XF_SEGMENTED = 2 };
 enum { FR_PT2PT = 0, FR_PT2PL = 1 };
 enum { FR_KIN_RIGID = 0, FR_KIN_ARTICULATED = 1, FR_KIN_NODEGRAPH = 2 };
-enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4, FR_BLURRED = 8 };
+enum { FR_FIXED_ITERS = 1, FR_PROFILE_EVENTS = 2, FR_FUSED = 4, FR_BLURRED = 8, FR_GRAPH = 16 };
 
 typedef struct fr_ctx fr_ctx;
 typedef struct fr_lattice fr_lattice;
@@ -272,7 +272,12 @@ typedef struct {
                               kernel: same terms, binary32 partial sums taken in another order) |
                               FR_BLURRED (the uncustomised filter: every iteration builds the joint
                               lattice of the observation and the moved model and blurs it, as
-                              fr_lattice_build_joint + fr_lattice_blur; not with FR_FUSED) */
+                              fr_lattice_build_joint + fr_lattice_blur; not with FR_FUSED) |
+                              FR_GRAPH (capture the kernels of up to 32 iterations -- 4, between
+                              the convergence checks, without FR_FIXED_ITERS -- into a HIP graph
+                              on a stream of the context and replay it; same results bitwise;
+                              ignored with FR_PROFILE_EVENTS or FR_BLURRED.  The capture costs
+                              more than it saves when the call is short) */
     int32_t kinematics;    /* FR_KIN_RIGID */
 } fr_register_params;
 

@@ -39,7 +39,7 @@ FR_SPLAT_SORTED, FR_SPLAT_ATOMIC = 0, 1
 FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
 FR_KIN_RIGID, FR_KIN_ARTICULATED, FR_KIN_NODEGRAPH = 0, 1, 2
-FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED, FR_BLURRED = 1, 2, 4, 8
+FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED, FR_BLURRED, FR_GRAPH = 1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
                 5: "FR_EDEGENERATE", 6: "FR_EDEVICE"}
@@ -511,11 +511,11 @@ def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
 
 def register_params(feat: int, residual: str, sigma, sigma_n=0.5, iters=20, w=0.1, c=None, tol=1e-6,
                     fixed=True, profile=False, splat=FR_SPLAT_SORTED, fused=False,
-                    m2=False, blurred=False) -> fr_register_params:
+                    m2=False, blurred=False, graph=False) -> fr_register_params:
     res = FR_PT2PL if residual == "pt2pl" else FR_PT2PT
     vals = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
     flags = (FR_FIXED_ITERS if fixed else 0) | (FR_PROFILE_EVENTS if profile else 0) | (FR_FUSED if fused else 0) | \
-        (FR_BLURRED if blurred else 0)
+        (FR_BLURRED if blurred else 0) | (FR_GRAPH if graph else 0)
     if m2:
         vals = FR_VAL_PT2PL_M2 if residual == "pt2pl" else FR_VAL_PT2PT_M2
     return fr_register_params(lattice_params(feat, vals, sigma, sigma_n, splat), res, iters, float(w),

@@ -1050,13 +1050,14 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     };
     auto t2 = clk::now();
     int it = 0;
-    if (!prof && !blurred && max_it > 0) {
-        // The iterations of a block are captured once into a HIP graph and replayed: one launch per block
-        // instead of three or four per iteration.  Capture needs a stream of its own (the caller's may be
+    if ((params->flags & FR_GRAPH) != 0 && !prof && !blurred && max_it > 0) {
+        // The iterations of a block (up to 32 with fixed iterations, the 4 between convergence checks
+        // otherwise) are captured once into a HIP graph and replayed: one launch per block instead of
+        // three or four per iteration.  Capture needs a stream of its own (the caller's may be
         // the null stream); the caller's stream is idle here, and the block is waited for below.
         hipStream_t gs = nullptr;
         FR_TRY(graph_stream(ctx, gs));
-        const int blk = fixed ? max_it : 4;
+        const int blk = fixed ? std::min(max_it, 32) : 4;   // bounded graph size; a remainder runs eagerly
         GraphGuard gg;
         FR_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
         fr_status cs = FR_OK;

@@ -394,8 +394,8 @@ def test_register_fused_matches_oracle_other_variants(fr, ctx, feat, residual):
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("fixed", [True, False])
 def test_graph_replay_equals_the_eager_loop(fr, ctx, fixed, fused):
-    """fr_register replays its iterations from a captured HIP graph unless FR_PROFILE_EVENTS asks for
-    per-kernel events (then every kernel is launched eagerly).  Several calls, each replaying its graph
+    """With FR_GRAPH, fr_register replays its iterations from a captured HIP graph (FR_PROFILE_EVENTS
+    launches every kernel eagerly).  Several calls, each replaying its graph
     (several times in the early-stopping mode, with the host's checks between replays), give the eager
     loop's poses, statuses and iteration counts bitwise."""
     pairs = [synth.depth_pair(40 + i, width=w, height=h, f=f)
@@ -409,9 +409,23 @@ def test_graph_replay_equals_the_eager_loop(fr, ctx, fixed, fused):
     eager = fr.register(ctx, model, obs, fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, profile=True, **kw),
                         T0=T0)
     for _ in range(3):
-        T, st, rep = fr.register(ctx, model, obs, fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, **kw), T0=T0)
+        T, st, rep = fr.register(ctx, model, obs, fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, graph=True,
+                                                                     **kw), T0=T0)
         np.testing.assert_array_equal(T, eager[0])
         np.testing.assert_array_equal(st, eager[1])
         assert rep.iterations == eager[2].iterations
     if not fixed:
         assert eager[2].iterations < 14     # stopped early: the graph was replayed several times
+
+
+def test_graph_blocks_and_remainder_equal_the_eager_loop(fr, ctx):
+    """40 fixed iterations: one 32-iteration graph replay, then 8 iterations launched eagerly."""
+    p = synth.ellipsoid_pair(6)
+    _say("[graph] 40 fixed iterations")
+    m, o = upload([p.model]), upload([p.obs])
+    kw = dict(iters=40, w=p.w, fixed=True)
+    eager = fr.register(ctx, m, o, fr.register_params(3, "pt2pt", p.sigma, profile=True, **kw))
+    for _ in range(2):
+        T, st, rep = fr.register(ctx, m, o, fr.register_params(3, "pt2pt", p.sigma, graph=True, **kw))
+        np.testing.assert_array_equal(T, eager[0])
+        assert rep.iterations == 40 and st[0] == eager[1][0]
