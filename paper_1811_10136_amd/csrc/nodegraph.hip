@@ -659,47 +659,17 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     d.K = K;
     d.E = E;
     d.M = M;
-    // blocks: unique (k <= l) pairs from co-skinned nodes and from edges
-    struct Ent {
-        int64_t key;
-        int32_t pt;
-        float w;
+    // blocks: unique (k <= l) pairs from co-skinned nodes and from edges, in key
+    // order (key = k K + l); each data block lists its (point, w_k w_l) entries in
+    // point order
+    auto pair_key = [&](int64_t i, int a, int c, int64_t &key, float &wt) {
+        int32_t k = g->skin_idx[4 * i + a], l = g->skin_idx[4 * i + c];
+        if (k < 0 || k >= K || l < 0 || l >= K || (a != c && k == l)) return false;
+        if (k > l) std::swap(k, l);
+        key = (int64_t)k * K + l;
+        wt = g->skin_w[4 * i + a] * g->skin_w[4 * i + c];
+        return true;
     };
-    std::vector<Ent> ent;
-    ent.reserve((size_t)M * 10);
-    for (int64_t i = 0; i < M; ++i) {
-        const int32_t *id = g->skin_idx + 4 * i;
-        const float *w = g->skin_w + 4 * i;
-        for (int a = 0; a < 4; ++a)
-            for (int c = a; c < 4; ++c) {
-                int32_t k = id[a], l = id[c];
-                if (k < 0 || k >= K || l < 0 || l >= K || (a != c && k == l)) continue;
-                if (k > l) std::swap(k, l);
-                ent.push_back({(int64_t)k * K + l, (int32_t)i, w[a] * w[c]});
-            }
-    }
-    // group the entries by block key, keeping point order inside a block: a
-    // counting sort over the K x K keys when that table is small, else a
-    // stable sort
-    if ((int64_t)K * K <= ((int64_t)1 << 24)) {
-        std::vector<int32_t> cnt((size_t)K * K + 1, 0);
-        for (const Ent &e : ent) ++cnt[(size_t)e.key + 1];
-        for (size_t q = 1; q < cnt.size(); ++q) cnt[q] += cnt[q - 1];
-        std::vector<Ent> sorted(ent.size());
-        for (const Ent &e : ent) sorted[(size_t)cnt[(size_t)e.key]++] = e;
-        ent.swap(sorted);
-    } else {
-        std::stable_sort(ent.begin(), ent.end(), [](const Ent &x, const Ent &y) { return x.key < y.key; });
-    }
-    std::vector<int64_t> keys;
-    std::vector<int32_t> data_off;   // per block offsets into ent
-    for (size_t e = 0; e < ent.size(); ++e)
-        if (e == 0 || ent[e].key != ent[e - 1].key) {
-            keys.push_back(ent[e].key);
-            data_off.push_back((int32_t)e);
-        }
-    const size_t n_data_blocks = keys.size();
-    // edge blocks (may add new keys)
     std::vector<int64_t> ekeys;
     for (int32_t q = 0; q < E; ++q) {
         const int32_t j = g->edges[2 * q], k = g->edges[2 * q + 1];
@@ -708,31 +678,81 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
         ekeys.push_back((int64_t)std::min(j, k) * K + std::max(j, k));
     }
     for (int32_t k = 0; k < K; ++k) ekeys.push_back((int64_t)k * K + k);   // every node has a diagonal block
-    std::vector<int64_t> all(keys);
-    all.insert(all.end(), ekeys.begin(), ekeys.end());
-    std::sort(all.begin(), all.end());
-    all.erase(std::unique(all.begin(), all.end()), all.end());
+    std::vector<int64_t> all;
+    std::vector<int32_t> boff, bpts, diag(K);
+    std::vector<float> bw;
+    if ((int64_t)K * K <= ((int64_t)1 << 24)) {
+        // dense K x K table: count per key, number the keys in order, scatter in point order
+        std::vector<int32_t> cnt((size_t)K * K, 0);
+        std::vector<uint8_t> used((size_t)K * K, 0);
+        for (int64_t i = 0; i < M; ++i)
+            for (int a = 0; a < 4; ++a)
+                for (int c = a; c < 4; ++c) {
+                    int64_t key;
+                    float wt;
+                    if (pair_key(i, a, c, key, wt)) {
+                        ++cnt[(size_t)key];
+                        used[(size_t)key] = 1;
+                    }
+                }
+        for (int64_t key : ekeys) used[(size_t)key] = 1;
+        std::vector<int32_t> fill((size_t)K * K, 0);
+        int32_t total = 0;
+        for (int64_t key = 0; key < (int64_t)K * K; ++key)
+            if (used[(size_t)key]) {
+                all.push_back(key);
+                boff.push_back(total);
+                fill[(size_t)key] = total;
+                total += cnt[(size_t)key];
+            }
+        boff.push_back(total);
+        bpts.resize(total);
+        bw.resize(total);
+        for (int64_t i = 0; i < M; ++i)
+            for (int a = 0; a < 4; ++a)
+                for (int c = a; c < 4; ++c) {
+                    int64_t key;
+                    float wt;
+                    if (pair_key(i, a, c, key, wt)) {
+                        const int32_t pos = fill[(size_t)key]++;
+                        bpts[pos] = (int32_t)i;
+                        bw[pos] = wt;
+                    }
+                }
+    } else {
+        // many nodes: a stable sort of the entries by key
+        struct Ent {
+            int64_t key;
+            int32_t pt;
+            float w;
+        };
+        std::vector<Ent> ent;
+        ent.reserve((size_t)M * 10);
+        for (int64_t i = 0; i < M; ++i)
+            for (int a = 0; a < 4; ++a)
+                for (int c = a; c < 4; ++c) {
+                    int64_t key;
+                    float wt;
+                    if (pair_key(i, a, c, key, wt)) ent.push_back({key, (int32_t)i, wt});
+                }
+        std::stable_sort(ent.begin(), ent.end(), [](const Ent &x, const Ent &y) { return x.key < y.key; });
+        for (const Ent &e : ent) all.push_back(e.key);
+        all.insert(all.end(), ekeys.begin(), ekeys.end());
+        std::sort(all.begin(), all.end());
+        all.erase(std::unique(all.begin(), all.end()), all.end());
+        size_t e = 0;
+        for (int64_t key : all) {
+            boff.push_back((int32_t)bpts.size());
+            for (; e < ent.size() && ent[e].key == key; ++e) {
+                bpts.push_back(ent[e].pt);
+                bw.push_back(ent[e].w);
+            }
+        }
+        boff.push_back((int32_t)bpts.size());
+    }
     const int32_t NB = (int32_t)all.size();
     d.n_blocks = NB;
     auto block_of = [&](int64_t key) { return (int32_t)(std::lower_bound(all.begin(), all.end(), key) - all.begin()); };
-    // data CSR over all blocks (empty for edge-only blocks)
-    std::vector<int32_t> boff(NB + 1, 0), bpts, diag(K);
-    std::vector<float> bw;
-    {
-        size_t di = 0;
-        for (int32_t b = 0; b < NB; ++b) {
-            boff[b] = (int32_t)bpts.size();
-            if (di < n_data_blocks && keys[di] == all[b]) {
-                const size_t e1 = (di + 1 < n_data_blocks) ? (size_t)data_off[di + 1] : ent.size();
-                for (size_t e = data_off[di]; e < e1; ++e) {
-                    bpts.push_back(ent[e].pt);
-                    bw.push_back(ent[e].w);
-                }
-                ++di;
-            }
-        }
-        boff[NB] = (int32_t)bpts.size();
-    }
     for (int32_t k = 0; k < K; ++k) diag[k] = block_of((int64_t)k * K + k);
     // node right-hand side CSR: (point, w_ki) in point order
     std::vector<int32_t> roff(K + 1, 0), rpts;
