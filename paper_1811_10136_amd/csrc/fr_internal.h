@@ -251,7 +251,7 @@ struct NodeGraphDev {
     const int32_t *row_off = nullptr, *row_blk = nullptr, *row_col = nullptr, *diag_blk = nullptr;
     double *T = nullptr, *dq = nullptr, *data21 = nullptr, *bdata = nullptr, *edge_terms = nullptr, *A = nullptr,
            *minv = nullptr, *rhs = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
-           *info = nullptr, *part = nullptr;
+           *s = nullptr, *info = nullptr, *part = nullptr;
     float *terms = nullptr;
     int32_t *bad = nullptr;
 };

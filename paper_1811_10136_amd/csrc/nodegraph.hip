@@ -425,110 +425,103 @@ __global__ void __launch_bounds__(kPcgThreads) k_ng_pcg(int32_t K, const int32_t
 
 // The same block-Jacobi PCG spread over G workgroups of one cooperative
 // launch: workgroup g owns a contiguous range of nodes (their rows of A, x, r,
-// z, p, q); the two dot products of an iteration are summed per workgroup in a
-// fixed order, exchanged through `part` and added in workgroup order after a
-// grid-wide barrier, so every workgroup takes the same decisions and the
-// result is reproducible.  Three barriers per iteration.
+// u, w, p, s).  The iteration is the single-reduction form of Chronopoulos and
+// Gear (1989): with u = M^-1 r and w = A u, the three sums (r, r), (r, u) and
+// (w, u) of an iteration are taken together, s = A p is carried by the
+// recurrence s <- w + beta s, and the step length follows from
+// alpha = gamma / (delta - beta gamma / alpha_old).  In exact arithmetic the
+// iterates are those of the textbook PCG.  Per iteration two grid-wide
+// barriers: one before the product (u of every workgroup complete), one for
+// the sums.  The sums are taken per workgroup in a fixed order, exchanged
+// through `part` and added in workgroup order, so every workgroup takes the
+// same decisions and the result is reproducible.
 struct PcgArgs {
     int32_t K;
     const int32_t *row_off, *row_blk, *row_col;
     const double *A, *minv, *rhs;
-    double *x, *r, *z, *p, *q;
+    double *x, *r, *u, *w, *p, *s;
     double *part;           // 2 x 3 x gridDim.x partial sums
     double tol;
     int32_t max_it;
     double *info;
 };
 
-__device__ double coop_block_sum(double v, double *red)
+// Block sums of three values at once (one pass through LDS).
+__device__ void coop_block_sum3(double v[3], double *red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wave] = v;
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+        if (lane == 0) red[3 * wave + i] = v[i];
+    }
     __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < kCoopThreads / 64; ++w) s += red[w];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double t = 0.0;
+        for (int w = 0; w < kCoopThreads / 64; ++w) t += red[3 * w + i];
+        v[i] = t;
+    }
     __syncthreads();
-    return s;
 }
 
 __global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
 {
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
-    __shared__ double red[kCoopThreads / 64];
+    __shared__ double red[3 * (kCoopThreads / 64)];
     __shared__ double lanes[kCoopThreads];
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const int kb = (a.K + G - 1) / G;
     const int k0 = min(a.K, g * kb), k1 = min(a.K, k0 + kb);
     const int u0 = 6 * k0, u1 = 6 * k1, R = u1 - u0;
     const int L = R > 0 ? max(1, min(8, kCoopThreads / R)) : 1;   // lanes per SpMV row
-    // grid-wide sums of n (1 or 2) values per workgroup through partial arrays
-    // slot, slot + 1 (of 6: a slot is written again only two iterations later,
-    // after every workgroup has passed further barriers)
-    auto grid_sum = [&](int n, double v0, double v1, int slot, double &s0, double &s1) {
-        const double b0 = coop_block_sum(v0, red);
-        const double b1 = n > 1 ? coop_block_sum(v1, red) : 0.0;
-        if (tid == 0) {
-            a.part[slot * G + g] = b0;
-            if (n > 1) a.part[(slot + 1) * G + g] = b1;
-        }
+    // grid-wide sums of three values per workgroup through the partial slots
+    // set*3 .. set*3+2 (sets alternate between successive sums)
+    auto grid_sum3 = [&](double v[3], int set) {
+        coop_block_sum3(v, red);
+        if (tid == 0)
+            for (int i = 0; i < 3; ++i) a.part[(3 * set + i) * G + g] = v[i];
         __threadfence();
         grid.sync();
-        s0 = 0.0;
-        s1 = 0.0;
-        for (int b = 0; b < G; ++b) {
-            s0 += a.part[slot * G + b];
-            if (n > 1) s1 += a.part[(slot + 1) * G + b];
+        for (int i = 0; i < 3; ++i) {
+            double t = 0.0;
+            for (int b = 0; b < G; ++b) t += a.part[(3 * set + i) * G + b];
+            v[i] = t;
         }
     };
+    // u = M^-1 r over the owned nodes; returns the owned parts of (r, u)
     auto precond = [&]() {
-        for (int u = u0 + tid; u < u1; u += kCoopThreads) {
-            const int k = u / 6, c = u % 6;
+        double ru = 0.0;
+        for (int q = u0 + tid; q < u1; q += kCoopThreads) {
+            const int k = q / 6, c = q % 6;
             const double *Mi = a.minv + 36 * k;
             double v = 0.0;
             for (int b = 0; b < 6; ++b) v += Mi[6 * c + b] * a.r[6 * k + b];
-            a.z[u] = v;
+            a.u[q] = v;
+            ru += a.r[q] * v;
         }
+        return ru;
     };
-    double bb = 0.0;
-    for (int u = u0 + tid; u < u1; u += kCoopThreads) {
-        a.x[u] = 0.0;
-        a.r[u] = -a.rhs[u];
-        bb += a.rhs[u] * a.rhs[u];
-    }
-    __syncthreads();   // the preconditioner reads the r of a node's six rows, written by other threads
-    precond();
-    double rz_loc = 0.0;
-    for (int u = u0 + tid; u < u1; u += kCoopThreads) {
-        a.p[u] = a.z[u];
-        rz_loc += a.r[u] * a.z[u];
-    }
-    double bnorm2, rz;
-    grid_sum(2, bb, rz_loc, 0, bnorm2, rz);
-    const double bnorm = sqrt(bnorm2);
-    int it = 0;
-    double rel = bnorm > 0.0 ? 1.0 : 0.0;
-    while (it < a.max_it && bnorm > 0.0) {
-        const int par = (it & 1) ? 3 : 0;   // partial slots of this iteration
-        grid.sync();   // p of every workgroup is complete
-        // q = A p for the owned rows, L lanes per row summing every L-th entry
-        double pq_loc = 0.0;
+    // w = A u for the owned rows, L lanes per row summing every L-th entry;
+    // returns the owned part of (w, u)
+    auto spmv = [&]() {
+        double wu = 0.0;
         for (int r0 = 0; r0 < R; r0 += kCoopThreads / L) {
             const int row = r0 + tid / L, lane = tid % L;
             double acc = 0.0;
             const bool on = tid / L < kCoopThreads / L && row < R;
             if (on) {
-                const int u = u0 + row, k = u / 6, c = u % 6;
+                const int q = u0 + row, k = q / 6, c = q % 6;
                 for (int e = a.row_off[k] + lane; e < a.row_off[k + 1]; e += L) {
                     const int ref = a.row_blk[e];
                     const double *B = a.A + (size_t)36 * (ref >> 1);
-                    const double *pl = a.p + 6 * a.row_col[e];
+                    const double *ul = a.u + 6 * a.row_col[e];
                     if (!(ref & 1))
-                        for (int b = 0; b < 6; ++b) acc += B[6 * c + b] * pl[b];
+                        for (int b = 0; b < 6; ++b) acc += B[6 * c + b] * ul[b];
                     else
-                        for (int b = 0; b < 6; ++b) acc += B[6 * b + c] * pl[b];
+                        for (int b = 0; b < 6; ++b) acc += B[6 * b + c] * ul[b];
                 }
             }
             lanes[tid] = acc;
@@ -536,34 +529,64 @@ __global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
             if (on && lane == 0) {
                 double y = 0.0;
                 for (int l = 0; l < L; ++l) y += lanes[tid + l];
-                const int u = u0 + row;
-                a.q[u] = y;
-                pq_loc += a.p[u] * y;
+                const int q = u0 + row;
+                a.w[q] = y;
+                wu += a.u[q] * y;
             }
             __syncthreads();
         }
-        double pq, unused;
-        grid_sum(1, pq_loc, 0.0, par, pq, unused);
-        if (!(pq > 0.0)) break;
-        const double alpha = rz / pq;
-        double rr_loc = 0.0;
-        for (int u = u0 + tid; u < u1; u += kCoopThreads) {
-            a.x[u] += alpha * a.p[u];
-            a.r[u] -= alpha * a.q[u];
-            rr_loc += a.r[u] * a.r[u];
+        return wu;
+    };
+    double bb = 0.0;
+    for (int q = u0 + tid; q < u1; q += kCoopThreads) {
+        a.x[q] = 0.0;
+        a.r[q] = -a.rhs[q];
+        bb += a.rhs[q] * a.rhs[q];
+    }
+    __syncthreads();   // the preconditioner reads the r of a node's six rows, written by other threads
+    const double ru0 = precond();
+    grid.sync();       // u of every workgroup complete
+    const double wu0 = spmv();
+    double v[3] = {bb, ru0, wu0};
+    grid_sum3(v, 0);
+    const double bnorm = sqrt(v[0]);
+    double gamma = v[1], delta = v[2];
+    double alpha = delta > 0.0 ? gamma / delta : 0.0;
+    for (int q = u0 + tid; q < u1; q += kCoopThreads) {
+        a.p[q] = a.u[q];
+        a.s[q] = a.w[q];
+    }
+    int it = 0;
+    double rel = bnorm > 0.0 ? 1.0 : 0.0;
+    bool go = bnorm > 0.0 && delta > 0.0;
+    while (go && it < a.max_it) {
+        double rr = 0.0;
+        for (int q = u0 + tid; q < u1; q += kCoopThreads) {
+            a.x[q] += alpha * a.p[q];
+            a.r[q] -= alpha * a.s[q];
+            rr += a.r[q] * a.r[q];
         }
         __syncthreads();
-        precond();
-        double rzn_loc = 0.0;
-        for (int u = u0 + tid; u < u1; u += kCoopThreads) rzn_loc += a.r[u] * a.z[u];
-        double rr, rz_new;
-        grid_sum(2, rr_loc, rzn_loc, par + 1, rr, rz_new);
+        const double ru = precond();
+        grid.sync();   // u of every workgroup complete
+        const double wu = spmv();
+        v[0] = rr;
+        v[1] = ru;
+        v[2] = wu;
+        grid_sum3(v, 1 - (it & 1));
         ++it;
-        rel = sqrt(rr) / bnorm;
+        rel = sqrt(v[0]) / bnorm;
         if (rel <= a.tol) break;
-        const double beta = rz_new / rz;
-        rz = rz_new;
-        for (int u = u0 + tid; u < u1; u += kCoopThreads) a.p[u] = a.z[u] + beta * a.p[u];
+        const double gamma_new = v[1];
+        const double beta = gamma_new / gamma;
+        const double denom = v[2] - beta * gamma_new / alpha;
+        if (!(denom > 0.0)) break;
+        alpha = gamma_new / denom;
+        gamma = gamma_new;
+        for (int q = u0 + tid; q < u1; q += kCoopThreads) {
+            a.p[q] = a.u[q] + beta * a.p[q];
+            a.s[q] = a.w[q] + beta * a.s[q];
+        }
     }
     if (g == 0 && tid == 0) {
         a.info[0] = it;
@@ -869,7 +892,7 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     const size_t n = 6 * (size_t)K;
     FR_TRY(d.work.alloc(ctx, sizeof(double) * (12 * (size_t)K + 8 * (size_t)K + 21 * (size_t)NB + 6 * (size_t)K +
                                                120 * (size_t)std::max(E, 1) + 36 * (size_t)NB + 36 * (size_t)K +
-                                               6 * n + 2 + 8 + 6 * (size_t)kCoopMaxBlocks) +
+                                               7 * n + 2 + 8 + 6 * (size_t)kCoopMaxBlocks) +
                                 sizeof(float) * 27 * (size_t)std::max<int64_t>(M, 1) + sizeof(int32_t) * 4));
     double *w = d.work.as<double>();
     d.T = w;
@@ -897,6 +920,8 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     d.p = w;
     w += n;
     d.q = w;
+    w += n;
+    d.s = w;
     w += n;
     d.info = w;
     w += 8;
@@ -962,8 +987,8 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
     const int G = std::min({kCoopMaxBlocks, std::max(1, d.K / 4), per_cu * cus});
     bool done = false;
     if (coop && G >= 8) {
-        PcgArgs pa{d.K, d.row_off, d.row_blk, d.row_col, d.A, d.minv, d.rhs, d.x, d.r, d.z, d.p, d.q, d.part,
-                   tol, max_it, d.info};
+        PcgArgs pa{d.K, d.row_off, d.row_blk, d.row_col, d.A, d.minv, d.rhs, d.x, d.r, d.z, d.q, d.p, d.s,
+                   d.part, tol, max_it, d.info};
         void *args[] = {&pa};
         done = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_ng_pcg_coop), dim3(G), dim3(kCoopThreads),
                                           args, 0, st) == hipSuccess;
