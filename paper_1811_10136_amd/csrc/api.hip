@@ -295,15 +295,13 @@ fr_status check_lattice_params(const fr_lattice_params *p)
 
 void free_lattice(fr_lattice *lat, hipStream_t st, bool idle)
 {
-    if (lat->tkey) dev_free(lat->ctx, lat->tkey, lat->tkey_bytes, st, idle);
-    if (lat->tval) dev_free(lat->ctx, lat->tval, lat->tval_bytes, st, idle);
+    if (lat->tab) dev_free(lat->ctx, lat->tab, lat->tab_bytes, st, idle);
     if (lat->sets_d) dev_free(lat->ctx, lat->sets_d, lat->sets_h.size() * sizeof(SetTable), st, idle);
     if (lat->vkey) dev_free(lat->ctx, lat->vkey, lat->vert_bytes, st, idle);
     if (lat->err_d) dev_free(lat->ctx, lat->err_d, sizeof(int32_t), st, idle);
     if (lat->kfeat_d) dev_free(lat->ctx, lat->kfeat_d, lat->kfeat.size() * sizeof(float), st, idle);
     lat->kfeat_d = nullptr;
-    lat->tkey = nullptr;
-    lat->tval = nullptr;
+    lat->tab = nullptr;
     lat->sets_d = nullptr;
     lat->vkey = nullptr;
     lat->err_d = nullptr;
@@ -690,7 +688,7 @@ fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertic
     if (n_vertices) *n_vertices = st.n_vertices;
     if (capacity) *capacity = (int64_t)st.cap;
     if (device_bytes)
-        *device_bytes = (int64_t)st.cap * (KW * 8 + VP * 4) +
+        *device_bytes = (int64_t)st.cap * slot_bytes(KW, VP) +
                         (int64_t)st.n_vertices * (KW * 8 + 4 + 4 * lat->V);
     return FR_OK;
 }

@@ -74,7 +74,7 @@ __device__ __forceinline__ void slice_point(const EstepArgs &a, int32_t s, int64
 
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0f;
-    slice_simplex<KW, V, D>(st.keys, st.vals, st, keys, b, acc);
+    slice_simplex<KW, V, D>(st, keys, b, acc);
     x[0] = p[0];
     x[1] = p[1];
     x[2] = p[2];
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     embed<d>(p, kk, keys, b);
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        const int64_t slot = find_slot<KW>(st.keys, st, keys[v]);
+        const int64_t slot = find_slot<KW, V>(st, keys[v]);
         if (slot >= 0) a.touched[st.slot_base + slot] = 1u;
     }
 }
@@ -324,9 +324,9 @@ __global__ void __launch_bounds__(256) k_estep_feat(FeatArgs a)
 #pragma unroll 1
     for (int m = 0; m < D; ++m) {   // one vertex at a time: keeps the key walk in registers
         const float b = embed_hd_next<d>(h, m);
-        const int64_t r = find_slot<KW>(st.keys, st, h.P);
+        const int64_t r = find_slot<KW, 4>(st, h.P);
         if (r >= 0) {
-            const u32x4 q = load_at<u32x4>(st.vals, (uint32_t)r * 16u);
+            const u32x4 q = load_at<u32x4>(st.vals, (uint32_t)r * SlotGeom<KW, 4>::bytes);
             acc[0] = fmaf(b, __uint_as_float(q.x), acc[0]);
             acc[1] = fmaf(b, __uint_as_float(q.y), acc[1]);
             acc[2] = fmaf(b, __uint_as_float(q.z), acc[2]);

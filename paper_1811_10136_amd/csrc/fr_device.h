@@ -23,13 +23,31 @@ constexpr int kEstepTile = 256;
 
 template <int d> struct KeyWords { static constexpr int value = (d + 2) / 3; };   // 3 coordinates per u64
 
-// The lattice table of one set is a two-choice cuckoo hash: every vertex key
-// sits in one of two slots p1(key), p2(key), so a lookup reads exactly two
-// key slots and, on a match, one value slot -- no probe chains.  Keys and
-// values are separate arrays: keys[slot] holds KW packed words (word 0 ==
-// kKeyEmpty marks a free slot), vals[slot] holds V binary32 values padded to
-// VP = 4 or 8 (one or two 16-byte loads).
+// The lattice table of one set is a bucketed two-choice cuckoo hash: a
+// bucket is two slots side by side, every vertex key sits in a slot of one of
+// its two buckets b1(key), b2(key), and a slot holds the key's KW packed words
+// (word 0 == kKeyEmpty marks a free slot) followed, at a 16-byte aligned
+// offset, by its V binary32 values padded to VP = 4 or 8.  A key goes to b2
+// only when b1 is full, and a filled slot is never emptied, so a lookup reads
+// b1 (one cache line holding both keys and their values), stops there if it
+// found the key or saw a free slot, and reads b2 otherwise.
 template <int V> struct ValPad { static constexpr int value = V <= 4 ? 4 : 8; };
+
+// Bytes of a slot (a power of two >= 32) and the byte offset of its values.
+__host__ __device__ constexpr uint32_t slot_value_offset(int kw) { return (uint32_t)((8 * kw + 15) / 16 * 16); }
+__host__ __device__ constexpr uint32_t slot_bytes(int kw, int vp)
+{
+    return slot_value_offset(kw) + 4u * vp <= 32u    ? 32u
+           : slot_value_offset(kw) + 4u * vp <= 64u  ? 64u
+           : slot_value_offset(kw) + 4u * vp <= 128u ? 128u
+                                                     : 256u;
+}
+constexpr int kBucketSlots = 2;
+template <int KW, int V> struct SlotGeom {
+    static constexpr uint32_t bytes = slot_bytes(KW, ValPad<V>::value);
+    static constexpr uint32_t val_off = slot_value_offset(KW);
+    static constexpr uint32_t bucket = kBucketSlots * bytes;
+};
 
 // Value channels splatted per observation point: [1, y] (V = 4), [1, y, |y|^2]
 // (V = 5), [1, y, n_y] (V = 7), [1, y, n_y, |y|^2] (V = 8).  |y|^2 feeds the
@@ -41,13 +59,15 @@ template <int V> struct ValLayout {
     static constexpr bool m2 = V == 5 || V == 8;
 };
 
-// Per-set view of the lattice table.  keys/vals point at the set's first
-// slot, so one launch can slice sets of lattices that were built separately.
+// Per-set view of the lattice table.  keys points at the set's first slot and
+// vals at the values of that slot (keys + slot_value_offset bytes); slot i of
+// the set starts slot_bytes * i bytes further.  Absolute pointers, so one
+// launch can slice sets of lattices that were built separately.
 struct SetTable {
-    const uint64_t *keys; // KW words per slot
-    const float *vals;    // VP binary32 per slot
+    const uint64_t *keys; // first slot of the set
+    const float *vals;    // values of the first slot
     uint64_t slot_base;   // first slot of the set in its lattice's table
-    uint32_t cap;         // slots of the set (>= 16)
+    uint32_t cap;         // slots of the set (even, >= 16; cap / 2 buckets)
     uint32_t n_vertices;
     uint32_t seed;        // hash seed (changed when a cuckoo insertion has to be redone)
     uint32_t mask;        // cap - 1 for the power-of-two tables of the build
@@ -129,37 +149,38 @@ __device__ __forceinline__ uint32_t hash_key(const uint64_t (&w)[KW], uint32_t s
     return h;
 }
 
-// The two candidate slots of a key in a table of `cap` slots: two hashes
-// mapped to [0, cap) by a multiply-high range reduction (no power-of-two
-// capacity needed); the second moves on by one if it coincides with the first.
-__device__ __forceinline__ void cuckoo_slots(uint32_t h, uint32_t cap, uint32_t &p1, uint32_t &p2)
+// The two candidate buckets of a key in a table of `nb` buckets: two hashes
+// mapped to [0, nb) by a multiply-high range reduction (no power-of-two size
+// needed); the second moves on by one if it coincides with the first.
+__device__ __forceinline__ void cuckoo_buckets(uint32_t h, uint32_t nb, uint32_t &b1, uint32_t &b2)
 {
-    p1 = __umulhi(h, cap);
+    b1 = __umulhi(h, nb);
     const uint32_t h2 = (h ^ (h >> 16)) * 0x7FEB352Du;
-    p2 = __umulhi(h2, cap);
-    p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
+    b2 = __umulhi(h2, nb);
+    b2 = (b2 == b1) ? ((b1 + 1u == nb) ? 0u : b1 + 1u) : b2;
 }
 
-// Both candidate slots of a key.  Positions (KW <= 2) take them from one
+// Both candidate buckets of a key.  Positions (KW <= 2) take them from one
 // 32-bit hash.  Descriptor lattices hold millions of vertices per set, where
-// several keys share a 32-bit hash and, with it, both slots (three such keys
-// cannot be placed); their second slot comes from a second hash with another
-// seed, so a shared first hash no longer implies a shared pair.
+// several keys share a 32-bit hash and, with it, both buckets (five such keys
+// cannot be placed); their second bucket comes from a second hash with
+// another seed, so a shared first hash no longer implies a shared pair.
 template <int KW>
-__device__ __forceinline__ void key_slots(const uint64_t (&key)[KW], uint32_t seed, uint32_t cap, uint32_t &p1,
-                                          uint32_t &p2)
+__device__ __forceinline__ void key_buckets(const uint64_t (&key)[KW], uint32_t seed, uint32_t nb, uint32_t &b1,
+                                            uint32_t &b2)
 {
     const uint32_t h = hash_key<KW>(key, seed);
     if constexpr (KW <= 2) {
-        cuckoo_slots(h, cap, p1, p2);
+        cuckoo_buckets(h, nb, b1, b2);
     } else {
-        p1 = __umulhi(h, cap);
-        p2 = __umulhi(hash_key<KW>(key, seed * 0x2545F491u + 0x9E3779B9u), cap);
-        p2 = (p2 == p1) ? ((p1 + 1u == cap) ? 0u : p1 + 1u) : p2;
+        b1 = __umulhi(h, nb);
+        b2 = __umulhi(hash_key<KW>(key, seed * 0x2545F491u + 0x9E3779B9u), nb);
+        b2 = (b2 == b1) ? ((b1 + 1u == nb) ? 0u : b1 + 1u) : b2;
     }
 }
 
-// Loads from a uniform table base with a 32-bit byte offset (slot < 2^27).
+// Loads from a uniform table base with a 32-bit byte offset (a set's table
+// is below 4 GiB; the build checks).
 // The base is cast to the global address space: table pointers arrive through
 // memory (the per-set table), where the compiler cannot infer it, and a
 // generic pointer would turn every lookup into a flat load with 64-bit address
@@ -175,19 +196,19 @@ __device__ __forceinline__ T load_at(const void *__restrict__ base, uint32_t byt
     return *(global_T *)((global_cchar *)base + byte_off);
 }
 
+// The key words of the slot that starts `base` bytes into the table.
 template <int KW>
-__device__ __forceinline__ void load_key(const uint64_t *__restrict__ keys, uint32_t slot, uint64_t (&k)[KW])
+__device__ __forceinline__ void load_key(const uint64_t *__restrict__ keys, uint32_t base, uint64_t (&k)[KW])
 {
     if constexpr (KW == 2) {
-        const u32x4 q = load_at<u32x4>(keys, slot << 4);
+        const u32x4 q = load_at<u32x4>(keys, base);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
         k[1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
     } else if constexpr (KW == 1) {
-        const u32x2 q = load_at<u32x2>(keys, slot << 3);
+        const u32x2 q = load_at<u32x2>(keys, base);
         k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
     } else {
-        // descriptor lattices: KW words of 8 bytes per slot
-        const uint32_t base = slot * (uint32_t)(8 * KW);
+        // descriptor lattices: KW words of 8 bytes
 #pragma unroll
         for (int w = 0; w < KW; ++w) {
             const u32x2 q = load_at<u32x2>(keys, base + 8u * w);
@@ -461,54 +482,87 @@ __device__ __forceinline__ void xform_normal(const float *m, float x, float y, f
     oz = (m[8] * x + m[9] * y) + m[10] * z;
 }
 
-// Slice one point: read the two candidate key slots of all D vertices at
-// once, then the value slot of each vertex found, and accumulate b * value.
-// A vertex absent from the lattice contributes nothing; its lane skips the
-// value load (a predicated load, the only divergence).  kb/vb are the set's
-// table bases (uniform per block), slots are 32-bit offsets.  For the |y|^2
-// layouts the last channel comes out as the second moment about the target,
-// sum_k K |y_k - t|^2 with t = M1 / M0 (0 without support).
-template <int KW, int V, int D>
-__device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, const float *__restrict__ vb,
-                                              const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
-                                              float (&acc)[V])
+// The values of the slot whose values start `off` bytes after vb.
+template <int V>
+__device__ __forceinline__ void load_vals(const float *__restrict__ vb, uint32_t off, float (&val)[8])
 {
     constexpr int VP = ValPad<V>::value;
-    uint32_t p1[D], p2[D];
-    uint64_t ka[D][KW], kc[D][KW];
-    float vw[D], vW[D], vm[D][3];   // |y|^2 layouts: weights, masses and first moments per vertex
+    const u32x4 q0 = load_at<u32x4>(vb, off);
+    u32x4 q1 = {0u, 0u, 0u, 0u};
+    if constexpr (VP == 8) q1 = load_at<u32x4>(vb, off + 16u);
+    val[0] = __uint_as_float(q0.x);
+    val[1] = __uint_as_float(q0.y);
+    val[2] = __uint_as_float(q0.z);
+    val[3] = __uint_as_float(q0.w);
+    val[4] = __uint_as_float(q1.x);
+    val[5] = __uint_as_float(q1.y);
+    val[6] = __uint_as_float(q1.z);
+    val[7] = __uint_as_float(q1.w);
+}
+
+// Slice one point.  Level 1 reads both key slots of every vertex's first
+// bucket (one line each); level 2, where a first bucket is full without the
+// key, both key slots of the second bucket; level 3 the values of every
+// vertex found, from a line the lookup has just fetched.  A vertex absent from
+// the lattice contributes nothing; vertices accumulate in order, each as
+// w * value with w = b or 0.  For the |y|^2 layouts the last channel comes out
+// as the second moment about the target, sum_k K |y_k - t|^2 with t = M1 / M0
+// (0 without support).
+template <int KW, int V, int D>
+__device__ __forceinline__ void slice_simplex(const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
+                                              float (&acc)[V])
+{
+    using G = SlotGeom<KW, V>;
+    const uint64_t *__restrict__ kb = st.keys;
+    const float *__restrict__ vb = st.vals;
+    const uint32_t nb = st.cap >> 1;
+    uint32_t off[D], alt[D];
+    uint64_t k0[D][KW], k1[D][KW];
+    bool found[D], second[D];
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        key_slots<KW>(keys[v], st.seed, st.cap, p1[v], p2[v]);
-        load_key<KW>(kb, p1[v], ka[v]);
-        load_key<KW>(kb, p2[v], kc[v]);
+        uint32_t b1, b2;
+        key_buckets<KW>(keys[v], st.seed, nb, b1, b2);
+        off[v] = b1 * G::bucket;
+        alt[v] = b2 * G::bucket;
+        load_key<KW>(kb, off[v], k0[v]);
+        load_key<KW>(kb, off[v] + G::bytes, k1[v]);
     }
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-        const bool in1 = key_equal<KW>(ka[v], keys[v]);
-        const bool in2 = key_equal<KW>(kc[v], keys[v]);
-        const uint32_t slot = in1 ? p1[v] : p2[v];
-        const float w = (in1 || in2) ? b[v] : 0.0f;
-        const uint32_t off = slot * (uint32_t)(VP * sizeof(float));
-        // only lanes whose vertex exists fetch its values: an absent vertex
-        // would otherwise pull a random table line through the caches
-        u32x4 q0 = {0u, 0u, 0u, 0u}, q1 = q0;
-        if (in1 || in2) {
-            q0 = load_at<u32x4>(vb, off);
-            if constexpr (VP == 8) q1 = load_at<u32x4>(vb, off + 16u);
+        const bool e0 = key_equal<KW>(k0[v], keys[v]);
+        const bool e1 = key_equal<KW>(k1[v], keys[v]);
+        found[v] = e0 || e1;
+        second[v] = !found[v] && k0[v][0] != kKeyEmpty && k1[v][0] != kKeyEmpty;
+        off[v] += e1 ? G::bytes : 0u;
+        if (second[v]) {
+            load_key<KW>(kb, alt[v], k0[v]);
+            load_key<KW>(kb, alt[v] + G::bytes, k1[v]);
         }
-        const float val[8] = {__uint_as_float(q0.x), __uint_as_float(q0.y), __uint_as_float(q0.z),
-                              __uint_as_float(q0.w), __uint_as_float(q1.x), __uint_as_float(q1.y),
-                              __uint_as_float(q1.z), __uint_as_float(q1.w)};
+    }
 #pragma unroll
-        for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
-        if constexpr (ValLayout<V>::m2) {
-            vw[v] = w;
-            vW[v] = val[0];
-            vm[v][0] = val[1];
-            vm[v][1] = val[2];
-            vm[v][2] = val[3];
+    for (int v = 0; v < D; ++v) {
+        if (second[v]) {
+            const bool e0 = key_equal<KW>(k0[v], keys[v]);
+            const bool e1 = key_equal<KW>(k1[v], keys[v]);
+            found[v] = e0 || e1;
+            off[v] = alt[v] + (e1 ? G::bytes : 0u);
         }
+    }
+    float val[D][8];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) val[v][c] = 0.0f;
+        if (found[v]) load_vals<V>(vb, off[v], val[v]);
+    }
+    float vw[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        const float w = found[v] ? b[v] : 0.0f;
+        vw[v] = w;
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[v][c], acc[c]);
     }
     if constexpr (ValLayout<V>::m2) {
         // second moment about the target t = M1 / M0:
@@ -518,26 +572,31 @@ __device__ __forceinline__ void slice_simplex(const uint64_t *__restrict__ kb, c
             const float tx = acc[1] * inv, ty = acc[2] * inv, tz = acc[3] * inv;
 #pragma unroll
             for (int v = 0; v < D; ++v) {
-                const float iw = vW[v] > 0.0f ? 1.0f / vW[v] : 0.0f;
-                const float dx = vm[v][0] * iw - tx, dy = vm[v][1] * iw - ty, dz = vm[v][2] * iw - tz;
-                acc[V - 1] = fmaf(vw[v] * vW[v], fmaf(dx, dx, fmaf(dy, dy, dz * dz)), acc[V - 1]);
+                const float W = val[v][0];
+                const float iw = W > 0.0f ? 1.0f / W : 0.0f;
+                const float dx = val[v][1] * iw - tx, dy = val[v][2] * iw - ty, dz = val[v][3] * iw - tz;
+                acc[V - 1] = fmaf(vw[v] * W, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), acc[V - 1]);
             }
         }
     }
 }
 
-// Slot of a key in a set's table (relative to the set's base), or -1.
-template <int KW>
-__device__ __forceinline__ int64_t find_slot(const uint64_t *__restrict__ kb, const SetTable &st,
-                                             const uint64_t (&key)[KW])
+// Slot of a key in a set's table (relative to the set's first slot), or -1.
+template <int KW, int V>
+__device__ __forceinline__ int64_t find_slot(const SetTable &st, const uint64_t (&key)[KW])
 {
-    uint32_t p1, p2;
-    key_slots<KW>(key, st.seed, st.cap, p1, p2);
-    uint64_t k1[KW], k2[KW];
-    load_key<KW>(kb, p1, k1);
-    load_key<KW>(kb, p2, k2);
-    if (key_equal<KW>(k1, key)) return (int64_t)p1;
-    if (key_equal<KW>(k2, key)) return (int64_t)p2;
+    using G = SlotGeom<KW, V>;
+    uint32_t bk[2];
+    key_buckets<KW>(key, st.seed, st.cap >> 1, bk[0], bk[1]);
+#pragma unroll 1
+    for (int i = 0; i < 2; ++i) {
+        uint64_t k0[KW], k1[KW];
+        load_key<KW>(st.keys, bk[i] * G::bucket, k0);
+        load_key<KW>(st.keys, bk[i] * G::bucket + G::bytes, k1);
+        if (key_equal<KW>(k0, key)) return (int64_t)kBucketSlots * bk[i];
+        if (key_equal<KW>(k1, key)) return (int64_t)kBucketSlots * bk[i] + 1;
+        if (k0[0] == kKeyEmpty || k1[0] == kKeyEmpty) return -1;   // the key never moved past a free slot
+    }
     return -1;
 }
 

@@ -78,10 +78,10 @@ struct fr_lattice {
     float k[8] = {0};               // scale factors of the lattice parameters
     std::vector<float> kset;        // n_sets x 8: scale factors of each set (per-set sigma)
     int64_t n_points_total = 0;
-    // cuckoo tables of all sets: keys (KW words per slot) and padded values
-    uint64_t *tkey = nullptr;
-    float *tval = nullptr;
-    size_t tkey_bytes = 0, tval_bytes = 0;
+    // bucketed cuckoo tables of all sets, back to back: slot_bytes(KW, VP) per
+    // slot, the key words then the padded values
+    uint64_t *tab = nullptr;
+    size_t tab_bytes = 0;
     uint64_t n_slots = 0;
     fr::SetTable *sets_d = nullptr;   // device copy of sets_h
     std::vector<fr::SetTable> sets_h;

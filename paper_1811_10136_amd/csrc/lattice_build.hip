@@ -527,13 +527,32 @@ __global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t R, const u
     unsafeAtomicAdd(&vval[(size_t)(V - 1) * NV + v], rec_b[r] * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
-// Two-choice cuckoo insertion of the vertices of each set (one thread per
-// vertex).  A thread always holds exactly one vertex: it swaps it into one of
-// the vertex's two slots and carries on with whatever it evicted, toward that
-// vertex's other slot, until it lands in a free slot.  Every vertex therefore
-// ends in exactly one slot; a thread that gives up after kMaxKicks raises
-// `fail` and the host rebuilds the table with another seed.
+// Bucketed two-choice cuckoo insertion of the vertices of each set (one
+// thread per vertex).  A thread holds exactly one vertex at a time.  A new
+// vertex takes a free slot of its first bucket, else of its second; with both
+// full it swaps itself into the first and carries the vertex it displaced
+// toward that vertex's other bucket, where the same happens: a free slot ends
+// the walk, a full bucket gives up one of its slots in turn.  A slot, once
+// filled, is never empty again, and a vertex reaches its second bucket only
+// when its first is full -- the property a lookup relies on to stop at a
+// first bucket with a free slot.  A thread that gives up after kMaxKicks
+// raises `fail` and the host rebuilds the table with another seed.
 constexpr int kMaxKicks = 512;
+
+template <int KW>
+__device__ __forceinline__ void vertex_key(const uint64_t *vkey, size_t NV, uint32_t v, uint64_t (&key)[KW])
+{
+#pragma unroll
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
+}
+
+__device__ __forceinline__ bool claim_free(uint32_t *own, uint32_t bucket, uint32_t v)
+{
+#pragma unroll
+    for (int j = 0; j < kBucketSlots; ++j)
+        if (atomicCAS(&own[kBucketSlots * bucket + j], kOwnerEmpty, v) == kOwnerEmpty) return true;
+    return false;
+}
 
 template <int KW>
 __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTable *tables, const uint64_t *vkey,
@@ -545,50 +564,54 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
     const int64_t v = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
     if (v >= tm.seg_end[s]) return;
     const SetTable st = tables[s];
+    const uint32_t nb = st.cap >> 1;
+    uint32_t *o = own + st.slot_base;
     uint32_t cur = (uint32_t)v;
     uint64_t key[KW];
-#pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
-    uint32_t p1, p2;
-    key_slots<KW>(key, st.seed, st.cap, p1, p2);
-    uint32_t pos = p1;
+    vertex_key<KW>(vkey, NV, cur, key);
+    uint32_t b1, b2;
+    key_buckets<KW>(key, st.seed, nb, b1, b2);
+    if (claim_free(o, b1, cur) || claim_free(o, b2, cur)) return;
+    uint32_t bk = b1;   // full: displace a vertex of the first bucket
     for (int it = 0; it < kMaxKicks; ++it) {
-        const uint32_t old = atomicExch(&own[st.slot_base + pos], cur);
+        const uint32_t old = atomicExch(&o[kBucketSlots * bk + (uint32_t)(it % kBucketSlots)], cur);
         if (old == kOwnerEmpty) return;
         cur = old;
-#pragma unroll
-        for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + cur];
-        key_slots<KW>(key, st.seed, st.cap, p1, p2);
-        pos = (pos == p1) ? p2 : p1;
+        vertex_key<KW>(vkey, NV, cur, key);
+        key_buckets<KW>(key, st.seed, nb, b1, b2);
+        bk = (bk == b1) ? b2 : b1;
+        if (claim_free(o, bk, cur)) return;
     }
     atomicOr(fail, 1);
 }
 
-// One thread per slot: write the key words and padded values of its vertex,
-// or the empty marker.
+// One thread per slot: write the key words of its vertex (or the empty
+// marker) and the padded values, at the slot's place in the table.
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_cuckoo_fill(size_t n_slots, const uint32_t *own, const uint64_t *vkey,
-                                                    const float *vval, size_t NV, uint64_t *tkey, float *tval)
+                                                    const float *vval, size_t NV, char *table)
 {
+    using G = SlotGeom<KW, V>;
     constexpr int VP = ValPad<V>::value;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_slots) return;
     const uint32_t o = own[j];
+    uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
     float val[VP];
 #pragma unroll
     for (int c = 0; c < VP; ++c) val[c] = 0.0f;
     if (o == kOwnerEmpty) {
 #pragma unroll
-        for (int w = 0; w < KW; ++w) tkey[KW * j + w] = kKeyEmpty;
+        for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
     } else {
 #pragma unroll
-        for (int w = 0; w < KW; ++w) tkey[KW * j + w] = vkey[(size_t)w * NV + o];
+        for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + o];
 #pragma unroll
         for (int c = 0; c < V; ++c) val[c] = vval[(size_t)c * NV + o];
     }
-    float4 *dst = reinterpret_cast<float4 *>(tval + VP * j);
-    dst[0] = make_float4(val[0], val[1], val[2], val[3]);
-    if constexpr (VP == 8) dst[1] = make_float4(val[4], val[5], val[6], val[7]);
+    float4 *dst = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
+#pragma unroll
+    for (int q = 0; q < VP / 4; ++q) dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -816,24 +839,29 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     ovid.reset();
     slot_vid.reset();
 
-    // 5. final two-choice cuckoo tables, load factor 0.4
+    // 5. final bucketed two-choice cuckoo tables, load factor 0.4
+    constexpr uint32_t SB = SlotGeom<KW, V>::bytes;
     lat->sets_h.resize(S);
     uint64_t n2 = 0;
     for (int32_t s = 0; s < S; ++s) {
-        const uint32_t cap = (uint32_t)std::max<uint64_t>(16, (5 * (uint64_t)counts[s] + 1) / 2);
+        const uint64_t nb = std::max<uint64_t>(8, (5 * (uint64_t)counts[s] + 3) / 4);
+        if (nb * kBucketSlots * SB > 0xFFFFFFFFull) {
+            set_error("fr_lattice_build: set %d has %u vertices, more than one table of 4 GiB holds", s, counts[s]);
+            return FR_ENOMEM;
+        }
+        const uint32_t cap = (uint32_t)(kBucketSlots * nb);
         lat->sets_h[s] = SetTable{nullptr, nullptr, n2, cap, counts[s], 0x2545F491u * (uint32_t)(s + 1), 0, {}};
         std::memcpy(lat->sets_h[s].k, lat->kset.data() + 8 * (size_t)s, sizeof(lat->sets_h[s].k));
         n2 += cap;
     }
     lat->n_slots = n2;
-    lat->tkey_bytes = n2 * KW * sizeof(uint64_t);
-    lat->tval_bytes = n2 * VP * sizeof(float);
-    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tkey), lat->tkey_bytes));
-    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tval), lat->tval_bytes));
+    lat->tab_bytes = n2 * SB;
+    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tab), lat->tab_bytes));
     FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->sets_d), S * sizeof(SetTable)));
     for (int32_t s = 0; s < S; ++s) {
-        lat->sets_h[s].keys = lat->tkey + lat->sets_h[s].slot_base * KW;
-        lat->sets_h[s].vals = lat->tval + lat->sets_h[s].slot_base * VP;
+        char *first = reinterpret_cast<char *>(lat->tab) + lat->sets_h[s].slot_base * SB;
+        lat->sets_h[s].keys = reinterpret_cast<const uint64_t *>(first);
+        lat->sets_h[s].vals = reinterpret_cast<const float *>(first + SlotGeom<KW, V>::val_off);
     }
     DevBuf own2, vtmap;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
@@ -860,7 +888,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     }
     if (n2 > 0) {
         k_cuckoo_fill<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, own2.as<uint32_t>(), lat->vkey, lat->vval, NV,
-                                                                 lat->tkey, lat->tval);
+                                                                 reinterpret_cast<char *>(lat->tab));
         FR_HIP(hipGetLastError());
     }
     FR_HIP(hipStreamSynchronize(st));
@@ -1013,15 +1041,17 @@ __device__ __forceinline__ bool neighbour_key(const uint64_t (&key)[KeyWords<d>:
 }
 
 // One blur pass along direction `dir`: every slot of every set (one thread per
-// slot) takes 1/2 its own values plus 1/4 of each neighbour's, read from `tin`;
-// absent neighbours read as zero; empty slots stay zero.  `scale` multiplies
-// the result (the filter's output scale on the last pass, 1 before).
+// slot) takes 1/2 its own values plus 1/4 of each neighbour's, read from `tin`
+// (VP binary32 per slot, slots in table order); absent neighbours read as
+// zero; empty slots stay zero.  `scale` multiplies the result (the filter's
+// output scale on the last pass, 1 before).  Keys come from the table.
 template <int d, int V>
 __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *sets, int dir, const float *tin,
                                                   float *tout, float scale)
 {
     constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
+    using G = SlotGeom<KW, V>;
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
@@ -1029,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *s
     if (q >= tm.seg_end[s]) return;
     const SetTable st = sets[tm.seg_set[s]];
     uint64_t key[KW];
-    load_key<KW>(st.keys, (uint32_t)(q - (int64_t)st.slot_base), key);
+    load_key<KW>(st.keys, (uint32_t)(q - (int64_t)st.slot_base) * G::bytes, key);
     float acc[VP];
 #pragma unroll
     for (int c = 0; c < VP; ++c) acc[c] = 0.0f;
@@ -1040,7 +1070,7 @@ __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *s
         for (int sgn = -1; sgn <= 1; sgn += 2) {
             uint64_t nk[KW];
             if (!neighbour_key<d>(key, dir, sgn, nk)) continue;
-            const int64_t r = find_slot<KW>(st.keys, st, nk);
+            const int64_t r = find_slot<KW, V>(st, nk);
             if (r < 0) continue;
             const float *src = tin + (size_t)VP * (st.slot_base + (uint64_t)r);
 #pragma unroll
@@ -1054,13 +1084,33 @@ __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *s
     if constexpr (VP == 8) dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
+// Copy the values of every slot between the table and a plain array of VP
+// binary32 per slot (to_table false: out of the table; true: back in).
+template <int KW, int V>
+__global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, char *table, float *plain, bool to_table)
+{
+    using G = SlotGeom<KW, V>;
+    constexpr int VP = ValPad<V>::value;
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_slots) return;
+    float4 *tv = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
+    float4 *pv = reinterpret_cast<float4 *>(plain + (size_t)VP * j);
+#pragma unroll
+    for (int c = 0; c < VP / 4; ++c) {
+        if (to_table)
+            tv[c] = pv[c];
+        else
+            pv[c] = tv[c];
+    }
+}
+
 // Copy the table values back to the vertex arrays (export reads those).
 template <int d, int V>
 __global__ void __launch_bounds__(256) k_table_to_vertices(TileMap tm, const SetTable *sets, const uint64_t *vkey,
-                                                          size_t NV, const float *tval, float *vval)
+                                                          size_t NV, float *vval)
 {
     constexpr int KW = KeyWords<d>::value;
-    constexpr int VP = ValPad<V>::value;
+    using G = SlotGeom<KW, V>;
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
@@ -1070,40 +1120,46 @@ __global__ void __launch_bounds__(256) k_table_to_vertices(TileMap tm, const Set
     uint64_t key[KW];
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
-    const int64_t r = find_slot<KW>(st.keys, st, key);
+    const int64_t r = find_slot<KW, V>(st, key);
     if (r < 0) return;   // cannot happen: every vertex sits in its set's table
-    const float *src = tval + (size_t)VP * (st.slot_base + (uint64_t)r);
+    float val[8];
+    load_vals<V>(st.vals, (uint32_t)r * G::bytes, val);
 #pragma unroll
-    for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = src[c];
+    for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = val[c];
 }
 
 template <int d, int V>
 static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
 {
+    constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
     fr_ctx *ctx = lat->ctx;
     const int32_t S = lat->n_sets;
     std::vector<int64_t> soff(S + 1, 0);
     for (int32_t s = 0; s < S; ++s) soff[s + 1] = soff[s] + lat->sets_h[s].cap;
-    DevBuf tmp, smap, vmap;
+    DevBuf bufa, bufb, smap, vmap;
     TileMap stm{}, vtm{};
     FR_TRY(make_offset_map(ctx, soff, 256, st, smap, stm));
     FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vmap, vtm));
     const size_t n = (size_t)lat->n_slots;
     if (n == 0) return FR_OK;
-    FR_TRY(tmp.alloc(ctx, n * VP * sizeof(float)));
-    float *bufs[2] = {lat->tval, tmp.as<float>()};
+    FR_TRY(bufa.alloc(ctx, n * VP * sizeof(float)));
+    FR_TRY(bufb.alloc(ctx, n * VP * sizeof(float)));
+    char *table = reinterpret_cast<char *>(lat->tab);
+    float *bufs[2] = {bufa.as<float>(), bufb.as<float>()};
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, table, bufs[0], false);
+    FR_HIP(hipGetLastError());
     const float scale = (float)(1.0 / (1.0 + std::ldexp(1.0, -d)));
     for (int j = 0; j <= d; ++j) {
         k_blur_pass<d, V><<<stm.n_tiles, 256, 0, st>>>(stm, lat->sets_d, j, bufs[j & 1], bufs[(j + 1) & 1],
                                                        j == d ? scale : 1.0f);
         FR_HIP(hipGetLastError());
     }
-    if (((d + 1) & 1) != 0)   // an odd number of passes ends in the scratch table
-        FR_HIP(hipMemcpyAsync(lat->tval, tmp.p, n * VP * sizeof(float), hipMemcpyDeviceToDevice, st));
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, table, bufs[(d + 1) & 1], true);
+    FR_HIP(hipGetLastError());
     if (vtm.n_tiles > 0) {
         k_table_to_vertices<d, V><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey,
-                                                               (size_t)lat->n_vertices_total, lat->tval, lat->vval);
+                                                               (size_t)lat->n_vertices_total, lat->vval);
         FR_HIP(hipGetLastError());
     }
     return FR_OK;
