@@ -325,67 +325,107 @@ __global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const flo
 }
 
 // One thread per record: find or claim the record's key in the provisional
-// linear-probing table of its set.  A slot that already has an owner is
-// compared with a plain read first; only free slots are claimed with a CAS.
-// Probing stops after kMaxProbe slots and raises `fail` (the host then
-// retries with a larger table).
+// linear-probing table of its set.  Neighbouring observation points share most
+// of their vertices, so the records of a tile (256 records of one set) are
+// first merged in LDS: each record finds or claims its key in a small
+// open-addressing table of the workgroup, and only the record that claimed a
+// key (its representative) probes the global table; the others take the
+// representative's slot.  In the global table a slot that already has an
+// owner is compared with a plain read first; only free slots are claimed with
+// a CAS; owner_flag[r] = 1 marks the record whose CAS claimed the slot (the
+// owner of its vertex).  Probing stops after kMaxProbe slots and raises
+// `fail` (the host then retries with a larger table).
 constexpr uint32_t kMaxProbe = 128;
+constexpr uint32_t kTileKeySlots = 512;   // LDS table of a tile: at most 256 keys, load <= 1/2
 
 template <int KW>
 __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTable *tables, const uint64_t *rec_key,
-                                                       size_t R, uint32_t *own, uint32_t *rec_slot, int32_t *fail)
+                                                       size_t R, uint32_t *own, uint32_t *rec_slot,
+                                                       uint32_t *owner_flag, int32_t *fail)
 {
+    __shared__ uint64_t lkey[KW][256];
+    __shared__ uint32_t lown[kTileKeySlots];
+    __shared__ uint32_t lslot[256];
     const int32_t t = logical_tile(tm);
-    if (t >= tm.n_tiles) return;
+    if (t >= tm.n_tiles) return;   // uniform over the workgroup
     const int32_t s = tile_segment(tm, t);
-    const int64_t r = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
-    if (r >= tm.seg_end[s]) return;
+    const uint32_t tid = threadIdx.x;
+    const int64_t r = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + tid;
+    const bool active = r < tm.seg_end[s];
+    for (uint32_t j = tid; j < kTileKeySlots; j += blockDim.x) lown[j] = kOwnerEmpty;
     uint64_t key[KW];
+    if (active) {
 #pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = rec_key[(size_t)w * R + r];
-    const SetTable st = tables[s];
-    uint32_t h = hash_key<KW>(key, 0u) & st.mask;
-    const uint32_t limit = min(st.mask + 1u, kMaxProbe);
-    for (uint32_t n = 0; n < limit; ++n) {
-        const size_t slot = st.slot_base + h;
-        uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
-        bool mine = (o == kOwnerEmpty);
-        if (!mine) {
-            mine = true;
-#pragma unroll
-            for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
+        for (int w = 0; w < KW; ++w) {
+            key[w] = rec_key[(size_t)w * R + r];
+            lkey[w][tid] = key[w];
         }
-        if (mine) {
-            rec_slot[r] = (uint32_t)slot;
-            return;
-        }
-        h = (h + 1) & st.mask;
     }
-    atomicOr(fail, 1);
+    __syncthreads();
+    uint32_t rep = tid;
+    if (active) {
+        uint32_t h = hash_key<KW>(key, 0x9E3779B9u) & (kTileKeySlots - 1);
+        for (uint32_t n = 0; n < kTileKeySlots; ++n) {   // ends: fewer keys than slots
+            const uint32_t o = atomicCAS(&lown[h], kOwnerEmpty, tid);
+            if (o == kOwnerEmpty) break;
+            bool same = true;
+#pragma unroll
+            for (int w = 0; w < KW; ++w) same = same && (lkey[w][o] == key[w]);
+            if (same) {
+                rep = o;
+                break;
+            }
+            h = (h + 1) & (kTileKeySlots - 1);
+        }
+    }
+    bool won = false;
+    if (active && rep == tid) {
+        const SetTable st = tables[s];
+        uint32_t h = hash_key<KW>(key, 0u) & st.mask;
+        const uint32_t limit = min(st.mask + 1u, kMaxProbe);
+        uint32_t found = kOwnerEmpty;
+        for (uint32_t n = 0; n < limit; ++n) {
+            const size_t slot = st.slot_base + h;
+            uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
+            won = (o == kOwnerEmpty);
+            bool mine = won;
+            if (!mine) {
+                mine = true;
+#pragma unroll
+                for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
+            }
+            if (mine) {
+                found = (uint32_t)slot;
+                break;
+            }
+            h = (h + 1) & st.mask;
+        }
+        if (found == kOwnerEmpty) atomicOr(fail, 1);
+        lslot[tid] = found;
+    }
+    __syncthreads();
+    if (active) {
+        const uint32_t slot = lslot[rep];
+        if (slot != kOwnerEmpty) rec_slot[r] = slot;
+        owner_flag[r] = won ? 1u : 0u;
+    }
 }
 
-// flag[r] = 1 if record r owns its slot (the first record of its vertex to claim it).
-__global__ void __launch_bounds__(256) k_owner_flags(size_t R, const uint32_t *rec_slot, const uint32_t *own,
-                                                    uint32_t *flag)
-{
-    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    flag[r] = own[rec_slot[r]] == (uint32_t)r ? 1u : 0u;
-}
-
-// Vertex ids in owner-record order (the exclusive scan of the flags): owners
-// write their vertex's key and the slot -> vertex map.
+// Vertex ids in owner-record order (the exclusive scan of the owner flags,
+// NV in all): owners -- the records whose id the scan steps past -- write
+// their vertex's key and the slot -> vertex map.
 template <int KW>
-__global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *own,
-                                                   const uint32_t *ovid, const uint64_t *rec_key, uint64_t *vkey,
-                                                   size_t NV, uint32_t *slot_vid)
+__global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *ovid,
+                                                   const uint64_t *rec_key, uint64_t *vkey, size_t NV,
+                                                   uint32_t *slot_vid)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    const uint32_t slot = rec_slot[r];
-    if (own[slot] != (uint32_t)r) return;
     const uint32_t v = ovid[r];
+    const uint32_t next = r + 1 < R ? ovid[r + 1] : (uint32_t)NV;
+    if (next == v) return;
+    const uint32_t slot = rec_slot[r];
 #pragma unroll
     for (int w = 0; w < KW; ++w) vkey[(size_t)w * NV + v] = rec_key[(size_t)w * R + r];
     slot_vid[slot] = v;
@@ -585,8 +625,8 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
     atomicOr(fail, 1);
 }
 
-// One thread per slot: write the key words of its vertex (or the empty
-// marker) and the padded values, at the slot's place in the table.
+// One thread per slot: write the key words of its vertex and its padded
+// values, or only the empty marker (a free slot's values are never read).
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_cuckoo_fill(size_t n_slots, const uint32_t *own, const uint64_t *vkey,
                                                     const float *vval, size_t NV, char *table)
@@ -597,18 +637,16 @@ __global__ void __launch_bounds__(256) k_cuckoo_fill(size_t n_slots, const uint3
     if (j >= n_slots) return;
     const uint32_t o = own[j];
     uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
-    float val[VP];
-#pragma unroll
-    for (int c = 0; c < VP; ++c) val[c] = 0.0f;
     if (o == kOwnerEmpty) {
 #pragma unroll
         for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
-    } else {
-#pragma unroll
-        for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + o];
-#pragma unroll
-        for (int c = 0; c < V; ++c) val[c] = vval[(size_t)c * NV + o];
+        return;
     }
+#pragma unroll
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + o];
+    float val[VP];
+#pragma unroll
+    for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * NV + o] : 0.0f;
     float4 *dst = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
 #pragma unroll
     for (int q = 0; q < VP / 4; ++q) dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
@@ -706,6 +744,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
     uint64_t n1 = 0;
+    DevBuf ovid, slot_vid, vb_d;
+    FR_TRY(ovid.alloc(ctx, R * sizeof(uint32_t)));   // owner flags, then their exclusive scan
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<SetTable> t1(S);
         n1 = 0;
@@ -726,7 +766,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         if (rtm.n_tiles > 0) {
             k_insert_records<KW><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
                                                               own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
-                                                              fail.as<int32_t>());
+                                                              ovid.as<uint32_t>(), fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
         int32_t failed = 0;
@@ -740,15 +780,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     }
 
     // 3. vertex ids in owner-record order, per-set ranges, keys
-    DevBuf ovid, slot_vid, vb_d;
-    FR_TRY(ovid.alloc(ctx, R * sizeof(uint32_t)));
     FR_TRY(slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
     FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
-    if (R > 0) {
-        k_owner_flags<<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), own1.as<uint32_t>(),
-                                                           ovid.as<uint32_t>());
-        FR_HIP(hipGetLastError());
-    }
     uint32_t last_flag = 0, last_scan = 0;
     if (R > 0) FR_HIP(hipMemcpyAsync(&last_flag, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToHost, st));
     FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), R, 0, st));
@@ -787,9 +820,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         lat->vocc = reinterpret_cast<uint32_t *>(c + NV * (KW * sizeof(uint64_t) + V * sizeof(float)));
     }
     if (NV > 0) {
-        k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), own1.as<uint32_t>(),
-                                                             ovid.as<uint32_t>(), rec_key.as<uint64_t>(), lat->vkey,
-                                                             NV, slot_vid.as<uint32_t>());
+        k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), ovid.as<uint32_t>(),
+                                                             rec_key.as<uint64_t>(), lat->vkey, NV,
+                                                             slot_vid.as<uint32_t>());
         FR_HIP(hipGetLastError());
     }
 
