@@ -466,13 +466,31 @@ __global__ void __launch_bounds__(256) k_segment_lengths(size_t NV, size_t R, co
     vocc[v] = (uint32_t)((v + 1 < NV ? voff[v + 1] : (uint32_t)R) - voff[v]);
 }
 
+// Sorted mode: the splatted point values, one or two float4 per point
+// ([y, n_x], [n_y, n_z, 0, 0] with normals, else [y, 0]), so the per-vertex
+// sums gather a point with one or two loads instead of six.
+template <int V> struct PointRow { static constexpr int words = ValLayout<V>::normals ? 2 : 1; };
+
+template <int V>
+__global__ void __launch_bounds__(256) k_point_rows(size_t N, Pts pts, float4 *rows)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if constexpr (ValLayout<V>::normals) {
+        rows[2 * i] = make_float4(pts.x[i], pts.y[i], pts.z[i], pts.nx[i]);
+        rows[2 * i + 1] = make_float4(pts.ny[i], pts.nz[i], 0.0f, 0.0f);
+    } else {
+        rows[i] = make_float4(pts.x[i], pts.y[i], pts.z[i], 0.0f);
+    }
+}
+
 // Sorted mode: ordered binary64 sums per vertex.  Vertex ids follow the
 // owner records, so neighbouring threads gather from neighbouring points;
 // record ids are fetched four at a time so the dependent gathers overlap.
 template <int D, int V>
 __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint32_t *voff, const uint32_t *vocc,
-                                                          const uint32_t *rid_sorted, const float *rec_b, Pts pts,
-                                                          float *vval)
+                                                          const uint32_t *rid_sorted, const float *rec_b,
+                                                          const float4 *rows, float *vval)
 {
     const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= NV) return;
@@ -489,13 +507,15 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
         for (int u = 0; u < 4; ++u) {
             const uint32_t i = r[u] / D;
             bw[u] = (q + u < q1) ? rec_b[r[u]] : 0.0f;
-            val[u][0] = pts.x[i];
-            val[u][1] = pts.y[i];
-            val[u][2] = pts.z[i];
+            const float4 a = rows[(size_t)PointRow<V>::words * i];
+            val[u][0] = a.x;
+            val[u][1] = a.y;
+            val[u][2] = a.z;
             if constexpr (ValLayout<V>::normals) {
-                val[u][3] = pts.nx[i];
-                val[u][4] = pts.ny[i];
-                val[u][5] = pts.nz[i];
+                const float4 c = rows[2 * (size_t)i + 1];
+                val[u][3] = a.w;
+                val[u][4] = c.x;
+                val[u][5] = c.y;
             }
         }
 #pragma unroll
@@ -829,7 +849,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // 4. values
     if (NV > 0) {
         if (sorted) {
-            DevBuf rvid, rid, tk, tv, voff;
+            DevBuf rvid, rid, tk, tv, voff, rows;
+            const size_t NP = R / D;
+            FR_TRY(rows.alloc(ctx, NP * PointRow<V>::words * sizeof(float4)));
+            if (NP > 0) {
+                k_point_rows<V><<<blocks_for(NP, 256), 256, 0, st>>>(NP, pts, rows.as<float4>());
+                FR_HIP(hipGetLastError());
+            }
             FR_TRY(rvid.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(rid.alloc(ctx, R * sizeof(uint32_t)));
             FR_TRY(tk.alloc(ctx, R * sizeof(uint32_t)));
@@ -847,7 +873,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             k_segment_lengths<<<blocks_for(NV, 256), 256, 0, st>>>(NV, R, voff.as<uint32_t>(), lat->vocc);
             FR_HIP(hipGetLastError());
             k_vertex_sum_sorted<D, V><<<blocks_for(NV, 256), 256, 0, st>>>(
-                NV, voff.as<uint32_t>(), lat->vocc, rid.as<uint32_t>(), rec_b.as<float>(), pts, lat->vval);
+                NV, voff.as<uint32_t>(), lat->vocc, rid.as<uint32_t>(), rec_b.as<float>(), rows.as<float4>(),
+                lat->vval);
             FR_HIP(hipGetLastError());
             FR_HIP(hipStreamSynchronize(st));
         } else {
