@@ -138,13 +138,18 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t *keys, si
 // item order): lanes with equal digits are found with 8 ballots, and a
 // per-wave LDS counter per digit carries the running count between rounds.
 // Waves are then ordered by a per-digit exclusive prefix, so the rank of an
-// item among equal digits of the block follows item order (stability).
+// item among equal digits of the block follows item order (stability).  The
+// block's items are placed in LDS in digit order and written out from there,
+// so consecutive threads write consecutive places of each digit's run.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                                                            uint32_t *vout, size_t n, int shift,
                                                            const uint32_t *hist_scan, uint32_t nblocks)
 {
     __shared__ uint32_t wcnt[kRsWaves][256];
     __shared__ uint32_t gbase[256];
+    __shared__ uint32_t dstart[256];      // first place of each digit among the block's items
+    __shared__ uint32_t wsum[kRsWaves];
+    __shared__ uint32_t skey[kRsTile], sval[kRsTile];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int w = 0; w < kRsWaves; ++w) wcnt[w][threadIdx.x] = 0;
@@ -175,32 +180,55 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t *kin, 
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        uint32_t run = 0;
+    uint32_t run = 0;   // items of digit threadIdx.x in the block
 #pragma unroll
-        for (int w = 0; w < kRsWaves; ++w) {
-            const uint32_t t = wcnt[w][threadIdx.x];
-            wcnt[w][threadIdx.x] = run;
-            run += t;
-        }
+    for (int w = 0; w < kRsWaves; ++w) {
+        const uint32_t t = wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = run;
+        run += t;
     }
+    // exclusive prefix of the digit counts over the block: per wave, then across waves
+    uint32_t inc = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    dstart[threadIdx.x] = before + inc - run;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
         const size_t idx = base + (size_t)r * 64 + lane;
         if (idx < n) {
             const uint32_t digit = (key[r] >> shift) & 255u;
-            const size_t pos = (size_t)gbase[digit] + wcnt[wave][digit] + lrank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            const uint32_t lpos = dstart[digit] + wcnt[wave][digit] + lrank[r];
+            skey[lpos] = key[r];
+            sval[lpos] = val[r];
         }
+    }
+    __syncthreads();
+    const size_t first = (size_t)blockIdx.x * kRsTile;
+    const uint32_t count = (uint32_t)min((size_t)kRsTile, n - first);
+    for (uint32_t i = threadIdx.x; i < count; i += kRsThreads) {
+        const uint32_t k = skey[i];
+        const uint32_t digit = (k >> shift) & 255u;
+        const size_t pos = (size_t)gbase[digit] + (i - dstart[digit]);
+        kout[pos] = k;
+        vout[pos] = sval[i];
     }
 }
 
-// Sorts keys/vals in place (ping-pong through tk/tv) by the low `bits` bits.
+// Sorts keys/vals by the low `bits` bits, ping-ponging through tk/tv; on
+// return *keys_out / *vals_out name the pair of arrays that holds the result.
 static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, size_t n,
-                                  int bits, hipStream_t st)
+                                  int bits, hipStream_t st, uint32_t **keys_out, uint32_t **vals_out)
 {
+    *keys_out = keys;
+    *vals_out = vals;
     if (n <= 1 || bits <= 0) return FR_OK;
     const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
     DevBuf hist;
@@ -216,10 +244,8 @@ static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, u
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    if (ka != keys) {
-        FR_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-        FR_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-    }
+    *keys_out = ka;
+    *vals_out = va;
     FR_HIP(hipStreamSynchronize(st));
     return FR_OK;
 }
@@ -866,15 +892,15 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             FR_HIP(hipGetLastError());
             int bits = 0;
             while (bits < 32 && (NV - 1) >> bits) ++bits;
+            uint32_t *svid = nullptr, *srid = nullptr;   // the sorted pairs
             FR_TRY(radix_sort_pairs(ctx, rvid.as<uint32_t>(), rid.as<uint32_t>(), tk.as<uint32_t>(),
-                                    tv.as<uint32_t>(), R, bits, st));
-            k_segment_heads<<<blocks_for(R, 256), 256, 0, st>>>(R, rvid.as<uint32_t>(), voff.as<uint32_t>());
+                                    tv.as<uint32_t>(), R, bits, st, &svid, &srid));
+            k_segment_heads<<<blocks_for(R, 256), 256, 0, st>>>(R, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
             k_segment_lengths<<<blocks_for(NV, 256), 256, 0, st>>>(NV, R, voff.as<uint32_t>(), lat->vocc);
             FR_HIP(hipGetLastError());
             k_vertex_sum_sorted<D, V><<<blocks_for(NV, 256), 256, 0, st>>>(
-                NV, voff.as<uint32_t>(), lat->vocc, rid.as<uint32_t>(), rec_b.as<float>(), rows.as<float4>(),
-                lat->vval);
+                NV, voff.as<uint32_t>(), lat->vocc, srid, rec_b.as<float>(), rows.as<float4>(), lat->vval);
             FR_HIP(hipGetLastError());
             FR_HIP(hipStreamSynchronize(st));
         } else {
