@@ -43,7 +43,7 @@ enum {
     FR_ENOMEM = 2,       /* device allocation failed */
     FR_EBUDGET = 3,      /* the context's HBM budget would be exceeded */
     FR_ERANGE = 4,       /* a lattice coordinate left the packed key range [-2^20, 2^20) */
-    FR_EDEGENERATE = 5,  /* normal equations not positive definite, or no model point has support */
+    FR_EDEGENERATE = 5,  /* normal equations singular (see fr_solve_rigid), or no model point has support */
     FR_EDEVICE = 6       /* a HIP runtime call failed */
 };
 
@@ -253,8 +253,12 @@ fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const f
  * poses (device, n x 16 row-major float64) are updated in place, mats
  * (device, n x 12) receive the binary32 [R | t], twist_norm (device, n x 2)
  * receives |omega| and |v| of dzeta, status (device, n int32) receives FR_OK
- * or FR_EDEGENERATE (pose left unchanged) per set.  Sets with active[i] == 0
- * are skipped (active may be NULL).
+ * or FR_EDEGENERATE (pose left unchanged) per set.  A is taken as singular
+ * when a Cholesky pivot is at most 1e-4 times its diagonal entry: A is summed
+ * from binary32 tile sums, whose rounding can leave a rank-deficient A (every
+ * supported point on one plane under point-to-plane) with positive pivots of
+ * relative size up to about 6e-5.  Sets with active[i] == 0 are skipped
+ * (active may be NULL).
  */
 fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
                          double *twist_norm, int32_t *status, const int32_t *active, void *stream);

@@ -356,12 +356,25 @@ class Degenerate(RuntimeError):
     """The normal equations are not positive definite (no support or rank-deficient)."""
 
 
-def gn_step(A: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Delta = -A^-1 b (Eq. 17) by Cholesky; raises Degenerate when A is not SPD."""
+# The rigid Gauss-Newton step (Eq. 17) exists only for an invertible A.  The GPU
+# sums A from binary32 tile sums, whose rounding can leave a singular A (all
+# supported points on one plane under point-to-plane: rank 3) with positive
+# pivots up to about 6e-5 of the diagonal; both sides take a Cholesky pivot at
+# or below this fraction of its diagonal entry as singular.
+RIGID_PIVOT_TOL = 1e-4
+
+
+def gn_step(A: np.ndarray, b: np.ndarray, pivot_tol: float = 0.0) -> np.ndarray:
+    """Delta = -A^-1 b (Eq. 17) by Cholesky; raises Degenerate when A is not SPD, or when a pivot
+    L_jj^2 is at most pivot_tol * A_jj."""
     try:
         L = np.linalg.cholesky(A)
     except np.linalg.LinAlgError as e:
         raise Degenerate(str(e)) from e
+    if pivot_tol > 0.0:
+        rel = np.diag(L) ** 2 / np.diag(A)
+        if (rel <= pivot_tol).any():
+            raise Degenerate(f"relative Cholesky pivot {rel.min():.2e} <= {pivot_tol:g}")
     y = np.linalg.solve(L, -b)
     return np.linalg.solve(L.T, y)
 
@@ -396,7 +409,7 @@ def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n
         R32 = mat.reshape(3, 4).astype(np.float64)
         x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
         A, b, stats = normal_equations(x64, m0, m1, ns, c, sig_m, residual, normalize_n)
-        dz = gn_step(A, b)
+        dz = gn_step(A, b, RIGID_PIVOT_TOL)
         T = se3_exp(dz) @ T
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
@@ -454,7 +467,7 @@ def register_rigid_sigma(model, model_n, obs, obs_n, *, feat, residual, sigma0, 
         R32 = mat.reshape(3, 4).astype(np.float64)
         x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
         A, b, stats = normal_equations(x64, m0, m1, ns, c, sig, residual)
-        dz = gn_step(A, b)
+        dz = gn_step(A, b, RIGID_PIVOT_TOL)
         T = se3_exp(dz) @ T
         vs, ws = variance_terms(x64, m0, m1, m2, c)
         if ws > 0:
@@ -483,7 +496,7 @@ def register_rigid_blurred(model, model_n, obs, obs_n, *, feat, residual, sigma,
         R32 = mat.reshape(3, 4).astype(np.float64)
         x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
         A, b, stats = normal_equations(x64, m0, m1, ns, c, sig_m, residual)
-        dz = gn_step(A, b)
+        dz = gn_step(A, b, RIGID_PIVOT_TOL)
         T = se3_exp(dz) @ T
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
@@ -524,7 +537,7 @@ def register_rigid_features(model, model_feat, obs, obs_feat, *, sigma_f, w=0.2,
         R32 = mat.reshape(3, 4).astype(np.float64)
         x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
         A, b, stats = normal_equations(x64, m0, m1, None, c, 1.0, "pt2pt")
-        dz = gn_step(A, b)
+        dz = gn_step(A, b, RIGID_PIVOT_TOL)
         T = se3_exp(dz) @ T
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy(), m0=m0, m1=m1))

@@ -45,6 +45,14 @@ __device__ inline void se3_exp(const double (&z)[6], double (&E)[3][4])
     }
 }
 
+// Relative pivot below which the 6x6 normal equations count as singular.
+// A is summed from binary32 sums over tiles of 1024 points, each rounded to
+// about 1024 * 2^-24 = 6e-5 of its absolute sum at worst, so a rank-deficient
+// A (all supported points on one plane under point-to-plane: rank 3) can come
+// out with positive pivots of that relative size; well-posed systems of the
+// depth workloads keep every pivot above 8e-2 of its diagonal entry.
+constexpr double kRigidPivotTol = 1e-4;
+
 __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses,
                                                     float *mats, double *twist_norm, int32_t *status,
                                                     const int32_t *active)
@@ -66,14 +74,18 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
 #pragma unroll
         for (int i = 0; i < 6; ++i) b[i] = jtr[(size_t)s * 6 + i];
     }
-    // Cholesky A = L L^T (in the lower triangle of A)
+    // Cholesky A = L L^T (in the lower triangle of A); a pivot at most
+    // kRigidPivotTol times its diagonal entry marks A as singular
+    double d0[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) d0[j] = A[j][j];
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double sum = A[j][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) sum -= A[j][k] * A[j][k];
-        ok = ok && (sum > 0.0);
+        ok = ok && (sum > 0.0) && (sum > kRigidPivotTol * d0[j]);
         const double ljj = sqrt(ok ? sum : 1.0);
         A[j][j] = ljj;
 #pragma unroll

@@ -210,7 +210,7 @@ def summarize(results: Sequence[Result], wall: Optional[float] = None) -> dict:
     return {"requests": len(results), "span_s": span, "registrations_per_s": len(results) / span,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
-            "failed": int(sum(r.status != 0 for r in results))}
+            "degenerate": int(sum(r.status != 0 for r in results))}
 
 
 # ------------------------------------------------------------------------------

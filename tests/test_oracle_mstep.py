@@ -134,6 +134,50 @@ def test_degenerate_system_raises():
         oracle.gn_step(np.zeros((6, 6)), np.zeros(6))
 
 
+def _plane_system(normals_of_planes, seed=0, n=300):
+    """Point-to-plane normal equations of points on the given planes through the origin, each point
+    with its plane's normal and a unit weight (Eq. 10 with the rigid Jacobian of Sec. 5)."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((6, 6))
+    for nrm in normals_of_planes:
+        nrm = np.asarray(nrm, float) / np.linalg.norm(nrm)
+        u = np.cross(nrm, [1.0, 0.3, 0.1]); u /= np.linalg.norm(u)
+        v = np.cross(nrm, u)
+        x = rng.uniform(-1, 1, (n, 1)) * u + rng.uniform(-1, 1, (n, 1)) * v
+        J = oracle.point_jacobian(x)                      # (n, 3, 6)
+        row = np.einsum("k,ikp->ip", nrm, J)              # n^T J
+        A += row.T @ row
+    return A
+
+
+def test_planar_point_to_plane_system_has_rank_three_and_is_refused():
+    # one plane constrains the translation along its normal and the two rotations about axes in it:
+    # rank 3, whatever the rounding of the sums
+    A = _plane_system([[0.2, -0.1, 1.0]])
+    ev = np.linalg.eigvalsh(A)
+    assert (np.abs(ev[:3]) < 1e-9 * ev[-1]).all() and (ev[3:] > 1e-3 * ev[-1]).all()
+    b = np.ones(6)
+    with pytest.raises(oracle.Degenerate):
+        oracle.gn_step(A, b, oracle.RIGID_PIVOT_TOL)
+    # binary32-sized perturbations can make it numerically positive definite; the relative pivot rule
+    # still refuses it, where the bare Cholesky would not
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        E = rng.normal(size=(6, 6)) * 3e-6 * np.abs(A).max()
+        Ap = A + E @ E.T / 6 + np.eye(6) * 1e-7 * np.abs(A).max()
+        oracle.gn_step(Ap, b)                                  # no error without the rule
+        with pytest.raises(oracle.Degenerate):
+            oracle.gn_step(Ap, b, oracle.RIGID_PIVOT_TOL)
+
+
+def test_three_planes_pass_the_pivot_rule():
+    A = _plane_system([[1, 0, 0.1], [0, 1, 0.2], [0.1, 0.1, 1]])
+    L = np.linalg.cholesky(A)
+    assert (np.diag(L) ** 2 / np.diag(A)).min() > 100 * oracle.RIGID_PIVOT_TOL
+    x = oracle.gn_step(A, np.ones(6), oracle.RIGID_PIVOT_TOL)
+    np.testing.assert_allclose(A @ x, -np.ones(6), rtol=0, atol=1e-9 * np.abs(A).max())
+
+
 def test_outlier_constant_formula():
     # c = w/(1-w) N/M in PDF units times (2 pi)^(3/2) sigma^3 for un-normalised kernel sums
     c = oracle.outlier_constant(0.5, 200, 100, (0.1, 0.1, 0.1))

@@ -67,7 +67,7 @@ def test_every_request_runs_exactly_its_iterations_under_the_limits():
         assert r.pose[1, 3] == r.rid and r.pose[0, 3] == 7
         assert r.completed >= r.admitted >= r.arrival
     s = summarize(res)
-    assert s["requests"] == len(reqs) and s["failed"] == 0
+    assert s["requests"] == len(reqs) and s["degenerate"] == 0
     assert s["latency_ms"]["p99"] >= s["latency_ms"]["p50"] > 0
 
 
