@@ -671,29 +671,44 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
     atomicOr(fail, 1);
 }
 
-// One thread per slot: write the key words of its vertex and its padded
-// values, or only the empty marker (a free slot's values are never read).
+// Filling the table, first pass (one thread per slot): a free slot gets the
+// empty key, an occupied one tells its vertex where it sits.
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_cuckoo_fill(size_t n_slots, const uint32_t *own, const uint64_t *vkey,
-                                                    const float *vval, size_t NV, char *table)
+__global__ void __launch_bounds__(256) k_slot_owner(size_t n_slots, const uint32_t *own, char *table,
+                                                   uint32_t *vslot)
 {
     using G = SlotGeom<KW, V>;
-    constexpr int VP = ValPad<V>::value;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_slots) return;
     const uint32_t o = own[j];
-    uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
-    if (o == kOwnerEmpty) {
-#pragma unroll
-        for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
+    if (o != kOwnerEmpty) {
+        vslot[o] = (uint32_t)j;
         return;
     }
+    uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
 #pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + o];
+    for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
+}
+
+// Second pass (one thread per vertex, reading the vertex arrays in order):
+// the key words and padded values of the vertex, written to its slot.  A free
+// slot's values are never read.
+template <int KW, int V>
+__global__ void __launch_bounds__(256) k_vertex_fill(size_t NV, const uint32_t *vslot, const uint64_t *vkey,
+                                                    const float *vval, char *table)
+{
+    using G = SlotGeom<KW, V>;
+    constexpr int VP = ValPad<V>::value;
+    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= NV) return;
+    char *slot = table + (size_t)G::bytes * vslot[v];
+    uint64_t *key = reinterpret_cast<uint64_t *>(slot);
+#pragma unroll
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
     float val[VP];
 #pragma unroll
-    for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * NV + o] : 0.0f;
-    float4 *dst = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
+    for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * NV + v] : 0.0f;
+    float4 *dst = reinterpret_cast<float4 *>(slot + G::val_off);
 #pragma unroll
     for (int q = 0; q < VP / 4; ++q) dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
 }
@@ -973,9 +988,18 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         for (int32_t s = 0; s < S; ++s) lat->sets_h[s].seed = lat->sets_h[s].seed * 0x9E3779B1u + 0x7F4A7C15u;
     }
     if (n2 > 0) {
-        k_cuckoo_fill<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, own2.as<uint32_t>(), lat->vkey, lat->vval, NV,
-                                                                 reinterpret_cast<char *>(lat->tab));
+        DevBuf vslot;
+        FR_TRY(vslot.alloc(ctx, std::max<size_t>(NV, 1) * sizeof(uint32_t)));
+        char *table = reinterpret_cast<char *>(lat->tab);
+        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, own2.as<uint32_t>(), table,
+                                                                vslot.as<uint32_t>());
         FR_HIP(hipGetLastError());
+        if (NV > 0) {
+            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, vslot.as<uint32_t>(), lat->vkey,
+                                                                     lat->vval, table);
+            FR_HIP(hipGetLastError());
+        }
+        FR_HIP(hipStreamSynchronize(st));
     }
     FR_HIP(hipStreamSynchronize(st));
     return FR_OK;
