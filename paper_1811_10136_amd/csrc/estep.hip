@@ -1,9 +1,9 @@
 // E-step slice (Eq. 6, Eq. 9 through the general Gaussian transform Eq. 11):
 // one thread per model point moves the point (Eq. 15), embeds its feature in
 // the lattice, looks the D = d + 1 vertices of its simplex up in the set's
-// cuckoo table (all 2D candidate key slots are read at once, then the value
-// slots of the vertices found) and accumulates b_k * [1, y, n_y] into M0, M1
-// and the normal sum.
+// bucketed cuckoo table (the first buckets of all D vertices at once, second
+// buckets where needed, then the values of the vertices found, from the lines
+// just read) and accumulates b_k * [1, y, n_y] into M0, M1 and the normal sum.
 //
 // Memory behaviour: model points and outputs are streamed once (structure of
 // arrays, coalesced, non-temporal so they do not evict the table from L2);
@@ -283,7 +283,8 @@ fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, i
 
 // Descriptor E-step (Eq. 8 with the features alone): one model point per
 // thread reads its descriptor row, walks the d+1 vertices of its simplex one at
-// a time (key, two candidate slots, value slot) and sums b * [1, y].
+// a time (key, its bucket or two, the values of the slot found) and sums
+// b * [1, y].
 struct FeatArgs {
     const float *feat;        // M x d row-major
     const float *kf;          // d scale factors

@@ -3,10 +3,11 @@
 // Pipeline for all sets of a cloud at once:
 //   1. embed      one thread per observation point: D vertex keys + weights
 //                 written as records r = point * D + k.
-//   2. insert     one thread per record: insert the key into a provisional
-//                 open-addressing table of the record's set (32-bit owner CAS,
-//                 keys compared through the owner record, so keys of any
-//                 width work).
+//   2. insert     one thread per record: the records of a tile are merged by
+//                 key in LDS, then one record per distinct key inserts it
+//                 into a provisional open-addressing table of the record's
+//                 set (32-bit owner CAS, keys compared through the owner
+//                 record, so keys of any width work).
 //   3. vertices   the record that owns each slot defines a vertex; an
 //                 exclusive scan over records numbers the vertices in owner
 //                 order (so vertex ids follow point order) and gives each
@@ -17,9 +18,10 @@
 //                 and one thread per vertex sums b * [1, y, n_y] in that
 //                 order in binary64 -> bitwise deterministic.  Atomic mode:
 //                 binary32 hardware atomics and an occupancy counter.
-//   5. final      per set, a two-choice cuckoo table (load factor <= 0.4):
-//                 every key sits in one of its two candidate slots, so an
-//                 E-step lookup is two key reads and one value read.
+//   5. final      per set, a bucketed two-choice cuckoo table (load factor
+//                 <= 0.4, two slots of key + values per bucket): an E-step
+//                 lookup reads one bucket line, and a second one only when
+//                 the first bucket is full without the key.
 #include <algorithm>
 
 #include <cstring>
