@@ -55,6 +55,33 @@ def test_lattice_build_parity(fr, ctx, feat, V, splat):
     lat.close()
 
 
+@pytest.mark.parametrize("splat", [0, 1], ids=["sorted", "atomic"])
+def test_lattice_of_repeated_points(fr, ctx, splat):
+    # 300 copies of one point among 500 others: whole tiles of splat records (256 each) carry the
+    # same seven keys (the records of a tile are merged by key before they probe the global table),
+    # and single vertices collect hundreds of incidences (few enough that the atomic mode's binary32
+    # sums of equal terms stay within the vertex-value tolerance)
+    p = synth.random_cloud_pair(7, 600, 500, feat=6, residual="pt2pl")
+    obs = np.concatenate([p.obs[:200], np.repeat(p.obs[200:201], 300, 0), p.obs[201:]])
+    obs_n = np.concatenate([p.obs_n[:200], np.repeat(p.obs_n[200:201], 300, 0), p.obs_n[201:]])
+    _say(f"[lattice-repeat] splat={splat} N={len(obs)}")
+    lat = fr.Lattice(ctx, upload([obs], [obs_n]), fr.lattice_params(6, 7, p.sigma, p.sigma_n, splat))
+    keys, occ, vals = lat.export(0)
+    ref = oracle_lattice(obs, obs_n, 6, "pt2pl", p.sigma, p.sigma_n)
+    assert_lattice_equal(keys, occ, vals, ref, L=float(np.abs(obs).max()))
+    assert occ.max() >= 300
+    M = len(p.model)
+    m0, m1 = torch.empty(M, device="cuda"), torch.empty(3 * M, device="cuda")
+    ns = torch.empty(3 * M, device="cuda")
+    model = upload([p.model], [p.model_n])
+    fr.fr_estep(lat.h, model, fr.XForm(), m0, m1, ns)
+    torch.cuda.synchronize()
+    g = oracle.lattice_slice(ref, oracle.features(p.model, p.model_n, 6))
+    assert_estep_close(soa(m0), soa(m1).reshape(3, M).T, soa(ns).reshape(3, M).T, g[:, 0], g[:, 1:4], g[:, 4:7],
+                       float(ref.vals[:, 0].max()), float(np.abs(obs).max()))
+    lat.close()
+
+
 def test_lattice_full_depth_frame(fr, ctx):
     p = synth.depth_pair(0)
     _say(f"[lattice-full] depth frame N={len(p.obs)} d=6 V=7")
