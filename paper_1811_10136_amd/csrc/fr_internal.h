@@ -67,6 +67,10 @@ struct fr_ctx {
     std::vector<Block> cache;
     std::vector<hipEvent_t> spare_events;
     hipStream_t graph_stream = nullptr;   // capture/replay stream of fr_register's graphs
+    // vertices per splat record of the context's last lattice build: sizes the
+    // first provisional table of the next one (loops that rebuild at a
+    // shrinking scale see most records carry keys of their own)
+    double vertex_ratio = 0.0;
 };
 
 struct fr_lattice {

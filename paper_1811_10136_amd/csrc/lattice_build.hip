@@ -718,10 +718,12 @@ __global__ void __launch_bounds__(256) k_vertex_fill(size_t NV, const uint32_t *
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
+// Smallest power of two >= max(x, 16), capped at 2^31 (callers check the
+// capacity they get against what they need).
 static uint32_t next_pow2(uint64_t x)
 {
     uint64_t p = 16;
-    while (p < x) p <<= 1;
+    while (p < x && p < (1ull << 31)) p <<= 1;
     return (uint32_t)p;
 }
 
@@ -802,7 +804,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         }
         FR_HIP(hipGetLastError());
     }
-    // 2. insert into provisional tables (pow2 >= R_set / 2 first; 2 R_set if that overflows)
+    // 2. insert into provisional tables (pow2 >= R_set / 2 first, or twice the
+    //    vertices the last build's vertices-per-record ratio predicts if that is
+    //    more; 2 R_set if that overflows)
     std::vector<int64_t> roff(S + 1);
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
@@ -814,7 +818,12 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         n1 = 0;
         for (int32_t s = 0; s < S; ++s) {
             const uint64_t rs = (uint64_t)(roff[s + 1] - roff[s]);
-            const uint32_t cap = next_pow2(attempt == 0 ? rs / 2 : 2 * rs);
+            const uint64_t guess = (uint64_t)(2.0 * std::min(ctx->vertex_ratio, 1.0) * (double)rs);
+            const uint32_t cap = next_pow2(attempt == 0 ? std::max<uint64_t>(rs / 2, guess) : 2 * rs);
+            if (2 * rs > (1ull << 31) && attempt == 1) {
+                set_error("fr_lattice_build: set %d has too many splat records (%llu)", s, (unsigned long long)rs);
+                return FR_EINVAL;
+            }
             t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1, {}};
             n1 += cap;
         }
@@ -871,6 +880,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     }
     const size_t NV = nv_total;
     lat->n_vertices_total = (int64_t)NV;
+    if (R > 0) ctx->vertex_ratio = (double)NV / (double)R;
 
     // vertex arrays (kept for export)
     lat->vert_bytes = NV * (KW * sizeof(uint64_t) + sizeof(uint32_t) + V * sizeof(float)) + 64;
