@@ -57,47 +57,60 @@ __device__ inline void axis_rotation(const double *a, double angle, double (&R)[
         }
 }
 
-// Forward kinematics by one thread: body frames (R in bodyR[9b], t in bodyT[3b])
-// and per-DOF world axis w (3k) and point q (3k).
-__device__ void forward_kinematics(const ArtTree &t, const double *theta, double *bodyR, double *bodyT, double *w,
-                                   double *q)
+// Forward kinematics: body frames (R in bodyR[9b], t in bodyT[3b]) and per-DOF
+// world axis w (3k) and point q (3k).  The DOF rotations exp(theta_k [a_k]_x)
+// are independent and are formed first, one thread per DOF, into Qs (9 per
+// DOF); thread 0 then composes them down the tree.  Called by the whole block.
+__device__ void forward_kinematics(const ArtTree &t, const double *theta, double *Qs, double *bodyR, double *bodyT,
+                                   double *w, double *q)
 {
-    for (int b = 0; b < t.n_bodies; ++b) {
-        double R[3][3], p[3];
-        const int pa = t.parent[b];
-        if (pa < 0) {
-            for (int i = 0; i < 3; ++i) {
-                for (int j = 0; j < 3; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
-                p[i] = 0.0;
-            }
-        } else {
-            for (int i = 0; i < 3; ++i) {
-                for (int j = 0; j < 3; ++j) R[i][j] = bodyR[9 * pa + 3 * i + j];
-                p[i] = bodyT[3 * pa + i];
-            }
-        }
-        // joint origin: F = P . Trans(o)
-        double o[3];
+    for (int k = threadIdx.x; k < t.n_dof; k += blockDim.x) {
+        double Q[3][3];
+        axis_rotation(t.axis + 3 * k, theta[k], Q);
         for (int i = 0; i < 3; ++i)
-            o[i] = R[i][0] * t.origin[3 * b] + R[i][1] * t.origin[3 * b + 1] + R[i][2] * t.origin[3 * b + 2] + p[i];
-        for (int k = t.dof_off[b]; k < t.dof_off[b + 1]; ++k) {
-            const double *a = t.axis + 3 * k;
-            for (int i = 0; i < 3; ++i) {
-                w[3 * k + i] = R[i][0] * a[0] + R[i][1] * a[1] + R[i][2] * a[2];
-                q[3 * k + i] = o[i];
+            for (int j = 0; j < 3; ++j) Qs[9 * k + 3 * i + j] = Q[i][j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int b = 0; b < t.n_bodies; ++b) {
+            double R[3][3], p[3];
+            const int pa = t.parent[b];
+            if (pa < 0) {
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
+                    p[i] = 0.0;
+                }
+            } else {
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) R[i][j] = bodyR[9 * pa + 3 * i + j];
+                    p[i] = bodyT[3 * pa + i];
+                }
             }
-            double Q[3][3], N[3][3];
-            axis_rotation(a, theta[k], Q);
+            // joint origin: F = P . Trans(o)
+            double o[3];
             for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) N[i][j] = R[i][0] * Q[0][j] + R[i][1] * Q[1][j] + R[i][2] * Q[2][j];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) R[i][j] = N[i][j];
-        }
-        for (int i = 0; i < 3; ++i) {
-            for (int j = 0; j < 3; ++j) bodyR[9 * b + 3 * i + j] = R[i][j];
-            bodyT[3 * b + i] = o[i];
+                o[i] = R[i][0] * t.origin[3 * b] + R[i][1] * t.origin[3 * b + 1] + R[i][2] * t.origin[3 * b + 2] + p[i];
+            for (int k = t.dof_off[b]; k < t.dof_off[b + 1]; ++k) {
+                const double *a = t.axis + 3 * k;
+                for (int i = 0; i < 3; ++i) {
+                    w[3 * k + i] = R[i][0] * a[0] + R[i][1] * a[1] + R[i][2] * a[2];
+                    q[3 * k + i] = o[i];
+                }
+                const double *Q = Qs + 9 * k;
+                double N[3][3];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        N[i][j] = R[i][0] * Q[0 * 3 + j] + R[i][1] * Q[1 * 3 + j] + R[i][2] * Q[2 * 3 + j];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) R[i][j] = N[i][j];
+            }
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) bodyR[9 * b + 3 * i + j] = R[i][j];
+                bodyT[3 * b + i] = o[i];
+            }
         }
     }
+    __syncthreads();
 }
 
 // mode 0: forward kinematics only (writes mats); mode 1: Gauss-Newton step + forward kinematics.
@@ -107,7 +120,11 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
 {
     __shared__ double s_th[kArtMaxDof], s_w[3 * kArtMaxDof], s_q[3 * kArtMaxDof], s_u[6 * kArtMaxDof];
     __shared__ double s_A[kArtMaxDof * kArtMaxDof], s_rhs[kArtMaxDof], s_x[kArtMaxDof];
-    __shared__ double s_R[9 * kArtMaxBodies], s_T[3 * kArtMaxBodies];
+    __shared__ double s_R[9 * kArtMaxBodies], s_T[3 * kArtMaxBodies], s_Q[9 * kArtMaxDof];
+    // per-body sums and the DOF masks, staged once: the assembly loops read
+    // them for every (DOF, DOF) entry and body
+    __shared__ double s_S[21 * kArtMaxBodies], s_g[6 * kArtMaxBodies];
+    __shared__ uint64_t s_mb[kArtMaxBodies];
     __shared__ int s_ok;
     const int tid = threadIdx.x;
     const int n = tree.n_dof;
@@ -115,8 +132,10 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
     if (tid == 0) s_ok = 1;
     __syncthreads();
     if (mode == 1) {
-        if (tid == 0) forward_kinematics(tree, s_th, s_R, s_T, s_w, s_q);
-        __syncthreads();
+        for (int i = tid; i < 21 * tree.n_bodies; i += kArtThreads) s_S[i] = jtj[i];
+        for (int i = tid; i < 6 * tree.n_bodies; i += kArtThreads) s_g[i] = jtr[i];
+        for (int b = tid; b < tree.n_bodies; b += kArtThreads) s_mb[b] = tree.moved_by[b];
+        forward_kinematics(tree, s_th, s_Q, s_R, s_T, s_w, s_q);
         for (int k = tid; k < n; k += kArtThreads) {
             const double *w = s_w + 3 * k, *q = s_q + 3 * k;
             s_u[6 * k + 0] = w[0];
@@ -133,9 +152,9 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
             if (l < k) continue;
             double acc = 0.0;
             for (int b = 0; b < tree.n_bodies; ++b) {
-                const uint64_t mb = tree.moved_by[b];
+                const uint64_t mb = s_mb[b];
                 if (!((mb >> k) & 1ull) || !((mb >> l) & 1ull)) continue;
-                const double *S = jtj + 21 * b;
+                const double *S = s_S + 21 * b;
                 double Su[6];
                 int idx = 0;
                 double Sf[6][6];
@@ -158,8 +177,8 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
         for (int k = tid; k < n; k += kArtThreads) {
             double acc = 0.0;
             for (int b = 0; b < tree.n_bodies; ++b) {
-                if (!((tree.moved_by[b] >> k) & 1ull)) continue;
-                for (int i = 0; i < 6; ++i) acc += s_u[6 * k + i] * jtr[6 * b + i];
+                if (!((s_mb[b] >> k) & 1ull)) continue;
+                for (int i = 0; i < 6; ++i) acc += s_u[6 * k + i] * s_g[6 * b + i];
             }
             s_rhs[k] = acc;
         }
@@ -173,11 +192,13 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
             }
         }
         __syncthreads();
-        // Cholesky A = L L^T in place (lower triangle), column by column
+        // Cholesky A = L L^T in place (lower triangle), right-looking: column j
+        // is scaled by its pivot, then the trailing triangle takes its rank-1
+        // update; every entry receives its updates in column order, as in the
+        // left-looking form
         for (int j = 0; j < n; ++j) {
             if (tid == 0) {
                 double v = s_A[j * n + j];
-                for (int k = 0; k < j; ++k) v -= s_A[j * n + k] * s_A[j * n + k];
                 if (!(v > 0.0)) {
                     s_ok = 0;
                     v = 1.0;
@@ -185,27 +206,35 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
                 s_A[j * n + j] = sqrt(v);
             }
             __syncthreads();
-            for (int i = j + 1 + tid; i < n; i += kArtThreads) {
-                double v = s_A[i * n + j];
-                for (int k = 0; k < j; ++k) v -= s_A[i * n + k] * s_A[j * n + k];
-                s_A[i * n + j] = v / s_A[j * n + j];
+            for (int i = j + 1 + tid; i < n; i += kArtThreads) s_A[i * n + j] = s_A[i * n + j] / s_A[j * n + j];
+            __syncthreads();
+            const int m = n - j - 1;   // trailing size
+            for (int e = tid; e < m * m; e += kArtThreads) {
+                const int i = j + 1 + e / m, k = j + 1 + e % m;
+                if (k <= i) s_A[i * n + k] -= s_A[i * n + j] * s_A[k * n + j];
             }
+            __syncthreads();
+        }
+        // L y = -rhs (column-oriented: y_k is final once the columns before it
+        // have been subtracted), then L^T x = y
+        for (int i = tid; i < n; i += kArtThreads) s_x[i] = -s_rhs[i];
+        __syncthreads();
+        for (int k = 0; k < n; ++k) {
+            if (tid == 0) s_x[k] = s_x[k] / s_A[k * n + k];
+            __syncthreads();
+            for (int i = k + 1 + tid; i < n; i += kArtThreads) s_x[i] -= s_A[i * n + k] * s_x[k];
+            __syncthreads();
+        }
+        for (int k = n - 1; k >= 0; --k) {
+            if (tid == 0) s_x[k] = s_x[k] / s_A[k * n + k];
+            __syncthreads();
+            for (int i = tid; i < k; i += kArtThreads) s_x[i] -= s_A[k * n + i] * s_x[k];
             __syncthreads();
         }
         if (tid == 0) {
             if (s_ok) {
-                for (int i = 0; i < n; ++i) {
-                    double v = -s_rhs[i];
-                    for (int k = 0; k < i; ++k) v -= s_A[i * n + k] * s_x[k];
-                    s_x[i] = v / s_A[i * n + i];
-                }
                 double nrm = 0.0;
-                for (int i = n - 1; i >= 0; --i) {
-                    double v = s_x[i];
-                    for (int k = i + 1; k < n; ++k) v -= s_A[k * n + i] * s_x[k];
-                    s_x[i] = v / s_A[i * n + i];
-                    nrm += s_x[i] * s_x[i];
-                }
+                for (int i = n - 1; i >= 0; --i) nrm += s_x[i] * s_x[i];
                 for (int i = 0; i < n; ++i) s_th[i] += s_x[i];
                 if (step_norm) *step_norm = sqrt(nrm);
                 if (status) *status = FR_OK;
@@ -217,8 +246,7 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
         __syncthreads();
         for (int k = tid; k < n; k += kArtThreads) theta[k] = s_th[k];
     }
-    if (tid == 0) forward_kinematics(tree, s_th, s_R, s_T, s_w, s_q);
-    __syncthreads();
+    forward_kinematics(tree, s_th, s_Q, s_R, s_T, s_w, s_q);
     for (int b = tid; b < tree.n_bodies; b += kArtThreads) {
         for (int i = 0; i < 3; ++i) {
             for (int j = 0; j < 3; ++j) mats[12 * b + 4 * i + j] = (float)s_R[9 * b + 3 * i + j];

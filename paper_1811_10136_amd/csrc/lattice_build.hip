@@ -1207,7 +1207,8 @@ __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *s
 }
 
 // Copy the values of every slot between the table and a plain array of VP
-// binary32 per slot (to_table false: out of the table; true: back in).
+// binary32 per slot (to_table false: out of the table, zeros for a free slot,
+// whose values the fill leaves unwritten; true: back in).
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, char *table, float *plain, bool to_table)
 {
@@ -1215,6 +1216,7 @@ __global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, char *table
     constexpr int VP = ValPad<V>::value;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_slots) return;
+    const bool free_slot = reinterpret_cast<const uint64_t *>(table + G::bytes * j)[0] == kKeyEmpty;
     float4 *tv = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
     float4 *pv = reinterpret_cast<float4 *>(plain + (size_t)VP * j);
 #pragma unroll
@@ -1222,7 +1224,7 @@ __global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, char *table
         if (to_table)
             tv[c] = pv[c];
         else
-            pv[c] = tv[c];
+            pv[c] = free_slot ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : tv[c];
     }
 }
 
