@@ -82,6 +82,28 @@ def test_lattice_of_repeated_points(fr, ctx, splat):
     lat.close()
 
 
+def test_provisional_table_overflow_and_sizing_from_the_previous_build(fr):
+    # points farther apart than the kernel: every splat record carries a key of its own, so a fresh
+    # context's first provisional table (sized for half the records) overflows and the insertion runs
+    # again in a larger one; the next build in that context sizes its table from this one's vertices
+    # per record and inserts once.  Both give the oracle's lattice.
+    p = synth.separated_pair(3, m=3000, sigma=0.02, feat=6, residual="pt2pl")
+    _say(f"[provisional] N={len(p.obs)}")
+    c = fr.Context(0)
+    ref = oracle_lattice(p.obs, p.obs_n, 6, "pt2pl", p.sigma, p.sigma_n)
+    assert ref.n_vertices > 0.5 * 7 * len(p.obs)          # more keys than the first table takes
+    outs = []
+    for _ in range(2):
+        lat = fr.Lattice(c, upload([p.obs], [p.obs_n]), fr.lattice_params(6, 7, p.sigma, p.sigma_n))
+        keys, occ, vals = lat.export(0)
+        assert_lattice_equal(keys, occ, vals, ref, L=float(np.abs(p.obs).max()))
+        outs.append((keys, occ, vals))
+        lat.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    c.close()
+
+
 def test_lattice_full_depth_frame(fr, ctx):
     p = synth.depth_pair(0)
     _say(f"[lattice-full] depth frame N={len(p.obs)} d=6 V=7")
