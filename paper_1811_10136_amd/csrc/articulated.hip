@@ -18,6 +18,9 @@
 // origin[3B] (joint origin in the parent frame), axis[3 n_dof] (unit axis in
 // the frame left by the preceding rotations), moved_by[B] (bit k set if DOF k
 // moves body b).  n_dof <= 64.
+#include <algorithm>
+#include <vector>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -33,6 +36,9 @@ struct ArtTree {
     const double *origin;
     const double *axis;
     const uint64_t *moved_by;
+    int32_t n_levels;
+    const int32_t *level_off;    // n_levels + 1: bodies of depth L are level_body[level_off[L] .. level_off[L+1])
+    const int32_t *level_body;
 };
 
 // R = exp(angle [a]_x) for a unit axis a (two-term series below |angle| = 1e-4).
@@ -60,7 +66,9 @@ __device__ inline void axis_rotation(const double *a, double angle, double (&R)[
 // Forward kinematics: body frames (R in bodyR[9b], t in bodyT[3b]) and per-DOF
 // world axis w (3k) and point q (3k).  The DOF rotations exp(theta_k [a_k]_x)
 // are independent and are formed first, one thread per DOF, into Qs (9 per
-// DOF); thread 0 then composes them down the tree.  Called by the whole block.
+// DOF); the frames are then composed level by level down the tree, the bodies
+// of a level in parallel (each in the same arithmetic as a serial walk).
+// Called by the whole block.
 __device__ void forward_kinematics(const ArtTree &t, const double *theta, double *Qs, double *bodyR, double *bodyT,
                                    double *w, double *q)
 {
@@ -71,8 +79,9 @@ __device__ void forward_kinematics(const ArtTree &t, const double *theta, double
             for (int j = 0; j < 3; ++j) Qs[9 * k + 3 * i + j] = Q[i][j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int b = 0; b < t.n_bodies; ++b) {
+    for (int L = 0; L < t.n_levels; ++L) {   // a body's parent is one level up, complete
+        for (int ib = t.level_off[L] + (int)threadIdx.x; ib < t.level_off[L + 1]; ib += blockDim.x) {
+            const int b = t.level_body[ib];
             double R[3][3], p[3];
             const int pa = t.parent[b];
             if (pa < 0) {
@@ -109,8 +118,8 @@ __device__ void forward_kinematics(const ArtTree &t, const double *theta, double
                 bodyT[3 * b + i] = o[i];
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // mode 0: forward kinematics only (writes mats); mode 1: Gauss-Newton step + forward kinematics.
@@ -258,7 +267,8 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
 fr_status launch_articulated_step(const ArtTreeHost &h, int mode, const double *jtj, const double *jtr, double *theta,
                                   float *mats, double *step_norm, int32_t *status, hipStream_t st)
 {
-    ArtTree t{h.n_bodies, h.n_dof, h.parent, h.dof_off, h.origin, h.axis, h.moved_by};
+    ArtTree t{h.n_bodies, h.n_dof, h.parent, h.dof_off, h.origin, h.axis, h.moved_by, h.n_levels, h.level_off,
+              h.level_body};
     k_articulated_step<<<1, kArtThreads, 0, st>>>(t, mode, jtj, jtr, theta, mats, step_norm, status);
     FR_HIP(hipGetLastError());
     return FR_OK;
@@ -278,33 +288,49 @@ fr_status upload_tree(fr_ctx *ctx, const fr_kinematic_tree *tree, hipStream_t st
         return FR_EINVAL;
     }
     std::vector<uint64_t> moved(B, 0);
+    std::vector<int32_t> depth(B, 0);
     for (int32_t b = 0; b < B; ++b) {
         if (tree->parent[b] >= b || tree->parent[b] < -1 || tree->dof_offset[b + 1] < tree->dof_offset[b]) {
             set_error("kinematic tree: parent[b] must be in [-1, b) and dof_offset non-decreasing (body %d)", b);
             return FR_EINVAL;
         }
         uint64_t m = tree->parent[b] >= 0 ? moved[tree->parent[b]] : 0ull;
+        depth[b] = tree->parent[b] >= 0 ? depth[tree->parent[b]] + 1 : 0;
         for (int32_t k = tree->dof_offset[b]; k < tree->dof_offset[b + 1]; ++k) m |= 1ull << k;
         moved[b] = m;
     }
+    // bodies grouped by depth (a parent always has a smaller index, so its depth is known first)
+    const int32_t n_levels = *std::max_element(depth.begin(), depth.end()) + 1;
+    std::vector<int32_t> level_off(n_levels + 1, 0), level_body;
+    for (int32_t L = 0; L < n_levels; ++L) {
+        level_off[L] = (int32_t)level_body.size();
+        for (int32_t b = 0; b < B; ++b)
+            if (depth[b] == L) level_body.push_back(b);
+    }
+    level_off[n_levels] = B;
     out.n_bodies = B;
     out.n_dof = n;
+    out.n_levels = n_levels;
     const size_t bp = sizeof(int32_t) * B, bd = sizeof(int32_t) * (B + 1), bo = sizeof(double) * 3 * B,
-                 ba = sizeof(double) * 3 * n, bm = sizeof(uint64_t) * B;
+                 ba = sizeof(double) * 3 * n, bm = sizeof(uint64_t) * B, bl = sizeof(int32_t) * (n_levels + 1);
     // 8-byte aligned sub-buffers: doubles and masks first
-    FR_TRY(out.buf.alloc(ctx, bo + ba + bm + bp + bd));
+    FR_TRY(out.buf.alloc(ctx, bo + ba + bm + bp + bd + bl + bp));
     char *p = out.buf.as<char>();
     FR_HIP(hipMemcpyAsync(p, tree->origin, bo, hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(p + bo, tree->axis, ba, hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(p + bo + ba, moved.data(), bm, hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(p + bo + ba + bm, tree->parent, bp, hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(p + bo + ba + bm + bp, tree->dof_offset, bd, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo + ba + bm + bp + bd, level_off.data(), bl, hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(p + bo + ba + bm + bp + bd + bl, level_body.data(), bp, hipMemcpyHostToDevice, st));
     FR_HIP(hipStreamSynchronize(st));
     out.origin = reinterpret_cast<const double *>(p);
     out.axis = reinterpret_cast<const double *>(p + bo);
     out.moved_by = reinterpret_cast<const uint64_t *>(p + bo + ba);
     out.parent = reinterpret_cast<const int32_t *>(p + bo + ba + bm);
     out.dof_off = reinterpret_cast<const int32_t *>(p + bo + ba + bm + bp);
+    out.level_off = reinterpret_cast<const int32_t *>(p + bo + ba + bm + bp + bd);
+    out.level_body = reinterpret_cast<const int32_t *>(p + bo + ba + bm + bp + bd + bl);
     return FR_OK;
 }
 

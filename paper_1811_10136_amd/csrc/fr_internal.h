@@ -230,8 +230,9 @@ fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, do
 
 // articulated.hip
 struct ArtTreeHost {
-    int32_t n_bodies = 0, n_dof = 0;
+    int32_t n_bodies = 0, n_dof = 0, n_levels = 0;
     const int32_t *parent = nullptr, *dof_off = nullptr;
+    const int32_t *level_off = nullptr, *level_body = nullptr;   // bodies grouped by depth in the tree
     const double *origin = nullptr, *axis = nullptr;
     const uint64_t *moved_by = nullptr;
     DevBuf buf;
