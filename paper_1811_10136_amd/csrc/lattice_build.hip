@@ -101,6 +101,7 @@ fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, siz
     }
     DevBuf bs;
     FR_TRY(bs.alloc(ctx, nb * sizeof(uint32_t)));
+    bs.stream = st;   // freed in the order of st: no wait here
     if (mode == 1) k_scan_tile<1><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
     else if (mode == 2) k_scan_tile<2><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
     else k_scan_tile<0><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
@@ -108,8 +109,6 @@ fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, siz
     FR_TRY(scan_exclusive_u32(ctx, bs.as<uint32_t>(), bs.as<uint32_t>(), nb, 0, st));
     k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, bs.as<uint32_t>(), n);
     FR_HIP(hipGetLastError());
-    // bs is freed by the destructor: DevBuf frees after a stream sync (see dev_free).
-    FR_HIP(hipStreamSynchronize(st));
     return FR_OK;
 }
 
@@ -235,6 +234,7 @@ static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, u
     const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
     DevBuf hist;
     FR_TRY(hist.alloc(ctx, (size_t)256 * nb * sizeof(uint32_t)));
+    hist.stream = st;
     uint32_t *ka = keys, *va = vals, *kb = tk, *vb = tv;
     int passes = 0;
     for (int shift = 0; shift < bits; shift += 8, ++passes) {
@@ -248,7 +248,6 @@ static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, u
     }
     *keys_out = ka;
     *vals_out = va;
-    FR_HIP(hipStreamSynchronize(st));
     return FR_OK;
 }
 
@@ -460,12 +459,15 @@ __global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *re
 }
 
 // Vertex count of each set: owners of its records form one contiguous id range.
-__global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32_t *ovid, size_t R, uint32_t nv_total,
-                            uint32_t *vbase)
+// The total is the last record's scanned id plus its own flag (saved before
+// the in-place scan).
+__global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32_t *ovid, size_t R,
+                            const uint32_t *last_flag, uint32_t *vbase)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s > n_sets) return;
     const int64_t r = rec_off[s];
+    const uint32_t nv_total = R > 0 ? ovid[R - 1] + last_flag[0] : 0u;
     vbase[s] = (r < (int64_t)R) ? ovid[r] : nv_total;
 }
 
@@ -769,6 +771,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
+    StreamScope scope(st);   // temporaries are freed in the order of st
     const int32_t S = obs->n_sets;
     const int64_t N = cloud_points(obs);
     const size_t R = (size_t)N * D;
@@ -811,8 +814,12 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
     uint64_t n1 = 0;
-    DevBuf ovid, slot_vid, vb_d;
+    DevBuf ovid, slot_vid, vb_d, last_d;
     FR_TRY(ovid.alloc(ctx, R * sizeof(uint32_t)));   // owner flags, then their exclusive scan
+    FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
+    FR_TRY(last_d.alloc(ctx, sizeof(uint32_t)));
+    std::vector<uint32_t> vb_h(S + 1);
+    int32_t err_h = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<SetTable> t1(S);
         n1 = 0;
@@ -841,8 +848,17 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                                               ovid.as<uint32_t>(), fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
+        // 3. vertex ids in owner-record order and per-set ranges, enqueued before the
+        //    overflow check (one wait for both; redone if the insertion overflowed)
+        if (R > 0) FR_HIP(hipMemcpyAsync(last_d.p, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToDevice, st));
+        FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), R, 0, st));
+        k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), R,
+                                                          last_d.as<uint32_t>(), vb_d.as<uint32_t>());
+        FR_HIP(hipGetLastError());
         int32_t failed = 0;
         FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(vb_h.data(), vb_d.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(&err_h, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
         if (!failed) break;
         if (attempt == 1) {
@@ -850,24 +866,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             return FR_EDEVICE;
         }
     }
-
-    // 3. vertex ids in owner-record order, per-set ranges, keys
     FR_TRY(slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
-    FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
-    uint32_t last_flag = 0, last_scan = 0;
-    if (R > 0) FR_HIP(hipMemcpyAsync(&last_flag, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToHost, st));
-    FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), R, 0, st));
-    if (R > 0) FR_HIP(hipMemcpyAsync(&last_scan, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToHost, st));
-    FR_HIP(hipStreamSynchronize(st));
-    const uint32_t nv_total = last_scan + last_flag;
-    k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), R, nv_total,
-                                                      vb_d.as<uint32_t>());
-    FR_HIP(hipGetLastError());
-    std::vector<uint32_t> vb_h(S + 1);
-    int32_t err_h = 0;
-    FR_HIP(hipMemcpyAsync(vb_h.data(), vb_d.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    FR_HIP(hipMemcpyAsync(&err_h, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    FR_HIP(hipStreamSynchronize(st));
+    const uint32_t nv_total = vb_h[S];
     if (err_h != 0) {
         set_error("fr_lattice_build: a lattice coordinate left [-2^20, 2^20); increase sigma or centre the cloud");
         return FR_ERANGE;
@@ -929,7 +929,6 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             k_vertex_sum_sorted<D, V><<<blocks_for(NV, 256), 256, 0, st>>>(
                 NV, voff.as<uint32_t>(), lat->vocc, srid, rec_b.as<float>(), rows.as<float4>(), lat->vval);
             FR_HIP(hipGetLastError());
-            FR_HIP(hipStreamSynchronize(st));
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
             FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
@@ -1011,7 +1010,6 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                                                      lat->vval, table);
             FR_HIP(hipGetLastError());
         }
-        FR_HIP(hipStreamSynchronize(st));
     }
     FR_HIP(hipStreamSynchronize(st));
     return FR_OK;
@@ -1258,6 +1256,7 @@ static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
     constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
     fr_ctx *ctx = lat->ctx;
+    StreamScope scope(st);   // temporaries are freed in the order of st
     const int32_t S = lat->n_sets;
     std::vector<int64_t> soff(S + 1, 0);
     for (int32_t s = 0; s < S; ++s) soff[s + 1] = soff[s] + lat->sets_h[s].cap;
