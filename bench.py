@@ -545,8 +545,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
-              f"note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): independent pairs shard across GPUs "
+              f"without communication, and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     t = time.time()
