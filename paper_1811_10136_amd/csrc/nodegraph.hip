@@ -479,17 +479,29 @@ __global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
     const int L = R > 0 ? max(1, min(8, kCoopThreads / R)) : 1;   // lanes per SpMV row
     // grid-wide sums of three values per workgroup through the partial slots
     // set*3 .. set*3+2 (sets alternate between successive sums)
+    // The G partials are read one per lane (one round trip instead of G
+    // dependent ones) and added by a fixed xor-shuffle tree within the first
+    // wave, so every workgroup adds the same values in the same order.
     auto grid_sum3 = [&](double v[3], int set) {
         coop_block_sum3(v, red);
         if (tid == 0)
             for (int i = 0; i < 3; ++i) a.part[(3 * set + i) * G + g] = v[i];
         __threadfence();
         grid.sync();
-        for (int i = 0; i < 3; ++i) {
-            double t = 0.0;
-            for (int b = 0; b < G; ++b) t += a.part[(3 * set + i) * G + b];
-            v[i] = t;
+        if (tid < 64) {
+            double t[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) t[i] = tid < G ? a.part[(3 * set + i) * G + tid] : 0.0;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) t[i] += __shfl_xor(t[i], off, 64);
+            if (tid == 0)
+                for (int i = 0; i < 3; ++i) red[i] = t[i];
         }
+        __syncthreads();
+        for (int i = 0; i < 3; ++i) v[i] = red[i];
+        __syncthreads();
     };
     // u = M^-1 r over the owned nodes; returns the owned parts of (r, u)
     auto precond = [&]() {
