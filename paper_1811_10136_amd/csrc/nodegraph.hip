@@ -34,7 +34,7 @@ namespace fr {
 
 constexpr int kNgThreads = 256;
 constexpr int kPcgThreads = 1024;
-constexpr int kCoopThreads = 128;      // threads per workgroup of the grid-wide PCG
+constexpr int kCoopThreads = 256;      // threads per workgroup of the grid-wide PCG
 constexpr int kCoopMaxBlocks = 32;
 
 // --- dual quaternions (w, x, y, z) --------------------------------------------
@@ -526,14 +526,34 @@ __global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
             const bool on = tid / L < kCoopThreads / L && row < R;
             if (on) {
                 const int q = u0 + row, k = q / 6, c = q % 6;
-                for (int e = a.row_off[k] + lane; e < a.row_off[k + 1]; e += L) {
-                    const int ref = a.row_blk[e];
-                    const double *B = a.A + (size_t)36 * (ref >> 1);
-                    const double *ul = a.u + 6 * a.row_col[e];
-                    if (!(ref & 1))
-                        for (int b = 0; b < 6; ++b) acc += B[6 * c + b] * ul[b];
-                    else
-                        for (int b = 0; b < 6; ++b) acc += B[6 * b + c] * ul[b];
+                const int ee = a.row_off[k + 1];
+                // four entries at a time: their indices, then all their block
+                // and vector loads, then the products in entry order
+                for (int e = a.row_off[k] + lane; e < ee; e += 4 * L) {
+                    int ref[4], col[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        ok[j] = e + j * L < ee;
+                        ref[j] = ok[j] ? a.row_blk[e + j * L] : 0;
+                        col[j] = ok[j] ? a.row_col[e + j * L] : 0;
+                    }
+                    double bv[4][6], uv[4][6];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double *B = a.A + (size_t)36 * (ref[j] >> 1);
+                        const double *ul = a.u + 6 * col[j];
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) {
+                            bv[j][b] = ok[j] ? ((ref[j] & 1) ? B[6 * b + c] : B[6 * c + b]) : 0.0;
+                            uv[j][b] = ok[j] ? ul[b] : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ok[j])
+#pragma unroll
+                            for (int b = 0; b < 6; ++b) acc += bv[j][b] * uv[j][b];
                 }
             }
             lanes[tid] = acc;
