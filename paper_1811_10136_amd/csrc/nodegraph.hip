@@ -628,37 +628,58 @@ __global__ void __launch_bounds__(kCoopThreads) k_ng_pcg_coop(PcgArgs a)
 
 // Inverse of each diagonal 6x6 block by Gauss-Jordan with partial pivoting
 // (blocks are SPD); flags a non-positive pivot.
-__global__ void k_ng_block_inverse(int32_t K, const double *A, const int32_t *diag_blk, double *minv, int32_t *bad)
+__global__ void __launch_bounds__(64) k_ng_block_inverse(int32_t K, const double *A, const int32_t *diag_blk,
+                                                         double *minv, int32_t *bad)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
+    // every index below is a compile-time constant once the loops are
+    // unrolled (the row swap is a select per row), so M stays in registers
     double M[6][12];
     const double *B = A + (size_t)36 * diag_blk[k];
+#pragma unroll
     for (int a = 0; a < 6; ++a)
+#pragma unroll
         for (int b = 0; b < 12; ++b) M[a][b] = b < 6 ? B[6 * a + b] : (b - 6 == a ? 1.0 : 0.0);
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
         int piv = c;
+        double best = fabs(M[c][c]);
+#pragma unroll
         for (int a = c + 1; a < 6; ++a)
-            if (fabs(M[a][c]) > fabs(M[piv][c])) piv = a;
-        if (!(fabs(M[piv][c]) > 0.0)) {
+            if (fabs(M[a][c]) > best) {
+                best = fabs(M[a][c]);
+                piv = a;
+            }
+        if (!(best > 0.0)) {
             atomicOr(bad, 1);
             for (int a = 0; a < 36; ++a) minv[36 * k + a] = (a % 7 == 0) ? 1.0 : 0.0;
             return;
         }
-        for (int b = 0; b < 12; ++b) {
-            const double t = M[c][b];
-            M[c][b] = M[piv][b];
-            M[piv][b] = t;
+#pragma unroll
+        for (int a = c + 1; a < 6; ++a) {
+            const bool sw = (piv == a);
+#pragma unroll
+            for (int b = 0; b < 12; ++b) {
+                const double t = M[c][b];
+                M[c][b] = sw ? M[a][b] : t;
+                M[a][b] = sw ? t : M[a][b];
+            }
         }
         const double inv = 1.0 / M[c][c];
+#pragma unroll
         for (int b = 0; b < 12; ++b) M[c][b] *= inv;
+#pragma unroll
         for (int a = 0; a < 6; ++a) {
             if (a == c) continue;
             const double f = M[a][c];
+#pragma unroll
             for (int b = 0; b < 12; ++b) M[a][b] -= f * M[c][b];
         }
     }
+#pragma unroll
     for (int a = 0; a < 6; ++a)
+#pragma unroll
         for (int b = 0; b < 6; ++b) minv[36 * k + 6 * a + b] = M[a][6 + b];
 }
 
