@@ -237,7 +237,7 @@ fr_status fr_estep_touched(const fr_lattice *lat, const fr_cloud *model_ref, con
 typedef struct {
     int32_t residual;      /* FR_PT2PT or FR_PT2PL */
     int32_t normalize_n;   /* 1: use n_i / |n_i| */
-    double c;              /* outlier constant of Eq. 7 in un-normalised kernel units, >= 0 */
+    double c;              /* outlier constant of Eq. 7 in the units of the lattice sums, >= 0 */
     double sigma;          /* residual scale (Sigma^-1/2 of Eq. 7), > 0 */
     const double *c_per_set;
 } fr_mstep_params;
@@ -254,10 +254,11 @@ fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const f
  * (device, n x 12) receive the binary32 [R | t], twist_norm (device, n x 2)
  * receives |omega| and |v| of dzeta, status (device, n int32) receives FR_OK
  * or FR_EDEGENERATE (pose left unchanged) per set.  A is taken as singular
- * when a Cholesky pivot is at most 1e-4 times its diagonal entry: A is summed
- * from binary32 tile sums, whose rounding can leave a rank-deficient A (every
- * supported point on one plane under point-to-plane) with positive pivots of
- * relative size up to about 6e-5.  Sets with active[i] == 0 are skipped
+ * when a Cholesky pivot is at most 1e-4 times its diagonal entry (a
+ * numerical-rank test: A is summed from binary32 terms over tiles of 1024
+ * points, whose rounding reaches about 6.1e-5 of the diagonal scale, so a
+ * smaller pivot cannot be told from zero -- e.g. every supported point on one
+ * plane under point-to-plane, rank 3).  Sets with active[i] == 0 are skipped
  * (active may be NULL).
  */
 fr_status fr_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
@@ -268,8 +269,12 @@ typedef struct {
     fr_lattice_params lattice;
     int32_t residual;      /* FR_PT2PT or FR_PT2PL */
     int32_t max_iters;     /* EM iterations (exact count with FR_FIXED_ITERS) */
-    double w;              /* outlier ratio of Eq. 4 in [0, 1); c derived per set as
-                              w/(1-w) N/M (2 pi)^(3/2) sigma_x sigma_y sigma_z */
+    double w;              /* outlier ratio of Eq. 4 in [0, 1); c derived per set as w/(1-w) N/M
+                              (Eq. 7) times the mass of the lattice kernel over feature space,
+                              (3/2)^(d/2) / sqrt(d+1) times the product of the d feature widths
+                              (sigma_x sigma_y sigma_z, and sigma_n^3 when feat == 6; divided by
+                              1 + 2^-d with FR_BLURRED): Eq. 7's c is taken against Gaussian PDFs
+                              of unit mass, M0 sums this kernel instead */
     double c_override;     /* >= 0: use this c for every set instead; < 0: derive from w */
     double twist_tol;      /* stop a set when |omega| and |v| of its step are below this */
     int32_t flags;         /* FR_FIXED_ITERS | FR_PROFILE_EVENTS | FR_FUSED (slice and reduction in one
@@ -338,8 +343,8 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
  * Rigid registration by descriptors alone (Sec. 3.3 "Features" with Eq. 8;
  * the global registration of Sec. 6.3): the kernel does not involve the pose,
  * so one E-step (fr_estep_features) fixes the targets M1/M0 and the weights
- * M0/(M0 + c), c = w/(1-w) N/M (2 pi)^(dim/2) sigma_f^dim (c_override if
- * >= 0), and each EM iteration is one point-to-point Gauss-Newton step toward
+ * M0/(M0 + c), c = w/(1-w) N/M (3/2)^(dim/2) / sqrt(dim+1) sigma_f^dim (the
+ * kernel mass rule of fr_register_params.w; c_override if >= 0), and each EM iteration is one point-to-point Gauss-Newton step toward
  * them (Eq. 17; residual scale 1).  params: residual FR_PT2PT, lattice.splat
  * selects the splat (the other lattice fields are not used), max_iters, w,
  * c_override, twist_tol, FR_FIXED_ITERS and
@@ -376,7 +381,8 @@ typedef struct {
  * twist (w_k, q_k x w_k) of its world axis w_k through the joint point q_k),
  * assembles A = sum_b J_b^T jtj_b J_b and b = sum_b J_b^T jtr_b, solves
  * A dtheta = -b by Cholesky (a DOF whose row of A is zero -- it moves no
- * supported point -- is held at its value), updates theta (device, n_dof) in place and writes
+ * supported point -- is held at its value; a pivot at most 1e-4 of its
+ * diagonal entry is refused as in fr_solve_rigid), updates theta (device, n_dof) in place and writes
  * the binary32 [R | t] of every body at the new angles to mats (device,
  * n_bodies x 12).  status (device int32, may be NULL) receives FR_OK or
  * FR_EDEGENERATE (theta unchanged).  jtj/jtr may be NULL for forward

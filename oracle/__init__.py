@@ -244,13 +244,32 @@ def estep(lat: Lattice, x32: np.ndarray, n32: Optional[np.ndarray], feat: int, r
     return m0, m1, ns
 
 
-def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
-    """c of Eq. (7), c = w/(1-w) N/M, converted from PDF units to the un-normalised
-    kernel sums of Eq. (11) by the dropped factor (2 pi)^(3/2) sigma_x sigma_y sigma_z."""
+def kernel_mass(sigmas, blurred: bool = False) -> float:
+    """Integral over feature space of the lattice kernel of one observation, K(x, y) = sum_v b_v(x) b_v(y)
+    (Sec. 4.2 splat and slice; sigmas: the width of every feature dimension, position and normal).
+
+    The hats b_v of the vertices sum to one everywhere and are congruent, so each integrates to the
+    volume per vertex, and so does K over x for any y.  The vertices, the points of the hyperplane
+    sum(v) = 0 whose d+1 integer coordinates share one remainder modulo d+1, are the scaled lattice
+    (d+1) A*_d, with (d+1)^(d - 1/2) volume per point; the embedding stretches the normalised feature
+    f_i / sigma_i by sqrt(2/3) (d+1) in every direction.  Hence (3/2)^(d/2) / sqrt(d+1) prod sigma_i.
+    The uncustomised filter's blur keeps the mass of the vertex values ([1/4, 1/2, 1/4] along each
+    direction) and scales the output by 1 / (1 + 2^-d)."""
+    s = np.asarray(sigmas, dtype=np.float64)
+    d = len(s)
+    h = 1.5 ** (d / 2.0) / math.sqrt(d + 1.0) * float(np.prod(s))
+    return h * blur_output_scale(d) if blurred else h
+
+
+def outlier_constant(w: float, n_obs: int, n_model: int, sigmas, blurred: bool = False) -> float:
+    """c of Eq. (7) in the units of the lattice sums.  Eq. (4) sets the uniform component beside
+    Gaussian PDFs of unit mass and Eq. (7) gives c = w/(1-w) N/M against their sum; the lattice
+    sum M0 = sum_k K(x, y_k) uses a kernel of mass kernel_mass(sigmas) per observation instead, so
+    the posterior weight M0 / (M0 + c) keeps its meaning with c = w/(1-w) N/M kernel_mass.
+    sigmas: every feature dimension's width (feature_sigmas)."""
     if n_model == 0 or w <= 0.0:
         return 0.0
-    s = np.asarray(sigma, dtype=np.float64)
-    return float(w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** 1.5 * s[0] * s[1] * s[2])
+    return float(w / (1.0 - w) * (n_obs / n_model) * kernel_mass(sigmas, blurred))
 
 
 # ---------------------------------------------------------------------------
@@ -356,11 +375,11 @@ class Degenerate(RuntimeError):
     """The normal equations are not positive definite (no support or rank-deficient)."""
 
 
-# The rigid Gauss-Newton step (Eq. 17) exists only for an invertible A.  The GPU
-# sums A from binary32 tile sums, whose rounding can leave a singular A (all
-# supported points on one plane under point-to-plane: rank 3) with positive
-# pivots up to about 6e-5 of the diagonal; both sides take a Cholesky pivot at
-# or below this fraction of its diagonal entry as singular.
+# The Gauss-Newton step (Eq. 17) exists only for an invertible A, and invertibility is decided at the
+# precision A is known to: its per-point terms are binary32 values summed in binary32 over tiles of 1024
+# points, so an entry carries rounding of up to about 1024 * 2^-24 = 6.1e-5 of the diagonal scale.  A
+# Cholesky pivot L_jj^2 (the part of A_jj the earlier directions leave unexplained) at or below 1e-4 A_jj
+# cannot be told from zero: the direction is numerically unobservable and the system counts as singular.
 RIGID_PIVOT_TOL = 1e-4
 
 
@@ -397,7 +416,7 @@ def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n
     T <- Exp(-A^-1 b) T.  Returns the float64 pose."""
     T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
     if c is None:
-        c = outlier_constant(w, len(obs), len(model), sigma)
+        c = outlier_constant(w, len(obs), len(model), feature_sigmas(feat, sigma, sigma_n))
     sig_m = float(np.mean(sigma))
     lat = lattice if lattice is not None else build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n)
     model = np.asarray(model, dtype=np.float32)
@@ -459,7 +478,7 @@ def register_rigid_sigma(model, model_n, obs, obs_n, *, feat, residual, sigma0, 
         sv = [sig, sig, sig]
         lat = lattice_build(features(obs, obs_n, feat), splat_values(obs, obs_n, residual, m2=True),
                             scale_factors(feature_sigmas(feat, sv, sigma_n)))
-        c = outlier_constant(w, len(obs), len(model), sv)
+        c = outlier_constant(w, len(obs), len(model), feature_sigmas(feat, sv, sigma_n))
         mat = pose_to_mat12(T)
         x32 = transform_f32(mat, model)
         n32 = transform_f32(mat, model_n, translate=False) if feat == 6 else None
@@ -484,7 +503,7 @@ def register_rigid_blurred(model, model_n, obs, obs_n, *, feat, residual, sigma,
     Gauss-Newton step as in register_rigid.  Returns the float64 pose."""
     T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
     if c is None:
-        c = outlier_constant(w, len(obs), len(model), sigma)
+        c = outlier_constant(w, len(obs), len(model), feature_sigmas(feat, sigma, sigma_n), blurred=True)
     sig_m = float(np.mean(sigma))
     k = scale_factors(feature_sigmas(feat, sigma, sigma_n))
     model = np.asarray(model, dtype=np.float32)
@@ -504,11 +523,9 @@ def register_rigid_blurred(model, model_n, obs, obs_n, *, feat, residual, sigma,
 
 
 def feature_outlier_constant(w: float, n_obs: int, n_model: int, sigma_f: float, dim: int) -> float:
-    """c of Eq. (7) for a kernel over `dim` feature dimensions of width sigma_f (Eq. 8): the uniform
-    term over the dropped Gaussian normaliser (2 pi)^(dim/2) sigma_f^dim."""
-    if n_model == 0 or w <= 0.0:
-        return 0.0
-    return float(w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** (dim / 2.0) * sigma_f ** dim)
+    """c of Eq. (7) for a kernel over `dim` descriptor dimensions of width sigma_f (Eq. 8): the rule of
+    outlier_constant with the descriptor lattice's kernel mass."""
+    return outlier_constant(w, n_obs, n_model, np.full(dim, float(sigma_f)))
 
 
 def feature_lattice(obs, obs_feat, sigma_f: float) -> Lattice:

@@ -21,8 +21,8 @@ import dataclasses
 
 import numpy as np
 
-from . import residuals_and_jacobians, se3_exp, gn_step, estep, pose_to_mat12, transform_f32, \
-    build_observation_lattice, outlier_constant
+from . import residuals_and_jacobians, se3_exp, gn_step, estep, pose_to_mat12, transform_f32, RIGID_PIVOT_TOL, \
+    build_observation_lattice, outlier_constant, feature_sigmas
 
 
 @dataclasses.dataclass
@@ -151,7 +151,7 @@ def register_articulated(tree: Tree, x_ref, n_ref, body_offsets, obs, obs_n, *, 
     binary32 body transforms, Alg. 1 normal equations, theta += -A^-1 b."""
     theta = np.zeros(tree.n_dof) if theta0 is None else np.array(theta0, dtype=np.float64)
     if c is None:
-        c = outlier_constant(w, len(obs), len(x_ref), sigma)
+        c = outlier_constant(w, len(obs), len(x_ref), feature_sigmas(feat, sigma, sigma_n))
     sig_m = float(np.mean(sigma))
     lat = build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n)
     x_ref = np.asarray(x_ref, dtype=np.float32)
@@ -170,7 +170,7 @@ def register_articulated(tree: Tree, x_ref, n_ref, body_offsets, obs, obs_n, *, 
             x64[sl] = x_ref[sl].astype(np.float64) @ R[:, :3].T + R[:, 3]
         m0, m1, ns = estep(lat, x32, n32, feat, residual)
         A, b = normal_equations_alg1(tree, theta, x64, body_offsets, m0, m1, ns, c, sig_m, residual)
-        dth = gn_step(*hold_unsupported(A, b))
+        dth = gn_step(*hold_unsupported(A, b), RIGID_PIVOT_TOL)
         theta = theta + dth
         if history is not None:
             history.append(dict(A=A, b=b, dtheta=dth, theta=theta.copy()))

@@ -21,7 +21,8 @@ import dataclasses
 
 import numpy as np
 
-from . import residuals_and_jacobians, se3_exp, gn_step, estep, build_observation_lattice, outlier_constant, skew
+from . import residuals_and_jacobians, se3_exp, gn_step, estep, build_observation_lattice, outlier_constant, skew, \
+    feature_sigmas
 
 
 @dataclasses.dataclass
@@ -168,7 +169,7 @@ def register_nodegraph(graph: Graph, x_ref, n_ref, obs, obs_n, *, feat=3, residu
     K = len(graph.nodes)
     T = np.repeat(np.eye(4)[None], K, 0) if T0 is None else np.array(T0, dtype=np.float64)
     if c is None:
-        c = outlier_constant(w, len(obs), len(x_ref), sigma)
+        c = outlier_constant(w, len(obs), len(x_ref), feature_sigmas(feat, sigma, sigma_n))
     sig_m = float(np.mean(sigma))
     lat = build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n)
     for _ in range(iters):

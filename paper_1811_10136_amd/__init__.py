@@ -12,7 +12,6 @@ been built (``python -m paper_1811_10136_amd.build``); there is no fallback.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import List, Optional, Sequence
 
@@ -499,14 +498,6 @@ class Lattice:
             self.close()
         except Exception:
             pass
-
-
-def outlier_constant(w: float, n_obs: int, n_model: int, sigma) -> float:
-    """c of Eq. (7) in un-normalised kernel units: w/(1-w) N/M (2 pi)^(3/2) sigma_x sigma_y sigma_z."""
-    if n_model == 0 or w <= 0:
-        return 0.0
-    s = list(sigma) if hasattr(sigma, "__len__") else [sigma] * 3
-    return w / (1.0 - w) * (n_obs / n_model) * (2.0 * math.pi) ** 1.5 * s[0] * s[1] * s[2]
 
 
 def register_params(feat: int, residual: str, sigma, sigma_n=0.5, iters=20, w=0.1, c=None, tol=1e-6,

@@ -248,15 +248,34 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
 bool ctx_ok(const fr_ctx *c) { return c != nullptr && c->magic == kCtxMagic; }
 static bool lat_ok(const fr_lattice *l) { return l != nullptr && l->magic == kLatMagic; }
 
-// Outlier constant c of Eq. 7 in un-normalised kernel units: the uniform term
-// w/(1-w) (1/M) over the Gaussian normaliser (2 pi)^(-3/2) / (sigma_x sigma_y
-// sigma_z) of the N observation components.
-double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns)
+// Integral over feature space of the lattice kernel of one observation,
+// K(x, y) = sum_v b_v(x) b_v(y) (splat and slice of Sec. 4.2), for d feature
+// dimensions of widths sig[0..d-1].  The vertex hats sum to one everywhere and
+// are congruent, so each integrates to the volume per vertex, and so does K
+// over x: the vertices form the scaled lattice (d+1) A*_d, (d+1)^(d - 1/2) of
+// volume per point, reached from the normalised features by a uniform stretch
+// of sqrt(2/3) (d+1); hence (3/2)^(d/2) / sqrt(d+1) prod sig_i.  The blur of
+// the uncustomised filter keeps the vertex mass and scales the output by
+// 1 / (1 + 2^-d).
+static double kernel_mass(int d, const double *sig, bool blurred)
+{
+    double h = std::pow(1.5, 0.5 * d) / std::sqrt(d + 1.0);
+    for (int i = 0; i < d; ++i) h *= sig[i];
+    return blurred ? h / (1.0 + std::ldexp(1.0, -d)) : h;
+}
+
+// Outlier constant c of Eq. 7 in the units of the lattice sums: Eq. 4 sets the
+// uniform component beside Gaussian PDFs of unit mass, and c = w/(1-w) N/M is
+// taken against their sum; M0 sums a kernel of mass kernel_mass per
+// observation instead, so the weight M0 / (M0 + c) keeps its meaning with c
+// scaled by that mass (every feature dimension: position and, for d = 6,
+// normal widths).
+double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns, bool blurred)
 {
     if (c_override >= 0.0) return c_override;
     if (!(Ms > 0) || !(w > 0.0)) return 0.0;
-    const double s3 = lp.sigma[0] * lp.sigma[1] * lp.sigma[2];
-    return w / (1.0 - w) * (Ns / Ms) * std::pow(2.0 * M_PI, 1.5) * s3;
+    double sig[6] = {lp.sigma[0], lp.sigma[1], lp.sigma[2], lp.sigma_n, lp.sigma_n, lp.sigma_n};
+    return w / (1.0 - w) * (Ns / Ms) * kernel_mass(lp.feat == 6 ? 6 : 3, sig, blurred);
 }
 
 fr_status check_lattice_params(const fr_lattice_params *p)
@@ -407,12 +426,15 @@ static fr_status feature_lattice_impl(fr_ctx *ctx, const fr_cloud *obs, const fl
     return FR_OK;
 }
 
-// c of Eq. 7 for a kernel over dim descriptor dimensions of width sigma_f.
+// c of Eq. 7 for a kernel over dim descriptor dimensions of width sigma_f:
+// the rule of outlier_constant with the descriptor lattice's kernel mass.
 static double feature_outlier_constant(double w, double c_override, double Ms, double Ns, double sigma_f, int dim)
 {
     if (c_override >= 0.0) return c_override;
     if (!(Ms > 0) || !(w > 0.0)) return 0.0;
-    return w / (1.0 - w) * (Ns / Ms) * std::pow(2.0 * M_PI, 0.5 * dim) * std::pow(sigma_f, (double)dim);
+    double sig[64];
+    for (int i = 0; i < dim; ++i) sig[i] = sigma_f;
+    return w / (1.0 - w) * (Ns / Ms) * kernel_mass(dim, sig, false);
 }
 
 static fr_status check_features(const float *feat, int32_t dim, const char *what)
@@ -966,12 +988,12 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     auto t1 = clk::now();
     rep.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 
-    // per-set outlier constant (Eq. 7 in un-normalised kernel units)
+    // per-set outlier constant (Eq. 7 in the units of the lattice sums)
     std::vector<double> cset(S, 0.0);
     for (int32_t s = 0; s < S; ++s)
         cset[s] = outlier_constant(params->lattice, params->w, params->c_override,
                                    (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]),
-                                   (double)(obs->offsets[s + 1] - obs->offsets[s]));
+                                   (double)(obs->offsets[s + 1] - obs->offsets[s]), blurred);
     const double sig_m = (params->lattice.sigma[0] + params->lattice.sigma[1] + params->lattice.sigma[2]) / 3.0;
 
     const bool fused = (params->flags & FR_FUSED) != 0;

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "fr_internal.h"
+#include "fr_mstep.h"
 
 namespace fr {
 
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
                                                                   double *step_norm, int32_t *status)
 {
     __shared__ double s_th[kArtMaxDof], s_w[3 * kArtMaxDof], s_q[3 * kArtMaxDof], s_u[6 * kArtMaxDof];
-    __shared__ double s_A[kArtMaxDof * kArtMaxDof], s_rhs[kArtMaxDof], s_x[kArtMaxDof];
+    __shared__ double s_A[kArtMaxDof * kArtMaxDof], s_rhs[kArtMaxDof], s_x[kArtMaxDof], s_dg[kArtMaxDof];
     __shared__ double s_R[9 * kArtMaxBodies], s_T[3 * kArtMaxBodies], s_Q[9 * kArtMaxDof];
     // per-body sums and the DOF masks, staged once: the assembly loops read
     // them for every (DOF, DOF) entry and body
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
                 s_A[k * n + k] = 1.0;
                 s_rhs[k] = 0.0;
             }
+            s_dg[k] = s_A[k * n + k];
         }
         __syncthreads();
         // Cholesky A = L L^T in place (lower triangle), right-looking: column j
@@ -207,8 +209,11 @@ __global__ void __launch_bounds__(kArtThreads) k_articulated_step(ArtTree tree, 
         // left-looking form
         for (int j = 0; j < n; ++j) {
             if (tid == 0) {
+                // a pivot at most kPivotTol of its diagonal entry is a numerically
+                // unobservable direction at the precision of the binary32 sums (as
+                // the rigid solve)
                 double v = s_A[j * n + j];
-                if (!(v > 0.0)) {
+                if (!(v > kPivotTol * s_dg[j])) {
                     s_ok = 0;
                     v = 1.0;
                 }

@@ -130,7 +130,10 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
                              fr_lattice **out, const double *sigma_set = nullptr,
                              const fr_cloud *joint_model = nullptr, const float *joint_mats = nullptr);
 void scale_factors(const fr_lattice_params *p, float *k);
-double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns);
+// c of Eq. 7 in the units of the lattice sums (w/(1-w) N/M times the kernel's
+// mass over feature space; blurred: the uncustomised filter's kernel).
+double outlier_constant(const fr_lattice_params &lp, double w, double c_override, double Ms, double Ns,
+                        bool blurred = false);
 void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle = false);
 void dev_release_cache(fr_ctx *ctx);
 

@@ -11,6 +11,14 @@ namespace fr {
 constexpr int kRedVals = 32;      // 21 JtJ (upper, row-major) + 6 Jtr + 4 statistics + variance term
 constexpr int kRedStride = 32;    // floats per partial row
 
+// Numerical-rank rule of the Gauss-Newton solves (Eq. 17 needs an invertible
+// A): A is summed from binary32 per-point terms over tiles of 1024 points, so
+// an entry carries rounding of up to about 1024 * 2^-24 = 6.1e-5 of the
+// diagonal scale; a Cholesky pivot (the part of A_jj the earlier directions do
+// not explain) at or below 1e-4 of A_jj is indistinguishable from zero and
+// its direction counts as unobservable.
+constexpr double kPivotTol = 1e-4;
+
 __host__ __device__ constexpr int ut_index(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
 
 template <int NR>

@@ -4,6 +4,7 @@
 // composes it on the left of the set's pose; it also refreshes the binary32
 // [R | t] the next E-step reads.
 #include "fr_internal.h"
+#include "fr_mstep.h"
 
 namespace fr {
 
@@ -45,13 +46,6 @@ __device__ inline void se3_exp(const double (&z)[6], double (&E)[3][4])
     }
 }
 
-// Relative pivot below which the 6x6 normal equations count as singular.
-// A is summed from binary32 sums over tiles of 1024 points, each rounded to
-// about 1024 * 2^-24 = 6e-5 of its absolute sum at worst, so a rank-deficient
-// A (all supported points on one plane under point-to-plane: rank 3) can come
-// out with positive pivots of that relative size; well-posed systems of the
-// depth workloads keep every pivot above 8e-2 of its diagonal entry.
-constexpr double kRigidPivotTol = 1e-4;
 
 __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses,
                                                     float *mats, double *twist_norm, int32_t *status,
@@ -75,7 +69,7 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
         for (int i = 0; i < 6; ++i) b[i] = jtr[(size_t)s * 6 + i];
     }
     // Cholesky A = L L^T (in the lower triangle of A); a pivot at most
-    // kRigidPivotTol times its diagonal entry marks A as singular
+    // kPivotTol times its diagonal entry marks A as singular
     double d0[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) d0[j] = A[j][j];
@@ -85,7 +79,7 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
         double sum = A[j][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) sum -= A[j][k] * A[j][k];
-        ok = ok && (sum > 0.0) && (sum > kRigidPivotTol * d0[j]);
+        ok = ok && (sum > 0.0) && (sum > kPivotTol * d0[j]);
         const double ljj = sqrt(ok ? sum : 1.0);
         A[j][j] = ljj;
 #pragma unroll

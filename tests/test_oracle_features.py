@@ -28,13 +28,6 @@ def test_descriptor_splat_slice_equals_brute_force(dim):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
 
 
-def test_feature_outlier_constant_reduces_to_the_position_case():
-    c3 = oracle.feature_outlier_constant(0.2, 900, 1000, 0.03, 3)
-    assert c3 == pytest.approx(oracle.outlier_constant(0.2, 900, 1000, [0.03, 0.03, 0.03]), rel=1e-14)
-    assert oracle.feature_outlier_constant(0.0, 900, 1000, 0.05, 16) == 0.0
-    assert oracle.feature_outlier_constant(0.5, 10, 10, 0.05, 16) == pytest.approx((2 * math.pi) ** 8 * 0.05 ** 16)
-
-
 @pytest.mark.parametrize("seed", [3, 4])
 def test_descriptors_recover_large_rotations(seed):
     p = synth.feature_pair(seed, m=6000, dim=16)

@@ -178,8 +178,35 @@ def test_three_planes_pass_the_pivot_rule():
     np.testing.assert_allclose(A @ x, -np.ones(6), rtol=0, atol=1e-9 * np.abs(A).max())
 
 
-def test_outlier_constant_formula():
-    # c = w/(1-w) N/M in PDF units times (2 pi)^(3/2) sigma^3 for un-normalised kernel sums
-    c = oracle.outlier_constant(0.5, 200, 100, (0.1, 0.1, 0.1))
-    assert math.isclose(c, 2.0 * (2 * math.pi) ** 1.5 * 1e-3, rel_tol=1e-14)
+def test_pivot_rule_threshold_on_designed_systems():
+    # A = L L^T with unit diagonal and one chosen relative pivot L_jj^2 / A_jj at the last position:
+    # 1e-3 passes (the step solves A x = -b), 1e-5 is refused, as is 1e-4 itself (at or below the rule)
+    rng = np.random.default_rng(3)
+    for rel, ok in ((1e-3, True), (2e-4, True), (1e-4, False), (1e-5, False)):
+        for _ in range(5):
+            u = rng.normal(size=5)
+            u /= np.linalg.norm(u)
+            L = np.zeros((6, 6))
+            L[:5, :5] = np.eye(5)
+            L[5, :5] = u * math.sqrt(1.0 - rel)
+            L[5, 5] = math.sqrt(rel)
+            A = L @ L.T
+            assert np.isclose(np.linalg.cholesky(A)[5, 5] ** 2 / A[5, 5], rel, rtol=1e-9)
+            b = rng.normal(size=6)
+            if ok:
+                x = oracle.gn_step(A, b, oracle.RIGID_PIVOT_TOL)
+                np.testing.assert_allclose(A @ x, -b, atol=1e-9)
+            else:
+                with pytest.raises(oracle.Degenerate):
+                    oracle.gn_step(A, b, oracle.RIGID_PIVOT_TOL)
+                oracle.gn_step(A, b)          # positive definite: only the rule refuses it
+
+
+def test_outlier_constant_zero_cases():
     assert oracle.outlier_constant(0.0, 10, 10, (1, 1, 1)) == 0.0
+    assert oracle.outlier_constant(0.3, 10, 0, (1, 1, 1)) == 0.0
+    # linear in N/M and in every width; w/(1-w) in w
+    c = oracle.outlier_constant(0.5, 200, 100, (0.1, 0.2, 0.3))
+    assert math.isclose(oracle.outlier_constant(0.5, 400, 100, (0.1, 0.2, 0.3)), 2 * c, rel_tol=1e-14)
+    assert math.isclose(oracle.outlier_constant(0.5, 200, 100, (0.2, 0.2, 0.3)), 2 * c, rel_tol=1e-14)
+    assert math.isclose(oracle.outlier_constant(0.75, 200, 100, (0.1, 0.2, 0.3)), 3 * c, rel_tol=1e-14)

@@ -100,3 +100,91 @@ def test_nodegraph_recovers_a_rigid_motion_exactly():
     T = ng.register_nodegraph(g, p.model, None, p.obs, None, sigma=p.sigma, c=0.0, lam=1.0, iters=12, T0=T0)
     for k in range(K):
         np.testing.assert_allclose(T[k], T_gt, atol=1e-6)
+
+
+def _regulariser_energy(g, T, lam, sigma):
+    """lam sum over directed edges (j, k) of |(T_j p_k - T_k p_k) / sigma|^2 (Eq. 21's regulariser)."""
+    E = 0.0
+    for j, k in g.edges:
+        pk = g.nodes[k]
+        e = (T[j][:3, :3] @ pk + T[j][:3, 3] - T[k][:3, :3] @ pk - T[k][:3, 3]) / sigma
+        E += lam * float(e @ e)
+    return E
+
+
+def _spread_nodes(seed, K=10):
+    """A small graph and node transforms that all differ (no agreement anywhere)."""
+    p = synth.nodegraph_pair(seed, m=400, n_nodes=K)
+    g = _graph(p)
+    rng = np.random.default_rng(seed + 100)
+    T = np.stack([synth.random_motion(rng, 0.4, 0.1) for _ in range(K)])
+    return p, g, T
+
+
+def _regulariser_blocks(g, T, lam, sigma):
+    """node_blocks with no supported point: only the regulariser's A and b remain."""
+    x = np.zeros((3, 3))
+    z = np.zeros(3)
+    g0 = ng.Graph(g.nodes, np.zeros((3, 4), np.int32), np.full((3, 4), 0.25), g.edges)
+    return ng.node_blocks(g0, T, x, z, np.zeros((3, 3)), None, 1.0, sigma, "pt2pt", lam)
+
+
+def test_regulariser_b_is_half_the_energy_gradient_away_from_agreement():
+    """b of the linearised regulariser is J^T e: half the gradient of the energy in the node twists
+    (left-multiplied, T_k <- Exp(zeta_k) T_k), checked by central differences of the energy at unequal
+    node transforms.  A flipped residual sign or b term, or a Jacobian taken at the other end of an
+    edge, fails it."""
+    lam, sigma = 1.7, 0.02
+    p, g, T = _spread_nodes(6)
+    K = len(g.nodes)
+    _, b = _regulariser_blocks(g, T, lam, sigma)
+    h = 1e-6
+    grad = np.zeros(6 * K)
+    for k in range(K):
+        for q in range(6):
+            z = np.zeros(6)
+            z[q] = h
+            Tp, Tm = T.copy(), T.copy()
+            Tp[k] = oracle.se3_exp(z) @ T[k]
+            Tm[k] = oracle.se3_exp(-z) @ T[k]
+            grad[6 * k + q] = (_regulariser_energy(g, Tp, lam, sigma) - _regulariser_energy(g, Tm, lam, sigma)) / (2 * h)
+    assert np.abs(b).max() > 1.0
+    np.testing.assert_allclose(b, 0.5 * grad, rtol=1e-6, atol=1e-6 * np.abs(grad).max())
+
+
+def test_regulariser_gauss_newton_matrix_from_finite_difference_jacobians():
+    """A of the regulariser is lam sum J^T J with J the derivative of each edge residual in the twists of
+    both end nodes, evaluated at unequal transforms by central differences of the residual itself."""
+    lam, sigma = 0.6, 0.03
+    p, g, T = _spread_nodes(7)
+    K = len(g.nodes)
+    A, _ = _regulariser_blocks(g, T, lam, sigma)
+    h = 1e-6
+    Afd = np.zeros((6 * K, 6 * K))
+    for j, k in g.edges:
+        pk = g.nodes[k]
+
+        def res(Tj, Tk):
+            return (Tj[:3, :3] @ pk + Tj[:3, 3] - Tk[:3, :3] @ pk - Tk[:3, 3]) / sigma
+        J = np.zeros((3, 6 * K))
+        for node in (j, k):
+            for q in range(6):
+                z = np.zeros(6)
+                z[q] = h
+                Tp, Tm = T.copy(), T.copy()
+                Tp[node] = oracle.se3_exp(z) @ T[node]
+                Tm[node] = oracle.se3_exp(-z) @ T[node]
+                J[:, 6 * node + q] += (res(Tp[j], Tp[k]) - res(Tm[j], Tm[k])) / (2 * h)
+        Afd += lam * J.T @ J
+    np.testing.assert_allclose(A, Afd, rtol=1e-6, atol=1e-6 * np.abs(Afd).max())
+
+
+def test_regulariser_step_reduces_its_energy():
+    """One Gauss-Newton step of the regulariser alone (anchored by a tiny ridge) lowers the energy."""
+    lam, sigma = 1.0, 0.02
+    p, g, T = _spread_nodes(8)
+    K = len(g.nodes)
+    A, b = _regulariser_blocks(g, T, lam, sigma)
+    dz = np.linalg.solve(A + 1e-9 * np.abs(A).max() * np.eye(6 * K), -b).reshape(K, 6)
+    T1 = np.stack([oracle.se3_exp(0.5 * dz[k]) @ T[k] for k in range(K)])
+    assert _regulariser_energy(g, T1, lam, sigma) < 0.5 * _regulariser_energy(g, T, lam, sigma)
