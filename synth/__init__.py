@@ -204,7 +204,7 @@ def _render(scene: _Scene, width: int, height: int, f: float, cx: float, cy: flo
         den = ds @ n
         with np.errstate(divide="ignore", invalid="ignore"):
             s = (off - o @ n) / den
-        p = o + s[:, None] * ds
+            p = o + s[:, None] * ds
         ok = (s > 1e-6) & np.all((p >= lo) & (p <= hi), axis=1) & (s < best)
         best = np.where(ok, s, best)
         nrm[ok] = n
