@@ -423,6 +423,28 @@ typedef struct {
 } fr_node_graph;
 
 /*
+ * Node-graph M-step (Sec. 5.2, Eq. 21: the Gauss-Newton normal equations of
+ * Eq. 17 in the node twists) at one EM iteration: x is the model moved by the
+ * node graph (one set, device; normals not used), m0/m1/nsum the E-step at it
+ * (fr_estep with FR_XF_NONE; nsum for FR_PT2PL only), node_T_h (host,
+ * n_nodes x 16 row-major) the node transforms the regulariser is linearised
+ * at, params->c/sigma/residual as in fr_mstep_reduce (normalize_n must be 0,
+ * c_per_set is not used).  The system is block sparse: a 6x6 block for every
+ * node pair (k <= l) that shares a model point's skinning or an edge, and for
+ * every node with itself, ordered by k * n_nodes + l.  Block (k, l) holds
+ *   sum_i w_ki w_li J_i^T J_i / sigma^2 (+ the regulariser's lambda J^T J terms)
+ * and rhs node k holds sum_i w_ki J_i^T r_i / sigma^2 + lambda J_k^T e, with
+ * J_i, r_i the rigid twist terms of fr_mstep_reduce at x_i and e the edge
+ * residual of fr_node_graph.  With blocks == NULL only *n_blocks is written;
+ * otherwise block_nodes_h (host, 2 x n_blocks int32: k, l), blocks (device,
+ * n_blocks x 36 float64, row-major, rows of node k) and rhs (device, 6 n_nodes
+ * float64) receive the system.  Synchronises.
+ */
+fr_status fr_mstep_reduce_nodes(fr_ctx *ctx, const fr_cloud *x, const float *m0, const float *m1, const float *nsum,
+                                const fr_node_graph *graph, const double *node_T_h, const fr_mstep_params *params,
+                                int64_t *n_blocks, int32_t *block_nodes_h, double *blocks, double *rhs, void *stream);
+
+/*
  * Node-graph registration of one model set onto one observation set: per EM
  * iteration the model is warped on the device (binary64 blend, binary32
  * output), sliced, reduced into the block-sparse node system, which is solved
@@ -430,6 +452,9 @@ typedef struct {
  * residual 1e-10, at most 2000 iterations), and every node is updated by
  * T_k <- Exp(dzeta_k) T_k.  node_T_inout_h (host, n_nodes x 16 row-major)
  * holds the start transforms and receives the result.  Synchronous.
+ * FR_EDEGENERATE when a node's diagonal block is singular (a node that skins
+ * no supported point and has no regulariser edge, or lambda = 0); the nodes
+ * keep the transforms of the iteration before.
  */
 fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_node_graph *graph,
                                 const fr_register_params *params, double *node_T_inout_h, fr_report *report_h,
@@ -451,7 +476,10 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
  * so a build overlaps the steps already queued; a step that includes a newly
  * admitted slot waits for that slot's build on the device, not on the host.
  * Results are bitwise those of fr_register on the same pair alone (sorted
- * splat; same iteration count and FR_FUSED setting).  One host thread at a time per engine.
+ * splat; same iteration count, twist tolerance and FR_FUSED setting).  A slot
+ * stops on the device (twist_tol, or a degenerate step): steps that still list
+ * it leave it unchanged, so the host may learn of the stop a few steps late
+ * (fr_engine_read) without changing the result.  One host thread at a time per engine.
  */
 typedef struct fr_engine fr_engine;
 
@@ -464,6 +492,9 @@ typedef struct {
     double c_override;          /* >= 0: this c for every request; < 0: derive from w */
     int32_t flags;              /* FR_FUSED: as fr_register with FR_FUSED */
     int32_t reserved;           /* must be 0 */
+    double twist_tol;           /* > 0: a slot stops (its later steps do nothing) after a step whose
+                                   |omega| and |v| are both below it (Sec. 6.1); <= 0: only a degenerate
+                                   step stops a slot */
 } fr_engine_params;
 
 /* Create an engine; allocates the point arena (52 bytes per point for d = 6
@@ -492,12 +523,21 @@ fr_status fr_engine_admit(fr_engine *eng, int32_t n, const int32_t *slots_h, con
  * n occupied slots listed in slots_h (host), enqueued on the engine stream. */
 fr_status fr_engine_step(fr_engine *eng, int32_t n, const int32_t *slots_h);
 
-/* Enqueue a copy of every slot's pose (max_slots x 16 float64, row-major) and
- * status (max_slots int32: FR_OK or FR_EDEGENERATE of its last solve, or
- * FR_ERANGE if one of its E-steps saw a lattice coordinate out of range; the
- * flag is cleared when the slot is admitted again) into host memory; pinned
- * host memory makes it asynchronous. */
-fr_status fr_engine_read(fr_engine *eng, double *poses_h, int32_t *status_h);
+/* Progress of a slot since its admission. */
+typedef struct {
+    int32_t status;       /* FR_OK or FR_EDEGENERATE of its last solve, or FR_ERANGE if one of its
+                             E-steps saw a lattice coordinate out of range */
+    int32_t iterations;   /* EM iterations (solves) the slot has run */
+    int32_t stopped;      /* 1: the slot has stopped -- its last step was degenerate or below
+                             twist_tol -- and later steps leave it unchanged */
+    int32_t reserved;
+} fr_slot_state;
+
+/* Enqueue a copy of every slot's pose (poses_h: max_slots x 16 float64,
+ * row-major, or NULL to skip) and state (state_h: max_slots entries) into host
+ * memory; pinned host memory makes it asynchronous.  The state of a slot is
+ * reset when it is admitted. */
+fr_status fr_engine_read(fr_engine *eng, double *poses_h, fr_slot_state *state_h);
 
 /* Free n slots.  Their arena ranges may be admitted again at once; a lattice
  * is freed (ordered after the queued steps) when its last slot is released. */

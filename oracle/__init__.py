@@ -410,10 +410,12 @@ def build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n):
 
 def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n=0.5, c=None, w=0.1,
                    iters=20, T0=None, lattice: Optional[Lattice] = None, normalize_n=False,
-                   history: Optional[list] = None):
-    """Rigid FilterReg: build the observation lattice once, then `iters` EM iterations of
+                   history: Optional[list] = None, twist_tol: Optional[float] = None, info: Optional[dict] = None):
+    """Rigid FilterReg: build the observation lattice once, then up to `iters` EM iterations of
     E-step (slice at the pinned binary32 transform of the model) and one Gauss-Newton step
-    T <- Exp(-A^-1 b) T.  Returns the float64 pose."""
+    T <- Exp(-A^-1 b) T.  With twist_tol, the loop ends after the first step whose rotation and
+    translation parts both have norm below it (Sec. 6.1 terminates on a small twist); info, if
+    given, receives the number of steps taken.  Returns the float64 pose."""
     T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
     if c is None:
         c = outlier_constant(w, len(obs), len(model), feature_sigmas(feat, sigma, sigma_n))
@@ -432,6 +434,10 @@ def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n
         T = se3_exp(dz) @ T
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
+        if info is not None:
+            info["iterations"] = info.get("iterations", 0) + 1
+        if twist_tol is not None and np.linalg.norm(dz[:3]) < twist_tol and np.linalg.norm(dz[3:]) < twist_tol:
+            break
     return T
 
 

@@ -95,7 +95,12 @@ class fr_node_graph(ctypes.Structure):
 class fr_engine_params(ctypes.Structure):
     _fields_ = [("lattice", fr_lattice_params), ("residual", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("arena_points", ctypes.c_int64), ("w", ctypes.c_double), ("c_override", ctypes.c_double),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32), ("twist_tol", ctypes.c_double)]
+
+
+# fr_slot_state: status, iterations, stopped, reserved (int32 each); a host array of these is an
+# int32 array of shape (max_slots, 4)
+SLOT_STATUS, SLOT_ITERATIONS, SLOT_STOPPED = 0, 1, 2
 
 
 class fr_report(ctypes.Structure):
@@ -157,6 +162,8 @@ _sig("fr_register_nodegraph", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER
 _sig("fr_register_articulated", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_kinematic_tree),
                                       ctypes.POINTER(fr_register_params), _P, ctypes.POINTER(fr_report), _P])
+_sig("fr_mstep_reduce_nodes", _st, [_P, ctypes.POINTER(fr_cloud), _P, _P, _P, ctypes.POINTER(fr_node_graph), _P,
+                                    ctypes.POINTER(fr_mstep_params), ctypes.POINTER(ctypes.c_int64), _P, _P, _P, _P])
 _sig("fr_engine_create", _st, [_P, ctypes.POINTER(fr_engine_params), _P, ctypes.POINTER(_P)])
 _sig("fr_engine_destroy", _st, [_P])
 _sig("fr_engine_admit", _st, [_P, _i32, _P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), _P, _P])
@@ -169,7 +176,7 @@ ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy
                  "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
                  "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
-                 "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph",
+                 "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph", "fr_mstep_reduce_nodes",
                  "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
                  "fr_engine_release"]
 
@@ -615,6 +622,27 @@ def fr_register_nodegraph(ctx, model: Cloud, obs: Cloud, graph: NodeGraph, param
     return st, rep
 
 
+def fr_mstep_reduce_nodes(ctx, x: Cloud, m0, m1, nsum, graph: NodeGraph, node_T: np.ndarray, residual: int,
+                          c: float, sigma: float, stream=None):
+    """Node-graph normal equations at the moved points x (one set): returns (block_nodes (n_blocks, 2) int32,
+    blocks (n_blocks, 6, 6) float64 device tensor, rhs (6 n_nodes,) float64 device tensor)."""
+    torch = _torch()
+    T = np.ascontiguousarray(node_T, dtype=np.float64).reshape(-1)
+    prm = fr_mstep_params(residual, 0, float(c), float(sigma), None)
+    nb = ctypes.c_int64(0)
+    _check(_lib.fr_mstep_reduce_nodes(ctx, x.c(), _ptr(m0), _ptr(m1), _ptr(nsum), graph.c(), T.ctypes.data,
+                                      ctypes.byref(prm), ctypes.byref(nb), None, None, None, _stream(stream)))
+    n = int(nb.value)
+    kl = np.zeros((max(n, 1), 2), dtype=np.int32)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    blocks = torch.empty((max(n, 1), 6, 6), dtype=torch.float64, device=dev)
+    rhs = torch.empty(6 * graph.n_nodes, dtype=torch.float64, device=dev)
+    _check(_lib.fr_mstep_reduce_nodes(ctx, x.c(), _ptr(m0), _ptr(m1), _ptr(nsum), graph.c(), T.ctypes.data,
+                                      ctypes.byref(prm), ctypes.byref(nb), kl.ctypes.data, _ptr(blocks), _ptr(rhs),
+                                      _stream(stream)))
+    return kl[:n], blocks[:n], rhs
+
+
 # --- serving engine ------------------------------------------------------------
 def _i32_array(v):
     return np.ascontiguousarray(np.asarray(v, dtype=np.int32).reshape(-1))
@@ -643,10 +671,11 @@ def fr_engine_step(eng, slots):
     _check(_lib.fr_engine_step(eng, len(sl), sl.ctypes.data))
 
 
-def fr_engine_read(eng, poses_h, status_h):
-    """Enqueue the copy of all slot poses / statuses into host buffers (pinned torch tensors or numpy arrays)."""
-    pp = poses_h.data_ptr() if hasattr(poses_h, "data_ptr") else poses_h.ctypes.data
-    sp = status_h.data_ptr() if hasattr(status_h, "data_ptr") else status_h.ctypes.data
+def fr_engine_read(eng, poses_h, state_h):
+    """Enqueue the copy of all slot poses (max_slots x 16 float64, or None) and states (int32, max_slots x 4:
+    status, iterations, stopped, reserved) into host buffers (pinned torch tensors or numpy arrays)."""
+    pp = None if poses_h is None else (poses_h.data_ptr() if hasattr(poses_h, "data_ptr") else poses_h.ctypes.data)
+    sp = state_h.data_ptr() if hasattr(state_h, "data_ptr") else state_h.ctypes.data
     _check(_lib.fr_engine_read(eng, pp, sp))
 
 
@@ -656,11 +685,12 @@ def fr_engine_release(eng, slots):
 
 
 def engine_params(feat: int, residual: str, sigma, sigma_n=0.5, max_slots=256, arena_points=1 << 24, w=0.1,
-                  c=None, splat: int = FR_SPLAT_SORTED, fused=False) -> fr_engine_params:
+                  c=None, splat: int = FR_SPLAT_SORTED, fused=False, tol=0.0) -> fr_engine_params:
+    """tol > 0: a slot stops on the device after a step with |omega| and |v| below it."""
     values = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
     return fr_engine_params(lattice_params(feat, values, sigma, sigma_n, splat),
                             FR_PT2PL if residual == "pt2pl" else FR_PT2PT, int(max_slots), int(arena_points),
-                            float(w), -1.0 if c is None else float(c), FR_FUSED if fused else 0, 0)
+                            float(w), -1.0 if c is None else float(c), FR_FUSED if fused else 0, 0, float(tol))
 
 
 class Engine:
@@ -679,8 +709,8 @@ class Engine:
     def step(self, slots):
         fr_engine_step(self.h, slots)
 
-    def read(self, poses_h, status_h):
-        fr_engine_read(self.h, poses_h, status_h)
+    def read(self, poses_h, state_h):
+        fr_engine_read(self.h, poses_h, state_h)
 
     def release(self, slots):
         fr_engine_release(self.h, slots)

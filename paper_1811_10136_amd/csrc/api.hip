@@ -537,6 +537,8 @@ fr_status fr_ctx_destroy(fr_ctx *ctx)
     dev_release_cache(ctx);
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     ctx->graph_stream = nullptr;
+    if (ctx->pin_flags) (void)hipHostFree(ctx->pin_flags);
+    ctx->pin_flags = nullptr;
     ctx->magic = kDeadMagic;
     delete ctx;
     return FR_OK;
@@ -911,6 +913,21 @@ static fr_status graph_stream(fr_ctx *ctx, hipStream_t &gs)
     return FR_OK;
 }
 
+// Pinned host memory for n words of stop flags (kept by the context; the
+// previous contents are not needed once the caller's stream is idle).
+static fr_status pinned_flags(fr_ctx *ctx, size_t n, int32_t *&out)
+{
+    if (ctx->pin_flags_n < n) {
+        if (ctx->pin_flags) FR_HIP(hipHostFree(ctx->pin_flags));
+        ctx->pin_flags = nullptr;
+        ctx->pin_flags_n = 0;
+        FR_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->pin_flags), n * sizeof(int32_t), hipHostMallocDefault));
+        ctx->pin_flags_n = n;
+    }
+    out = ctx->pin_flags;
+    return FR_OK;
+}
+
 struct GraphGuard {
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
@@ -1002,7 +1019,7 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     if (!fused) FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
     const bool pl = params->residual == FR_PT2PL;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);
-    DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive;
+    DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive, witers;
     if (!fused) {
         FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
         FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
@@ -1017,67 +1034,95 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     FR_TRY(wtn.alloc(ctx, S * 2 * sizeof(double)));
     FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
     FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
+    FR_TRY(witers.alloc(ctx, S * sizeof(int32_t)));
     std::vector<float> mats_h((size_t)S * 12);
     for (int32_t s = 0; s < S; ++s)
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 4; ++j) mats_h[(size_t)s * 12 + 4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
-    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK);
+    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK), iters_v(S, 0);
     FR_HIP(hipMemcpyAsync(wpose.p, theta_inout_h, S * 16 * sizeof(double), hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(wmats.p, mats_h.data(), S * 12 * sizeof(float), hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
     FR_HIP(hipMemcpyAsync(wstatus.p, status_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    FR_HIP(hipMemcpyAsync(witers.p, iters_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
     FR_HIP(hipStreamSynchronize(st));
 
     const bool prof = (params->flags & FR_PROFILE_EVENTS) != 0;
     const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
     const int max_it = params->max_iters;
+    // Iteration control on the device: every solve clears the active flag of
+    // a set whose step degenerated or, without FR_FIXED_ITERS, fell below the
+    // twist tolerance (Sec. 6.1), and the kernels of later iterations skip that
+    // set.  The host never waits for an iteration: it enqueues blocks of 4 and,
+    // once the block before the last one has finished, reads its copy of the
+    // flags and stops enqueuing when no set is left.
+    const double tol = fixed ? -1.0 : params->twist_tol;
+    int32_t *act = wactive.as<int32_t>();
     std::vector<hipEvent_t> ev;
     if (prof) {
         ev.resize(3 * (size_t)max_it + 1);
         for (auto &e : ev) FR_HIP(hipEventCreate(&e));
     }
+    struct EventPair {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~EventPair()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } bev;
+    int32_t *pin = nullptr;
+    if (!fixed) {
+        FR_TRY(pinned_flags(ctx, 2 * (size_t)S, pin));
+        for (hipEvent_t &x : bev.e) FR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    }
+    int n_blocks = 0;
+    // after a block of iterations on stream q: copy the flags; false once the previous block's copy
+    // shows that every set has stopped
+    auto block_done = [&](hipStream_t q, bool &more) -> fr_status {
+        more = true;
+        if (fixed) return FR_OK;
+        const int b = n_blocks & 1;
+        FR_HIP(hipMemcpyAsync(pin + (size_t)b * S, act, S * sizeof(int32_t), hipMemcpyDeviceToHost, q));
+        FR_HIP(hipEventRecord(bev.e[b], q));
+        if (n_blocks > 0) {
+            FR_HIP(hipEventSynchronize(bev.e[b ^ 1]));
+            const int32_t *f = pin + (size_t)(b ^ 1) * S;
+            int32_t any = 0;
+            for (int32_t s = 0; s < S; ++s) any |= f[s];
+            more = any != 0;
+        }
+        ++n_blocks;
+        return FR_OK;
+    };
     // one EM iteration on stream q (without the profiling events)
     auto enqueue_iter = [&](hipStream_t q) -> fr_status {
         if (fused) {
             FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe, wmats.as<float>(),
-                                      params->residual, 0, part.as<float>(), q));
+                                      params->residual, 0, part.as<float>(), q, act));
             FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
                                        wstat.as<double>(), q));
         } else {
             FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
-                                wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, q));
+                                wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, q, nullptr, act));
             FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
                                  pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m, wjtj.as<double>(),
-                                 wjtr.as<double>(), wstat.as<double>(), part.as<float>(), q));
+                                 wjtr.as<double>(), wstat.as<double>(), part.as<float>(), q, nullptr, nullptr, act));
         }
         return launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
-                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), q);
-    };
-    // sets whose step fell below the twist tolerance (or degenerated) stop; returns the sets still active
-    auto check_active = [&](hipStream_t q, int &n_active) -> fr_status {
-        std::vector<double> tn((size_t)S * 2);
-        FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, q));
-        FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, q));
-        FR_HIP(hipStreamSynchronize(q));
-        n_active = 0;
-        for (int32_t s = 0; s < S; ++s) {
-            if (status_v[s] != FR_OK || (tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
-                active_h[s] = 0;
-            n_active += active_h[s];
-        }
-        FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, q));
-        return FR_OK;
+                                  wtn.as<double>(), wstatus.as<int32_t>(), act, q, act, tol, witers.as<int32_t>());
     };
     auto t2 = clk::now();
     int it = 0;
+    constexpr int kBlock = 4;
     if ((params->flags & FR_GRAPH) != 0 && !prof && !blurred && max_it > 0) {
-        // The iterations of a block (up to 32 with fixed iterations, the 4 between convergence checks
-        // otherwise) are captured once into a HIP graph and replayed: one launch per block instead of
-        // three or four per iteration.  Capture needs a stream of its own (the caller's may be
-        // the null stream); the caller's stream is idle here, and the block is waited for below.
+        // The iterations of a block (up to 32 with fixed iterations, 4 otherwise) are captured once
+        // into a HIP graph and replayed: one launch per block instead of three or four per
+        // iteration.  Capture needs a stream of its own (the caller's may be the null stream); the
+        // caller's stream is idle here, and the blocks are waited for below.
         hipStream_t gs = nullptr;
         FR_TRY(graph_stream(ctx, gs));
-        const int blk = fixed ? std::min(max_it, 32) : 4;   // bounded graph size; a remainder runs eagerly
+        const int blk = fixed ? std::min(max_it, 32) : kBlock;   // bounded graph size; a remainder runs eagerly
         GraphGuard gg;
         FR_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
         fr_status cs = FR_OK;
@@ -1097,15 +1142,13 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                 for (int k = 0; k < n; ++k) FR_TRY(enqueue_iter(gs));
             }
             it += n;
-            if (!fixed) {
-                int n_active = 0;
-                FR_TRY(check_active(gs, n_active));
-                if (n_active == 0) break;
-            }
+            bool more = true;
+            if (it < max_it) FR_TRY(block_done(gs, more));
+            if (!more) break;
         }
         FR_HIP(hipStreamSynchronize(gs));
     } else {
-        for (; it < max_it; ++it) {
+        while (it < max_it) {
             if (blurred) {
                 auto tb = clk::now();
                 if (lat != nullptr) {
@@ -1121,37 +1164,37 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
             if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
             if (fused) {
                 FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
-                                          wmats.as<float>(), params->residual, 0, part.as<float>(), st));
+                                          wmats.as<float>(), params->residual, 0, part.as<float>(), st, act));
                 if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
                 FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
                                            wstat.as<double>(), st));
             } else {
                 FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
-                                    wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st));
+                                    wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st, nullptr,
+                                    act));
                 if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
                 FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
                                      wm1.as<float>(), pl ? wns.as<float>() : nullptr, params->residual, 0, sig_m,
-                                     wjtj.as<double>(), wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st));
+                                     wjtj.as<double>(), wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st,
+                                     nullptr, nullptr, act));
             }
             FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(),
-                                      wmats.as<float>(), wtn.as<double>(), wstatus.as<int32_t>(),
-                                      wactive.as<int32_t>(), st));
+                                      wmats.as<float>(), wtn.as<double>(), wstatus.as<int32_t>(), act, st, act, tol,
+                                      witers.as<int32_t>()));
             if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
-            if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_it)) {
-                int n_active = 0;
-                FR_TRY(check_active(st, n_active));
-                if (n_active == 0) {
-                    ++it;
-                    break;
-                }
-            }
+            ++it;
+            bool more = true;
+            if (it % kBlock == 0 && it < max_it) FR_TRY(block_done(st, more));
+            if (!more) break;
         }
     }
+    FR_HIP(hipMemcpyAsync(iters_v.data(), witers.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
     FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipStreamSynchronize(st));
     auto t3 = clk::now();
-    rep.iterations = it;
+    rep.iterations = 0;
+    for (int32_t s = 0; s < S; ++s) rep.iterations = std::max(rep.iterations, iters_v[s]);
     rep.em_ms = std::chrono::duration<double, std::milli>(t3 - t2).count();
     if (prof) {
         for (int i = 0; i < it; ++i) {
@@ -1655,6 +1698,81 @@ fr_status fr_register_articulated(fr_ctx *ctx, const fr_cloud *model_ref, const 
 }
 
 
+static fr_status check_graph(const fr_node_graph *graph, int64_t M, const char *what)
+{
+    const int32_t K = graph->n_nodes;
+    if (K < 1 || graph->nodes == nullptr || (M > 0 && (graph->skin_idx == nullptr || graph->skin_w == nullptr)) ||
+        graph->n_edges < 0 || (graph->n_edges > 0 && graph->edges == nullptr) || !(graph->lambda >= 0.0)) {
+        set_error("%s: graph needs nodes, skinning arrays, edges and lambda >= 0", what);
+        return FR_EINVAL;
+    }
+    for (int64_t i = 0; i < 4 * M; ++i)
+        if (graph->skin_idx[i] < 0 || graph->skin_idx[i] >= K) {
+            set_error("%s: skin index %d out of [0, %d)", what, graph->skin_idx[i], K);
+            return FR_EINVAL;
+        }
+    for (int32_t q = 0; q < 2 * graph->n_edges; ++q)
+        if (graph->edges[q] < 0 || graph->edges[q] >= K) {
+            set_error("%s: edge node out of range", what);
+            return FR_EINVAL;
+        }
+    return FR_OK;
+}
+
+// The node-graph M-step alone (the reduction fr_register_nodegraph runs every
+// iteration, without the solve): block structure from the graph, per-point
+// terms at the moved points, ordered binary64 block sums, regulariser at the
+// given node transforms, assembly; then copies of the blocks and the
+// right-hand side into the caller's arrays.
+fr_status fr_mstep_reduce_nodes(fr_ctx *ctx, const fr_cloud *x, const float *m0, const float *m1, const float *nsum,
+                                const fr_node_graph *graph, const double *node_T_h, const fr_mstep_params *params,
+                                int64_t *n_blocks, int32_t *block_nodes_h, double *blocks, double *rhs, void *stream)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || x == nullptr || graph == nullptr || node_T_h == nullptr || params == nullptr ||
+        n_blocks == nullptr) {
+        set_error("fr_mstep_reduce_nodes: invalid context, cloud, graph, node transforms, params or n_blocks");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_cloud(x, false, "fr_mstep_reduce_nodes(x)"));
+    if (x->n_sets != 1 || (params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
+        params->normalize_n != 0 || !(params->sigma > 0.0) || !(params->c >= 0.0)) {
+        set_error("fr_mstep_reduce_nodes: one set, residual FR_PT2PT or FR_PT2PL, normalize_n 0, sigma > 0, c >= 0");
+        return FR_EINVAL;
+    }
+    const int64_t M = cloud_points(x);
+    if (M > 0 && (m0 == nullptr || m1 == nullptr || (params->residual == FR_PT2PL && nsum == nullptr))) {
+        set_error("fr_mstep_reduce_nodes: m0, m1 (and nsum for point-to-plane) are required");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_graph(graph, M, "fr_mstep_reduce_nodes"));
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    NodeGraphDev d;
+    FR_TRY(ng_setup(ctx, graph, M, st, d));
+    *n_blocks = d.n_blocks;
+    if (blocks == nullptr) return FR_OK;
+    if (rhs == nullptr || block_nodes_h == nullptr) {
+        set_error("fr_mstep_reduce_nodes: blocks, rhs and block_nodes_h are required together");
+        return FR_EINVAL;
+    }
+    const int32_t K = graph->n_nodes;
+    std::vector<double> T12((size_t)12 * K);
+    for (int32_t k = 0; k < K; ++k)
+        for (int j = 0; j < 12; ++j) T12[(size_t)12 * k + j] = node_T_h[(size_t)16 * k + j];
+    FR_HIP(hipMemcpyAsync(d.T, T12.data(), T12.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    FR_TRY(ng_reduce(d, x->x, x->y, x->z, m0, m1, nsum, params->residual, params->c, params->sigma, graph->lambda, st));
+    FR_HIP(hipMemcpyAsync(blocks, d.A, (size_t)36 * d.n_blocks * sizeof(double), hipMemcpyDeviceToDevice, st));
+    FR_HIP(hipMemcpyAsync(rhs, d.rhs, (size_t)6 * K * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int32_t b = 0; b < d.n_blocks; ++b) {
+        block_nodes_h[2 * b] = (int32_t)(d.block_keys[b] / K);
+        block_nodes_h[2 * b + 1] = (int32_t)(d.block_keys[b] % K);
+    }
+    FR_HIP(hipStreamSynchronize(st));
+    return FR_OK;
+}
+
 fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs, const fr_node_graph *graph,
                                 const fr_register_params *params, double *node_T_inout_h, fr_report *report_h,
                                 void *stream)
@@ -1681,21 +1799,7 @@ fr_status fr_register_nodegraph(fr_ctx *ctx, const fr_cloud *model_ref, const fr
     }
     const int64_t M = cloud_points(model_ref);
     const int32_t K = graph->n_nodes;
-    if (K < 1 || graph->nodes == nullptr || (M > 0 && (graph->skin_idx == nullptr || graph->skin_w == nullptr)) ||
-        graph->n_edges < 0 || (graph->n_edges > 0 && graph->edges == nullptr) || !(graph->lambda >= 0.0)) {
-        set_error("fr_register_nodegraph: graph needs nodes, skinning arrays, edges and lambda >= 0");
-        return FR_EINVAL;
-    }
-    for (int64_t i = 0; i < 4 * M; ++i)
-        if (graph->skin_idx[i] < 0 || graph->skin_idx[i] >= K) {
-            set_error("fr_register_nodegraph: skin index %d out of [0, %d)", graph->skin_idx[i], K);
-            return FR_EINVAL;
-        }
-    for (int32_t q = 0; q < 2 * graph->n_edges; ++q)
-        if (graph->edges[q] < 0 || graph->edges[q] >= K) {
-            set_error("fr_register_nodegraph: edge node out of range");
-            return FR_EINVAL;
-        }
+    FR_TRY(check_graph(graph, M, "fr_register_nodegraph"));
     FR_HIP(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     StreamScope scope(st);

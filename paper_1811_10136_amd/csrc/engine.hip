@@ -35,7 +35,8 @@ struct AdmitRec {
 };
 
 __global__ void __launch_bounds__(64) k_engine_admit(int32_t n, const AdmitRec *recs, double *poses, float *mats,
-                                                      int32_t *status, int32_t *err, SetTable *tables)
+                                                      int32_t *status, int32_t *err, SetTable *tables, int32_t *run,
+                                                      int32_t *iters)
 {
     const int32_t j = blockIdx.x * 64 + threadIdx.x;
     if (j >= n) return;
@@ -47,14 +48,24 @@ __global__ void __launch_bounds__(64) k_engine_admit(int32_t n, const AdmitRec *
     status[s] = FR_OK;
     err[s] = 0;
     tables[s] = r.tab;
+    run[s] = 1;
+    iters[s] = 0;
 }
 
-// Status of every slot for the host: a range error of the slot's E-step wins.
-__global__ void __launch_bounds__(256) k_engine_status(int32_t n, const int32_t *status, const int32_t *err,
-                                                        int32_t *out)
+// State of every slot for the host: a range error of the slot's E-step wins
+// over the solve's status.
+__global__ void __launch_bounds__(256) k_engine_state(int32_t n, const int32_t *status, const int32_t *err,
+                                                       const int32_t *run, const int32_t *iters, fr_slot_state *out)
 {
     const int32_t s = blockIdx.x * 256 + threadIdx.x;
-    if (s < n) out[s] = err[s] ? FR_ERANGE : status[s];
+    if (s < n) {
+        fr_slot_state v;
+        v.status = err[s] ? FR_ERANGE : status[s];
+        v.iterations = iters[s];
+        v.stopped = run[s] == 0 ? 1 : 0;
+        v.reserved = 0;
+        out[s] = v;
+    }
 }
 
 }  // namespace fr
@@ -77,7 +88,11 @@ struct fr_engine {
     float *m0 = nullptr, *m1 = nullptr, *ns = nullptr;
     double *poses = nullptr, *jtj = nullptr, *jtr = nullptr, *stats = nullptr, *twist = nullptr;
     float *mats = nullptr;
-    int32_t *status = nullptr, *err = nullptr, *status_out = nullptr;
+    int32_t *status = nullptr, *err = nullptr;
+    int32_t *run = nullptr;           // per slot: 1 while the slot runs, cleared by the solve when it stops
+    int32_t *iters = nullptr;         // per slot: solves since admission
+    fr_slot_state *state_out = nullptr;
+    double tol = -1.0;
     SetTable *tables = nullptr;
     int64_t offsets_h[2] = {0, 0};  // the arena as a one-set cloud
     // pinned staging: kEngRing plan images, then the admission records
@@ -186,6 +201,7 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     e->st = st;
     e->offsets_h[1] = e->P;
     e->sig_m = (p.lattice.sigma[0] + p.lattice.sigma[1] + p.lattice.sigma[2]) / 3.0;
+    e->tol = p.twist_tol > 0.0 ? p.twist_tol : -1.0;
     const int64_t P = e->P, S = e->S;
     auto fail = [&](fr_status s) {
         engine_free(e);
@@ -216,8 +232,8 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     // per-slot state
     const size_t b_pose = S * 16 * sizeof(double), b_jtj = S * 21 * sizeof(double), b_jtr = S * 6 * sizeof(double);
     const size_t b_stat = S * 4 * sizeof(double), b_tw = S * 2 * sizeof(double), b_mats = S * 12 * sizeof(float);
-    const size_t b_i32 = S * sizeof(int32_t), b_tab = S * sizeof(SetTable);
-    s = e->state.alloc(ctx, b_pose + b_jtj + b_jtr + b_stat + b_tw + b_mats + 3 * b_i32 + b_tab + 64);
+    const size_t b_i32 = S * sizeof(int32_t), b_tab = S * sizeof(SetTable), b_st = S * sizeof(fr_slot_state);
+    s = e->state.alloc(ctx, b_pose + b_jtj + b_jtr + b_stat + b_tw + b_mats + 4 * b_i32 + b_st + b_tab + 64);
     if (s != FR_OK) return fail(s);
     char *q = e->state.as<char>();
     e->poses = reinterpret_cast<double *>(q);
@@ -238,7 +254,11 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     q += b_i32;
     e->err = reinterpret_cast<int32_t *>(q);
     q += b_i32;
-    e->status_out = reinterpret_cast<int32_t *>(q);
+    e->run = reinterpret_cast<int32_t *>(q);
+    q += b_i32;
+    e->iters = reinterpret_cast<int32_t *>(q);
+    q += b_i32;
+    e->state_out = reinterpret_cast<fr_slot_state *>(q);
     if (hipMemsetAsync(e->state.p, 0, e->state.bytes, st) != hipSuccess) return fail(FR_EDEVICE);
     e->plan_bytes = plan_image_bytes(e->S);
     s = e->plan_d.alloc(ctx, e->plan_bytes);
@@ -392,7 +412,7 @@ fr_status fr_engine_admit(fr_engine *e, int32_t n, const int32_t *slots_h, const
     }
     FR_HIP(hipMemcpyAsync(e->admit_d.p, rec, n * sizeof(AdmitRec), hipMemcpyHostToDevice, e->bst));
     k_engine_admit<<<(n + 63) / 64, 64, 0, e->bst>>>(n, e->admit_d.as<AdmitRec>(), e->poses, e->mats, e->status,
-                                                     e->err, e->tables);
+                                                     e->err, e->tables, e->run, e->iters);
     FR_HIP(hipGetLastError());
     FR_HIP(hipEventRecord(e->admit_ev, e->bst));
     hipEvent_t built = nullptr;
@@ -502,35 +522,40 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
     make(d_te, te[S], kEstepTile, pe);
     make(d_tr, tr[S], 1024, pr);
     fr_cloud arena{e->x, e->y, e->z, e->nx, e->ny, e->nz, e->offsets_h, 1};
+    // slots that have stopped on the device (twist below tolerance, or degenerate) are skipped by
+    // every kernel: a step that still lists them leaves them unchanged
     if (e->fused) {
         FR_TRY(launch_estep_fused(e->d, e->V, e->tables, e->err, 1, &arena, pe, e->mats, e->prm.residual, 0,
-                                  e->partials.as<float>(), e->st));
+                                  e->partials.as<float>(), e->st, e->run));
         FR_TRY(launch_reduce_final(pe, e->partials.as<float>(), e->sig_m, e->jtj, e->jtr, e->stats, e->st));
     } else {
         FR_TRY(launch_estep_sets(e->d, e->V, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats,
-                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, nullptr, e->st));
+                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, nullptr, e->st, e->run));
         FR_TRY(launch_reduce(&arena, pr, FR_XF_RIGID, e->mats, e->m0, e->m1,
                              e->prm.residual == FR_PT2PL ? e->ns : nullptr, e->prm.residual, 0, e->sig_m, e->jtj,
-                             e->jtr, e->stats, e->partials.as<float>(), e->st));
+                             e->jtr, e->stats, e->partials.as<float>(), e->st, nullptr, nullptr, e->run));
     }
-    FR_TRY(launch_solve_rigid(S, e->jtj, e->jtr, e->poses, e->mats, e->twist, e->status, d_act, e->st));
+    FR_TRY(launch_solve_rigid(S, e->jtj, e->jtr, e->poses, e->mats, e->twist, e->status, d_act, e->st, e->run,
+                              e->tol, e->iters));
     return FR_OK;
 }
 
-fr_status fr_engine_read(fr_engine *e, double *poses_h, int32_t *status_h)
+fr_status fr_engine_read(fr_engine *e, double *poses_h, fr_slot_state *state_h)
 {
     clear_error();
-    if (!eng_ok(e) || poses_h == nullptr || status_h == nullptr) {
+    if (!eng_ok(e) || state_h == nullptr) {
         set_error("fr_engine_read: invalid engine or output");
         return FR_EINVAL;
     }
     FR_HIP(hipSetDevice(e->ctx->device));
     StreamScope scope(e->st);
     FR_TRY(join_pending(e));
-    k_engine_status<<<(e->S + 255) / 256, 256, 0, e->st>>>(e->S, e->status, e->err, e->status_out);
+    k_engine_state<<<(e->S + 255) / 256, 256, 0, e->st>>>(e->S, e->status, e->err, e->run, e->iters, e->state_out);
     FR_HIP(hipGetLastError());
-    FR_HIP(hipMemcpyAsync(poses_h, e->poses, (size_t)e->S * 16 * sizeof(double), hipMemcpyDeviceToHost, e->st));
-    FR_HIP(hipMemcpyAsync(status_h, e->status_out, (size_t)e->S * sizeof(int32_t), hipMemcpyDeviceToHost, e->st));
+    if (poses_h != nullptr)
+        FR_HIP(hipMemcpyAsync(poses_h, e->poses, (size_t)e->S * 16 * sizeof(double), hipMemcpyDeviceToHost, e->st));
+    FR_HIP(hipMemcpyAsync(state_h, e->state_out, (size_t)e->S * sizeof(fr_slot_state), hipMemcpyDeviceToHost,
+                          e->st));
     return FR_OK;
 }
 

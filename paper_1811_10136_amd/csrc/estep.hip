@@ -25,6 +25,7 @@ struct EstepArgs {
     uint32_t *touched;            // optional: per-slot "was found" flags
     int32_t *err;                 // range-error flag: one word, or one per segment
     int32_t err_stride;           // 0: one word; 1: err[segment]
+    const int32_t *active;        // per set: 0 = the set has stopped, its tiles do nothing (or NULL)
     // fused slice + reduction only
     const float *seg_c;           // outlier constant per segment
     float *partials;              // one row of kRedStride floats per tile
@@ -86,6 +87,7 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
+    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
     const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
     if (i >= a.tm.seg_end[s]) return;
     const SetTable st = a.sets[a.tm.seg_set[s]];
@@ -118,6 +120,7 @@ __global__ void __launch_bounds__(256) k_estep_fused(EstepArgs a)
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
+    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;   // no partial row: the set is not solved
     const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
     float red[kRedVals];
 #pragma unroll
@@ -193,10 +196,12 @@ static void launch_dv(const EstepArgs &a, bool xf, bool touch, int grid, hipStre
 
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                             const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
-                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st)
+                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st,
+                            const int32_t *active)
 {
     if (plan.grid == 0) return FR_OK;
     EstepArgs a{};
+    a.active = active;
     a.x = model->x;
     a.y = model->y;
     a.z = model->z;
@@ -246,7 +251,7 @@ static void launch_fused_dv(const EstepArgs &a, int residual, int grid, hipStrea
 
 fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                              const fr_cloud *model, const Plan &plan, const float *mats, int residual,
-                             int normalize_n, float *partials, hipStream_t st)
+                             int normalize_n, float *partials, hipStream_t st, const int32_t *active)
 {
     if (plan.grid == 0) return FR_OK;
     if ((residual == FR_PT2PL && V != 7) || (V != 4 && V != 7)) {
@@ -269,6 +274,7 @@ fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, i
     a.seg_c = plan.seg_c;
     a.partials = partials;
     a.normalize_n = normalize_n;
+    a.active = active;
     if (d == 3 && V == 4) launch_fused_dv<3, 4>(a, residual, plan.grid, st);
     else if (d == 3 && V == 7) launch_fused_dv<3, 7>(a, residual, plan.grid, st);
     else if (d == 6 && V == 4) launch_fused_dv<6, 4>(a, residual, plan.grid, st);
@@ -357,10 +363,11 @@ fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, co
 }
 
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
-                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2)
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2,
+                       const int32_t *active)
 {
     return launch_estep_sets(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model, cloud_points(model), plan,
-                             xf_kind, mats, m0, m1, nsum, m2, touched, st);
+                             xf_kind, mats, m0, m1, nsum, m2, touched, st, active);
 }
 
 }  // namespace fr

@@ -67,6 +67,9 @@ struct fr_ctx {
     std::vector<Block> cache;
     std::vector<hipEvent_t> spare_events;
     hipStream_t graph_stream = nullptr;   // capture/replay stream of fr_register's graphs
+    // pinned host words the EM loops read the device's per-set stop flags into
+    int32_t *pin_flags = nullptr;
+    size_t pin_flags_n = 0;
     // vertices per splat record of the context's last lattice build: sizes the
     // first provisional table of the next one (loops that rebuild at a
     // shrinking scale see most records carry keys of their own)
@@ -204,11 +207,15 @@ fr_status build_feature_lattice(fr_ctx *ctx, const fr_cloud *obs, const float *f
 bool feature_dim_supported(int dim);
 
 // estep.hip
+// active (device, per set, may be NULL): tiles of a set with active == 0 do
+// nothing (a set that has stopped on its twist or degenerated).
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                             const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
-                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st);
+                            float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st,
+                            const int32_t *active = nullptr);
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
-                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2 = nullptr);
+                       float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2 = nullptr,
+                       const int32_t *active = nullptr);
 // Descriptor E-step (Eq. 8): slice lat at feat (device, M x lat->d) -> m0, m1.
 fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, const float *feat,
                                 float *m0, float *m1, hipStream_t st);
@@ -217,7 +224,7 @@ fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, co
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
                         double *jtr, double *stats, float *partials, hipStream_t st, const float *m2 = nullptr,
-                        double *var_stat = nullptr);
+                        double *var_stat = nullptr, const int32_t *active = nullptr);
 size_t reduce_partials_floats(const Plan &plan);
 fr_status launch_reduce_final(const Plan &plan, const float *partials, double sigma, double *jtj, double *jtr,
                               double *stats, hipStream_t st, double *var_stat = nullptr);
@@ -225,11 +232,16 @@ fr_status launch_reduce_final(const Plan &plan, const float *partials, double si
 // pass): one partial row per E-step tile, then launch_reduce_final on `plan`.
 fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                              const fr_cloud *model, const Plan &plan, const float *mats, int residual,
-                             int normalize_n, float *partials, hipStream_t st);
+                             int normalize_n, float *partials, hipStream_t st, const int32_t *active = nullptr);
 
 // solve.hip
+// Sets with active[i] == 0 or stop[i] == 0 are skipped (either may be NULL).
+// After a set's solve, stop[i] is cleared when the step degenerated or both
+// twist norms are below twist_tol (twist_tol < 0: only when it degenerated);
+// iters (may be NULL) counts the solves of every set.
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
-                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t stream);
+                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t stream,
+                             int32_t *stop = nullptr, double twist_tol = -1.0, int32_t *iters = nullptr);
 
 // articulated.hip
 struct ArtTreeHost {
@@ -262,9 +274,14 @@ struct NodeGraphDev {
            *s = nullptr, *info = nullptr, *part = nullptr;
     float *terms = nullptr;
     int32_t *bad = nullptr;
+    std::vector<int64_t> block_keys;   // block b holds rows of node key / K, columns of node key % K
 };
 fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t stream, NodeGraphDev &d);
 fr_status ng_warp(const NodeGraphDev &d, const fr_cloud *ref, float *const out[6], hipStream_t stream);
+// The node system of one EM iteration (data blocks, regulariser, right-hand
+// side) into d.A (n_blocks x 36, row-major, scaled by 1 / sigma^2) and d.rhs (6K).
+fr_status ng_reduce(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
+                    const float *ns, int residual, double c, double sigma, double lambda, hipStream_t stream);
 fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
                   const float *ns, int residual, double c, double sigma, double lambda, double tol, int32_t max_it,
                   hipStream_t stream);

@@ -23,6 +23,7 @@ struct ReduceArgs {
     const float *seg_c;
     float *partials;
     int normalize_n;
+    const int32_t *active;        // per set: 0 = stopped, its tiles do nothing (or NULL)
 };
 
 template <int RES, bool XF, bool M2>
@@ -32,6 +33,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
+    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;   // no partial row: the set is not solved
     const int64_t start = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
     const int64_t stop = min(start + (int64_t)a.tm.tile, a.tm.seg_end[s]);
     const float c = a.seg_c[s];
@@ -122,10 +124,11 @@ static void launch_reduce_rm(const ReduceArgs &a, bool xf, int grid, hipStream_t
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
                         const float *m1, const float *nsum, int residual, int normalize_n, double sigma, double *jtj,
                         double *jtr, double *stats, float *partials, hipStream_t st, const float *m2,
-                        double *var_stat)
+                        double *var_stat, const int32_t *active)
 {
     if (plan.n_seg == 0) return FR_OK;
     ReduceArgs a{};
+    a.active = active;
     a.x = model->x;
     a.y = model->y;
     a.z = model->z;

@@ -711,10 +711,11 @@ __device__ inline void twist_exp(const double *z, double (&E)[3][4])
     }
 }
 
-__global__ void k_ng_update(int32_t K, const double *dz, double *T)
+// A singular diagonal block (bad set by the block inverse) leaves every node unchanged.
+__global__ void k_ng_update(int32_t K, const double *dz, double *T, const int32_t *bad)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
+    if (k >= K || *bad != 0) return;
     double E[3][4];
     twist_exp(dz + 6 * k, E);
     double N[3][4];
@@ -828,6 +829,7 @@ fr_status ng_setup(fr_ctx *ctx, const fr_node_graph *g, int64_t M, hipStream_t s
     }
     const int32_t NB = (int32_t)all.size();
     d.n_blocks = NB;
+    d.block_keys = all;
     auto block_of = [&](int64_t key) { return (int32_t)(std::lower_bound(all.begin(), all.end(), key) - all.begin()); };
     for (int32_t k = 0; k < K; ++k) diag[k] = block_of((int64_t)k * K + k);
     // node right-hand side CSR: (point, w_ki) in point order
@@ -998,9 +1000,8 @@ fr_status ng_warp(const NodeGraphDev &d, const fr_cloud *ref, float *const out[6
     return FR_OK;
 }
 
-fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
-                  const float *ns, int residual, double c, double sigma, double lambda, double tol, int32_t max_it,
-                  hipStream_t st)
+fr_status ng_reduce(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
+                    const float *ns, int residual, double c, double sigma, double lambda, hipStream_t st)
 {
     const unsigned gM = (unsigned)((std::max<int64_t>(d.M, 1) + kNgThreads - 1) / kNgThreads);
     if (d.M > 0) {
@@ -1025,6 +1026,14 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
                                                  1.0 / (sigma * sigma), d.A, d.K, d.bdata, d.nreg_off, d.nreg_ref,
                                                  d.rhs);
     FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *z, const float *m0, const float *m1,
+                  const float *ns, int residual, double c, double sigma, double lambda, double tol, int32_t max_it,
+                  hipStream_t st)
+{
+    FR_TRY(ng_reduce(d, x, y, z, m0, m1, ns, residual, c, sigma, lambda, st));
     FR_HIP(hipMemsetAsync(d.bad, 0, sizeof(int32_t), st));
     k_ng_block_inverse<<<(d.K + 63) / 64, 64, 0, st>>>(d.K, d.A, d.diag_blk, d.minv, d.bad);
     FR_HIP(hipGetLastError());
@@ -1052,7 +1061,7 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
                                             d.p, d.q, tol, max_it, d.info);
         FR_HIP(hipGetLastError());
     }
-    k_ng_update<<<(d.K + 63) / 64, 64, 0, st>>>(d.K, d.x, d.T);
+    k_ng_update<<<(d.K + 63) / 64, 64, 0, st>>>(d.K, d.x, d.T, d.bad);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

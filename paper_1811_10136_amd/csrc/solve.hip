@@ -49,11 +49,12 @@ __device__ inline void se3_exp(const double (&z)[6], double (&E)[3][4])
 
 __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses,
                                                     float *mats, double *twist_norm, int32_t *status,
-                                                    const int32_t *active)
+                                                    const int32_t *active, int32_t *stop, double twist_tol,
+                                                    int32_t *iters)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    if (active != nullptr && active[s] == 0) return;
+    if ((active != nullptr && active[s] == 0) || (stop != nullptr && stop[s] == 0)) return;
     double A[6][6], b[6];
     {
         int idx = 0;
@@ -90,10 +91,12 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
             A[i][j] = v / ljj;
         }
     }
+    if (iters != nullptr) iters[s] += 1;
     if (!ok) {
         status[s] = FR_EDEGENERATE;
         twist_norm[2 * s] = 0.0;
         twist_norm[2 * s + 1] = 0.0;
+        if (stop != nullptr) stop[s] = 0;
         return;
     }
     double y[6], z[6];
@@ -131,16 +134,22 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
             poses[(size_t)s * 16 + 4 * i + j] = N[i][j];
             mats[(size_t)s * 12 + 4 * i + j] = (float)N[i][j];
         }
-    twist_norm[2 * s] = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
-    twist_norm[2 * s + 1] = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    const double tw = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    const double tv = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    twist_norm[2 * s] = tw;
+    twist_norm[2 * s + 1] = tv;
     status[s] = FR_OK;
+    // stop on a small twist (Sec. 6.1): the set's later iterations do nothing
+    if (stop != nullptr && tw < twist_tol && tv < twist_tol) stop[s] = 0;
 }
 
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
-                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t st)
+                             double *twist_norm, int32_t *status, const int32_t *active, hipStream_t st,
+                             int32_t *stop, double twist_tol, int32_t *iters)
 {
     if (n <= 0) return FR_OK;
-    k_solve_rigid<<<(n + 63) / 64, 64, 0, st>>>(n, jtj, jtr, poses, mats, twist_norm, status, active);
+    k_solve_rigid<<<(n + 63) / 64, 64, 0, st>>>(n, jtj, jtr, poses, mats, twist_norm, status, active, stop,
+                                                 twist_tol, iters);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -1,13 +1,18 @@
 """Continuous-batching server for rigid registration requests.
 
-A request is one observation/model pair registered by a fixed number of EM
-iterations (Sec. 3.1 with the rigid twist M-step of Sec. 5).  The server keeps
-up to ``max_slots`` requests resident on the device and advances all of them
-one EM iteration per tick with one batched engine step; a request that arrives
-while others are running joins at the next tick as soon as a slot, a range of
-the point arena and enough of the HBM budget are free, and leaves (its slot,
-arena range and lattice freed) after its last iteration.  The device side is
-the C engine (fr_engine_*); everything here is scheduling.
+A request is one observation/model pair registered by at most ``iters`` EM
+iterations (Sec. 3.1 with the rigid twist M-step of Sec. 5), or fewer when the
+engine stops it on a small twist (Sec. 6.1; the engine's twist_tol) or a
+degenerate step.  The server keeps up to ``max_slots`` requests resident on the
+device and advances all of them one EM iteration per tick with one batched
+engine step; a request that arrives while others are running joins at the next
+tick as soon as a slot, a range of the point arena and enough of the HBM budget
+are free, and leaves (its slot, arena range and lattice freed) after its last
+iteration.  Stopping is decided on the device: every tick the server enqueues
+a read of the slots' states and retires the stopped ones when such a read has
+completed, a tick or two later (the steps in between leave a stopped slot
+unchanged).  The device side is the C engine (fr_engine_*); everything here is
+scheduling.
 
 The scheduling logic is written against a small backend interface so that it
 can be exercised with a simulated device (``SimBackend``) as well as the GPU
@@ -46,6 +51,7 @@ class Result:
     completed: float
     pose: np.ndarray
     status: int
+    iterations: int = -1           # EM iterations the request ran (-1: not reported)
 
     @property
     def latency(self) -> float:
@@ -130,10 +136,12 @@ class Server:
         nxt = 0                                   # next request not yet arrived
         queue: collections.deque = collections.deque()
         free_slots = list(range(self.b.max_slots - 1, -1, -1))
-        active: Dict[int, list] = {}              # slot -> [request, iterations done, arena begin, admitted at]
-        reads: collections.deque = collections.deque()   # (token, [(slot, request, admitted)])
+        active: Dict[int, list] = {}              # slot -> [request, steps enqueued, arena begin, admitted at]
+        reads: collections.deque = collections.deque()   # (token, [(slot, request, admitted)]): final reads
+        polls: collections.deque = collections.deque()   # (token, {slot: request id}): state reads
         ticks: collections.deque = collections.deque()   # tick tokens in flight
         results: List[Result] = []
+        poll = bool(getattr(self.b, "stops_on_device", False))
         self.b.start()
         while nxt < len(reqs) or queue or active or reads:
             now = self.b.now()
@@ -161,24 +169,34 @@ class Server:
                 t_adm = self.b.now()
                 for s, r, bgn in zip(slots, group, begins):
                     active[s] = [r, 0, bgn, t_adm]
+            done = []
             if active:
                 step_slots = sorted(active)
                 self.b.step(step_slots)
                 self.ticks += 1
                 self.max_resident = max(self.max_resident, len(active))
-                done = []
                 for s in step_slots:
                     active[s][1] += 1
                     if active[s][1] == self.iters:
                         done.append(s)
-                if done:
-                    token = self.b.read()
-                    reads.append((token, [(s, active[s][0], active[s][3]) for s in done]))
-                    self.b.release(done)
-                    for s in done:
-                        r, _, bgn, _ = active.pop(s)
-                        self.arena.release(bgn, r.m)
-                        free_slots.append(s)
+                if poll:
+                    polls.append((self.b.read(poses=False), {s: active[s][0].rid for s in step_slots}))
+            # slots the device has stopped, from the state reads that have completed
+            while polls and self.b.done(polls[0][0]):
+                token, snap = polls.popleft()
+                state = self.b.states(token)
+                for s, rid in snap.items():
+                    if s in active and active[s][0].rid == rid and s not in done and state[s][2]:
+                        done.append(s)
+            if done:
+                token = self.b.read()
+                reads.append((token, [(s, active[s][0], active[s][3]) for s in done]))
+                self.b.release(done)
+                for s in done:
+                    r, _, bgn, _ = active.pop(s)
+                    self.arena.release(bgn, r.m)
+                    free_slots.append(s)
+            if active or group:
                 ticks.append(self.b.mark())
                 if on_tick is not None:
                     on_tick(self)
@@ -187,9 +205,10 @@ class Server:
                 token, fin = reads.popleft()
                 self.b.wait(token)
                 t_done = self.b.completion_time(token)
-                poses, status = self.b.poses(token)
+                poses, state = self.b.poses(token)
                 for s, r, t_adm in fin:
-                    results.append(Result(r.rid, r.arrival, t_adm, t_done, poses[s].copy(), int(status[s])))
+                    results.append(Result(r.rid, r.arrival, t_adm, t_done, poses[s].copy(), int(state[s][0]),
+                                          int(state[s][1])))
             # keep the host at most max_inflight ticks ahead of the device
             while len(ticks) > self.max_inflight:
                 self.b.wait(ticks.popleft())
@@ -210,7 +229,9 @@ def summarize(results: Sequence[Result], wall: Optional[float] = None) -> dict:
     return {"requests": len(results), "span_s": span, "registrations_per_s": len(results) / span,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "max": float(lat.max())},
-            "degenerate": int(sum(r.status != 0 for r in results))}
+            "degenerate": int(sum(r.status != 0 for r in results)),
+            "solved_per_s": sum(r.status == 0 for r in results) / span,
+            "mean_iterations": float(np.mean([r.iterations for r in results]))}
 
 
 # ------------------------------------------------------------------------------
@@ -220,8 +241,13 @@ class SimBackend:
     step is logged so that a test can check what ran."""
 
     def __init__(self, max_slots=8, arena_points=10_000, step_fixed=1e-4, step_per_point=1e-8,
-                 admit_fixed=5e-4, admit_per_point=2e-8, lattice_bytes_per_obs_point=300.0, fail=()):
+                 admit_fixed=5e-4, admit_per_point=2e-8, lattice_bytes_per_obs_point=300.0, fail=(),
+                 stop_after=None):
         self.max_slots = max_slots
+        # stop_after: request id -> the iteration after which the device stops it (its twist fell below
+        # the tolerance); the server then learns of stops from state reads
+        self.stop_after = dict(stop_after or {})
+        self.stops_on_device = stop_after is not None
         self.arena_points = arena_points
         self.sf, self.sp, self.af, self.ap = step_fixed, step_per_point, admit_fixed, admit_per_point
         self.lbpp = lattice_bytes_per_obs_point
@@ -264,19 +290,25 @@ class SimBackend:
         self.host += dur
         self.log.append(("admit", tuple(slots), tuple(r.rid for r in reqs)))
 
+    def _stopped(self, v):
+        r, _, it = v
+        return r.rid in self.fail and it >= 1 or it >= self.stop_after.get(r.rid, 1 << 30)
+
     def step(self, slots):
         for s in slots:
-            self.slots[s][2] += 1
-        pts = sum(self.slots[s][0].m for s in slots)
+            if not self._stopped(self.slots[s]):      # a stopped slot is left unchanged
+                self.slots[s][2] += 1
+        pts = sum(self.slots[s][0].m for s in slots if not self._stopped(self.slots[s]))
         self.clock = max(self.clock, self.host) + self.sf + self.sp * pts
         self.host += 2e-5                  # enqueue cost
         self.log.append(("step", tuple(slots)))
 
-    def read(self):
-        poses = {s: np.array([[1.0, 0, 0, v[2]], [0, 1, 0, v[0].rid], [0, 0, 1, 0], [0, 0, 0, 1]])
-                 for s, v in self.slots.items()}
-        status = {s: (5 if v[0].rid in self.fail else 0) for s, v in self.slots.items()}
-        self.poses_at.append((self.clock, poses, status))
+    def read(self, poses=True):
+        P = {s: np.array([[1.0, 0, 0, v[2]], [0, 1, 0, v[0].rid], [0, 0, 1, 0], [0, 0, 0, 1]])
+             for s, v in self.slots.items()} if poses else None
+        state = {s: (5 if v[0].rid in self.fail else 0, v[2], int(self._stopped(v))) for s, v in self.slots.items()}
+        self.poses_at.append((self.clock, P, state))
+        self.log.append(("read", poses))
         return len(self.poses_at) - 1
 
     def release(self, slots):
@@ -304,6 +336,9 @@ class SimBackend:
     def poses(self, token):
         return self.poses_at[token][1], self.poses_at[token][2]
 
+    def states(self, token):
+        return self.poses_at[token][2]
+
 
 class EngineBackend:
     """The GPU: an fr_engine on the current torch stream.  Completion times are read from timing
@@ -318,6 +353,7 @@ class EngineBackend:
         self.eng = Engine(ctx, params)
         self.max_slots = int(params.max_slots)
         self.arena_points = int(params.arena_points)
+        self.stops_on_device = float(params.twist_tol) > 0.0
         self.clouds = payload_clouds            # requests -> (model Cloud, obs Cloud) of len(requests) sets
         self._usage = fr_ctx_usage
         self.base = self.arena_bytes = 0
@@ -357,10 +393,10 @@ class EngineBackend:
     def step(self, slots):
         self.eng.step(slots)
 
-    def read(self):
+    def read(self, poses=True):
         torch = self.torch
-        pp = torch.empty((self.max_slots, 16), dtype=torch.float64, pin_memory=True)
-        ps = torch.empty(self.max_slots, dtype=torch.int32, pin_memory=True)
+        pp = torch.empty((self.max_slots, 16), dtype=torch.float64, pin_memory=True) if poses else None
+        ps = torch.empty((self.max_slots, 4), dtype=torch.int32, pin_memory=True)
         self.eng.read(pp, ps)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
@@ -390,6 +426,10 @@ class EngineBackend:
     def poses(self, token):
         ev, pp, ps = self.read_ev.pop(token)
         return pp.numpy().reshape(-1, 4, 4), ps.numpy()
+
+    def states(self, token):
+        ev, _, ps = self.read_ev.pop(token)
+        return ps.numpy()
 
     def close(self):
         self.eng.close()

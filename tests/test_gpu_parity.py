@@ -478,3 +478,63 @@ def test_graph_blocks_and_remainder_equal_the_eager_loop(fr, ctx):
         T, st, rep = fr.register(ctx, m, o, fr.register_params(3, "pt2pt", p.sigma, graph=True, **kw))
         np.testing.assert_array_equal(T, eager[0])
         assert rep.iterations == 40 and st[0] == eager[1][0]
+
+
+def _twist_sizes(hist):
+    return [max(np.linalg.norm(h["dz"][:3]), np.linalg.norm(h["dz"][3:])) for h in hist]
+
+
+@pytest.mark.parametrize("case", ["ellipsoid", "depth", "depth_far"])
+def test_stop_on_twist_matches_the_oracle_stop_iteration(fr, ctx, case):
+    """Iteration control (Sec. 6.1): without FR_FIXED_ITERS the device stops a set after the first step
+    whose rotation and translation parts both fall below twist_tol; the oracle applies the same rule.
+    Stop iterations must agree, except where the oracle's decisive twist lies within 25% of the
+    tolerance (binary32 sums move a twist by about 1e-6 of its size, so only a near tie may split)."""
+    tol = 1e-5
+    if case == "ellipsoid":
+        p = synth.ellipsoid_pair(3)
+        T0 = p.T_gt @ oracle.se3_exp(np.array([0.02, -0.01, 0.01, 0.005, 0.004, -0.003]))
+        kw = dict(feat=3, residual="pt2pt")
+    else:
+        p = synth.depth_pair(7 if case == "depth" else 8, width=160, height=120, f=131.25)
+        d = 0.004 if case == "depth" else 0.012
+        T0 = p.T_gt @ oracle.se3_exp(np.array([d, -d, d / 2, d, d / 2, -d]))
+        kw = dict(feat=6, residual="pt2pl")
+    _say(f"[stop] {case} M={len(p.model)} tol={tol}")
+    hist, info = [], {}
+    ref = oracle.register_rigid(p.model, p.model_n, p.obs, p.obs_n, sigma=p.sigma, sigma_n=p.sigma_n, w=p.w,
+                                iters=60, T0=T0, twist_tol=tol, history=hist, info=info, **kw)
+    prm = fr.register_params(kw["feat"], kw["residual"], p.sigma, p.sigma_n, iters=60, w=p.w, fixed=False, tol=tol)
+    T, st, rep = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm, T0=T0[None])
+    assert st[0] == 0
+    k = info["iterations"]
+    assert 2 <= k < 60, k
+    tw = _twist_sizes(hist)
+    clear = tw[k - 1] < 0.75 * tol and tw[k - 2] > 1.25 * tol
+    if clear:
+        assert rep.iterations == k, (rep.iterations, k, tw[k - 3:k])
+    else:
+        assert abs(rep.iterations - k) <= 1, (rep.iterations, k, tw[k - 3:k])
+    ang, dt, ok = pose_close(T[0], ref)
+    assert ok, (ang, dt)
+
+
+def test_stop_on_twist_batch_equals_each_pair_alone(fr, ctx):
+    """Sets of one call stop at different iterations on the device; each ends bitwise where it ends
+    alone, and the call reports the largest count."""
+    pairs = [synth.depth_pair(60 + i, width=w, height=h, f=f)
+             for i, (w, h, f) in enumerate([(160, 120, 131.25), (96, 72, 78.75), (200, 150, 164.0)])]
+    T0 = np.stack([p.T_gt @ oracle.se3_exp(np.array([0.003 * (i + 1), -0.004, 0.002, 0.01 * (i + 1), 0.0, -0.005]))
+                   for i, p in enumerate(pairs)])
+    q = pairs[0]
+    prm = fr.register_params(6, "pt2pl", q.sigma, q.sigma_n, iters=50, w=q.w, fixed=False, tol=1e-5)
+    T, st, rep = fr.register(ctx, upload([p.model for p in pairs], [p.model_n for p in pairs]),
+                             upload([p.obs for p in pairs], [p.obs_n for p in pairs]), prm, T0=T0)
+    its = []
+    for i, p in enumerate(pairs):
+        Ta, sa, ra = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm,
+                                 T0=T0[i][None])
+        np.testing.assert_array_equal(T[i], Ta[0])
+        assert st[i] == sa[0]
+        its.append(ra.iterations)
+    assert rep.iterations == max(its) and len(set(its)) > 1, its

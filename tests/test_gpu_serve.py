@@ -45,18 +45,20 @@ def _alone(fr, ctx, p, iters=ITERS, fused=False):
     return T[0], int(st[0])
 
 
-def _engine(fr, ctx, p0, slots=4, arena=150_000, fused=False):
+def _engine(fr, ctx, p0, slots=4, arena=150_000, fused=False, tol=0.0):
     prm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=slots, arena_points=arena, w=p0.w,
-                           fused=fused)
+                           fused=fused, tol=tol)
     return fr.Engine(ctx, prm)
 
 
-def _read(eng, S):
+def _read(eng, S, with_state=False):
     poses = torch.empty((S, 16), dtype=torch.float64, pin_memory=True)
-    status = torch.empty(S, dtype=torch.int32, pin_memory=True)
-    eng.read(poses, status)
+    state = torch.empty((S, 4), dtype=torch.int32, pin_memory=True)
+    eng.read(poses, state)
     torch.cuda.synchronize()
-    return poses.numpy().reshape(S, 4, 4).copy(), status.numpy().copy()
+    if with_state:
+        return poses.numpy().reshape(S, 4, 4).copy(), state.numpy().copy()
+    return poses.numpy().reshape(S, 4, 4).copy(), state.numpy()[:, 0].copy()
 
 
 @pytest.mark.parametrize("fused", [False, True])
@@ -175,3 +177,65 @@ def test_server_on_the_gpu_matches_alone_runs(fr, ctx, pairs):
         assert r.completed > r.admitted >= r.arrival
     s = summarize(res)
     print(f"[serve] {s}", flush=True)
+
+
+TOL = 2e-5
+
+
+def _alone_tol(fr, ctx, p, iters=40):
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=iters, w=p.w, fixed=False, tol=TOL)
+    T, st, rep = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm, T0=_T0(p)[None])
+    return T[0], int(st[0]), rep.iterations
+
+
+def test_engine_stops_a_slot_on_its_twist_as_the_pair_alone(fr, ctx, pairs):
+    """With a twist tolerance, each slot stops on the device after the same step as fr_register on the
+    pair alone (Sec. 6.1); steps that still list a stopped slot leave it bitwise unchanged, and its state
+    reports the stop and the iteration count."""
+    print("[serve] stop on twist", flush=True)
+    sub = [pairs[i] for i in (0, 2, 5, 6)]
+    alone = [_alone_tol(fr, ctx, p) for p in sub]
+    assert min(a[2] for a in alone) < 40, [a[2] for a in alone]
+    eng = _engine(fr, ctx, sub[0], slots=4, arena=150_000, tol=TOL)
+    keep = []
+    begin = 0
+    for j, p in enumerate(sub):
+        keep.append(upload([p.model], [p.model_n]))
+        eng.admit([j], keep[-1], upload([p.obs], [p.obs_n]), [begin], _T0(p)[None])
+        begin += len(p.model)
+    for _ in range(45):                   # every slot listed in every step, stopped or not
+        eng.step([0, 1, 2, 3])
+    poses, state = _read(eng, 4, with_state=True)
+    eng.close()
+    for j, (T, st, it) in enumerate(alone):
+        assert state[j, 0] == st and state[j, 1] == it and state[j, 2] == 1, (j, state[j], it)
+        np.testing.assert_array_equal(poses[j], T, err_msg=f"slot {j}")
+
+
+def test_server_with_device_stops_matches_alone_runs(fr, ctx, pairs):
+    """The server retires twist-stopped requests from the slots' states: poses, statuses and iteration
+    counts equal fr_register's on each pair alone with the same tolerance."""
+    from paper_1811_10136_amd.serve import EngineBackend, Request, Server, poisson_arrivals
+    reqs_p = [pairs[i % len(pairs)] for i in range(12)]
+    model = fr.Cloud.from_numpy([p.model for p in reqs_p], [p.model_n for p in reqs_p])
+    obs = fr.Cloud.from_numpy([p.obs for p in reqs_p], [p.obs_n for p in reqs_p])
+
+    def clouds(reqs):
+        a, b = reqs[0].rid, reqs[-1].rid + 1
+        return model.sets(a, b), obs.sets(a, b)
+
+    prm = fr.engine_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, max_slots=5, arena_points=160_000,
+                           w=pairs[0].w, tol=TOL)
+    be = EngineBackend(ctx, prm, clouds)
+    t = poisson_arrivals(len(reqs_p), 300.0, 9)
+    reqs = [Request(i, float(t[i]), len(p.model), len(p.obs), T0=_T0(p)) for i, p in enumerate(reqs_p)]
+    res = Server(be, iters=40, budget_bytes=1 << 31, max_admit=3).run(reqs)
+    be.close()
+    alone = {}
+    for r in res:
+        k = r.rid % len(pairs)
+        if k not in alone:
+            alone[k] = _alone_tol(fr, ctx, pairs[k])
+        T, st, it = alone[k]
+        assert r.status == st and r.iterations == it, (r.rid, r.status, r.iterations, st, it)
+        np.testing.assert_array_equal(r.pose, T, err_msg=f"request {r.rid}")

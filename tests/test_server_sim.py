@@ -53,7 +53,7 @@ def test_every_request_runs_exactly_its_iterations_under_the_limits():
             assert len(ev[1]) <= 6
             for s in ev[1]:
                 steps[slot_of[s]] += 1
-        else:
+        elif ev[0] == "release":
             for s in ev[1]:
                 del slot_of[s]
     assert set(steps.values()) == {7}
@@ -64,7 +64,7 @@ def test_every_request_runs_exactly_its_iterations_under_the_limits():
     assert order == sorted(order)
     # the recorded pose is the one the device held after the request's last step
     for r in res:
-        assert r.pose[1, 3] == r.rid and r.pose[0, 3] == 7
+        assert r.pose[1, 3] == r.rid and r.pose[0, 3] == 7 and r.iterations == 7
         assert r.completed >= r.admitted >= r.arrival
     s = summarize(res)
     assert s["requests"] == len(reqs) and s["degenerate"] == 0
@@ -91,7 +91,9 @@ def test_a_failing_request_retires_without_disturbing_others():
     res = Server(be, iters=4, budget_bytes=1 << 30).run(reqs)
     for r in res:
         assert r.status == (5 if r.rid in (5, 11) else 0)
-        assert r.pose[1, 3] == r.rid and r.pose[0, 3] == 4
+        # a degenerate step stops the slot on the device: later steps leave it unchanged
+        n = 1 if r.rid in (5, 11) else 4
+        assert r.pose[1, 3] == r.rid and r.pose[0, 3] == n and r.iterations == n
 
 
 def test_requests_larger_than_the_arena_or_budget_are_rejected():
@@ -113,3 +115,27 @@ def test_idle_server_waits_for_arrivals_and_latency_reflects_queueing():
     assert lat[1] == pytest.approx(10e-3, rel=0.05)      # queued behind request 0
     assert lat[2] == pytest.approx(5e-3, rel=0.05)       # arrives to an idle server
     assert res[2].admitted >= 1.0
+
+
+def test_requests_that_stop_on_the_device_retire_early():
+    """Twist-stopped requests (Sec. 6.1): the device stops a slot after its request's stop iteration; the
+    server learns of it from a state read a tick or two later, retires it, and reports the pose and the
+    iteration count the device held at the stop.  The others run the cap."""
+    reqs = _stream(n=24, seed=5)
+    stop = {r.rid: 2 + r.rid % 5 for r in reqs if r.rid % 3 != 0}
+    be = SimBackend(max_slots=5, arena_points=20_000, stop_after=stop)
+    srv = Server(be, iters=9, budget_bytes=1 << 30, max_admit=3)
+    res = srv.run(reqs)
+    assert [r.rid for r in res] == [r.rid for r in reqs]
+    for r in res:
+        n = stop.get(r.rid, 9)
+        assert r.iterations == n and r.pose[0, 3] == n and r.pose[1, 3] == r.rid
+    # a stopped request leaves within a few ticks of its stop: fewer steps in all than the cap would take
+    steps = sum(len(ev[1]) for ev in be.log if ev[0] == "step")
+    assert steps < 9 * len(reqs)
+    assert any(ev == ("read", False) for ev in be.log)
+    # the same stream with the cap alone runs every request 9 iterations
+    be2 = SimBackend(max_slots=5, arena_points=20_000)
+    res2 = Server(be2, iters=9, budget_bytes=1 << 30, max_admit=3).run(reqs)
+    assert all(r.iterations == 9 for r in res2)
+    assert not any(ev[0] == "read" and ev[1] is False for ev in be2.log)
