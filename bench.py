@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--iters", type=int, default=ITERS)
     ap.add_argument("--splat", choices=["sorted", "atomic"], default="sorted")
     ap.add_argument("--fused", type=int, default=0, help="1: slice and reduction in one kernel (FR_FUSED)")
+    ap.add_argument("--slice", choices=["auto", "plain", "shared"], default="auto",
+                    help="E-step slice kernel (auto: the library's autotuner picks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=3, help="pairs the CPU oracle baseline runs")
     ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
@@ -561,6 +563,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     ctx = fr.Context(0)
+    fr.fr_ctx_set_tuning(ctx.h, {"auto": fr.FR_SLICE_AUTO, "plain": fr.FR_SLICE_PLAIN,
+                                 "shared": fr.FR_SLICE_SHARED}[args.slice])
     model = fr.Cloud.from_numpy([p.model for p in pairs], [p.model_n for p in pairs], dev)
     obs = fr.Cloud.from_numpy([p.obs for p in pairs], [p.obs_n for p in pairs], dev)
     sigma, sigma_n = pairs[0].sigma, pairs[0].sigma_n
@@ -602,7 +606,17 @@ def main():
     alg_bytes = points_per_launch * per_point + touched * VERTEX_BYTES
     est_avg_s = est_ms / max(1, est_n) / 1e3
     achieved = alg_bytes / est_avg_s / 1e9
-    kernel = "k_estep_fused<6,7,rigid,pt2pl>" if args.fused else "k_estep<6,7,rigid>"
+    tuned = fr.fr_ctx_tuning_table(ctx.h)
+    chosen = {"auto": None, "plain": fr.FR_SLICE_PLAIN, "shared": fr.FR_SLICE_SHARED}[args.slice]
+    if chosen is None:
+        big = [e for e in tuned if e["d"] == 6 and e["V"] == 7 and e["xf_kind"] == fr.FR_XF_RIGID]
+        chosen = max(big, key=lambda e: e["size_class"])["slice"] if big else fr.FR_SLICE_PLAIN
+    if args.fused:
+        kernel = "k_estep_fused<6,7,rigid,pt2pl>"
+    elif chosen == fr.FR_SLICE_SHARED:
+        kernel = "k_estep_dedup<6,7,rigid>"
+    else:
+        kernel = "k_estep<6,7,rigid>"
     traffic = traffic_from_profile(points_per_launch, kernel)
     copy_gbs = copy_bandwidth()
 
@@ -634,6 +648,7 @@ def main():
                   "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
                   "outcome": batch_outcome(pairs, T, status)},
         "build_ms_mean": float(np.mean(build_ms)),
+        "autotuner": {"slice_mode": args.slice, "slice_used": fr.SLICE_NAMES[chosen], "table": tuned},
         "roofline": {
             "kernel": kernel,
             "bytes_per_point": per_point, "bytes_per_touched_vertex": VERTEX_BYTES,

@@ -75,6 +75,40 @@ fr_status fr_ctx_destroy(fr_ctx *ctx);
 /* Bytes currently charged to the context's budget. */
 fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes_in_use);
 
+/*
+ * Kernel choices of a context (tuning only: every choice gives bitwise the
+ * same results).  The slice of Sec. 4.2 interpolates the lattice at each model
+ * point from the d+1 vertices of its simplex:
+ *   FR_SLICE_PLAIN   each model point looks its d+1 vertices up in the
+ *                    lattice table (any point order);
+ *   FR_SLICE_SHARED  a wavefront of 64 consecutive model points looks each
+ *                    distinct vertex up once: neighbouring points of a
+ *                    range-image scan share most of their vertices;
+ *   FR_SLICE_AUTO    (the default) an autotuner times both on the first E-step
+ *                    launch of each (d, V, transform kind, size class) the
+ *                    context meets -- the launches compute the same outputs,
+ *                    so they are that E-step -- and keeps the faster.  The
+ *                    timing waits for the stream once; a launch enqueued while
+ *                    the stream is being captured into a graph is not timed
+ *                    (it takes FR_SLICE_PLAIN until a later launch tunes).
+ * size class = floor(log2(model points of the launch)).
+ */
+enum { FR_SLICE_AUTO = 0, FR_SLICE_PLAIN = 1, FR_SLICE_SHARED = 2 };
+typedef struct {
+    int32_t slice;         /* FR_SLICE_* */
+} fr_tuning;
+fr_status fr_ctx_set_tuning(fr_ctx *ctx, const fr_tuning *tuning);
+
+/* One choice of the autotuner: the mean launch times it measured (us). */
+typedef struct {
+    int32_t d, V, xf_kind, size_class;
+    int32_t slice;         /* FR_SLICE_PLAIN or FR_SLICE_SHARED */
+    float us_plain, us_shared;
+} fr_tuning_entry;
+/* Copies up to `cap` entries of the context's autotuner table to out_h (host)
+ * and their total count to *n (host). */
+fr_status fr_ctx_tuning_table(const fr_ctx *ctx, fr_tuning_entry *out_h, int32_t cap, int32_t *n);
+
 /* A point cloud of n_sets sets (see the conventions above). */
 typedef struct {
     const float *x, *y, *z;        /* device, offsets[n_sets] entries each */

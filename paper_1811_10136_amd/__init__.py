@@ -39,6 +39,8 @@ FR_XF_NONE, FR_XF_RIGID, FR_XF_SEGMENTED = 0, 1, 2
 FR_PT2PT, FR_PT2PL = 0, 1
 FR_KIN_RIGID, FR_KIN_ARTICULATED, FR_KIN_NODEGRAPH = 0, 1, 2
 FR_FIXED_ITERS, FR_PROFILE_EVENTS, FR_FUSED, FR_BLURRED, FR_GRAPH = 1, 2, 4, 8, 16
+FR_SLICE_AUTO, FR_SLICE_PLAIN, FR_SLICE_SHARED = 0, 1, 2
+SLICE_NAMES = {FR_SLICE_AUTO: "auto", FR_SLICE_PLAIN: "plain", FR_SLICE_SHARED: "shared"}
 
 STATUS_NAMES = {0: "FR_OK", 1: "FR_EINVAL", 2: "FR_ENOMEM", 3: "FR_EBUDGET", 4: "FR_ERANGE",
                 5: "FR_EDEGENERATE", 6: "FR_EDEVICE"}
@@ -98,6 +100,19 @@ class fr_engine_params(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32), ("twist_tol", ctypes.c_double)]
 
 
+class fr_tuning(ctypes.Structure):
+    _fields_ = [("slice", ctypes.c_int32)]
+
+
+class fr_tuning_entry(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("V", ctypes.c_int32), ("xf_kind", ctypes.c_int32),
+                ("size_class", ctypes.c_int32), ("slice", ctypes.c_int32), ("us_plain", ctypes.c_float),
+                ("us_shared", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # fr_slot_state: status, iterations, stopped, reserved (int32 each); a host array of these is an
 # int32 array of shape (max_slots, 4)
 SLOT_STATUS, SLOT_ITERATIONS, SLOT_STOPPED = 0, 1, 2
@@ -127,6 +142,8 @@ _sig("fr_last_error", ctypes.c_char_p, [])
 _sig("fr_ctx_create", _st, [_i32, ctypes.c_size_t, ctypes.POINTER(_P)])
 _sig("fr_ctx_destroy", _st, [_P])
 _sig("fr_ctx_usage", _st, [_P, ctypes.POINTER(ctypes.c_size_t)])
+_sig("fr_ctx_set_tuning", _st, [_P, ctypes.POINTER(fr_tuning)])
+_sig("fr_ctx_tuning_table", _st, [_P, ctypes.POINTER(fr_tuning_entry), _i32, ctypes.POINTER(_i32)])
 _sig("fr_lattice_build", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_lattice_params), _P,
                                ctypes.POINTER(_P)])
 _sig("fr_lattice_build_joint", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform),
@@ -172,6 +189,7 @@ _sig("fr_engine_read", _st, [_P, _P, _P])
 _sig("fr_engine_release", _st, [_P, _i32, _P])
 
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
+                 "fr_ctx_set_tuning", "fr_ctx_tuning_table",
                  "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
                  "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
                  "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
@@ -290,6 +308,19 @@ def fr_ctx_usage(ctx) -> int:
     v = ctypes.c_size_t()
     _check(_lib.fr_ctx_usage(ctx, ctypes.byref(v)))
     return v.value
+
+
+def fr_ctx_set_tuning(ctx, slice: int = FR_SLICE_AUTO):
+    t = fr_tuning(slice)
+    _check(_lib.fr_ctx_set_tuning(ctx, ctypes.byref(t)))
+
+
+def fr_ctx_tuning_table(ctx) -> List[dict]:
+    n = _i32()
+    _check(_lib.fr_ctx_tuning_table(ctx, None, 0, ctypes.byref(n)))
+    buf = (fr_tuning_entry * max(1, n.value))()
+    _check(_lib.fr_ctx_tuning_table(ctx, buf, n.value, ctypes.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
 
 
 def fr_lattice_build(ctx, obs: Cloud, params: fr_lattice_params, stream=None):

@@ -183,6 +183,8 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
 {
     plan.tile = tile;
     plan.n_sets = cloud->n_sets;
+    plan.ctx = ctx;
+    plan.slice = ctx->slice_mode;
     const bool seg = xf != nullptr && xf->kind == FR_XF_SEGMENTED;
     if (seg) {
         plan.n_seg = xf->n_seg;
@@ -552,6 +554,33 @@ fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes)
         return FR_EINVAL;
     }
     *bytes = ctx->in_use;
+    return FR_OK;
+}
+
+fr_status fr_ctx_set_tuning(fr_ctx *ctx, const fr_tuning *t)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || t == nullptr) {
+        set_error("fr_ctx_set_tuning: invalid argument");
+        return FR_EINVAL;
+    }
+    if (t->slice != FR_SLICE_AUTO && t->slice != FR_SLICE_PLAIN && t->slice != FR_SLICE_SHARED) {
+        set_error("fr_ctx_set_tuning: slice %d is not an FR_SLICE_* value", t->slice);
+        return FR_EINVAL;
+    }
+    ctx->slice_mode = t->slice;
+    return FR_OK;
+}
+
+fr_status fr_ctx_tuning_table(const fr_ctx *ctx, fr_tuning_entry *out_h, int32_t cap, int32_t *n)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || n == nullptr || cap < 0 || (cap > 0 && out_h == nullptr)) {
+        set_error("fr_ctx_tuning_table: invalid argument");
+        return FR_EINVAL;
+    }
+    *n = (int32_t)ctx->tuned.size();
+    for (int32_t i = 0; i < cap && i < *n; ++i) out_h[i] = ctx->tuned[i];
     return FR_OK;
 }
 

@@ -517,6 +517,8 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         p.tm.tile = tile;
         p.tm.xcd_chunk = chunk;
         p.seg_c = d_c;
+        p.ctx = e->ctx;
+        p.slice = e->ctx->slice_mode;
     };
     Plan pe, pr;
     make(d_te, te[S], kEstepTile, pe);

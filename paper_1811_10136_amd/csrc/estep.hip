@@ -109,6 +109,226 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Slice with the lookups of a wave shared (k_estep_dedup).
+//
+// On a 640 x 480 depth frame about one vertex in four of a wave's 64 points
+// starts a run of shared vertices (wave_runs).  A wave therefore
+//   1. embeds its 64 points and finds its runs;
+//   2. looks each run's key up once (64 runs per round, one per lane, with the
+//      same bucket probes as the plain slice) and parks the values in LDS;
+//   3. gives every point the values of its D vertices from LDS and sums them
+//      in vertex order m = 0..d with the plain slice's arithmetic, so the
+//      result is bitwise that of k_estep.
+// A wave with more runs than its LDS holds (points in no particular order)
+// takes the plain slice.  LDS is private to each wave: no barrier across the
+// workgroup.
+// ---------------------------------------------------------------------------
+template <int d, int V> struct DedupGeom {
+    static constexpr int D = d + 1;
+    static constexpr int KW = KeyWords<d>::value;
+    static constexpr int VP = ValPad<V>::value;
+    static constexpr int key_bytes = WaveKeys<d>::bytes;        // keys of the wave, [lane][class]
+    static constexpr int by_vals = key_bytes / (VP * 4) / 64 * 64;
+    static constexpr int C0 = by_vals < 64 * D ? by_vals : 64 * D;
+    static constexpr int C = C0 < 192 ? C0 : 192;               // runs a wave can hold (entries fit a byte)
+    static constexpr int NL = C / 64;                           // lookups per lane
+    static constexpr int region = key_bytes > C * VP * 4 ? key_bytes : C * VP * 4;
+    static constexpr int src_off = region;                      // u16 per entry: (lane << 3) | class
+    static constexpr int ent_off = src_off + 2 * C;             // u8 per (lane, vertex): its entry
+    static constexpr int fnd_off = ent_off + 64 * D;            // u8 per entry: found
+    static constexpr int wave_bytes = (fnd_off + C + 15) / 16 * 16;
+    static_assert(NL >= 1, "a wave must hold at least one round of lookups");
+};
+
+// Slice of a wave's points with shared lookups.  live: the lane has a point
+// (dead lanes form the tail of the wave).  Returns acc for live lanes.
+template <int d, int V>
+__device__ __forceinline__ void slice_wave_dedup(const SetTable &st, const uint64_t (&keys)[d + 1][KeyWords<d>::value],
+                                                 const float (&b)[d + 1], int32_t sdiv, bool live, char *lds,
+                                                 float (&acc)[V])
+{
+    using G = DedupGeom<d, V>;
+    using SG = SlotGeom<KeyWords<d>::value, V>;
+    constexpr int D = G::D;
+    constexpr int KW = G::KW;
+    constexpr int VP = G::VP;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int32_t r = class_shift<D>(sdiv);
+    char *kreg = lds;
+    uint16_t *src = reinterpret_cast<uint16_t *>(lds + G::src_off);
+    uint8_t *ent = reinterpret_cast<uint8_t *>(lds + G::ent_off) + lane * D;
+    uint8_t *fnd = reinterpret_cast<uint8_t *>(lds + G::fnd_off);
+    constexpr int KB = 8 * KW;
+    const int32_t U = wave_runs<d>(keys, r, live, kreg, src, G::C, ent, nullptr);
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[c] = 0.0f;
+    if (U > G::C) {
+        // more runs than the wave's LDS holds (points in no particular order)
+        if (!live) return;
+        if constexpr (ValLayout<V>::m2) {
+            slice_simplex<KW, V, D>(st, keys, b, acc);
+        } else {
+            // one vertex at a time (few registers), the plain slice's arithmetic and order
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                const int64_t slot = find_slot<KW, V>(st, keys[m]);
+                float val[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) val[c] = 0.0f;
+                if (slot >= 0) load_vals<V>(st.vals, (uint32_t)slot * SG::bytes, val);
+                const float w = slot >= 0 ? b[m] : 0.0f;
+#pragma unroll
+                for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
+            }
+        }
+        return;
+    }
+    wave_sync();
+    // look every distinct key up once
+    uint64_t lk[G::NL][KW];
+    bool ll[G::NL];
+#pragma unroll
+    for (int j = 0; j < G::NL; ++j) {
+        const int32_t e = j * 64 + lane;
+        ll[j] = e < U;
+        if (ll[j]) {
+            const uint32_t sc = src[e];
+            lds_get_key<KW>(kreg + ((int32_t)(sc >> 3) * D + (int32_t)(sc & 7u)) * KB, lk[j]);
+        } else {
+#pragma unroll
+            for (int w = 0; w < KW; ++w) lk[j][w] = 0;
+        }
+    }
+    wave_sync();   // the keys are read: their LDS region takes the values now
+    uint32_t off[G::NL];
+    bool found[G::NL];
+    lookup_keys<KW, V, G::NL>(st, lk, ll, off, found);
+    float *vreg = reinterpret_cast<float *>(lds);
+#pragma unroll
+    for (int j = 0; j < G::NL; ++j) {
+        if (ll[j]) {
+            float val[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) val[c] = 0.0f;
+            if (found[j]) load_vals<V>(st.vals, off[j], val);
+            const int32_t e = j * 64 + lane;
+            float4 *dst = reinterpret_cast<float4 *>(vreg + e * VP);
+#pragma unroll
+            for (int q = 0; q < VP / 4; ++q)
+                dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+            fnd[e] = found[j] ? 1 : 0;
+        }
+    }
+    wave_sync();
+    if (!live) return;
+    if constexpr (ValLayout<V>::m2) {
+        float val[D][8];
+        bool fv[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const int32_t e = ent[m];
+            fv[m] = fnd[e] != 0;
+            const float4 *q = reinterpret_cast<const float4 *>(vreg + e * VP);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 f = (h < VP / 4) ? q[h] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                val[m][4 * h] = f.x;
+                val[m][4 * h + 1] = f.y;
+                val[m][4 * h + 2] = f.z;
+                val[m][4 * h + 3] = f.w;
+            }
+        }
+        accumulate_simplex<V, D>(val, fv, b, acc);
+    } else {
+        // the sums of accumulate_simplex, one vertex at a time from LDS
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const int32_t e = ent[m];
+            const float w = fnd[e] != 0 ? b[m] : 0.0f;
+            const float4 *q = reinterpret_cast<const float4 *>(vreg + e * VP);
+            float val[8];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 f = (h < VP / 4) ? q[h] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                val[4 * h] = f.x;
+                val[4 * h + 1] = f.y;
+                val[4 * h + 2] = f.z;
+                val[4 * h + 3] = f.w;
+            }
+#pragma unroll
+            for (int c = 0; c < V; ++c) acc[c] = fmaf(w, val[c], acc[c]);
+        }
+    }
+}
+
+template <int d, int V, bool XF>
+__global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
+{
+    using G = DedupGeom<d, V>;
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    __shared__ __attribute__((aligned(16))) char lds[4 * G::wave_bytes];
+    const int32_t t = logical_tile(a.tm);
+    if (t >= a.tm.n_tiles) return;
+    const int32_t s = tile_segment(a.tm, t);
+    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
+    const int64_t i0 = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t end = a.tm.seg_end[s];
+    if (i0 + (int64_t)(threadIdx.x & ~63u) >= end) return;   // the whole wave is past the segment
+    const bool live = i < end;
+    const SetTable st = a.sets[a.tm.seg_set[s]];
+    float p[d];
+#pragma unroll
+    for (int j = 0; j < d; ++j) p[j] = 0.0f;
+    if (live) {
+        const float px = ld_stream(a.x + i), py = ld_stream(a.y + i), pz = ld_stream(a.z + i);
+        if constexpr (XF) {
+            float m[12];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) m[j] = a.mats[12 * s + j];
+            xform_point(m, px, py, pz, p[0], p[1], p[2]);
+            if constexpr (d == 6)
+                xform_normal(m, ld_stream(a.nx + i), ld_stream(a.ny + i), ld_stream(a.nz + i), p[3], p[4], p[5]);
+        } else {
+            p[0] = px;
+            p[1] = py;
+            p[2] = pz;
+            if constexpr (d == 6) {
+                p[3] = ld_stream(a.nx + i);
+                p[4] = ld_stream(a.ny + i);
+                p[5] = ld_stream(a.nz + i);
+            }
+        }
+    }
+    float kk[d];
+#pragma unroll
+    for (int j = 0; j < d; ++j) kk[j] = st.k[j];
+    uint64_t keys[D][KW];
+    float b[D];
+    int32_t sdiv = 0;
+    const bool ok = embed<d>(p, kk, keys, b, &sdiv);
+    if (live && !ok) atomicOr(a.err + a.err_stride * s, 1);
+    float acc[V];
+    slice_wave_dedup<d, V>(st, keys, b, sdiv, live, lds + (threadIdx.x >> 6) * G::wave_bytes, acc);
+    if (!live) return;
+    st_stream(a.m0 + i, acc[0]);
+    st_stream(a.m1 + i, acc[1]);
+    st_stream(a.m1 + a.M + i, acc[2]);
+    st_stream(a.m1 + 2 * a.M + i, acc[3]);
+    if constexpr (ValLayout<V>::normals) {
+        if (a.ns != nullptr) {
+            st_stream(a.ns + i, acc[4]);
+            st_stream(a.ns + a.M + i, acc[5]);
+            st_stream(a.ns + 2 * a.M + i, acc[6]);
+        }
+    }
+    if constexpr (ValLayout<V>::m2) {
+        if (a.m2 != nullptr) st_stream(a.m2 + i, acc[V - 1]);
+    }
+}
+
 // Fused slice + reduction: every point's M-step terms (Eq. 7 / Eq. 10 in the
 // twist of Eq. 16) are formed right after its slice and the block writes one
 // partial row of the normal equations per tile; M0, M1 and N never leave the
@@ -183,15 +403,75 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
 }
 
 template <int d, int V>
-static void launch_dv(const EstepArgs &a, bool xf, bool touch, int grid, hipStream_t st)
+static void launch_dv(const EstepArgs &a, bool xf, bool touch, int slice, int grid, hipStream_t st)
 {
     if (touch) {
         if (xf) k_estep_touch<d, V, true><<<grid, 256, 0, st>>>(a);
         else k_estep_touch<d, V, false><<<grid, 256, 0, st>>>(a);
+    } else if (slice == FR_SLICE_SHARED) {
+        if (xf) k_estep_dedup<d, V, true><<<grid, 256, 0, st>>>(a);
+        else k_estep_dedup<d, V, false><<<grid, 256, 0, st>>>(a);
     } else {
         if (xf) k_estep<d, V, true><<<grid, 256, 0, st>>>(a);
         else k_estep<d, V, false><<<grid, 256, 0, st>>>(a);
     }
+}
+
+// The slice autotuner: the first launch of each (d, V, transform kind, size
+// class) a context meets is timed in both forms -- they compute the same
+// outputs, so the timing launches are that E-step -- and the faster form is
+// kept in the context's table.  One wait for the stream; nothing is timed
+// while the stream is being captured into a graph.
+template <class Launch>
+static fr_status autotune_slice(fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts, hipStream_t st, Launch &launch,
+                                int &slice)
+{
+    slice = FR_SLICE_PLAIN;
+    if (ctx == nullptr) return FR_OK;
+    int32_t cls = 0;
+    while (cls < 62 && (2ll << cls) <= pts) ++cls;
+    for (const fr_tuning_entry &e : ctx->tuned)
+        if (e.d == d && e.V == V && e.xf_kind == xf_kind && e.size_class == cls) {
+            slice = e.slice;
+            return FR_OK;
+        }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    FR_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return FR_OK;
+    constexpr int kReps = 4;
+    const int cand[2] = {FR_SLICE_PLAIN, FR_SLICE_SHARED};
+    float us[2] = {0.0f, 0.0f};
+    hipEvent_t ev[2];
+    FR_HIP(hipEventCreate(&ev[0]));
+    FR_HIP(hipEventCreate(&ev[1]));
+    fr_status rc = FR_OK;
+    for (int c = 0; c < 2 && rc == FR_OK; ++c) {
+        rc = launch(cand[c]);   // warm-up
+        if (rc != FR_OK) break;
+        if (hipEventRecord(ev[0], st) != hipSuccess) rc = FR_EDEVICE;
+        for (int r = 0; r < kReps && rc == FR_OK; ++r) rc = launch(cand[c]);
+        if (rc == FR_OK && (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(&us[c], ev[0], ev[1]) != hipSuccess))
+            rc = FR_EDEVICE;
+        us[c] *= 1000.0f / kReps;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc != FR_OK) {
+        if (rc == FR_EDEVICE) set_error("slice autotuner: timing events failed");
+        return rc;
+    }
+    fr_tuning_entry e{};
+    e.d = d;
+    e.V = V;
+    e.xf_kind = xf_kind;
+    e.size_class = cls;
+    e.slice = us[1] < us[0] ? FR_SLICE_SHARED : FR_SLICE_PLAIN;
+    e.us_plain = us[0];
+    e.us_shared = us[1];
+    ctx->tuned.push_back(e);
+    slice = e.slice;
+    return FR_OK;
 }
 
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
@@ -221,20 +501,26 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
     a.err_stride = err_stride;
     const bool xf = xf_kind != FR_XF_NONE;
     const bool touch = touched != nullptr;
-    if (d == 3 && V == 4) launch_dv<3, 4>(a, xf, touch, plan.grid, st);
-    else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, plan.grid, st);
-    else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, plan.grid, st);
-    else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, plan.grid, st);
-    else if (d == 3 && V == 5) launch_dv<3, 5>(a, xf, touch, plan.grid, st);
-    else if (d == 3 && V == 8) launch_dv<3, 8>(a, xf, touch, plan.grid, st);
-    else if (d == 6 && V == 5) launch_dv<6, 5>(a, xf, touch, plan.grid, st);
-    else if (d == 6 && V == 8) launch_dv<6, 8>(a, xf, touch, plan.grid, st);
-    else {
-        set_error("fr_estep: unsupported lattice d=%d V=%d", d, V);
-        return FR_EINVAL;
-    }
-    FR_HIP(hipGetLastError());
-    return FR_OK;
+    auto launch = [&](int slice) -> fr_status {
+        if (d == 3 && V == 4) launch_dv<3, 4>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 3 && V == 5) launch_dv<3, 5>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 3 && V == 8) launch_dv<3, 8>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 6 && V == 5) launch_dv<6, 5>(a, xf, touch, slice, plan.grid, st);
+        else if (d == 6 && V == 8) launch_dv<6, 8>(a, xf, touch, slice, plan.grid, st);
+        else {
+            set_error("fr_estep: unsupported lattice d=%d V=%d", d, V);
+            return FR_EINVAL;
+        }
+        FR_HIP(hipGetLastError());
+        return FR_OK;
+    };
+    int slice = touch ? FR_SLICE_PLAIN : plan.slice;
+    if (slice == FR_SLICE_AUTO)
+        FR_TRY(autotune_slice(plan.ctx, d, V, xf_kind, (int64_t)plan.n_tiles * plan.tile, st, launch, slice));
+    return launch(slice);
 }
 
 template <int d, int V>

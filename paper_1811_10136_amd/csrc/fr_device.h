@@ -246,9 +246,13 @@ __device__ __forceinline__ bool key_equal(const uint64_t (&a)[KW], const uint64_
 // field of word 0); vertex m's key is vertex m-1's plus +1 in every field and
 // -D in the field of the coordinate of rank d - m + 1.  Returns false if a
 // coordinate leaves the packed range.
+// s_out receives s: every coordinate of vertex m is congruent to m - s
+// modulo D, so equal keys of two points sit at vertex indices that differ by
+// the difference of their s (mod D).
 template <int d>
 __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
-                                      uint64_t (&keys)[d + 1][KeyWords<d>::value], float (&b)[d + 1])
+                                      uint64_t (&keys)[d + 1][KeyWords<d>::value], float (&b)[d + 1],
+                                      int32_t *s_out = nullptr)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -285,6 +289,7 @@ __device__ __forceinline__ bool embed(const float (&p)[d], const float (&k)[d],
         sum_g += g[j];
     }
     const int32_t s = sum_g / D;
+    if (s_out != nullptr) *s_out = s;
 
     int32_t rank[D];
 #pragma unroll
@@ -500,48 +505,51 @@ __device__ __forceinline__ void load_vals(const float *__restrict__ vb, uint32_t
     val[7] = __uint_as_float(q1.w);
 }
 
-// Slice one point.  Level 1 reads both key slots of every vertex's first
-// bucket (one line each); level 2, where a first bucket is full without the
-// key, both key slots of the second bucket; level 3 the values of every
-// vertex found, from a line the lookup has just fetched.  A vertex absent from
-// the lattice contributes nothing; vertices accumulate in order, each as
-// w * value with w = b or 0.  For the |y|^2 layouts the last channel comes out
-// as the second moment about the target, sum_k K |y_k - t|^2 with t = M1 / M0
-// (0 without support).
-template <int KW, int V, int D>
-__device__ __forceinline__ void slice_simplex(const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
-                                              float (&acc)[V])
+// Lookup of NL keys (live[v] == false: no key, nothing read).  Level 1 reads
+// both key slots of every key's first bucket (one line each); level 2, where
+// a first bucket is full without the key, both key slots of the second
+// bucket.  off[v] is the byte offset of the slot found (found[v]).
+template <int KW, int V, int NL>
+__device__ __forceinline__ void lookup_keys(const SetTable &st, const uint64_t (&keys)[NL][KW], const bool (&live)[NL],
+                                            uint32_t (&off)[NL], bool (&found)[NL])
 {
     using G = SlotGeom<KW, V>;
     const uint64_t *__restrict__ kb = st.keys;
-    const float *__restrict__ vb = st.vals;
     const uint32_t nb = st.cap >> 1;
-    uint32_t off[D], alt[D];
-    uint64_t k0[D][KW], k1[D][KW];
-    bool found[D], second[D];
+    uint32_t alt[NL];
+    uint64_t k0[NL][KW], k1[NL][KW];
+    bool second[NL];
 #pragma unroll
-    for (int v = 0; v < D; ++v) {
-        uint32_t b1, b2;
-        key_buckets<KW>(keys[v], st.seed, nb, b1, b2);
-        off[v] = b1 * G::bucket;
-        alt[v] = b2 * G::bucket;
-        load_key<KW>(kb, off[v], k0[v]);
-        load_key<KW>(kb, off[v] + G::bytes, k1[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < D; ++v) {
-        const bool e0 = key_equal<KW>(k0[v], keys[v]);
-        const bool e1 = key_equal<KW>(k1[v], keys[v]);
-        found[v] = e0 || e1;
-        second[v] = !found[v] && k0[v][0] != kKeyEmpty && k1[v][0] != kKeyEmpty;
-        off[v] += e1 ? G::bytes : 0u;
-        if (second[v]) {
-            load_key<KW>(kb, alt[v], k0[v]);
-            load_key<KW>(kb, alt[v] + G::bytes, k1[v]);
+    for (int v = 0; v < NL; ++v) {
+        off[v] = 0u;
+        alt[v] = 0u;
+        if (live[v]) {
+            uint32_t b1, b2;
+            key_buckets<KW>(keys[v], st.seed, nb, b1, b2);
+            off[v] = b1 * G::bucket;
+            alt[v] = b2 * G::bucket;
+            load_key<KW>(kb, off[v], k0[v]);
+            load_key<KW>(kb, off[v] + G::bytes, k1[v]);
         }
     }
 #pragma unroll
-    for (int v = 0; v < D; ++v) {
+    for (int v = 0; v < NL; ++v) {
+        found[v] = false;
+        second[v] = false;
+        if (live[v]) {
+            const bool e0 = key_equal<KW>(k0[v], keys[v]);
+            const bool e1 = key_equal<KW>(k1[v], keys[v]);
+            found[v] = e0 || e1;
+            second[v] = !found[v] && k0[v][0] != kKeyEmpty && k1[v][0] != kKeyEmpty;
+            off[v] += e1 ? G::bytes : 0u;
+            if (second[v]) {
+                load_key<KW>(kb, alt[v], k0[v]);
+                load_key<KW>(kb, alt[v] + G::bytes, k1[v]);
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NL; ++v) {
         if (second[v]) {
             const bool e0 = key_equal<KW>(k0[v], keys[v]);
             const bool e1 = key_equal<KW>(k1[v], keys[v]);
@@ -549,13 +557,17 @@ __device__ __forceinline__ void slice_simplex(const SetTable &st, const uint64_t
             off[v] = alt[v] + (e1 ? G::bytes : 0u);
         }
     }
-    float val[D][8];
-#pragma unroll
-    for (int v = 0; v < D; ++v) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) val[v][c] = 0.0f;
-        if (found[v]) load_vals<V>(vb, off[v], val[v]);
-    }
+}
+
+// Slice sums of one point from the values of its D vertices (val[v] = 0 and
+// found[v] == false for a vertex absent from the lattice): vertices
+// accumulate in order v = 0..d, each as w * value with w = b or 0.  For the
+// |y|^2 layouts the last channel comes out as the second moment about the
+// target, sum_k K |y_k - t|^2 with t = M1 / M0 (0 without support).
+template <int V, int D>
+__device__ __forceinline__ void accumulate_simplex(const float (&val)[D][8], const bool (&found)[D],
+                                                   const float (&b)[D], float (&acc)[V])
+{
     float vw[D];
 #pragma unroll
     for (int v = 0; v < D; ++v) {
@@ -579,6 +591,137 @@ __device__ __forceinline__ void slice_simplex(const SetTable &st, const uint64_t
             }
         }
     }
+}
+
+// Slice one point: look its D vertices up (all first buckets at once, then
+// the second buckets needed), read the values of the vertices found from the
+// lines just fetched, and accumulate.  A vertex absent from the lattice
+// contributes nothing.
+template <int KW, int V, int D>
+__device__ __forceinline__ void slice_simplex(const SetTable &st, const uint64_t (&keys)[D][KW], const float (&b)[D],
+                                              float (&acc)[V])
+{
+    const float *__restrict__ vb = st.vals;
+    bool live[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) live[v] = true;
+    uint32_t off[D];
+    bool found[D];
+    lookup_keys<KW, V, D>(st, keys, live, off, found);
+    float val[D][8];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) val[v][c] = 0.0f;
+        if (found[v]) load_vals<V>(vb, off[v], val[v]);
+    }
+    accumulate_simplex<V, D>(val, found, b, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Runs of shared vertices along a wavefront.
+//
+// Consecutive points of a range-image scan lie side by side on the surface,
+// so their simplices share most vertices.  Vertex m of a point has every
+// coordinate congruent to m - s (mod D) (see embed), so its key can only equal
+// the previous point's vertex of the same class c = (m - s) mod D.  Along the
+// 64 lanes of a wave (lane = point), the vertices of one class form runs of
+// equal keys; a run starts at a lane whose class-c key differs from the
+// previous lane's (lane 0 starts a run in every class).  Runs are numbered
+// class by class, and by start lane within a class: entry e of the wave.
+// ---------------------------------------------------------------------------
+
+// Orders the LDS accesses of the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int KW>
+__device__ __forceinline__ void lds_put_key(char *p, const uint64_t (&k)[KW])
+{
+#pragma unroll
+    for (int w = 0; w < KW; ++w) reinterpret_cast<uint64_t *>(p)[w] = k[w];
+}
+template <int KW>
+__device__ __forceinline__ void lds_get_key(const char *p, uint64_t (&k)[KW])
+{
+#pragma unroll
+    for (int w = 0; w < KW; ++w) k[w] = reinterpret_cast<const uint64_t *>(p)[w];
+}
+
+// Bytes of the key region of a wave: 64 lanes x D classes x KW words.
+template <int d> struct WaveKeys {
+    static constexpr int D = d + 1;
+    static constexpr int KW = KeyWords<d>::value;
+    static constexpr int bytes = 64 * D * KW * 8;
+};
+
+// Class of vertex m: (m - r) mod D with r = s mod D.
+template <int D>
+__device__ __forceinline__ int32_t class_shift(int32_t sdiv)
+{
+    int32_t r = sdiv % D;
+    return r + (r < 0 ? D : 0);
+}
+
+// Finds the runs of the wave.  live: the lane has a point (dead lanes form
+// the tail of the wave).  kreg (LDS, WaveKeys<d>::bytes) receives every live
+// lane's keys at [lane][class].  Each run start writes (lane << 3) | class at
+// src[e] if e < src_cap; with ent != NULL every live lane writes the entry of
+// the run holding its vertex m at ent[m] (valid when U <= 256, the only case
+// its callers read it); with hc != NULL lane 0 writes the
+// run-start mask of class c at hc[c].  Returns the number of runs U (uniform).
+template <int d>
+__device__ __forceinline__ int32_t wave_runs(const uint64_t (&keys)[d + 1][KeyWords<d>::value], int32_t r, bool live,
+                                             char *kreg, uint16_t *src, int32_t src_cap, uint8_t *ent,
+                                             uint64_t *hc)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    constexpr int KB = 8 * KW;
+    const int lane = (int)(threadIdx.x & 63u);
+    if (live) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            int32_t c = m - r;
+            c += c < 0 ? D : 0;
+            lds_put_key<KW>(kreg + (lane * D + c) * KB, keys[m]);
+        }
+    }
+    wave_sync();
+    uint32_t hmask = 0;
+    if (live) {
+        if (lane == 0) {
+            hmask = (1u << D) - 1u;
+        } else {
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                int32_t c = m - r;
+                c += c < 0 ? D : 0;
+                uint64_t pk[KW];
+                lds_get_key<KW>(kreg + ((lane - 1) * D + c) * KB, pk);
+                hmask |= key_equal<KW>(pk, keys[m]) ? 0u : (1u << m);
+            }
+        }
+    }
+    int32_t U = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        int32_t mc = c + r;
+        mc -= mc >= D ? D : 0;
+        const bool bit = live && ((hmask >> mc) & 1u);
+        const uint64_t H = __ballot(bit);
+        const int32_t below = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(H >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)H, 0u));
+        if (bit && U + below < src_cap) src[U + below] = (uint16_t)((lane << 3) | c);
+        if (ent != nullptr && live) ent[mc] = (uint8_t)(U + below + (bit ? 0 : -1));
+        if (hc != nullptr && lane == 0) hc[c] = H;
+        U += (int32_t)__popcll(H);
+    }
+    return U;
 }
 
 // Slot of a key in a set's table (relative to the set's first slot), or -1.

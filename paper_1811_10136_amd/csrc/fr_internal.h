@@ -74,6 +74,9 @@ struct fr_ctx {
     // first provisional table of the next one (loops that rebuild at a
     // shrinking scale see most records carry keys of their own)
     double vertex_ratio = 0.0;
+    // kernel choices: the fixed choice (fr_ctx_set_tuning) and the autotuner's table
+    int32_t slice_mode = FR_SLICE_AUTO;
+    std::vector<fr_tuning_entry> tuned;
 };
 
 struct fr_lattice {
@@ -179,6 +182,8 @@ struct Plan {
     DevBuf meta;                    // device: seg_off | seg_tile | seg_set | seg_c | mats of NONE
     TileMap tm{};
     const float *seg_c = nullptr;   // device, per segment outlier constant (reduce only)
+    int32_t slice = FR_SLICE_AUTO;  // E-step slice kernel (FR_SLICE_*; AUTO: the context's autotuner)
+    fr_ctx *ctx = nullptr;          // context of the plan (autotuner table)
 };
 
 // Build a plan for `model_ref` segmented per `xf` (NULL = per set).

@@ -258,66 +258,198 @@ struct Pts {
     const float *x, *y, *z, *nx, *ny, *nz;
 };
 
-// One thread per observation point: the D (key, weight) records of its
-// simplex.  Records are r = point * D + m; the block stages its 256 * D
-// records in LDS so the global writes are contiguous.
+// Partial records (d <= 6).  Neighbouring observation points of a scan share
+// most simplex vertices; a wave of 64 points finds its runs of shared
+// vertices (wave_runs) and emits one partial record per run: the key, the
+// number of incidences (the run's length) and the sums over the run's points,
+// in lane order and binary64, of b [1, y, n_y] (and b |y|^2 for the variance
+// layouts).  A depth frame has about one run per four incidences, so the
+// insertion, sort and sums that follow handle a quarter of the D N records.
+// Partials are numbered wave by wave (run order within a wave), so that their
+// order -- and with it every sum -- is fixed by the input alone.
+template <int V> struct PartialType { using T = float; };
+template <> struct PartialType<5> { using T = double; };   // |y|^2 layouts: the scatter about the
+template <> struct PartialType<8> { using T = double; };   // mean is formed after the sums
+
 template <int d>
-__global__ void __launch_bounds__(256) k_embed_obs(Pts pts, TileMap tm, const float *kset, uint64_t *rec_key,
-                                                  float *rec_b, size_t R, int32_t *err, const int64_t *valued_end)
+__device__ __forceinline__ void load_feature(const Pts &pts, int64_t i, float (&p)[d])
+{
+    p[0] = pts.x[i];
+    p[1] = pts.y[i];
+    p[2] = pts.z[i];
+    if constexpr (d == 6) {
+        p[3] = pts.nx[i];
+        p[4] = pts.ny[i];
+        p[5] = pts.nz[i];
+    }
+}
+
+// Count pass: the runs of every wave (4 waves per tile of 256 points; a wave
+// past its set's end counts 0).
+template <int d>
+__global__ void __launch_bounds__(256) k_build_count(Pts pts, TileMap tm, const float *kset, uint32_t *wave_cnt,
+                                                    int32_t *err)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    __shared__ uint64_t s_key[KW][256 * D];
-    __shared__ float s_b[256 * D];
+    __shared__ __attribute__((aligned(16))) char lds[4][WaveKeys<d>::bytes];
+    __shared__ uint16_t no_src[4];
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;
     const int32_t s = tile_segment(tm, t);
-    const int64_t first = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile;
-    const int64_t i = first + threadIdx.x;
-    const int64_t n_here = min((int64_t)tm.tile, tm.seg_end[s] - first);
-    if (i < tm.seg_end[s]) {
-        float p[d];
-        float kk[d];
+    const int wv = (int)(threadIdx.x >> 6);
+    const int64_t i0 = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + 64 * wv;
+    const int64_t end = tm.seg_end[s];
+    const int64_t i = i0 + (threadIdx.x & 63u);
+    if (i0 >= end) {
+        if ((threadIdx.x & 63u) == 0) wave_cnt[4 * (size_t)t + wv] = 0;
+        return;
+    }
+    const bool live = i < end;
+    float p[d], kk[d];
 #pragma unroll
-        for (int j = 0; j < d; ++j) kk[j] = kset[8 * s + j];
-        p[0] = pts.x[i];
-        p[1] = pts.y[i];
-        p[2] = pts.z[i];
-        if constexpr (d == 6) {
-            p[3] = pts.nx[i];
-            p[4] = pts.ny[i];
-            p[5] = pts.nz[i];
+    for (int j = 0; j < d; ++j) {
+        kk[j] = kset[8 * s + j];
+        p[j] = 0.0f;
+    }
+    if (live) load_feature<d>(pts, i, p);
+    uint64_t keys[D][KW];
+    float b[D];
+    int32_t sdiv = 0;
+    if (!embed<d>(p, kk, keys, b, &sdiv) && live) atomicOr(err, 1);
+    const int32_t U = wave_runs<d>(keys, class_shift<D>(sdiv), live, lds[wv], no_src, 0, nullptr, nullptr);
+    if ((threadIdx.x & 63u) == 0) wave_cnt[4 * (size_t)t + wv] = (uint32_t)U;
+}
+
+// Partial pass: the same runs, their sums, written at the wave's offset
+// (exclusive scan of the counts).  Points past valued_end[s] create their
+// vertices but carry no value.
+template <int d, int V> struct PartialLds {
+    static constexpr int D = d + 1;
+    static constexpr int NCH = ValLayout<V>::normals ? 6 : 3;   // point values after the 1: y (and n_y)
+    static constexpr int keys = WaveKeys<d>::bytes;
+    static constexpr int src = keys;                           // u16 per run, up to 64 D
+    static constexpr int hc = src + ((2 * 64 * D + 7) / 8) * 8; // u64 per class
+    static constexpr int bw = hc + 8 * D;                      // float [lane][class]: b
+    static constexpr int pv = bw + 4 * 64 * D;                 // float [lane][NCH]: y, n_y
+    static constexpr int bytes = pv + 4 * 64 * NCH;
+};
+
+template <int d, int V>
+__global__ void __launch_bounds__(256) k_build_partials(Pts pts, TileMap tm, const float *kset,
+                                                       const uint32_t *wave_off, uint64_t *pkey, uint32_t *pcnt,
+                                                       typename PartialType<V>::T *pval, size_t P,
+                                                       const int64_t *valued_end)
+{
+    using T = typename PartialType<V>::T;
+    using L = PartialLds<d, V>;
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    constexpr int NCH = L::NCH;
+    __shared__ __attribute__((aligned(16))) char lds_all[4][L::bytes];
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;
+    const int32_t s = tile_segment(tm, t);
+    const int wv = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t i0 = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + 64 * wv;
+    const int64_t end = tm.seg_end[s];
+    if (i0 >= end) return;
+    const int64_t i = i0 + lane;
+    const bool live = i < end;
+    char *lds = lds_all[wv];
+    uint16_t *src = reinterpret_cast<uint16_t *>(lds + L::src);
+    uint64_t *hc = reinterpret_cast<uint64_t *>(lds + L::hc);
+    float *bw = reinterpret_cast<float *>(lds + L::bw);
+    float *pv = reinterpret_cast<float *>(lds + L::pv);
+    float p[d], kk[d];
+#pragma unroll
+    for (int j = 0; j < d; ++j) {
+        kk[j] = kset[8 * s + j];
+        p[j] = 0.0f;
+    }
+    float val[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) val[c] = 0.0f;
+    if (live) {
+        load_feature<d>(pts, i, p);
+        val[0] = pts.x[i];
+        val[1] = pts.y[i];
+        val[2] = pts.z[i];
+        if constexpr (NCH == 6) {
+            val[3] = pts.nx[i];
+            val[4] = pts.ny[i];
+            val[5] = pts.nz[i];
         }
-        uint64_t keys[D][KW];
-        float b[D];
-        if (!embed<d>(p, kk, keys, b)) atomicOr(err, 1);
-        // points past valued_end[s] create their vertices but carry no value
+    }
+    uint64_t keys[D][KW];
+    float b[D];
+    int32_t sdiv = 0;
+    embed<d>(p, kk, keys, b, &sdiv);   // range errors were raised by the count pass
+    const int32_t r = class_shift<D>(sdiv);
+    if (live) {
         const float keep = (valued_end == nullptr || i < valued_end[s]) ? 1.0f : 0.0f;
 #pragma unroll
-        for (int v = 0; v < D; ++v) b[v] *= keep;
-#pragma unroll
-        for (int v = 0; v < D; ++v) {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) s_key[w][threadIdx.x * D + v] = keys[v][w];
-            s_b[threadIdx.x * D + v] = b[v];
+        for (int m = 0; m < D; ++m) {
+            int32_t c = m - r;
+            c += c < 0 ? D : 0;
+            bw[lane * D + c] = b[m] * keep;
         }
-    }
-    __syncthreads();
-    const size_t r0 = (size_t)first * D;
-    const int nrec = (int)n_here * D;
-    for (int q = threadIdx.x; q < nrec; q += 256) {
 #pragma unroll
-        for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r0 + q] = s_key[w][q];
-        rec_b[r0 + q] = s_b[q];
+        for (int c = 0; c < NCH; ++c) pv[lane * NCH + c] = val[c];
     }
+    const int32_t U = wave_runs<d>(keys, r, live, lds, src, 64 * D, nullptr, hc);
+    wave_sync();
+    const int32_t n_live = (int32_t)__popcll(__ballot(live));
+    const size_t base = wave_off[4 * (size_t)t + wv];
+    for (int32_t e = lane; e < U; e += 64) {
+        const uint32_t sc = src[e];
+        const int32_t o = (int32_t)(sc >> 3), c = (int32_t)(sc & 7u);
+        const uint64_t above = hc[c] & ~((2ull << o) - 1ull);   // run starts of class c after lane o
+        const int32_t stop = above != 0ull ? (int32_t)__builtin_ctzll(above) : n_live;
+        double acc[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] = 0.0;
+        for (int32_t l = o; l < stop; ++l) {
+            const double w = (double)bw[l * D + c];
+            acc[0] += w;
+            double y2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const double y = (double)pv[l * NCH + q];
+                acc[1 + q] += w * y;
+                if (q < 3) y2 += y * y;
+            }
+            if constexpr (ValLayout<V>::m2) acc[V - 1] += w * y2;
+        }
+        uint64_t key[KW];
+        lds_get_key<KW>(lds + (o * D + c) * 8 * KW, key);
+        const size_t q = base + (size_t)e;
+#pragma unroll
+        for (int w = 0; w < KW; ++w) pkey[(size_t)w * P + q] = key[w];
+        pcnt[q] = (uint32_t)(stop - o);
+#pragma unroll
+        for (int ch = 0; ch < V; ++ch) pval[(size_t)ch * P + q] = (T)acc[ch];
+    }
+}
+
+// Set boundaries of the partials: the offset of each set's first wave.
+__global__ void k_set_partial_off(int32_t n_sets, const int32_t *seg_tile, const uint32_t *wave_off,
+                                  uint32_t *set_off)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_sets) return;
+    set_off[s] = wave_off[4 * (size_t)seg_tile[s]];
 }
 
 // Descriptor lattices: one thread per observation point writes its D records
 // straight to memory (D * KW words are too many to stage in LDS), producing the
-// vertices one at a time.
+// vertices one at a time; each record is a partial of one incidence, values
+// b [1, y] (binary32 products).
 template <int d>
-__global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const float *kf, TileMap tm,
-                                                   uint64_t *rec_key, float *rec_b, size_t R, int32_t *err)
+__global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const float *kf, TileMap tm, Pts pts,
+                                                   uint64_t *rec_key, uint32_t *rec_cnt, float *rec_val, size_t R,
+                                                   int32_t *err)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -342,12 +474,17 @@ __global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const flo
     embed_hd_init<d>(p, kk, h);
     if (!h.ok) atomicOr(err, 1);
     const size_t r0 = (size_t)i * D;
+    const float y0 = pts.x[i], y1 = pts.y[i], y2 = pts.z[i];
 #pragma unroll 1
     for (int m = 0; m < D; ++m) {   // one vertex at a time: keeps the key walk in registers
         const float b = embed_hd_next<d>(h, m);
 #pragma unroll
         for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r0 + m] = h.P[w];
-        rec_b[r0 + m] = b;
+        rec_cnt[r0 + m] = 1u;
+        rec_val[r0 + m] = b;
+        rec_val[R + r0 + m] = b * y0;
+        rec_val[2 * R + r0 + m] = b * y1;
+        rec_val[3 * R + r0 + m] = b * y2;
     }
 }
 
@@ -480,7 +617,7 @@ __global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t 
     rid[r] = (uint32_t)r;
 }
 
-// Sorted mode: segment starts and lengths of the vertex-sorted records.
+// Sorted mode: segment starts and lengths of the vertex-sorted partials.
 __global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t *rvid_sorted, uint32_t *voff)
 {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -489,77 +626,38 @@ __global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t 
     if (q == 0 || rvid_sorted[q - 1] != v) voff[v] = (uint32_t)q;
 }
 
-__global__ void __launch_bounds__(256) k_segment_lengths(size_t NV, size_t R, const uint32_t *voff, uint32_t *vocc)
-{
-    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= NV) return;
-    vocc[v] = (uint32_t)((v + 1 < NV ? voff[v + 1] : (uint32_t)R) - voff[v]);
-}
-
-// Sorted mode: the splatted point values, one or two float4 per point
-// ([y, n_x], [n_y, n_z, 0, 0] with normals, else [y, 0]), so the per-vertex
-// sums gather a point with one or two loads instead of six.
-template <int V> struct PointRow { static constexpr int words = ValLayout<V>::normals ? 2 : 1; };
-
-template <int V>
-__global__ void __launch_bounds__(256) k_point_rows(size_t N, Pts pts, float4 *rows)
-{
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if constexpr (ValLayout<V>::normals) {
-        rows[2 * i] = make_float4(pts.x[i], pts.y[i], pts.z[i], pts.nx[i]);
-        rows[2 * i + 1] = make_float4(pts.ny[i], pts.nz[i], 0.0f, 0.0f);
-    } else {
-        rows[i] = make_float4(pts.x[i], pts.y[i], pts.z[i], 0.0f);
-    }
-}
-
-// Sorted mode: ordered binary64 sums per vertex.  Vertex ids follow the
-// owner records, so neighbouring threads gather from neighbouring points;
-// record ids are fetched four at a time so the dependent gathers overlap.
-template <int D, int V>
-__global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint32_t *voff, const uint32_t *vocc,
-                                                          const uint32_t *rid_sorted, const float *rec_b,
-                                                          const float4 *rows, float *vval)
+// Sorted mode: per vertex, the partials in partial order summed in binary64
+// (occupancy = the sum of their incidence counts) -> bitwise deterministic.
+template <int V, typename T>
+__global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, const uint32_t *voff,
+                                                          const uint32_t *rid_sorted, const uint32_t *pcnt,
+                                                          const T *pval, float *vval, uint32_t *vocc)
 {
     const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= NV) return;
     double acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0;
-    const uint32_t q0 = voff[v], q1 = q0 + vocc[v];
+    uint32_t occ = 0;
+    const uint32_t q0 = voff[v], q1 = v + 1 < NV ? voff[v + 1] : (uint32_t)P;
     for (uint32_t q = q0; q < q1; q += 4) {
         uint32_t r[4];
-        float bw[4], val[4][V - 1];
 #pragma unroll
         for (int u = 0; u < 4; ++u) r[u] = (q + u < q1) ? rid_sorted[q + u] : rid_sorted[q0];
+        T val[4][V];
+        uint32_t cnt[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint32_t i = r[u] / D;
-            bw[u] = (q + u < q1) ? rec_b[r[u]] : 0.0f;
-            const float4 a = rows[(size_t)PointRow<V>::words * i];
-            val[u][0] = a.x;
-            val[u][1] = a.y;
-            val[u][2] = a.z;
-            if constexpr (ValLayout<V>::normals) {
-                const float4 c = rows[2 * (size_t)i + 1];
-                val[u][3] = a.w;
-                val[u][4] = c.x;
-                val[u][5] = c.y;
-            }
+            cnt[u] = pcnt[r[u]];
+#pragma unroll
+            for (int c = 0; c < V; ++c) val[u][c] = pval[(size_t)c * P + r[u]];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (q + u >= q1) break;
-            const double w = (double)bw[u];
-            acc[0] += w;
-            constexpr int NL = ValLayout<V>::m2 ? V - 2 : V - 1;   // linear channels after the 1
+            occ += cnt[u];
 #pragma unroll
-            for (int c = 0; c < NL; ++c) acc[1 + c] += w * (double)val[u][c];
-            if constexpr (ValLayout<V>::m2) {
-                const double y0 = val[u][0], y1 = val[u][1], y2 = val[u][2];
-                acc[V - 1] += w * (y0 * y0 + y1 * y1 + y2 * y2);
-            }
+            for (int c = 0; c < V; ++c) acc[c] += (double)val[u][c];
         }
     }
     if constexpr (ValLayout<V>::m2) {
@@ -568,53 +666,50 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
         const double q = acc[0] > 0.0 ? (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0] : 0.0;
         acc[V - 1] = fmax(acc[V - 1] - q, 0.0);
     }
+    vocc[v] = occ;
 #pragma unroll
     for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = (float)acc[c];
 }
 
-// Atomic mode: one thread per record, binary32 hardware atomics; occupancy by
-// integer atomics.
-template <int D, int V>
-__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t R, const uint32_t *rec_slot, const uint32_t *slot_vid,
-                                                          const float *rec_b, Pts pts, float *vval, uint32_t *vocc,
-                                                          size_t NV)
+// Atomic mode: one thread per partial, binary32 hardware atomics of its sums;
+// occupancy by integer atomics.  The |y|^2 channel waits for the second pass.
+template <int V, typename T>
+__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint32_t *rec_slot,
+                                                          const uint32_t *slot_vid, const uint32_t *pcnt,
+                                                          const T *pval, float *vval, uint32_t *vocc, size_t NV)
 {
-    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const uint32_t v = slot_vid[rec_slot[r]];
-    const size_t i = r / D;
-    const float bw = rec_b[r];
-    atomicAdd(&vocc[v], 1u);
-    unsafeAtomicAdd(&vval[v], bw);
-    unsafeAtomicAdd(&vval[NV + v], bw * pts.x[i]);
-    unsafeAtomicAdd(&vval[2 * NV + v], bw * pts.y[i]);
-    unsafeAtomicAdd(&vval[3 * NV + v], bw * pts.z[i]);
-    if constexpr (ValLayout<V>::normals) {
-        unsafeAtomicAdd(&vval[4 * NV + v], bw * pts.nx[i]);
-        unsafeAtomicAdd(&vval[5 * NV + v], bw * pts.ny[i]);
-        unsafeAtomicAdd(&vval[6 * NV + v], bw * pts.nz[i]);
-    }
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const uint32_t v = slot_vid[rec_slot[q]];
+    atomicAdd(&vocc[v], pcnt[q]);
+    constexpr int NL = ValLayout<V>::m2 ? V - 1 : V;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) unsafeAtomicAdd(&vval[(size_t)c * NV + v], (float)pval[(size_t)c * P + q]);
 }
 
-// Atomic mode, |y|^2 layouts: second pass once the means are complete, adding
-// b |y - mu_v|^2 about the vertex mean mu_v = M1_v / W_v (the scatter that the
-// sorted mode keeps; about a mean rounded to binary32 it is larger by
+// Atomic mode, |y|^2 layouts: second pass once the means are complete.  A
+// partial p adds its own scatter S_p = Q_p - |M1_p|^2 / W_p plus
+// W_p |mu_p - mu_v|^2 about the vertex mean mu_v = M1_v / W_v (the parallel
+// form of the scatter; about a mean rounded to binary32 it is larger by
 // W |mu - mu'|^2, far below the binary32 resolution of the sum).
-template <int D, int V>
-__global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t R, const uint32_t *rec_slot,
-                                                              const uint32_t *slot_vid, const float *rec_b, Pts pts,
-                                                              float *vval, size_t NV)
+template <int V, typename T>
+__global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t P, const uint32_t *rec_slot,
+                                                              const uint32_t *slot_vid, const T *pval, float *vval,
+                                                              size_t NV)
 {
-    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const uint32_t v = slot_vid[rec_slot[r]];
-    const size_t i = r / D;
-    const float W = vval[v];
-    const float inv = W > 0.0f ? 1.0f / W : 0.0f;
-    const float dx = pts.x[i] - vval[NV + v] * inv;
-    const float dy = pts.y[i] - vval[2 * NV + v] * inv;
-    const float dz = pts.z[i] - vval[3 * NV + v] * inv;
-    unsafeAtomicAdd(&vval[(size_t)(V - 1) * NV + v], rec_b[r] * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const uint32_t v = slot_vid[rec_slot[q]];
+    const double W = (double)pval[q];
+    if (!(W > 0.0)) return;
+    const double m1x = (double)pval[P + q], m1y = (double)pval[2 * P + q], m1z = (double)pval[3 * P + q];
+    const double own = fmax((double)pval[(size_t)(V - 1) * P + q] - (m1x * m1x + m1y * m1y + m1z * m1z) / W, 0.0);
+    const float Wv = vval[v];
+    const double iv = Wv > 0.0f ? 1.0 / (double)Wv : 0.0;
+    const double dx = m1x / W - (double)vval[NV + v] * iv;
+    const double dy = m1y / W - (double)vval[2 * NV + v] * iv;
+    const double dz = m1z / W - (double)vval[3 * NV + v] * iv;
+    unsafeAtomicAdd(&vval[(size_t)(V - 1) * NV + v], (float)(own + W * (dx * dx + dy * dy + dz * dz)));
 }
 
 // Bucketed two-choice cuckoo insertion of the vertices of each set (one
@@ -781,41 +876,81 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         return FR_EINVAL;
     }
     Pts pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
+    using T = typename PartialType<V>::T;
 
-    DevBuf rec_key, rec_b, rec_slot, own1, t1_d, ptmap, rtmap, fail;
-    FR_TRY(rec_key.alloc(ctx, R * KW * sizeof(uint64_t)));
-    FR_TRY(rec_b.alloc(ctx, R * sizeof(float)));
-    FR_TRY(rec_slot.alloc(ctx, R * sizeof(uint32_t)));
+    DevBuf rec_key, rec_cnt, rec_val, rec_slot, own1, t1_d, ptmap, rtmap, fail;
     FR_TRY(fail.alloc(ctx, sizeof(int32_t)));
     FR_TRY(t1_d.alloc(ctx, S * sizeof(SetTable)));
     FR_HIP(hipMemsetAsync(lat->err_d, 0, sizeof(int32_t), st));
 
-    // 1. embed
+    // 1. embed: partial records (the runs of each wave, d <= 6; one per
+    //    incidence for descriptors); roff = the partials of each set
     std::vector<int64_t> poff(obs->offsets, obs->offsets + S + 1);
     TileMap ptm{}, rtm{};
     FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm));
     DevBuf kset_d;
     FR_TRY(kset_d.alloc(ctx, lat->kset.size() * sizeof(float)));
     FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    if (ptm.n_tiles > 0) {
-        if constexpr (d > 6) {
-            k_embed_feat<d><<<ptm.n_tiles, 256, 0, st>>>(feat, lat->kfeat_d, ptm, rec_key.as<uint64_t>(),
-                                                         rec_b.as<float>(), R, lat->err_d);
-        } else {
-            k_embed_obs<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), rec_key.as<uint64_t>(),
-                                                        rec_b.as<float>(), R, lat->err_d, valued_end);
+    std::vector<int64_t> roff(S + 1);
+    size_t P = 0;   // partial records
+    if constexpr (d > 6) {
+        P = R;
+        for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
+        FR_TRY(rec_key.alloc(ctx, P * KW * sizeof(uint64_t)));
+        FR_TRY(rec_cnt.alloc(ctx, P * sizeof(uint32_t)));
+        FR_TRY(rec_val.alloc(ctx, P * V * sizeof(T)));
+        if (ptm.n_tiles > 0) {
+            k_embed_feat<d><<<ptm.n_tiles, 256, 0, st>>>(feat, lat->kfeat_d, ptm, pts, rec_key.as<uint64_t>(),
+                                                         rec_cnt.as<uint32_t>(), rec_val.as<float>(), P,
+                                                         lat->err_d);
+            FR_HIP(hipGetLastError());
         }
+    } else {
+        const size_t n_waves = (size_t)ptm.n_tiles * 4;
+        DevBuf wave_cnt, set_off;
+        FR_TRY(wave_cnt.alloc(ctx, (n_waves + 1) * sizeof(uint32_t)));
+        FR_TRY(set_off.alloc(ctx, (S + 1) * sizeof(uint32_t)));
+        FR_HIP(hipMemsetAsync(wave_cnt.as<uint32_t>() + n_waves, 0, sizeof(uint32_t), st));
+        if (ptm.n_tiles > 0) {
+            k_build_count<d><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(), wave_cnt.as<uint32_t>(),
+                                                          lat->err_d);
+            FR_HIP(hipGetLastError());
+        }
+        FR_TRY(scan_exclusive_u32(ctx, wave_cnt.as<uint32_t>(), wave_cnt.as<uint32_t>(), n_waves + 1, 0, st));
+        k_set_partial_off<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, ptm.seg_tile, wave_cnt.as<uint32_t>(),
+                                                                set_off.as<uint32_t>());
         FR_HIP(hipGetLastError());
+        std::vector<uint32_t> so(S + 1);
+        int32_t err0 = 0;
+        FR_HIP(hipMemcpyAsync(so.data(), set_off.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(&err0, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipStreamSynchronize(st));
+        if (err0 != 0) {
+            set_error("fr_lattice_build: a lattice coordinate left [-2^20, 2^20); increase sigma or centre the cloud");
+            return FR_ERANGE;
+        }
+        for (int32_t s = 0; s <= S; ++s) roff[s] = so[s];
+        P = so[S];
+        FR_TRY(rec_key.alloc(ctx, P * KW * sizeof(uint64_t)));
+        FR_TRY(rec_cnt.alloc(ctx, P * sizeof(uint32_t)));
+        FR_TRY(rec_val.alloc(ctx, P * V * sizeof(T)));
+        if (ptm.n_tiles > 0 && P > 0) {
+            k_build_partials<d, V><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(),
+                                                                wave_cnt.as<uint32_t>(), rec_key.as<uint64_t>(),
+                                                                rec_cnt.as<uint32_t>(), rec_val.as<T>(), P,
+                                                                valued_end);
+            FR_HIP(hipGetLastError());
+        }
     }
+    FR_TRY(rec_slot.alloc(ctx, P * sizeof(uint32_t)));
+
     // 2. insert into provisional tables (pow2 >= R_set / 2 first, or twice the
     //    vertices the last build's vertices-per-record ratio predicts if that is
-    //    more; 2 R_set if that overflows)
-    std::vector<int64_t> roff(S + 1);
-    for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
+    //    more; 2 R_set if that overflows; R_set = the set's partial records)
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
     uint64_t n1 = 0;
     DevBuf ovid, slot_vid, vb_d, last_d;
-    FR_TRY(ovid.alloc(ctx, R * sizeof(uint32_t)));   // owner flags, then their exclusive scan
+    FR_TRY(ovid.alloc(ctx, P * sizeof(uint32_t)));   // owner flags, then their exclusive scan
     FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
     FR_TRY(last_d.alloc(ctx, sizeof(uint32_t)));
     std::vector<uint32_t> vb_h(S + 1);
@@ -828,7 +963,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             const uint64_t guess = (uint64_t)(2.0 * std::min(ctx->vertex_ratio, 1.0) * (double)rs);
             const uint32_t cap = next_pow2(attempt == 0 ? std::max<uint64_t>(rs / 2, guess) : 2 * rs);
             if (2 * rs > (1ull << 31) && attempt == 1) {
-                set_error("fr_lattice_build: set %d has too many splat records (%llu)", s, (unsigned long long)rs);
+                set_error("fr_lattice_build: set %d has too many partial records (%llu)", s, (unsigned long long)rs);
                 return FR_EINVAL;
             }
             t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1, {}};
@@ -843,16 +978,16 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (rtm.n_tiles > 0) {
-            k_insert_records<KW><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), R,
+            k_insert_records<KW><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), P,
                                                               own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
                                                               ovid.as<uint32_t>(), fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
         // 3. vertex ids in owner-record order and per-set ranges, enqueued before the
         //    overflow check (one wait for both; redone if the insertion overflowed)
-        if (R > 0) FR_HIP(hipMemcpyAsync(last_d.p, ovid.as<uint32_t>() + R - 1, 4, hipMemcpyDeviceToDevice, st));
-        FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), R, 0, st));
-        k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), R,
+        if (P > 0) FR_HIP(hipMemcpyAsync(last_d.p, ovid.as<uint32_t>() + P - 1, 4, hipMemcpyDeviceToDevice, st));
+        FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), P, 0, st));
+        k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), P,
                                                           last_d.as<uint32_t>(), vb_d.as<uint32_t>());
         FR_HIP(hipGetLastError());
         int32_t failed = 0;
@@ -880,7 +1015,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     }
     const size_t NV = nv_total;
     lat->n_vertices_total = (int64_t)NV;
-    if (R > 0) ctx->vertex_ratio = (double)NV / (double)R;
+    if (P > 0) ctx->vertex_ratio = (double)NV / (double)P;
 
     // vertex arrays (kept for export)
     lat->vert_bytes = NV * (KW * sizeof(uint64_t) + sizeof(uint32_t) + V * sizeof(float)) + 64;
@@ -893,7 +1028,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         lat->vocc = reinterpret_cast<uint32_t *>(c + NV * (KW * sizeof(uint64_t) + V * sizeof(float)));
     }
     if (NV > 0) {
-        k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), ovid.as<uint32_t>(),
+        k_owner_emit<KW><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(), ovid.as<uint32_t>(),
                                                              rec_key.as<uint64_t>(), lat->vkey, NV,
                                                              slot_vid.as<uint32_t>());
         FR_HIP(hipGetLastError());
@@ -902,50 +1037,44 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // 4. values
     if (NV > 0) {
         if (sorted) {
-            DevBuf rvid, rid, tk, tv, voff, rows;
-            const size_t NP = R / D;
-            FR_TRY(rows.alloc(ctx, NP * PointRow<V>::words * sizeof(float4)));
-            if (NP > 0) {
-                k_point_rows<V><<<blocks_for(NP, 256), 256, 0, st>>>(NP, pts, rows.as<float4>());
-                FR_HIP(hipGetLastError());
-            }
-            FR_TRY(rvid.alloc(ctx, R * sizeof(uint32_t)));
-            FR_TRY(rid.alloc(ctx, R * sizeof(uint32_t)));
-            FR_TRY(tk.alloc(ctx, R * sizeof(uint32_t)));
-            FR_TRY(tv.alloc(ctx, R * sizeof(uint32_t)));
+            DevBuf rvid, rid, tk, tv, voff;
+            FR_TRY(rvid.alloc(ctx, P * sizeof(uint32_t)));
+            FR_TRY(rid.alloc(ctx, P * sizeof(uint32_t)));
+            FR_TRY(tk.alloc(ctx, P * sizeof(uint32_t)));
+            FR_TRY(tv.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(voff.alloc(ctx, NV * sizeof(uint32_t)));
-            k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(),
+            k_record_vertex<<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(),
                                                                  rvid.as<uint32_t>(), rid.as<uint32_t>());
             FR_HIP(hipGetLastError());
             int bits = 0;
             while (bits < 32 && (NV - 1) >> bits) ++bits;
             uint32_t *svid = nullptr, *srid = nullptr;   // the sorted pairs
             FR_TRY(radix_sort_pairs(ctx, rvid.as<uint32_t>(), rid.as<uint32_t>(), tk.as<uint32_t>(),
-                                    tv.as<uint32_t>(), R, bits, st, &svid, &srid));
-            k_segment_heads<<<blocks_for(R, 256), 256, 0, st>>>(R, svid, voff.as<uint32_t>());
+                                    tv.as<uint32_t>(), P, bits, st, &svid, &srid));
+            k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
-            k_segment_lengths<<<blocks_for(NV, 256), 256, 0, st>>>(NV, R, voff.as<uint32_t>(), lat->vocc);
-            FR_HIP(hipGetLastError());
-            k_vertex_sum_sorted<D, V><<<blocks_for(NV, 256), 256, 0, st>>>(
-                NV, voff.as<uint32_t>(), lat->vocc, srid, rec_b.as<float>(), rows.as<float4>(), lat->vval);
+            k_vertex_sum_sorted<V, T><<<blocks_for(NV, 256), 256, 0, st>>>(
+                NV, P, voff.as<uint32_t>(), srid, rec_cnt.as<uint32_t>(), rec_val.as<T>(), lat->vval, lat->vocc);
             FR_HIP(hipGetLastError());
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
             FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
-            k_vertex_sum_atomic<D, V><<<blocks_for(R, 256), 256, 0, st>>>(R, rec_slot.as<uint32_t>(),
-                                                                           slot_vid.as<uint32_t>(), rec_b.as<float>(),
-                                                                           pts, lat->vval, lat->vocc, NV);
+            k_vertex_sum_atomic<V, T><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(),
+                                                                           slot_vid.as<uint32_t>(),
+                                                                           rec_cnt.as<uint32_t>(), rec_val.as<T>(),
+                                                                           lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
             if constexpr (ValLayout<V>::m2) {
-                k_vertex_scatter_atomic<D, V><<<blocks_for(R, 256), 256, 0, st>>>(
-                    R, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_b.as<float>(), pts, lat->vval, NV);
+                k_vertex_scatter_atomic<V, T><<<blocks_for(P, 256), 256, 0, st>>>(
+                    P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_val.as<T>(), lat->vval, NV);
                 FR_HIP(hipGetLastError());
             }
         }
     }
     // the provisional table and records are no longer needed
     rec_key.reset();
-    rec_b.reset();
+    rec_cnt.reset();
+    rec_val.reset();
     rec_slot.reset();
     own1.reset();
     ovid.reset();

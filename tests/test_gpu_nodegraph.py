@@ -124,8 +124,10 @@ def test_nodegraph_full_size_one_step_from_the_oracle_state(fr, ctx, blob, start
 
 
 def _spread(K, seed):
+    # node motions of up to 0.1 rad and 0.02 units: all different, small enough against sigma = 0.02 that
+    # most moved points keep lattice support
     rng = np.random.default_rng(seed)
-    return np.stack([synth.random_motion(rng, 0.3, 0.05) for _ in range(K)])
+    return np.stack([synth.random_motion(rng, 0.1, 0.02) for _ in range(K)])
 
 
 @pytest.mark.parametrize("residual", ["pt2pt", "pt2pl"])

@@ -121,16 +121,28 @@ def _register_sigma(fr, ctx, pairs, feat, res, sigma0, sigma_min, iters, T0s, si
 
 
 def test_register_sigma_matches_the_oracle_from_far(fr, ctx):
-    """An ellipsoid 8 cm off: the scale widens, then shrinks to the noise; both sides agree."""
+    """An ellipsoid 8 cm off: the scale widens, then shrinks to the noise.  Every GPU iteration, started
+    from the oracle's state before it, lands on the oracle's next state (1e-4 in pose and relative scale);
+    the 25-iteration GPU trajectory follows the oracle's to 1e-3 in pose and 1e-2 in scale (each
+    iteration's binary32 lattice sums differ from the oracle's binary64 ones in the last bits, and 25
+    rebuilt lattices compound that)."""
     p = synth.ellipsoid_pair(2, m=2000, max_angle_deg=10, max_trans=0.05, noise=0.01)
     _say(f"[sigma-em] ellipsoid M={len(p.model)} N={len(p.obs)} 25 iterations")
-    T, s, st, rep = _register_sigma(fr, ctx, [p], 3, "pt2pt", 0.02, 1e-3, 25, [np.eye(4)], w=p.w)
     hist = []
     Tr, sr = oracle.register_rigid_sigma(p.model, p.model_n, p.obs, p.obs_n, feat=3, residual="pt2pt", sigma0=0.02,
                                          sigma_min=1e-3, w=p.w, iters=25, T0=np.eye(4), history=hist)
-    ang, dt, ok = pose_close(T[0], Tr)
+    for k in range(25):
+        Sk = 0.02 if k == 0 else hist[k - 1]["sigma"]
+        Tk = np.eye(4) if k == 0 else hist[k - 1]["T"]
+        T1, s1, st1, _ = _register_sigma(fr, ctx, [p], 3, "pt2pt", Sk, 1e-3, 1, [Tk], w=p.w)
+        assert st1[0] == 0
+        assert abs(s1[0] / hist[k]["sigma"] - 1.0) < 1e-4, (k, s1[0], hist[k]["sigma"])
+        ang, dt, ok = pose_close(T1[0], hist[k]["T"])
+        assert ok, (k, ang, dt)
+    T, s, st, rep = _register_sigma(fr, ctx, [p], 3, "pt2pt", 0.02, 1e-3, 25, [np.eye(4)], w=p.w)
+    ang, dt, ok = pose_close(T[0], Tr, tol=1e-3)
     assert st[0] == 0 and ok, (ang, dt)
-    assert abs(s[0] / sr - 1.0) < 1e-3, (s[0], sr)
+    assert abs(s[0] / sr - 1.0) < 1e-2, (s[0], sr)
     assert rep.iterations == 25
     assert oracle.alignment_error(T[0], p.T_gt, p.model) < 2e-3
     # a short run stops at the oracle's intermediate scale as well
@@ -142,8 +154,8 @@ def test_register_sigma_matches_the_oracle_from_far(fr, ctx):
 @pytest.mark.parametrize("feat,res", [(6, "pt2pl"), (3, "pt2pl"), (6, "pt2pt")])
 def test_register_sigma_batch_matches_oracle_and_alone(fr, ctx, feat, res):
     """Several depth frames of different sizes and start scales in one call: one step from the
-    oracle's state at iteration 5 matches the oracle's next state; ten steps follow the oracle; and a
-    set registered alone is bitwise the same set in the batch."""
+    oracle's state before every iteration 0..9 matches the oracle's next state (1e-4); ten steps follow
+    the oracle's trajectory (1e-3); and a set registered alone is bitwise the same set in the batch."""
     pairs = [synth.depth_pair(60 + i, width=w, height=h, f=f)
              for i, (w, h, f) in enumerate([(160, 120, 131.25), (96, 72, 78.75), (200, 150, 164.0)])]
     d = np.array([0.01, -0.01, 0.005, 0.01, 0.005, -0.01])
@@ -157,8 +169,8 @@ def test_register_sigma_batch_matches_oracle_and_alone(fr, ctx, feat, res):
         oracle.register_rigid_sigma(q.model, q.model_n, q.obs, q.obs_n, feat=feat, residual=res, sigma0=s0[i],
                                     sigma_min=0.004, sigma_n=q.sigma_n, w=q.w, iters=10, T0=T0s[i], history=h)
         hists.append(h)
-    # one step from the oracle's state after k steps
-    for k in (0, 4, 8):
+    # one step from the oracle's state after k steps, at every iteration
+    for k in range(10):
         Sk = [s0[i] if k == 0 else h[k - 1]["sigma"] for i, h in enumerate(hists)]
         Tk = [T0s[i] if k == 0 else h[k - 1]["T"] for i, h in enumerate(hists)]
         T1, s1, st1, _ = _register_sigma(fr, ctx, pairs, feat, res, Sk, 0.004, 1, Tk, **kw)
