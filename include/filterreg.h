@@ -281,6 +281,24 @@ fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const f
                           double *stats, void *stream);
 
 /*
+ * fr_mstep_reduce for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it).
+ * Same arguments, kernels and results (bitwise) as fr_mstep_reduce; it
+ * allocates nothing.  Its tile map and per-tile partial rows live in a
+ * device array of FR_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
+ * held until the process ends.  A call needs 20 bytes per segment plus
+ * 128 bytes per 1024 points (about 67 M points in one segment); a larger one
+ * fails with FR_EINVAL before anything is enqueued.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (from several host
+ * threads, or on several streams) race and must be serialised by the caller.
+ * Synchronises `stream` before returning, like fr_mstep_reduce.
+ */
+#define FR_NOALLOC_SCRATCH_BYTES (8 << 20)
+fr_status fr_mstep_reduce_noalloc(const fr_cloud *model_ref, const fr_xform *xf, const float *m0, const float *m1,
+                                  const float *nsum, const fr_mstep_params *params, double *jtj, double *jtr,
+                                  double *stats, void *stream);
+
+/*
  * Rigid Gauss-Newton update on the device in binary64 (Eq. 17 and the
  * left-multiplied update of Eq. 16): for each of n sets,
  *   dzeta = -A^-1 b (Cholesky), T <- Exp(dzeta) T,

@@ -165,6 +165,8 @@ _sig("fr_estep_touched", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_x
                                ctypes.POINTER(ctypes.c_int64)])
 _sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
                               ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
+_sig("fr_mstep_reduce_noalloc", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
+                                      ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
 _sig("fr_solve_rigid", _st, [_i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("fr_register", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud),
                           ctypes.POINTER(fr_register_params), _P, _P, ctypes.POINTER(fr_report), _P])
@@ -192,7 +194,7 @@ ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy
                  "fr_ctx_set_tuning", "fr_ctx_tuning_table",
                  "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
                  "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
-                 "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_solve_rigid", "fr_register",
+                 "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_mstep_reduce_noalloc", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
                  "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph", "fr_mstep_reduce_nodes",
                  "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
@@ -409,6 +411,19 @@ def fr_mstep_reduce(model: Cloud, xf: XForm, m0, m1, nsum, residual: int, c: flo
     prm = fr_mstep_params(residual, normalize_n, float(c), float(sigma), cps)
     _check(_lib.fr_mstep_reduce(model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), ctypes.byref(prm),
                                 _ptr(jtj), _ptr(jtr), _ptr(stats), _stream(stream)))
+    del keep
+
+
+def fr_mstep_reduce_noalloc(model: Cloud, xf: XForm, m0, m1, nsum, residual: int, c: float, sigma: float, jtj, jtr,
+                            stats, normalize_n: int = 0, c_per_set: Optional[Sequence[float]] = None, stream=None):
+    cps = None
+    keep = None
+    if c_per_set is not None:
+        keep = np.ascontiguousarray(c_per_set, dtype=np.float64)
+        cps = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    prm = fr_mstep_params(residual, normalize_n, float(c), float(sigma), cps)
+    _check(_lib.fr_mstep_reduce_noalloc(model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), ctypes.byref(prm),
+                                        _ptr(jtj), _ptr(jtr), _ptr(stats), _stream(stream)))
     del keep
 
 

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstring>
 
+#include <mutex>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -178,13 +180,11 @@ fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what)
     return FR_OK;
 }
 
-fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host,
-                    hipStream_t st, Plan &plan)
+fr_status plan_layout(const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host, Plan &plan,
+                      std::vector<char> &image)
 {
     plan.tile = tile;
     plan.n_sets = cloud->n_sets;
-    plan.ctx = ctx;
-    plan.slice = ctx->slice_mode;
     const bool seg = xf != nullptr && xf->kind == FR_XF_SEGMENTED;
     if (seg) {
         plan.n_seg = xf->n_seg;
@@ -219,6 +219,10 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
         grid = chunk * 8;
     }
     plan.grid = grid;
+    plan.tm.n_seg = plan.n_seg;
+    plan.tm.n_tiles = plan.n_tiles;
+    plan.tm.tile = tile;
+    plan.tm.xcd_chunk = chunk;
     std::vector<float> cseg(plan.n_seg, 0.0f);
     if (c_seg_host)
         for (int32_t s = 0; s < plan.n_seg; ++s) cseg[s] = (float)c_seg_host[plan.seg_set[s]];
@@ -226,24 +230,38 @@ fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int3
     const size_t b_tile = sizeof(int32_t) * (plan.n_seg + 1);
     const size_t b_set = sizeof(int32_t) * plan.n_seg;
     const size_t b_c = sizeof(float) * plan.n_seg;
-    std::vector<char> host(b_off + b_tile + b_set + b_c);
-    std::memcpy(host.data(), plan.seg_off.data(), b_off);
-    std::memcpy(host.data() + b_off, plan.seg_tile.data(), b_tile);
-    std::memcpy(host.data() + b_off + b_tile, plan.seg_set.data(), b_set);
-    std::memcpy(host.data() + b_off + b_tile + b_set, cseg.data(), b_c);
-    FR_TRY(plan.meta.alloc(ctx, host.size()));
-    FR_HIP(hipMemcpyAsync(plan.meta.p, host.data(), host.size(), hipMemcpyHostToDevice, st));
-    FR_HIP(hipStreamSynchronize(st));
-    const char *p = plan.meta.as<char>();
+    image.assign(b_off + b_tile + b_set + b_c, 0);
+    std::memcpy(image.data(), plan.seg_off.data(), b_off);
+    std::memcpy(image.data() + b_off, plan.seg_tile.data(), b_tile);
+    std::memcpy(image.data() + b_off + b_tile, plan.seg_set.data(), b_set);
+    std::memcpy(image.data() + b_off + b_tile + b_set, cseg.data(), b_c);
+    return FR_OK;
+}
+
+void plan_bind(Plan &plan, const void *dev_image)
+{
+    const size_t b_off = sizeof(int64_t) * (plan.n_seg + 1);
+    const size_t b_tile = sizeof(int32_t) * (plan.n_seg + 1);
+    const size_t b_set = sizeof(int32_t) * plan.n_seg;
+    const char *p = static_cast<const char *>(dev_image);
     plan.tm.seg_off = reinterpret_cast<const int64_t *>(p);
     plan.tm.seg_end = plan.tm.seg_off + 1;
     plan.tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
     plan.tm.seg_set = reinterpret_cast<const int32_t *>(p + b_off + b_tile);
     plan.seg_c = reinterpret_cast<const float *>(p + b_off + b_tile + b_set);
-    plan.tm.n_seg = plan.n_seg;
-    plan.tm.n_tiles = plan.n_tiles;
-    plan.tm.tile = tile;
-    plan.tm.xcd_chunk = chunk;
+}
+
+fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host,
+                    hipStream_t st, Plan &plan)
+{
+    plan.ctx = ctx;
+    plan.slice = ctx->slice_mode;
+    std::vector<char> host;
+    FR_TRY(plan_layout(cloud, xf, tile, c_seg_host, plan, host));
+    FR_TRY(plan.meta.alloc(ctx, host.size()));
+    FR_HIP(hipMemcpyAsync(plan.meta.p, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    FR_HIP(hipStreamSynchronize(st));
+    plan_bind(plan, plan.meta.p);
     return FR_OK;
 }
 
@@ -918,6 +936,93 @@ fr_status fr_mstep_reduce(const fr_cloud *model_ref, const fr_xform *xf, const f
                          params->residual, params->normalize_n, params->sigma, jtj, jtr, stats, part.as<float>(),
                          st));
     FR_HIP(hipStreamSynchronize(st));
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fr_mstep_reduce without allocation: the tile map and the per-tile partial
+// rows of the reduction live in one file-scope device array.  Each GPU the
+// library runs on holds its own copy until the process ends; host code only
+// ever uses the address hipGetSymbolAddress returns for it on that device.
+// ---------------------------------------------------------------------------
+static __device__ __attribute__((aligned(256))) unsigned char scratch[FR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static fr_status scratch_address(void **out)
+{
+    int dev = 0;
+    FR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("fr_mstep_reduce_noalloc: device %d beyond the %d the library tracks", dev, kMaxDevices);
+        return FR_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("fr_mstep_reduce_noalloc: hipGetSymbolAddress of the scratch array failed: %s",
+                      hipGetErrorString(e));
+            return FR_EDEVICE;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return FR_OK;
+}
+
+fr_status fr_mstep_reduce_noalloc(const fr_cloud *model_ref, const fr_xform *xf, const float *m0, const float *m1,
+                                  const float *nsum, const fr_mstep_params *params, double *jtj, double *jtr,
+                                  double *stats, void *stream)
+{
+    clear_error();
+    FR_TRY(check_cloud(model_ref, false, "fr_mstep_reduce_noalloc"));
+    FR_TRY(check_xform(xf, model_ref, "fr_mstep_reduce_noalloc"));
+    if (params == nullptr || (params->residual != FR_PT2PT && params->residual != FR_PT2PL) ||
+        !(params->sigma > 0.0) || !(params->c >= 0.0)) {
+        set_error("fr_mstep_reduce_noalloc: residual must be PT2PT/PT2PL, sigma > 0, c >= 0");
+        return FR_EINVAL;
+    }
+    if (jtj == nullptr || jtr == nullptr || stats == nullptr) {
+        set_error("fr_mstep_reduce_noalloc: outputs must be non-NULL");
+        return FR_EINVAL;
+    }
+    const int64_t M = cloud_points(model_ref);
+    if (M > 0 && (m0 == nullptr || m1 == nullptr || (params->residual == FR_PT2PL && nsum == nullptr))) {
+        set_error("fr_mstep_reduce_noalloc: m0/m1 (and nsum for point-to-plane) must be non-NULL");
+        return FR_EINVAL;
+    }
+    std::vector<double> cset(model_ref->n_sets, params->c);
+    if (params->c_per_set)
+        for (int32_t s = 0; s < model_ref->n_sets; ++s) cset[s] = params->c_per_set[s];
+    Plan plan;
+    std::vector<char> image;
+    FR_TRY(plan_layout(model_ref, xf, 1024, cset.data(), plan, image));
+    // scratch = [tile map image | partial rows], the rows 256-byte aligned
+    const size_t rows_off = (image.size() + 255) / 256 * 256;
+    const size_t need = rows_off + reduce_partials_floats(plan) * sizeof(float);
+    if (need > (size_t)FR_NOALLOC_SCRATCH_BYTES) {
+        set_error("fr_mstep_reduce_noalloc: %zu bytes of tile map and partial rows (%d segments, %d tiles of 1024 "
+                  "points) exceed its %d-byte scratch; use fr_mstep_reduce",
+                  need, plan.n_seg, plan.n_tiles, (int)FR_NOALLOC_SCRATCH_BYTES);
+        return FR_EINVAL;
+    }
+    void *base = nullptr;
+    FR_TRY(scratch_address(&base));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *sp = static_cast<char *>(base);
+    if (!image.empty()) FR_HIP(hipMemcpyAsync(sp, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    plan_bind(plan, sp);
+    // every tile rewrites its whole partial row before the final sum reads it: nothing to clear
+    const int kind = xf ? xf->kind : FR_XF_NONE;
+    FR_TRY(launch_reduce(model_ref, plan, kind, kind == FR_XF_NONE ? nullptr : xf->mats, m0, m1, nsum,
+                         params->residual, params->normalize_n, params->sigma, jtj, jtr, stats,
+                         reinterpret_cast<float *>(sp + rows_off), st));
+    FR_HIP(hipStreamSynchronize(st));   // the host image and the scratch are free for the next call
     return FR_OK;
 }
 

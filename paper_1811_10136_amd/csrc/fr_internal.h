@@ -189,6 +189,13 @@ struct Plan {
 // Build a plan for `model_ref` segmented per `xf` (NULL = per set).
 fr_status make_plan(fr_ctx *ctx, const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host,
                     hipStream_t stream, Plan &plan);
+// The host half of make_plan: segments, tiles and launch shape of the plan,
+// and the byte image of its device tables (seg_off | seg_tile | seg_set |
+// seg_c) in `image`; plan_bind points the plan's tile map at a device copy
+// of that image.
+fr_status plan_layout(const fr_cloud *cloud, const fr_xform *xf, int32_t tile, const double *c_seg_host, Plan &plan,
+                      std::vector<char> &image);
+void plan_bind(Plan &plan, const void *dev_image);
 
 inline int64_t cloud_points(const fr_cloud *c) { return c->offsets[c->n_sets]; }
 fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what);
