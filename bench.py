@@ -32,6 +32,7 @@ import concurrent.futures as cf
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -82,20 +83,76 @@ def traffic_from_profile(pairs_points, kernel):
     return prof.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(pairs, iters):
-    """The CPU oracle on the first pairs of the batch: lattice build + `iters` EM iterations each."""
+CPU_ITERS = 10     # EM iterations of each CPU sample (the rate is per model-point iteration, build included)
+CPU_REPS = 5
+
+
+def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_one(pair, iters):
+    """One oracle registration in this process (one BLAS thread): (seconds, stage timings)."""
+    from threadpoolctl import threadpool_limits
     import oracle
-    T0 = np.eye(4)
-    t0 = time.perf_counter()
-    for pair in pairs:
+    with threadpool_limits(limits=1):
+        tm = {}
+        t0 = time.perf_counter()
         oracle.register_rigid(pair.model, pair.model_n, pair.obs, pair.obs_n, feat=6, residual="pt2pl",
-                              sigma=pair.sigma, sigma_n=pair.sigma_n, w=pair.w, iters=iters, T0=T0)
-    dt = time.perf_counter() - t0
-    pts = sum(len(p.model) for p in pairs)
-    return {"value": pts * iters / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {len(pairs)} pairs of the batch ({pts} model / {sum(len(p.obs) for p in pairs)} obs "
-                      f"points): lattice build + {iters} EM iterations each, single-threaded C + NumPy float64, "
-                      f"{dt:.1f} s"}
+                              sigma=pair.sigma, sigma_n=pair.sigma_n, w=pair.w, iters=iters, T0=np.eye(4),
+                              timings=tm)
+        return time.perf_counter() - t0, tm
+
+
+def cpu_baseline(pairs, iters=CPU_ITERS, reps=CPU_REPS):
+    """The CPU oracle (C + NumPy float64, as written) on a bounded sample of the batch's pairs.
+
+    One thread: the first pair, `reps` times (lattice build + `iters` EM iterations): median of the
+    full registration, of the build, and of the per-iteration E-step and M-step.  All cores: one pair
+    per process on every core of the host share (at most 16), all at once, `reps` times; the median
+    wall time gives the aggregate rate.  Rates are model-point iterations per second, build included,
+    like the GPU figure."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu, len(pairs)))
+    one = [_oracle_one(pairs[0], iters) for _ in range(reps)]
+    reg = float(np.median([t for t, _ in one]))
+    build = float(np.median([tm["build"] for _, tm in one]))
+    est = float(np.median([x for _, tm in one for x in tm["estep"]]))
+    mst = float(np.median([x for _, tm in one for x in tm["mstep"]]))
+    m0 = len(pairs[0].model)
+    walls = []
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        list(ex.map(_oracle_one, pairs[:workers], [1] * workers))   # start the workers and load the oracle
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(_oracle_one, pairs[:workers], [iters] * workers))
+            walls.append(time.perf_counter() - t0)
+    wall = float(np.median(walls))
+    pts = sum(len(p.model) for p in pairs[:workers])
+    return {"value": pts * iters / wall, "unit": "points/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} depth pairs of the batch ({pts} model points), one per process, each a lattice "
+                      f"build + {iters} EM iterations, run together {reps} times (median wall {wall:.2f} s); "
+                      f"single-threaded C + NumPy float64 per process",
+            "nproc": ncpu, "cpu_model": _cpu_model(),
+            "single_thread": {"value": m0 * iters / reg, "unit": "points/s", "cores": 1,
+                              "sample": f"pair 0 ({m0} model points), {reps} runs, medians",
+                              "registration_ms": reg * 1e3, "build_ms": build * 1e3,
+                              "estep_ms_per_iter": est * 1e3, "mstep_ms_per_iter": mst * 1e3}}
 
 
 def copy_reference(nbytes=256 << 20, reps=3):
@@ -213,9 +270,11 @@ def serve_bench(fr, ctx, args):
     log(f"request stream: {n} requests, {int(m.sum())} model / {int(k.sum())} obs points, staged in "
         f"{time.time() - t:.1f} s")
     p0 = synth.depth_pair(0, target_points=1000)
-    prm = fr.register_params(6, "pt2pl", p0.sigma, p0.sigma_n, iters=args.iters, w=0.1, fixed=True)
+    stop = args.serve_tol > 0.0
+    prm = fr.register_params(6, "pt2pl", p0.sigma, p0.sigma_n, iters=args.iters, w=0.1, fixed=not stop,
+                             tol=args.serve_tol if stop else 1e-6)
     eprm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=args.serve_slots,
-                            arena_points=args.serve_arena, w=0.1)
+                            arena_points=args.serve_arena, w=0.1, tol=args.serve_tol if stop else 0.0)
     budget = int(args.serve_budget_gib * (1 << 30))
     # warm both paths
     run_plain(fr, ctx, model, obs, np.zeros(8), prm)
@@ -251,14 +310,16 @@ def serve_bench(fr, ctx, args):
     del keep
     return {
         "workload": f"{n} rigid point-to-plane requests, model points log-uniform in [1k, 300k] (sorted random "
-                    f"subsamples of {SERVE_FRAMES} depth renders at 300k points), d=6, {args.iters} EM iterations "
-                    f"each, Poisson arrivals",
+                    f"subsamples of {SERVE_FRAMES} depth renders at 300k points), d=6, at most {args.iters} EM "
+                    f"iterations each" + (f", stopped on a twist below {args.serve_tol:g}" if stop else "") +
+                    ", Poisson arrivals",
         "requests": n, "model_points": int(m.sum()), "obs_points": int(k.sum()),
         "plain_capacity_per_s": cap, "served": served, "plain": plain,
         "engine": {"max_slots": args.serve_slots, "arena_points": args.serve_arena,
                    "lattice_budget_gib": args.serve_budget_gib, "max_admit": args.serve_admit},
         "headline": None if head is None else {
             "lambda_x": head["lambda_x"], "registrations_per_s": head["registrations_per_s"],
+            "solved_per_s": head["solved_per_s"], "degenerate": head["degenerate"],
             "p50_ms": head["latency_ms"]["p50"], "p99_ms": head["latency_ms"]["p99"],
             "rule": "largest swept arrival rate whose served p99 latency is under 100 ms"},
         "degenerate_note": "requests ending FR_EDEGENERATE (singular normal equations, pose kept): the frames' "
@@ -503,14 +564,61 @@ def profile_workload(name):
     ctx.close()
 
 
+BUILD_IN_BYTES = 24                        # observation position + normal in (binary32)
+BUILD_VERTEX_BYTES = 16 + 4 + 4 * 8        # vertex out: packed key, occupancy, 7 values padded to 8 (binary32)
+TABLE_SLOT_BYTES = 64                      # lookup table: key + padded values per slot, 2.5 slots per vertex
+# bytes a partial record moves through the sorted build: written by the partial pass (key 16, count 4,
+# values 28), key read by the insertion (16), (vertex, record) pair written and read (16), three radix
+# passes over the pairs (3 x 16), count and values read by the per-vertex sums (32)
+PARTIAL_BYTES_SORTED = 48 + 16 + 16 + 48 + 32
+ATOMICS_PER_PARTIAL = 8                    # 7 binary32 value atomics + 1 occupancy atomic
+
+
 def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):
-    """Lattice build of the 64 observation frames, sorted and atomic splat (observation points per second)."""
+    """Lattice build of the 64 observation frames, sorted and atomic splat: observation points per second,
+    stage times, the algorithmic bytes of the build against HBM, the partial records' own traffic, and the
+    atomic splat's value stage against the uncontended-atomic probe."""
     res = {}
     for name, splat in (("sorted", fr.FR_SPLAT_SORTED), ("atomic", fr.FR_SPLAT_ATOMIC)):
         prm = fr.lattice_params(6, 7, sigma, sigma_n, splat)
         ms, _ = _timed(lambda: fr.Lattice(ctx, obs, prm).close(), reps)
-        res[name] = {"ms": ms, "obs_points_per_s": obs.n / ms * 1e3}
+        stages = []
+        for _ in range(reps):
+            lat = fr.Lattice(ctx, obs, prm)
+            stages.append(fr.fr_lattice_build_times(lat.h))
+            inc, part = fr.fr_lattice_records(lat.h)
+            nv = sum(lat.stats(s)[0] for s in range(obs.n_sets))
+            lat.close()
+        st = np.median(np.array(stages), axis=0)
+        alg = obs.n * BUILD_IN_BYTES + nv * BUILD_VERTEX_BYTES
+        entry = {"ms": ms, "obs_points_per_s": obs.n / ms * 1e3,
+                 "stage_ms": {"embed": st[0], "insert_and_ids": st[1], "values": st[2], "tables": st[3]},
+                 "incidences": inc, "partial_records": part, "vertices": nv,
+                 "algorithmic_bytes": alg, "table_bytes": nv * 2.5 * TABLE_SLOT_BYTES,
+                 "achieved_gbs": alg / ms / 1e6,
+                 "frac_of_hbm_peak": alg / ms / 1e6 / HBM_PEAK_GBS}
+        if name == "sorted":
+            entry["partial_record_bytes"] = part * PARTIAL_BYTES_SORTED
+        else:
+            atomics = part * ATOMICS_PER_PARTIAL
+            probe = fr.fr_probe_atomics(ctx.h, 1 << 26, 1 << 30)
+            entry["atomic_splat"] = {"atomics": atomics, "values_ms": st[2],
+                                     "atomics_per_s": atomics / st[2] * 1e3,
+                                     "probe_uncontended_atomics_per_s": probe,
+                                     "frac_of_probe": atomics / st[2] * 1e3 / probe}
+        res[name] = entry
     return res
+
+
+def line_rates(fr, ctx):
+    """The line-access ceiling of hash lookups: 16-byte lane loads, one lane per 128-byte line (a
+    lookup's key or value read) and eight lanes per line, from an L2-resident (2 MiB) and an
+    HBM-resident (1 GiB) table."""
+    out = {}
+    for where, nbytes in (("l2", 2 << 20), ("hbm", 1 << 30)):
+        for g in (1, 8):
+            out[f"{where}_lanes{g}_lines_per_s"] = fr.fr_probe_lines(ctx.h, g, nbytes)
+    return out
 
 
 def main():
@@ -525,7 +633,7 @@ def main():
     ap.add_argument("--slice", choices=["auto", "plain", "shared"], default="auto",
                     help="E-step slice kernel (auto: the library's autotuner picks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=3, help="pairs the CPU oracle baseline runs")
+    ap.add_argument("--cpu-pairs", type=int, default=16, help="pairs the all-cores CPU oracle baseline runs")
     ap.add_argument("--copy-ref", action="store_true", help="end with plain copies of known size (counter scale)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
@@ -535,6 +643,8 @@ def main():
     ap.add_argument("--serve-arena", type=int, default=64 << 20)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--serve-admit", type=int, default=32)
+    ap.add_argument("--serve-tol", type=float, default=1e-6,
+                    help="a request stops after a step with |omega| and |v| below this (0: all iterations)")
     ap.add_argument("--serve-capacity-requests", type=int, default=256)
     ap.add_argument("--serve-lambdas", type=float, nargs="*", default=[1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--plain-lambdas", type=float, nargs="*", default=[1.0])
@@ -668,6 +778,7 @@ def main():
         log("other workloads and build rates ...")
         out["other_workloads"] = other_workloads(fr, ctx)
         out["build"] = build_rates(fr, ctx, obs, sigma, sigma_n)
+        out["roofline"]["line_rates"] = line_rates(fr, ctx)
     if not args.no_serve:
         out["serving"] = serve_bench(fr, ctx, args)
         h = out["serving"]["headline"]
@@ -675,9 +786,10 @@ def main():
             out["registrations_per_s"] = h["registrations_per_s"]
             out["latency_ms"] = {"p50": h["p50_ms"], "p99": h["p99_ms"],
                                  "note": f"served request stream at {h['lambda_x']}x the plain loop's capacity"}
+            out["solved_per_s"] = h["solved_per_s"]
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on {args.cpu_pairs} pairs ...")
-        out["cpu_baseline"] = cpu_baseline(pairs[:args.cpu_pairs], args.iters)
+        out["cpu_baseline"] = cpu_baseline(pairs[:args.cpu_pairs])
     if args.copy_ref:
         copy_reference()
     print(json.dumps(out), flush=True)

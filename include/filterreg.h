@@ -158,6 +158,25 @@ fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertic
 fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h, int32_t *occ_h, float *vals_h);
 
 /*
+ * Splat records of the lattice's build (all sets): *incidences (host) = D N,
+ * one per observation point and simplex vertex (Eq. 14's splat), and
+ * *partial_records (host) = the runs of shared vertices the build inserted,
+ * sorted and summed in their place (neighbouring points of a scan share most
+ * vertices; descriptor lattices insert every incidence).
+ */
+fr_status fr_lattice_records(const fr_lattice *lat, int64_t *incidences, int64_t *partial_records);
+
+/*
+ * Device time of the build's stages, from HIP events on the build stream
+ * (host, 4 doubles, ms; -1 where not measured): [0] embedding and partial
+ * records, [1] insertion into the provisional tables and vertex numbering,
+ * [2] the vertex values (radix sort and binary64 sums, or the atomic sums),
+ * [3] the final bucketed tables.  The stages include the build's waits for
+ * its sizes (the host round trips between them).
+ */
+fr_status fr_lattice_build_times(const fr_lattice *lat, double *stage_ms_h);
+
+/*
  * Motion applied to model reference points before the E-step (Eq. 15,
  * x_i = T_i x_ref_i).  mats is device memory, one row-major [R | t] of 12
  * binary32 per segment.  FR_XF_RIGID: one matrix per set.  FR_XF_SEGMENTED:
@@ -597,6 +616,23 @@ fr_status fr_engine_release(fr_engine *eng, int32_t n, const int32_t *slots_h);
 
 /* Return (and clear) a device fault latched in `lat` by earlier async calls; synchronises. */
 fr_status fr_sync_status(const fr_lattice *lat);
+
+/*
+ * Roofline probes (measurement only; their buffers are charged to ctx).
+ *  fr_probe_atomics: n_atomics binary32 atomic adds without return value, each
+ *    to its own word of a power-of-two table of table_bytes (at least
+ *    4 n_atomics bytes), neighbouring
+ *    threads on different lines: atomics per second (*per_s, host).  The
+ *    uncontended ceiling of the atomic splat's vertex sums.
+ *  fr_probe_lines: 16-byte loads, lanes_per_line (1, 2, 4 or 8) lanes of a
+ *    wave reading the same 128-byte line, lines drawn at random from a table
+ *    of table_bytes (L2-resident when small, HBM when large): 128-byte line
+ *    accesses per second (*lines_per_s, host).  A hash lookup with one lane
+ *    per key costs one line access per 16-byte load.
+ * Both time a few launches with HIP events on `stream` and wait for them.
+ */
+fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, double *per_s, void *stream);
+fr_status fr_probe_lines(fr_ctx *ctx, int32_t lanes_per_line, size_t table_bytes, double *lines_per_s, void *stream);
 
 #ifdef __cplusplus
 }

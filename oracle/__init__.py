@@ -18,6 +18,7 @@ Every function names the passage of the paper it follows.
 from __future__ import annotations
 
 import ctypes
+import time
 import math
 import os
 import subprocess
@@ -410,28 +411,42 @@ def build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n):
 
 def register_rigid(model, model_n, obs, obs_n, *, feat, residual, sigma, sigma_n=0.5, c=None, w=0.1,
                    iters=20, T0=None, lattice: Optional[Lattice] = None, normalize_n=False,
-                   history: Optional[list] = None, twist_tol: Optional[float] = None, info: Optional[dict] = None):
+                   history: Optional[list] = None, twist_tol: Optional[float] = None, info: Optional[dict] = None,
+                   timings: Optional[dict] = None):
     """Rigid FilterReg: build the observation lattice once, then up to `iters` EM iterations of
     E-step (slice at the pinned binary32 transform of the model) and one Gauss-Newton step
     T <- Exp(-A^-1 b) T.  With twist_tol, the loop ends after the first step whose rotation and
     translation parts both have norm below it (Sec. 6.1 terminates on a small twist); info, if
-    given, receives the number of steps taken.  Returns the float64 pose."""
+    given, receives the number of steps taken; timings, if given, the wall-clock seconds of the
+    build ("build") and of each iteration's E-step and M-step ("estep", "mstep" lists).  Returns
+    the float64 pose."""
+    clock = time.perf_counter
     T = np.eye(4) if T0 is None else np.array(T0, dtype=np.float64)
     if c is None:
         c = outlier_constant(w, len(obs), len(model), feature_sigmas(feat, sigma, sigma_n))
     sig_m = float(np.mean(sigma))
+    t0 = clock()
     lat = lattice if lattice is not None else build_observation_lattice(obs, obs_n, feat, residual, sigma, sigma_n)
+    if timings is not None:
+        timings["build"] = clock() - t0
+        timings.setdefault("estep", [])
+        timings.setdefault("mstep", [])
     model = np.asarray(model, dtype=np.float32)
     for _ in range(iters):
+        t0 = clock()
         mat = pose_to_mat12(T)
         x32 = transform_f32(mat, model)
         n32 = transform_f32(mat, model_n, translate=False) if feat == 6 else None
         m0, m1, ns = estep(lat, x32, n32, feat, residual)
+        t1 = clock()
         R32 = mat.reshape(3, 4).astype(np.float64)
         x64 = model.astype(np.float64) @ R32[:, :3].T + R32[:, 3]
         A, b, stats = normal_equations(x64, m0, m1, ns, c, sig_m, residual, normalize_n)
         dz = gn_step(A, b, RIGID_PIVOT_TOL)
         T = se3_exp(dz) @ T
+        if timings is not None:
+            timings["estep"].append(t1 - t0)
+            timings["mstep"].append(clock() - t1)
         if history is not None:
             history.append(dict(A=A, b=b, stats=stats, dz=dz, T=T.copy()))
         if info is not None:

@@ -165,6 +165,10 @@ _sig("fr_estep_touched", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_x
                                ctypes.POINTER(ctypes.c_int64)])
 _sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
                               ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
+_sig("fr_lattice_records", _st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
+_sig("fr_lattice_build_times", _st, [_P, _P])
+_sig("fr_probe_atomics", _st, [_P, ctypes.c_int64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P])
+_sig("fr_probe_lines", _st, [_P, _i32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P])
 _sig("fr_mstep_reduce_noalloc", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
                                       ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
 _sig("fr_solve_rigid", _st, [_i32, _P, _P, _P, _P, _P, _P, _P, _P])
@@ -194,7 +198,7 @@ ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy
                  "fr_ctx_set_tuning", "fr_ctx_tuning_table",
                  "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
                  "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
-                 "fr_lattice_stats", "fr_lattice_export", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_mstep_reduce_noalloc", "fr_solve_rigid", "fr_register",
+                 "fr_lattice_stats", "fr_lattice_export", "fr_lattice_records", "fr_lattice_build_times", "fr_probe_atomics", "fr_probe_lines", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_mstep_reduce_noalloc", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
                  "fr_articulated_step", "fr_register_articulated", "fr_register_nodegraph", "fr_mstep_reduce_nodes",
                  "fr_engine_create", "fr_engine_destroy", "fr_engine_admit", "fr_engine_step", "fr_engine_read",
@@ -412,6 +416,32 @@ def fr_mstep_reduce(model: Cloud, xf: XForm, m0, m1, nsum, residual: int, c: flo
     _check(_lib.fr_mstep_reduce(model.c(), xf.c(), _ptr(m0), _ptr(m1), _ptr(nsum), ctypes.byref(prm),
                                 _ptr(jtj), _ptr(jtr), _ptr(stats), _stream(stream)))
     del keep
+
+
+def fr_lattice_records(lat):
+    """(incidences D N, partial records inserted) of a lattice's build."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.fr_lattice_records(lat, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def fr_lattice_build_times(lat) -> List[float]:
+    """Device ms of the build's stages: embed, insert + vertex ids, values, final tables."""
+    v = (ctypes.c_double * 4)()
+    _check(_lib.fr_lattice_build_times(lat, v))
+    return list(v)
+
+
+def fr_probe_atomics(ctx, n_atomics: int, table_bytes: int, stream=None) -> float:
+    v = ctypes.c_double()
+    _check(_lib.fr_probe_atomics(ctx, int(n_atomics), int(table_bytes), ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def fr_probe_lines(ctx, lanes_per_line: int, table_bytes: int, stream=None) -> float:
+    v = ctypes.c_double()
+    _check(_lib.fr_probe_lines(ctx, int(lanes_per_line), int(table_bytes), ctypes.byref(v), _stream(stream)))
+    return v.value
 
 
 def fr_mstep_reduce_noalloc(model: Cloud, xf: XForm, m0, m1, nsum, residual: int, c: float, sigma: float, jtj, jtr,

@@ -575,6 +575,29 @@ fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes)
     return FR_OK;
 }
 
+fr_status fr_lattice_records(const fr_lattice *lat, int64_t *incidences, int64_t *partial_records)
+{
+    clear_error();
+    if (!lat_ok(lat) || incidences == nullptr || partial_records == nullptr) {
+        set_error("fr_lattice_records: invalid argument");
+        return FR_EINVAL;
+    }
+    *incidences = lat->n_points_total * (lat->d + 1);
+    *partial_records = lat->n_partials;
+    return FR_OK;
+}
+
+fr_status fr_lattice_build_times(const fr_lattice *lat, double *stage_ms_h)
+{
+    clear_error();
+    if (!lat_ok(lat) || stage_ms_h == nullptr) {
+        set_error("fr_lattice_build_times: invalid argument");
+        return FR_EINVAL;
+    }
+    for (int i = 0; i < 4; ++i) stage_ms_h[i] = (double)lat->stage_ms[i];
+    return FR_OK;
+}
+
 fr_status fr_ctx_set_tuning(fr_ctx *ctx, const fr_tuning *t)
 {
     clear_error();

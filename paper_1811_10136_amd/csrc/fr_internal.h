@@ -88,6 +88,8 @@ struct fr_lattice {
     float k[8] = {0};               // scale factors of the lattice parameters
     std::vector<float> kset;        // n_sets x 8: scale factors of each set (per-set sigma)
     int64_t n_points_total = 0;
+    int64_t n_partials = 0;           // partial records of the last build (runs of shared vertices)
+    float stage_ms[4] = {-1.0f, -1.0f, -1.0f, -1.0f};   // build stages: embed, insert + ids, values, tables
     // bucketed cuckoo tables of all sets, back to back: slot_bytes(KW, VP) per
     // slot, the key words then the padded values
     uint64_t *tab = nullptr;

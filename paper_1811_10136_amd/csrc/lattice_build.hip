@@ -859,6 +859,33 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     return FR_OK;
 }
 
+// HIP events at the boundaries of the build's stages (embed | insert and
+// vertex ids | values | final tables), read after the build's last wait.
+struct StageEvents {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = true;
+    StageEvents()
+    {
+        for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+    ~StageEvents()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t st)
+    {
+        if (ok) ok = hipEventRecord(ev[i], st) == hipSuccess;
+    }
+    void read(float (&ms)[4]) const
+    {
+        for (int i = 0; i < 4; ++i) {
+            ms[i] = -1.0f;
+            if (ok) (void)hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+        }
+    }
+};
+
 template <int d, int V>
 static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat,
                             const int64_t *valued_end, const float *feat = nullptr)
@@ -881,6 +908,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     DevBuf rec_key, rec_cnt, rec_val, rec_slot, own1, t1_d, ptmap, rtmap, fail;
     FR_TRY(fail.alloc(ctx, sizeof(int32_t)));
     FR_TRY(t1_d.alloc(ctx, S * sizeof(SetTable)));
+    StageEvents stage;
+    stage.mark(0, st);
     FR_HIP(hipMemsetAsync(lat->err_d, 0, sizeof(int32_t), st));
 
     // 1. embed: partial records (the runs of each wave, d <= 6; one per
@@ -943,7 +972,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         }
     }
     FR_TRY(rec_slot.alloc(ctx, P * sizeof(uint32_t)));
+    lat->n_partials = (int64_t)P;
 
+    stage.mark(1, st);
     // 2. insert into provisional tables (pow2 >= R_set / 2 first, or twice the
     //    vertices the last build's vertices-per-record ratio predicts if that is
     //    more; 2 R_set if that overflows; R_set = the set's partial records)
@@ -1035,6 +1066,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     }
 
     // 4. values
+    stage.mark(2, st);
     if (NV > 0) {
         if (sorted) {
             DevBuf rvid, rid, tk, tv, voff;
@@ -1080,6 +1112,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     ovid.reset();
     slot_vid.reset();
 
+    stage.mark(3, st);
     // 5. final bucketed two-choice cuckoo tables, load factor 0.4
     constexpr uint32_t SB = SlotGeom<KW, V>::bytes;
     lat->sets_h.resize(S);
@@ -1140,7 +1173,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             FR_HIP(hipGetLastError());
         }
     }
+    stage.mark(4, st);
     FR_HIP(hipStreamSynchronize(st));
+    stage.read(lat->stage_ms);
     return FR_OK;
 }
 
