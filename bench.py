@@ -601,11 +601,15 @@ def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):
             entry["partial_record_bytes"] = part * PARTIAL_BYTES_SORTED
         else:
             atomics = part * ATOMICS_PER_PARTIAL
-            probe = fr.fr_probe_atomics(ctx.h, 1 << 26, 1 << 30)
-            entry["atomic_splat"] = {"atomics": atomics, "values_ms": st[2],
-                                     "atomics_per_s": atomics / st[2] * 1e3,
-                                     "probe_uncontended_atomics_per_s": probe,
-                                     "frac_of_probe": atomics / st[2] * 1e3 / probe}
+            scat = fr.fr_probe_atomics(ctx.h, 1 << 26, 1 << 30, True)
+            pack = fr.fr_probe_atomics(ctx.h, 1 << 26, 1 << 30, False)
+            rate = atomics / st[2] * 1e3
+            entry["atomic_splat"] = {"atomics": atomics, "values_ms": st[2], "atomics_per_s": rate,
+                                     "probe_scattered_atomics_per_s": scat, "probe_packed_atomics_per_s": pack,
+                                     "frac_of_packed_probe": rate / pack,
+                                     "note": "a wave's partial records carry vertex ids in first-touch order, so "
+                                             "its atomics fall on few lines: between the scattered (one line "
+                                             "per atomic) and packed (two lines per wave) probes"}
         res[name] = entry
     return res
 

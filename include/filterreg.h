@@ -621,9 +621,10 @@ fr_status fr_sync_status(const fr_lattice *lat);
  * Roofline probes (measurement only; their buffers are charged to ctx).
  *  fr_probe_atomics: n_atomics binary32 atomic adds without return value, each
  *    to its own word of a power-of-two table of table_bytes (at least
- *    4 n_atomics bytes), neighbouring
- *    threads on different lines: atomics per second (*per_s, host).  The
- *    uncontended ceiling of the atomic splat's vertex sums.
+ *    4 n_atomics bytes); scattered != 0 puts neighbouring threads on
+ *    different lines (one line per atomic), scattered == 0 on neighbouring
+ *    words (a wave's 64 atomics on two lines): atomics per second (*per_s,
+ *    host).  The two uncontended ceilings of the atomic splat's vertex sums.
  *  fr_probe_lines: 16-byte loads, lanes_per_line (1, 2, 4 or 8) lanes of a
  *    wave reading the same 128-byte line, lines drawn at random from a table
  *    of table_bytes (L2-resident when small, HBM when large): 128-byte line
@@ -631,7 +632,8 @@ fr_status fr_sync_status(const fr_lattice *lat);
  *    per key costs one line access per 16-byte load.
  * Both time a few launches with HIP events on `stream` and wait for them.
  */
-fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, double *per_s, void *stream);
+fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, int32_t scattered, double *per_s,
+                           void *stream);
 fr_status fr_probe_lines(fr_ctx *ctx, int32_t lanes_per_line, size_t table_bytes, double *lines_per_s, void *stream);
 
 #ifdef __cplusplus

@@ -167,7 +167,7 @@ _sig("fr_mstep_reduce", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform)
                               ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
 _sig("fr_lattice_records", _st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
 _sig("fr_lattice_build_times", _st, [_P, _P])
-_sig("fr_probe_atomics", _st, [_P, ctypes.c_int64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P])
+_sig("fr_probe_atomics", _st, [_P, ctypes.c_int64, ctypes.c_size_t, _i32, ctypes.POINTER(ctypes.c_double), _P])
 _sig("fr_probe_lines", _st, [_P, _i32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P])
 _sig("fr_mstep_reduce_noalloc", _st, [ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform), _P, _P, _P,
                                       ctypes.POINTER(fr_mstep_params), _P, _P, _P, _P])
@@ -432,9 +432,10 @@ def fr_lattice_build_times(lat) -> List[float]:
     return list(v)
 
 
-def fr_probe_atomics(ctx, n_atomics: int, table_bytes: int, stream=None) -> float:
+def fr_probe_atomics(ctx, n_atomics: int, table_bytes: int, scattered: bool = True, stream=None) -> float:
     v = ctypes.c_double()
-    _check(_lib.fr_probe_atomics(ctx, int(n_atomics), int(table_bytes), ctypes.byref(v), _stream(stream)))
+    _check(_lib.fr_probe_atomics(ctx, int(n_atomics), int(table_bytes), int(bool(scattered)), ctypes.byref(v),
+                                 _stream(stream)))
     return v.value
 
 

@@ -25,14 +25,15 @@ __device__ __forceinline__ uint32_t probe_mix(uint32_t h)
     return h;
 }
 
-// Thread i adds to word (i * odd) mod n_words: a bijection of [0, n_words)
-// for a power-of-two n_words, so no two threads share an address, and
-// neighbouring threads land on different lines.
-__global__ void __launch_bounds__(256) k_probe_atomics(float *table, uint32_t mask, uint64_t n)
+// Thread i adds to word i (packed: the 64 lanes of a wave cover two lines)
+// or to word (i * odd) mod n_words (scattered: a bijection of [0, n_words)
+// for a power-of-two n_words, neighbouring threads on different lines); no
+// two threads share an address either way.
+__global__ void __launch_bounds__(256) k_probe_atomics(float *table, uint32_t mask, uint64_t n, int scattered)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t w = (uint32_t)(i * 0x9E3779B1ull) & mask;
+    const uint32_t w = scattered ? (uint32_t)(i * 0x9E3779B1ull) & mask : (uint32_t)i & mask;
     unsafeAtomicAdd(&table[w], 1.0f);
 }
 
@@ -86,7 +87,8 @@ fr_status time_launches(hipStream_t st, int reps, Launch &&launch, double *sec)
 }
 }  // namespace
 
-fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, double *per_s, void *stream)
+fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, int32_t scattered, double *per_s,
+                           void *stream)
 {
     clear_error();
     if (!ctx_ok(ctx) || per_s == nullptr || n_atomics <= 0 || table_bytes < 1024 ||
@@ -104,7 +106,7 @@ fr_status fr_probe_atomics(fr_ctx *ctx, int64_t n_atomics, size_t table_bytes, d
     const unsigned grid = (unsigned)((n_atomics + 255) / 256);
     double sec = 0.0;
     FR_TRY(time_launches(st, 5, [&](int) {
-        k_probe_atomics<<<grid, 256, 0, st>>>(table.as<float>(), mask, (uint64_t)n_atomics);
+        k_probe_atomics<<<grid, 256, 0, st>>>(table.as<float>(), mask, (uint64_t)n_atomics, scattered);
     }, &sec));
     *per_s = (double)n_atomics / sec;
     return FR_OK;

@@ -62,3 +62,37 @@ def test_a_well_posed_frame_of_the_same_workload_matches_the_oracle(fr, ctx):
     ang, dt, ok = pose_close(T[0], Tr)
     assert st[0] == fr.FR_OK and ok, (ang, dt)
     assert oracle.alignment_error(T[0], p.T_gt, M) < 5e-3
+
+
+# the pairs of the benchmark batch (depth_pair seeds 0..63) that the oracle refuses, and after how many
+# steps: five at the first system, one after one step
+BENCH_REFUSED = {26: 0, 30: 0, 31: 0, 43: 0, 52: 0, 60: 1}
+
+
+def test_the_benchmark_batch_refusals_match_the_oracle(fr, ctx):
+    """The six refused pairs of the 640x480 benchmark batch, with two accepted ones, in one batched call:
+    the GPU refuses exactly those six, each at the oracle's iteration (its pose is the oracle's pose before
+    the refused step), and registers the other two to the oracle's poses."""
+    seeds = list(BENCH_REFUSED) + [0, 1]
+    pairs = [synth.depth_pair(s) for s in seeds]
+    print(f"[degenerate-bench] seeds {seeds}", flush=True)
+    prm = fr.register_params(6, "pt2pl", pairs[0].sigma, pairs[0].sigma_n, iters=20, w=0.1, fixed=True)
+    T, st, rep = fr.register(ctx, upload([p.model for p in pairs], [p.model_n for p in pairs]),
+                             upload([p.obs for p in pairs], [p.obs_n for p in pairs]), prm)
+    assert rep.n_degenerate == len(BENCH_REFUSED)
+    for i, (s, p) in enumerate(zip(seeds, pairs)):
+        hist, info = [], {}
+        if s in BENCH_REFUSED:
+            with pytest.raises(oracle.Degenerate):
+                oracle.register_rigid(p.model, p.model_n, p.obs, p.obs_n, feat=6, residual="pt2pl", sigma=p.sigma,
+                                      sigma_n=p.sigma_n, w=p.w, iters=20, history=hist, info=info)
+            k = info.get("iterations", 0)
+            assert k == BENCH_REFUSED[s]
+            assert st[i] == fr.FR_EDEGENERATE, (s, st[i])
+            ref = np.eye(4) if k == 0 else hist[k - 1]["T"]
+        else:
+            ref = oracle.register_rigid(p.model, p.model_n, p.obs, p.obs_n, feat=6, residual="pt2pl",
+                                        sigma=p.sigma, sigma_n=p.sigma_n, w=p.w, iters=20)
+            assert st[i] == fr.FR_OK, (s, st[i])
+        ang, dt, ok = pose_close(T[i], ref)
+        assert ok, (s, ang, dt)

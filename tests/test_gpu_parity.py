@@ -104,11 +104,12 @@ def test_provisional_table_overflow_and_sizing_from_the_previous_build(fr):
     c.close()
 
 
-def test_lattice_full_depth_frame(fr, ctx):
+@pytest.mark.parametrize("splat", [0, 1], ids=["sorted", "atomic"])
+def test_lattice_full_depth_frame(fr, ctx, splat):
     p = synth.depth_pair(0)
-    _say(f"[lattice-full] depth frame N={len(p.obs)} d=6 V=7")
+    _say(f"[lattice-full] depth frame N={len(p.obs)} d=6 V=7 splat={splat}")
     obs = upload([p.obs], [p.obs_n])
-    lat = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, 0))
+    lat = fr.Lattice(ctx, obs, fr.lattice_params(6, 7, p.sigma, p.sigma_n, splat))
     keys, occ, vals = lat.export(0)
     ref = oracle_lattice(p.obs, p.obs_n, 6, "pt2pl", p.sigma, p.sigma_n)
     assert_lattice_equal(keys, occ, vals, ref, L=float(np.abs(p.obs).max()))
