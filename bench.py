@@ -237,7 +237,18 @@ def make_request_stream(n, seed, workers):
 
 
 def run_plain(fr, ctx, model, obs, arrivals, prm):
-    """One request at a time through fr_register, in arrival order."""
+    """One request at a time through fr_register, in arrival order (the collector frozen as in the
+    server's loop, so neither side pauses for a full collection of the host heap)."""
+    import gc
+    gc.collect()
+    gc.freeze()
+    try:
+        return _run_plain(fr, ctx, model, obs, arrivals, prm)
+    finally:
+        gc.unfreeze()
+
+
+def _run_plain(fr, ctx, model, obs, arrivals, prm):
     from paper_1811_10136_amd.serve import Result
     out = []
     t0 = time.perf_counter()

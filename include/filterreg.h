@@ -91,6 +91,9 @@ fr_status fr_ctx_usage(const fr_ctx *ctx, size_t *bytes_in_use);
  *                    timing waits for the stream once; a launch enqueued while
  *                    the stream is being captured into a graph is not timed
  *                    (it takes FR_SLICE_PLAIN until a later launch tunes).
+ *                    The serving engine times only when the table has no
+ *                    entry for its (d, V, transform kind) yet; otherwise a
+ *                    new size class takes the nearest tuned class's choice.
  * size class = floor(log2(model points of the launch)).
  */
 enum { FR_SLICE_AUTO = 0, FR_SLICE_PLAIN = 1, FR_SLICE_SHARED = 2 };

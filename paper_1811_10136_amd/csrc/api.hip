@@ -32,6 +32,10 @@ StreamScope::~StreamScope() { tls_stream = prev; }
 
 // Sizes are rounded so that freed blocks fit later requests of similar size:
 // powers of two up to 1 MiB, multiples of 2 MiB above.
+// Size classes of the block cache: powers of two up to 1 MiB, then four
+// classes per octave (2^k times 1, 1.25, 1.5, 1.75), so that blocks freed by
+// calls of similar size -- a serving engine's lattice builds -- fit later
+// ones, and the cache holds few distinct sizes; at most 25% is unused.
 static size_t round_alloc(size_t b)
 {
     if (b == 0) b = 16;
@@ -40,8 +44,13 @@ static size_t round_alloc(size_t b)
         while (r < b) r <<= 1;
         return r;
     }
-    const size_t g = (size_t)2 << 20;
-    return (b + g - 1) / g * g;
+    size_t oct = (size_t)1 << 20;   // the largest power of two below b
+    while (oct * 2 < b) oct <<= 1;
+    for (int q = 1; q < 4; ++q) {
+        const size_t c = oct + oct / 4 * (size_t)q;
+        if (b <= c) return c;
+    }
+    return oct * 2;
 }
 
 static void recycle_event(fr_ctx *ctx, hipEvent_t ev)
@@ -76,7 +85,7 @@ fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes)
     const hipStream_t st = current_stream();
     // best fit among cached blocks of this size class that this stream may use now
     int best = -1;
-    const size_t slack = rb <= ((size_t)1 << 20) ? 0 : rb / 4;
+    const size_t slack = 0;   // one size class
     for (int i = 0; i < (int)ctx->cache.size(); ++i) {
         const fr_ctx::Block &b = ctx->cache[i];
         if (b.bytes < rb || b.bytes > rb + slack) continue;
@@ -361,7 +370,7 @@ void scale_factors(const fr_lattice_params *p, float *k)
 
 fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
                              fr_lattice **out, const double *sigma_set, const fr_cloud *joint_model,
-                             const float *joint_mats)
+                             const float *joint_mats, bool wait_end)
 {
     fr_lattice *lat = new (std::nothrow) fr_lattice();
     if (!lat) {
@@ -389,7 +398,7 @@ fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_
     fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
     if (s == FR_OK)
         s = joint_model ? build_joint_lattice(ctx, obs, joint_model, joint_mats, params, st, lat)
-                        : build_lattice(ctx, obs, params, st, lat);
+                        : build_lattice(ctx, obs, params, st, lat, nullptr, wait_end);
     if (s != FR_OK) {
         free_lattice(lat, st, false);
         lat->magic = kDeadMagic;

@@ -366,18 +366,10 @@ fr_status fr_engine_admit(fr_engine *e, int32_t n, const int32_t *slots_h, const
     StreamScope scope(e->bst);
 
     // lattices of the n observations: one build on the build stream
+    // (the build reports a key-range overflow itself, FR_ERANGE, from the wait for its record
+    // counts; its last kernels need no wait: the steps are ordered after the build on the device)
     fr_lattice *lat = nullptr;
-    FR_TRY(lattice_build_impl(e->ctx, obs, &lp, e->bst, &lat));
-    int32_t lat_err = 0;
-    FR_HIP(hipMemcpyAsync(&lat_err, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, e->bst));
-    FR_HIP(hipStreamSynchronize(e->bst));
-    if (lat_err) {
-        free_lattice(lat, e->bst, false);
-        lat->magic = kDeadMagic;
-        delete lat;
-        set_error("fr_engine_admit: an observation coordinate left the lattice key range");
-        return FR_ERANGE;
-    }
+    FR_TRY(lattice_build_impl(e->ctx, obs, &lp, e->bst, &lat, nullptr, nullptr, nullptr, false));
     int32_t g = 0;
     while (g < (int32_t)e->groups.size() && e->groups[g].lat != nullptr) ++g;
     if (g == (int32_t)e->groups.size()) e->groups.push_back(fr_engine::Group{});
@@ -519,6 +511,7 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         p.seg_c = d_c;
         p.ctx = e->ctx;
         p.slice = e->ctx->slice_mode;
+        p.tune_new_classes = false;   // the resident set changes size every step: reuse the nearest tuned class
     };
     Plan pe, pr;
     make(d_te, te[S], kEstepTile, pe);

@@ -9,6 +9,8 @@
 // arrays, coalesced, non-temporal so they do not evict the table from L2);
 // the table of the set being sliced is read through L2, and the logical tile
 // order keeps one set's tiles on one XCD.
+#include <cstdlib>
+
 #include "fr_internal.h"
 #include "fr_mstep.h"
 
@@ -423,18 +425,26 @@ static void launch_dv(const EstepArgs &a, bool xf, bool touch, int slice, int gr
 // kept in the context's table.  One wait for the stream; nothing is timed
 // while the stream is being captured into a graph.
 template <class Launch>
-static fr_status autotune_slice(fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts, hipStream_t st, Launch &launch,
-                                int &slice)
+static fr_status autotune_slice(fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts, bool tune_new, hipStream_t st,
+                                Launch &launch, int &slice)
 {
     slice = FR_SLICE_PLAIN;
     if (ctx == nullptr) return FR_OK;
     int32_t cls = 0;
     while (cls < 62 && (2ll << cls) <= pts) ++cls;
-    for (const fr_tuning_entry &e : ctx->tuned)
-        if (e.d == d && e.V == V && e.xf_kind == xf_kind && e.size_class == cls) {
+    const fr_tuning_entry *near = nullptr;
+    for (const fr_tuning_entry &e : ctx->tuned) {
+        if (e.d != d || e.V != V || e.xf_kind != xf_kind) continue;
+        if (e.size_class == cls) {
             slice = e.slice;
             return FR_OK;
         }
+        if (near == nullptr || std::abs(e.size_class - cls) < std::abs(near->size_class - cls)) near = &e;
+    }
+    if (!tune_new && near != nullptr) {
+        slice = near->slice;
+        return FR_OK;
+    }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     FR_HIP(hipStreamIsCapturing(st, &cs));
     if (cs != hipStreamCaptureStatusNone) return FR_OK;
@@ -519,7 +529,8 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
     };
     int slice = touch ? FR_SLICE_PLAIN : plan.slice;
     if (slice == FR_SLICE_AUTO)
-        FR_TRY(autotune_slice(plan.ctx, d, V, xf_kind, (int64_t)plan.n_tiles * plan.tile, st, launch, slice));
+        FR_TRY(autotune_slice(plan.ctx, d, V, xf_kind, (int64_t)plan.n_tiles * plan.tile, plan.tune_new_classes, st,
+                              launch, slice));
     return launch(slice);
 }
 

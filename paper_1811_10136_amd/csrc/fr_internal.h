@@ -136,7 +136,8 @@ fr_status check_lattice_params(const fr_lattice_params *p);
 // NULL for the identity); the model points carry no value.
 fr_status lattice_build_impl(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params, hipStream_t st,
                              fr_lattice **out, const double *sigma_set = nullptr,
-                             const fr_cloud *joint_model = nullptr, const float *joint_mats = nullptr);
+                             const fr_cloud *joint_model = nullptr, const float *joint_mats = nullptr,
+                             bool wait_end = true);
 void scale_factors(const fr_lattice_params *p, float *k);
 // c of Eq. 7 in the units of the lattice sums (w/(1-w) N/M times the kernel's
 // mass over feature space; blurred: the uncustomised filter's kernel).
@@ -186,6 +187,9 @@ struct Plan {
     const float *seg_c = nullptr;   // device, per segment outlier constant (reduce only)
     int32_t slice = FR_SLICE_AUTO;  // E-step slice kernel (FR_SLICE_*; AUTO: the context's autotuner)
     fr_ctx *ctx = nullptr;          // context of the plan (autotuner table)
+    // false: an untuned size class takes the choice of the nearest tuned class of the same (d, V,
+    // transform) instead of timing (the serving engine, whose launches change size every step)
+    bool tune_new_classes = true;
 };
 
 // Build a plan for `model_ref` segmented per `xf` (NULL = per set).
@@ -204,8 +208,11 @@ fr_status check_cloud(const fr_cloud *c, bool need_normals, const char *what);
 
 // --- launchers ---------------------------------------------------------------
 // lattice_build.hip
+// wait_end == false: return once the last kernel is enqueued (the build still
+// waits for its own sizes on the way); later work must be ordered after it on
+// the device, and the stage times are not read.
 fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
-                        fr_lattice *lat, const int64_t *valued_end = nullptr);
+                        fr_lattice *lat, const int64_t *valued_end = nullptr, bool wait_end = true);
 // Joint splat of each set's observation (valued) and its model moved by mats
 // (device, n_sets x 12 [R | t], or NULL), for the uncustomised filter.
 fr_status build_joint_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model, const float *mats,

@@ -271,6 +271,37 @@ template <int V> struct PartialType { using T = float; };
 template <> struct PartialType<5> { using T = double; };   // |y|^2 layouts: the scatter about the
 template <> struct PartialType<8> { using T = double; };   // mean is formed after the sums
 
+// A partial record's values are one row: the V sums, then the incidence count
+// (exact in T), padded to whole 16-byte chunks, so a gather reads one or two
+// lines per record instead of one per channel.  Keys are rows of KW words.
+template <int V> struct PartialRow {
+    using T = typename PartialType<V>::T;
+    static constexpr int S = (int)((((V + 1) * sizeof(T)) + 15) / 16 * 16 / sizeof(T));   // elements per row
+    static constexpr int Q = (int)(S * sizeof(T) / 16);                                   // 16-byte chunks
+};
+
+template <int V>
+__device__ __forceinline__ void store_row(typename PartialRow<V>::T *rows, size_t q,
+                                          const typename PartialRow<V>::T (&v)[PartialRow<V>::S])
+{
+    using R = PartialRow<V>;
+    uint4 *dst = reinterpret_cast<uint4 *>(rows + q * R::S);
+    const uint4 *src = reinterpret_cast<const uint4 *>(v);
+#pragma unroll
+    for (int c = 0; c < R::Q; ++c) dst[c] = src[c];
+}
+
+template <int V>
+__device__ __forceinline__ void load_row(const typename PartialRow<V>::T *rows, size_t q,
+                                         typename PartialRow<V>::T (&v)[PartialRow<V>::S])
+{
+    using R = PartialRow<V>;
+    const uint4 *src = reinterpret_cast<const uint4 *>(rows + q * R::S);
+    uint4 *dst = reinterpret_cast<uint4 *>(v);
+#pragma unroll
+    for (int c = 0; c < R::Q; ++c) dst[c] = src[c];
+}
+
 template <int d>
 __device__ __forceinline__ void load_feature(const Pts &pts, int64_t i, float (&p)[d])
 {
@@ -337,8 +368,8 @@ template <int d, int V> struct PartialLds {
 
 template <int d, int V>
 __global__ void __launch_bounds__(256) k_build_partials(Pts pts, TileMap tm, const float *kset,
-                                                       const uint32_t *wave_off, uint64_t *pkey, uint32_t *pcnt,
-                                                       typename PartialType<V>::T *pval, size_t P,
+                                                       const uint32_t *wave_off, uint64_t *pkey,
+                                                       typename PartialType<V>::T *prow, size_t P,
                                                        const int64_t *valued_end)
 {
     using T = typename PartialType<V>::T;
@@ -426,10 +457,12 @@ __global__ void __launch_bounds__(256) k_build_partials(Pts pts, TileMap tm, con
         lds_get_key<KW>(lds + (o * D + c) * 8 * KW, key);
         const size_t q = base + (size_t)e;
 #pragma unroll
-        for (int w = 0; w < KW; ++w) pkey[(size_t)w * P + q] = key[w];
-        pcnt[q] = (uint32_t)(stop - o);
+        for (int w = 0; w < KW; ++w) pkey[q * KW + w] = key[w];
+        alignas(16) T row[PartialRow<V>::S];
 #pragma unroll
-        for (int ch = 0; ch < V; ++ch) pval[(size_t)ch * P + q] = (T)acc[ch];
+        for (int ch = 0; ch < PartialRow<V>::S; ++ch) row[ch] = ch < V ? (T)acc[ch] : (T)0;
+        row[V] = (T)(stop - o);
+        store_row<V>(prow, q, row);
     }
 }
 
@@ -448,8 +481,7 @@ __global__ void k_set_partial_off(int32_t n_sets, const int32_t *seg_tile, const
 // b [1, y] (binary32 products).
 template <int d>
 __global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const float *kf, TileMap tm, Pts pts,
-                                                   uint64_t *rec_key, uint32_t *rec_cnt, float *rec_val, size_t R,
-                                                   int32_t *err)
+                                                   uint64_t *rec_key, float *rec_row, size_t R, int32_t *err)
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
@@ -479,12 +511,23 @@ __global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const flo
     for (int m = 0; m < D; ++m) {   // one vertex at a time: keeps the key walk in registers
         const float b = embed_hd_next<d>(h, m);
 #pragma unroll
-        for (int w = 0; w < KW; ++w) rec_key[(size_t)w * R + r0 + m] = h.P[w];
-        rec_cnt[r0 + m] = 1u;
-        rec_val[r0 + m] = b;
-        rec_val[R + r0 + m] = b * y0;
-        rec_val[2 * R + r0 + m] = b * y1;
-        rec_val[3 * R + r0 + m] = b * y2;
+        for (int w = 0; w < KW; ++w) rec_key[(r0 + m) * KW + w] = h.P[w];
+        alignas(16) float row[PartialRow<4>::S] = {b, b * y0, b * y1, b * y2, 1.0f, 0.0f, 0.0f, 0.0f};
+        store_row<4>(rec_row, r0 + m, row);
+    }
+}
+
+// Key words of record r (rows of KW words; one 16-byte load for KW = 2).
+template <int KW>
+__device__ __forceinline__ void load_key_row(const uint64_t *rec_key, size_t r, uint64_t (&k)[KW])
+{
+    if constexpr (KW == 2) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(rec_key + 2 * r);
+        k[0] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+        k[1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+    } else {
+#pragma unroll
+        for (int w = 0; w < KW; ++w) k[w] = rec_key[r * KW + w];
     }
 }
 
@@ -494,40 +537,41 @@ __global__ void __launch_bounds__(256) k_embed_feat(const float *feat, const flo
 // first merged in LDS: each record finds or claims its key in a small
 // open-addressing table of the workgroup, and only the record that claimed a
 // key (its representative) probes the global table; the others take the
-// representative's slot.  In the global table a slot that already has an
+// representative's slot (MERGE; without it every record probes).  In the global table a slot that already has an
 // owner is compared with a plain read first; only free slots are claimed with
 // a CAS; owner_flag[r] = 1 marks the record whose CAS claimed the slot (the
 // owner of its vertex).  Probing stops after kMaxProbe slots and raises
 // `fail` (the host then retries with a larger table).
 constexpr uint32_t kMaxProbe = 128;
+constexpr unsigned long long kSlotEmpty = ~0ull;   // a free provisional slot
 constexpr uint32_t kTileKeySlots = 512;   // LDS table of a tile: at most 256 keys, load <= 1/2
 
-template <int KW>
+template <int KW, bool MERGE>
 __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTable *tables, const uint64_t *rec_key,
-                                                       size_t R, uint32_t *own, uint32_t *rec_slot,
+                                                       size_t R, unsigned long long *own, uint32_t *rec_slot,
                                                        uint32_t *owner_flag, int32_t *fail)
 {
-    __shared__ uint64_t lkey[KW][256];
-    __shared__ uint32_t lown[kTileKeySlots];
-    __shared__ uint32_t lslot[256];
+    __shared__ uint64_t lkey[MERGE ? KW : 1][MERGE ? 256 : 1];
+    __shared__ uint32_t lown[MERGE ? kTileKeySlots : 1];
+    __shared__ uint32_t lslot[MERGE ? 256 : 1];
     const int32_t t = logical_tile(tm);
     if (t >= tm.n_tiles) return;   // uniform over the workgroup
     const int32_t s = tile_segment(tm, t);
     const uint32_t tid = threadIdx.x;
     const int64_t r = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + tid;
     const bool active = r < tm.seg_end[s];
-    for (uint32_t j = tid; j < kTileKeySlots; j += blockDim.x) lown[j] = kOwnerEmpty;
+    if constexpr (MERGE)
+        for (uint32_t j = tid; j < kTileKeySlots; j += blockDim.x) lown[j] = kOwnerEmpty;
     uint64_t key[KW];
     if (active) {
+        load_key_row<KW>(rec_key, (size_t)r, key);
+        if constexpr (MERGE)
 #pragma unroll
-        for (int w = 0; w < KW; ++w) {
-            key[w] = rec_key[(size_t)w * R + r];
-            lkey[w][tid] = key[w];
-        }
+            for (int w = 0; w < KW; ++w) lkey[w][tid] = key[w];
     }
-    __syncthreads();
+    if constexpr (MERGE) __syncthreads();
     uint32_t rep = tid;
-    if (active) {
+    if (MERGE && active) {
         uint32_t h = hash_key<KW>(key, 0x9E3779B9u) & (kTileKeySlots - 1);
         for (uint32_t n = 0; n < kTileKeySlots; ++n) {   // ends: fewer keys than slots
             const uint32_t o = atomicCAS(&lown[h], kOwnerEmpty, tid);
@@ -546,33 +590,44 @@ __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTab
     if (active && rep == tid) {
         const SetTable st = tables[s];
         uint32_t h = hash_key<KW>(key, 0u) & st.mask;
+        // a slot holds (fingerprint << 32) | owner record; the fingerprint, a second hash of the key,
+        // lets a probe pass slots of other keys without reading their owner's key
+        const uint32_t fp = hash_key<KW>(key, 0x51ED270Bu);
+        const unsigned long long mine64 = ((unsigned long long)fp << 32) | (uint32_t)r;
         const uint32_t limit = min(st.mask + 1u, kMaxProbe);
         uint32_t found = kOwnerEmpty;
         for (uint32_t n = 0; n < limit; ++n) {
             const size_t slot = st.slot_base + h;
-            uint32_t o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (o == kOwnerEmpty) o = atomicCAS(&own[slot], kOwnerEmpty, (uint32_t)r);
-            won = (o == kOwnerEmpty);
-            bool mine = won;
-            if (!mine) {
-                mine = true;
-#pragma unroll
-                for (int w = 0; w < KW; ++w) mine = mine && (rec_key[(size_t)w * R + o] == key[w]);
+            unsigned long long o = __hip_atomic_load(&own[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (o == kSlotEmpty) o = atomicCAS(&own[slot], kSlotEmpty, mine64);
+            won = (o == kSlotEmpty);
+            bool match = won;
+            if (!match && (uint32_t)(o >> 32) == fp) {
+                uint64_t ok[KW];
+                load_key_row<KW>(rec_key, (size_t)(uint32_t)o, ok);
+                match = key_equal<KW>(ok, key);
             }
-            if (mine) {
+            if (match) {
                 found = (uint32_t)slot;
                 break;
             }
             h = (h + 1) & st.mask;
         }
         if (found == kOwnerEmpty) atomicOr(fail, 1);
-        lslot[tid] = found;
+        if constexpr (MERGE) {
+            lslot[tid] = found;
+        } else {
+            if (found != kOwnerEmpty) rec_slot[r] = found;
+            owner_flag[r] = won ? 1u : 0u;
+        }
     }
-    __syncthreads();
-    if (active) {
-        const uint32_t slot = lslot[rep];
-        if (slot != kOwnerEmpty) rec_slot[r] = slot;
-        owner_flag[r] = won ? 1u : 0u;
+    if constexpr (MERGE) {
+        __syncthreads();
+        if (active) {
+            const uint32_t slot = lslot[rep];
+            if (slot != kOwnerEmpty) rec_slot[r] = slot;
+            owner_flag[r] = won ? 1u : 0u;
+        }
     }
 }
 
@@ -591,7 +646,7 @@ __global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *re
     if (next == v) return;
     const uint32_t slot = rec_slot[r];
 #pragma unroll
-    for (int w = 0; w < KW; ++w) vkey[(size_t)w * NV + v] = rec_key[(size_t)w * R + r];
+    for (int w = 0; w < KW; ++w) vkey[(size_t)w * NV + v] = rec_key[(size_t)r * KW + w];
     slot_vid[slot] = v;
 }
 
@@ -628,11 +683,14 @@ __global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t 
 
 // Sorted mode: per vertex, the partials in partial order summed in binary64
 // (occupancy = the sum of their incidence counts) -> bitwise deterministic.
-template <int V, typename T>
+template <int V>
 __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, const uint32_t *voff,
-                                                          const uint32_t *rid_sorted, const uint32_t *pcnt,
-                                                          const T *pval, float *vval, uint32_t *vocc)
+                                                          const uint32_t *rid_sorted,
+                                                          const typename PartialRow<V>::T *prow, float *vval,
+                                                          uint32_t *vocc)
 {
+    using R = PartialRow<V>;
+    using T = typename R::T;
     const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= NV) return;
     double acc[V];
@@ -640,24 +698,20 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, 
     for (int c = 0; c < V; ++c) acc[c] = 0.0;
     uint32_t occ = 0;
     const uint32_t q0 = voff[v], q1 = v + 1 < NV ? voff[v + 1] : (uint32_t)P;
-    for (uint32_t q = q0; q < q1; q += 4) {
-        uint32_t r[4];
+    for (uint32_t q = q0; q < q1; q += 2) {
+        // two rows in flight
+        uint32_t r[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = (q + u < q1) ? rid_sorted[q + u] : rid_sorted[q0];
-        T val[4][V];
-        uint32_t cnt[4];
+        for (int u = 0; u < 2; ++u) r[u] = (q + u < q1) ? rid_sorted[q + u] : rid_sorted[q0];
+        alignas(16) T row[2][R::S];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            cnt[u] = pcnt[r[u]];
+        for (int u = 0; u < 2; ++u) load_row<V>(prow, r[u], row[u]);
 #pragma unroll
-            for (int c = 0; c < V; ++c) val[u][c] = pval[(size_t)c * P + r[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
             if (q + u >= q1) break;
-            occ += cnt[u];
+            occ += (uint32_t)row[u][V];
 #pragma unroll
-            for (int c = 0; c < V; ++c) acc[c] += (double)val[u][c];
+            for (int c = 0; c < V; ++c) acc[c] += (double)row[u][c];
         }
     }
     if constexpr (ValLayout<V>::m2) {
@@ -673,18 +727,22 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, 
 
 // Atomic mode: one thread per partial, binary32 hardware atomics of its sums;
 // occupancy by integer atomics.  The |y|^2 channel waits for the second pass.
-template <int V, typename T>
+template <int V>
 __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint32_t *rec_slot,
-                                                          const uint32_t *slot_vid, const uint32_t *pcnt,
-                                                          const T *pval, float *vval, uint32_t *vocc, size_t NV)
+                                                          const uint32_t *slot_vid,
+                                                          const typename PartialRow<V>::T *prow, float *vval,
+                                                          uint32_t *vocc, size_t NV)
 {
+    using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= P) return;
     const uint32_t v = slot_vid[rec_slot[q]];
-    atomicAdd(&vocc[v], pcnt[q]);
+    alignas(16) typename R::T row[R::S];
+    load_row<V>(prow, q, row);
+    atomicAdd(&vocc[v], (uint32_t)row[V]);
     constexpr int NL = ValLayout<V>::m2 ? V - 1 : V;
 #pragma unroll
-    for (int c = 0; c < NL; ++c) unsafeAtomicAdd(&vval[(size_t)c * NV + v], (float)pval[(size_t)c * P + q]);
+    for (int c = 0; c < NL; ++c) unsafeAtomicAdd(&vval[(size_t)c * NV + v], (float)row[c]);
 }
 
 // Atomic mode, |y|^2 layouts: second pass once the means are complete.  A
@@ -692,18 +750,22 @@ __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint3
 // W_p |mu_p - mu_v|^2 about the vertex mean mu_v = M1_v / W_v (the parallel
 // form of the scatter; about a mean rounded to binary32 it is larger by
 // W |mu - mu'|^2, far below the binary32 resolution of the sum).
-template <int V, typename T>
+template <int V>
 __global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t P, const uint32_t *rec_slot,
-                                                              const uint32_t *slot_vid, const T *pval, float *vval,
+                                                              const uint32_t *slot_vid,
+                                                              const typename PartialRow<V>::T *prow, float *vval,
                                                               size_t NV)
 {
+    using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= P) return;
     const uint32_t v = slot_vid[rec_slot[q]];
-    const double W = (double)pval[q];
+    alignas(16) typename R::T row[R::S];
+    load_row<V>(prow, q, row);
+    const double W = (double)row[0];
     if (!(W > 0.0)) return;
-    const double m1x = (double)pval[P + q], m1y = (double)pval[2 * P + q], m1z = (double)pval[3 * P + q];
-    const double own = fmax((double)pval[(size_t)(V - 1) * P + q] - (m1x * m1x + m1y * m1y + m1z * m1z) / W, 0.0);
+    const double m1x = (double)row[1], m1y = (double)row[2], m1z = (double)row[3];
+    const double own = fmax((double)row[V - 1] - (m1x * m1x + m1y * m1y + m1z * m1z) / W, 0.0);
     const float Wv = vval[v];
     const double iv = Wv > 0.0f ? 1.0 / (double)Wv : 0.0;
     const double dx = m1x / W - (double)vval[NV + v] * iv;
@@ -831,8 +893,12 @@ static inline unsigned blocks_for(size_t n, int threads) { return (unsigned)((n 
 // past the last tile return at once).
 static unsigned grid_of(const TileMap &tm) { return (unsigned)(tm.xcd_chunk > 0 ? tm.xcd_chunk * 8 : tm.n_tiles); }
 
+// keep != NULL: the host image is kept there until the caller's next wait
+// (no wait here); else the call waits for the copy.
+using HostKeep = std::vector<std::vector<char>>;
+
 static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, int32_t tile, hipStream_t st,
-                                 DevBuf &buf, TileMap &tm, bool xcd = false)
+                                 DevBuf &buf, TileMap &tm, bool xcd = false, HostKeep *keep = nullptr)
 {
     const int32_t n = (int32_t)off.size() - 1;
     std::vector<int32_t> tiles(n + 1, 0), sets(n);
@@ -843,9 +909,11 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     const size_t b_off = sizeof(int64_t) * (n + 1), b_tile = sizeof(int32_t) * (n + 1), b_set = sizeof(int32_t) * n;
     FR_TRY(buf.alloc(ctx, b_off + b_tile + b_set));
     char *p = buf.as<char>();
-    FR_HIP(hipMemcpyAsync(p, off.data(), b_off, hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(p + b_off, tiles.data(), b_tile, hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(p + b_off + b_tile, sets.data(), b_set, hipMemcpyHostToDevice, st));
+    std::vector<char> image(b_off + b_tile + b_set);
+    std::memcpy(image.data(), off.data(), b_off);
+    std::memcpy(image.data() + b_off, tiles.data(), b_tile);
+    std::memcpy(image.data() + b_off + b_tile, sets.data(), b_set);
+    FR_HIP(hipMemcpyAsync(p, image.data(), image.size(), hipMemcpyHostToDevice, st));
     tm.seg_off = reinterpret_cast<const int64_t *>(p);
     tm.seg_end = tm.seg_off + 1;
     tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
@@ -855,7 +923,11 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     tm.tile = tile;
     // XCD-contiguous tiles: a set's tiles run on one XCD, so the set's tables stay in that XCD's L2
     tm.xcd_chunk = (xcd && tm.n_tiles >= 8 * 64) ? (tm.n_tiles + 7) / 8 : 0;
-    FR_HIP(hipStreamSynchronize(st));   // host vectors go out of scope
+    if (keep != nullptr) {
+        keep->push_back(std::move(image));
+        return FR_OK;
+    }
+    FR_HIP(hipStreamSynchronize(st));   // the host image goes out of scope
     return FR_OK;
 }
 
@@ -888,8 +960,9 @@ struct StageEvents {
 
 template <int d, int V>
 static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat,
-                            const int64_t *valued_end, const float *feat = nullptr)
+                            const int64_t *valued_end, const float *feat = nullptr, bool wait_end = true)
 {
+    HostKeep keep;   // host images of the tile maps, alive until the build's waits
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
@@ -905,7 +978,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     Pts pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
     using T = typename PartialType<V>::T;
 
-    DevBuf rec_key, rec_cnt, rec_val, rec_slot, own1, t1_d, ptmap, rtmap, fail;
+    DevBuf rec_key, rec_row, rec_slot, own1, t1_d, ptmap, rtmap, fail;
     FR_TRY(fail.alloc(ctx, sizeof(int32_t)));
     FR_TRY(t1_d.alloc(ctx, S * sizeof(SetTable)));
     StageEvents stage;
@@ -916,7 +989,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     //    incidence for descriptors); roff = the partials of each set
     std::vector<int64_t> poff(obs->offsets, obs->offsets + S + 1);
     TileMap ptm{}, rtm{};
-    FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm));
+    FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm, false, &keep));
     DevBuf kset_d;
     FR_TRY(kset_d.alloc(ctx, lat->kset.size() * sizeof(float)));
     FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -926,12 +999,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         P = R;
         for (int32_t s = 0; s <= S; ++s) roff[s] = obs->offsets[s] * D;
         FR_TRY(rec_key.alloc(ctx, P * KW * sizeof(uint64_t)));
-        FR_TRY(rec_cnt.alloc(ctx, P * sizeof(uint32_t)));
-        FR_TRY(rec_val.alloc(ctx, P * V * sizeof(T)));
+        FR_TRY(rec_row.alloc(ctx, P * PartialRow<V>::S * sizeof(T)));
         if (ptm.n_tiles > 0) {
             k_embed_feat<d><<<ptm.n_tiles, 256, 0, st>>>(feat, lat->kfeat_d, ptm, pts, rec_key.as<uint64_t>(),
-                                                         rec_cnt.as<uint32_t>(), rec_val.as<float>(), P,
-                                                         lat->err_d);
+                                                         rec_row.as<float>(), P, lat->err_d);
             FR_HIP(hipGetLastError());
         }
     } else {
@@ -961,13 +1032,11 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         for (int32_t s = 0; s <= S; ++s) roff[s] = so[s];
         P = so[S];
         FR_TRY(rec_key.alloc(ctx, P * KW * sizeof(uint64_t)));
-        FR_TRY(rec_cnt.alloc(ctx, P * sizeof(uint32_t)));
-        FR_TRY(rec_val.alloc(ctx, P * V * sizeof(T)));
+        FR_TRY(rec_row.alloc(ctx, P * PartialRow<V>::S * sizeof(T)));
         if (ptm.n_tiles > 0 && P > 0) {
             k_build_partials<d, V><<<ptm.n_tiles, 256, 0, st>>>(pts, ptm, kset_d.as<float>(),
                                                                 wave_cnt.as<uint32_t>(), rec_key.as<uint64_t>(),
-                                                                rec_cnt.as<uint32_t>(), rec_val.as<T>(), P,
-                                                                valued_end);
+                                                                rec_row.as<T>(), P, valued_end);
             FR_HIP(hipGetLastError());
         }
     }
@@ -975,10 +1044,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     lat->n_partials = (int64_t)P;
 
     stage.mark(1, st);
-    // 2. insert into provisional tables (pow2 >= R_set / 2 first, or twice the
-    //    vertices the last build's vertices-per-record ratio predicts if that is
-    //    more; 2 R_set if that overflows; R_set = the set's partial records)
-    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
+    // 2. insert into provisional tables (pow2 >= R_set / 2 first, or four times
+    //    the vertices the last build's vertices-per-record ratio predicts if that
+    //    is more; 2 R_set if that overflows; R_set = the set's partial records)
+    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true, &keep));
     uint64_t n1 = 0;
     DevBuf ovid, slot_vid, vb_d, last_d;
     FR_TRY(ovid.alloc(ctx, P * sizeof(uint32_t)));   // owner flags, then their exclusive scan
@@ -991,7 +1060,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         n1 = 0;
         for (int32_t s = 0; s < S; ++s) {
             const uint64_t rs = (uint64_t)(roff[s + 1] - roff[s]);
-            const uint64_t guess = (uint64_t)(2.0 * std::min(ctx->vertex_ratio, 1.0) * (double)rs);
+            const uint64_t guess = (uint64_t)(4.0 * std::min(ctx->vertex_ratio, 1.0) * (double)rs);
             const uint32_t cap = next_pow2(attempt == 0 ? std::max<uint64_t>(rs / 2, guess) : 2 * rs);
             if (2 * rs > (1ull << 31) && attempt == 1) {
                 set_error("fr_lattice_build: set %d has too many partial records (%llu)", s, (unsigned long long)rs);
@@ -1004,14 +1073,16 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             set_error("fr_lattice_build: provisional table too large");
             return FR_EINVAL;
         }
-        FR_TRY(own1.alloc(ctx, n1 * sizeof(uint32_t)));
+        FR_TRY(own1.alloc(ctx, n1 * sizeof(unsigned long long)));
         FR_HIP(hipMemcpyAsync(t1_d.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
-        FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(uint32_t), st));
+        FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(unsigned long long), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (rtm.n_tiles > 0) {
-            k_insert_records<KW><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), P,
-                                                              own1.as<uint32_t>(), rec_slot.as<uint32_t>(),
-                                                              ovid.as<uint32_t>(), fail.as<int32_t>());
+            k_insert_records<KW, true><<<grid_of(rtm), 256, 0, st>>>(rtm, t1_d.as<SetTable>(),
+                                                                        rec_key.as<uint64_t>(), P,
+                                                                        own1.as<unsigned long long>(),
+                                                                        rec_slot.as<uint32_t>(),
+                                                                        ovid.as<uint32_t>(), fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
         // 3. vertex ids in owner-record order and per-set ranges, enqueued before the
@@ -1085,28 +1156,26 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                     tv.as<uint32_t>(), P, bits, st, &svid, &srid));
             k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
-            k_vertex_sum_sorted<V, T><<<blocks_for(NV, 256), 256, 0, st>>>(
-                NV, P, voff.as<uint32_t>(), srid, rec_cnt.as<uint32_t>(), rec_val.as<T>(), lat->vval, lat->vocc);
+            k_vertex_sum_sorted<V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, P, voff.as<uint32_t>(), srid,
+                                                                        rec_row.as<T>(), lat->vval, lat->vocc);
             FR_HIP(hipGetLastError());
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
             FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
-            k_vertex_sum_atomic<V, T><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(),
-                                                                           slot_vid.as<uint32_t>(),
-                                                                           rec_cnt.as<uint32_t>(), rec_val.as<T>(),
-                                                                           lat->vval, lat->vocc, NV);
+            k_vertex_sum_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(),
+                                                                        slot_vid.as<uint32_t>(), rec_row.as<T>(),
+                                                                        lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
             if constexpr (ValLayout<V>::m2) {
-                k_vertex_scatter_atomic<V, T><<<blocks_for(P, 256), 256, 0, st>>>(
-                    P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_val.as<T>(), lat->vval, NV);
+                k_vertex_scatter_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(
+                    P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_row.as<T>(), lat->vval, NV);
                 FR_HIP(hipGetLastError());
             }
         }
     }
     // the provisional table and records are no longer needed
     rec_key.reset();
-    rec_cnt.reset();
-    rec_val.reset();
+    rec_row.reset();
     rec_slot.reset();
     own1.reset();
     ovid.reset();
@@ -1140,7 +1209,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     DevBuf own2, vtmap;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
     TileMap vtm{};
-    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true));
+    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true, &keep));
     for (int attempt = 0;; ++attempt) {
         FR_HIP(hipMemcpyAsync(lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
         FR_HIP(hipMemsetAsync(own2.p, 0xFF, n2 * sizeof(uint32_t), st));
@@ -1174,23 +1243,25 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         }
     }
     stage.mark(4, st);
+    if (!wait_end) return FR_OK;   // the caller orders later work after the build on the device
     FR_HIP(hipStreamSynchronize(st));
     stage.read(lat->stage_ms);
     return FR_OK;
 }
 
 fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
-                        fr_lattice *lat, const int64_t *valued_end)
+                        fr_lattice *lat, const int64_t *valued_end, bool wait_end)
 {
     const int64_t *ve = valued_end;
-    if (prm->feat == 3 && prm->values == 4) return build_impl<3, 4>(ctx, obs, st, lat, ve);
-    if (prm->feat == 3 && prm->values == 7) return build_impl<3, 7>(ctx, obs, st, lat, ve);
-    if (prm->feat == 6 && prm->values == 4) return build_impl<6, 4>(ctx, obs, st, lat, ve);
-    if (prm->feat == 6 && prm->values == 7) return build_impl<6, 7>(ctx, obs, st, lat, ve);
-    if (prm->feat == 3 && prm->values == 5) return build_impl<3, 5>(ctx, obs, st, lat, ve);
-    if (prm->feat == 3 && prm->values == 8) return build_impl<3, 8>(ctx, obs, st, lat, ve);
-    if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat, ve);
-    if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat, ve);
+    const bool w = wait_end;
+    if (prm->feat == 3 && prm->values == 4) return build_impl<3, 4>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 3 && prm->values == 7) return build_impl<3, 7>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 6 && prm->values == 4) return build_impl<6, 4>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 6 && prm->values == 7) return build_impl<6, 7>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 3 && prm->values == 5) return build_impl<3, 5>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 3 && prm->values == 8) return build_impl<3, 8>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 6 && prm->values == 5) return build_impl<6, 5>(ctx, obs, st, lat, ve, nullptr, w);
+    if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat, ve, nullptr, w);
     set_error("fr_lattice_build: unsupported feat=%d values=%d", prm->feat, prm->values);
     return FR_EINVAL;
 }

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import bisect
 import collections
+import gc
 import dataclasses
 import math
 import time
@@ -127,6 +128,17 @@ class Server:
         return self.b.usage() + extra + self.bpp * req.n <= self.budget
 
     def run(self, requests: Sequence[Request], on_tick: Optional[Callable] = None) -> List[Result]:
+        # a collection of Python's oldest generation walks the whole host heap and stalls the tick loop
+        # for tens of milliseconds (every request resident then waits); the objects alive at the start
+        # are frozen out of the collector for the run, so collections only see what the run allocates
+        gc.collect()
+        gc.freeze()
+        try:
+            return self._run(requests, on_tick)
+        finally:
+            gc.unfreeze()
+
+    def _run(self, requests: Sequence[Request], on_tick: Optional[Callable] = None) -> List[Result]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in reqs:
             if r.m > self.arena.capacity:
@@ -393,10 +405,20 @@ class EngineBackend:
     def step(self, slots):
         self.eng.step(slots)
 
+    def _pinned(self, kind):
+        # pinned host buffers are reused once their read has been consumed (allocating pinned memory
+        # every tick costs more host time than the tick itself)
+        pool = self.pin_poses if kind == "poses" else self.pin_status
+        if pool:
+            return pool.pop()
+        shape, dt = ((self.max_slots, 16), self.torch.float64) if kind == "poses" else \
+            ((self.max_slots, 4), self.torch.int32)
+        return self.torch.empty(shape, dtype=dt, pin_memory=True)
+
     def read(self, poses=True):
         torch = self.torch
-        pp = torch.empty((self.max_slots, 16), dtype=torch.float64, pin_memory=True) if poses else None
-        ps = torch.empty((self.max_slots, 4), dtype=torch.int32, pin_memory=True)
+        pp = self._pinned("poses") if poses else None
+        ps = self._pinned("status")
         self.eng.read(pp, ps)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
@@ -425,11 +447,18 @@ class EngineBackend:
 
     def poses(self, token):
         ev, pp, ps = self.read_ev.pop(token)
-        return pp.numpy().reshape(-1, 4, 4), ps.numpy()
+        out = pp.numpy().reshape(-1, 4, 4).copy(), ps.numpy().copy()
+        self.pin_poses.append(pp)
+        self.pin_status.append(ps)
+        return out
 
     def states(self, token):
-        ev, _, ps = self.read_ev.pop(token)
-        return ps.numpy()
+        ev, pp, ps = self.read_ev.pop(token)
+        out = ps.numpy().copy()
+        self.pin_status.append(ps)
+        if pp is not None:
+            self.pin_poses.append(pp)
+        return out
 
     def close(self):
         self.eng.close()
