@@ -296,18 +296,24 @@ def serve_bench(fr, ctx, args):
     run_plain(fr, ctx, model, obs, np.zeros(nc), prm)
     cap = nc / (time.perf_counter() - t0)
     log(f"plain loop capacity {cap:.1f} registrations/s ({nc} requests back to back)")
-    served, plain = [], []
-    for x in args.serve_lambdas:
-        rate = x * cap
-        arr = poisson_arrivals(n, rate, 11)
-        t0 = time.perf_counter()
-        res, srv = run_served(fr, ctx, model, obs, m, k, arr, args.iters, eprm, budget, args.serve_admit)
-        s = summarize(res)
-        s.update({"lambda_x": x, "lambda_per_s": rate, "ticks": srv.ticks, "max_resident": srv.max_resident,
-                  "wall_s": time.perf_counter() - t0})
-        served.append(s)
-        log(f"served  lambda={x}x ({rate:.0f}/s): {s['registrations_per_s']:.1f} reg/s, p50 "
-            f"{s['latency_ms']['p50']:.1f} ms, p99 {s['latency_ms']['p99']:.1f} ms, resident <= {srv.max_resident}")
+    served, served_graph, plain = [], [], []
+    eprm_graph = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=args.serve_slots,
+                                  arena_points=args.serve_arena, w=0.1, tol=args.serve_tol if stop else 0.0,
+                                  graph=True)
+    run_served(fr, ctx, model, obs, m[:16], k[:16], np.zeros(16), args.iters, eprm_graph, budget, args.serve_admit)
+    for graph, dest, ep in ((False, served, eprm), (True, served_graph, eprm_graph)):
+        for x in args.serve_lambdas:
+            rate = x * cap
+            arr = poisson_arrivals(n, rate, 11)
+            t0 = time.perf_counter()
+            res, srv = run_served(fr, ctx, model, obs, m, k, arr, args.iters, ep, budget, args.serve_admit)
+            s = summarize(res)
+            s.update({"lambda_x": x, "lambda_per_s": rate, "ticks": srv.ticks, "max_resident": srv.max_resident,
+                      "wall_s": time.perf_counter() - t0, "graph": graph})
+            dest.append(s)
+            log(f"served{' graph' if graph else ''} lambda={x}x ({rate:.0f}/s): {s['registrations_per_s']:.1f} "
+                f"reg/s, p50 {s['latency_ms']['p50']:.1f} ms, p99 {s['latency_ms']['p99']:.1f} ms, resident <= "
+                f"{srv.max_resident}")
     for x in args.plain_lambdas:
         rate = x * cap
         arr = poisson_arrivals(n, rate, 11)
@@ -316,8 +322,8 @@ def serve_bench(fr, ctx, args):
         plain.append(s)
         log(f"plain   lambda={x}x ({rate:.0f}/s): {s['registrations_per_s']:.1f} reg/s, p50 "
             f"{s['latency_ms']['p50']:.1f} ms, p99 {s['latency_ms']['p99']:.1f} ms")
-    ok = [s for s in served if s["latency_ms"]["p99"] < 100.0]
-    head = max(ok, key=lambda s: s["lambda_x"]) if ok else None
+    ok = [s for s in served + served_graph if s["latency_ms"]["p99"] < 100.0]
+    head = max(ok, key=lambda s: (s["lambda_x"], s["registrations_per_s"])) if ok else None
     del keep
     return {
         "workload": f"{n} rigid point-to-plane requests, model points log-uniform in [1k, 300k] (sorted random "
@@ -325,14 +331,15 @@ def serve_bench(fr, ctx, args):
                     f"iterations each" + (f", stopped on a twist below {args.serve_tol:g}" if stop else "") +
                     ", Poisson arrivals",
         "requests": n, "model_points": int(m.sum()), "obs_points": int(k.sum()),
-        "plain_capacity_per_s": cap, "served": served, "plain": plain,
+        "plain_capacity_per_s": cap, "served": served, "served_graph": served_graph, "plain": plain,
         "engine": {"max_slots": args.serve_slots, "arena_points": args.serve_arena,
                    "lattice_budget_gib": args.serve_budget_gib, "max_admit": args.serve_admit},
         "headline": None if head is None else {
             "lambda_x": head["lambda_x"], "registrations_per_s": head["registrations_per_s"],
-            "solved_per_s": head["solved_per_s"], "degenerate": head["degenerate"],
+            "solved_per_s": head["solved_per_s"], "degenerate": head["degenerate"], "graph": head["graph"],
             "p50_ms": head["latency_ms"]["p50"], "p99_ms": head["latency_ms"]["p99"],
-            "rule": "largest swept arrival rate whose served p99 latency is under 100 ms"},
+            "rule": "largest swept arrival rate whose served p99 latency is under 100 ms (eager or graph-replayed "
+                    "steps, the higher throughput at that rate)"},
         "degenerate_note": "requests ending FR_EDEGENERATE (singular normal equations, pose kept): the frames' "
                            "rigid motions of up to 10 degrees about the camera leave too little of the model "
                            "within the 3 cm kernel, often only one plane (rank 3); the same count in the served "

@@ -564,7 +564,13 @@ typedef struct {
     int64_t arena_points;       /* model points resident at once (>= 1) */
     double w;                   /* outlier ratio of Eq. 4; c per request as in fr_register_params */
     double c_override;          /* >= 0: this c for every request; < 0: derive from w */
-    int32_t flags;              /* FR_FUSED: as fr_register with FR_FUSED */
+    int32_t flags;              /* FR_FUSED: as fr_register with FR_FUSED;
+                                   FR_GRAPH: the first step captures, for each of the engine's pinned plan
+                                   buffers, one HIP graph -- the plan's copy to the device, a persistent
+                                   E-step and reduction (a fixed grid that walks the plan's tiles, their
+                                   count read on the device), the final sums and the solve -- and every step
+                                   then fills a plan buffer and replays its graph, whatever the resident
+                                   set; same results bitwise (not with FR_FUSED) */
     int32_t reserved;           /* must be 0 */
     double twist_tol;           /* > 0: a slot stops (its later steps do nothing) after a step whose
                                    |omega| and |v| are both below it (Sec. 6.1); <= 0: only a degenerate

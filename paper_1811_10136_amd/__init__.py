@@ -762,12 +762,14 @@ def fr_engine_release(eng, slots):
 
 
 def engine_params(feat: int, residual: str, sigma, sigma_n=0.5, max_slots=256, arena_points=1 << 24, w=0.1,
-                  c=None, splat: int = FR_SPLAT_SORTED, fused=False, tol=0.0) -> fr_engine_params:
-    """tol > 0: a slot stops on the device after a step with |omega| and |v| below it."""
+                  c=None, splat: int = FR_SPLAT_SORTED, fused=False, tol=0.0, graph=False) -> fr_engine_params:
+    """tol > 0: a slot stops on the device after a step with |omega| and |v| below it; graph: every step
+    replays a captured HIP graph (FR_GRAPH)."""
     values = FR_VAL_PT2PL if residual == "pt2pl" else FR_VAL_PT2PT
+    flags = (FR_FUSED if fused else 0) | (FR_GRAPH if graph else 0)
     return fr_engine_params(lattice_params(feat, values, sigma, sigma_n, splat),
                             FR_PT2PL if residual == "pt2pl" else FR_PT2PT, int(max_slots), int(arena_points),
-                            float(w), -1.0 if c is None else float(c), FR_FUSED if fused else 0, 0, float(tol))
+                            float(w), -1.0 if c is None else float(c), flags, 0, float(tol))
 
 
 class Engine:

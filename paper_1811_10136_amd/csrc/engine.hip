@@ -102,6 +102,11 @@ struct fr_engine {
     int ring = 0;
     hipEvent_t admit_ev = nullptr;
     std::vector<hipEvent_t> pending;  // admissions the engine stream has not waited for yet
+    // FR_GRAPH: the kernels of a step captured once per plan ring entry and replayed
+    bool graph = false;
+    bool captured = false;
+    hipGraphExec_t gexec[kEngRing] = {};
+    int32_t graph_slice = FR_SLICE_PLAIN;
     struct Slot {
         int32_t used = 0;
         int64_t begin = 0, m = 0;
@@ -144,6 +149,8 @@ static void engine_free(fr_engine *e)
     if (e->admit_ev) (void)hipEventDestroy(e->admit_ev);
     for (hipEvent_t ev : e->pending) (void)hipEventDestroy(ev);
     e->pending.clear();
+    for (hipGraphExec_t &g : e->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (e->pin) (void)hipHostFree(e->pin);
     if (e->bst) (void)hipStreamDestroy(e->bst);
     e->pin = nullptr;
@@ -180,8 +187,9 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
         set_error("fr_engine_create: 0 <= w < 1 required");
         return FR_EINVAL;
     }
-    if ((p.flags & ~FR_FUSED) != 0 || p.reserved != 0) {
-        set_error("fr_engine_create: flags may only hold FR_FUSED and reserved must be 0");
+    if ((p.flags & ~(FR_FUSED | FR_GRAPH)) != 0 || p.reserved != 0 ||
+        ((p.flags & FR_FUSED) && (p.flags & FR_GRAPH))) {
+        set_error("fr_engine_create: flags may hold FR_FUSED or FR_GRAPH (not both) and reserved must be 0");
         return FR_EINVAL;
     }
     FR_HIP(hipSetDevice(ctx->device));
@@ -194,6 +202,7 @@ fr_status fr_engine_create(fr_ctx *ctx, const fr_engine_params *params, void *st
     }
     e->ctx = ctx;
     e->prm = p;
+    e->graph = (p.flags & FR_GRAPH) != 0;
     e->d = p.lattice.feat;
     e->V = p.lattice.values;
     e->S = p.max_slots;
@@ -435,6 +444,10 @@ static fr_status join_pending(fr_engine *e)
     return FR_OK;
 }
 
+static fr_status enqueue_step_kernels(fr_engine *e, int32_t e_tiles, int32_t r_tiles, int persist_e, int persist_r,
+                                      hipStream_t st);
+static fr_status capture_steps(fr_engine *e);
+
 fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
 {
     clear_error();
@@ -478,9 +491,25 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         cs[s] = sl.c;
     }
     for (int32_t j = 0; j < n; ++j) e->mark[slots_h[j]] = 0;
+    if (e->graph) {
+        if (!e->captured) FR_TRY(capture_steps(e));
+        // the graph copies this ring entry's plan image to the device, then runs the step's kernels
+        FR_HIP(hipGraphLaunch(e->gexec[r], e->st));
+        FR_HIP(hipEventRecord(e->ring_ev[r], e->st));
+        return FR_OK;
+    }
     FR_HIP(hipMemcpyAsync(e->plan_d.p, img, e->plan_bytes, hipMemcpyHostToDevice, e->st));
     FR_HIP(hipEventRecord(e->ring_ev[r], e->st));
+    return enqueue_step_kernels(e, te[S], tr[S], 0, 0, e->st);
+}
 
+// The kernels of one step on `st`, reading the plan at plan_d: with
+// persist_e > 0 the persistent E-step and reduction on persist_e / persist_r
+// workgroups, their tile counts read from the plan on the device.
+static fr_status enqueue_step_kernels(fr_engine *e, int32_t e_tiles, int32_t r_tiles, int persist_e, int persist_r,
+                                      hipStream_t st)
+{
+    const int32_t S = e->S;
     const char *pd = e->plan_d.as<char>();
     const int64_t *d_off = reinterpret_cast<const int64_t *>(pd);
     const int64_t *d_end = d_off + S;
@@ -514,24 +543,76 @@ fr_status fr_engine_step(fr_engine *e, int32_t n, const int32_t *slots_h)
         p.tune_new_classes = false;   // the resident set changes size every step: reuse the nearest tuned class
     };
     Plan pe, pr;
-    make(d_te, te[S], kEstepTile, pe);
-    make(d_tr, tr[S], 1024, pr);
+    make(d_te, e_tiles, kEstepTile, pe);
+    make(d_tr, r_tiles, 1024, pr);
+    if (persist_e > 0) {
+        pe.persist_grid = persist_e;
+        pe.slice = e->graph_slice;
+        pr.persist_grid = persist_r;
+    }
     fr_cloud arena{e->x, e->y, e->z, e->nx, e->ny, e->nz, e->offsets_h, 1};
     // slots that have stopped on the device (twist below tolerance, or degenerate) are skipped by
     // every kernel: a step that still lists them leaves them unchanged
     if (e->fused) {
         FR_TRY(launch_estep_fused(e->d, e->V, e->tables, e->err, 1, &arena, pe, e->mats, e->prm.residual, 0,
-                                  e->partials.as<float>(), e->st, e->run));
-        FR_TRY(launch_reduce_final(pe, e->partials.as<float>(), e->sig_m, e->jtj, e->jtr, e->stats, e->st));
+                                  e->partials.as<float>(), st, e->run));
+        FR_TRY(launch_reduce_final(pe, e->partials.as<float>(), e->sig_m, e->jtj, e->jtr, e->stats, st));
     } else {
         FR_TRY(launch_estep_sets(e->d, e->V, e->tables, e->err, 1, &arena, e->P, pe, FR_XF_RIGID, e->mats,
-                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, nullptr, e->st, e->run));
+                                 e->m0, e->m1, e->V == 7 ? e->ns : nullptr, nullptr, nullptr, st, e->run));
         FR_TRY(launch_reduce(&arena, pr, FR_XF_RIGID, e->mats, e->m0, e->m1,
                              e->prm.residual == FR_PT2PL ? e->ns : nullptr, e->prm.residual, 0, e->sig_m, e->jtj,
-                             e->jtr, e->stats, e->partials.as<float>(), e->st, nullptr, nullptr, e->run));
+                             e->jtr, e->stats, e->partials.as<float>(), st, nullptr, nullptr, e->run));
     }
-    FR_TRY(launch_solve_rigid(S, e->jtj, e->jtr, e->poses, e->mats, e->twist, e->status, d_act, e->st, e->run,
+    FR_TRY(launch_solve_rigid(S, e->jtj, e->jtr, e->poses, e->mats, e->twist, e->status, d_act, st, e->run,
                               e->tol, e->iters));
+    return FR_OK;
+}
+
+// FR_GRAPH: one graph per plan ring entry -- the copy of that entry's pinned
+// plan image to the device, the persistent E-step and reduction, the final
+// sums and the solve -- captured on a stream of its own and instantiated
+// once.  Launch shapes do not depend on the plan, so every later step only
+// fills the ring entry and replays its graph.  The slice form is the one the
+// autotuner's table gives for the largest resident set (no timing).
+static fr_status capture_steps(fr_engine *e)
+{
+    const int pe = estep_persistent_grid(e->d, e->V, FR_SLICE_PLAIN);
+    e->graph_slice = tuned_slice_nearest(e->ctx, e->d, e->V, FR_XF_RIGID, e->P);
+    const int pes = e->graph_slice == FR_SLICE_SHARED ? estep_persistent_grid(e->d, e->V, FR_SLICE_SHARED) : pe;
+    const int pr = reduce_persistent_grid(e->prm.residual);
+    if (pes <= 0 || pr <= 0) {
+        set_error("fr_engine_step: no persistent launch shape for d=%d V=%d", e->d, e->V);
+        return FR_EINVAL;
+    }
+    hipStream_t cs = nullptr;
+    FR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    fr_status rc = FR_OK;
+    for (int r = 0; r < kEngRing && rc == FR_OK; ++r) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = FR_EDEVICE;
+            break;
+        }
+        hipError_t he = hipMemcpyAsync(e->plan_d.p, e->pin + (size_t)r * e->plan_bytes, e->plan_bytes,
+                                       hipMemcpyHostToDevice, cs);
+        fr_status ks = he == hipSuccess ? enqueue_step_kernels(e, 0, 0, pes, pr, cs) : FR_EDEVICE;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (ks != FR_OK || ee != hipSuccess || g == nullptr) {
+            rc = ks != FR_OK ? ks : FR_EDEVICE;
+        } else if (hipGraphInstantiate(&e->gexec[r], g, nullptr, nullptr, 0) != hipSuccess) {
+            rc = FR_EDEVICE;
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != FR_OK) {
+        for (hipGraphExec_t &x : e->gexec)
+            if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+        if (rc == FR_EDEVICE) set_error("fr_engine_step: capturing the step graph failed");
+        return rc;
+    }
+    e->captured = true;
     return FR_OK;
 }
 

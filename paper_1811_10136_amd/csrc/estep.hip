@@ -9,6 +9,7 @@
 // arrays, coalesced, non-temporal so they do not evict the table from L2);
 // the table of the set being sliced is read through L2, and the logical tile
 // order keeps one set's tiles on one XCD.
+#include <algorithm>
 #include <cstdlib>
 
 #include "fr_internal.h"
@@ -84,10 +85,8 @@ __device__ __forceinline__ void slice_point(const EstepArgs &a, int32_t s, int64
 }
 
 template <int d, int V, bool XF>
-__global__ void __launch_bounds__(256) k_estep(EstepArgs a)
+__device__ __forceinline__ void estep_tile(const EstepArgs &a, int32_t t)
 {
-    const int32_t t = logical_tile(a.tm);
-    if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
     const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
@@ -108,6 +107,18 @@ __global__ void __launch_bounds__(256) k_estep(EstepArgs a)
     }
     if constexpr (ValLayout<V>::m2) {
         if (a.m2 != nullptr) st_stream(a.m2 + i, acc[V - 1]);
+    }
+}
+
+template <int d, int V, bool XF, bool PERSIST>
+__global__ void __launch_bounds__(256) k_estep(EstepArgs a)
+{
+    if constexpr (PERSIST) {
+        for_each_tile_persistent(a.tm, [&](int32_t t) { estep_tile<d, V, XF>(a, t); });
+    } else {
+        const int32_t t = logical_tile(a.tm);
+        if (t >= a.tm.n_tiles) return;
+        estep_tile<d, V, XF>(a, t);
     }
 }
 
@@ -265,14 +276,11 @@ __device__ __forceinline__ void slice_wave_dedup(const SetTable &st, const uint6
 }
 
 template <int d, int V, bool XF>
-__global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
+__device__ __forceinline__ void estep_dedup_tile(const EstepArgs &a, int32_t t, char *lds)
 {
     using G = DedupGeom<d, V>;
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    __shared__ __attribute__((aligned(16))) char lds[4 * G::wave_bytes];
-    const int32_t t = logical_tile(a.tm);
-    if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
     const int64_t i0 = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
@@ -313,7 +321,7 @@ __global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
     const bool ok = embed<d>(p, kk, keys, b, &sdiv);
     if (live && !ok) atomicOr(a.err + a.err_stride * s, 1);
     float acc[V];
-    slice_wave_dedup<d, V>(st, keys, b, sdiv, live, lds + (threadIdx.x >> 6) * G::wave_bytes, acc);
+    slice_wave_dedup<d, V>(st, keys, b, sdiv, live, lds, acc);
     if (!live) return;
     st_stream(a.m0 + i, acc[0]);
     st_stream(a.m1 + i, acc[1]);
@@ -328,6 +336,24 @@ __global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
     }
     if constexpr (ValLayout<V>::m2) {
         if (a.m2 != nullptr) st_stream(a.m2 + i, acc[V - 1]);
+    }
+}
+
+template <int d, int V, bool XF, bool PERSIST>
+__global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
+{
+    using G = DedupGeom<d, V>;
+    __shared__ __attribute__((aligned(16))) char lds[4 * G::wave_bytes];
+    char *wl = lds + (threadIdx.x >> 6) * G::wave_bytes;
+    if constexpr (PERSIST) {
+        for_each_tile_persistent(a.tm, [&](int32_t t) {
+            wave_sync();   // the wave's LDS reads of the previous tile are done before it is written again
+            estep_dedup_tile<d, V, XF>(a, t, wl);
+        });
+    } else {
+        const int32_t t = logical_tile(a.tm);
+        if (t >= a.tm.n_tiles) return;
+        estep_dedup_tile<d, V, XF>(a, t, wl);
     }
 }
 
@@ -404,19 +430,27 @@ __global__ void __launch_bounds__(256) k_estep_touch(EstepArgs a)
     }
 }
 
-template <int d, int V>
-static void launch_dv(const EstepArgs &a, bool xf, bool touch, int slice, int grid, hipStream_t st)
+template <int d, int V, bool P>
+static void launch_dvp(const EstepArgs &a, bool xf, bool touch, int slice, int grid, hipStream_t st)
 {
     if (touch) {
         if (xf) k_estep_touch<d, V, true><<<grid, 256, 0, st>>>(a);
         else k_estep_touch<d, V, false><<<grid, 256, 0, st>>>(a);
     } else if (slice == FR_SLICE_SHARED) {
-        if (xf) k_estep_dedup<d, V, true><<<grid, 256, 0, st>>>(a);
-        else k_estep_dedup<d, V, false><<<grid, 256, 0, st>>>(a);
+        if (xf) k_estep_dedup<d, V, true, P><<<grid, 256, 0, st>>>(a);
+        else k_estep_dedup<d, V, false, P><<<grid, 256, 0, st>>>(a);
     } else {
-        if (xf) k_estep<d, V, true><<<grid, 256, 0, st>>>(a);
-        else k_estep<d, V, false><<<grid, 256, 0, st>>>(a);
+        if (xf) k_estep<d, V, true, P><<<grid, 256, 0, st>>>(a);
+        else k_estep<d, V, false, P><<<grid, 256, 0, st>>>(a);
     }
+}
+
+// persist_grid > 0: the persistent kernels on that many workgroups (tile count from the device)
+template <int d, int V>
+static void launch_dv(const EstepArgs &a, bool xf, bool touch, int slice, int grid, int persist_grid, hipStream_t st)
+{
+    if (persist_grid > 0 && !touch) launch_dvp<d, V, true>(a, xf, false, slice, persist_grid, st);
+    else launch_dvp<d, V, false>(a, xf, touch, slice, grid, st);
 }
 
 // The slice autotuner: the first launch of each (d, V, transform kind, size
@@ -484,12 +518,26 @@ static fr_status autotune_slice(fr_ctx *ctx, int d, int V, int xf_kind, int64_t 
     return FR_OK;
 }
 
+int tuned_slice_nearest(const fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts)
+{
+    if (ctx == nullptr) return FR_SLICE_PLAIN;
+    if (ctx->slice_mode != FR_SLICE_AUTO) return ctx->slice_mode;
+    int32_t cls = 0;
+    while (cls < 62 && (2ll << cls) <= pts) ++cls;
+    const fr_tuning_entry *near = nullptr;
+    for (const fr_tuning_entry &e : ctx->tuned)
+        if (e.d == d && e.V == V && e.xf_kind == xf_kind &&
+            (near == nullptr || std::abs(e.size_class - cls) < std::abs(near->size_class - cls)))
+            near = &e;
+    return near != nullptr ? near->slice : FR_SLICE_PLAIN;
+}
+
 fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
                             const fr_cloud *model, int64_t M, const Plan &plan, int xf_kind, const float *mats,
                             float *m0, float *m1, float *nsum, float *m2, uint32_t *touched, hipStream_t st,
                             const int32_t *active)
 {
-    if (plan.grid == 0) return FR_OK;
+    if (plan.grid == 0 && plan.persist_grid == 0) return FR_OK;
     EstepArgs a{};
     a.active = active;
     a.x = model->x;
@@ -512,14 +560,14 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
     const bool xf = xf_kind != FR_XF_NONE;
     const bool touch = touched != nullptr;
     auto launch = [&](int slice) -> fr_status {
-        if (d == 3 && V == 4) launch_dv<3, 4>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 3 && V == 5) launch_dv<3, 5>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 3 && V == 8) launch_dv<3, 8>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 6 && V == 5) launch_dv<6, 5>(a, xf, touch, slice, plan.grid, st);
-        else if (d == 6 && V == 8) launch_dv<6, 8>(a, xf, touch, slice, plan.grid, st);
+        if (d == 3 && V == 4) launch_dv<3, 4>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 3 && V == 7) launch_dv<3, 7>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 6 && V == 4) launch_dv<6, 4>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 6 && V == 7) launch_dv<6, 7>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 3 && V == 5) launch_dv<3, 5>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 3 && V == 8) launch_dv<3, 8>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 6 && V == 5) launch_dv<6, 5>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
+        else if (d == 6 && V == 8) launch_dv<6, 8>(a, xf, touch, slice, plan.grid, plan.persist_grid, st);
         else {
             set_error("fr_estep: unsupported lattice d=%d V=%d", d, V);
             return FR_EINVAL;
@@ -532,6 +580,30 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
         FR_TRY(autotune_slice(plan.ctx, d, V, xf_kind, (int64_t)plan.n_tiles * plan.tile, plan.tune_new_classes, st,
                               launch, slice));
     return launch(slice);
+}
+
+// Workgroups of a persistent E-step launch: what the device holds at once
+// (occupancy per CU times the CUs), a multiple of 8.
+template <int d, int V>
+static int persistent_grid_dv(int slice)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    const void *f = slice == FR_SLICE_SHARED ? reinterpret_cast<const void *>(k_estep_dedup<d, V, true, true>)
+                                             : reinterpret_cast<const void *>(k_estep<d, V, true, true>);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0);
+    (void)hipGetLastError();
+    return std::max(8, per_cu * cus / 8 * 8);
+}
+
+int estep_persistent_grid(int d, int V, int slice)
+{
+    if (d == 3 && V == 4) return persistent_grid_dv<3, 4>(slice);
+    if (d == 3 && V == 7) return persistent_grid_dv<3, 7>(slice);
+    if (d == 6 && V == 4) return persistent_grid_dv<6, 4>(slice);
+    if (d == 6 && V == 7) return persistent_grid_dv<6, 7>(slice);
+    return 0;
 }
 
 template <int d, int V>

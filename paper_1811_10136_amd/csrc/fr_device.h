@@ -97,6 +97,23 @@ __device__ __forceinline__ int32_t logical_tile(const TileMap &tm)
     return (b & 7) * tm.xcd_chunk + (b >> 3);
 }
 
+// Persistent launches (a fixed grid, a multiple of 8 workgroups): the tile
+// count comes from the device (seg_tile[n_seg]), XCD x = block % 8 takes the
+// x-th of 8 contiguous runs of tiles, and its workgroups walk that run with a
+// stride of grid / 8 -- the same XCD-contiguous order as logical_tile, for a
+// grid that does not depend on the plan (a captured graph replays it for any
+// set of resident requests).
+template <class Body>
+__device__ __forceinline__ void for_each_tile_persistent(const TileMap &tm, Body &&body)
+{
+    const int32_t n = tm.seg_tile[tm.n_seg];
+    const int32_t chunk = (n + 7) / 8;
+    const int32_t x = (int32_t)(blockIdx.x & 7u);
+    const int32_t hi = min((x + 1) * chunk, n);
+    const int32_t stride = (int32_t)(gridDim.x >> 3);
+    for (int32_t t = x * chunk + (int32_t)(blockIdx.x >> 3); t < hi; t += stride) body(t);
+}
+
 // Segment of a logical tile: last s with seg_tile[s] <= t (uniform per block).
 __device__ __forceinline__ int32_t tile_segment(const TileMap &tm, int32_t t)
 {

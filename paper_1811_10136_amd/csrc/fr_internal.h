@@ -190,6 +190,9 @@ struct Plan {
     // false: an untuned size class takes the choice of the nearest tuned class of the same (d, V,
     // transform) instead of timing (the serving engine, whose launches change size every step)
     bool tune_new_classes = true;
+    // > 0: launch the persistent E-step / reduction kernels on this many workgroups (a multiple of
+    // 8), reading the tile count from the device plan (graph replay with any resident set)
+    int32_t persist_grid = 0;
 };
 
 // Build a plan for `model_ref` segmented per `xf` (NULL = per set).
@@ -237,6 +240,12 @@ fr_status launch_estep_sets(int d, int V, const SetTable *sets, int32_t *err, in
 fr_status launch_estep(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats,
                        float *m0, float *m1, float *nsum, uint32_t *touched, hipStream_t st, float *m2 = nullptr,
                        const int32_t *active = nullptr);
+// Persistent launches (graph replay): workgroups the device holds at once,
+// a multiple of 8; the slice form the autotuner's table gives without timing
+// (nearest tuned size class, else FR_SLICE_PLAIN).
+int estep_persistent_grid(int d, int V, int slice);
+int reduce_persistent_grid(int residual);
+int tuned_slice_nearest(const fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts);
 // Descriptor E-step (Eq. 8): slice lat at feat (device, M x lat->d) -> m0, m1.
 fr_status launch_estep_features(const fr_lattice *lat, const fr_cloud *model, const Plan &plan, const float *feat,
                                 float *m0, float *m1, hipStream_t st);

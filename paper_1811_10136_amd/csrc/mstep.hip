@@ -27,11 +27,8 @@ struct ReduceArgs {
 };
 
 template <int RES, bool XF, bool M2>
-__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
+__device__ __forceinline__ void reduce_tile(const ReduceArgs &a, int32_t t, float (&part)[kRedThreads / 64][kRedStride])
 {
-    __shared__ float part[kRedThreads / 64][kRedStride];
-    const int32_t t = logical_tile(a.tm);
-    if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;   // no partial row: the set is not solved
     const int64_t start = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
@@ -71,6 +68,22 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
                              M2 ? __builtin_nontemporal_load(a.m2 + i) : 0.0f);
     }
     block_partials(acc, part, a.partials + (size_t)t * kRedStride);
+}
+
+template <int RES, bool XF, bool M2, bool PERSIST>
+__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
+{
+    __shared__ float part[kRedThreads / 64][kRedStride];
+    if constexpr (PERSIST) {
+        for_each_tile_persistent(a.tm, [&](int32_t t) {
+            __syncthreads();   // the previous tile's partial row has been read out of LDS
+            reduce_tile<RES, XF, M2>(a, t, part);
+        });
+    } else {
+        const int32_t t = logical_tile(a.tm);
+        if (t >= a.tm.n_tiles) return;
+        reduce_tile<RES, XF, M2>(a, t, part);
+    }
 }
 
 // One block per segment: 8 lanes per value each sum every 8th tile in binary64,
@@ -115,10 +128,28 @@ fr_status launch_reduce_final(const Plan &plan, const float *partials, double si
 }
 
 template <int RES, bool M2>
-static void launch_reduce_rm(const ReduceArgs &a, bool xf, int grid, hipStream_t st)
+static void launch_reduce_rm(const ReduceArgs &a, bool xf, int grid, int persist_grid, hipStream_t st)
 {
-    if (xf) k_reduce<RES, true, M2><<<grid, kRedThreads, 0, st>>>(a);
-    else k_reduce<RES, false, M2><<<grid, kRedThreads, 0, st>>>(a);
+    if (persist_grid > 0) {
+        if (xf) k_reduce<RES, true, M2, true><<<persist_grid, kRedThreads, 0, st>>>(a);
+        else k_reduce<RES, false, M2, true><<<persist_grid, kRedThreads, 0, st>>>(a);
+    } else {
+        if (xf) k_reduce<RES, true, M2, false><<<grid, kRedThreads, 0, st>>>(a);
+        else k_reduce<RES, false, M2, false><<<grid, kRedThreads, 0, st>>>(a);
+    }
+}
+
+int reduce_persistent_grid(int residual)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    const void *f = residual == FR_PT2PL ? reinterpret_cast<const void *>(k_reduce<FR_PT2PL, true, false, true>)
+                                         : reinterpret_cast<const void *>(k_reduce<FR_PT2PT, true, false, true>);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kRedThreads, 0);
+    (void)hipGetLastError();
+    const int g = per_cu * cus / 8 * 8;
+    return g > 8 ? g : 8;
 }
 
 fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, const float *mats, const float *m0,
@@ -143,13 +174,14 @@ fr_status launch_reduce(const fr_cloud *model, const Plan &plan, int xf_kind, co
     a.partials = partials;
     a.normalize_n = normalize_n;
     const bool xf = xf_kind != FR_XF_NONE;
-    if (plan.grid > 0) {
+    if (plan.grid > 0 || plan.persist_grid > 0) {
+        const int pg = plan.persist_grid;
         if (residual == FR_PT2PT) {
-            if (m2) launch_reduce_rm<FR_PT2PT, true>(a, xf, plan.grid, st);
-            else launch_reduce_rm<FR_PT2PT, false>(a, xf, plan.grid, st);
+            if (m2) launch_reduce_rm<FR_PT2PT, true>(a, xf, plan.grid, pg, st);
+            else launch_reduce_rm<FR_PT2PT, false>(a, xf, plan.grid, pg, st);
         } else {
-            if (m2) launch_reduce_rm<FR_PT2PL, true>(a, xf, plan.grid, st);
-            else launch_reduce_rm<FR_PT2PL, false>(a, xf, plan.grid, st);
+            if (m2) launch_reduce_rm<FR_PT2PL, true>(a, xf, plan.grid, pg, st);
+            else launch_reduce_rm<FR_PT2PL, false>(a, xf, plan.grid, pg, st);
         }
         FR_HIP(hipGetLastError());
     }

@@ -45,9 +45,9 @@ def _alone(fr, ctx, p, iters=ITERS, fused=False):
     return T[0], int(st[0])
 
 
-def _engine(fr, ctx, p0, slots=4, arena=150_000, fused=False, tol=0.0):
+def _engine(fr, ctx, p0, slots=4, arena=150_000, fused=False, tol=0.0, graph=False):
     prm = fr.engine_params(6, "pt2pl", p0.sigma, p0.sigma_n, max_slots=slots, arena_points=arena, w=p0.w,
-                           fused=fused, tol=tol)
+                           fused=fused, tol=tol, graph=graph)
     return fr.Engine(ctx, prm)
 
 
@@ -61,13 +61,15 @@ def _read(eng, S, with_state=False):
     return poses.numpy().reshape(S, 4, 4).copy(), state.numpy()[:, 0].copy()
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_engine_mix_is_bitwise_the_pair_alone(fr, ctx, pairs, fused):
+@pytest.mark.parametrize("mode", ["eager", "fused", "graph"])
+def test_engine_mix_is_bitwise_the_pair_alone(fr, ctx, pairs, mode):
     """Requests join and leave at different ticks, reuse slots and arena ranges, and share every
-    launch with different neighbours; each ends bitwise where fr_register leaves it alone."""
-    print(f"[serve] mix fused={fused}", flush=True)
+    launch with different neighbours; each ends bitwise where fr_register leaves it alone (graph: every
+    step replays a captured graph, admissions and reads in between)."""
+    fused = mode == "fused"
+    print(f"[serve] mix {mode}", flush=True)
     alone = [_alone(fr, ctx, p, fused=fused) for p in pairs]
-    eng = _engine(fr, ctx, pairs[0], fused=fused)
+    eng = _engine(fr, ctx, pairs[0], fused=fused, graph=mode == "graph")
     S = eng.max_slots
     # schedule: (tick, requests admitted at that tick into (slot, arena begin))
     admissions = {0: [(0, 0, 0), (1, 1, 10_000)], 2: [(2, 2, 65_000), (3, 3, 70_000)],
@@ -239,3 +241,33 @@ def test_server_with_device_stops_matches_alone_runs(fr, ctx, pairs):
         T, st, it = alone[k]
         assert r.status == st and r.iterations == it, (r.rid, r.status, r.iterations, st, it)
         np.testing.assert_array_equal(r.pose, T, err_msg=f"request {r.rid}")
+
+
+def test_graph_replays_equal_the_eager_steps_every_tick(fr, ctx, pairs):
+    """Two engines run the same schedule, one replaying captured graphs: after every step the poses, the
+    statuses, the iteration counts and the stop flags of both agree bitwise (the resident set changes
+    between replays: admissions, a stop on the twist, releases)."""
+    engs = [_engine(fr, ctx, pairs[0], slots=4, tol=1e-6), _engine(fr, ctx, pairs[0], slots=4, tol=1e-6,
+                                                                   graph=True)]
+    plan = {0: [(0, 0, 0), (5, 1, 10_000)], 1: [(2, 2, 60_000)], 4: [(3, 3, 90_000)]}
+    keep = []
+    resident = set()
+    for tick in range(12):
+        for rid, slot, begin in plan.get(tick, []):
+            p = pairs[rid]
+            keep.append((upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n])))
+            for eng in engs:
+                eng.admit([slot], keep[-1][0], keep[-1][1], [begin], _T0(p)[None])
+            resident.add(slot)
+        if tick == 8:
+            for eng in engs:
+                eng.release([1])
+            resident.discard(1)
+        for eng in engs:
+            eng.step(sorted(resident))
+        (pa, sa), (pb, sb) = (_read(e, e.max_slots, with_state=True) for e in engs)
+        for s in resident:
+            np.testing.assert_array_equal(pa[s], pb[s], err_msg=f"tick {tick} slot {s}")
+            np.testing.assert_array_equal(sa[s], sb[s], err_msg=f"tick {tick} slot {s}")
+    for eng in engs:
+        eng.close()
