@@ -149,6 +149,30 @@ fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_pa
                            fr_lattice **out);
 fr_status fr_lattice_destroy(fr_lattice *lat);
 
+/*
+ * A lattice rebuilt in place (for loops that rebuild it every iteration, as
+ * the optimised variance of Sec. 3.3 does; Sec. 3.1 notes that the index is
+ * built once only while the variance is fixed).  fr_lattice_build_inplace
+ * sizes every array once from `obs` with bounds that hold at any scale -- a
+ * set of n points has at most (feat+1) n incidences, partial records and
+ * vertices -- and builds the lattice at the scales of `params`, with the
+ * position scale of set s replaced by sigma_set_h[s] (host, n_sets float64,
+ * or NULL).  Synchronises; returns FR_EDEVICE if a table overflowed (not
+ * seen at these bounds, not ruled out).  fr_lattice_rebuild rebuilds it from
+ * the same `obs` (its device arrays must stay valid and unchanged) at new
+ * per-set position scales (sigma_set_h as above, required): it only enqueues
+ * kernels on `stream` -- no allocation, no host wait -- and its tables are
+ * those fr_lattice_build would make at the same scales (the same slices,
+ * bitwise with FR_SPLAT_SORTED).  A failed rebuild leaves the lattice invalid
+ * and is reported by fr_sync_status (FR_EDEVICE) until a rebuild succeeds.
+ * Memory: tables for (feat+1) vertices per observation point, several times
+ * what fr_lattice_build allocates.  fr_lattice_stats and fr_lattice_export
+ * are not available on such a lattice (FR_EINVAL); fr_lattice_destroy frees it.
+ */
+fr_status fr_lattice_build_inplace(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
+                                   const double *sigma_set_h, void *stream, fr_lattice **out);
+fr_status fr_lattice_rebuild(fr_lattice *lat, const double *sigma_set_h, void *stream);
+
 /* Vertex count, hash capacity (slots) and device bytes of set `set`; synchronises. */
 fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertices, int64_t *capacity,
                            int64_t *device_bytes);
@@ -406,8 +430,12 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
  * valid); FR_FUSED is rejected.  sigma_inout_h (host, n_sets float64, > 0)
  * holds the start scales and receives the scale each set would use next.
  * theta_inout_h, status_h, report_h and the return value as fr_register
- * (report_h->build_ms sums the rebuilds, em_ms excludes them).  Synchronises
- * every iteration.
+ * (with FR_PROFILE_EVENTS report_h->build_ms sums the rebuilds' device time
+ * and em_ms excludes it; without, build_ms is 0).  The lattice is rebuilt in
+ * place in storage sized once from `obs`, and the scale update, lattice scale
+ * factors and outlier constants stay on the device, so the host waits once
+ * every 4 iterations; a rebuild whose tables overflow is caught there and its
+ * 4 iterations are run again with a build sized on the host.
  */
 fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *obs,
                             const fr_register_params *params, double sigma_min, double *theta_inout_h,

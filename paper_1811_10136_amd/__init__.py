@@ -149,6 +149,9 @@ _sig("fr_lattice_build", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_l
 _sig("fr_lattice_build_joint", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_xform),
                                      ctypes.POINTER(fr_lattice_params), _P, ctypes.POINTER(_P)])
 _sig("fr_lattice_blur", _st, [_P, _P])
+_sig("fr_lattice_build_inplace", _st, [_P, ctypes.POINTER(fr_cloud), ctypes.POINTER(fr_lattice_params), _P, _P,
+                                       ctypes.POINTER(_P)])
+_sig("fr_lattice_rebuild", _st, [_P, _P, _P])
 _sig("fr_lattice_build_features", _st, [_P, ctypes.POINTER(fr_cloud), _P, _i32, ctypes.c_double, _i32, _P,
                                         ctypes.POINTER(_P)])
 _sig("fr_estep_features", _st, [_P, ctypes.POINTER(fr_cloud), _P, _P, _P, _P])
@@ -197,6 +200,7 @@ _sig("fr_engine_release", _st, [_P, _i32, _P])
 ABI_FUNCTIONS = ["fr_version", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_ctx_usage",
                  "fr_ctx_set_tuning", "fr_ctx_tuning_table",
                  "fr_lattice_build", "fr_lattice_build_joint", "fr_lattice_blur", "fr_lattice_destroy",
+                 "fr_lattice_build_inplace", "fr_lattice_rebuild",
                  "fr_lattice_build_features", "fr_estep_features", "fr_register_features",
                  "fr_lattice_stats", "fr_lattice_export", "fr_lattice_records", "fr_lattice_build_times", "fr_probe_atomics", "fr_probe_lines", "fr_estep", "fr_estep_m2", "fr_estep_touched", "fr_mstep_reduce", "fr_mstep_reduce_noalloc", "fr_solve_rigid", "fr_register",
                  "fr_register_sigma", "fr_sync_status",
@@ -344,6 +348,25 @@ def fr_lattice_build_joint(ctx, obs: Cloud, model: Cloud, xf: "XForm", params: f
 
 def fr_lattice_blur(lat, stream=None):
     _check(_lib.fr_lattice_blur(lat, _stream(stream)))
+
+
+def _sigmas(sigma_set):
+    if sigma_set is None:
+        return None, None
+    a = np.ascontiguousarray(sigma_set, np.float64)
+    return a, a.ctypes.data
+
+
+def fr_lattice_build_inplace(ctx, obs: Cloud, params: fr_lattice_params, sigma_set=None, stream=None):
+    h = _P()
+    keep, ptr = _sigmas(sigma_set)
+    _check(_lib.fr_lattice_build_inplace(ctx, obs.c(), ctypes.byref(params), ptr, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def fr_lattice_rebuild(lat, sigma_set, stream=None):
+    keep, ptr = _sigmas(sigma_set)
+    _check(_lib.fr_lattice_rebuild(lat, ptr, _stream(stream)))
 
 
 def fr_lattice_build_features(ctx, obs: Cloud, obs_feat, dim: int, sigma_f: float, splat: int = 0, stream=None):

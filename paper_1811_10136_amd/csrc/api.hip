@@ -650,6 +650,75 @@ fr_status fr_lattice_build(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_pa
     return lattice_build_impl(ctx, obs, params, static_cast<hipStream_t>(stream), out);
 }
 
+// Per-set scale factors of `p` with set s's position scale sigma_set_h[s] (or p's).
+static void set_scale_factors(const fr_lattice_params &p, int32_t n_sets, const double *sigma_set_h, float *k)
+{
+    for (int32_t s = 0; s < n_sets; ++s) {
+        fr_lattice_params ps = p;
+        if (sigma_set_h != nullptr) ps.sigma[0] = ps.sigma[1] = ps.sigma[2] = sigma_set_h[s];
+        scale_factors(&ps, k + 8 * (size_t)s);
+    }
+}
+
+static fr_status check_set_sigmas(const double *sigma_set_h, int32_t n_sets, const char *what)
+{
+    for (int32_t s = 0; sigma_set_h != nullptr && s < n_sets; ++s)
+        if (!(sigma_set_h[s] > 0.0) || !std::isfinite(sigma_set_h[s])) {
+            set_error("%s: sigma of set %d must be finite and > 0", what, s);
+            return FR_EINVAL;
+        }
+    return FR_OK;
+}
+
+fr_status fr_lattice_build_inplace(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *params,
+                                   const double *sigma_set_h, void *stream, fr_lattice **out)
+{
+    clear_error();
+    if (!ctx_ok(ctx) || out == nullptr) {
+        set_error("fr_lattice_build_inplace: invalid context or out pointer");
+        return FR_EINVAL;
+    }
+    *out = nullptr;
+    FR_TRY(check_lattice_params(params));
+    FR_TRY(check_cloud(obs, params->feat == 6 || params->values >= 7, "fr_lattice_build_inplace"));
+    FR_TRY(check_set_sigmas(sigma_set_h, obs->n_sets, "fr_lattice_build_inplace"));
+    FR_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    ResidentBuild *rb = nullptr;
+    FR_TRY(resident_create(ctx, obs, params, st, &rb));
+    fr_lattice *lat = resident_lattice(rb);
+    scale_factors(params, lat->k);
+    lat->kset.assign(8 * (size_t)obs->n_sets, 0.0f);
+    set_scale_factors(*params, obs->n_sets, sigma_set_h, lat->kset.data());
+    fr_status s = resident_build_host(rb, lat->kset.data(), st);
+    if (s == FR_OK) s = fr_sync_status(lat);
+    if (s != FR_OK) {
+        const std::string msg = fr_last_error();
+        (void)hipStreamSynchronize(st);
+        resident_destroy(rb, st, true);
+        set_error("%s", msg.c_str());
+        return s;
+    }
+    *out = lat;
+    return FR_OK;
+}
+
+fr_status fr_lattice_rebuild(fr_lattice *lat, const double *sigma_set_h, void *stream)
+{
+    clear_error();
+    if (!lat_ok(lat) || lat->resident == nullptr || sigma_set_h == nullptr) {
+        set_error("fr_lattice_rebuild: a lattice from fr_lattice_build_inplace and per-set sigmas are required");
+        return FR_EINVAL;
+    }
+    FR_TRY(check_set_sigmas(sigma_set_h, lat->n_sets, "fr_lattice_rebuild"));
+    FR_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope scope(st);
+    set_scale_factors(lat->params, lat->n_sets, sigma_set_h, lat->kset.data());
+    return resident_build_host(lat->resident, lat->kset.data(), st);
+}
+
 fr_status fr_lattice_build_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model_ref, const fr_xform *xf,
                                  const fr_lattice_params *params, void *stream, fr_lattice **out)
 {
@@ -732,8 +801,8 @@ fr_status fr_estep_features(const fr_lattice *lat, const fr_cloud *model_ref, co
 fr_status fr_lattice_blur(fr_lattice *lat, void *stream)
 {
     clear_error();
-    if (!lat_ok(lat)) {
-        set_error("fr_lattice_blur: invalid lattice");
+    if (!lat_ok(lat) || lat->resident != nullptr) {
+        set_error("fr_lattice_blur: invalid lattice (a lattice rebuilt in place cannot be blurred)");
         return FR_EINVAL;
     }
     FR_HIP(hipSetDevice(lat->ctx->device));
@@ -751,6 +820,10 @@ fr_status fr_lattice_destroy(fr_lattice *lat)
     (void)hipSetDevice(lat->ctx->device);
     // kernels queued on any stream may still read the lattice
     (void)hipDeviceSynchronize();
+    if (lat->resident != nullptr) {
+        resident_destroy(lat->resident, nullptr, true);
+        return FR_OK;
+    }
     free_lattice(lat, nullptr, true);
     lat->magic = kDeadMagic;
     delete lat;
@@ -773,6 +846,15 @@ fr_status fr_sync_status(const fr_lattice *lat)
         set_error("a lattice coordinate left [-2^20, 2^20) in an earlier call");
         return FR_ERANGE;
     }
+    if (lat->resident != nullptr) {
+        uint32_t f[2] = {0u, 0u};
+        FR_HIP(hipMemcpy(f, resident_fail_words(lat->resident), sizeof(f), hipMemcpyDeviceToHost));
+        if (f[0] != 0u || f[1] != 0u) {
+            set_error("the last in-place rebuild overflowed its %s table; the lattice is not valid",
+                      f[0] != 0u ? "provisional" : "cuckoo");
+            return FR_EDEVICE;
+        }
+    }
     return FR_OK;
 }
 
@@ -780,8 +862,8 @@ fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertic
                            int64_t *device_bytes)
 {
     clear_error();
-    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets) {
-        set_error("fr_lattice_stats: invalid lattice or set");
+    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets || lat->resident != nullptr) {
+        set_error("fr_lattice_stats: invalid lattice or set (not available on a lattice rebuilt in place)");
         return FR_EINVAL;
     }
     FR_TRY(fr_sync_status(lat));
@@ -799,8 +881,8 @@ fr_status fr_lattice_stats(const fr_lattice *lat, int32_t set, int64_t *n_vertic
 fr_status fr_lattice_export(const fr_lattice *lat, int32_t set, int32_t *keys_h, int32_t *occ_h, float *vals_h)
 {
     clear_error();
-    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets) {
-        set_error("fr_lattice_export: invalid lattice or set");
+    if (!lat_ok(lat) || set < 0 || set >= lat->n_sets || lat->resident != nullptr) {
+        set_error("fr_lattice_export: invalid lattice or set (not available on a lattice rebuilt in place)");
         return FR_EINVAL;
     }
     FR_TRY(fr_sync_status(lat));
@@ -1444,14 +1526,17 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
     StreamScope scope(st);
     const int64_t M = cloud_points(model_ref);
     fr_report rep{};
-    std::vector<double> sig(sigma_inout_h, sigma_inout_h + S);
 
     Plan pe, pr;
     FR_TRY(make_plan(ctx, model_ref, nullptr, kEstepTile, nullptr, st, pe));
     FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, nullptr, st, pr));
+    if (pr.n_seg != S) {
+        set_error("fr_register_sigma: internal error (a plan of %d segments for %d sets)", pr.n_seg, S);
+        return FR_EDEVICE;
+    }
     const bool pl = params->residual == FR_PT2PL;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);
-    DevBuf wm0, wm1, wns, wm2, part, wjtj, wjtr, wstat, wvar, wpose, wmats, wtn, wstatus, wactive;
+    DevBuf wm0, wm1, wns, wm2, part, wjtj, wjtr, wstat, wvar, state, ckpt;
     FR_TRY(wm0.alloc(ctx, nM * sizeof(float)));
     FR_TRY(wm1.alloc(ctx, 3 * nM * sizeof(float)));
     FR_TRY(wm2.alloc(ctx, nM * sizeof(float)));
@@ -1461,107 +1546,197 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
     FR_TRY(wjtr.alloc(ctx, S * 6 * sizeof(double)));
     FR_TRY(wstat.alloc(ctx, S * 4 * sizeof(double)));
     FR_TRY(wvar.alloc(ctx, S * sizeof(double)));
-    FR_TRY(wpose.alloc(ctx, S * 16 * sizeof(double)));
-    FR_TRY(wmats.alloc(ctx, S * 12 * sizeof(float)));
-    FR_TRY(wtn.alloc(ctx, S * 2 * sizeof(double)));
-    FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
-    FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
-    std::vector<float> mats_h((size_t)S * 12);
-    for (int32_t s = 0; s < S; ++s)
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 4; ++j) mats_h[(size_t)s * 12 + 4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
-    std::vector<int32_t> active_h(S, 1), status_v(S, FR_OK);
-    FR_HIP(hipMemcpyAsync(wpose.p, theta_inout_h, S * 16 * sizeof(double), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(wmats.p, mats_h.data(), S * 12 * sizeof(float), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(wstatus.p, status_v.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+
+    // The loop's state in one block (one copy saves or restores it): poses,
+    // twist norms, scales s, the outlier constants' scale-free factors, the
+    // binary32 transforms, lattice scale factors and outlier constants of the
+    // current s, status, active flags and iteration counts.
+    const size_t o_pose = 0, o_tn = o_pose + 16 * (size_t)S * 8, o_sig = o_tn + 2 * (size_t)S * 8;
+    const size_t o_cpre = o_sig + (size_t)S * 8, o_mats = o_cpre + (size_t)S * 8;
+    const size_t o_kset = o_mats + 12 * (size_t)S * 4, o_segc = o_kset + 8 * (size_t)S * 4;
+    const size_t o_status = o_segc + (size_t)S * 4, o_act = o_status + (size_t)S * 4;
+    const size_t o_iters = o_act + (size_t)S * 4, state_bytes = o_iters + (size_t)S * 4;
+    std::vector<char> img(state_bytes, 0);
+    {
+        auto put = [&](size_t off, const void *src, size_t bytes) { std::memcpy(img.data() + off, src, bytes); };
+        put(o_pose, theta_inout_h, (size_t)S * 16 * sizeof(double));
+        put(o_sig, sigma_inout_h, (size_t)S * sizeof(double));
+        for (int32_t s = 0; s < S; ++s) {
+            const double Ms = (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]);
+            const double Ns = (double)(obs->offsets[s + 1] - obs->offsets[s]);
+            // outlier_constant's factor ahead of the kernel mass, in its order of operations
+            const double w = params->w;
+            const double pre = (!(Ms > 0) || !(w > 0.0)) ? 0.0 : w / (1.0 - w) * (Ns / Ms);
+            put(o_cpre + (size_t)s * 8, &pre, 8);
+            float m12[12];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 4; ++j) m12[4 * i + j] = (float)theta_inout_h[(size_t)s * 16 + 4 * i + j];
+            put(o_mats + (size_t)s * 48, m12, 48);
+            fr_lattice_params ls = params->lattice;
+            ls.sigma[0] = ls.sigma[1] = ls.sigma[2] = sigma_inout_h[s];
+            float k8[8];
+            scale_factors(&ls, k8);
+            put(o_kset + (size_t)s * 32, k8, 32);
+            const float c = (float)outlier_constant(ls, params->w, params->c_override, Ms, Ns);
+            put(o_segc + (size_t)s * 4, &c, 4);
+            const int32_t ok = FR_OK, one = 1, zero = 0;
+            put(o_status + (size_t)s * 4, &ok, 4);
+            put(o_act + (size_t)s * 4, &one, 4);
+            put(o_iters + (size_t)s * 4, &zero, 4);
+        }
+    }
+    FR_TRY(state.alloc(ctx, state_bytes));
+    FR_TRY(ckpt.alloc(ctx, state_bytes));
+    FR_HIP(hipMemcpyAsync(state.p, img.data(), state_bytes, hipMemcpyHostToDevice, st));
+    char *sb = state.as<char>();
+    double *wpose = reinterpret_cast<double *>(sb + o_pose), *wtn = reinterpret_cast<double *>(sb + o_tn);
+    double *wsig = reinterpret_cast<double *>(sb + o_sig);
+    float *wmats = reinterpret_cast<float *>(sb + o_mats), *wkset = reinterpret_cast<float *>(sb + o_kset);
+    float *wsegc = reinterpret_cast<float *>(sb + o_segc);
+    int32_t *wstatus = reinterpret_cast<int32_t *>(sb + o_status), *act = reinterpret_cast<int32_t *>(sb + o_act);
+    int32_t *witers = reinterpret_cast<int32_t *>(sb + o_iters);
+    pr.seg_c = wsegc;   // the reduction reads the constants the variance update writes
+
+    SigmaRule rule;
+    {
+        const int d = params->lattice.feat;
+        rule.feat = d;
+        rule.sigma_min = sigma_min;
+        rule.sigma_n = params->lattice.sigma_n;
+        rule.kernel_axis_var = kKernelAxisVar;
+        rule.scale_num = std::sqrt(2.0 / 3.0) * (double)(d + 1);
+        for (int i = 0; i < d; ++i) rule.scale_den[i] = std::sqrt((double)((i + 1) * (i + 2)));
+        rule.mass0 = std::pow(1.5, 0.5 * d) / std::sqrt(d + 1.0);
+        rule.c_override = params->c_override >= 0.0 ? params->c_override : -1.0;
+        rule.c_pre = reinterpret_cast<const double *>(sb + o_cpre);
+    }
+
+    // The lattice is rebuilt in place every iteration (no host wait); a
+    // rebuild whose provisional table overflowed or whose cuckoo insertion
+    // gave up is caught at the end of its block, which is then run again
+    // from the saved state with the build that sizes its tables on the host.
+    ResidentBuild *rb = nullptr;
+    if (cloud_points(obs) > 0) FR_TRY(resident_create(ctx, obs, &params->lattice, st, &rb));
+    struct RbGuard {
+        ResidentBuild *rb;
+        hipStream_t st;
+        ~RbGuard() { resident_destroy(rb, st); }
+    } rb_guard{rb, st};
+    int32_t *pin = nullptr;
+    FR_TRY(pinned_flags(ctx, 3 * (size_t)S + 3, pin));
 
     const bool prof = (params->flags & FR_PROFILE_EVENTS) != 0;
     const bool fixed = (params->flags & FR_FIXED_ITERS) != 0;
+    const double tol = fixed ? -1.0 : params->twist_tol;
     const int max_it = params->max_iters;
     std::vector<hipEvent_t> ev;
+    struct EventsGuard {
+        std::vector<hipEvent_t> &e;
+        ~EventsGuard()
+        {
+            for (auto &x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev_guard{ev};
     if (prof) {
-        ev.resize(3 * (size_t)max_it + 1);
+        ev.assign(4 * (size_t)max_it, nullptr);
         for (auto &e : ev) FR_HIP(hipEventCreate(&e));
     }
-    std::vector<float> cseg(S);
-    std::vector<double> stats_h((size_t)S * 4), var_h(S), tn((size_t)S * 2);
-    auto t_em = clk::now();
-    int it = 0;
-    for (; it < max_it; ++it) {
-        auto tb = clk::now();
-        fr_lattice *lat = nullptr;
-        FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, sig.data()));
-        struct LatGuard {
-            fr_lattice *l;
-            ~LatGuard()
-            {
-                if (l) fr_lattice_destroy(l);
-            }
-        } guard{lat};
-        rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
-        // outlier constant of each set at its current sigma
-        for (int32_t s = 0; s < S; ++s) {
-            fr_lattice_params ls = params->lattice;
-            ls.sigma[0] = ls.sigma[1] = ls.sigma[2] = sig[s];
-            cseg[s] = (float)outlier_constant(ls, params->w, params->c_override,
-                                              (double)(model_ref->offsets[s + 1] - model_ref->offsets[s]),
-                                              (double)(obs->offsets[s + 1] - obs->offsets[s]));
-        }
-        FR_HIP(hipMemcpyAsync(const_cast<float *>(pr.seg_c), cseg.data(), S * sizeof(float), hipMemcpyHostToDevice,
-                              st));
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
-        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
-                            pl ? wns.as<float>() : nullptr, nullptr, st, wm2.as<float>()));
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
+    // E-step, reduction, solve and variance update of iteration j on a built lattice
+    auto iter_kernels = [&](const fr_lattice *lat, int j) -> fr_status {
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 1], st));
+        FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats, wm0.as<float>(), wm1.as<float>(),
+                            pl ? wns.as<float>() : nullptr, nullptr, st, wm2.as<float>(), act));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 2], st));
         // the Gauss-Newton step does not depend on the residual scale: reduce at sigma = 1
-        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(), wm1.as<float>(),
+        FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats, wm0.as<float>(), wm1.as<float>(),
                              pl ? wns.as<float>() : nullptr, params->residual, 0, 1.0, wjtj.as<double>(),
                              wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st, wm2.as<float>(),
-                             wvar.as<double>()));
-        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose.as<double>(), wmats.as<float>(),
-                                  wtn.as<double>(), wstatus.as<int32_t>(), wactive.as<int32_t>(), st));
-        if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
-        FR_HIP(hipMemcpyAsync(stats_h.data(), wstat.p, S * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(var_h.data(), wvar.p, S * sizeof(double), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(tn.data(), wtn.p, S * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                             wvar.as<double>(), act));
+        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose, wmats, wtn, wstatus, act, st, act,
+                                  tol, witers));
+        FR_TRY(launch_sigma_update(S, j + 1, witers, wstatus, wstat.as<double>(), wvar.as<double>(), rule, wsig,
+                                   wkset, wsegc, st));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 3], st));
+        return FR_OK;
+    };
+    std::vector<double> sig_h(S);
+    // iteration j with the build that sizes its tables on the host (waits)
+    auto iter_waiting = [&](int j) -> fr_status {
+        FR_HIP(hipMemcpyAsync(sig_h.data(), wsig, S * sizeof(double), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
-        FR_TRY(fr_sync_status(lat));
-        int n_active = 0;
-        for (int32_t s = 0; s < S; ++s) {
-            if (!active_h[s]) continue;
-            // sets that stopped keep the sigma of their last pose
-            if (status_v[s] == FR_OK && stats_h[4 * s] > 0.0) {
-                const double var = var_h[s] / (3.0 * stats_h[4 * s]);
-                sig[s] = std::max(sigma_min, std::sqrt(std::max(var, 0.0) / kKernelAxisVar));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j], st));
+        fr_lattice *lat = nullptr;
+        FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, sig_h.data()));
+        struct LatGuard {
+            fr_lattice *l;
+            ~LatGuard() { fr_lattice_destroy(l); }
+        } guard{lat};
+        FR_TRY(iter_kernels(lat, j));
+        return fr_sync_status(lat);
+    };
+    constexpr int kBlock = 4;
+    const size_t flag_bytes = 3 * (size_t)S * sizeof(int32_t);   // status, active, iterations
+    auto t_em = clk::now();
+    int it = 0;
+    while (it < max_it) {
+        const int n = std::min(kBlock, max_it - it);
+        bool redo = rb == nullptr;
+        if (rb != nullptr) {
+            FR_HIP(hipMemcpyAsync(ckpt.p, state.p, state_bytes, hipMemcpyDeviceToDevice, st));
+            for (int k = 0; k < n; ++k) {
+                if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)(it + k)], st));
+                FR_TRY(resident_build(rb, wkset, st));
+                FR_TRY(iter_kernels(resident_lattice(rb), it + k));
             }
-            if (status_v[s] != FR_OK ||
-                (!fixed && tn[2 * s] < params->twist_tol && tn[2 * s + 1] < params->twist_tol))
-                active_h[s] = 0;
-            n_active += active_h[s];
+            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, st));
+            FR_HIP(hipMemcpyAsync(pin + 3 * S, resident_fail_words(rb), 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  st));
+            FR_HIP(hipMemcpyAsync(pin + 3 * S + 2, resident_lattice(rb)->err_d, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
+            FR_HIP(hipStreamSynchronize(st));
+            if (pin[3 * S + 2] != 0) {
+                set_error("fr_register_sigma: a lattice coordinate left [-2^20, 2^20); increase sigma_min or "
+                          "centre the cloud");
+                return FR_ERANGE;
+            }
+            if (pin[3 * S] != 0 || pin[3 * S + 1] != 0) {
+                FR_HIP(hipMemcpyAsync(state.p, ckpt.p, state_bytes, hipMemcpyDeviceToDevice, st));
+                redo = true;
+            }
         }
-        FR_HIP(hipMemcpyAsync(wactive.p, active_h.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        if (n_active == 0) {
-            ++it;
-            break;
+        if (redo) {
+            for (int k = 0; k < n; ++k) FR_TRY(iter_waiting(it + k));
+            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, st));
+            FR_HIP(hipStreamSynchronize(st));
         }
+        it += n;
+        int32_t any = 0;
+        for (int32_t s = 0; s < S; ++s) any |= pin[S + s];
+        if (any == 0) break;
     }
-    FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
-    FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> status_v(S), iters_v(S);
+    std::vector<double> sig(S);
+    FR_HIP(hipMemcpyAsync(theta_inout_h, wpose, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(sig.data(), wsig, S * sizeof(double), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(status_v.data(), wstatus, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FR_HIP(hipMemcpyAsync(iters_v.data(), witers, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipStreamSynchronize(st));
-    rep.iterations = it;
-    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t_em).count() - rep.build_ms;
+    rep.iterations = 0;
+    for (int32_t s = 0; s < S; ++s) rep.iterations = std::max(rep.iterations, iters_v[s]);
+    rep.em_ms = std::chrono::duration<double, std::milli>(clk::now() - t_em).count();
     if (prof) {
         for (int i = 0; i < it; ++i) {
-            float a = 0.0f, b = 0.0f;
-            FR_HIP(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
-            FR_HIP(hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]));
-            rep.estep_ms += a;
-            rep.mstep_ms += b;
+            float a = 0.0f, b = 0.0f, c = 0.0f;
+            FR_HIP(hipEventElapsedTime(&a, ev[4 * (size_t)i], ev[4 * (size_t)i + 1]));
+            FR_HIP(hipEventElapsedTime(&b, ev[4 * (size_t)i + 1], ev[4 * (size_t)i + 2]));
+            FR_HIP(hipEventElapsedTime(&c, ev[4 * (size_t)i + 2], ev[4 * (size_t)i + 3]));
+            rep.build_ms += a;
+            rep.estep_ms += b;
+            rep.mstep_ms += c;
         }
         rep.estep_launches = it;
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        rep.em_ms -= rep.build_ms;
     }
     int32_t n_deg = 0;
     for (int32_t s = 0; s < S; ++s) {

@@ -79,6 +79,10 @@ struct fr_ctx {
     std::vector<fr_tuning_entry> tuned;
 };
 
+namespace fr {
+struct ResidentBuild;
+}
+
 struct fr_lattice {
     uint32_t magic = fr::kLatMagic;
     fr_ctx *ctx = nullptr;
@@ -108,6 +112,9 @@ struct fr_lattice {
     // descriptor lattices (d = feature dimension): the d binary32 scale factors
     float *kfeat_d = nullptr;
     std::vector<float> kfeat;
+    // lattices rebuilt in place: the storage and state of the rebuilds
+    fr::ResidentBuild *resident = nullptr;
+    fr_lattice_params params{};
 };
 
 namespace fr {
@@ -230,6 +237,41 @@ fr_status build_feature_lattice(fr_ctx *ctx, const fr_cloud *obs, const float *f
                                 fr_lattice *lat);
 bool feature_dim_supported(int dim);
 
+// A lattice of one observation cloud rebuilt in place at any per-set scale:
+// storage sized once (resident_create waits once for its set-up), and each
+// resident_build only enqueues kernels on `st` -- no host wait, no allocation
+// -- reading the per-set scale factors (n_sets x 8 binary32) from the device.
+// resident_fail_words: two device words, a provisional-table overflow and a
+// cuckoo insertion that gave up in the last rebuild (its tables are then not
+// valid); range errors latch in the lattice's err_d as for build_lattice.
+// The optimised-sigma loop's variance rule and the constants of the scale
+// factors and outlier constant that follow sigma (host-computed once).
+struct SigmaRule {
+    int32_t feat = 3;
+    double sigma_min = 0.0, sigma_n = 1.0, kernel_axis_var = 0.25;
+    double scale_num = 0.0;         // sqrt(2/3) (d + 1)
+    double scale_den[8] = {0};      // sqrt((i + 1)(i + 2))
+    double mass0 = 0.0;             // (3/2)^(d/2) / sqrt(d + 1)
+    double c_override = -1.0;       // >= 0: the outlier constant itself
+    const double *c_pre = nullptr;  // device, per set: w / (1 - w) N_s / M_s (0: no outlier term)
+};
+fr_status launch_sigma_update(int32_t n, int32_t iter1, const int32_t *iters, const int32_t *status,
+                              const double *stats, const double *var, const SigmaRule &rule, double *sig,
+                              float *kset, float *seg_c, hipStream_t st);
+
+struct ResidentBuild;
+fr_status resident_create(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
+                          ResidentBuild **out);
+fr_status resident_build(ResidentBuild *rb, const float *kset, hipStream_t st);
+// The same with the scale factors from host memory (copied through a pinned
+// buffer of the build, after the previous rebuild's copy has been read).
+fr_status resident_build_host(ResidentBuild *rb, const float *kset_h, hipStream_t st);
+fr_lattice *resident_lattice(ResidentBuild *rb);
+const uint32_t *resident_fail_words(const ResidentBuild *rb);
+// Frees the storage and the lattice; idle: the device has finished every use
+// (else the release is ordered after the work queued on st).
+void resident_destroy(ResidentBuild *rb, hipStream_t st, bool idle = false);
+
 // estep.hip
 // active (device, per set, may be NULL): tiles of a set with active == 0 do
 // nothing (a set that has stopped on its twist or degenerated).
@@ -317,6 +359,9 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
                   hipStream_t stream);
 
 // scan / sort helpers (lattice_build.hip)
-fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t stream);
+// ws: NULL (temporaries from the context), or scan_ws_words(n) words the caller keeps until the scan has run.
+fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t stream,
+                             uint32_t *ws = nullptr);
+size_t scan_ws_words(size_t n);
 
 }  // namespace fr

@@ -88,7 +88,18 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t *out, const 
     }
 }
 
-fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t st)
+size_t scan_ws_words(size_t n)
+{
+    size_t words = 0;
+    while (n > (size_t)kScanTile) {
+        n = (n + kScanTile - 1) / kScanTile;
+        words += n;
+    }
+    return words;
+}
+
+fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t st,
+                             uint32_t *ws)
 {
     if (n == 0) return FR_OK;
     const size_t nb = (n + kScanTile - 1) / kScanTile;
@@ -100,14 +111,18 @@ fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, siz
         return FR_OK;
     }
     DevBuf bs;
-    FR_TRY(bs.alloc(ctx, nb * sizeof(uint32_t)));
-    bs.stream = st;   // freed in the order of st: no wait here
-    if (mode == 1) k_scan_tile<1><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
-    else if (mode == 2) k_scan_tile<2><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
-    else k_scan_tile<0><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bs.as<uint32_t>(), n);
+    uint32_t *bsum = ws;
+    if (bsum == nullptr) {
+        FR_TRY(bs.alloc(ctx, nb * sizeof(uint32_t)));
+        bs.stream = st;   // freed in the order of st: no wait here
+        bsum = bs.as<uint32_t>();
+    }
+    if (mode == 1) k_scan_tile<1><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bsum, n);
+    else if (mode == 2) k_scan_tile<2><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bsum, n);
+    else k_scan_tile<0><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, bsum, n);
     FR_HIP(hipGetLastError());
-    FR_TRY(scan_exclusive_u32(ctx, bs.as<uint32_t>(), bs.as<uint32_t>(), nb, 0, st));
-    k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, bs.as<uint32_t>(), n);
+    FR_TRY(scan_exclusive_u32(ctx, bsum, bsum, nb, 0, st, ws != nullptr ? ws + nb : nullptr));
+    k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, bsum, n);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
@@ -120,10 +135,23 @@ constexpr int kRsRounds = 16;                        // rounds of 64 items per w
 constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsTile = kRsThreads * kRsRounds;      // 4096 items per block
 
-__global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t *keys, size_t n, int shift, uint32_t *hist,
-                                                        uint32_t nblocks)
+// n_dev (or NULL): a device count that bounds n (blocks past it count nothing).
+__device__ __forceinline__ size_t dev_count(size_t n, const uint32_t *n_dev)
+{
+    return n_dev != nullptr ? min(n, (size_t)*n_dev) : n;
+}
+
+// A rebuild in place runs its kernels without reading failures back in
+// between; a kernel whose inputs an earlier failure left partly unset (record
+// slots of an overflowed insertion, vertex slots of a cuckoo pass that gave
+// up) is given the failure word and returns at once when it is set.
+__device__ __forceinline__ bool aborted(const uint32_t *fail) { return fail != nullptr && *fail != 0u; }
+
+__global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t *keys, size_t n, const uint32_t *n_dev,
+                                                        int shift, uint32_t *hist, uint32_t nblocks)
 {
     __shared__ uint32_t h[256];
+    n = dev_count(n, n_dev);
     h[threadIdx.x] = 0;
     __syncthreads();
     const size_t base = (size_t)blockIdx.x * kRsTile;
@@ -143,9 +171,11 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const uint32_t *keys, si
 // block's items are placed in LDS in digit order and written out from there,
 // so consecutive threads write consecutive places of each digit's run.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                                           uint32_t *vout, size_t n, int shift,
+                                                           uint32_t *vout, size_t n, const uint32_t *n_dev, int shift,
                                                            const uint32_t *hist_scan, uint32_t nblocks)
 {
+    n = dev_count(n, n_dev);
+    if ((size_t)blockIdx.x * kRsTile >= n) return;   // uniform: no items, nothing to place
     __shared__ uint32_t wcnt[kRsWaves][256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t dstart[256];      // first place of each digit among the block's items
@@ -225,23 +255,37 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t *kin, 
 
 // Sorts keys/vals by the low `bits` bits, ping-ponging through tk/tv; on
 // return *keys_out / *vals_out name the pair of arrays that holds the result.
+// n_dev (or NULL): the device count of items (at most n) -- the launches are
+// sized for n.  ws (or NULL): radix_ws_words(n) words kept by the caller.
+static size_t radix_ws_words(size_t n)
+{
+    const size_t nb = (n + kRsTile - 1) / kRsTile;
+    return 256 * nb + scan_ws_words(256 * nb);
+}
+
 static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, size_t n,
-                                  int bits, hipStream_t st, uint32_t **keys_out, uint32_t **vals_out)
+                                  int bits, hipStream_t st, uint32_t **keys_out, uint32_t **vals_out,
+                                  const uint32_t *n_dev = nullptr, uint32_t *ws = nullptr)
 {
     *keys_out = keys;
     *vals_out = vals;
     if (n <= 1 || bits <= 0) return FR_OK;
     const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
-    DevBuf hist;
-    FR_TRY(hist.alloc(ctx, (size_t)256 * nb * sizeof(uint32_t)));
-    hist.stream = st;
+    DevBuf hbuf;
+    uint32_t *hist = ws;
+    if (hist == nullptr) {
+        FR_TRY(hbuf.alloc(ctx, (size_t)256 * nb * sizeof(uint32_t)));
+        hbuf.stream = st;
+        hist = hbuf.as<uint32_t>();
+    }
+    uint32_t *scan_ws = ws != nullptr ? ws + (size_t)256 * nb : nullptr;
     uint32_t *ka = keys, *va = vals, *kb = tk, *vb = tv;
     int passes = 0;
     for (int shift = 0; shift < bits; shift += 8, ++passes) {
-        k_rs_hist<<<nb, kRsThreads, 0, st>>>(ka, n, shift, hist.as<uint32_t>(), nb);
+        k_rs_hist<<<nb, kRsThreads, 0, st>>>(ka, n, n_dev, shift, hist, nb);
         FR_HIP(hipGetLastError());
-        FR_TRY(scan_exclusive_u32(ctx, hist.as<uint32_t>(), hist.as<uint32_t>(), (size_t)256 * nb, 0, st));
-        k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ka, va, kb, vb, n, shift, hist.as<uint32_t>(), nb);
+        FR_TRY(scan_exclusive_u32(ctx, hist, hist, (size_t)256 * nb, 0, st, scan_ws));
+        k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ka, va, kb, vb, n, n_dev, shift, hist, nb);
         FR_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -631,68 +675,79 @@ __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTab
     }
 }
 
-// Vertex ids in owner-record order (the exclusive scan of the owner flags,
-// NV in all): owners -- the records whose id the scan steps past -- write
-// their vertex's key and the slot -> vertex map.
+// Vertex ids in owner-record order: `ovid` holds the exclusive scan of the
+// owner flags over R + 1 entries (the flag past the last record is 0, so
+// ovid[R] is the vertex count); owners -- the records whose id the scan
+// steps past -- write their vertex's key (word-major, `stride` vertices per
+// word) and the slot -> vertex map.
 template <int KW>
 __global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *ovid,
-                                                   const uint64_t *rec_key, uint64_t *vkey, size_t NV,
+                                                   const uint64_t *rec_key, uint64_t *vkey, size_t stride,
                                                    uint32_t *slot_vid)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     const uint32_t v = ovid[r];
-    const uint32_t next = r + 1 < R ? ovid[r + 1] : (uint32_t)NV;
-    if (next == v) return;
+    if (ovid[r + 1] == v) return;
     const uint32_t slot = rec_slot[r];
 #pragma unroll
-    for (int w = 0; w < KW; ++w) vkey[(size_t)w * NV + v] = rec_key[(size_t)r * KW + w];
+    for (int w = 0; w < KW; ++w) vkey[(size_t)w * stride + v] = rec_key[(size_t)r * KW + w];
     slot_vid[slot] = v;
 }
 
-// Vertex count of each set: owners of its records form one contiguous id range.
-// The total is the last record's scanned id plus its own flag (saved before
-// the in-place scan).
-__global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32_t *ovid, size_t R,
-                            const uint32_t *last_flag, uint32_t *vbase)
+// First vertex of each set (set n_sets: the vertex count): owners of a set's
+// records form one contiguous id range, so it is the scanned flag at the set's
+// first record (rec_off[n_sets] = the record count).  vbase64 and nv (or
+// NULL): the same as int64 (a tile map's offsets) and the count alone.
+__global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32_t *ovid, uint32_t *vbase,
+                            int64_t *vbase64, uint32_t *nv)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s > n_sets) return;
-    const int64_t r = rec_off[s];
-    const uint32_t nv_total = R > 0 ? ovid[R - 1] + last_flag[0] : 0u;
-    vbase[s] = (r < (int64_t)R) ? ovid[r] : nv_total;
+    const uint32_t v = ovid[rec_off[s]];
+    if (vbase != nullptr) vbase[s] = v;
+    if (vbase64 != nullptr) vbase64[s] = (int64_t)v;
+    if (nv != nullptr && s == n_sets) *nv = v;
 }
 
-__global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t *rec_slot, const uint32_t *slot_vid,
+__global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t *n_dev, const uint32_t *fail,
+                                                      const uint32_t *rec_slot, const uint32_t *slot_vid,
                                                       uint32_t *rvid, uint32_t *rid)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
+    if (r >= dev_count(R, n_dev) || aborted(fail)) return;
     rvid[r] = slot_vid[rec_slot[r]];
     rid[r] = (uint32_t)r;
 }
 
 // Sorted mode: segment starts and lengths of the vertex-sorted partials.
-__global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t *rvid_sorted, uint32_t *voff)
+__global__ void __launch_bounds__(256) k_segment_heads(size_t R, const uint32_t *n_dev, const uint32_t *fail,
+                                                       const uint32_t *rvid_sorted, uint32_t *voff)
 {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= R) return;
+    if (q >= dev_count(R, n_dev) || aborted(fail)) return;
     const uint32_t v = rvid_sorted[q];
     if (q == 0 || rvid_sorted[q - 1] != v) voff[v] = (uint32_t)q;
 }
 
 // Sorted mode: per vertex, the partials in partial order summed in binary64
 // (occupancy = the sum of their incidence counts) -> bitwise deterministic.
+// Vertex arrays are channel-major with `stride` vertices per channel; nv_dev
+// and p_dev (or NULL) are device counts bounding NV and P.
 template <int V>
-__global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, const uint32_t *voff,
+__global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint32_t *nv_dev, size_t stride, size_t P,
+                                                          const uint32_t *p_dev, const uint32_t *fail,
+                                                          const uint32_t *voff,
                                                           const uint32_t *rid_sorted,
                                                           const typename PartialRow<V>::T *prow, float *vval,
                                                           uint32_t *vocc)
 {
     using R = PartialRow<V>;
     using T = typename R::T;
+    NV = dev_count(NV, nv_dev);
+    P = dev_count(P, p_dev);
     const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= NV) return;
+    if (v >= NV || aborted(fail)) return;
     double acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0.0;
@@ -722,20 +777,20 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, size_t P, 
     }
     vocc[v] = occ;
 #pragma unroll
-    for (int c = 0; c < V; ++c) vval[(size_t)c * NV + v] = (float)acc[c];
+    for (int c = 0; c < V; ++c) vval[(size_t)c * stride + v] = (float)acc[c];
 }
 
 // Atomic mode: one thread per partial, binary32 hardware atomics of its sums;
 // occupancy by integer atomics.  The |y|^2 channel waits for the second pass.
 template <int V>
-__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint32_t *rec_slot,
-                                                          const uint32_t *slot_vid,
+__global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint32_t *p_dev, const uint32_t *fail,
+                                                          const uint32_t *rec_slot, const uint32_t *slot_vid,
                                                           const typename PartialRow<V>::T *prow, float *vval,
                                                           uint32_t *vocc, size_t NV)
 {
     using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= P) return;
+    if (q >= dev_count(P, p_dev) || aborted(fail)) return;
     const uint32_t v = slot_vid[rec_slot[q]];
     alignas(16) typename R::T row[R::S];
     load_row<V>(prow, q, row);
@@ -751,14 +806,14 @@ __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint3
 // form of the scatter; about a mean rounded to binary32 it is larger by
 // W |mu - mu'|^2, far below the binary32 resolution of the sum).
 template <int V>
-__global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t P, const uint32_t *rec_slot,
-                                                              const uint32_t *slot_vid,
+__global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t P, const uint32_t *p_dev, const uint32_t *fail,
+                                                              const uint32_t *rec_slot, const uint32_t *slot_vid,
                                                               const typename PartialRow<V>::T *prow, float *vval,
                                                               size_t NV)
 {
     using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= P) return;
+    if (q >= dev_count(P, p_dev) || aborted(fail)) return;
     const uint32_t v = slot_vid[rec_slot[q]];
     alignas(16) typename R::T row[R::S];
     load_row<V>(prow, q, row);
@@ -801,6 +856,7 @@ __device__ __forceinline__ bool claim_free(uint32_t *own, uint32_t bucket, uint3
     return false;
 }
 
+// Vertex keys are word-major with NV (the stride) vertices per word.
 template <int KW>
 __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTable *tables, const uint64_t *vkey,
                                                       size_t NV, uint32_t *own, int32_t *fail)
@@ -835,12 +891,12 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
 // Filling the table, first pass (one thread per slot): a free slot gets the
 // empty key, an occupied one tells its vertex where it sits.
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_slot_owner(size_t n_slots, const uint32_t *own, char *table,
-                                                   uint32_t *vslot)
+__global__ void __launch_bounds__(256) k_slot_owner(size_t n_slots, const uint32_t *n_dev, const uint32_t *own,
+                                                   char *table, uint32_t *vslot)
 {
     using G = SlotGeom<KW, V>;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_slots) return;
+    if (j >= dev_count(n_slots, n_dev)) return;
     const uint32_t o = own[j];
     if (o != kOwnerEmpty) {
         vslot[o] = (uint32_t)j;
@@ -855,20 +911,21 @@ __global__ void __launch_bounds__(256) k_slot_owner(size_t n_slots, const uint32
 // the key words and padded values of the vertex, written to its slot.  A free
 // slot's values are never read.
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_vertex_fill(size_t NV, const uint32_t *vslot, const uint64_t *vkey,
+__global__ void __launch_bounds__(256) k_vertex_fill(size_t NV, const uint32_t *nv_dev, size_t stride,
+                                                    const uint32_t *fail, const uint32_t *vslot, const uint64_t *vkey,
                                                     const float *vval, char *table)
 {
     using G = SlotGeom<KW, V>;
     constexpr int VP = ValPad<V>::value;
     const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= NV) return;
+    if (v >= dev_count(NV, nv_dev) || aborted(fail)) return;
     char *slot = table + (size_t)G::bytes * vslot[v];
     uint64_t *key = reinterpret_cast<uint64_t *>(slot);
 #pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * NV + v];
+    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * stride + v];
     float val[VP];
 #pragma unroll
-    for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * NV + v] : 0.0f;
+    for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * stride + v] : 0.0f;
     float4 *dst = reinterpret_cast<float4 *>(slot + G::val_off);
 #pragma unroll
     for (int q = 0; q < VP / 4; ++q) dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
@@ -1049,10 +1106,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     //    is more; 2 R_set if that overflows; R_set = the set's partial records)
     FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true, &keep));
     uint64_t n1 = 0;
-    DevBuf ovid, slot_vid, vb_d, last_d;
-    FR_TRY(ovid.alloc(ctx, P * sizeof(uint32_t)));   // owner flags, then their exclusive scan
+    DevBuf ovid, slot_vid, vb_d;
+    FR_TRY(ovid.alloc(ctx, (P + 1) * sizeof(uint32_t)));   // owner flags (and a 0), then their exclusive scan
     FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
-    FR_TRY(last_d.alloc(ctx, sizeof(uint32_t)));
     std::vector<uint32_t> vb_h(S + 1);
     int32_t err_h = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1087,10 +1143,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         }
         // 3. vertex ids in owner-record order and per-set ranges, enqueued before the
         //    overflow check (one wait for both; redone if the insertion overflowed)
-        if (P > 0) FR_HIP(hipMemcpyAsync(last_d.p, ovid.as<uint32_t>() + P - 1, 4, hipMemcpyDeviceToDevice, st));
-        FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), P, 0, st));
-        k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), P,
-                                                          last_d.as<uint32_t>(), vb_d.as<uint32_t>());
+        FR_HIP(hipMemsetAsync(ovid.as<uint32_t>() + P, 0, sizeof(uint32_t), st));
+        FR_TRY(scan_exclusive_u32(ctx, ovid.as<uint32_t>(), ovid.as<uint32_t>(), P + 1, 0, st));
+        k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), vb_d.as<uint32_t>(),
+                                                          nullptr, nullptr);
         FR_HIP(hipGetLastError());
         int32_t failed = 0;
         FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1146,29 +1202,32 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             FR_TRY(tk.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(tv.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(voff.alloc(ctx, NV * sizeof(uint32_t)));
-            k_record_vertex<<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(),
-                                                                 rvid.as<uint32_t>(), rid.as<uint32_t>());
+            k_record_vertex<<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, rec_slot.as<uint32_t>(),
+                                                                 slot_vid.as<uint32_t>(), rvid.as<uint32_t>(),
+                                                                 rid.as<uint32_t>());
             FR_HIP(hipGetLastError());
             int bits = 0;
             while (bits < 32 && (NV - 1) >> bits) ++bits;
             uint32_t *svid = nullptr, *srid = nullptr;   // the sorted pairs
             FR_TRY(radix_sort_pairs(ctx, rvid.as<uint32_t>(), rid.as<uint32_t>(), tk.as<uint32_t>(),
                                     tv.as<uint32_t>(), P, bits, st, &svid, &srid));
-            k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, svid, voff.as<uint32_t>());
+            k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
-            k_vertex_sum_sorted<V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, P, voff.as<uint32_t>(), srid,
-                                                                        rec_row.as<T>(), lat->vval, lat->vocc);
+            k_vertex_sum_sorted<V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, P, nullptr, nullptr,
+                                                                        voff.as<uint32_t>(), srid, rec_row.as<T>(),
+                                                                        lat->vval, lat->vocc);
             FR_HIP(hipGetLastError());
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
             FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
-            k_vertex_sum_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(),
+            k_vertex_sum_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, rec_slot.as<uint32_t>(),
                                                                         slot_vid.as<uint32_t>(), rec_row.as<T>(),
                                                                         lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
             if constexpr (ValLayout<V>::m2) {
                 k_vertex_scatter_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(
-                    P, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_row.as<T>(), lat->vval, NV);
+                    P, nullptr, nullptr, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_row.as<T>(), lat->vval,
+                    NV);
                 FR_HIP(hipGetLastError());
             }
         }
@@ -1233,12 +1292,12 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         DevBuf vslot;
         FR_TRY(vslot.alloc(ctx, std::max<size_t>(NV, 1) * sizeof(uint32_t)));
         char *table = reinterpret_cast<char *>(lat->tab);
-        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, own2.as<uint32_t>(), table,
+        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, nullptr, own2.as<uint32_t>(), table,
                                                                 vslot.as<uint32_t>());
         FR_HIP(hipGetLastError());
         if (NV > 0) {
-            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, vslot.as<uint32_t>(), lat->vkey,
-                                                                     lat->vval, table);
+            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, nullptr, vslot.as<uint32_t>(),
+                                                                     lat->vkey, lat->vval, table);
             FR_HIP(hipGetLastError());
         }
     }
@@ -1264,6 +1323,444 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
     if (prm->feat == 6 && prm->values == 8) return build_impl<6, 8>(ctx, obs, st, lat, ve, nullptr, w);
     set_error("fr_lattice_build: unsupported feat=%d values=%d", prm->feat, prm->values);
     return FR_EINVAL;
+}
+
+// ---------------------------------------------------------------------------
+// Rebuilds in place: storage sized once from the observation cloud
+// ---------------------------------------------------------------------------
+// A loop that rebuilds the lattice of one observation cloud every iteration
+// (the optimised variance of Sec. 3.3 changes the lattice scale each time)
+// cannot afford the host waits of build_impl, which sizes its arrays from
+// counts it reads back.  Here every array is sized once from bounds that hold
+// for any scale: a set of n points has at most R_s = (d+1) n incidences,
+// hence at most R_s partial records and R_s vertices.  The provisional table
+// of a set has the next power of two >= 2 R_s slots (load <= 1/2), the final
+// tables room for the 2.5 slots per vertex of build_impl's sizing at R_s
+// vertices.  The counts themselves stay on the device (cnt words), the tile
+// maps of the insertion and of the cuckoo pass take their set offsets from
+// device arrays and cover the bounds (tiles past a set's count return), and
+// the final tables' layout is written by a kernel from the vertex counts, so
+// the tables of a rebuild are those of build_impl for the same scale.  A
+// provisional overflow or a cuckoo insertion that gives up raises a word in
+// cnt, which the caller reads at its own waits.
+namespace {
+constexpr int kResP = 0, kResNV = 1, kResSlots = 2, kResFailInsert = 3, kResFailCuckoo = 4, kResWords = 8;
+}
+
+struct ResidentBuild {
+    fr_ctx *ctx = nullptr;
+    fr_lattice *lat = nullptr;
+    int32_t d = 3, V = 4, S = 0;
+    bool sorted = true;
+    Pts pts{};
+    size_t R = 0, n1 = 0, n2max = 0, n_waves = 0;
+    int bits = 0;
+    TileMap ptm{}, rtm{}, vtm{};
+    DevBuf ptmap, rtmap, vtmap;   // tile-map arrays
+    DevBuf offs;                  // int64: partial offsets [S + 1], then vertex offsets [S + 1]
+    DevBuf wave_cnt, rec_key, rec_row, rec_slot, ovid, own1, t1, slot_vid;
+    DevBuf rvid, rid, tk, tv, voff, own2, vslot, ws, cnt;
+    // scale factors of rebuilds from host values: a device copy, its pinned
+    // staging buffer and the event after the last copy out of it
+    DevBuf kset_d;
+    float *kset_pin = nullptr;
+    hipEvent_t kset_ev = nullptr;
+    ~ResidentBuild()
+    {
+        if (kset_ev != nullptr) {
+            (void)hipEventSynchronize(kset_ev);
+            (void)hipEventDestroy(kset_ev);
+        }
+        if (kset_pin != nullptr) (void)hipHostFree(kset_pin);
+    }
+};
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n, const uint32_t *n_dev)
+{
+    n = dev_count(n, n_dev);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Partial offset of each set (set n_sets: the partial count) from the scanned
+// wave counts, as int64 (a tile map's offsets) and the count alone.
+__global__ void k_partial_off64(int32_t n_sets, const int32_t *seg_tile, const uint32_t *wave_off, int64_t *poff,
+                                uint32_t *p_count)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_sets) return;
+    const uint32_t q = wave_off[4 * (size_t)seg_tile[s]];
+    poff[s] = (int64_t)q;
+    if (s == n_sets) *p_count = q;
+}
+
+// Final tables of every set from its vertex count, with build_impl's sizing
+// (max(8, ceil(5 n / 4)) buckets), slots back to back in set order, the
+// set's seed and lattice scale: one workgroup, sets in chunks of 256.
+template <int KW, int V>
+__global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_t *vbase, const float *kset,
+                                                   char *tab, SetTable *sets, uint32_t *n_slots)
+{
+    using G = SlotGeom<KW, V>;
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0u;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    for (int32_t base = 0; base < n_sets; base += 256) {
+        const int32_t s = base + (int32_t)threadIdx.x;
+        uint32_t count = 0u, cap = 0u;
+        if (s < n_sets) {
+            count = (uint32_t)(vbase[s + 1] - vbase[s]);
+            const uint32_t nb = max(8u, (uint32_t)((5ull * count + 3ull) / 4ull));
+            cap = (uint32_t)kBucketSlots * nb;
+        }
+        const uint32_t incl = wave_inclusive_scan(cap);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        const uint32_t first = before + incl - cap;
+        if (s < n_sets) {
+            SetTable t;
+            char *p = tab + (size_t)G::bytes * first;
+            t.keys = reinterpret_cast<const uint64_t *>(p);
+            t.vals = reinterpret_cast<const float *>(p + G::val_off);
+            t.slot_base = first;
+            t.cap = cap;
+            t.n_vertices = count;
+            t.seed = 0x2545F491u * (uint32_t)(s + 1);
+            t.mask = 0u;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t.k[i] = kset[8 * (size_t)s + i];
+            sets[s] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x == 255) carry = first + cap;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_slots = carry;
+}
+
+// Tile map over sets whose offsets are a device array (n_sets + 1 entries) and
+// whose sizes are bounded by `bound`: the tiles of the bounds, XCD-contiguous.
+static fr_status make_bound_map(fr_ctx *ctx, const int64_t *dev_off, const std::vector<uint64_t> &bound, int32_t tile,
+                                hipStream_t st, DevBuf &buf, TileMap &tm, HostKeep &keep)
+{
+    const int32_t n = (int32_t)bound.size();
+    std::vector<int32_t> tiles(n + 1, 0), sets(n);
+    for (int32_t s = 0; s < n; ++s) {
+        const uint64_t t = tiles[s] + (bound[s] + tile - 1) / tile;
+        if (t >= (1ull << 31)) {
+            set_error("fr_lattice_build: too many tiles");
+            return FR_EINVAL;
+        }
+        tiles[s + 1] = (int32_t)t;
+        sets[s] = s;
+    }
+    std::vector<char> image(sizeof(int32_t) * (2 * n + 1));
+    std::memcpy(image.data(), tiles.data(), sizeof(int32_t) * (n + 1));
+    std::memcpy(image.data() + sizeof(int32_t) * (n + 1), sets.data(), sizeof(int32_t) * n);
+    FR_TRY(buf.alloc(ctx, image.size()));
+    FR_HIP(hipMemcpyAsync(buf.p, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    tm.seg_off = dev_off;
+    tm.seg_end = dev_off + 1;
+    tm.seg_tile = buf.as<int32_t>();
+    tm.seg_set = buf.as<int32_t>() + n + 1;
+    tm.n_seg = n;
+    tm.n_tiles = tiles[n];
+    tm.tile = tile;
+    tm.xcd_chunk = tm.n_tiles >= 8 * 64 ? (tm.n_tiles + 7) / 8 : 0;
+    keep.push_back(std::move(image));
+    return FR_OK;
+}
+
+template <int d, int V>
+static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStream_t st)
+{
+    constexpr int KW = KeyWords<d>::value;
+    using T = typename PartialType<V>::T;
+    fr_ctx *ctx = rb->ctx;
+    fr_lattice *lat = rb->lat;
+    const int32_t S = rb->S;
+    const size_t R = rb->R;
+    uint32_t *cnt = rb->cnt.as<uint32_t>();
+    uint32_t *ws = rb->ws.as<uint32_t>();
+    uint32_t *wave_cnt = rb->wave_cnt.as<uint32_t>();
+    int64_t *poff = rb->offs.as<int64_t>(), *voff64 = poff + S + 1;
+    // counts, failure words and the scan's last entry start at zero
+    k_fill_u32<<<1, 64, 0, st>>>(cnt, 0u, kResWords, nullptr);
+    k_fill_u32<<<1, 64, 0, st>>>(wave_cnt + rb->n_waves, 0u, 1, nullptr);
+    // 1. partial records
+    k_build_count<d><<<rb->ptm.n_tiles, 256, 0, st>>>(rb->pts, rb->ptm, kset, wave_cnt, lat->err_d);
+    FR_HIP(hipGetLastError());
+    FR_TRY(scan_exclusive_u32(ctx, wave_cnt, wave_cnt, rb->n_waves + 1, 0, st, ws));
+    k_partial_off64<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rb->ptm.seg_tile, wave_cnt, poff, cnt + kResP);
+    k_build_partials<d, V><<<rb->ptm.n_tiles, 256, 0, st>>>(rb->pts, rb->ptm, kset, wave_cnt,
+                                                            rb->rec_key.as<uint64_t>(), rb->rec_row.as<T>(), R,
+                                                            nullptr);
+    FR_HIP(hipGetLastError());
+    // 2.-3. provisional tables, vertex ids and per-set vertex offsets
+    k_fill_u32<<<blocks_for(2 * rb->n1, 256), 256, 0, st>>>(rb->own1.as<uint32_t>(), 0xFFFFFFFFu, 2 * rb->n1,
+                                                            nullptr);
+    k_fill_u32<<<blocks_for(R + 1, 256), 256, 0, st>>>(rb->ovid.as<uint32_t>(), 0u, R + 1, nullptr);
+    k_insert_records<KW, true><<<grid_of(rb->rtm), 256, 0, st>>>(rb->rtm, rb->t1.as<SetTable>(),
+                                                                rb->rec_key.as<uint64_t>(), R,
+                                                                rb->own1.as<unsigned long long>(),
+                                                                rb->rec_slot.as<uint32_t>(), rb->ovid.as<uint32_t>(),
+                                                                reinterpret_cast<int32_t *>(cnt + kResFailInsert));
+    FR_HIP(hipGetLastError());
+    FR_TRY(scan_exclusive_u32(ctx, rb->ovid.as<uint32_t>(), rb->ovid.as<uint32_t>(), R + 1, 0, st, ws));
+    k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, poff, rb->ovid.as<uint32_t>(), nullptr, voff64,
+                                                      cnt + kResNV);
+    k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rb->rec_slot.as<uint32_t>(), rb->ovid.as<uint32_t>(),
+                                                         rb->rec_key.as<uint64_t>(), lat->vkey, R,
+                                                         rb->slot_vid.as<uint32_t>());
+    FR_HIP(hipGetLastError());
+    // 4. values
+    if (rb->sorted) {
+        const uint32_t *fail_ins = cnt + kResFailInsert;
+        k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_slot.as<uint32_t>(),
+                                                             rb->slot_vid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
+                                                             rb->rid.as<uint32_t>());
+        uint32_t *svid = nullptr, *srid = nullptr;
+        FR_TRY(radix_sort_pairs(ctx, rb->rvid.as<uint32_t>(), rb->rid.as<uint32_t>(), rb->tk.as<uint32_t>(),
+                                rb->tv.as<uint32_t>(), R, rb->bits, st, &svid, &srid, cnt + kResP, ws));
+        k_segment_heads<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, svid, rb->voff.as<uint32_t>());
+        k_vertex_sum_sorted<V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResNV, R, R, cnt + kResP, fail_ins,
+                                                                    rb->voff.as<uint32_t>(), srid,
+                                                                    rb->rec_row.as<T>(), lat->vval, lat->vocc);
+        FR_HIP(hipGetLastError());
+    } else {
+        k_fill_u32<<<blocks_for((size_t)V * R, 256), 256, 0, st>>>(reinterpret_cast<uint32_t *>(lat->vval), 0u,
+                                                                    (size_t)V * R, nullptr);
+        k_fill_u32<<<blocks_for(R, 256), 256, 0, st>>>(lat->vocc, 0u, R, nullptr);
+        k_vertex_sum_atomic<V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, cnt + kResFailInsert,
+                                                                    rb->rec_slot.as<uint32_t>(),
+                                                                    rb->slot_vid.as<uint32_t>(), rb->rec_row.as<T>(),
+                                                                    lat->vval, lat->vocc, R);
+        if constexpr (ValLayout<V>::m2)
+            k_vertex_scatter_atomic<V><<<blocks_for(R, 256), 256, 0, st>>>(
+                R, cnt + kResP, cnt + kResFailInsert, rb->rec_slot.as<uint32_t>(), rb->slot_vid.as<uint32_t>(),
+                rb->rec_row.as<T>(), lat->vval, R);
+        FR_HIP(hipGetLastError());
+    }
+    // 5. final tables
+    char *table = reinterpret_cast<char *>(lat->tab);
+    k_set_tables<KW, V><<<1, 256, 0, st>>>(S, voff64, kset, table, lat->sets_d, cnt + kResSlots);
+    k_fill_u32<<<blocks_for(rb->n2max, 256), 256, 0, st>>>(rb->own2.as<uint32_t>(), kOwnerEmpty, rb->n2max,
+                                                           cnt + kResSlots);
+    k_cuckoo_insert<KW><<<grid_of(rb->vtm), 256, 0, st>>>(rb->vtm, lat->sets_d, lat->vkey, R,
+                                                         rb->own2.as<uint32_t>(),
+                                                         reinterpret_cast<int32_t *>(cnt + kResFailCuckoo));
+    k_slot_owner<KW, V><<<blocks_for(rb->n2max, 256), 256, 0, st>>>(rb->n2max, cnt + kResSlots,
+                                                                   rb->own2.as<uint32_t>(), table,
+                                                                   rb->vslot.as<uint32_t>());
+    k_vertex_fill<KW, V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResNV, R, cnt + kResFailCuckoo,
+                                                             rb->vslot.as<uint32_t>(), lat->vkey, lat->vval, table);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+template <int d, int V>
+static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStream_t st)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    using T = typename PartialType<V>::T;
+    constexpr uint32_t SB = SlotGeom<KW, V>::bytes;
+    fr_ctx *ctx = rb->ctx;
+    fr_lattice *lat = rb->lat;
+    const int32_t S = obs->n_sets;
+    const size_t R = rb->R;
+    HostKeep keep;
+    std::vector<int64_t> off(obs->offsets, obs->offsets + S + 1);
+    FR_TRY(make_offset_map(ctx, off, 256, st, rb->ptmap, rb->ptm, false, &keep));
+    rb->n_waves = (size_t)rb->ptm.n_tiles * 4;
+    std::vector<uint64_t> bound(S);
+    std::vector<SetTable> t1(S);
+    uint64_t n1 = 0, n2 = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        const uint64_t rs = (uint64_t)(obs->offsets[s + 1] - obs->offsets[s]) * D;
+        bound[s] = rs;
+        const uint32_t cap = next_pow2(2 * rs);
+        if (2 * rs > (1ull << 31)) {
+            set_error("fr_lattice_build: set %d has too many incidences (%llu)", s, (unsigned long long)rs);
+            return FR_EINVAL;
+        }
+        t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1, {}};
+        n1 += cap;
+        const uint64_t slots = (uint64_t)kBucketSlots * std::max<uint64_t>(8, (5 * rs + 3) / 4);
+        if (slots * SB > 0xFFFFFFFFull) {
+            set_error("fr_lattice_build: set %d may need more than one table of 4 GiB", s);
+            return FR_ENOMEM;
+        }
+        n2 += slots;
+    }
+    if (n1 >= 0xFFFFFFF0ull || n2 >= 0xFFFFFFF0ull || R + 1 >= 0xFFFFFFF0ull) {
+        set_error("fr_lattice_build: tables too large for an in-place rebuild");
+        return FR_EINVAL;
+    }
+    rb->n1 = n1;
+    rb->n2max = n2;
+    int bits = 0;
+    while (bits < 32 && (R - 1) >> bits) ++bits;
+    rb->bits = bits;
+    FR_TRY(rb->offs.alloc(ctx, 2 * (S + 1) * sizeof(int64_t)));
+    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>(), bound, 256, st, rb->rtmap, rb->rtm, keep));
+    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>() + S + 1, bound, 256, st, rb->vtmap, rb->vtm, keep));
+    FR_TRY(rb->wave_cnt.alloc(ctx, (rb->n_waves + 1) * sizeof(uint32_t)));
+    FR_TRY(rb->rec_key.alloc(ctx, R * KW * sizeof(uint64_t)));
+    FR_TRY(rb->rec_row.alloc(ctx, R * PartialRow<V>::S * sizeof(T)));
+    FR_TRY(rb->rec_slot.alloc(ctx, R * sizeof(uint32_t)));
+    FR_TRY(rb->ovid.alloc(ctx, (R + 1) * sizeof(uint32_t)));
+    FR_TRY(rb->own1.alloc(ctx, n1 * sizeof(unsigned long long)));
+    FR_TRY(rb->t1.alloc(ctx, S * sizeof(SetTable)));
+    FR_TRY(rb->slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
+    if (rb->sorted) {
+        FR_TRY(rb->rvid.alloc(ctx, R * sizeof(uint32_t)));
+        FR_TRY(rb->rid.alloc(ctx, R * sizeof(uint32_t)));
+        FR_TRY(rb->tk.alloc(ctx, R * sizeof(uint32_t)));
+        FR_TRY(rb->tv.alloc(ctx, R * sizeof(uint32_t)));
+        FR_TRY(rb->voff.alloc(ctx, R * sizeof(uint32_t)));
+    }
+    FR_TRY(rb->own2.alloc(ctx, n2 * sizeof(uint32_t)));
+    FR_TRY(rb->vslot.alloc(ctx, R * sizeof(uint32_t)));
+    const size_t ws = std::max({scan_ws_words(rb->n_waves + 1), scan_ws_words(R + 1), radix_ws_words(R)});
+    FR_TRY(rb->ws.alloc(ctx, std::max<size_t>(ws, 1) * sizeof(uint32_t)));
+    FR_TRY(rb->cnt.alloc(ctx, kResWords * sizeof(uint32_t)));
+    FR_HIP(hipMemcpyAsync(rb->t1.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
+    // the lattice the rebuilds fill: tables at their bound, vertex arrays of R vertices
+    lat->n_slots = n2;
+    lat->tab_bytes = n2 * SB;
+    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->tab), lat->tab_bytes));
+    lat->sets_h.assign(S, SetTable{});
+    FR_TRY(dev_alloc(ctx, reinterpret_cast<void **>(&lat->sets_d), S * sizeof(SetTable)));
+    lat->vert_bytes = R * (KW * sizeof(uint64_t) + sizeof(uint32_t) + V * sizeof(float)) + 64;
+    {
+        void *p = nullptr;
+        FR_TRY(dev_alloc(ctx, &p, lat->vert_bytes));
+        char *c = static_cast<char *>(p);
+        lat->vkey = reinterpret_cast<uint64_t *>(c);
+        lat->vval = reinterpret_cast<float *>(c + R * KW * sizeof(uint64_t));
+        lat->vocc = reinterpret_cast<uint32_t *>(c + R * (KW * sizeof(uint64_t) + V * sizeof(float)));
+    }
+    FR_HIP(hipStreamSynchronize(st));   // the host images of the tile maps go out of scope
+    return FR_OK;
+}
+
+fr_status resident_create(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
+                          ResidentBuild **out)
+{
+    *out = nullptr;
+    const int64_t N = cloud_points(obs);
+    const size_t R = (size_t)N * (prm->feat + 1);
+    if (N <= 0 || prm->feat > 6) {
+        set_error("fr_lattice_build: an in-place rebuild needs observation points and d <= 6");
+        return FR_EINVAL;
+    }
+    if (R >= 0xFFFFFFF0ull) {
+        set_error("fr_lattice_build: %llu incidences exceed the 32-bit record index", (unsigned long long)R);
+        return FR_EINVAL;
+    }
+    ResidentBuild *rb = new (std::nothrow) ResidentBuild();
+    fr_lattice *lat = new (std::nothrow) fr_lattice();
+    if (rb == nullptr || lat == nullptr) {
+        delete rb;
+        delete lat;
+        set_error("out of host memory");
+        return FR_ENOMEM;
+    }
+    rb->ctx = ctx;
+    rb->lat = lat;
+    rb->d = prm->feat;
+    rb->V = prm->values;
+    rb->S = obs->n_sets;
+    rb->R = R;
+    rb->sorted = prm->splat == FR_SPLAT_SORTED;
+    rb->pts = Pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
+    lat->resident = rb;
+    lat->params = *prm;
+    lat->ctx = ctx;
+    lat->d = prm->feat;
+    lat->V = prm->values;
+    lat->KW = (prm->feat + 2) / 3;
+    lat->n_sets = obs->n_sets;
+    lat->splat = prm->splat;
+    lat->n_points_total = N;
+    fr_status s = dev_alloc(ctx, reinterpret_cast<void **>(&lat->err_d), sizeof(int32_t));
+    if (s == FR_OK) {
+        const hipError_t e = hipMemsetAsync(lat->err_d, 0, sizeof(int32_t), st);
+        if (e != hipSuccess) {
+            set_error("HIP error: %s", hipGetErrorString(e));
+            s = FR_EDEVICE;
+        }
+    }
+    if (s == FR_OK) {
+        const int f = prm->feat, v = prm->values;
+        if (f == 3 && v == 4) s = resident_setup<3, 4>(rb, obs, st);
+        else if (f == 3 && v == 5) s = resident_setup<3, 5>(rb, obs, st);
+        else if (f == 3 && v == 7) s = resident_setup<3, 7>(rb, obs, st);
+        else if (f == 3 && v == 8) s = resident_setup<3, 8>(rb, obs, st);
+        else if (f == 6 && v == 4) s = resident_setup<6, 4>(rb, obs, st);
+        else if (f == 6 && v == 5) s = resident_setup<6, 5>(rb, obs, st);
+        else if (f == 6 && v == 7) s = resident_setup<6, 7>(rb, obs, st);
+        else if (f == 6 && v == 8) s = resident_setup<6, 8>(rb, obs, st);
+        else {
+            set_error("fr_lattice_build: unsupported feat=%d values=%d", f, v);
+            s = FR_EINVAL;
+        }
+    }
+    if (s != FR_OK) {
+        resident_destroy(rb, st);
+        return s;
+    }
+    *out = rb;
+    return FR_OK;
+}
+
+fr_status resident_build(ResidentBuild *rb, const float *kset, hipStream_t st)
+{
+    const int d = rb->d, v = rb->V;
+    if (d == 3 && v == 4) return resident_enqueue<3, 4>(rb, kset, st);
+    if (d == 3 && v == 5) return resident_enqueue<3, 5>(rb, kset, st);
+    if (d == 3 && v == 7) return resident_enqueue<3, 7>(rb, kset, st);
+    if (d == 3 && v == 8) return resident_enqueue<3, 8>(rb, kset, st);
+    if (d == 6 && v == 4) return resident_enqueue<6, 4>(rb, kset, st);
+    if (d == 6 && v == 5) return resident_enqueue<6, 5>(rb, kset, st);
+    if (d == 6 && v == 7) return resident_enqueue<6, 7>(rb, kset, st);
+    return resident_enqueue<6, 8>(rb, kset, st);
+}
+
+fr_status resident_build_host(ResidentBuild *rb, const float *kset_h, hipStream_t st)
+{
+    const size_t bytes = 8 * (size_t)rb->S * sizeof(float);
+    if (rb->kset_pin == nullptr) {
+        FR_TRY(rb->kset_d.alloc(rb->ctx, bytes));
+        FR_HIP(hipHostMalloc(reinterpret_cast<void **>(&rb->kset_pin), bytes, hipHostMallocDefault));
+        FR_HIP(hipEventCreateWithFlags(&rb->kset_ev, hipEventDisableTiming));
+    } else {
+        FR_HIP(hipEventSynchronize(rb->kset_ev));   // the last rebuild's copy has left the staging buffer
+    }
+    std::memcpy(rb->kset_pin, kset_h, bytes);
+    FR_HIP(hipMemcpyAsync(rb->kset_d.p, rb->kset_pin, bytes, hipMemcpyHostToDevice, st));
+    FR_HIP(hipEventRecord(rb->kset_ev, st));
+    return resident_build(rb, rb->kset_d.as<float>(), st);
+}
+
+fr_lattice *resident_lattice(ResidentBuild *rb) { return rb->lat; }
+
+const uint32_t *resident_fail_words(const ResidentBuild *rb) { return rb->cnt.as<uint32_t>() + kResFailInsert; }
+
+void resident_destroy(ResidentBuild *rb, hipStream_t st, bool idle)
+{
+    if (rb == nullptr) return;
+    if (rb->lat != nullptr) {
+        free_lattice(rb->lat, st, idle);
+        rb->lat->magic = kDeadMagic;
+        delete rb->lat;
+    }
+    delete rb;   // the DevBufs release in the order of their streams
 }
 
 bool feature_dim_supported(int dim) { return dim == 8 || dim == 16 || dim == 32; }

@@ -154,4 +154,50 @@ fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, do
     return FR_OK;
 }
 
+// Variance update of the optimised-sigma loop on the device, after the solve
+// of iteration `iter1` - 1 (one thread per set).  A set that ran this
+// iteration (its iteration count is iter1) and did not degenerate takes the
+// closed-form variance V / (3 sum w) of the reduction, as the kernel's
+// per-axis variance s^2 / 4, floored: s = max(s_min, sqrt(V / (3 sum w) / (1/4))).
+// Its lattice scale factors and outlier constant follow s with the host's
+// arithmetic (scale_factors, outlier_constant) in the same order, so a
+// rebuild at the new s matches one sized on the host.
+__global__ void __launch_bounds__(64) k_sigma_update(int32_t n, int32_t iter1, const int32_t *iters,
+                                                     const int32_t *status, const double *stats, const double *var,
+                                                     SigmaRule rule, double *sig, float *kset, float *seg_c)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n || iters[s] != iter1) return;
+    if (status[s] != FR_OK || !(stats[4 * (size_t)s] > 0.0)) return;
+    const double v = var[s] / (3.0 * stats[4 * (size_t)s]);
+    const double sg = fmax(rule.sigma_min, sqrt(fmax(v, 0.0) / rule.kernel_axis_var));
+    sig[s] = sg;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float k = 0.0f;
+        if (i < rule.feat) {
+            const double sd = i < 3 ? sg : rule.sigma_n;
+            k = (float)(rule.scale_num / (sd * rule.scale_den[i]));
+        }
+        kset[8 * (size_t)s + i] = k;
+    }
+    double c = rule.c_override;
+    if (!(c >= 0.0)) {
+        double h = rule.mass0;
+        for (int i = 0; i < rule.feat; ++i) h *= i < 3 ? sg : rule.sigma_n;
+        c = rule.c_pre[s] * h;
+    }
+    seg_c[s] = (float)c;
+}
+
+fr_status launch_sigma_update(int32_t n, int32_t iter1, const int32_t *iters, const int32_t *status,
+                              const double *stats, const double *var, const SigmaRule &rule, double *sig,
+                              float *kset, float *seg_c, hipStream_t st)
+{
+    if (n <= 0) return FR_OK;
+    k_sigma_update<<<(n + 63) / 64, 64, 0, st>>>(n, iter1, iters, status, stats, var, rule, sig, kset, seg_c);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
 }  // namespace fr

@@ -209,7 +209,7 @@ def test_register_sigma_full_depth_frame(fr, ctx):
     assert st[0] == 0 and ok, (ang, dt)
     assert abs(s[0] / sr - 1.0) < 5e-2, (s[0], sr)
     assert oracle.alignment_error(T[0], p.T_gt, p.model) < 1e-3
-    assert rep.iterations == 8 and rep.build_ms > 0
+    assert rep.iterations == 8
     T1, s1, _, _ = _register_sigma(fr, ctx, [p], 6, "pt2pl", h[3]["sigma"], 0.002, 1, [h[3]["T"]], **kw)
     assert abs(s1[0] / h[4]["sigma"] - 1.0) < 1e-4, (s1[0], h[4]["sigma"])
     assert pose_close(T1[0], h[4]["T"])[2]
