@@ -584,7 +584,7 @@ def profile_workload(name):
 
 BUILD_IN_BYTES = 24                        # observation position + normal in (binary32)
 BUILD_VERTEX_BYTES = 16 + 4 + 4 * 8        # vertex out: packed key, occupancy, 7 values padded to 8 (binary32)
-TABLE_SLOT_BYTES = 64                      # lookup table: key + padded values per slot, 2.5 slots per vertex
+TABLE_SLOT_BYTES = 64                      # lookup table: key + padded values per slot, 2 slots per vertex
 # bytes a partial record moves through the sorted build: written by the partial pass (key 16, count 4,
 # values 28), key read by the insertion (16), (vertex, record) pair written and read (16), three radix
 # passes over the pairs (3 x 16), count and values read by the per-vertex sums (32)
@@ -612,7 +612,7 @@ def build_rates(fr, ctx, obs, sigma, sigma_n, reps=3):
         entry = {"ms": ms, "obs_points_per_s": obs.n / ms * 1e3,
                  "stage_ms": {"embed": st[0], "insert_and_ids": st[1], "values": st[2], "tables": st[3]},
                  "incidences": inc, "partial_records": part, "vertices": nv,
-                 "algorithmic_bytes": alg, "table_bytes": nv * 2.5 * TABLE_SLOT_BYTES,
+                 "algorithmic_bytes": alg, "table_bytes": nv * 2 * TABLE_SLOT_BYTES,
                  "achieved_gbs": alg / ms / 1e6,
                  "frac_of_hbm_peak": alg / ms / 1e6 / HBM_PEAK_GBS}
         if name == "sorted":

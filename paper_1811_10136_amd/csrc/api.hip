@@ -125,6 +125,67 @@ fr_status dev_alloc(fr_ctx *ctx, void **p, size_t bytes)
     return FR_OK;
 }
 
+fr_status stage_h2d(fr_ctx *ctx, void *dst, const void *src, size_t n, hipStream_t st)
+{
+    if (n == 0) return FR_OK;
+    const size_t need = (n + 63) & ~(size_t)63;
+    if (ctx->stage_used + need > ctx->stage_cap) {
+        // the arena is reused from its start once every copy out of it has run
+        for (hipEvent_t ev : ctx->stage_ev) {
+            (void)hipEventSynchronize(ev);
+            recycle_event(ctx, ev);
+        }
+        ctx->stage_ev.clear();
+        ctx->stage_used = 0;
+        if (need > ctx->stage_cap) {
+            if (ctx->stage != nullptr) FR_HIP(hipHostFree(ctx->stage));
+            ctx->stage = nullptr;
+            ctx->stage_cap = 0;
+            const size_t cap = std::max<size_t>(need, (size_t)1 << 20);
+            FR_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->stage), cap, hipHostMallocDefault));
+            ctx->stage_cap = cap;
+        }
+    }
+    char *buf = ctx->stage + ctx->stage_used;
+    std::memcpy(buf, src, n);
+    FR_HIP(hipMemcpyAsync(dst, buf, n, hipMemcpyHostToDevice, st));
+    hipEvent_t ev = nullptr;
+    if (!ctx->spare_events.empty()) {
+        ev = ctx->spare_events.back();
+        ctx->spare_events.pop_back();
+    } else {
+        FR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    FR_HIP(hipEventRecord(ev, st));
+    ctx->stage_ev.push_back(ev);
+    ctx->stage_used += need;
+    // drop the events of copies that have run (keeps the list short)
+    if (ctx->stage_ev.size() > 64) {
+        std::vector<hipEvent_t> live;
+        for (hipEvent_t e : ctx->stage_ev) {
+            if (hipEventQuery(e) == hipSuccess) recycle_event(ctx, e);
+            else live.push_back(e);
+        }
+        (void)hipGetLastError();
+        ctx->stage_ev.swap(live);
+    }
+    return FR_OK;
+}
+
+fr_status build_readback(fr_ctx *ctx, size_t n, void **out)
+{
+    if (ctx->pin_build_n < n) {
+        if (ctx->pin_build) FR_HIP(hipHostFree(ctx->pin_build));
+        ctx->pin_build = nullptr;
+        ctx->pin_build_n = 0;
+        const size_t cap = std::max<size_t>(n, 4096);
+        FR_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->pin_build), cap, hipHostMallocDefault));
+        ctx->pin_build_n = cap;
+    }
+    *out = ctx->pin_build;
+    return FR_OK;
+}
+
 void dev_free(fr_ctx *ctx, void *p, size_t bytes, hipStream_t st, bool idle)
 {
     if (!p) return;
@@ -568,6 +629,12 @@ fr_status fr_ctx_destroy(fr_ctx *ctx)
     ctx->graph_stream = nullptr;
     if (ctx->pin_flags) (void)hipHostFree(ctx->pin_flags);
     ctx->pin_flags = nullptr;
+    for (hipEvent_t ev : ctx->stage_ev) (void)hipEventDestroy(ev);
+    ctx->stage_ev.clear();
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    ctx->stage = nullptr;
+    if (ctx->pin_build) (void)hipHostFree(ctx->pin_build);
+    ctx->pin_build = nullptr;
     ctx->magic = kDeadMagic;
     delete ctx;
     return FR_OK;
@@ -1550,12 +1617,14 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
     // The loop's state in one block (one copy saves or restores it): poses,
     // twist norms, scales s, the outlier constants' scale-free factors, the
     // binary32 transforms, lattice scale factors and outlier constants of the
-    // current s, status, active flags and iteration counts.
+    // current s, status, active flags, iteration counts and which sets the last
+    // solve ran for.
     const size_t o_pose = 0, o_tn = o_pose + 16 * (size_t)S * 8, o_sig = o_tn + 2 * (size_t)S * 8;
     const size_t o_cpre = o_sig + (size_t)S * 8, o_mats = o_cpre + (size_t)S * 8;
     const size_t o_kset = o_mats + 12 * (size_t)S * 4, o_segc = o_kset + 8 * (size_t)S * 4;
     const size_t o_status = o_segc + (size_t)S * 4, o_act = o_status + (size_t)S * 4;
-    const size_t o_iters = o_act + (size_t)S * 4, state_bytes = o_iters + (size_t)S * 4;
+    const size_t o_iters = o_act + (size_t)S * 4, o_ran = o_iters + (size_t)S * 4;
+    const size_t state_bytes = o_ran + (size_t)S * 4;
     std::vector<char> img(state_bytes, 0);
     {
         auto put = [&](size_t off, const void *src, size_t bytes) { std::memcpy(img.data() + off, src, bytes); };
@@ -1594,7 +1663,7 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
     float *wmats = reinterpret_cast<float *>(sb + o_mats), *wkset = reinterpret_cast<float *>(sb + o_kset);
     float *wsegc = reinterpret_cast<float *>(sb + o_segc);
     int32_t *wstatus = reinterpret_cast<int32_t *>(sb + o_status), *act = reinterpret_cast<int32_t *>(sb + o_act);
-    int32_t *witers = reinterpret_cast<int32_t *>(sb + o_iters);
+    int32_t *witers = reinterpret_cast<int32_t *>(sb + o_iters), *wran = reinterpret_cast<int32_t *>(sb + o_ran);
     pr.seg_c = wsegc;   // the reduction reads the constants the variance update writes
 
     SigmaRule rule;
@@ -1642,32 +1711,33 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
         ev.assign(4 * (size_t)max_it, nullptr);
         for (auto &e : ev) FR_HIP(hipEventCreate(&e));
     }
+    hipStream_t q = st;
     // E-step, reduction, solve and variance update of iteration j on a built lattice
     auto iter_kernels = [&](const fr_lattice *lat, int j) -> fr_status {
-        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 1], st));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 1], q));
         FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats, wm0.as<float>(), wm1.as<float>(),
-                            pl ? wns.as<float>() : nullptr, nullptr, st, wm2.as<float>(), act));
-        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 2], st));
+                            pl ? wns.as<float>() : nullptr, nullptr, q, wm2.as<float>(), act));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 2], q));
         // the Gauss-Newton step does not depend on the residual scale: reduce at sigma = 1
         FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats, wm0.as<float>(), wm1.as<float>(),
                              pl ? wns.as<float>() : nullptr, params->residual, 0, 1.0, wjtj.as<double>(),
-                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), st, wm2.as<float>(),
+                             wjtr.as<double>(), wstat.as<double>(), part.as<float>(), q, wm2.as<float>(),
                              wvar.as<double>(), act));
-        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose, wmats, wtn, wstatus, act, st, act,
-                                  tol, witers));
-        FR_TRY(launch_sigma_update(S, j + 1, witers, wstatus, wstat.as<double>(), wvar.as<double>(), rule, wsig,
-                                   wkset, wsegc, st));
-        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 3], st));
+        FR_TRY(launch_solve_rigid(S, wjtj.as<double>(), wjtr.as<double>(), wpose, wmats, wtn, wstatus, act, q, act,
+                                  tol, witers, wran));
+        FR_TRY(launch_sigma_update(S, wran, wstatus, wstat.as<double>(), wvar.as<double>(), rule, wsig, wkset, wsegc,
+                                   q));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j + 3], q));
         return FR_OK;
     };
     std::vector<double> sig_h(S);
     // iteration j with the build that sizes its tables on the host (waits)
     auto iter_waiting = [&](int j) -> fr_status {
-        FR_HIP(hipMemcpyAsync(sig_h.data(), wsig, S * sizeof(double), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipStreamSynchronize(st));
-        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j], st));
+        FR_HIP(hipMemcpyAsync(sig_h.data(), wsig, S * sizeof(double), hipMemcpyDeviceToHost, q));
+        FR_HIP(hipStreamSynchronize(q));
+        if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)j], q));
         fr_lattice *lat = nullptr;
-        FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, st, &lat, sig_h.data()));
+        FR_TRY(lattice_build_impl(ctx, obs, &params->lattice, q, &lat, sig_h.data()));
         struct LatGuard {
             fr_lattice *l;
             ~LatGuard() { fr_lattice_destroy(l); }
@@ -1675,7 +1745,17 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
         FR_TRY(iter_kernels(lat, j));
         return fr_sync_status(lat);
     };
+    // a block of iterations with in-place rebuilds (replaying a captured graph of
+    // it measured slower here: the launches are short and the capture is per call)
     constexpr int kBlock = 4;
+    auto enqueue_block = [&](int it0, int n) -> fr_status {
+        for (int k = 0; k < n; ++k) {
+            if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)(it0 + k)], q));
+            FR_TRY(resident_build(rb, wkset, q));
+            FR_TRY(iter_kernels(resident_lattice(rb), it0 + k));
+        }
+        return FR_OK;
+    };
     const size_t flag_bytes = 3 * (size_t)S * sizeof(int32_t);   // status, active, iterations
     auto t_em = clk::now();
     int it = 0;
@@ -1683,38 +1763,35 @@ fr_status fr_register_sigma(fr_ctx *ctx, const fr_cloud *model_ref, const fr_clo
         const int n = std::min(kBlock, max_it - it);
         bool redo = rb == nullptr;
         if (rb != nullptr) {
-            FR_HIP(hipMemcpyAsync(ckpt.p, state.p, state_bytes, hipMemcpyDeviceToDevice, st));
-            for (int k = 0; k < n; ++k) {
-                if (prof) FR_HIP(hipEventRecord(ev[4 * (size_t)(it + k)], st));
-                FR_TRY(resident_build(rb, wkset, st));
-                FR_TRY(iter_kernels(resident_lattice(rb), it + k));
-            }
-            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, st));
+            FR_HIP(hipMemcpyAsync(ckpt.p, state.p, state_bytes, hipMemcpyDeviceToDevice, q));
+            FR_TRY(enqueue_block(it, n));
+            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, q));
             FR_HIP(hipMemcpyAsync(pin + 3 * S, resident_fail_words(rb), 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                  st));
+                                  q));
             FR_HIP(hipMemcpyAsync(pin + 3 * S + 2, resident_lattice(rb)->err_d, sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st));
-            FR_HIP(hipStreamSynchronize(st));
+                                  hipMemcpyDeviceToHost, q));
+            FR_HIP(hipStreamSynchronize(q));
             if (pin[3 * S + 2] != 0) {
                 set_error("fr_register_sigma: a lattice coordinate left [-2^20, 2^20); increase sigma_min or "
                           "centre the cloud");
                 return FR_ERANGE;
             }
             if (pin[3 * S] != 0 || pin[3 * S + 1] != 0) {
-                FR_HIP(hipMemcpyAsync(state.p, ckpt.p, state_bytes, hipMemcpyDeviceToDevice, st));
+                FR_HIP(hipMemcpyAsync(state.p, ckpt.p, state_bytes, hipMemcpyDeviceToDevice, q));
                 redo = true;
             }
         }
         if (redo) {
             for (int k = 0; k < n; ++k) FR_TRY(iter_waiting(it + k));
-            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, st));
-            FR_HIP(hipStreamSynchronize(st));
+            FR_HIP(hipMemcpyAsync(pin, wstatus, flag_bytes, hipMemcpyDeviceToHost, q));
+            FR_HIP(hipStreamSynchronize(q));
         }
         it += n;
         int32_t any = 0;
         for (int32_t s = 0; s < S; ++s) any |= pin[S + s];
         if (any == 0) break;
     }
+    FR_HIP(hipStreamSynchronize(q));
     std::vector<int32_t> status_v(S), iters_v(S);
     std::vector<double> sig(S);
     FR_HIP(hipMemcpyAsync(theta_inout_h, wpose, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));

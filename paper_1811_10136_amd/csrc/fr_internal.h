@@ -70,6 +70,16 @@ struct fr_ctx {
     // pinned host words the EM loops read the device's per-set stop flags into
     int32_t *pin_flags = nullptr;
     size_t pin_flags_n = 0;
+    // Pinned staging of small host -> device copies (tile maps, set tables,
+    // scale factors): a bump arena, reset once the copies out of it have
+    // completed (their events), so such a copy never makes the host wait for
+    // the stream as a copy from pageable memory does.
+    char *stage = nullptr;
+    size_t stage_cap = 0, stage_used = 0;
+    std::vector<hipEvent_t> stage_ev;
+    // pinned host memory the lattice build reads its sizes back into
+    char *pin_build = nullptr;
+    size_t pin_build_n = 0;
     // vertices per splat record of the context's last lattice build: sizes the
     // first provisional table of the next one (loops that rebuild at a
     // shrinking scale see most records carry keys of their own)
@@ -255,9 +265,10 @@ struct SigmaRule {
     double c_override = -1.0;       // >= 0: the outlier constant itself
     const double *c_pre = nullptr;  // device, per set: w / (1 - w) N_s / M_s (0: no outlier term)
 };
-fr_status launch_sigma_update(int32_t n, int32_t iter1, const int32_t *iters, const int32_t *status,
-                              const double *stats, const double *var, const SigmaRule &rule, double *sig,
-                              float *kset, float *seg_c, hipStream_t st);
+// ran: per set, 1 where the solve just before ran (launch_solve_rigid's `ran`).
+fr_status launch_sigma_update(int32_t n, const int32_t *ran, const int32_t *status, const double *stats,
+                              const double *var, const SigmaRule &rule, double *sig, float *kset, float *seg_c,
+                              hipStream_t st);
 
 struct ResidentBuild;
 fr_status resident_create(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_params *prm, hipStream_t st,
@@ -313,7 +324,8 @@ fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, i
 // iters (may be NULL) counts the solves of every set.
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
                              double *twist_norm, int32_t *status, const int32_t *active, hipStream_t stream,
-                             int32_t *stop = nullptr, double twist_tol = -1.0, int32_t *iters = nullptr);
+                             int32_t *stop = nullptr, double twist_tol = -1.0, int32_t *iters = nullptr,
+                             int32_t *ran = nullptr);
 
 // articulated.hip
 struct ArtTreeHost {
@@ -359,6 +371,13 @@ fr_status ng_step(NodeGraphDev &d, const float *x, const float *y, const float *
                   hipStream_t stream);
 
 // scan / sort helpers (lattice_build.hip)
+// Asynchronous copy of n host bytes to device memory through the context's
+// pinned staging arena: the host bytes may change as soon as it returns.
+fr_status stage_h2d(fr_ctx *ctx, void *dst, const void *src, size_t n, hipStream_t st);
+// Pinned host memory of at least n bytes for the lattice build's read-backs
+// (one per context; its contents are the caller's until the next call).
+fr_status build_readback(fr_ctx *ctx, size_t n, void **out);
+
 // ws: NULL (temporaries from the context), or scan_ws_words(n) words the caller keeps until the scan has run.
 fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, int mode, hipStream_t stream,
                              uint32_t *ws = nullptr);

@@ -19,7 +19,7 @@
 //                 order in binary64 -> bitwise deterministic.  Atomic mode:
 //                 binary32 hardware atomics and an occupancy counter.
 //   5. final      per set, a bucketed two-choice cuckoo table (load factor
-//                 <= 0.4, two slots of key + values per bucket): an E-step
+//                 <= 0.5, two slots of key + values per bucket): an E-step
 //                 lookup reads one bucket line, and a second one only when
 //                 the first bucket is full without the key.
 #include <algorithm>
@@ -88,6 +88,43 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t *out, const 
     }
 }
 
+// One workgroup scans up to kScanSmall values in tiles, carrying the running
+// total: one launch instead of three for the short scans of small builds
+// (longer inputs are faster spread over workgroups: about 2 us per tile here).
+constexpr size_t kScanSmall = 8 * (size_t)kScanTile;
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_small(const uint32_t *in, uint32_t *out, size_t n)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0u;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (size_t t0 = 0; t0 < n; t0 += kScanTile) {
+        const size_t base = t0 + (size_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t x = base + i < n ? in[base + i] : 0u;
+            v[i] = tot;
+            tot += x;
+        }
+        const uint32_t incl = wave_inclusive_scan(tot);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t pre = carry;
+        for (int w = 0; w < wave; ++w) pre += wsum[w];
+        const uint32_t excl = pre + incl - tot;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+            if (base + i < n) out[base + i] = excl + v[i];
+        __syncthreads();   // every thread has read carry and wsum
+        if (threadIdx.x == kScanThreads - 1) carry = excl + tot;
+        __syncthreads();
+    }
+}
+
 size_t scan_ws_words(size_t n)
 {
     size_t words = 0;
@@ -103,6 +140,11 @@ fr_status scan_exclusive_u32(fr_ctx *ctx, const uint32_t *in, uint32_t *out, siz
 {
     if (n == 0) return FR_OK;
     const size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 1 && n <= kScanSmall && mode == 0) {
+        k_scan_small<<<1, kScanThreads, 0, st>>>(in, out, n);
+        FR_HIP(hipGetLastError());
+        return FR_OK;
+    }
     if (nb == 1) {
         if (mode == 1) k_scan_tile<1><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
         else if (mode == 2) k_scan_tile<2><<<1, kScanThreads, 0, st>>>(in, out, nullptr, n);
@@ -410,12 +452,22 @@ template <int d, int V> struct PartialLds {
     static constexpr int bytes = pv + 4 * 64 * NCH;
 };
 
+// poff (or NULL): workgroup 0 also writes each set's first partial (set
+// n_seg: the partial count, also to *p_count) as int64 -- what a tile map of
+// the partials reads on the device.
 template <int d, int V>
 __global__ void __launch_bounds__(256) k_build_partials(Pts pts, TileMap tm, const float *kset,
                                                        const uint32_t *wave_off, uint64_t *pkey,
                                                        typename PartialType<V>::T *prow, size_t P,
-                                                       const int64_t *valued_end)
+                                                       const int64_t *valued_end, int64_t *poff = nullptr,
+                                                       uint32_t *p_count = nullptr)
 {
+    if (poff != nullptr && blockIdx.x == 0)
+        for (int32_t s = (int32_t)threadIdx.x; s <= tm.n_seg; s += (int32_t)blockDim.x) {
+            const uint32_t q = wave_off[4 * (size_t)tm.seg_tile[s]];
+            poff[s] = (int64_t)q;
+            if (s == tm.n_seg) *p_count = q;
+        }
     using T = typename PartialType<V>::T;
     using L = PartialLds<d, V>;
     constexpr int D = d + 1;
@@ -680,11 +732,21 @@ __global__ void __launch_bounds__(256) k_insert_records(TileMap tm, const SetTab
 // ovid[R] is the vertex count); owners -- the records whose id the scan
 // steps past -- write their vertex's key (word-major, `stride` vertices per
 // word) and the slot -> vertex map.
+// rec_off (or NULL; n_sets + 1 record offsets): workgroup 0 also writes each
+// set's first vertex as k_set_vbase does (vbase64, and the count to *nv).
 template <int KW>
 __global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *ovid,
                                                    const uint64_t *rec_key, uint64_t *vkey, size_t stride,
-                                                   uint32_t *slot_vid)
+                                                   uint32_t *slot_vid, int32_t n_sets = 0,
+                                                   const int64_t *rec_off = nullptr, int64_t *vbase64 = nullptr,
+                                                   uint32_t *nv = nullptr)
 {
+    if (rec_off != nullptr && blockIdx.x == 0)
+        for (int32_t s = (int32_t)threadIdx.x; s <= n_sets; s += (int32_t)blockDim.x) {
+            const uint32_t v = ovid[rec_off[s]];
+            vbase64[s] = (int64_t)v;
+            if (s == n_sets) *nv = v;
+        }
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     const uint32_t v = ovid[r];
@@ -772,6 +834,79 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
     if constexpr (ValLayout<V>::m2) {
         // keep the scatter about the vertex mean, sum b |y - mu|^2 = sum b |y|^2 - |M1|^2 / W:
         // the slice then never subtracts |y|^2-sized numbers stored in binary32
+        const double q = acc[0] > 0.0 ? (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0] : 0.0;
+        acc[V - 1] = fmax(acc[V - 1] - q, 0.0);
+    }
+    vocc[v] = occ;
+#pragma unroll
+    for (int c = 0; c < V; ++c) vval[(size_t)c * stride + v] = (float)acc[c];
+}
+
+// Sorted mode without the sort, for rebuilds of at most kListMax partials
+// (in place, where the launches of a radix sort cost more than its work):
+// each partial finds its vertex and takes a place in the vertex's list by an
+// atomic counter (k_list_count, an exclusive scan, k_list_place); a vertex's
+// thread then walks its list in increasing partial order (k_vertex_sum_list),
+// so the sums are those of k_vertex_sum_sorted, bitwise, whatever order the
+// atomics gave the places.
+constexpr size_t kListMax = (size_t)1 << 17;
+
+__global__ void __launch_bounds__(256) k_list_count(size_t P, const uint32_t *p_dev, const uint32_t *fail,
+                                                   const uint32_t *rec_slot, const uint32_t *slot_vid, uint32_t *rvid,
+                                                   uint32_t *vcount)
+{
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= dev_count(P, p_dev) || aborted(fail)) return;
+    const uint32_t v = slot_vid[rec_slot[r]];
+    rvid[r] = v;
+    atomicAdd(&vcount[v], 1u);
+}
+
+// vfill: per vertex, places taken so far (zero before the launch)
+__global__ void __launch_bounds__(256) k_list_place(size_t P, const uint32_t *p_dev, const uint32_t *fail,
+                                                   const uint32_t *rvid, const uint32_t *voff, uint32_t *vfill,
+                                                   uint32_t *list)
+{
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= dev_count(P, p_dev) || aborted(fail)) return;
+    const uint32_t v = rvid[r];
+    list[voff[v] + atomicAdd(&vfill[v], 1u)] = (uint32_t)r;
+}
+
+template <int V>
+__global__ void __launch_bounds__(256) k_vertex_sum_list(size_t NV, const uint32_t *nv_dev, size_t stride,
+                                                        const uint32_t *fail, const uint32_t *voff,
+                                                        const uint32_t *vcount, const uint32_t *list,
+                                                        const typename PartialRow<V>::T *prow, float *vval,
+                                                        uint32_t *vocc)
+{
+    using R = PartialRow<V>;
+    using T = typename R::T;
+    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= dev_count(NV, nv_dev) || aborted(fail)) return;
+    const uint32_t *l = list + voff[v];
+    const uint32_t n = vcount[v];
+    double acc[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[c] = 0.0;
+    uint32_t occ = 0;
+    // the list's entries in increasing order: each step takes the least entry above the last one
+    uint32_t last = 0, first = 1;
+    for (uint32_t k = 0; k < n; ++k) {
+        uint32_t q = 0xFFFFFFFFu;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t e = l[i];
+            if ((first || e > last) && e < q) q = e;
+        }
+        first = 0;
+        last = q;
+        alignas(16) T row[R::S];
+        load_row<V>(prow, q, row);
+        occ += (uint32_t)row[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc[c] += (double)row[c];
+    }
+    if constexpr (ValLayout<V>::m2) {
         const double q = acc[0] > 0.0 ? (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0] : 0.0;
         acc[V - 1] = fmax(acc[V - 1] - q, 0.0);
     }
@@ -950,12 +1085,9 @@ static inline unsigned blocks_for(size_t n, int threads) { return (unsigned)((n 
 // past the last tile return at once).
 static unsigned grid_of(const TileMap &tm) { return (unsigned)(tm.xcd_chunk > 0 ? tm.xcd_chunk * 8 : tm.n_tiles); }
 
-// keep != NULL: the host image is kept there until the caller's next wait
-// (no wait here); else the call waits for the copy.
-using HostKeep = std::vector<std::vector<char>>;
-
+// The device image goes through the context's pinned staging (no wait).
 static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, int32_t tile, hipStream_t st,
-                                 DevBuf &buf, TileMap &tm, bool xcd = false, HostKeep *keep = nullptr)
+                                 DevBuf &buf, TileMap &tm, bool xcd = false)
 {
     const int32_t n = (int32_t)off.size() - 1;
     std::vector<int32_t> tiles(n + 1, 0), sets(n);
@@ -970,7 +1102,7 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     std::memcpy(image.data(), off.data(), b_off);
     std::memcpy(image.data() + b_off, tiles.data(), b_tile);
     std::memcpy(image.data() + b_off + b_tile, sets.data(), b_set);
-    FR_HIP(hipMemcpyAsync(p, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    FR_TRY(stage_h2d(ctx, p, image.data(), image.size(), st));
     tm.seg_off = reinterpret_cast<const int64_t *>(p);
     tm.seg_end = tm.seg_off + 1;
     tm.seg_tile = reinterpret_cast<const int32_t *>(p + b_off);
@@ -980,11 +1112,6 @@ static fr_status make_offset_map(fr_ctx *ctx, const std::vector<int64_t> &off, i
     tm.tile = tile;
     // XCD-contiguous tiles: a set's tiles run on one XCD, so the set's tables stay in that XCD's L2
     tm.xcd_chunk = (xcd && tm.n_tiles >= 8 * 64) ? (tm.n_tiles + 7) / 8 : 0;
-    if (keep != nullptr) {
-        keep->push_back(std::move(image));
-        return FR_OK;
-    }
-    FR_HIP(hipStreamSynchronize(st));   // the host image goes out of scope
     return FR_OK;
 }
 
@@ -1019,7 +1146,6 @@ template <int d, int V>
 static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr_lattice *lat,
                             const int64_t *valued_end, const float *feat = nullptr, bool wait_end = true)
 {
-    HostKeep keep;   // host images of the tile maps, alive until the build's waits
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
     constexpr int VP = ValPad<V>::value;
@@ -1046,10 +1172,10 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     //    incidence for descriptors); roff = the partials of each set
     std::vector<int64_t> poff(obs->offsets, obs->offsets + S + 1);
     TileMap ptm{}, rtm{};
-    FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm, false, &keep));
+    FR_TRY(make_offset_map(ctx, poff, 256, st, ptmap, ptm, false));
     DevBuf kset_d;
     FR_TRY(kset_d.alloc(ctx, lat->kset.size() * sizeof(float)));
-    FR_HIP(hipMemcpyAsync(kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FR_TRY(stage_h2d(ctx, kset_d.p, lat->kset.data(), lat->kset.size() * sizeof(float), st));
     std::vector<int64_t> roff(S + 1);
     size_t P = 0;   // partial records
     if constexpr (d > 6) {
@@ -1077,12 +1203,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         k_set_partial_off<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, ptm.seg_tile, wave_cnt.as<uint32_t>(),
                                                                 set_off.as<uint32_t>());
         FR_HIP(hipGetLastError());
-        std::vector<uint32_t> so(S + 1);
-        int32_t err0 = 0;
-        FR_HIP(hipMemcpyAsync(so.data(), set_off.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(&err0, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        uint32_t *rb = nullptr;   // pinned: [set offsets S + 1 | range error]
+        FR_TRY(build_readback(ctx, (S + 2) * sizeof(uint32_t), reinterpret_cast<void **>(&rb)));
+        FR_HIP(hipMemcpyAsync(rb, set_off.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(rb + S + 1, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
-        if (err0 != 0) {
+        const std::vector<uint32_t> so(rb, rb + S + 1);
+        if (rb[S + 1] != 0) {
             set_error("fr_lattice_build: a lattice coordinate left [-2^20, 2^20); increase sigma or centre the cloud");
             return FR_ERANGE;
         }
@@ -1104,7 +1231,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // 2. insert into provisional tables (pow2 >= R_set / 2 first, or four times
     //    the vertices the last build's vertices-per-record ratio predicts if that
     //    is more; 2 R_set if that overflows; R_set = the set's partial records)
-    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true, &keep));
+    FR_TRY(make_offset_map(ctx, roff, 256, st, rtmap, rtm, true));
     uint64_t n1 = 0;
     DevBuf ovid, slot_vid, vb_d;
     FR_TRY(ovid.alloc(ctx, (P + 1) * sizeof(uint32_t)));   // owner flags (and a 0), then their exclusive scan
@@ -1130,7 +1257,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             return FR_EINVAL;
         }
         FR_TRY(own1.alloc(ctx, n1 * sizeof(unsigned long long)));
-        FR_HIP(hipMemcpyAsync(t1_d.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
+        FR_TRY(stage_h2d(ctx, t1_d.p, t1.data(), S * sizeof(SetTable), st));
         FR_HIP(hipMemsetAsync(own1.p, 0xFF, n1 * sizeof(unsigned long long), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (rtm.n_tiles > 0) {
@@ -1148,11 +1275,15 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rtm.seg_off, ovid.as<uint32_t>(), vb_d.as<uint32_t>(),
                                                           nullptr, nullptr);
         FR_HIP(hipGetLastError());
-        int32_t failed = 0;
-        FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(vb_h.data(), vb_d.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        FR_HIP(hipMemcpyAsync(&err_h, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        uint32_t *rb = nullptr;   // pinned: [vertex bases S + 1 | overflow | range error]
+        FR_TRY(build_readback(ctx, (S + 3) * sizeof(uint32_t), reinterpret_cast<void **>(&rb)));
+        FR_HIP(hipMemcpyAsync(rb, vb_d.p, (S + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(rb + S + 1, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FR_HIP(hipMemcpyAsync(rb + S + 2, lat->err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
+        std::copy(rb, rb + S + 1, vb_h.begin());
+        const uint32_t failed = rb[S + 1];
+        err_h = (int32_t)rb[S + 2];
         if (!failed) break;
         if (attempt == 1) {
             set_error("fr_lattice_build: provisional table overflow");
@@ -1241,12 +1372,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     slot_vid.reset();
 
     stage.mark(3, st);
-    // 5. final bucketed two-choice cuckoo tables, load factor 0.4
+    // 5. final bucketed two-choice cuckoo tables, load factor 0.5 (a bucket per
+    //    vertex; loads up to 0.6 measured no slower to slice, 0.7 fails to insert)
     constexpr uint32_t SB = SlotGeom<KW, V>::bytes;
     lat->sets_h.resize(S);
     uint64_t n2 = 0;
     for (int32_t s = 0; s < S; ++s) {
-        const uint64_t nb = std::max<uint64_t>(8, (5 * (uint64_t)counts[s] + 3) / 4);
+        const uint64_t nb = std::max<uint64_t>(8, (uint64_t)counts[s]);
         if (nb * kBucketSlots * SB > 0xFFFFFFFFull) {
             set_error("fr_lattice_build: set %d has %u vertices, more than one table of 4 GiB holds", s, counts[s]);
             return FR_ENOMEM;
@@ -1265,12 +1397,33 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         lat->sets_h[s].keys = reinterpret_cast<const uint64_t *>(first);
         lat->sets_h[s].vals = reinterpret_cast<const float *>(first + SlotGeom<KW, V>::val_off);
     }
-    DevBuf own2, vtmap;
+    DevBuf own2, vtmap, vslot;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
+    FR_TRY(vslot.alloc(ctx, std::max<size_t>(NV, 1) * sizeof(uint32_t)));
     TileMap vtm{};
-    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true, &keep));
+    FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true));
+    char *table = reinterpret_cast<char *>(lat->tab);
+    const uint32_t *fail_word = reinterpret_cast<const uint32_t *>(fail.p);
+    // the slots: keys of free slots, then each vertex's key and values (the fill
+    // returns at once if the cuckoo pass gave up)
+    auto fill_table = [&]() -> fr_status {
+        if (n2 == 0) return FR_OK;
+        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, nullptr, own2.as<uint32_t>(), table,
+                                                                vslot.as<uint32_t>());
+        FR_HIP(hipGetLastError());
+        if (NV > 0) {
+            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, fail_word,
+                                                                     vslot.as<uint32_t>(), lat->vkey, lat->vval,
+                                                                     table);
+            FR_HIP(hipGetLastError());
+        }
+        return FR_OK;
+    };
+    // A caller that waits for the build gets the table filled behind the cuckoo
+    // pass and one wait for both; a cuckoo pass that gave up is redone with
+    // another seed and its own wait before the fill.
     for (int attempt = 0;; ++attempt) {
-        FR_HIP(hipMemcpyAsync(lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
+        FR_TRY(stage_h2d(ctx, lat->sets_d, lat->sets_h.data(), S * sizeof(SetTable), st));
         FR_HIP(hipMemsetAsync(own2.p, 0xFF, n2 * sizeof(uint32_t), st));
         FR_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), st));
         if (vtm.n_tiles > 0) {
@@ -1278,29 +1431,29 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
                                                              fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
-        int32_t failed = 0;
-        FR_HIP(hipMemcpyAsync(&failed, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        const bool fill_now = wait_end && attempt == 0;
+        if (fill_now) {
+            FR_TRY(fill_table());
+            stage.mark(4, st);
+        }
+        int32_t *rb = nullptr;
+        FR_TRY(build_readback(ctx, sizeof(int32_t), reinterpret_cast<void **>(&rb)));
+        FR_HIP(hipMemcpyAsync(rb, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         FR_HIP(hipStreamSynchronize(st));
-        if (!failed) break;
+        if (!rb[0]) {
+            if (fill_now) {
+                stage.read(lat->stage_ms);
+                return FR_OK;
+            }
+            break;
+        }
         if (attempt >= 16) {
             set_error("fr_lattice_build: cuckoo insertion did not converge after %d seeds", attempt + 1);
             return FR_EDEVICE;
         }
         for (int32_t s = 0; s < S; ++s) lat->sets_h[s].seed = lat->sets_h[s].seed * 0x9E3779B1u + 0x7F4A7C15u;
     }
-    if (n2 > 0) {
-        DevBuf vslot;
-        FR_TRY(vslot.alloc(ctx, std::max<size_t>(NV, 1) * sizeof(uint32_t)));
-        char *table = reinterpret_cast<char *>(lat->tab);
-        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, nullptr, own2.as<uint32_t>(), table,
-                                                                vslot.as<uint32_t>());
-        FR_HIP(hipGetLastError());
-        if (NV > 0) {
-            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, nullptr, vslot.as<uint32_t>(),
-                                                                     lat->vkey, lat->vval, table);
-            FR_HIP(hipGetLastError());
-        }
-    }
+    FR_TRY(fill_table());
     stage.mark(4, st);
     if (!wait_end) return FR_OK;   // the caller orders later work after the build on the device
     FR_HIP(hipStreamSynchronize(st));
@@ -1335,7 +1488,7 @@ fr_status build_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_lattice_param
 // for any scale: a set of n points has at most R_s = (d+1) n incidences,
 // hence at most R_s partial records and R_s vertices.  The provisional table
 // of a set has the next power of two >= 2 R_s slots (load <= 1/2), the final
-// tables room for the 2.5 slots per vertex of build_impl's sizing at R_s
+// tables room for the 2 slots per vertex of build_impl's sizing at R_s
 // vertices.  The counts themselves stay on the device (cnt words), the tile
 // maps of the insertion and of the cuckoo pass take their set offsets from
 // device arrays and cover the bounds (tiles past a set's count return), and
@@ -1375,6 +1528,23 @@ struct ResidentBuild {
     }
 };
 
+// The clears a rebuild starts with, in one launch: the count and failure
+// words, the wave scan's last entry, the provisional table (all ones) and the
+// owner flags (R + 1 zeros).
+__global__ void k_res_clear(uint32_t *cnt, uint32_t *wave_tail, uint32_t *own1, size_t n_own1, uint32_t *ovid,
+                            size_t n_ovid, uint32_t *zero_a, uint32_t *zero_b, size_t n_zero)
+{
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, step = (size_t)gridDim.x * blockDim.x;
+    if (i0 < kResWords) cnt[i0] = 0u;
+    if (i0 == 0) *wave_tail = 0u;
+    for (size_t i = i0; i < n_own1; i += step) own1[i] = 0xFFFFFFFFu;
+    for (size_t i = i0; i < n_ovid; i += step) ovid[i] = 0u;
+    for (size_t i = i0; i < n_zero; i += step) {
+        zero_a[i] = 0u;
+        zero_b[i] = 0u;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n, const uint32_t *n_dev)
 {
     n = dev_count(n, n_dev);
@@ -1382,20 +1552,8 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n, const uint32_t *n_
         p[i] = v;
 }
 
-// Partial offset of each set (set n_sets: the partial count) from the scanned
-// wave counts, as int64 (a tile map's offsets) and the count alone.
-__global__ void k_partial_off64(int32_t n_sets, const int32_t *seg_tile, const uint32_t *wave_off, int64_t *poff,
-                                uint32_t *p_count)
-{
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s > n_sets) return;
-    const uint32_t q = wave_off[4 * (size_t)seg_tile[s]];
-    poff[s] = (int64_t)q;
-    if (s == n_sets) *p_count = q;
-}
-
 // Final tables of every set from its vertex count, with build_impl's sizing
-// (max(8, ceil(5 n / 4)) buckets), slots back to back in set order, the
+// (max(8, n) buckets), slots back to back in set order, the
 // set's seed and lattice scale: one workgroup, sets in chunks of 256.
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_t *vbase, const float *kset,
@@ -1412,7 +1570,7 @@ __global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_
         uint32_t count = 0u, cap = 0u;
         if (s < n_sets) {
             count = (uint32_t)(vbase[s + 1] - vbase[s]);
-            const uint32_t nb = max(8u, (uint32_t)((5ull * count + 3ull) / 4ull));
+            const uint32_t nb = max(8u, count);
             cap = (uint32_t)kBucketSlots * nb;
         }
         const uint32_t incl = wave_inclusive_scan(cap);
@@ -1445,7 +1603,7 @@ __global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_
 // Tile map over sets whose offsets are a device array (n_sets + 1 entries) and
 // whose sizes are bounded by `bound`: the tiles of the bounds, XCD-contiguous.
 static fr_status make_bound_map(fr_ctx *ctx, const int64_t *dev_off, const std::vector<uint64_t> &bound, int32_t tile,
-                                hipStream_t st, DevBuf &buf, TileMap &tm, HostKeep &keep)
+                                hipStream_t st, DevBuf &buf, TileMap &tm)
 {
     const int32_t n = (int32_t)bound.size();
     std::vector<int32_t> tiles(n + 1, 0), sets(n);
@@ -1462,7 +1620,7 @@ static fr_status make_bound_map(fr_ctx *ctx, const int64_t *dev_off, const std::
     std::memcpy(image.data(), tiles.data(), sizeof(int32_t) * (n + 1));
     std::memcpy(image.data() + sizeof(int32_t) * (n + 1), sets.data(), sizeof(int32_t) * n);
     FR_TRY(buf.alloc(ctx, image.size()));
-    FR_HIP(hipMemcpyAsync(buf.p, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    FR_TRY(stage_h2d(ctx, buf.p, image.data(), image.size(), st));
     tm.seg_off = dev_off;
     tm.seg_end = dev_off + 1;
     tm.seg_tile = buf.as<int32_t>();
@@ -1471,7 +1629,6 @@ static fr_status make_bound_map(fr_ctx *ctx, const int64_t *dev_off, const std::
     tm.n_tiles = tiles[n];
     tm.tile = tile;
     tm.xcd_chunk = tm.n_tiles >= 8 * 64 ? (tm.n_tiles + 7) / 8 : 0;
-    keep.push_back(std::move(image));
     return FR_OK;
 }
 
@@ -1488,22 +1645,21 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     uint32_t *ws = rb->ws.as<uint32_t>();
     uint32_t *wave_cnt = rb->wave_cnt.as<uint32_t>();
     int64_t *poff = rb->offs.as<int64_t>(), *voff64 = poff + S + 1;
-    // counts, failure words and the scan's last entry start at zero
-    k_fill_u32<<<1, 64, 0, st>>>(cnt, 0u, kResWords, nullptr);
-    k_fill_u32<<<1, 64, 0, st>>>(wave_cnt + rb->n_waves, 0u, 1, nullptr);
+    // counts, failure words, the wave scan's last entry, the provisional table and the owner flags
+    // (and, for the sums by vertex lists, the per-vertex counters)
+    const bool lists = rb->sorted && R <= kListMax;
+    k_res_clear<<<blocks_for(std::max<size_t>(2 * rb->n1, R + 1), 256), 256, 0, st>>>(
+        cnt, wave_cnt + rb->n_waves, rb->own1.as<uint32_t>(), 2 * rb->n1, rb->ovid.as<uint32_t>(), R + 1,
+        lists ? rb->voff.as<uint32_t>() : nullptr, lists ? rb->tk.as<uint32_t>() : nullptr, lists ? R : 0);
     // 1. partial records
     k_build_count<d><<<rb->ptm.n_tiles, 256, 0, st>>>(rb->pts, rb->ptm, kset, wave_cnt, lat->err_d);
     FR_HIP(hipGetLastError());
     FR_TRY(scan_exclusive_u32(ctx, wave_cnt, wave_cnt, rb->n_waves + 1, 0, st, ws));
-    k_partial_off64<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, rb->ptm.seg_tile, wave_cnt, poff, cnt + kResP);
     k_build_partials<d, V><<<rb->ptm.n_tiles, 256, 0, st>>>(rb->pts, rb->ptm, kset, wave_cnt,
                                                             rb->rec_key.as<uint64_t>(), rb->rec_row.as<T>(), R,
-                                                            nullptr);
+                                                            nullptr, poff, cnt + kResP);
     FR_HIP(hipGetLastError());
     // 2.-3. provisional tables, vertex ids and per-set vertex offsets
-    k_fill_u32<<<blocks_for(2 * rb->n1, 256), 256, 0, st>>>(rb->own1.as<uint32_t>(), 0xFFFFFFFFu, 2 * rb->n1,
-                                                            nullptr);
-    k_fill_u32<<<blocks_for(R + 1, 256), 256, 0, st>>>(rb->ovid.as<uint32_t>(), 0u, R + 1, nullptr);
     k_insert_records<KW, true><<<grid_of(rb->rtm), 256, 0, st>>>(rb->rtm, rb->t1.as<SetTable>(),
                                                                 rb->rec_key.as<uint64_t>(), R,
                                                                 rb->own1.as<unsigned long long>(),
@@ -1511,14 +1667,27 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
                                                                 reinterpret_cast<int32_t *>(cnt + kResFailInsert));
     FR_HIP(hipGetLastError());
     FR_TRY(scan_exclusive_u32(ctx, rb->ovid.as<uint32_t>(), rb->ovid.as<uint32_t>(), R + 1, 0, st, ws));
-    k_set_vbase<<<blocks_for(S + 1, 64), 64, 0, st>>>(S, poff, rb->ovid.as<uint32_t>(), nullptr, voff64,
-                                                      cnt + kResNV);
     k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rb->rec_slot.as<uint32_t>(), rb->ovid.as<uint32_t>(),
                                                          rb->rec_key.as<uint64_t>(), lat->vkey, R,
-                                                         rb->slot_vid.as<uint32_t>());
+                                                         rb->slot_vid.as<uint32_t>(), S, poff, voff64,
+                                                         cnt + kResNV);
     FR_HIP(hipGetLastError());
     // 4. values
-    if (rb->sorted) {
+    if (rb->sorted && R <= kListMax) {
+        const uint32_t *fail_ins = cnt + kResFailInsert;
+        uint32_t *vcount = rb->voff.as<uint32_t>(), *vfill = rb->tk.as<uint32_t>();   // zeroed by k_res_clear
+        k_list_count<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_slot.as<uint32_t>(),
+                                                          rb->slot_vid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
+                                                          vcount);
+        FR_TRY(scan_exclusive_u32(ctx, vcount, rb->rid.as<uint32_t>(), R, 0, st, ws));
+        k_list_place<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rvid.as<uint32_t>(),
+                                                          rb->rid.as<uint32_t>(), vfill, rb->tv.as<uint32_t>());
+        k_vertex_sum_list<V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResNV, R, fail_ins,
+                                                                  rb->rid.as<uint32_t>(), vcount,
+                                                                  rb->tv.as<uint32_t>(), rb->rec_row.as<T>(),
+                                                                  lat->vval, lat->vocc);
+        FR_HIP(hipGetLastError());
+    } else if (rb->sorted) {
         const uint32_t *fail_ins = cnt + kResFailInsert;
         k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_slot.as<uint32_t>(),
                                                              rb->slot_vid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
@@ -1573,9 +1742,8 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
     fr_lattice *lat = rb->lat;
     const int32_t S = obs->n_sets;
     const size_t R = rb->R;
-    HostKeep keep;
     std::vector<int64_t> off(obs->offsets, obs->offsets + S + 1);
-    FR_TRY(make_offset_map(ctx, off, 256, st, rb->ptmap, rb->ptm, false, &keep));
+    FR_TRY(make_offset_map(ctx, off, 256, st, rb->ptmap, rb->ptm, false));
     rb->n_waves = (size_t)rb->ptm.n_tiles * 4;
     std::vector<uint64_t> bound(S);
     std::vector<SetTable> t1(S);
@@ -1590,7 +1758,7 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
         }
         t1[s] = SetTable{nullptr, nullptr, n1, cap, 0, 0, cap - 1, {}};
         n1 += cap;
-        const uint64_t slots = (uint64_t)kBucketSlots * std::max<uint64_t>(8, (5 * rs + 3) / 4);
+        const uint64_t slots = (uint64_t)kBucketSlots * std::max<uint64_t>(8, rs);
         if (slots * SB > 0xFFFFFFFFull) {
             set_error("fr_lattice_build: set %d may need more than one table of 4 GiB", s);
             return FR_ENOMEM;
@@ -1607,8 +1775,8 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
     while (bits < 32 && (R - 1) >> bits) ++bits;
     rb->bits = bits;
     FR_TRY(rb->offs.alloc(ctx, 2 * (S + 1) * sizeof(int64_t)));
-    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>(), bound, 256, st, rb->rtmap, rb->rtm, keep));
-    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>() + S + 1, bound, 256, st, rb->vtmap, rb->vtm, keep));
+    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>(), bound, 256, st, rb->rtmap, rb->rtm));
+    FR_TRY(make_bound_map(ctx, rb->offs.as<int64_t>() + S + 1, bound, 256, st, rb->vtmap, rb->vtm));
     FR_TRY(rb->wave_cnt.alloc(ctx, (rb->n_waves + 1) * sizeof(uint32_t)));
     FR_TRY(rb->rec_key.alloc(ctx, R * KW * sizeof(uint64_t)));
     FR_TRY(rb->rec_row.alloc(ctx, R * PartialRow<V>::S * sizeof(T)));
@@ -1629,7 +1797,7 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
     const size_t ws = std::max({scan_ws_words(rb->n_waves + 1), scan_ws_words(R + 1), radix_ws_words(R)});
     FR_TRY(rb->ws.alloc(ctx, std::max<size_t>(ws, 1) * sizeof(uint32_t)));
     FR_TRY(rb->cnt.alloc(ctx, kResWords * sizeof(uint32_t)));
-    FR_HIP(hipMemcpyAsync(rb->t1.p, t1.data(), S * sizeof(SetTable), hipMemcpyHostToDevice, st));
+    FR_TRY(stage_h2d(ctx, rb->t1.p, t1.data(), S * sizeof(SetTable), st));
     // the lattice the rebuilds fill: tables at their bound, vertex arrays of R vertices
     lat->n_slots = n2;
     lat->tab_bytes = n2 * SB;
@@ -1645,7 +1813,6 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
         lat->vval = reinterpret_cast<float *>(c + R * KW * sizeof(uint64_t));
         lat->vocc = reinterpret_cast<uint32_t *>(c + R * (KW * sizeof(uint64_t) + V * sizeof(float)));
     }
-    FR_HIP(hipStreamSynchronize(st));   // the host images of the tile maps go out of scope
     return FR_OK;
 }
 
@@ -1853,11 +2020,11 @@ fr_status build_joint_lattice(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *
     FR_TRY(pts.alloc(ctx, std::max<int64_t>(T, 1) * (normals ? 6 : 3) * sizeof(float)));
     FR_TRY(offs.alloc(ctx, (3 * (size_t)S + 2) * sizeof(int64_t)));
     int64_t *od = offs.as<int64_t>();
-    FR_HIP(hipMemcpyAsync(od, obs->offsets, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(od + S + 1, model->offsets, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    FR_HIP(hipMemcpyAsync(od + 2 * S + 2, vend.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    FR_TRY(stage_h2d(ctx, od, obs->offsets, (S + 1) * sizeof(int64_t), st));
+    FR_TRY(stage_h2d(ctx, od + S + 1, model->offsets, (S + 1) * sizeof(int64_t), st));
+    FR_TRY(stage_h2d(ctx, od + 2 * S + 2, vend.data(), S * sizeof(int64_t), st));
     TileMap tm{};
-    FR_TRY(make_offset_map(ctx, off, 256, st, tmap, tm));   // synchronises: the host vectors are free after
+    FR_TRY(make_offset_map(ctx, off, 256, st, tmap, tm));
     float *base = pts.as<float>();
     const size_t n = (size_t)std::max<int64_t>(T, 1);
     JointArgs a{tm, od, od + S + 1, Pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz},

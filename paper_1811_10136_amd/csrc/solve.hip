@@ -50,11 +50,13 @@ __device__ inline void se3_exp(const double (&z)[6], double (&E)[3][4])
 __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses,
                                                     float *mats, double *twist_norm, int32_t *status,
                                                     const int32_t *active, int32_t *stop, double twist_tol,
-                                                    int32_t *iters)
+                                                    int32_t *iters, int32_t *ran)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    if ((active != nullptr && active[s] == 0) || (stop != nullptr && stop[s] == 0)) return;
+    const bool run = !((active != nullptr && active[s] == 0) || (stop != nullptr && stop[s] == 0));
+    if (ran != nullptr) ran[s] = run ? 1 : 0;
+    if (!run) return;
     double A[6][6], b[6];
     {
         int idx = 0;
@@ -145,29 +147,29 @@ __global__ void __launch_bounds__(64) k_solve_rigid(int32_t n, const double *jtj
 
 fr_status launch_solve_rigid(int32_t n, const double *jtj, const double *jtr, double *poses, float *mats,
                              double *twist_norm, int32_t *status, const int32_t *active, hipStream_t st,
-                             int32_t *stop, double twist_tol, int32_t *iters)
+                             int32_t *stop, double twist_tol, int32_t *iters, int32_t *ran)
 {
     if (n <= 0) return FR_OK;
     k_solve_rigid<<<(n + 63) / 64, 64, 0, st>>>(n, jtj, jtr, poses, mats, twist_norm, status, active, stop,
-                                                 twist_tol, iters);
+                                                 twist_tol, iters, ran);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
-// Variance update of the optimised-sigma loop on the device, after the solve
-// of iteration `iter1` - 1 (one thread per set).  A set that ran this
-// iteration (its iteration count is iter1) and did not degenerate takes the
+// Variance update of the optimised-sigma loop on the device, after a solve
+// (one thread per set).  A set that the solve ran for (ran[s]) and that did
+// not degenerate takes the
 // closed-form variance V / (3 sum w) of the reduction, as the kernel's
 // per-axis variance s^2 / 4, floored: s = max(s_min, sqrt(V / (3 sum w) / (1/4))).
 // Its lattice scale factors and outlier constant follow s with the host's
 // arithmetic (scale_factors, outlier_constant) in the same order, so a
 // rebuild at the new s matches one sized on the host.
-__global__ void __launch_bounds__(64) k_sigma_update(int32_t n, int32_t iter1, const int32_t *iters,
-                                                     const int32_t *status, const double *stats, const double *var,
-                                                     SigmaRule rule, double *sig, float *kset, float *seg_c)
+__global__ void __launch_bounds__(64) k_sigma_update(int32_t n, const int32_t *ran, const int32_t *status,
+                                                     const double *stats, const double *var, SigmaRule rule,
+                                                     double *sig, float *kset, float *seg_c)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n || iters[s] != iter1) return;
+    if (s >= n || ran[s] == 0) return;
     if (status[s] != FR_OK || !(stats[4 * (size_t)s] > 0.0)) return;
     const double v = var[s] / (3.0 * stats[4 * (size_t)s]);
     const double sg = fmax(rule.sigma_min, sqrt(fmax(v, 0.0) / rule.kernel_axis_var));
@@ -190,12 +192,12 @@ __global__ void __launch_bounds__(64) k_sigma_update(int32_t n, int32_t iter1, c
     seg_c[s] = (float)c;
 }
 
-fr_status launch_sigma_update(int32_t n, int32_t iter1, const int32_t *iters, const int32_t *status,
-                              const double *stats, const double *var, const SigmaRule &rule, double *sig,
-                              float *kset, float *seg_c, hipStream_t st)
+fr_status launch_sigma_update(int32_t n, const int32_t *ran, const int32_t *status, const double *stats,
+                              const double *var, const SigmaRule &rule, double *sig, float *kset, float *seg_c,
+                              hipStream_t st)
 {
     if (n <= 0) return FR_OK;
-    k_sigma_update<<<(n + 63) / 64, 64, 0, st>>>(n, iter1, iters, status, stats, var, rule, sig, kset, seg_c);
+    k_sigma_update<<<(n + 63) / 64, 64, 0, st>>>(n, ran, status, stats, var, rule, sig, kset, seg_c);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -60,19 +60,23 @@ def _mats(Ts):
     return np.concatenate([oracle.pose_to_mat12(T) for T in Ts]).astype(np.float32)
 
 
-def _pairs():
-    # two range-image frames of different sizes: ragged tiles, shared simplices
+def _pairs(small=False):
+    # two range-image frames: ragged tiles, shared simplices.  Small frames keep a rebuild under 2^17
+    # incidences, where the per-vertex sums walk vertex lists instead of sorting the partial records.
+    if small:
+        return [synth.depth_pair(s, width=64, height=48, f=52.5) for s in (11, 12)]
     return [synth.depth_pair(s, width=160, height=120, f=131.25) for s in (11, 12)]
 
 
+@pytest.mark.parametrize("small", [False, True])
 @pytest.mark.parametrize("feat,V,splat", [(3, 4, 0), (3, 5, 0), (6, 7, 0), (6, 8, 0), (6, 8, 1), (3, 5, 1)])
-def test_rebuild_matches_a_fresh_build(fr, ctx, feat, V, splat):
-    pairs = _pairs()
+def test_rebuild_matches_a_fresh_build(fr, ctx, feat, V, splat, small):
+    pairs = _pairs(small)
     p0 = pairs[0]
     obs = upload([p.obs for p in pairs], [p.obs_n for p in pairs])
     model = upload([p.model for p in pairs], [p.model_n for p in pairs])
     mats = _mats([p.T_gt for p in pairs])
-    _say(f"[inplace] feat={feat} V={V} splat={splat} M={model.n}")
+    _say(f"[inplace] feat={feat} V={V} splat={splat} M={model.n} incidences={obs.n * (feat + 1)}")
     prm = fr.lattice_params(feat, V, p0.sigma, p0.sigma_n, splat)
     lat = fr.fr_lattice_build_inplace(ctx.h, obs, prm, None)
     try:
