@@ -80,6 +80,8 @@ def test_articulated_register_parity(fr, ctx):
     ref = art.register_articulated(tree, p.model, p.model_n, bo, p.obs, p.obs_n, feat=6, residual="pt2pl",
                                    sigma=p.sigma, sigma_n=p.sigma_n, w=p.w, iters=p.iters, theta0=p.extra["theta0"])
     assert st == 0 and rep.iterations == p.iters
+    print(f"[error] articulated, 32 DOF, {p.iters} iterations: joint angles, max |d theta| (rad): "
+          f"{np.abs(th - ref).max():.3e} (bound 1e-04)", flush=True)
     assert np.abs(th - ref).max() < 1e-4, np.abs(th - ref).max()
     # and it is a registration: the error to the ground truth shrinks
     assert np.abs(th - p.extra["theta_gt"]).mean() < np.abs(p.extra["theta0"] - p.extra["theta_gt"]).mean()
