@@ -1332,6 +1332,29 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     Plan pe, pr;
     FR_TRY(make_plan(ctx, model_ref, nullptr, kEstepTile, cset.data(), st, pe));
     if (!fused) FR_TRY(make_plan(ctx, model_ref, nullptr, 1024, cset.data(), st, pr));
+    // The uncustomised filter rebuilds its joint lattice every iteration: in
+    // place (storage sized once, no host wait) for joint clouds of up to 2^20
+    // incidences, with a fall-back to the host-sized build for the rest of the
+    // call if a rebuild overflows.  Larger ones keep the host-sized build:
+    // there the storage's bounds (every incidence a vertex) cost the blur's
+    // passes over the bound of the slots more than the waits they save (one
+    // 640x480 frame: 1.1 against 0.94 ms per rebuild).
+    constexpr int64_t kInplaceJointMax = (int64_t)1 << 20;
+    ResidentBuild *rbj = nullptr;
+    DevBuf kset_j;
+    const int64_t joint_incidences = (cloud_points(obs) + M) * (params->lattice.feat + 1);
+    if (blurred && joint_incidences > 0 && joint_incidences <= kInplaceJointMax) {
+        FR_TRY(resident_create_joint(ctx, obs, model_ref, &params->lattice, st, &rbj));
+        std::vector<float> k8((size_t)S * 8);
+        set_scale_factors(params->lattice, S, nullptr, k8.data());
+        FR_TRY(kset_j.alloc(ctx, k8.size() * sizeof(float)));
+        FR_TRY(stage_h2d(ctx, kset_j.p, k8.data(), k8.size() * sizeof(float), st));
+    }
+    struct RbGuard {
+        ResidentBuild *rb;
+        hipStream_t st;
+        ~RbGuard() { resident_destroy(rb, st); }
+    } rbj_guard{rbj, st};
     const bool pl = params->residual == FR_PT2PL;
     const size_t nM = (size_t)std::max<int64_t>(M, 1);
     DevBuf wm0, wm1, wns, part, wjtj, wjtr, wstat, wpose, wmats, wtn, wstatus, wactive, witers;
@@ -1350,6 +1373,12 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
     FR_TRY(wstatus.alloc(ctx, S * sizeof(int32_t)));
     FR_TRY(wactive.alloc(ctx, S * sizeof(int32_t)));
     FR_TRY(witers.alloc(ctx, S * sizeof(int32_t)));
+    // the loop's state as saved at the start of a block of in-place rebuilds
+    DevBuf ckpt;
+    const size_t ck_pose = 0, ck_mats = 16 * (size_t)S * 8, ck_tn = ck_mats + 12 * (size_t)S * 4;
+    const size_t ck_status = ck_tn + 2 * (size_t)S * 8, ck_act = ck_status + (size_t)S * 4;
+    const size_t ck_iters = ck_act + (size_t)S * 4, ck_bytes = ck_iters + (size_t)S * 4;
+    if (rbj != nullptr) FR_TRY(ckpt.alloc(ctx, ck_bytes));
     std::vector<float> mats_h((size_t)S * 12);
     for (int32_t s = 0; s < S; ++s)
         for (int i = 0; i < 3; ++i)
@@ -1387,10 +1416,9 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         }
     } bev;
     int32_t *pin = nullptr;
-    if (!fixed) {
-        FR_TRY(pinned_flags(ctx, 2 * (size_t)S, pin));
+    if (!fixed || rbj != nullptr) FR_TRY(pinned_flags(ctx, std::max<size_t>(2 * (size_t)S, (size_t)S + 3), pin));
+    if (!fixed)
         for (hipEvent_t &x : bev.e) FR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
-    }
     int n_blocks = 0;
     // after a block of iterations on stream q: copy the flags; false once the previous block's copy
     // shows that every set has stopped
@@ -1463,8 +1491,46 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
         }
         FR_HIP(hipStreamSynchronize(gs));
     } else {
+        // in-place rebuilds: the state copies of a block, and the block's check (one wait)
+        char *ck = ckpt.as<char>();
+        auto state_copy = [&](bool save) -> fr_status {
+            const struct {
+                void *dev;
+                size_t off, bytes;
+            } parts[] = {{wpose.p, ck_pose, 16 * (size_t)S * 8}, {wmats.p, ck_mats, 12 * (size_t)S * 4},
+                         {wtn.p, ck_tn, 2 * (size_t)S * 8},       {wstatus.p, ck_status, (size_t)S * 4},
+                         {wactive.p, ck_act, (size_t)S * 4},      {witers.p, ck_iters, (size_t)S * 4}};
+            for (const auto &q : parts)
+                FR_HIP(hipMemcpyAsync(save ? ck + q.off : q.dev, save ? q.dev : ck + q.off, q.bytes,
+                                      hipMemcpyDeviceToDevice, st));
+            return FR_OK;
+        };
+        const fr_lattice *elat = lat;   // the lattice the iteration slices
+        int block_start = 0;
+        std::vector<hipEvent_t> bev2;
+        struct BuildEvents {
+            std::vector<hipEvent_t> &e;
+            ~BuildEvents()
+            {
+                for (auto &x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } bev2_guard{bev2};
+        if (prof && rbj != nullptr) {
+            bev2.assign(2 * (size_t)max_it, nullptr);
+            for (auto &e : bev2) FR_HIP(hipEventCreate(&e));
+        }
         while (it < max_it) {
-            if (blurred) {
+            if (rbj != nullptr && it % kBlock == 0) {
+                FR_TRY(state_copy(true));
+                block_start = it;
+            }
+            if (blurred && rbj != nullptr) {
+                if (prof) FR_HIP(hipEventRecord(bev2[2 * (size_t)it], st));
+                FR_TRY(resident_build_joint(rbj, wmats.as<float>(), kset_j.as<float>(), st));
+                if (prof) FR_HIP(hipEventRecord(bev2[2 * (size_t)it + 1], st));
+                elat = resident_lattice(rbj);
+            } else if (blurred) {
                 auto tb = clk::now();
                 if (lat != nullptr) {
                     release_lattice(lat, st);
@@ -1475,17 +1541,17 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                 guard.l = lat;
                 FR_TRY(blur_lattice(lat, st));
                 rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
-            }
-            if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+                elat = lat;
+            }            if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
             if (fused) {
-                FR_TRY(launch_estep_fused(lat->d, lat->V, lat->sets_d, lat->err_d, 0, model_ref, pe,
+                FR_TRY(launch_estep_fused(elat->d, elat->V, elat->sets_d, elat->err_d, 0, model_ref, pe,
                                           wmats.as<float>(), params->residual, 0, part.as<float>(), st, act));
                 if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
                 FR_TRY(launch_reduce_final(pe, part.as<float>(), sig_m, wjtj.as<double>(), wjtr.as<double>(),
                                            wstat.as<double>(), st));
             } else {
-                FR_TRY(launch_estep(lat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
-                                    wm1.as<float>(), lat->V == 7 ? wns.as<float>() : nullptr, nullptr, st, nullptr,
+                FR_TRY(launch_estep(elat, model_ref, pe, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
+                                    wm1.as<float>(), elat->V == 7 ? wns.as<float>() : nullptr, nullptr, st, nullptr,
                                     act));
                 if (prof) FR_HIP(hipEventRecord(ev[3 * it + 1], st));
                 FR_TRY(launch_reduce(model_ref, pr, FR_XF_RIGID, wmats.as<float>(), wm0.as<float>(),
@@ -1498,12 +1564,47 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                                       witers.as<int32_t>()));
             if (prof) FR_HIP(hipEventRecord(ev[3 * it + 2], st));
             ++it;
+            if (rbj != nullptr && (it % kBlock == 0 || it == max_it)) {
+                // the block's check: a rebuild that overflowed a table sends the block back to its start,
+                // and the rest of the call to the host-sized build
+                FR_HIP(hipMemcpyAsync(pin, act, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                FR_HIP(hipMemcpyAsync(pin + S, resident_fail_words(rbj), 2 * sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, st));
+                FR_HIP(hipMemcpyAsync(pin + S + 2, resident_lattice(rbj)->err_d, sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, st));
+                FR_HIP(hipStreamSynchronize(st));
+                if (pin[S + 2] != 0) {
+                    set_error("fr_register: a lattice coordinate left [-2^20, 2^20); increase sigma or centre the "
+                              "cloud");
+                    return FR_ERANGE;
+                }
+                if (pin[S] != 0 || pin[S + 1] != 0) {
+                    FR_TRY(state_copy(false));
+                    it = block_start;
+                    elat = nullptr;
+                    FR_HIP(hipStreamSynchronize(st));
+                    resident_destroy(rbj, st, true);
+                    rbj = rbj_guard.rb = nullptr;
+                    continue;
+                }
+                int32_t any = 0;
+                for (int32_t s2 = 0; s2 < S; ++s2) any |= pin[s2];
+                if (any == 0) break;
+                continue;
+            }
             bool more = true;
             if (it % kBlock == 0 && it < max_it) FR_TRY(block_done(st, more));
             if (!more) break;
         }
-    }
-    FR_HIP(hipMemcpyAsync(iters_v.data(), witers.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (prof && !bev2.empty()) {
+            FR_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < it; ++i) {
+                float b = 0.0f;
+                FR_HIP(hipEventElapsedTime(&b, bev2[2 * (size_t)i], bev2[2 * (size_t)i + 1]));
+                rep.build_ms += b;
+            }
+        }
+    }    FR_HIP(hipMemcpyAsync(iters_v.data(), witers.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipMemcpyAsync(theta_inout_h, wpose.p, S * 16 * sizeof(double), hipMemcpyDeviceToHost, st));
     FR_HIP(hipMemcpyAsync(status_v.data(), wstatus.p, S * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FR_HIP(hipStreamSynchronize(st));

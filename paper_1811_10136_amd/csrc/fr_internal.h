@@ -278,6 +278,13 @@ fr_status resident_build(ResidentBuild *rb, const float *kset, hipStream_t st);
 // buffer of the build, after the previous rebuild's copy has been read).
 fr_status resident_build_host(ResidentBuild *rb, const float *kset_h, hipStream_t st);
 fr_lattice *resident_lattice(ResidentBuild *rb);
+// The uncustomised filter's joint lattice rebuilt in place: per set the
+// observation points (valued) then the model points moved by the set's
+// [R | t] (valueless), built and blurred by resident_build_joint; its
+// arrays, tile maps, offsets and blur buffers are allocated once here.
+fr_status resident_create_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model,
+                                const fr_lattice_params *prm, hipStream_t st, ResidentBuild **out);
+fr_status resident_build_joint(ResidentBuild *rb, const float *mats, const float *kset, hipStream_t st);
 const uint32_t *resident_fail_words(const ResidentBuild *rb);
 // Frees the storage and the lattice; idle: the device has finished every use
 // (else the release is ordered after the work queued on st).

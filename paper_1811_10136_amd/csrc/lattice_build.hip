@@ -1148,7 +1148,6 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
 {
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    constexpr int VP = ValPad<V>::value;
     StreamScope scope(st);   // temporaries are freed in the order of st
     const int32_t S = obs->n_sets;
     const int64_t N = cloud_points(obs);
@@ -1513,6 +1512,16 @@ struct ResidentBuild {
     DevBuf offs;                  // int64: partial offsets [S + 1], then vertex offsets [S + 1]
     DevBuf wave_cnt, rec_key, rec_row, rec_slot, ovid, own1, t1, slot_vid;
     DevBuf rvid, rid, tk, tv, voff, own2, vslot, ws, cnt;
+    // valued points of each set end here (device, n_sets; NULL: all valued)
+    const int64_t *valued_end = nullptr;
+    // joint rebuilds (the uncustomised filter): the joint cloud, its tile map
+    // and offsets, the kernel arguments that assemble it; the blur's slot
+    // offsets per set (written by k_set_tables), tile map and value buffers
+    bool joint = false, blur = false, jnormals = false;
+    DevBuf jpts, joff, jtmap, soff, stmap, bufa, bufb;
+    TileMap jtm{}, stm{};
+    Pts obs_pts{}, model_pts{};
+    size_t jn = 0;   // points per array of the joint cloud
     // scale factors of rebuilds from host values: a device copy, its pinned
     // staging buffer and the event after the last copy out of it
     DevBuf kset_d;
@@ -1555,9 +1564,11 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n, const uint32_t *n_
 // Final tables of every set from its vertex count, with build_impl's sizing
 // (max(8, n) buckets), slots back to back in set order, the
 // set's seed and lattice scale: one workgroup, sets in chunks of 256.
+// slot_off (or NULL): each set's first slot as int64 (set n_sets: the total).
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_t *vbase, const float *kset,
-                                                   char *tab, SetTable *sets, uint32_t *n_slots)
+                                                   char *tab, SetTable *sets, uint32_t *n_slots,
+                                                   int64_t *slot_off)
 {
     using G = SlotGeom<KW, V>;
     __shared__ uint32_t wsum[4];
@@ -1592,12 +1603,16 @@ __global__ void __launch_bounds__(256) k_set_tables(int32_t n_sets, const int64_
 #pragma unroll
             for (int i = 0; i < 8; ++i) t.k[i] = kset[8 * (size_t)s + i];
             sets[s] = t;
+            if (slot_off != nullptr) slot_off[s] = (int64_t)first;
         }
         __syncthreads();
         if (threadIdx.x == 255) carry = first + cap;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *n_slots = carry;
+    if (threadIdx.x == 0) {
+        *n_slots = carry;
+        if (slot_off != nullptr) slot_off[n_sets] = (int64_t)carry;
+    }
 }
 
 // Tile map over sets whose offsets are a device array (n_sets + 1 entries) and
@@ -1633,6 +1648,9 @@ static fr_status make_bound_map(fr_ctx *ctx, const int64_t *dev_off, const std::
 }
 
 template <int d, int V>
+static fr_status resident_blur(ResidentBuild *rb, hipStream_t st);
+
+template <int d, int V>
 static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStream_t st)
 {
     constexpr int KW = KeyWords<d>::value;
@@ -1657,7 +1675,7 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     FR_TRY(scan_exclusive_u32(ctx, wave_cnt, wave_cnt, rb->n_waves + 1, 0, st, ws));
     k_build_partials<d, V><<<rb->ptm.n_tiles, 256, 0, st>>>(rb->pts, rb->ptm, kset, wave_cnt,
                                                             rb->rec_key.as<uint64_t>(), rb->rec_row.as<T>(), R,
-                                                            nullptr, poff, cnt + kResP);
+                                                            rb->valued_end, poff, cnt + kResP);
     FR_HIP(hipGetLastError());
     // 2.-3. provisional tables, vertex ids and per-set vertex offsets
     k_insert_records<KW, true><<<grid_of(rb->rtm), 256, 0, st>>>(rb->rtm, rb->t1.as<SetTable>(),
@@ -1716,7 +1734,8 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     }
     // 5. final tables
     char *table = reinterpret_cast<char *>(lat->tab);
-    k_set_tables<KW, V><<<1, 256, 0, st>>>(S, voff64, kset, table, lat->sets_d, cnt + kResSlots);
+    k_set_tables<KW, V><<<1, 256, 0, st>>>(S, voff64, kset, table, lat->sets_d, cnt + kResSlots,
+                                           rb->blur ? rb->soff.as<int64_t>() : nullptr);
     k_fill_u32<<<blocks_for(rb->n2max, 256), 256, 0, st>>>(rb->own2.as<uint32_t>(), kOwnerEmpty, rb->n2max,
                                                            cnt + kResSlots);
     k_cuckoo_insert<KW><<<grid_of(rb->vtm), 256, 0, st>>>(rb->vtm, lat->sets_d, lat->vkey, R,
@@ -1728,6 +1747,8 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     k_vertex_fill<KW, V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResNV, R, cnt + kResFailCuckoo,
                                                              rb->vslot.as<uint32_t>(), lat->vkey, lat->vval, table);
     FR_HIP(hipGetLastError());
+    if constexpr (V == 4 || V == 7)
+        if (rb->blur) FR_TRY((resident_blur<d, V>(rb, st)));
     return FR_OK;
 }
 
@@ -2107,12 +2128,13 @@ __global__ void __launch_bounds__(256) k_blur_pass(TileMap tm, const SetTable *s
 // binary32 per slot (to_table false: out of the table, zeros for a free slot,
 // whose values the fill leaves unwritten; true: back in).
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, char *table, float *plain, bool to_table)
+__global__ void __launch_bounds__(256) k_slot_values(size_t n_slots, const uint32_t *n_dev, char *table, float *plain,
+                                                    bool to_table)
 {
     using G = SlotGeom<KW, V>;
     constexpr int VP = ValPad<V>::value;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_slots) return;
+    if (j >= dev_count(n_slots, n_dev)) return;
     const bool free_slot = reinterpret_cast<const uint64_t *>(table + G::bytes * j)[0] == kKeyEmpty;
     float4 *tv = reinterpret_cast<float4 *>(table + G::bytes * j + G::val_off);
     float4 *pv = reinterpret_cast<float4 *>(plain + (size_t)VP * j);
@@ -2169,7 +2191,7 @@ static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
     FR_TRY(bufb.alloc(ctx, n * VP * sizeof(float)));
     char *table = reinterpret_cast<char *>(lat->tab);
     float *bufs[2] = {bufa.as<float>(), bufb.as<float>()};
-    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, table, bufs[0], false);
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, nullptr, table, bufs[0], false);
     FR_HIP(hipGetLastError());
     const float scale = (float)(1.0 / (1.0 + std::ldexp(1.0, -d)));
     for (int j = 0; j <= d; ++j) {
@@ -2177,7 +2199,7 @@ static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
                                                        j == d ? scale : 1.0f);
         FR_HIP(hipGetLastError());
     }
-    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, table, bufs[(d + 1) & 1], true);
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, nullptr, table, bufs[(d + 1) & 1], true);
     FR_HIP(hipGetLastError());
     if (vtm.n_tiles > 0) {
         k_table_to_vertices<d, V><<<vtm.n_tiles, 256, 0, st>>>(vtm, lat->sets_d, lat->vkey,
@@ -2185,6 +2207,107 @@ static fr_status blur_impl(fr_lattice *lat, hipStream_t st)
         FR_HIP(hipGetLastError());
     }
     return FR_OK;
+}
+
+// The blur of a lattice rebuilt in place: the slots of set s start at the
+// device offset k_set_tables wrote; the tile map covers each set's bound and
+// the value buffers the bound of all slots.
+template <int d, int V>
+static fr_status resident_blur(ResidentBuild *rb, hipStream_t st)
+{
+    constexpr int KW = KeyWords<d>::value;
+    fr_lattice *lat = rb->lat;
+    uint32_t *cnt = rb->cnt.as<uint32_t>();
+    const size_t n = rb->n2max;
+    char *table = reinterpret_cast<char *>(lat->tab);
+    float *bufs[2] = {rb->bufa.as<float>(), rb->bufb.as<float>()};
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, cnt + kResSlots, table, bufs[0], false);
+    FR_HIP(hipGetLastError());
+    const float scale = (float)(1.0 / (1.0 + std::ldexp(1.0, -d)));
+    for (int j = 0; j <= d; ++j) {
+        k_blur_pass<d, V><<<grid_of(rb->stm), 256, 0, st>>>(rb->stm, lat->sets_d, j, bufs[j & 1], bufs[(j + 1) & 1],
+                                                          j == d ? scale : 1.0f);
+        FR_HIP(hipGetLastError());
+    }
+    k_slot_values<KW, V><<<blocks_for(n, 256), 256, 0, st>>>(n, cnt + kResSlots, table, bufs[(d + 1) & 1], true);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status resident_create_joint(fr_ctx *ctx, const fr_cloud *obs, const fr_cloud *model,
+                                const fr_lattice_params *prm, hipStream_t st, ResidentBuild **out)
+{
+    *out = nullptr;
+    if ((prm->values != 4 && prm->values != 7) || prm->feat > 6) {
+        set_error("fr_register: the uncustomised filter needs values FR_VAL_PT2PT or FR_VAL_PT2PL");
+        return FR_EINVAL;
+    }
+    const int32_t S = obs->n_sets;
+    std::vector<int64_t> off(S + 1, 0), vend(S);
+    for (int32_t s = 0; s < S; ++s) {
+        const int64_t no = obs->offsets[s + 1] - obs->offsets[s], nm = model->offsets[s + 1] - model->offsets[s];
+        off[s + 1] = off[s] + no + nm;
+        vend[s] = off[s] + no;
+    }
+    const int64_t T = off[S];
+    const bool normals = obs->nx != nullptr;
+    // the joint cloud's layout; its arrays are attached once the build's storage exists
+    fr_cloud joint{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, off.data(), S};
+    ResidentBuild *rb = nullptr;
+    FR_TRY(resident_create(ctx, &joint, prm, st, &rb));
+    auto fail = [&](fr_status s) {
+        resident_destroy(rb, st);
+        return s;
+    };
+    const size_t n = (size_t)std::max<int64_t>(T, 1);
+    fr_status s = rb->jpts.alloc(ctx, n * (normals ? 6 : 3) * sizeof(float));
+    if (s == FR_OK) s = rb->joff.alloc(ctx, (3 * (size_t)S + 2) * sizeof(int64_t));
+    if (s != FR_OK) return fail(s);
+    int64_t *od = rb->joff.as<int64_t>();
+    s = stage_h2d(ctx, od, obs->offsets, (S + 1) * sizeof(int64_t), st);
+    if (s == FR_OK) s = stage_h2d(ctx, od + S + 1, model->offsets, (S + 1) * sizeof(int64_t), st);
+    if (s == FR_OK) s = stage_h2d(ctx, od + 2 * S + 2, vend.data(), S * sizeof(int64_t), st);
+    if (s == FR_OK) s = make_offset_map(ctx, off, 256, st, rb->jtmap, rb->jtm);
+    if (s != FR_OK) return fail(s);
+    float *base = rb->jpts.as<float>();
+    rb->pts = Pts{base, base + n, base + 2 * n, normals ? base + 3 * n : nullptr, normals ? base + 4 * n : nullptr,
+                  normals ? base + 5 * n : nullptr};
+    rb->obs_pts = Pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
+    rb->model_pts = Pts{model->x, model->y, model->z, model->nx, model->ny, model->nz};
+    rb->jn = n;
+    rb->jnormals = normals;
+    rb->valued_end = od + 2 * S + 2;
+    rb->joint = true;
+    // the blur's storage: slot offsets, a tile map over each set's bound of slots, two value buffers
+    const int D = prm->feat + 1;
+    std::vector<uint64_t> slot_bound(S);
+    for (int32_t q = 0; q < S; ++q)
+        slot_bound[q] = (uint64_t)kBucketSlots * std::max<uint64_t>(8, (uint64_t)(off[q + 1] - off[q]) * D);
+    const int VP = prm->values <= 4 ? 4 : 8;
+    s = rb->soff.alloc(ctx, (S + 1) * sizeof(int64_t));
+    if (s == FR_OK) s = make_bound_map(ctx, rb->soff.as<int64_t>(), slot_bound, 256, st, rb->stmap, rb->stm);
+    if (s == FR_OK) s = rb->bufa.alloc(ctx, std::max<size_t>(rb->n2max, 1) * VP * sizeof(float));
+    if (s == FR_OK) s = rb->bufb.alloc(ctx, std::max<size_t>(rb->n2max, 1) * VP * sizeof(float));
+    if (s != FR_OK) return fail(s);
+    rb->blur = true;
+    *out = rb;
+    return FR_OK;
+}
+
+fr_status resident_build_joint(ResidentBuild *rb, const float *mats, const float *kset, hipStream_t st)
+{
+    const int32_t S = rb->S;
+    const int64_t *od = rb->joff.as<int64_t>();
+    float *base = rb->jpts.as<float>();
+    const size_t n = rb->jn;
+    const bool nm = rb->jnormals;
+    JointArgs a{rb->jtm, od, od + S + 1, rb->obs_pts, rb->model_pts, mats, base, base + n, base + 2 * n,
+                nm ? base + 3 * n : nullptr, nm ? base + 4 * n : nullptr, nm ? base + 5 * n : nullptr};
+    if (rb->jtm.n_tiles > 0) {
+        k_joint_points<<<rb->jtm.n_tiles, 256, 0, st>>>(a);
+        FR_HIP(hipGetLastError());
+    }
+    return resident_build(rb, kset, st);
 }
 
 fr_status blur_lattice(fr_lattice *lat, hipStream_t st)
