@@ -65,8 +65,9 @@ def make_pairs(n, workers):
 
 
 def kernel_source_hash():
+    """Hash of the sources that decide the E-step kernel and the table it reads (the build lays it out)."""
     h = hashlib.sha256()
-    for f in ("estep.hip", "fr_device.h", "fr_mstep.h"):
+    for f in ("estep.hip", "fr_device.h", "fr_mstep.h", "lattice_build.hip"):
         h.update(open(os.path.join(ROOT, "paper_1811_10136_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
