@@ -1028,47 +1028,60 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
     atomicOr(fail, 1);
 }
 
-// Filling the table, first pass (one thread per slot): a free slot gets the
-// empty key, an occupied one tells its vertex where it sits.
+// Filling the table without a slot -> vertex map: free slots get the empty
+// key (one thread per slot), and each vertex (one thread per vertex, over the
+// cuckoo pass's tile map) finds its own slot among the four of its two
+// buckets -- two random 8-byte reads instead of the map's random 4-byte
+// writes and its read-back -- and writes its key and padded values there.  A
+// vertex the cuckoo pass failed to place writes nothing (the pass is redone).
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_slot_owner(size_t n_slots, const uint32_t *n_dev, const uint32_t *own,
-                                                   char *table, uint32_t *vslot)
+__global__ void __launch_bounds__(256) k_slot_empty(size_t n_slots, const uint32_t *n_dev, const uint32_t *own,
+                                                   char *table)
 {
     using G = SlotGeom<KW, V>;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= dev_count(n_slots, n_dev)) return;
-    const uint32_t o = own[j];
-    if (o != kOwnerEmpty) {
-        vslot[o] = (uint32_t)j;
-        return;
-    }
+    if (j >= dev_count(n_slots, n_dev) || own[j] != kOwnerEmpty) return;
     uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
 }
 
-// Second pass (one thread per vertex, reading the vertex arrays in order):
-// the key words and padded values of the vertex, written to its slot.  A free
-// slot's values are never read.
 template <int KW, int V>
-__global__ void __launch_bounds__(256) k_vertex_fill(size_t NV, const uint32_t *nv_dev, size_t stride,
-                                                    const uint32_t *fail, const uint32_t *vslot, const uint64_t *vkey,
-                                                    const float *vval, char *table)
+__global__ void __launch_bounds__(256) k_vertex_place(TileMap tm, const SetTable *tables, const uint32_t *own,
+                                                     const uint64_t *vkey, const float *vval, size_t stride,
+                                                     const uint32_t *fail, char *table)
 {
     using G = SlotGeom<KW, V>;
     constexpr int VP = ValPad<V>::value;
-    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= dev_count(NV, nv_dev) || aborted(fail)) return;
-    char *slot = table + (size_t)G::bytes * vslot[v];
-    uint64_t *key = reinterpret_cast<uint64_t *>(slot);
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles || aborted(fail)) return;
+    const int32_t s = tile_segment(tm, t);
+    const int64_t v = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile + threadIdx.x;
+    if (v >= tm.seg_end[s]) return;
+    const SetTable st = tables[s];
+    uint64_t key[KW];
+    vertex_key<KW>(vkey, stride, (uint32_t)v, key);
+    uint32_t b1, b2;
+    key_buckets<KW>(key, st.seed, st.cap >> 1, b1, b2);
+    const uint2 o1 = *reinterpret_cast<const uint2 *>(own + st.slot_base + (size_t)kBucketSlots * b1);
+    const uint2 o2 = *reinterpret_cast<const uint2 *>(own + st.slot_base + (size_t)kBucketSlots * b2);
+    const uint32_t u = (uint32_t)v;
+    int64_t slot = -1;
+    if (o1.x == u) slot = (int64_t)kBucketSlots * b1;
+    else if (o1.y == u) slot = (int64_t)kBucketSlots * b1 + 1;
+    else if (o2.x == u) slot = (int64_t)kBucketSlots * b2;
+    else if (o2.y == u) slot = (int64_t)kBucketSlots * b2 + 1;
+    if (slot < 0) return;
+    char *dst = table + (size_t)G::bytes * (st.slot_base + (uint64_t)slot);
+    uint64_t *kd = reinterpret_cast<uint64_t *>(dst);
 #pragma unroll
-    for (int w = 0; w < KW; ++w) key[w] = vkey[(size_t)w * stride + v];
+    for (int w = 0; w < KW; ++w) kd[w] = key[w];
     float val[VP];
 #pragma unroll
     for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * stride + v] : 0.0f;
-    float4 *dst = reinterpret_cast<float4 *>(slot + G::val_off);
+    float4 *vd = reinterpret_cast<float4 *>(dst + G::val_off);
 #pragma unroll
-    for (int q = 0; q < VP / 4; ++q) dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+    for (int q = 0; q < VP / 4; ++q) vd[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1400,9 +1413,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         lat->sets_h[s].keys = reinterpret_cast<const uint64_t *>(first);
         lat->sets_h[s].vals = reinterpret_cast<const float *>(first + SlotGeom<KW, V>::val_off);
     }
-    DevBuf own2, vtmap, vslot;
+    DevBuf own2, vtmap;
     FR_TRY(own2.alloc(ctx, n2 * sizeof(uint32_t)));
-    FR_TRY(vslot.alloc(ctx, std::max<size_t>(NV, 1) * sizeof(uint32_t)));
     TileMap vtm{};
     FR_TRY(make_offset_map(ctx, lat->vbase, 256, st, vtmap, vtm, true));
     char *table = reinterpret_cast<char *>(lat->tab);
@@ -1411,13 +1423,11 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // returns at once if the cuckoo pass gave up)
     auto fill_table = [&]() -> fr_status {
         if (n2 == 0) return FR_OK;
-        k_slot_owner<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, nullptr, own2.as<uint32_t>(), table,
-                                                                vslot.as<uint32_t>());
+        k_slot_empty<KW, V><<<blocks_for(n2, 256), 256, 0, st>>>(n2, nullptr, own2.as<uint32_t>(), table);
         FR_HIP(hipGetLastError());
-        if (NV > 0) {
-            k_vertex_fill<KW, V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, fail_word,
-                                                                     vslot.as<uint32_t>(), lat->vkey, lat->vval,
-                                                                     table);
+        if (vtm.n_tiles > 0) {
+            k_vertex_place<KW, V><<<grid_of(vtm), 256, 0, st>>>(vtm, lat->sets_d, own2.as<uint32_t>(), lat->vkey,
+                                                               lat->vval, NV, fail_word, table);
             FR_HIP(hipGetLastError());
         }
         return FR_OK;
@@ -1515,7 +1525,7 @@ struct ResidentBuild {
     DevBuf ptmap, rtmap, vtmap;   // tile-map arrays
     DevBuf offs;                  // int64: partial offsets [S + 1], then vertex offsets [S + 1]
     DevBuf wave_cnt, rec_key, rec_row, rec_slot, ovid, own1, t1, slot_vid;
-    DevBuf rvid, rid, tk, tv, voff, own2, vslot, ws, cnt;
+    DevBuf rvid, rid, tk, tv, voff, own2, ws, cnt;
     // valued points of each set end here (device, n_sets; NULL: all valued)
     const int64_t *valued_end = nullptr;
     // joint rebuilds (the uncustomised filter): the joint cloud, its tile map
@@ -1745,11 +1755,10 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     k_cuckoo_insert<KW><<<grid_of(rb->vtm), 256, 0, st>>>(rb->vtm, lat->sets_d, lat->vkey, R,
                                                          rb->own2.as<uint32_t>(),
                                                          reinterpret_cast<int32_t *>(cnt + kResFailCuckoo));
-    k_slot_owner<KW, V><<<blocks_for(rb->n2max, 256), 256, 0, st>>>(rb->n2max, cnt + kResSlots,
-                                                                   rb->own2.as<uint32_t>(), table,
-                                                                   rb->vslot.as<uint32_t>());
-    k_vertex_fill<KW, V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResNV, R, cnt + kResFailCuckoo,
-                                                             rb->vslot.as<uint32_t>(), lat->vkey, lat->vval, table);
+    k_slot_empty<KW, V><<<blocks_for(rb->n2max, 256), 256, 0, st>>>(rb->n2max, cnt + kResSlots,
+                                                                   rb->own2.as<uint32_t>(), table);
+    k_vertex_place<KW, V><<<grid_of(rb->vtm), 256, 0, st>>>(rb->vtm, lat->sets_d, rb->own2.as<uint32_t>(), lat->vkey,
+                                                           lat->vval, R, cnt + kResFailCuckoo, table);
     FR_HIP(hipGetLastError());
     if constexpr (V == 4 || V == 7)
         if (rb->blur) FR_TRY((resident_blur<d, V>(rb, st)));
@@ -1818,7 +1827,6 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
         FR_TRY(rb->voff.alloc(ctx, R * sizeof(uint32_t)));
     }
     FR_TRY(rb->own2.alloc(ctx, n2 * sizeof(uint32_t)));
-    FR_TRY(rb->vslot.alloc(ctx, R * sizeof(uint32_t)));
     const size_t ws = std::max({scan_ws_words(rb->n_waves + 1), scan_ws_words(R + 1), radix_ws_words(R)});
     FR_TRY(rb->ws.alloc(ctx, std::max<size_t>(ws, 1) * sizeof(uint32_t)));
     FR_TRY(rb->cnt.alloc(ctx, kResWords * sizeof(uint32_t)));
