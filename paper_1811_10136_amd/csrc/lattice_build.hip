@@ -338,6 +338,201 @@ static fr_status radix_sort_pairs(fr_ctx *ctx, uint32_t *keys, uint32_t *vals, u
 }
 
 // ---------------------------------------------------------------------------
+// Sorted splat of a one-shot build: the records of each set (a contiguous
+// range) are ordered by vertex id, stably, with a segmented LSD radix sort
+// of the id less the set's first vertex id, in 9-bit digits -- sets of up to
+// 2^18 vertices take two passes, where the global ids of many sets would
+// take three 8-bit ones.  Tiles of kRsTile records never straddle two sets,
+// and a histogram entry of (set s, digit g, tile j of s) sits at
+// kSrDigits * tile0(s) + g * tiles(s) + j: one exclusive scan over all of
+// them then gives each (tile, digit) its first place inside its set's range.
+// Keys stay the global ids (the digits are taken from the local ones).
+// ---------------------------------------------------------------------------
+constexpr int kSrBits = 9;
+constexpr uint32_t kSrDigits = 1u << kSrBits;
+
+__device__ __forceinline__ size_t sr_hist_index(const TileMap &tm, int32_t s, int32_t t, uint32_t digit)
+{
+    const int32_t t0 = tm.seg_tile[s];
+    return (size_t)kSrDigits * t0 + (size_t)digit * (size_t)(tm.seg_tile[s + 1] - t0) + (size_t)(t - t0);
+}
+
+// keys (or NULL): the items' keys; with NULL, pass 0 -- each record's vertex
+// id is taken through its provisional slot (slot_vid[rec_slot[r]]) and
+// written to keys_out.
+__global__ void __launch_bounds__(kRsThreads) k_sr_hist(TileMap tm, const uint32_t *vbase, const uint32_t *keys,
+                                                        const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                        uint32_t *keys_out, int shift, uint32_t *hist)
+{
+    __shared__ uint32_t h[kSrDigits];
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;   // uniform over the workgroup
+    const int32_t s = tile_segment(tm, t);
+    for (uint32_t i = threadIdx.x; i < kSrDigits; i += kRsThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t first = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile;
+    const int64_t end = min(first + (int64_t)tm.tile, tm.seg_end[s]);
+    const uint32_t vb = vbase[s];
+    for (int64_t r = first + threadIdx.x; r < end; r += kRsThreads) {
+        uint32_t k;
+        if (keys == nullptr) {
+            k = slot_vid[rec_slot[r]];
+            keys_out[r] = k;
+        } else {
+            k = keys[r];
+        }
+        atomicAdd(&h[((k - vb) >> shift) & (kSrDigits - 1)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kSrDigits; i += kRsThreads) hist[sr_hist_index(tm, s, t, i)] = h[i];
+}
+
+// The ranking of k_rs_scatter with 9-bit digits (each thread keeps two digits
+// in the block prefix).  vin (or NULL): the values; with NULL each item's
+// value is its own index (pass 0).
+__global__ void __launch_bounds__(kRsThreads) k_sr_scatter(TileMap tm, const uint32_t *vbase, const uint32_t *kin,
+                                                           const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                                                           int shift, const uint32_t *hist_scan)
+{
+    __shared__ uint32_t wcnt[kRsWaves][kSrDigits];
+    __shared__ uint32_t gbase[kSrDigits];
+    __shared__ uint32_t dstart[kSrDigits];
+    __shared__ uint32_t wsum[kRsWaves];
+    __shared__ uint32_t skey[kRsTile], sval[kRsTile];
+    const int32_t t = logical_tile(tm);
+    if (t >= tm.n_tiles) return;   // uniform over the workgroup
+    const int32_t s = tile_segment(tm, t);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t i = threadIdx.x; i < kSrDigits; i += kRsThreads) {
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) wcnt[w][i] = 0;
+        gbase[i] = hist_scan[sr_hist_index(tm, s, t, i)];
+    }
+    __syncthreads();
+
+    const int64_t first = tm.seg_off[s] + (int64_t)(t - tm.seg_tile[s]) * tm.tile;
+    const int64_t end = min(first + (int64_t)tm.tile, tm.seg_end[s]);
+    const uint32_t vb = vbase[s];
+    const int64_t base = first + (int64_t)wave * (64 * kRsRounds);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kRsRounds], val[kRsRounds], lrank[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t idx = base + (int64_t)r * 64 + lane;
+        const bool valid = idx < end;
+        key[r] = valid ? kin[idx] : vb;
+        val[r] = valid ? (vin != nullptr ? vin[idx] : (uint32_t)idx) : 0u;
+        const uint32_t digit = ((key[r] - vb) >> shift) & (kSrDigits - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < kSrBits; ++bit) {
+            const bool on = (digit >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t before = wcnt[wave][digit];
+        lrank[r] = before + (uint32_t)__popcll(peers & lt);
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (__ffsll((long long)peers) - 1) == lane) wcnt[wave][digit] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digits 2i and 2i+1 of thread i: per-wave offsets, then the block prefix
+    uint32_t run[2] = {0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t g = 2u * threadIdx.x + (uint32_t)j;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) {
+            const uint32_t c = wcnt[w][g];
+            wcnt[w][g] = run[j];
+            run[j] += c;
+        }
+    }
+    const uint32_t pair = run[0] + run[1];
+    uint32_t inc = pair;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    dstart[2 * threadIdx.x] = before + inc - pair;
+    dstart[2 * threadIdx.x + 1] = before + inc - pair + run[0];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t idx = base + (int64_t)r * 64 + lane;
+        if (idx < end) {
+            const uint32_t digit = ((key[r] - vb) >> shift) & (kSrDigits - 1);
+            const uint32_t lpos = dstart[digit] + wcnt[wave][digit] + lrank[r];
+            skey[lpos] = key[r];
+            sval[lpos] = val[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t count = (uint32_t)(end - first);
+    for (uint32_t i = threadIdx.x; i < count; i += kRsThreads) {
+        const uint32_t k = skey[i];
+        const uint32_t digit = ((k - vb) >> shift) & (kSrDigits - 1);
+        const size_t pos = (size_t)gbase[digit] + (i - dstart[digit]);
+        kout[pos] = k;
+        vout[pos] = sval[i];
+    }
+}
+
+// Sorts the records of a one-shot build by vertex id (stable).  tm: tiles of
+// kRsTile records over the sets' record ranges; vbase: the sets' first
+// vertex ids (device); local_bits: bits of the largest local vertex id.
+// Pass 0 takes the ids through the provisional slots, so keys0 needs no
+// input.  On return *keys_out / *vals_out name the arrays holding the result
+// (sorted vertex ids and record indices); keys0/vals0 and keys1/vals1 are the
+// two ping-pong pairs, each of n entries.
+static fr_status segmented_sort_records(fr_ctx *ctx, const TileMap &tm, const uint32_t *vbase,
+                                        const uint32_t *rec_slot, const uint32_t *slot_vid, uint32_t *keys0,
+                                        uint32_t *vals0, uint32_t *keys1, uint32_t *vals1, size_t n, int local_bits,
+                                        hipStream_t st, uint32_t **keys_out, uint32_t **vals_out)
+{
+    *keys_out = keys0;
+    *vals_out = vals0;
+    if (n == 0 || tm.n_tiles == 0) return FR_OK;
+    if (tm.tile != kRsTile) {
+        set_error("segmented sort: tiles of %d records, the kernels take %d", tm.tile, kRsTile);
+        return FR_EINVAL;
+    }
+    const int passes = std::max(1, (local_bits + kSrBits - 1) / kSrBits);
+    const size_t n_hist = (size_t)kSrDigits * tm.n_tiles;
+    DevBuf hbuf;
+    FR_TRY(hbuf.alloc(ctx, n_hist * sizeof(uint32_t)));
+    hbuf.stream = st;
+    uint32_t *hist = hbuf.as<uint32_t>();
+    // pass p reads (ka, va) and writes (kb, vb); pass 0 writes the ids into keys0 first
+    uint32_t *ka = keys0, *va = nullptr, *kb = keys1, *vb = vals1;
+    const unsigned grid = (unsigned)(tm.xcd_chunk > 0 ? tm.xcd_chunk * 8 : tm.n_tiles);
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kSrBits;
+        k_sr_hist<<<grid, kRsThreads, 0, st>>>(tm, vbase, p == 0 ? nullptr : ka, rec_slot, slot_vid, keys0, shift,
+                                               hist);
+        FR_HIP(hipGetLastError());
+        FR_TRY(scan_exclusive_u32(ctx, hist, hist, n_hist, 0, st));
+        k_sr_scatter<<<grid, kRsThreads, 0, st>>>(tm, vbase, ka, va, kb, vb, shift, hist);
+        FR_HIP(hipGetLastError());
+        // next pass reads what this one wrote and writes the other pair
+        uint32_t *kn = (kb == keys1) ? keys0 : keys1, *vn = (vb == vals1) ? vals0 : vals1;
+        ka = kb;
+        va = vb;
+        kb = kn;
+        vb = vn;
+    }
+    *keys_out = ka;
+    *vals_out = va;
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Build kernels
 // ---------------------------------------------------------------------------
 struct Pts {
@@ -1343,21 +1538,23 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     stage.mark(2, st);
     if (NV > 0) {
         if (sorted) {
-            DevBuf rvid, rid, tk, tv, voff;
+            DevBuf rvid, rid, tk, tv, voff, stmap;
             FR_TRY(rvid.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(rid.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(tk.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(tv.alloc(ctx, P * sizeof(uint32_t)));
             FR_TRY(voff.alloc(ctx, NV * sizeof(uint32_t)));
-            k_record_vertex<<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, rec_slot.as<uint32_t>(),
-                                                                 slot_vid.as<uint32_t>(), rvid.as<uint32_t>(),
-                                                                 rid.as<uint32_t>());
-            FR_HIP(hipGetLastError());
+            // sort each set's records by their vertex id less the set's first one
+            uint32_t max_local = 0;
+            for (int32_t s = 0; s < S; ++s) max_local = std::max(max_local, counts[s] > 0 ? counts[s] - 1 : 0u);
             int bits = 0;
-            while (bits < 32 && (NV - 1) >> bits) ++bits;
+            while (bits < 32 && (max_local >> bits) != 0) ++bits;
+            TileMap srtm{};
+            FR_TRY(make_offset_map(ctx, roff, kRsTile, st, stmap, srtm, true));
             uint32_t *svid = nullptr, *srid = nullptr;   // the sorted pairs
-            FR_TRY(radix_sort_pairs(ctx, rvid.as<uint32_t>(), rid.as<uint32_t>(), tk.as<uint32_t>(),
-                                    tv.as<uint32_t>(), P, bits, st, &svid, &srid));
+            FR_TRY(segmented_sort_records(ctx, srtm, vb_d.as<uint32_t>(), rec_slot.as<uint32_t>(),
+                                          slot_vid.as<uint32_t>(), rvid.as<uint32_t>(), rid.as<uint32_t>(),
+                                          tk.as<uint32_t>(), tv.as<uint32_t>(), P, bits, st, &svid, &srid));
             k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
             k_vertex_sum_sorted<V><<<blocks_for(NV, 256), 256, 0, st>>>(NV, nullptr, NV, P, nullptr, nullptr,
