@@ -358,10 +358,10 @@ __device__ __forceinline__ size_t sr_hist_index(const TileMap &tm, int32_t s, in
 }
 
 // keys (or NULL): the items' keys; with NULL, pass 0 -- each record's vertex
-// id is taken through its provisional slot (slot_vid[rec_slot[r]]) and
+// id is taken through its owner record (ovid[rec_own[r]]) and
 // written to keys_out.
 __global__ void __launch_bounds__(kRsThreads) k_sr_hist(TileMap tm, const uint32_t *vbase, const uint32_t *keys,
-                                                        const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                        const uint32_t *rec_own, const uint32_t *ovid,
                                                         uint32_t *keys_out, int shift, uint32_t *hist)
 {
     __shared__ uint32_t h[kSrDigits];
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kRsThreads) k_sr_hist(TileMap tm, const uint32
     for (int64_t r = first + threadIdx.x; r < end; r += kRsThreads) {
         uint32_t k;
         if (keys == nullptr) {
-            k = slot_vid[rec_slot[r]];
+            k = ovid[rec_own[r]];
             keys_out[r] = k;
         } else {
             k = keys[r];
@@ -487,12 +487,12 @@ __global__ void __launch_bounds__(kRsThreads) k_sr_scatter(TileMap tm, const uin
 // Sorts the records of a one-shot build by vertex id (stable).  tm: tiles of
 // kRsTile records over the sets' record ranges; vbase: the sets' first
 // vertex ids (device); local_bits: bits of the largest local vertex id.
-// Pass 0 takes the ids through the provisional slots, so keys0 needs no
+// Pass 0 takes the ids through the owner records, so keys0 needs no
 // input.  On return *keys_out / *vals_out name the arrays holding the result
 // (sorted vertex ids and record indices); keys0/vals0 and keys1/vals1 are the
 // two ping-pong pairs, each of n entries.
 static fr_status segmented_sort_records(fr_ctx *ctx, const TileMap &tm, const uint32_t *vbase,
-                                        const uint32_t *rec_slot, const uint32_t *slot_vid, uint32_t *keys0,
+                                        const uint32_t *rec_own, const uint32_t *ovid, uint32_t *keys0,
                                         uint32_t *vals0, uint32_t *keys1, uint32_t *vals1, size_t n, int local_bits,
                                         hipStream_t st, uint32_t **keys_out, uint32_t **vals_out)
 {
@@ -514,7 +514,7 @@ static fr_status segmented_sort_records(fr_ctx *ctx, const TileMap &tm, const ui
     const unsigned grid = (unsigned)(tm.xcd_chunk > 0 ? tm.xcd_chunk * 8 : tm.n_tiles);
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kSrBits;
-        k_sr_hist<<<grid, kRsThreads, 0, st>>>(tm, vbase, p == 0 ? nullptr : ka, rec_slot, slot_vid, keys0, shift,
+        k_sr_hist<<<grid, kRsThreads, 0, st>>>(tm, vbase, p == 0 ? nullptr : ka, rec_own, ovid, keys0, shift,
                                                hist);
         FR_HIP(hipGetLastError());
         FR_TRY(scan_exclusive_u32(ctx, hist, hist, n_hist, 0, st));
@@ -828,13 +828,16 @@ __device__ __forceinline__ void load_key_row(const uint64_t *rec_key, size_t r, 
 // first merged in LDS: each record finds or claims its key in a small
 // open-addressing table of the workgroup, and only the record that claimed a
 // key (its representative) probes the global table; the others take the
-// representative's slot (MERGE; without it every record probes).  In the
+// representative's result (MERGE; without it every record probes).  In the
 // global table a slot holds a fingerprint of its key above its owner record;
 // a slot read as taken is compared by fingerprint, then by the owner's key;
 // only free slots are claimed with a CAS; owner_flag[r] = 1 marks the record
-// whose CAS claimed the slot (the owner of its vertex).  Probing stops after
-// kMaxProbe slots and raises `fail` (the host then retries with a larger
-// table).
+// whose CAS claimed the slot (the owner of its vertex), and rec_own[r] is the
+// owner record of r's key.  An owner lies near the records of its vertex (they
+// come from neighbouring points), so later passes that go from a record to
+// its vertex id through rec_own read a few nearby lines, where the slot would
+// send them to a random one.  Probing stops after kMaxProbe slots and raises
+// `fail` (the host then retries with a larger table).
 constexpr uint32_t kMaxProbe = 128;
 constexpr unsigned long long kSlotEmpty = ~0ull;   // a free provisional slot
 
@@ -843,7 +846,7 @@ constexpr unsigned long long kSlotEmpty = ~0ull;   // a free provisional slot
 // one-shot build: its insertion 0.08 ms faster than with 256 on 64 depth frames).
 template <int KW, bool MERGE, int TILE = 256>
 __global__ void __launch_bounds__(TILE) k_insert_records(TileMap tm, const SetTable *tables, const uint64_t *rec_key,
-                                                        size_t R, unsigned long long *own, uint32_t *rec_slot,
+                                                        size_t R, unsigned long long *own, uint32_t *rec_own,
                                                         uint32_t *owner_flag, int32_t *fail)
 {
     constexpr uint32_t kTileKeySlots = 2 * TILE;   // LDS table of a tile: load <= 1/2
@@ -904,7 +907,7 @@ __global__ void __launch_bounds__(TILE) k_insert_records(TileMap tm, const SetTa
                 match = key_equal<KW>(ok, key);
             }
             if (match) {
-                found = (uint32_t)slot;
+                found = won ? (uint32_t)r : (uint32_t)o;   // the owner record of the key
                 break;
             }
             h = (h + 1) & st.mask;
@@ -913,15 +916,15 @@ __global__ void __launch_bounds__(TILE) k_insert_records(TileMap tm, const SetTa
         if constexpr (MERGE) {
             lslot[tid] = found;
         } else {
-            if (found != kOwnerEmpty) rec_slot[r] = found;
+            if (found != kOwnerEmpty) rec_own[r] = found;
             owner_flag[r] = won ? 1u : 0u;
         }
     }
     if constexpr (MERGE) {
         __syncthreads();
         if (active) {
-            const uint32_t slot = lslot[rep];
-            if (slot != kOwnerEmpty) rec_slot[r] = slot;
+            const uint32_t o = lslot[rep];
+            if (o != kOwnerEmpty) rec_own[r] = o;
             owner_flag[r] = won ? 1u : 0u;
         }
     }
@@ -929,15 +932,14 @@ __global__ void __launch_bounds__(TILE) k_insert_records(TileMap tm, const SetTa
 
 // Vertex ids in owner-record order: `ovid` holds the exclusive scan of the
 // owner flags over R + 1 entries (the flag past the last record is 0, so
-// ovid[R] is the vertex count); owners -- the records whose id the scan
-// steps past -- write their vertex's key (word-major, `stride` vertices per
-// word) and the slot -> vertex map.
+// ovid[R] is the vertex count, and a record's vertex id is ovid[rec_own[r]]);
+// owners -- the records whose id the scan steps past -- write their vertex's
+// key (word-major, `stride` vertices per word).
 // rec_off (or NULL; n_sets + 1 record offsets): workgroup 0 also writes each
 // set's first vertex as k_set_vbase does (vbase64, and the count to *nv).
 template <int KW>
-__global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *rec_slot, const uint32_t *ovid,
-                                                   const uint64_t *rec_key, uint64_t *vkey, size_t stride,
-                                                   uint32_t *slot_vid, int32_t n_sets = 0,
+__global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *ovid, const uint64_t *rec_key,
+                                                   uint64_t *vkey, size_t stride, int32_t n_sets = 0,
                                                    const int64_t *rec_off = nullptr, int64_t *vbase64 = nullptr,
                                                    uint32_t *nv = nullptr)
 {
@@ -951,10 +953,8 @@ __global__ void __launch_bounds__(256) k_owner_emit(size_t R, const uint32_t *re
     if (r >= R) return;
     const uint32_t v = ovid[r];
     if (ovid[r + 1] == v) return;
-    const uint32_t slot = rec_slot[r];
 #pragma unroll
     for (int w = 0; w < KW; ++w) vkey[(size_t)w * stride + v] = rec_key[(size_t)r * KW + w];
-    slot_vid[slot] = v;
 }
 
 // First vertex of each set (set n_sets: the vertex count): owners of a set's
@@ -973,12 +973,12 @@ __global__ void k_set_vbase(int32_t n_sets, const int64_t *rec_off, const uint32
 }
 
 __global__ void __launch_bounds__(256) k_record_vertex(size_t R, const uint32_t *n_dev, const uint32_t *fail,
-                                                      const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                      const uint32_t *rec_own, const uint32_t *ovid,
                                                       uint32_t *rvid, uint32_t *rid)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= dev_count(R, n_dev) || aborted(fail)) return;
-    rvid[r] = slot_vid[rec_slot[r]];
+    rvid[r] = ovid[rec_own[r]];
     rid[r] = (uint32_t)r;
 }
 
@@ -1052,12 +1052,12 @@ __global__ void __launch_bounds__(256) k_vertex_sum_sorted(size_t NV, const uint
 constexpr size_t kListMax = (size_t)1 << 17;
 
 __global__ void __launch_bounds__(256) k_list_count(size_t P, const uint32_t *p_dev, const uint32_t *fail,
-                                                   const uint32_t *rec_slot, const uint32_t *slot_vid, uint32_t *rvid,
+                                                   const uint32_t *rec_own, const uint32_t *ovid, uint32_t *rvid,
                                                    uint32_t *vcount)
 {
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= dev_count(P, p_dev) || aborted(fail)) return;
-    const uint32_t v = slot_vid[rec_slot[r]];
+    const uint32_t v = ovid[rec_own[r]];
     rvid[r] = v;
     atomicAdd(&vcount[v], 1u);
 }
@@ -1119,14 +1119,14 @@ __global__ void __launch_bounds__(256) k_vertex_sum_list(size_t NV, const uint32
 // occupancy by integer atomics.  The |y|^2 channel waits for the second pass.
 template <int V>
 __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint32_t *p_dev, const uint32_t *fail,
-                                                          const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                          const uint32_t *rec_own, const uint32_t *ovid,
                                                           const typename PartialRow<V>::T *prow, float *vval,
                                                           uint32_t *vocc, size_t NV)
 {
     using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= dev_count(P, p_dev) || aborted(fail)) return;
-    const uint32_t v = slot_vid[rec_slot[q]];
+    const uint32_t v = ovid[rec_own[q]];
     alignas(16) typename R::T row[R::S];
     load_row<V>(prow, q, row);
     atomicAdd(&vocc[v], (uint32_t)row[V]);
@@ -1142,14 +1142,14 @@ __global__ void __launch_bounds__(256) k_vertex_sum_atomic(size_t P, const uint3
 // W |mu - mu'|^2, far below the binary32 resolution of the sum).
 template <int V>
 __global__ void __launch_bounds__(256) k_vertex_scatter_atomic(size_t P, const uint32_t *p_dev, const uint32_t *fail,
-                                                              const uint32_t *rec_slot, const uint32_t *slot_vid,
+                                                              const uint32_t *rec_own, const uint32_t *ovid,
                                                               const typename PartialRow<V>::T *prow, float *vval,
                                                               size_t NV)
 {
     using R = PartialRow<V>;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= dev_count(P, p_dev) || aborted(fail)) return;
-    const uint32_t v = slot_vid[rec_slot[q]];
+    const uint32_t v = ovid[rec_own[q]];
     alignas(16) typename R::T row[R::S];
     load_row<V>(prow, q, row);
     const double W = (double)row[0];
@@ -1229,6 +1229,36 @@ __global__ void __launch_bounds__(256) k_cuckoo_insert(TileMap tm, const SetTabl
 // buckets -- two random 8-byte reads instead of the map's random 4-byte
 // writes and its read-back -- and writes its key and padded values there.  A
 // vertex the cuckoo pass failed to place writes nothing (the pass is redone).
+// One whole slot -- key, values padded to VP, zeros in the padding -- in
+// 16-byte stores: every byte of the slot is written, so no sector of the
+// table is written in part (a 16-byte key alone in a 64-byte slot wrote at
+// well under half the rate of whole slots).
+template <int KW, int V>
+__device__ __forceinline__ void store_slot(char *dst, const uint64_t (&key)[KW], const float (&val)[ValPad<V>::value])
+{
+    using G = SlotGeom<KW, V>;
+    constexpr uint32_t VP = ValPad<V>::value;
+    constexpr uint32_t kUnits = G::bytes / 16;
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+    for (uint32_t u = 0; u < kUnits; ++u) {
+        uint32_t w[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t byte = 16u * u + 4u * j;
+            uint32_t x = 0u;
+            if (byte < 8u * KW) {
+                const uint64_t k = key[byte / 8u];
+                x = (byte % 8u == 0u) ? (uint32_t)k : (uint32_t)(k >> 32);
+            } else if (byte >= G::val_off && byte < G::val_off + 4u * VP) {
+                x = __float_as_uint(val[(byte - G::val_off) / 4u]);
+            }
+            w[j] = x;
+        }
+        d[u] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 template <int KW, int V>
 __global__ void __launch_bounds__(256) k_slot_empty(size_t n_slots, const uint32_t *n_dev, const uint32_t *own,
                                                    char *table)
@@ -1236,9 +1266,13 @@ __global__ void __launch_bounds__(256) k_slot_empty(size_t n_slots, const uint32
     using G = SlotGeom<KW, V>;
     const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= dev_count(n_slots, n_dev) || own[j] != kOwnerEmpty) return;
-    uint64_t *key = reinterpret_cast<uint64_t *>(table + G::bytes * j);
+    uint64_t key[KW];
 #pragma unroll
     for (int w = 0; w < KW; ++w) key[w] = kKeyEmpty;
+    float val[ValPad<V>::value];
+#pragma unroll
+    for (int c = 0; c < ValPad<V>::value; ++c) val[c] = 0.0f;
+    store_slot<KW, V>(table + (size_t)G::bytes * j, key, val);
 }
 
 template <int KW, int V>
@@ -1267,16 +1301,10 @@ __global__ void __launch_bounds__(256) k_vertex_place(TileMap tm, const SetTable
     else if (o2.x == u) slot = (int64_t)kBucketSlots * b2;
     else if (o2.y == u) slot = (int64_t)kBucketSlots * b2 + 1;
     if (slot < 0) return;
-    char *dst = table + (size_t)G::bytes * (st.slot_base + (uint64_t)slot);
-    uint64_t *kd = reinterpret_cast<uint64_t *>(dst);
-#pragma unroll
-    for (int w = 0; w < KW; ++w) kd[w] = key[w];
     float val[VP];
 #pragma unroll
     for (int c = 0; c < VP; ++c) val[c] = c < V ? vval[(size_t)c * stride + v] : 0.0f;
-    float4 *vd = reinterpret_cast<float4 *>(dst + G::val_off);
-#pragma unroll
-    for (int q = 0; q < VP / 4; ++q) vd[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+    store_slot<KW, V>(table + (size_t)G::bytes * (st.slot_base + (uint64_t)slot), key, val);
 }
 
 // ---------------------------------------------------------------------------
@@ -1373,7 +1401,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     Pts pts{obs->x, obs->y, obs->z, obs->nx, obs->ny, obs->nz};
     using T = typename PartialType<V>::T;
 
-    DevBuf rec_key, rec_row, rec_slot, own1, t1_d, ptmap, rtmap, fail;
+    DevBuf rec_key, rec_row, rec_own, own1, t1_d, ptmap, rtmap, fail;
     FR_TRY(fail.alloc(ctx, sizeof(int32_t)));
     FR_TRY(t1_d.alloc(ctx, S * sizeof(SetTable)));
     StageEvents stage;
@@ -1436,7 +1464,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             FR_HIP(hipGetLastError());
         }
     }
-    FR_TRY(rec_slot.alloc(ctx, P * sizeof(uint32_t)));
+    FR_TRY(rec_own.alloc(ctx, P * sizeof(uint32_t)));
     lat->n_partials = (int64_t)P;
 
     stage.mark(1, st);
@@ -1446,7 +1474,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     constexpr int kInsertTile = 1024;
     FR_TRY(make_offset_map(ctx, roff, kInsertTile, st, rtmap, rtm, true));
     uint64_t n1 = 0;
-    DevBuf ovid, slot_vid, vb_d;
+    DevBuf ovid, vb_d;
     FR_TRY(ovid.alloc(ctx, (P + 1) * sizeof(uint32_t)));   // owner flags (and a 0), then their exclusive scan
     FR_TRY(vb_d.alloc(ctx, (S + 1) * sizeof(uint32_t)));
     std::vector<uint32_t> vb_h(S + 1);
@@ -1476,7 +1504,7 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         if (rtm.n_tiles > 0) {
             k_insert_records<KW, true, kInsertTile><<<grid_of(rtm), kInsertTile, 0, st>>>(
                 rtm, t1_d.as<SetTable>(), rec_key.as<uint64_t>(), P, own1.as<unsigned long long>(),
-                rec_slot.as<uint32_t>(), ovid.as<uint32_t>(), fail.as<int32_t>());
+                rec_own.as<uint32_t>(), ovid.as<uint32_t>(), fail.as<int32_t>());
             FR_HIP(hipGetLastError());
         }
         // 3. vertex ids in owner-record order and per-set ranges, enqueued before the
@@ -1501,7 +1529,6 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             return FR_EDEVICE;
         }
     }
-    FR_TRY(slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
     const uint32_t nv_total = vb_h[S];
     if (err_h != 0) {
         set_error("fr_lattice_build: a lattice coordinate left [-2^20, 2^20); increase sigma or centre the cloud");
@@ -1528,9 +1555,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         lat->vocc = reinterpret_cast<uint32_t *>(c + NV * (KW * sizeof(uint64_t) + V * sizeof(float)));
     }
     if (NV > 0) {
-        k_owner_emit<KW><<<blocks_for(P, 256), 256, 0, st>>>(P, rec_slot.as<uint32_t>(), ovid.as<uint32_t>(),
-                                                             rec_key.as<uint64_t>(), lat->vkey, NV,
-                                                             slot_vid.as<uint32_t>());
+        k_owner_emit<KW><<<blocks_for(P, 256), 256, 0, st>>>(P, ovid.as<uint32_t>(), rec_key.as<uint64_t>(),
+                                                             lat->vkey, NV);
         FR_HIP(hipGetLastError());
     }
 
@@ -1552,8 +1578,8 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
             TileMap srtm{};
             FR_TRY(make_offset_map(ctx, roff, kRsTile, st, stmap, srtm, true));
             uint32_t *svid = nullptr, *srid = nullptr;   // the sorted pairs
-            FR_TRY(segmented_sort_records(ctx, srtm, vb_d.as<uint32_t>(), rec_slot.as<uint32_t>(),
-                                          slot_vid.as<uint32_t>(), rvid.as<uint32_t>(), rid.as<uint32_t>(),
+            FR_TRY(segmented_sort_records(ctx, srtm, vb_d.as<uint32_t>(), rec_own.as<uint32_t>(),
+                                          ovid.as<uint32_t>(), rvid.as<uint32_t>(), rid.as<uint32_t>(),
                                           tk.as<uint32_t>(), tv.as<uint32_t>(), P, bits, st, &svid, &srid));
             k_segment_heads<<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, svid, voff.as<uint32_t>());
             FR_HIP(hipGetLastError());
@@ -1564,13 +1590,13 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
         } else {
             FR_HIP(hipMemsetAsync(lat->vval, 0, NV * V * sizeof(float), st));
             FR_HIP(hipMemsetAsync(lat->vocc, 0, NV * sizeof(uint32_t), st));
-            k_vertex_sum_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, rec_slot.as<uint32_t>(),
-                                                                        slot_vid.as<uint32_t>(), rec_row.as<T>(),
+            k_vertex_sum_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(P, nullptr, nullptr, rec_own.as<uint32_t>(),
+                                                                        ovid.as<uint32_t>(), rec_row.as<T>(),
                                                                         lat->vval, lat->vocc, NV);
             FR_HIP(hipGetLastError());
             if constexpr (ValLayout<V>::m2) {
                 k_vertex_scatter_atomic<V><<<blocks_for(P, 256), 256, 0, st>>>(
-                    P, nullptr, nullptr, rec_slot.as<uint32_t>(), slot_vid.as<uint32_t>(), rec_row.as<T>(), lat->vval,
+                    P, nullptr, nullptr, rec_own.as<uint32_t>(), ovid.as<uint32_t>(), rec_row.as<T>(), lat->vval,
                     NV);
                 FR_HIP(hipGetLastError());
             }
@@ -1579,10 +1605,9 @@ static fr_status build_impl(fr_ctx *ctx, const fr_cloud *obs, hipStream_t st, fr
     // the provisional table and records are no longer needed
     rec_key.reset();
     rec_row.reset();
-    rec_slot.reset();
+    rec_own.reset();
     own1.reset();
     ovid.reset();
-    slot_vid.reset();
 
     stage.mark(3, st);
     // 5. final bucketed two-choice cuckoo tables, load factor 0.5 (a bucket per
@@ -1721,7 +1746,7 @@ struct ResidentBuild {
     TileMap ptm{}, rtm{}, vtm{};
     DevBuf ptmap, rtmap, vtmap;   // tile-map arrays
     DevBuf offs;                  // int64: partial offsets [S + 1], then vertex offsets [S + 1]
-    DevBuf wave_cnt, rec_key, rec_row, rec_slot, ovid, own1, t1, slot_vid;
+    DevBuf wave_cnt, rec_key, rec_row, rec_own, ovid, own1, t1;
     DevBuf rvid, rid, tk, tv, voff, own2, ws, cnt;
     // valued points of each set end here (device, n_sets; NULL: all valued)
     const int64_t *valued_end = nullptr;
@@ -1892,21 +1917,19 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
     k_insert_records<KW, true><<<grid_of(rb->rtm), 256, 0, st>>>(rb->rtm, rb->t1.as<SetTable>(),
                                                                 rb->rec_key.as<uint64_t>(), R,
                                                                 rb->own1.as<unsigned long long>(),
-                                                                rb->rec_slot.as<uint32_t>(), rb->ovid.as<uint32_t>(),
+                                                                rb->rec_own.as<uint32_t>(), rb->ovid.as<uint32_t>(),
                                                                 reinterpret_cast<int32_t *>(cnt + kResFailInsert));
     FR_HIP(hipGetLastError());
     FR_TRY(scan_exclusive_u32(ctx, rb->ovid.as<uint32_t>(), rb->ovid.as<uint32_t>(), R + 1, 0, st, ws));
-    k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rb->rec_slot.as<uint32_t>(), rb->ovid.as<uint32_t>(),
-                                                         rb->rec_key.as<uint64_t>(), lat->vkey, R,
-                                                         rb->slot_vid.as<uint32_t>(), S, poff, voff64,
-                                                         cnt + kResNV);
+    k_owner_emit<KW><<<blocks_for(R, 256), 256, 0, st>>>(R, rb->ovid.as<uint32_t>(), rb->rec_key.as<uint64_t>(),
+                                                         lat->vkey, R, S, poff, voff64, cnt + kResNV);
     FR_HIP(hipGetLastError());
     // 4. values
     if (rb->sorted && R <= kListMax) {
         const uint32_t *fail_ins = cnt + kResFailInsert;
         uint32_t *vcount = rb->voff.as<uint32_t>(), *vfill = rb->tk.as<uint32_t>();   // zeroed by k_res_clear
-        k_list_count<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_slot.as<uint32_t>(),
-                                                          rb->slot_vid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
+        k_list_count<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_own.as<uint32_t>(),
+                                                          rb->ovid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
                                                           vcount);
         FR_TRY(scan_exclusive_u32(ctx, vcount, rb->rid.as<uint32_t>(), R, 0, st, ws));
         k_list_place<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rvid.as<uint32_t>(),
@@ -1918,8 +1941,8 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
         FR_HIP(hipGetLastError());
     } else if (rb->sorted) {
         const uint32_t *fail_ins = cnt + kResFailInsert;
-        k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_slot.as<uint32_t>(),
-                                                             rb->slot_vid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
+        k_record_vertex<<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, fail_ins, rb->rec_own.as<uint32_t>(),
+                                                             rb->ovid.as<uint32_t>(), rb->rvid.as<uint32_t>(),
                                                              rb->rid.as<uint32_t>());
         uint32_t *svid = nullptr, *srid = nullptr;
         FR_TRY(radix_sort_pairs(ctx, rb->rvid.as<uint32_t>(), rb->rid.as<uint32_t>(), rb->tk.as<uint32_t>(),
@@ -1934,12 +1957,12 @@ static fr_status resident_enqueue(ResidentBuild *rb, const float *kset, hipStrea
                                                                     (size_t)V * R, nullptr);
         k_fill_u32<<<blocks_for(R, 256), 256, 0, st>>>(lat->vocc, 0u, R, nullptr);
         k_vertex_sum_atomic<V><<<blocks_for(R, 256), 256, 0, st>>>(R, cnt + kResP, cnt + kResFailInsert,
-                                                                    rb->rec_slot.as<uint32_t>(),
-                                                                    rb->slot_vid.as<uint32_t>(), rb->rec_row.as<T>(),
+                                                                    rb->rec_own.as<uint32_t>(),
+                                                                    rb->ovid.as<uint32_t>(), rb->rec_row.as<T>(),
                                                                     lat->vval, lat->vocc, R);
         if constexpr (ValLayout<V>::m2)
             k_vertex_scatter_atomic<V><<<blocks_for(R, 256), 256, 0, st>>>(
-                R, cnt + kResP, cnt + kResFailInsert, rb->rec_slot.as<uint32_t>(), rb->slot_vid.as<uint32_t>(),
+                R, cnt + kResP, cnt + kResFailInsert, rb->rec_own.as<uint32_t>(), rb->ovid.as<uint32_t>(),
                 rb->rec_row.as<T>(), lat->vval, R);
         FR_HIP(hipGetLastError());
     }
@@ -2011,11 +2034,10 @@ static fr_status resident_setup(ResidentBuild *rb, const fr_cloud *obs, hipStrea
     FR_TRY(rb->wave_cnt.alloc(ctx, (rb->n_waves + 1) * sizeof(uint32_t)));
     FR_TRY(rb->rec_key.alloc(ctx, R * KW * sizeof(uint64_t)));
     FR_TRY(rb->rec_row.alloc(ctx, R * PartialRow<V>::S * sizeof(T)));
-    FR_TRY(rb->rec_slot.alloc(ctx, R * sizeof(uint32_t)));
+    FR_TRY(rb->rec_own.alloc(ctx, R * sizeof(uint32_t)));
     FR_TRY(rb->ovid.alloc(ctx, (R + 1) * sizeof(uint32_t)));
     FR_TRY(rb->own1.alloc(ctx, n1 * sizeof(unsigned long long)));
     FR_TRY(rb->t1.alloc(ctx, S * sizeof(SetTable)));
-    FR_TRY(rb->slot_vid.alloc(ctx, n1 * sizeof(uint32_t)));
     if (rb->sorted) {
         FR_TRY(rb->rvid.alloc(ctx, R * sizeof(uint32_t)));
         FR_TRY(rb->rid.alloc(ctx, R * sizeof(uint32_t)));
