@@ -154,6 +154,131 @@ template <int d, int V> struct DedupGeom {
     static_assert(NL >= 1, "a wave must hold at least one round of lookups");
 };
 
+// The lookups of a wave's distinct keys by lane pairs.  Lanes 2i and 2i+1
+// take entries e = 64 j + 32 h + i (h = 0, 1) and read the two slots of the
+// entry's bucket side by side, lane parity = slot: one load instruction
+// covers 32 buckets, two lanes per line, where a lane reading both key slots
+// and then the values of its own key touches a line per lane and piece.  The
+// lane whose slot holds the key (found by a ballot) tells the pair which slot
+// to read the values from; as in lookup_keys the second bucket is read only
+// when the first is full without the key.  Three dependent rounds: first-
+// bucket keys; second-bucket keys (skipped by a wave none of whose keys needs
+// them); the values, from the bucket that holds each key.  Keys are read from
+// the wave's LDS key region (src[e] names the lane and class that hold entry
+// e's key), which the values overwrite once every key read is done.  fnd[e] =
+// 1 found; absent keys get zero values.
+template <int d, int V, int NL>
+__device__ __forceinline__ void lookup_pairs(const SetTable &st, const char *kreg, const uint16_t *src, int32_t U,
+                                             float *vreg, uint8_t *fnd)
+{
+    constexpr int D = d + 1;
+    constexpr int KW = KeyWords<d>::value;
+    constexpr int KB = 8 * KW;
+    using SG = SlotGeom<KW, V>;
+    constexpr int VP = ValPad<V>::value;
+    constexpr int VU = VP / 4;   // 16-byte value pieces of a slot
+    constexpr int NE = 2 * NL;   // entries per lane pair
+    static_assert(KB <= 16 && 2 * SG::bytes <= 128 && VU <= 2, "a key fits one piece, a bucket one line");
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t half = (uint32_t)(lane & 1), pi = (uint32_t)(lane >> 1);
+    const uint32_t nb = st.cap >> 1;
+    const uint64_t *kb = st.keys;
+    auto entry = [&](int q) { return (int32_t)(64 * (q >> 1) + 32 * (q & 1) + (int)pi); };
+    auto key_of = [&](int32_t e, uint64_t(&k)[KW]) {
+        const uint32_t sc = src[e];
+        lds_get_key<KW>(kreg + ((int32_t)(sc >> 3) * D + (int32_t)(sc & 7u)) * KB, k);
+    };
+    auto matches = [&](const u32x4 &qv, const uint64_t(&k)[KW]) {
+        bool m = qv.x == (uint32_t)k[0] && qv.y == (uint32_t)(k[0] >> 32);
+        if constexpr (KW == 2) m = m && qv.z == (uint32_t)k[1] && qv.w == (uint32_t)(k[1] >> 32);
+        return m;
+    };
+    auto taken = [](const u32x4 &qv) { return !(qv.x == 0xFFFFFFFFu && qv.y == 0xFFFFFFFFu); };
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    // round 1: each lane's slot key of the first buckets
+    uint32_t bo1[NE], bo2[NE];
+    u32x4 kq[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int32_t e = entry(q);
+        bo1[q] = 0u;
+        bo2[q] = 0u;
+        kq[q] = zero;
+        if (e < U) {
+            uint64_t k[KW];
+            key_of(e, k);
+            uint32_t b1, b2;
+            key_buckets<KW>(k, st.seed, nb, b1, b2);
+            bo1[q] = b1 * SG::bucket;
+            bo2[q] = b2 * SG::bucket;
+            kq[q] = load_at<u32x4>(kb, bo1[q] + half * SG::bytes);
+        }
+    }
+    // state: bit 0 found, bit 1 the slot holding the key, bit 2 second bucket next, bit 3 found there
+    uint32_t state[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int32_t e = entry(q);
+        const bool live = e < U;
+        uint64_t k[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) k[w] = 0;
+        if (live) key_of(e, k);
+        const bool eq = live && matches(kq[q], k);
+        const bool tk = live && taken(kq[q]);
+        const uint64_t M = __ballot(eq), T = __ballot(tk);
+        const bool pe = ((M >> (lane ^ 1)) & 1ull) != 0ull, pt = ((T >> (lane ^ 1)) & 1ull) != 0ull;
+        const bool found = eq || pe;
+        const uint32_t slot = eq ? half : half ^ 1u;
+        const bool second = live && !found && tk && pt;
+        state[q] = (found ? 1u : 0u) | (slot << 1) | (second ? 4u : 0u);
+    }
+    // round 2 (if a wave's key needs it): each lane's slot key of the second buckets
+    bool any_second = false;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) any_second = any_second || (state[q] & 4u) != 0u;
+    if (__ballot(any_second) != 0ull) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            kq[q] = zero;
+            if (state[q] & 4u) kq[q] = load_at<u32x4>(kb, bo2[q] + half * SG::bytes);
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const bool sec = (state[q] & 4u) != 0u;
+            uint64_t k[KW];
+#pragma unroll
+            for (int w = 0; w < KW; ++w) k[w] = 0;
+            if (sec) key_of(entry(q), k);
+            const bool eq = sec && matches(kq[q], k);
+            const uint64_t M = __ballot(eq);
+            const bool pe = ((M >> (lane ^ 1)) & 1ull) != 0ull;
+            if (sec) state[q] = (eq || pe) ? (1u | ((eq ? half : half ^ 1u) << 1) | 8u) : 0u;
+        }
+    }
+    // round 3: the values of every key found, from the bucket that holds it
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        kq[q] = zero;
+        if ((state[q] & 1u) && half < (uint32_t)VU)
+            kq[q] = load_at<u32x4>(kb, ((state[q] & 8u) ? bo2[q] : bo1[q]) + ((state[q] >> 1) & 1u) * SG::bytes +
+                                           SG::val_off + 16u * half);
+    }
+    wave_sync();   // every key read: the values may overwrite the key region now
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int32_t e = entry(q);
+        if (e < U) {
+            if (half < (uint32_t)VU)
+                reinterpret_cast<float4 *>(vreg + e * VP)[half] = make_float4(
+                    __uint_as_float(kq[q].x), __uint_as_float(kq[q].y), __uint_as_float(kq[q].z),
+                    __uint_as_float(kq[q].w));
+            if (half == 0u) fnd[e] = (state[q] & 1u) ? 1 : 0;
+        }
+    }
+}
+
 // Slice of a wave's points with shared lookups.  live: the lane has a point
 // (dead lanes form the tail of the wave).  Returns acc for live lanes.
 template <int d, int V>
@@ -199,40 +324,8 @@ __device__ __forceinline__ void slice_wave_dedup(const SetTable &st, const uint6
     }
     wave_sync();
     // look every distinct key up once
-    uint64_t lk[G::NL][KW];
-    bool ll[G::NL];
-#pragma unroll
-    for (int j = 0; j < G::NL; ++j) {
-        const int32_t e = j * 64 + lane;
-        ll[j] = e < U;
-        if (ll[j]) {
-            const uint32_t sc = src[e];
-            lds_get_key<KW>(kreg + ((int32_t)(sc >> 3) * D + (int32_t)(sc & 7u)) * KB, lk[j]);
-        } else {
-#pragma unroll
-            for (int w = 0; w < KW; ++w) lk[j][w] = 0;
-        }
-    }
-    wave_sync();   // the keys are read: their LDS region takes the values now
-    uint32_t off[G::NL];
-    bool found[G::NL];
-    lookup_keys<KW, V, G::NL>(st, lk, ll, off, found);
     float *vreg = reinterpret_cast<float *>(lds);
-#pragma unroll
-    for (int j = 0; j < G::NL; ++j) {
-        if (ll[j]) {
-            float val[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) val[c] = 0.0f;
-            if (found[j]) load_vals<V>(st.vals, off[j], val);
-            const int32_t e = j * 64 + lane;
-            float4 *dst = reinterpret_cast<float4 *>(vreg + e * VP);
-#pragma unroll
-            for (int q = 0; q < VP / 4; ++q)
-                dst[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
-            fnd[e] = found[j] ? 1 : 0;
-        }
-    }
+    lookup_pairs<d, V, G::NL>(st, kreg, src, U, vreg, fnd);
     wave_sync();
     if (!live) return;
     if constexpr (ValLayout<V>::m2) {
