@@ -159,7 +159,7 @@ template <int d, int V> struct DedupGeom {
 // entry's bucket side by side, lane parity = slot: one load instruction
 // covers 32 buckets, two lanes per line, where a lane reading both key slots
 // and then the values of its own key touches a line per lane and piece.  The
-// lane whose slot holds the key (found by a ballot) tells the pair which slot
+// lane whose slot holds the key (told by a lane swap) tells the pair which slot
 // to read the values from; as in lookup_keys the second bucket is read only
 // when the first is full without the key.  Three dependent rounds: first-
 // bucket keys; second-bucket keys (skipped by a wave none of whose keys needs
@@ -194,26 +194,38 @@ __device__ __forceinline__ void lookup_pairs(const SetTable &st, const char *kre
         return m;
     };
     auto taken = [](const u32x4 &qv) { return !(qv.x == 0xFFFFFFFFu && qv.y == 0xFFFFFFFFu); };
+    // the other lane of the pair: quad_perm [1, 0, 3, 2] (every lane runs it)
+    auto swap_pair = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false); };
+    auto partner = [&](bool b) { return swap_pair(b ? 1u : 0u) != 0u; };
     const u32x4 zero = {0u, 0u, 0u, 0u};
 
-    // round 1: each lane's slot key of the first buckets
+    // bucket offsets: of entries q = 2j and 2j+1 each lane of a pair hashes
+    // the one of its parity and takes the other from its partner
     uint32_t bo1[NE], bo2[NE];
-    u32x4 kq[NE];
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int32_t e = entry(q);
-        bo1[q] = 0u;
-        bo2[q] = 0u;
-        kq[q] = zero;
+    for (int j = 0; j < NL; ++j) {
+        const int32_t e = entry(2 * j + (int)half);
+        uint32_t o1 = 0u, o2 = 0u;
         if (e < U) {
             uint64_t k[KW];
             key_of(e, k);
             uint32_t b1, b2;
             key_buckets<KW>(k, st.seed, nb, b1, b2);
-            bo1[q] = b1 * SG::bucket;
-            bo2[q] = b2 * SG::bucket;
-            kq[q] = load_at<u32x4>(kb, bo1[q] + half * SG::bytes);
+            o1 = b1 * SG::bucket;
+            o2 = b2 * SG::bucket;
         }
+        const uint32_t p1 = swap_pair(o1), p2 = swap_pair(o2);
+        bo1[2 * j] = half ? p1 : o1;
+        bo1[2 * j + 1] = half ? o1 : p1;
+        bo2[2 * j] = half ? p2 : o2;
+        bo2[2 * j + 1] = half ? o2 : p2;
+    }
+    // round 1: each lane's slot key of the first buckets
+    u32x4 kq[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        kq[q] = zero;
+        if (entry(q) < U) kq[q] = load_at<u32x4>(kb, bo1[q] + half * SG::bytes);
     }
     // state: bit 0 found, bit 1 the slot holding the key, bit 2 second bucket next, bit 3 found there
     uint32_t state[NE];
@@ -227,8 +239,7 @@ __device__ __forceinline__ void lookup_pairs(const SetTable &st, const char *kre
         if (live) key_of(e, k);
         const bool eq = live && matches(kq[q], k);
         const bool tk = live && taken(kq[q]);
-        const uint64_t M = __ballot(eq), T = __ballot(tk);
-        const bool pe = ((M >> (lane ^ 1)) & 1ull) != 0ull, pt = ((T >> (lane ^ 1)) & 1ull) != 0ull;
+        const bool pe = partner(eq), pt = partner(tk);
         const bool found = eq || pe;
         const uint32_t slot = eq ? half : half ^ 1u;
         const bool second = live && !found && tk && pt;
@@ -252,8 +263,7 @@ __device__ __forceinline__ void lookup_pairs(const SetTable &st, const char *kre
             for (int w = 0; w < KW; ++w) k[w] = 0;
             if (sec) key_of(entry(q), k);
             const bool eq = sec && matches(kq[q], k);
-            const uint64_t M = __ballot(eq);
-            const bool pe = ((M >> (lane ^ 1)) & 1ull) != 0ull;
+            const bool pe = partner(eq);
             if (sec) state[q] = (eq || pe) ? (1u | ((eq ? half : half ^ 1u) << 1) | 8u) : 0u;
         }
     }
