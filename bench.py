@@ -1,9 +1,11 @@
 """Benchmark: batched rigid point-to-plane registration of depth-frame pairs on one MI355X.
 
 One step = one fr_register call over a batch of B pairs (default 64): lattice
-build of every observation, then 20 EM iterations of E-step (slice), M-step
-reduction and binary64 solve/update, all through the C ABI.  Inputs are
-resident in HBM before the timed region starts.
+build of every observation, then 20 EM iterations of E-step (slice) and M-step
+reduction -- by default in one fused kernel (FR_FUSED; --fused 0 runs them as
+two kernels, and the line reports that form's step beside) -- and binary64
+solve/update, all through the C ABI.  Inputs are resident in HBM before the
+timed region starts.
 
 Workload: 640x480 pinhole depth renders (fx = fy = 525) of 3 planes + 5
 spheres (about 260k points with normals); observation = the scene after a
@@ -46,6 +48,9 @@ import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 EST_BYTES_PER_POINT = 24 + 28          # model position + normal in, M0 + M1 + N out (binary32)
 FUSED_BYTES_PER_POINT = 24             # fused slice + reduction: only the model point and normal move
+PARTIAL_ROW_BYTES = 32 * 4             # fused: one binary32 partial row of the normal equations per tile
+FUSED_TILE = 256                       # points per fused tile (the E-step tile)
+TUNE_FUSED = 16                        # autotuner entries of the fused kernel: 16 + transform kind
 VERTEX_BYTES = 16 + 4 * 7              # packed 6-coordinate key + 7 binary32 values
 ITERS = 20
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "estep_depth64_counters.json")
@@ -652,7 +657,10 @@ def main():
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--iters", type=int, default=ITERS)
     ap.add_argument("--splat", choices=["sorted", "atomic"], default="sorted")
-    ap.add_argument("--fused", type=int, default=0, help="1: slice and reduction in one kernel (FR_FUSED)")
+    ap.add_argument("--fused", type=int, default=1,
+                    help="1: slice and reduction in one kernel (FR_FUSED, the default); 0: two kernels")
+    ap.add_argument("--unfused-steps", type=int, default=3,
+                    help="with --fused 1: steps of the two-kernel form timed after the headline, for comparison")
     ap.add_argument("--slice", choices=["auto", "plain", "shared"], default="auto",
                     help="E-step slice kernel (auto: the library's autotuner picks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -734,18 +742,46 @@ def main():
     n_vertices = sum(lat.stats(s)[0] for s in range(len(pairs)))
     lat.close()
 
+    unfused = None
+    if args.fused and args.unfused_steps > 0:
+        # the same registrations with slice and reduction as two kernels, for comparison
+        prm2 = fr.register_params(6, "pt2pl", sigma, sigma_n, iters=args.iters, w=0.1, fixed=True, profile=True,
+                                  splat=splat, fused=False)
+        fr.register(ctx, model, obs, prm2, T0=T0)   # warm-up (and the slice autotuner)
+        torch.cuda.synchronize()
+        u_est, u_n, u_m = 0.0, 0, 0.0
+        t_u = time.perf_counter()
+        for _ in range(args.unfused_steps):
+            _, _, rep2 = fr.register(ctx, model, obs, prm2, T0=T0)
+            u_est += rep2.estep_ms
+            u_n += rep2.estep_launches
+            u_m += rep2.mstep_ms
+        torch.cuda.synchronize()
+        u_s = (time.perf_counter() - t_u) / args.unfused_steps
+        unfused = {"ms_per_step": u_s * 1e3, "value": sum(M) * args.iters / u_s,
+                   "estep_ms_per_launch": u_est / max(1, u_n),
+                   "reduction_ms_per_iter": u_m / (args.unfused_steps * args.iters),
+                   "estep_roofline": {"bytes_per_point": EST_BYTES_PER_POINT,
+                                      "achieved_gbs": (sum(M) * EST_BYTES_PER_POINT + touched * VERTEX_BYTES)
+                                      / (u_est / max(1, u_n) / 1e3) / 1e9}}
+        unfused["estep_roofline"]["frac"] = unfused["estep_roofline"]["achieved_gbs"] / HBM_PEAK_GBS
+        log(f"two-kernel form: {unfused['ms_per_step']:.2f} ms/step, E-step {unfused['estep_ms_per_launch']:.3f} "
+            f"ms/launch")
+
     points_per_launch = sum(M)
     per_point = FUSED_BYTES_PER_POINT if args.fused else EST_BYTES_PER_POINT
-    alg_bytes = points_per_launch * per_point + touched * VERTEX_BYTES
+    tiles = sum((m + FUSED_TILE - 1) // FUSED_TILE for m in M)
+    alg_bytes = points_per_launch * per_point + touched * VERTEX_BYTES + (tiles * PARTIAL_ROW_BYTES if args.fused else 0)
     est_avg_s = est_ms / max(1, est_n) / 1e3
     achieved = alg_bytes / est_avg_s / 1e9
     tuned = fr.fr_ctx_tuning_table(ctx.h)
     chosen = {"auto": None, "plain": fr.FR_SLICE_PLAIN, "shared": fr.FR_SLICE_SHARED}[args.slice]
     if chosen is None:
-        big = [e for e in tuned if e["d"] == 6 and e["V"] == 7 and e["xf_kind"] == fr.FR_XF_RIGID]
+        kind = fr.FR_XF_RIGID + (TUNE_FUSED if args.fused else 0)
+        big = [e for e in tuned if e["d"] == 6 and e["V"] == 7 and e["xf_kind"] == kind]
         chosen = max(big, key=lambda e: e["size_class"])["slice"] if big else fr.FR_SLICE_PLAIN
     if args.fused:
-        kernel = "k_estep_fused<6,7,rigid,pt2pl>"
+        kernel = "k_estep_fused<6,7,rigid,pt2pl,%s>" % fr.SLICE_NAMES[chosen]
     elif chosen == fr.FR_SLICE_SHARED:
         kernel = "k_estep_dedup<6,7,rigid>"
     else:
@@ -785,6 +821,7 @@ def main():
         "roofline": {
             "kernel": kernel,
             "bytes_per_point": per_point, "bytes_per_touched_vertex": VERTEX_BYTES,
+            "partial_row_bytes_per_tile": PARTIAL_ROW_BYTES if args.fused else 0,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -797,6 +834,8 @@ def main():
             "frac_of_measured_copy": achieved / copy_gbs,
         },
     }
+    if unfused is not None:
+        out["unfused"] = unfused
     if not args.no_other:
         log("other workloads and build rates ...")
         out["other_workloads"] = other_workloads(fr, ctx)

@@ -102,7 +102,9 @@ typedef struct {
 } fr_tuning;
 fr_status fr_ctx_set_tuning(fr_ctx *ctx, const fr_tuning *tuning);
 
-/* One choice of the autotuner: the mean launch times it measured (us). */
+/* One choice of the autotuner: the mean launch times it measured (us).
+ * xf_kind: the E-step's transform (FR_XF_*), or 16 + it for the fused slice
+ * and reduction (FR_FUSED). */
 typedef struct {
     int32_t d, V, xf_kind, size_class;
     int32_t slice;         /* FR_SLICE_PLAIN or FR_SLICE_SHARED */

@@ -378,18 +378,20 @@ __device__ __forceinline__ void slice_wave_dedup(const SetTable &st, const uint6
     }
 }
 
+// The shared-lookup slice of this thread's point of tile t (segment s): x =
+// the moved point, acc = its sums; false for a lane without a point.  The
+// lanes of a wave with a point in the segment all take part (run detection
+// and lookups are wave-wide); a wave wholly past the segment does nothing.
 template <int d, int V, bool XF>
-__device__ __forceinline__ void estep_dedup_tile(const EstepArgs &a, int32_t t, char *lds)
+__device__ __forceinline__ bool dedup_point(const EstepArgs &a, int32_t s, int32_t t, char *lds, int64_t &i,
+                                            float (&x)[3], float (&acc)[V])
 {
-    using G = DedupGeom<d, V>;
     constexpr int D = d + 1;
     constexpr int KW = KeyWords<d>::value;
-    const int32_t s = tile_segment(a.tm, t);
-    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
     const int64_t i0 = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile;
-    const int64_t i = i0 + threadIdx.x;
+    i = i0 + threadIdx.x;
     const int64_t end = a.tm.seg_end[s];
-    if (i0 + (int64_t)(threadIdx.x & ~63u) >= end) return;   // the whole wave is past the segment
+    if (i0 + (int64_t)(threadIdx.x & ~63u) >= end) return false;   // the whole wave is past the segment
     const bool live = i < end;
     const SetTable st = a.sets[a.tm.seg_set[s]];
     float p[d];
@@ -423,9 +425,21 @@ __device__ __forceinline__ void estep_dedup_tile(const EstepArgs &a, int32_t t, 
     int32_t sdiv = 0;
     const bool ok = embed<d>(p, kk, keys, b, &sdiv);
     if (live && !ok) atomicOr(a.err + a.err_stride * s, 1);
-    float acc[V];
     slice_wave_dedup<d, V>(st, keys, b, sdiv, live, lds, acc);
-    if (!live) return;
+    x[0] = p[0];
+    x[1] = p[1];
+    x[2] = p[2];
+    return live;
+}
+
+template <int d, int V, bool XF>
+__device__ __forceinline__ void estep_dedup_tile(const EstepArgs &a, int32_t t, char *lds)
+{
+    const int32_t s = tile_segment(a.tm, t);
+    if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;
+    int64_t i = 0;
+    float x[3], acc[V];
+    if (!dedup_point<d, V, XF>(a, s, t, lds, i, x, acc)) return;
     st_stream(a.m0 + i, acc[0]);
     st_stream(a.m1 + i, acc[1]);
     st_stream(a.m1 + a.M + i, acc[2]);
@@ -460,26 +474,85 @@ __global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
     }
 }
 
+// One lane's value of another lane `OFF` apart (lane ^ OFF): a swizzle
+// within 32 lanes, a permute across the halves of the wave.
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v)
+{
+    if constexpr (OFF == 32) return __shfl_xor(v, 32, 64);
+    else return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (OFF << 10) | 0x1F));
+}
+
+template <int OFF, int HALF>
+__device__ __forceinline__ void halve(float (&v)[kRedVals], int lane)
+{
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+        const float send = up ? v[k] : v[k + HALF];
+        const float keep = up ? v[k + HALF] : v[k];
+        v[k] = keep + xor_lane<OFF>(send);
+    }
+}
+
+// The block's partial row of the normal equations.  Each wave sums its 32
+// terms over its 64 lanes by halving exchanges (a lane keeps the half of its
+// values its lane bit selects and adds its partner's sums of that half: five
+// rounds leave value lane >> 1, summed over 32 lanes, and one more exchange
+// adds the other lane of the pair -- 32 exchanges where one butterfly per
+// value takes 192); the even lanes put the wave's sums in `wrow` (32 floats
+// of LDS per wave, `stride` floats apart), and the first 32 threads add the
+// four waves in order.
+__device__ __forceinline__ void block_partials_halving(float (&v)[kRedVals], float *wrow, int stride, float *row)
+{
+    static_assert(kRedVals == 32, "five halvings of 32 values");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    halve<32, 16>(v, lane);
+    halve<16, 8>(v, lane);
+    halve<8, 4>(v, lane);
+    halve<4, 2>(v, lane);
+    halve<2, 1>(v, lane);
+    v[0] += xor_lane<1>(v[0]);
+    if ((lane & 1) == 0) wrow[wave * stride + (lane >> 1)] = v[0];
+    __syncthreads();
+    if (threadIdx.x < kRedVals) {
+        float t = 0.0f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) t += wrow[w * stride + threadIdx.x];
+        row[threadIdx.x] = t;
+    }
+}
+
 // Fused slice + reduction: every point's M-step terms (Eq. 7 / Eq. 10 in the
 // twist of Eq. 16) are formed right after its slice and the block writes one
 // partial row of the normal equations per tile; M0, M1 and N never leave the
-// chip.
-template <int d, int V, bool XF, int RES>
-__global__ void __launch_bounds__(256) k_estep_fused(EstepArgs a)
+// chip.  SHARED: the shared-lookup slice (its per-wave LDS region holds the
+// wave's sums once its slice is done), else the per-point slice.
+template <int d, int V, bool XF, int RES, bool SHARED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHARED ? 5 : 1))) k_estep_fused(EstepArgs a)
 {
-    __shared__ float part[4][kRedStride];
+    using G = DedupGeom<d, V>;
+    constexpr int kWaveLds = SHARED ? G::wave_bytes : kRedStride * (int)sizeof(float);
+    __shared__ __attribute__((aligned(16))) char lds[4 * kWaveLds];
     const int32_t t = logical_tile(a.tm);
     if (t >= a.tm.n_tiles) return;
     const int32_t s = tile_segment(a.tm, t);
     if (a.active != nullptr && a.active[a.tm.seg_set[s]] == 0) return;   // no partial row: the set is not solved
-    const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+    const int wave = threadIdx.x >> 6;
     float red[kRedVals];
 #pragma unroll
     for (int j = 0; j < kRedVals; ++j) red[j] = 0.0f;
-    if (i < a.tm.seg_end[s]) {
-        const SetTable st = a.sets[a.tm.seg_set[s]];
-        float x[3], acc[V];
-        slice_point<d, V, XF>(a, s, i, st, x, acc);
+    float x[3], acc[V];
+    bool live;
+    if constexpr (SHARED) {
+        int64_t i = 0;
+        live = dedup_point<d, V, XF>(a, s, t, lds + wave * kWaveLds, i, x, acc);
+    } else {
+        const int64_t i = a.tm.seg_off[s] + (int64_t)(t - a.tm.seg_tile[s]) * a.tm.tile + threadIdx.x;
+        live = i < a.tm.seg_end[s];
+        if (live) slice_point<d, V, XF>(a, s, i, a.sets[a.tm.seg_set[s]], x, acc);
+    }
+    if (live) {
         const float c = a.seg_c[s];
         if constexpr (RES == FR_PT2PL)
             mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], c,
@@ -488,7 +561,9 @@ __global__ void __launch_bounds__(256) k_estep_fused(EstepArgs a)
             mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], 0.0f, 0.0f, 0.0f, c,
                              a.normalize_n);
     }
-    block_partials(red, part, a.partials + (size_t)t * kRedStride);
+    wave_sync();   // the wave's slice has read its LDS region
+    block_partials_halving(red, reinterpret_cast<float *>(lds), kWaveLds / (int)sizeof(float),
+                           a.partials + (size_t)t * kRedStride);
 }
 
 // Diagnostic twin of k_estep: marks every table slot a lookup finds.
@@ -561,6 +636,9 @@ static void launch_dv(const EstepArgs &a, bool xf, bool touch, int slice, int gr
 // outputs, so the timing launches are that E-step -- and the faster form is
 // kept in the context's table.  One wait for the stream; nothing is timed
 // while the stream is being captured into a graph.
+// Autotuner entries of the fused slice + reduction carry this plus the transform kind.
+constexpr int kTuneFused = 16;
+
 template <class Launch>
 static fr_status autotune_slice(fr_ctx *ctx, int d, int V, int xf_kind, int64_t pts, bool tune_new, hipStream_t st,
                                 Launch &launch, int &slice)
@@ -709,16 +787,23 @@ int estep_persistent_grid(int d, int V, int slice)
     return 0;
 }
 
-template <int d, int V>
-static void launch_fused_dv(const EstepArgs &a, int residual, int grid, hipStream_t st)
+template <int d, int V, bool SHARED>
+static void launch_fused_dvs(const EstepArgs &a, int residual, int grid, hipStream_t st)
 {
     if constexpr (V == 7) {
         if (residual == FR_PT2PL) {
-            k_estep_fused<d, V, true, FR_PT2PL><<<grid, 256, 0, st>>>(a);
+            k_estep_fused<d, V, true, FR_PT2PL, SHARED><<<grid, 256, 0, st>>>(a);
             return;
         }
     }
-    k_estep_fused<d, V, true, FR_PT2PT><<<grid, 256, 0, st>>>(a);
+    k_estep_fused<d, V, true, FR_PT2PT, SHARED><<<grid, 256, 0, st>>>(a);
+}
+
+template <int d, int V>
+static void launch_fused_dv(const EstepArgs &a, int residual, int slice, int grid, hipStream_t st)
+{
+    if (slice == FR_SLICE_SHARED) launch_fused_dvs<d, V, true>(a, residual, grid, st);
+    else launch_fused_dvs<d, V, false>(a, residual, grid, st);
 }
 
 fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, int32_t err_stride,
@@ -747,16 +832,23 @@ fr_status launch_estep_fused(int d, int V, const SetTable *sets, int32_t *err, i
     a.partials = partials;
     a.normalize_n = normalize_n;
     a.active = active;
-    if (d == 3 && V == 4) launch_fused_dv<3, 4>(a, residual, plan.grid, st);
-    else if (d == 3 && V == 7) launch_fused_dv<3, 7>(a, residual, plan.grid, st);
-    else if (d == 6 && V == 4) launch_fused_dv<6, 4>(a, residual, plan.grid, st);
-    else if (d == 6 && V == 7) launch_fused_dv<6, 7>(a, residual, plan.grid, st);
-    else {
+    if (!((d == 3 || d == 6) && (V == 4 || V == 7))) {
         set_error("fused E-step: unsupported lattice d=%d V=%d", d, V);
         return FR_EINVAL;
     }
-    FR_HIP(hipGetLastError());
-    return FR_OK;
+    auto launch = [&](int slice) -> fr_status {
+        if (d == 3 && V == 4) launch_fused_dv<3, 4>(a, residual, slice, plan.grid, st);
+        else if (d == 3 && V == 7) launch_fused_dv<3, 7>(a, residual, slice, plan.grid, st);
+        else if (d == 6 && V == 4) launch_fused_dv<6, 4>(a, residual, slice, plan.grid, st);
+        else launch_fused_dv<6, 7>(a, residual, slice, plan.grid, st);
+        FR_HIP(hipGetLastError());
+        return FR_OK;
+    };
+    int slice = plan.slice;
+    if (slice == FR_SLICE_AUTO)
+        FR_TRY(autotune_slice(plan.ctx, d, V, kTuneFused + FR_XF_RIGID, (int64_t)plan.n_tiles * plan.tile,
+                              plan.tune_new_classes, st, launch, slice));
+    return launch(slice);
 }
 
 // Descriptor E-step (Eq. 8 with the features alone): one model point per

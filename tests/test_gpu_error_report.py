@@ -113,6 +113,13 @@ def test_registration_poses(fr, ctx):
     assert st[0] == 0
     _report("depth frame, 20 iterations: pose rotation (rad)", ang, 1e-4)
     _report("depth frame, 20 iterations: pose translation (m)", dt, 1e-4)
+    # the same registration with the slice and the reduction in one kernel (the benchmark's step)
+    prm = fr.register_params(6, "pt2pl", p.sigma, p.sigma_n, iters=20, w=p.w, fused=True)
+    T, st, _ = fr.register(ctx, upload([p.model], [p.model_n]), upload([p.obs], [p.obs_n]), prm, T0=T0[None])
+    ang, dt, _ = pose_close(T[0], ref)
+    assert st[0] == 0
+    _report("depth frame, 20 iterations, fused slice + reduction: pose rotation (rad)", ang, 1e-4)
+    _report("depth frame, 20 iterations, fused slice + reduction: pose translation (m)", dt, 1e-4)
 
     e = synth.ellipsoid_pair(1)
     T0 = e.T_gt @ oracle.se3_exp(np.array([0.01, -0.01, 0.005, 0.004, 0.0, -0.003]))

@@ -441,6 +441,34 @@ def test_register_fused_matches_oracle_other_variants(fr, ctx, feat, residual):
     assert ok, (ang, dt)
 
 
+@pytest.mark.parametrize("feat,residual", [(6, "pt2pl"), (3, "pt2pt")])
+def test_fused_shared_and_plain_slices_agree_bitwise(fr, ctx, feat, residual):
+    """The fused slice + reduction with the shared-lookup slice and with the per-point slice: their slice
+    sums are bitwise the same and the reduction is one code, so the poses must be identical; both are
+    held to the oracle."""
+    q = synth.depth_pair(4, width=320, height=240, f=262.5)
+    T0 = q.T_gt @ oracle.se3_exp(np.array([0.004, -0.003, 0.002, 0.004, 0.003, -0.002]))
+    prm = fr.register_params(feat, residual, q.sigma, q.sigma_n, iters=12, w=0.1, fused=True)
+    nrm = feat == 6 or residual == "pt2pl"
+    model = upload([q.model], [q.model_n] if feat == 6 else None)
+    obs = upload([q.obs], [q.obs_n] if nrm else None)
+    _say(f"[fused-forms] feat={feat} {residual} model {len(q.model)} points")
+    T = {}
+    try:
+        for sl in (fr.FR_SLICE_PLAIN, fr.FR_SLICE_SHARED):
+            fr.fr_ctx_set_tuning(ctx.h, sl)
+            T[sl], st, _ = fr.register(ctx, model, obs, prm, T0=T0[None])
+            assert int(st[0]) == 0
+    finally:
+        fr.fr_ctx_set_tuning(ctx.h, fr.FR_SLICE_AUTO)
+    np.testing.assert_array_equal(T[fr.FR_SLICE_PLAIN], T[fr.FR_SLICE_SHARED])
+    ref = oracle.register_rigid(q.model, q.model_n if feat == 6 else None, q.obs, q.obs_n if nrm else None,
+                                feat=feat, residual=residual, sigma=q.sigma, sigma_n=q.sigma_n, w=0.1, iters=12,
+                                T0=T0)
+    ang, dt, ok = pose_close(T[fr.FR_SLICE_SHARED][0], ref)
+    assert ok, (ang, dt)
+
+
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("fixed", [True, False])
 def test_graph_replay_equals_the_eager_loop(fr, ctx, fixed, fused):
