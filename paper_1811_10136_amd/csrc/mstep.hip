@@ -6,8 +6,8 @@
 // in binary32 registers over its points; the block reduces the 31 values with
 // wavefront butterflies and an LDS exchange between its 4 waves and writes one
 // partial row per tile.  k_reduce_final: one block per segment sums its
-// tiles' partial rows in tile order in binary64 (fixed order -> bitwise
-// reproducible) and applies the 1/sigma^2 of the residual scaling.
+// tiles' partial rows in binary64 in a fixed order (bitwise reproducible)
+// and applies the 1/sigma^2 of the residual scaling.
 #include "fr_internal.h"
 #include "fr_mstep.h"
 
@@ -86,33 +86,52 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceArgs a)
     }
 }
 
-// One block per segment: 8 lanes per value each sum every 8th tile in binary64,
-// then the 8 lane sums are added in lane order (fixed order, reproducible).
-constexpr int kFinalLanes = 8;
+// One block per segment.  Thread (g, j) of the 32 x 32 threads sums value j
+// of tiles g, g + 32, g + 64, ... in binary64 -- four interleaved chains
+// (tiles g + 128 k + 32 u for chain u), added in chain order at the end, so
+// four loads are in flight per thread -- and the 32 group sums are then added
+// in group order: a fixed order, reproducible, and one wave reads two whole
+// partial rows per load.
+constexpr int kFinalGroups = 32;
+constexpr int kFinalChains = 4;
 
-__global__ void __launch_bounds__(256) k_reduce_final(TileMap tm, const float *partials, double inv_s2, double *jtj,
-                                                      double *jtr, double *stats, double *var_stat)
+__global__ void __launch_bounds__(kFinalGroups * kRedVals) k_reduce_final(TileMap tm, const float *partials,
+                                                                          double inv_s2, double *jtj, double *jtr,
+                                                                          double *stats, double *var_stat)
 {
-    __shared__ double lane_sum[kRedVals][kFinalLanes];
+    __shared__ double group_sum[kFinalGroups][kRedVals];
     const int32_t s = blockIdx.x;
-    const int j = threadIdx.x / kFinalLanes;
-    const int l = threadIdx.x % kFinalLanes;
-    if (j < kRedVals) {
-        double acc = 0.0;
-        for (int32_t t = tm.seg_tile[s] + l; t < tm.seg_tile[s + 1]; t += kFinalLanes)
-            acc += (double)partials[(size_t)t * kRedStride + j];
-        lane_sum[j][l] = acc;
+    const int j = threadIdx.x % kRedVals;
+    const int g = threadIdx.x / kRedVals;
+    const int32_t t0 = tm.seg_tile[s], t1 = tm.seg_tile[s + 1];
+    double acc[kFinalChains];
+#pragma unroll
+    for (int u = 0; u < kFinalChains; ++u) acc[u] = 0.0;
+    constexpr int32_t kStep = kFinalGroups * kFinalChains;
+    for (int32_t t = t0 + g; t < t1; t += kStep) {
+        float v[kFinalChains];
+#pragma unroll
+        for (int u = 0; u < kFinalChains; ++u) {
+            const int32_t tu = t + u * kFinalGroups;
+            v[u] = tu < t1 ? partials[(size_t)tu * kRedStride + j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinalChains; ++u) acc[u] += (double)v[u];
     }
+    double sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFinalChains; ++u) sum += acc[u];
+    group_sum[g][j] = sum;
     __syncthreads();
     if (threadIdx.x < kRedVals) {
         const int jj = threadIdx.x;
-        double acc = 0.0;
+        double tot = 0.0;
 #pragma unroll
-        for (int q = 0; q < kFinalLanes; ++q) acc += lane_sum[jj][q];
-        if (jj < 21) jtj[(size_t)s * 21 + jj] = acc * inv_s2;
-        else if (jj < 27) jtr[(size_t)s * 6 + (jj - 21)] = acc * inv_s2;
-        else if (jj < 31) stats[(size_t)s * 4 + (jj - 27)] = (jj == 28) ? acc * inv_s2 : acc;
-        else if (var_stat != nullptr) var_stat[s] = acc;
+        for (int q = 0; q < kFinalGroups; ++q) tot += group_sum[q][jj];
+        if (jj < 21) jtj[(size_t)s * 21 + jj] = tot * inv_s2;
+        else if (jj < 27) jtr[(size_t)s * 6 + (jj - 21)] = tot * inv_s2;
+        else if (jj < 31) stats[(size_t)s * 4 + (jj - 27)] = (jj == 28) ? tot * inv_s2 : tot;
+        else if (var_stat != nullptr) var_stat[s] = tot;
     }
 }
 
@@ -122,7 +141,8 @@ fr_status launch_reduce_final(const Plan &plan, const float *partials, double si
                               double *stats, hipStream_t st, double *var_stat)
 {
     if (plan.n_seg == 0) return FR_OK;
-    k_reduce_final<<<plan.n_seg, 256, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj, jtr, stats, var_stat);
+    k_reduce_final<<<plan.n_seg, kFinalGroups * kRedVals, 0, st>>>(plan.tm, partials, 1.0 / (sigma * sigma), jtj,
+                                                                     jtr, stats, var_stat);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
