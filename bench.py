@@ -677,7 +677,7 @@ def main():
     ap.add_argument("--serve-tol", type=float, default=1e-6,
                     help="a request stops after a step with |omega| and |v| below this (0: all iterations)")
     ap.add_argument("--serve-capacity-requests", type=int, default=256)
-    ap.add_argument("--serve-lambdas", type=float, nargs="*", default=[1.0, 2.0, 4.0, 8.0])
+    ap.add_argument("--serve-lambdas", type=float, nargs="*", default=[1.0, 2.0, 4.0, 8.0, 12.0, 16.0])
     ap.add_argument("--plain-lambdas", type=float, nargs="*", default=[1.0])
     ap.add_argument("--profile-workload", choices=["nodegraph", "articulated", "descriptors", "uncustomised",
                                                     "updated-sigma"],
