@@ -1542,7 +1542,8 @@ fr_status fr_register(fr_ctx *ctx, const fr_cloud *model_ref, const fr_cloud *ob
                 FR_TRY(blur_lattice(lat, st));
                 rep.build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
                 elat = lat;
-            }            if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
+            }
+            if (prof) FR_HIP(hipEventRecord(ev[3 * it], st));
             if (fused) {
                 FR_TRY(launch_estep_fused(elat->d, elat->V, elat->sets_d, elat->err_d, 0, model_ref, pe,
                                           wmats.as<float>(), params->residual, 0, part.as<float>(), st, act));
