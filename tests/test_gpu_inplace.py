@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from _helpers import assert_estep_close, oracle_lattice, soa, upload
+from _helpers import assert_estep_close, assert_lattice_equal, oracle_lattice, soa, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -170,3 +170,36 @@ def test_inplace_lattice_refuses_what_it_does_not_hold(fr, ctx):
     finally:
         plain.close()
         fr.fr_lattice_destroy(lat)
+
+
+def test_one_shot_build_of_a_set_beyond_two_sort_passes(fr, ctx):
+    """A full 640x480 frame at sigma 0.02 m has about 322k vertices in one set, more than the 2^18 that the
+    one-shot build's two 9-bit passes over per-set vertex ids cover, so its sort takes a third pass.  The
+    lattice equals the oracle's (keys and counts exactly), and its slice is bitwise that of the in-place build,
+    which sorts the same records by global vertex id in 8-bit passes."""
+    p = synth.depth_pair(0)
+    sig = 0.02
+    obs = upload([p.obs], [p.obs_n])
+    model = upload([p.model], [p.model_n])
+    prm = fr.lattice_params(6, 7, (sig, sig, sig), p.sigma_n, 0)
+    lat = fr.Lattice(ctx, obs, prm)
+    res = None
+    try:
+        nv = lat.stats(0)[0]
+        _say(f"[sort-3-pass] {len(p.obs)} observation points, {nv} vertices")
+        assert nv > 1 << 18
+        keys, occ, vals = lat.export(0)
+        ref = oracle_lattice(p.obs, p.obs_n, 6, "pt2pl", (sig, sig, sig), p.sigma_n)
+        assert_lattice_equal(keys, occ, vals, ref, float(np.abs(p.obs).max()))
+        res = fr.fr_lattice_build_inplace(ctx.h, obs, prm, None)
+        fr.fr_lattice_rebuild(res, [sig])
+        fr.fr_sync_status(res)
+        mats = _mats([p.T_gt])
+        a = _estep(fr, res, model, mats, 7)
+        b = _estep(fr, lat.h, model, mats, 7)
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u.view(np.uint32), v.view(np.uint32))
+    finally:
+        if res is not None:
+            fr.fr_lattice_destroy(res)
+        lat.close()
