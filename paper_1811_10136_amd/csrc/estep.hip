@@ -486,12 +486,26 @@ __device__ __forceinline__ float xor_lane(float v)
 template <int OFF, int HALF>
 __device__ __forceinline__ void halve(float (&v)[kRedVals], int lane)
 {
-    const bool up = (lane & OFF) != 0;
+    if constexpr (OFF == 32 || OFF == 16) {
+        // gfx950's lane swaps exchange the upper OFF lanes of each 2 OFF-lane group of the first operand
+        // with the lower OFF lanes of the second: the first result holds v[k] in the lower and v[k + HALF]
+        // of the lower partner in the upper lanes, the second the partners' values, so their sum is the
+        // exchange and addition below with no selects (the same sums: addition commutes)
 #pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-        const float send = up ? v[k] : v[k + HALF];
-        const float keep = up ? v[k + HALF] : v[k];
-        v[k] = keep + xor_lane<OFF>(send);
+        for (int k = 0; k < HALF; ++k) {
+            const uint32_t a = __float_as_uint(v[k]), b = __float_as_uint(v[k + HALF]);
+            const auto r = OFF == 32 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
+                                     : __builtin_amdgcn_permlane16_swap(a, b, false, false);
+            v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        }
+    } else {
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            const float send = up ? v[k] : v[k + HALF];
+            const float keep = up ? v[k + HALF] : v[k];
+            v[k] = keep + xor_lane<OFF>(send);
+        }
     }
 }
 
