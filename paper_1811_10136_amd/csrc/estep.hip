@@ -474,13 +474,21 @@ __global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
     }
 }
 
-// One lane's value of another lane `OFF` apart (lane ^ OFF): a swizzle
-// within 32 lanes, a permute across the halves of the wave.
+// One lane's value of another lane `OFF` apart (lane ^ OFF): DPP lane moves
+// where one gives exactly lane ^ OFF (quad permutations [1,0,3,2] and
+// [2,3,0,1]; a rotation by 8 within a 16-lane row), a swizzle within 32
+// lanes otherwise, a permute across the halves of the wave.
 template <int OFF>
 __device__ __forceinline__ float xor_lane(float v)
 {
-    if constexpr (OFF == 32) return __shfl_xor(v, 32, 64);
-    else return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (OFF << 10) | 0x1F));
+    if constexpr (OFF == 1 || OFF == 2 || OFF == 8) {
+        constexpr int ctrl = OFF == 1 ? 0xB1 : OFF == 2 ? 0x4E : 0x128;
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    } else if constexpr (OFF == 32) {
+        return __shfl_xor(v, 32, 64);
+    } else {
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (OFF << 10) | 0x1F));
+    }
 }
 
 template <int OFF, int HALF>
