@@ -474,77 +474,6 @@ __global__ void __launch_bounds__(256) k_estep_dedup(EstepArgs a)
     }
 }
 
-// One lane's value of another lane `OFF` apart (lane ^ OFF): DPP lane moves
-// where one gives exactly lane ^ OFF (quad permutations [1,0,3,2] and
-// [2,3,0,1]; a rotation by 8 within a 16-lane row), a swizzle within 32
-// lanes otherwise, a permute across the halves of the wave.
-template <int OFF>
-__device__ __forceinline__ float xor_lane(float v)
-{
-    if constexpr (OFF == 1 || OFF == 2 || OFF == 8) {
-        constexpr int ctrl = OFF == 1 ? 0xB1 : OFF == 2 ? 0x4E : 0x128;
-        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
-    } else if constexpr (OFF == 32) {
-        return __shfl_xor(v, 32, 64);
-    } else {
-        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (OFF << 10) | 0x1F));
-    }
-}
-
-template <int OFF, int HALF>
-__device__ __forceinline__ void halve(float (&v)[kRedVals], int lane)
-{
-    if constexpr (OFF == 32 || OFF == 16) {
-        // gfx950's lane swaps exchange the upper OFF lanes of each 2 OFF-lane group of the first operand
-        // with the lower OFF lanes of the second: the first result holds v[k] in the lower and v[k + HALF]
-        // of the lower partner in the upper lanes, the second the partners' values, so their sum is the
-        // exchange and addition below with no selects (the same sums: addition commutes)
-#pragma unroll
-        for (int k = 0; k < HALF; ++k) {
-            const uint32_t a = __float_as_uint(v[k]), b = __float_as_uint(v[k + HALF]);
-            const auto r = OFF == 32 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
-                                     : __builtin_amdgcn_permlane16_swap(a, b, false, false);
-            v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-        }
-    } else {
-        const bool up = (lane & OFF) != 0;
-#pragma unroll
-        for (int k = 0; k < HALF; ++k) {
-            const float send = up ? v[k] : v[k + HALF];
-            const float keep = up ? v[k + HALF] : v[k];
-            v[k] = keep + xor_lane<OFF>(send);
-        }
-    }
-}
-
-// The block's partial row of the normal equations.  Each wave sums its 32
-// terms over its 64 lanes by halving exchanges (a lane keeps the half of its
-// values its lane bit selects and adds its partner's sums of that half: five
-// rounds leave value lane >> 1, summed over 32 lanes, and one more exchange
-// adds the other lane of the pair -- 32 exchanges where one butterfly per
-// value takes 192); the even lanes put the wave's sums in `wrow` (32 floats
-// of LDS per wave, `stride` floats apart), and the first 32 threads add the
-// four waves in order.
-__device__ __forceinline__ void block_partials_halving(float (&v)[kRedVals], float *wrow, int stride, float *row)
-{
-    static_assert(kRedVals == 32, "five halvings of 32 values");
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    halve<32, 16>(v, lane);
-    halve<16, 8>(v, lane);
-    halve<8, 4>(v, lane);
-    halve<4, 2>(v, lane);
-    halve<2, 1>(v, lane);
-    v[0] += xor_lane<1>(v[0]);
-    if ((lane & 1) == 0) wrow[wave * stride + (lane >> 1)] = v[0];
-    __syncthreads();
-    if (threadIdx.x < kRedVals) {
-        float t = 0.0f;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) t += wrow[w * stride + threadIdx.x];
-        row[threadIdx.x] = t;
-    }
-}
-
 // Fused slice + reduction: every point's M-step terms (Eq. 7 / Eq. 10 in the
 // twist of Eq. 16) are formed right after its slice and the block writes one
 // partial row of the normal equations per tile; M0, M1 and N never leave the
@@ -584,8 +513,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHARED
                              a.normalize_n);
     }
     wave_sync();   // the wave's slice has read its LDS region
-    block_partials_halving(red, reinterpret_cast<float *>(lds), kWaveLds / (int)sizeof(float),
-                           a.partials + (size_t)t * kRedStride);
+    block_partials(red, reinterpret_cast<float *>(lds), kWaveLds / (int)sizeof(float),
+                   a.partials + (size_t)t * kRedStride);
 }
 
 // Diagnostic twin of k_estep: marks every table slot a lookup finds.

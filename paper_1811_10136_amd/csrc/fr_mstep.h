@@ -90,25 +90,74 @@ __device__ __forceinline__ void mstep_point(float (&acc)[kRedVals], float x, flo
     }
 }
 
-// Sum acc over the 256 threads of the block (wavefront butterflies, then the 4
-// waves in order through LDS) and write the block's partial row.
-__device__ __forceinline__ void block_partials(const float (&acc)[kRedVals], float (&part)[4][kRedStride],
-                                               float *row)
+// One lane's value of another lane `OFF` apart (lane ^ OFF, OFF < 16): DPP
+// lane moves where one gives exactly lane ^ OFF (quad permutations
+// [1,0,3,2] and [2,3,0,1]; a rotation by 8 within a 16-lane row), a swizzle
+// within 32 lanes otherwise.
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int j = 0; j < kRedVals; ++j) {
-        float v = acc[j];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) part[wave][j] = v;
+    static_assert(OFF < 16, "wider exchanges use the lane swaps");
+    if constexpr (OFF == 1 || OFF == 2 || OFF == 8) {
+        constexpr int ctrl = OFF == 1 ? 0xB1 : OFF == 2 ? 0x4E : 0x128;
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    } else {
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (OFF << 10) | 0x1F));
     }
+}
+
+template <int OFF, int HALF>
+__device__ __forceinline__ void halve(float (&v)[kRedVals], int lane)
+{
+    if constexpr (OFF == 32 || OFF == 16) {
+        // gfx950's lane swaps exchange the upper OFF lanes of each 2 OFF-lane group of the first operand
+        // with the lower OFF lanes of the second: the first result holds v[k] in the lower and v[k + HALF]
+        // of the lower partner in the upper lanes, the second the partners' values, so their sum is the
+        // exchange and addition below with no selects (the same sums: addition commutes)
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            const uint32_t a = __float_as_uint(v[k]), b = __float_as_uint(v[k + HALF]);
+            const auto r = OFF == 32 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
+                                     : __builtin_amdgcn_permlane16_swap(a, b, false, false);
+            v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        }
+    } else {
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            const float send = up ? v[k] : v[k + HALF];
+            const float keep = up ? v[k + HALF] : v[k];
+            v[k] = keep + xor_lane<OFF>(send);
+        }
+    }
+}
+
+// Sum acc over the 256 threads of the block and write the block's partial row
+// of the normal equations (acc is consumed).  Each wave sums its 32
+// terms over its 64 lanes by halving exchanges (a lane keeps the half of its
+// values its lane bit selects and adds its partner's sums of that half: five
+// rounds leave value lane >> 1, summed over 32 lanes, and one more exchange
+// adds the other lane of the pair -- 32 exchanges where one butterfly per
+// value takes 192); the even lanes put the wave's sums in `wrow` (32 floats
+// of LDS per wave, `stride` floats apart), and the first 32 threads add the
+// four waves in order.
+__device__ __forceinline__ void block_partials(float (&v)[kRedVals], float *wrow, int stride, float *row)
+{
+    static_assert(kRedVals == 32, "five halvings of 32 values");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    halve<32, 16>(v, lane);
+    halve<16, 8>(v, lane);
+    halve<8, 4>(v, lane);
+    halve<4, 2>(v, lane);
+    halve<2, 1>(v, lane);
+    v[0] += xor_lane<1>(v[0]);
+    if ((lane & 1) == 0) wrow[wave * stride + (lane >> 1)] = v[0];
     __syncthreads();
     if (threadIdx.x < kRedVals) {
-        float v = 0.0f;
+        float t = 0.0f;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) v += part[w][threadIdx.x];
-        row[threadIdx.x] = v;
+        for (int w = 0; w < 4; ++w) t += wrow[w * stride + threadIdx.x];
+        row[threadIdx.x] = t;
     }
 }
 

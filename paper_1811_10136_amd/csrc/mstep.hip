@@ -3,9 +3,9 @@
 //
 // k_reduce: one block per tile of 1024 model points of one segment.  Each
 // thread accumulates w J^T J (21 upper entries), w J^T r (6) and 4 statistics
-// in binary32 registers over its points; the block reduces the 31 values with
-// wavefront butterflies and an LDS exchange between its 4 waves and writes one
-// partial row per tile.  k_reduce_final: one block per segment sums its
+// in binary32 registers over its points; the block reduces the 32 values with
+// halving lane exchanges and an LDS exchange between its 4 waves and writes
+// one partial row per tile.  k_reduce_final: one block per segment sums its
 // tiles' partial rows in binary64 in a fixed order (bitwise reproducible)
 // and applies the 1/sigma^2 of the residual scaling.
 #include "fr_internal.h"
@@ -67,7 +67,7 @@ __device__ __forceinline__ void reduce_tile(const ReduceArgs &a, int32_t t, floa
                              __builtin_nontemporal_load(a.m1 + 2 * a.M + i), nsx, nsy, nsz, c, a.normalize_n,
                              M2 ? __builtin_nontemporal_load(a.m2 + i) : 0.0f);
     }
-    block_partials(acc, part, a.partials + (size_t)t * kRedStride);
+    block_partials(acc, &part[0][0], kRedStride, a.partials + (size_t)t * kRedStride);
 }
 
 template <int RES, bool XF, bool M2, bool PERSIST>
