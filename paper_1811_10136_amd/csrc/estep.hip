@@ -493,7 +493,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHARED
     float red[kRedVals];
 #pragma unroll
     for (int j = 0; j < kRedVals; ++j) red[j] = 0.0f;
-    float x[3], acc[V];
+    float x[3] = {0.0f, 0.0f, 0.0f}, acc[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[c] = 0.0f;
     bool live;
     if constexpr (SHARED) {
         int64_t i = 0;
@@ -503,13 +505,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHARED
         live = i < a.tm.seg_end[s];
         if (live) slice_point<d, V, XF>(a, s, i, a.sets[a.tm.seg_set[s]], x, acc);
     }
-    if (live) {
+    {
+        // one branch (m0 > 0 in mstep_point): a lane without a point passes m0 = 0 and adds nothing,
+        // so the accumulators' zeros are not set up again for each of two nested branches
         const float c = a.seg_c[s];
+        const float m0 = live ? acc[0] : 0.0f;
         if constexpr (RES == FR_PT2PL)
-            mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], c,
+            mstep_point<RES>(red, x[0], x[1], x[2], m0, acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], c,
                              a.normalize_n);
         else
-            mstep_point<RES>(red, x[0], x[1], x[2], acc[0], acc[1], acc[2], acc[3], 0.0f, 0.0f, 0.0f, c,
+            mstep_point<RES>(red, x[0], x[1], x[2], m0, acc[1], acc[2], acc[3], 0.0f, 0.0f, 0.0f, c,
                              a.normalize_n);
     }
     wave_sync();   // the wave's slice has read its LDS region

@@ -52,16 +52,22 @@ __device__ __forceinline__ void mstep_point(float (&acc)[kRedVals], float x, flo
                                             float m1y, float m1z, float nsx, float nsy, float nsz, float c,
                                             int normalize_n, float m2 = 0.0f)
 {
-    if (!(m0 > 0.0f)) return;
-    const float w = m0 / (m0 + c);
-    const float inv = 1.0f / m0;
+    // No branch: a point without support (m0 = 0, or not a number) takes zeros in place of its
+    // position, normal, residual and weight, so each of its terms is +0 whatever its inputs, and adding
+    // +0 leaves a sum unchanged (a sum that starts at +0 is never -0).  The other points evaluate the
+    // same expressions as with a branch.  Without one the accumulators are not set up again for a path
+    // that skips the point.
+    const bool ok = m0 > 0.0f;
+    const float w = ok ? m0 / (m0 + c) : 0.0f;
+    const float inv = ok ? 1.0f / m0 : 0.0f;
     const float tx = m1x * inv, ty = m1y * inv, tz = m1z * inv;
-    const float dx = x - tx, dy = y - ty, dz = z - tz;
+    const float dx = ok ? x - tx : 0.0f, dy = ok ? y - ty : 0.0f, dz = ok ? z - tz : 0.0f;
+    const float px = ok ? x : 0.0f, py = ok ? y : 0.0f, pz = ok ? z : 0.0f;
     float r2;
     if constexpr (RES == FR_PT2PT) {
-        const float J[3][6] = {{0.0f, z, -y, 1.0f, 0.0f, 0.0f},
-                               {-z, 0.0f, x, 0.0f, 1.0f, 0.0f},
-                               {y, -x, 0.0f, 0.0f, 0.0f, 1.0f}};
+        const float J[3][6] = {{0.0f, pz, -py, 1.0f, 0.0f, 0.0f},
+                               {-pz, 0.0f, px, 0.0f, 1.0f, 0.0f},
+                               {py, -px, 0.0f, 0.0f, 0.0f, 1.0f}};
         const float r[3] = {dx, dy, dz};
         accumulate_rows<3>(acc, J, r, w);
         r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -74,19 +80,23 @@ __device__ __forceinline__ void mstep_point(float (&acc)[kRedVals], float x, flo
             ny *= in;
             nz *= in;
         }
+        nx = ok ? nx : 0.0f;
+        ny = ok ? ny : 0.0f;
+        nz = ok ? nz : 0.0f;
         const float rr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
-        const float J[1][6] = {{y * nz - z * ny, z * nx - x * nz, x * ny - y * nx, nx, ny, nz}};
+        const float J[1][6] = {{py * nz - pz * ny, pz * nx - px * nz, px * ny - py * nx, nx, ny, nz}};
         const float r[1] = {rr};
         accumulate_rows<1>(acc, J, r, w);
         r2 = rr * rr;
     }
     acc[27] += w;
     acc[28] = fmaf(w, r2, acc[28]);
-    acc[29] += 1.0f;
-    acc[30] += m0;
+    acc[29] += ok ? 1.0f : 0.0f;
+    acc[30] += ok ? m0 : 0.0f;
     if constexpr (M2) {
         const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        acc[31] = fmaf(w, fmaf(m2, inv, dd), acc[31]);
+        const float v = fmaf(m2, inv, dd);
+        acc[31] = fmaf(w, ok ? v : 0.0f, acc[31]);
     }
 }
 
