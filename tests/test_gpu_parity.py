@@ -469,6 +469,38 @@ def test_fused_shared_and_plain_slices_agree_bitwise(fr, ctx, feat, residual):
     assert ok, (ang, dt)
 
 
+@pytest.mark.parametrize("feat,residual", [(6, "pt2pl"), (3, "pt2pt")])
+def test_fused_points_without_support_add_nothing(fr, ctx, feat, residual):
+    """Eq. 7 / Eq. 10 weigh a model point by M0 / (M0 + c): a point whose simplex meets no lattice vertex
+    (M0 = 0) has weight 0, and the fused step adds exact zeros for it whatever its position and normal.
+    Appending 300 model points 10 m away from the frame (they fill the lanes past the cloud's end and a
+    tile of their own) must leave every pose bitwise unchanged, with either slice form.  c is given
+    explicitly, since its rule scales with the number of model points."""
+    q = synth.depth_pair(7, width=160, height=120, f=131.25)
+    sig = np.broadcast_to(np.asarray(q.sigma, dtype=np.float64), (3,))
+    c = oracle.outlier_constant(0.1, len(q.obs), len(q.model), oracle.feature_sigmas(feat, sig, q.sigma_n))
+    prm = fr.register_params(feat, residual, q.sigma, q.sigma_n, iters=8, w=0.1, c=c, fused=True)
+    nrm = feat == 6 or residual == "pt2pl"
+    far = (q.model[:300] + np.array([10.0, -10.0, 10.0], dtype=np.float32)).astype(np.float32)
+    clouds = {
+        "alone": upload([q.model], [q.model_n] if feat == 6 else None),
+        "with far points": upload([np.concatenate([q.model, far])],
+                                  [np.concatenate([q.model_n, q.model_n[:300]])] if feat == 6 else None),
+    }
+    obs = upload([q.obs], [q.obs_n] if nrm else None)
+    T0 = q.T_gt @ oracle.se3_exp(np.array([0.004, -0.003, 0.002, 0.004, 0.003, -0.002]))
+    _say(f"[fused-far] feat={feat} {residual} model {len(q.model)} + 300 far points")
+    try:
+        for sl in (fr.FR_SLICE_PLAIN, fr.FR_SLICE_SHARED):
+            fr.fr_ctx_set_tuning(ctx.h, sl)
+            res = {k: fr.register(ctx, m, obs, prm, T0=T0[None]) for k, m in clouds.items()}
+            assert int(res["alone"][1][0]) == 0
+            np.testing.assert_array_equal(res["alone"][0], res["with far points"][0])
+            np.testing.assert_array_equal(res["alone"][1], res["with far points"][1])
+    finally:
+        fr.fr_ctx_set_tuning(ctx.h, fr.FR_SLICE_AUTO)
+
+
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("fixed", [True, False])
 def test_graph_replay_equals_the_eager_loop(fr, ctx, fixed, fused):
